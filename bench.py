@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Benchmark of the path-graph hot path on one MI355X.
+
+Workload: the 128^3 fBm ball (sigma_t <= 32, per-voxel albedo U[0.95,0.999],
+HG g = 0.8, sun + environment), 512x512 px at 4 spp, delta-tracking paths to
+depth 64; k = 16 neighbours, D = 64 iterations.  Inputs are generated on the
+host, copied to HBM, and are resident before the timed region starts.
+
+One step = one pg_render call: grid build + exact kNN, aggregation operators,
+path pass, D iterations of aggregation + propagation, output to pixels.
+value = E * D / step time  (E = N * K edges), in Gedge-updates/s.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gedge-updates/s fwd, fwd+adjoint, batched vs per-scene on 1 GPU; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(step, N, K):
+    """Compulsory HBM bytes of one launch of a propagation step (every input
+    read once, every output written once):
+      spmv / spmv_shifted: col + weight per edge (8 B), one x gather, b (or c)
+      and albedo or row mask per row, one y write: N (8K + 12 + 12 + 4 + 12)
+      shift: successor id, one y gather, one x write: N (4 + 12 + 12)."""
+    if step in ("spmv", "spmv_shifted"):
+        return N * (8 * K + 40)
+    if step == "shift":
+        return N * 28
+    return None
+
+
+def read_traffic(kernel, workload):
+    """HBM bytes per launch measured with rocprofv3 counters, if the summary
+    under profiles/ was taken from the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"bytes_per_launch:\s*([0-9.eE+]+)", text)
+    h = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    if not m or not h:
+        return None
+    src = os.path.join(ROOT, "paper_2404_11894_amd", "csrc", "pg_prop.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+        return None
+    return float(m.group(1))
+
+
+def profile_entries(pg):
+    L = pg.lib()
+    arr = (pg.ProfileEntry * 64)()
+    n = ctypes.c_int32()
+    pg._check(L.pg_profile_stop(64, arr, ctypes.byref(n)))
+    return {arr[i].name.decode(): (arr[i].count, arr[i].total_ms, arr[i].max_ms) for i in range(min(n.value, 64))}
+
+
+def cpu_baseline(workload, k, D, g):
+    """The FP64 oracle, single-threaded, on a centred 64x64-pixel crop of the
+    same workload (all 4 samples per pixel): the whole pipeline."""
+    import oracle
+    import scenegen
+    sc = scenegen.generate(scenegen.crop_of(workload.scene, 64, 64))
+    K = min(k, sc.n_vertices)
+    log(f"cpu baseline: oracle on 64x64 crop, N={sc.n_vertices}")
+    t0 = time.perf_counter()
+    oracle.render(sc, oracle.params(k=k, D=D, g=g))
+    dt = time.perf_counter() - t0
+    E = sc.n_vertices * K
+    return {"value": E * D / dt / 1e9, "unit": "Gedge-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"centred 64x64-pixel crop of the same image, 4 spp: N={sc.n_vertices}, E={E}, D={D}; "
+                      f"whole pipeline (kNN, weights, {D} iterations, pixels) in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large"])
+    ap.add_argument("--schedule", type=int, default=0, help="0 default, 1 two-pass, 2 shifted")
+    ap.add_argument("--cell-shift", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run a 1 GiB device copy then the render steps (for rocprofv3 --pmc)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import scenegen
+    import paper_2404_11894_amd as pg
+
+    w = scenegen.WORKLOADS[args.workload]
+    log(f"generating workload {args.workload}")
+    t0 = time.perf_counter()
+    sc = scenegen.generate(w.scene)
+    log(f"N={sc.n_vertices} P={sc.n_paths} generated in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    paths = pg.DevicePaths(sc, device=dev)
+    q = pg.params(k=w.k, D=w.D, g=w.g, schedule=args.schedule, cell_shift=args.cell_shift)
+    N = sc.n_vertices
+    K = min(w.k, N)
+    E = N * K
+    render = pg.Renderer(paths, q)
+    image = torch.empty(sc.height, sc.width, 3, device=dev)
+
+    if args.pmc_probe:
+        a = torch.ones(256 * 1024 * 1024, device=dev)          # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("pmc probe: copied 1 GiB (1 GiB read + 1 GiB written)")
+
+    for _ in range(args.warmup):
+        render(image)
+    torch.cuda.synchronize()
+    log(f"warm-up done ({args.warmup} steps); timing {args.steps} steps")
+
+    pg._check(pg.lib().pg_profile_start())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        render(image)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = profile_entries(pg)
+    ms = dt * 1e3 / args.steps
+    value = E * w.D / (ms / 1e3) / 1e9
+    log(f"{ms:.2f} ms/step, {value:.1f} Gedge-updates/s")
+    if args.pmc_probe:
+        print(json.dumps({"pmc_probe": True, "ms_per_step": ms}))
+        return
+
+    phases = {k: round(v[1] / args.steps, 4) for k, v in prof.items()}
+    prop_steps = [s for s in ("spmv", "shift", "spmv_shifted") if s in prof]
+    prop_ms = sum(prof[s][1] for s in prop_steps) / args.steps
+    dom = max(prop_steps, key=lambda s: prof[s][1])
+    cnt, tot, _ = prof[dom]
+    avg_s = tot / cnt / 1e3
+    ab = algorithmic_bytes(dom, N, K)
+    achieved = ab / avg_s / 1e9
+    traffic = read_traffic(dom, args.workload)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+            "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(avg_s * 1e3, 4)}
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Gedge-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {w.scene.R}^3 fBm medium, {w.scene.width}x{w.scene.height} px, "
+                               f"{w.scene.spp} spp, depth {w.scene.max_depth}, k {w.k}, D {w.D}",
+                   "N": N, "E": E, "P": sc.n_paths, "K": K, "D": w.D,
+                   "schedule": pg.resolved_schedule(q), "cell_shift": args.cell_shift or pg.pg_default_cell_shift(N)},
+        "propagation": {"ms_per_step": round(prop_ms, 3), "gedge_updates_per_s": round(E * w.D / prop_ms / 1e6, 2),
+                        "algorithmic_GBs": round((8 * K + 68) * N * w.D / (prop_ms / 1e3) / 1e9, 1)},
+        "phases_ms": phases,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, w.k, w.D, w.g)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,240 @@
+/*
+ * pathgraph.h -- C ABI of the MI355X (gfx950) path-graph library.
+ *
+ * The library implements the data-parallel hot path of path-graph rendering
+ * for participating media (Hu, Deng, Luan, Hasan, Marschner, arXiv
+ * 2404.11894): from the volume path vertices a path tracer recorded, it builds
+ * the path graph (neighbour search), turns each vertex's neighbours into
+ * weighted edges (aggregation operators), iterates aggregation + propagation
+ * D times and writes the radiance of every path's first continuation edge
+ * into its pixel.  It also provides the reverse-mode derivative of an image
+ * objective with respect to a trilinear albedo grid and the HG parameter, and
+ * a batched render of many independent scenes.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Memory.  Every array argument is DEVICE memory owned by the caller; the
+ *   library never allocates, frees or retains it.  Temporary memory is a
+ *   caller-provided device workspace of at least the size the matching
+ *   *_workspace_size call reports (256-byte alignment required).  The library
+ *   keeps no state between calls except a thread-local error string.
+ * Streams.  `stream` is a hipStream_t (NULL: the null stream).  Calls enqueue
+ *   work and return; results are ready when the stream is.  With
+ *   PG_FLAG_CHECK in params->flags a call synchronises the stream and reports
+ *   input errors detected on the device as PG_ERR_INPUT.
+ * Errors.  Every call returns a pg_status.  On error the outputs are
+ *   undefined and pg_last_error() describes the cause.  No C++ exception
+ *   crosses the interface.  Bad device data (NaN or out-of-range positions,
+ *   non-monotone path offsets, neighbour ids out of range) never causes an
+ *   out-of-bounds access: the offending item is skipped and a device flag set.
+ * Layout.  Per-vertex arrays are in PATH ORDER (the order the path tracer
+ *   recorded the vertices, paper Sec. "Rendering System", instrumented path
+ *   tracer).  float3 data is packed [N][3].  Vertex ids are int32, so N must be
+ *   below 2^31; path offsets and CSR row pointers are int64.
+ * Threading.  Calls on different streams/workspaces may run concurrently.
+ */
+#ifndef PATHGRAPH_H
+#define PATHGRAPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pg_status;
+#define PG_OK               0
+#define PG_ERR_ARG         -1   /* invalid argument (null pointer, size, range) */
+#define PG_ERR_WORKSPACE   -2   /* workspace missing, too small or misaligned */
+#define PG_ERR_HIP         -3   /* a HIP runtime call failed */
+#define PG_ERR_INPUT       -4   /* bad device data detected (PG_FLAG_CHECK) */
+#define PG_ERR_UNSUPPORTED -5   /* valid request the library does not support */
+
+#define PG_INIT_PT   0  /* start from the path tracer's own incoming-indirect estimate */
+#define PG_INIT_ZERO 1  /* start from zero */
+
+#define PG_FLAG_CHECK 1u  /* synchronise and report device-detected input errors */
+#define PG_FLAG_TAPE  2u  /* pg_render keeps the graph and every iterate in the workspace
+                             for a following pg_backward on the same workspace */
+
+#define PG_SCHED_TWO_PASS 1  /* aggregate over spatially sorted rows, then shift along paths */
+#define PG_SCHED_SHIFTED  2  /* rows pre-arranged in predecessor order: one pass per iteration */
+
+#define PG_MAX_K 64
+
+/* The recorded paths of one image (paper Sec. "Path Graph Framework": a path
+ * graph is built from complete light paths sampled at one or more samples per
+ * pixel; all samples of the image go into one graph).
+ * Path p = vertices [path_offsets[p], path_offsets[p+1]) belongs to pixel
+ * p / spp (row-major, width fastest), sample p % spp.  An empty path is a
+ * camera ray that escaped; inside a path, vertex v+1 is the successor of v. */
+typedef struct pg_paths {
+    int64_t n_vertices;           /* N */
+    int64_t n_paths;              /* P = width * height * spp */
+    int32_t width, height, spp;
+    int32_t albedo_grid_res;      /* R of albedo_grid, 0 if none */
+    const int64_t* path_offsets;  /* [P+1], path_offsets[0] = 0, path_offsets[P] = N */
+    const float* pos;             /* [N][3] collision position in [0,1]^3 */
+    const float* dir_in;          /* [N][3] unit travel direction of the path arriving at v */
+    const float* dir_out;         /* [N][3] unit continuation direction, sampled from HG(g_s) about dir_in */
+    const float* albedo;          /* [N] scattering albedo sigma_s / sigma_t at v (ignored with a grid) */
+    const float* l_sun;           /* [N][3] sun NEE: sun irradiance x shadow-ray transmittance */
+    const float* dir_env;         /* [N][3] unit environment NEE direction (pdf env_pdf) */
+    const float* l_env;           /* [N][3] environment radiance x shadow-ray transmittance */
+    const float* l_phase;         /* [N][3] environment radiance if the continuation escaped, else 0 */
+    const float* e_cam;           /* [P][3] environment radiance if the camera ray escaped, else 0 */
+    const float* albedo_grid;     /* [R][R][R] (z,y,x) or NULL: albedo = cell-centred trilinear
+                                     interpolation of the grid at pos (indices clamped to [0,R-1]) */
+} pg_paths;
+
+/* Method parameters. */
+typedef struct pg_params {
+    int32_t k;              /* neighbours per vertex, the vertex itself included; 1..PG_MAX_K.
+                               K = min(k, N) */
+    int32_t D;              /* aggregation + propagation iterations, >= 0 */
+    float g;                /* HG parameter of the receiver's phase function, |g| < 1 */
+    float g_s;              /* HG parameter of the sampling pdfs in the MIS marginals, |g_s| < 1 */
+    float sun_dir[3];       /* unit direction toward the (delta) sun */
+    float env_pdf;          /* solid-angle pdf of environment sampling, > 0 (1/(4 pi)) */
+    int32_t init;           /* PG_INIT_PT or PG_INIT_ZERO */
+    int32_t final_gather;   /* 0: the first vertex aggregates its neighbours' radiance for the
+                               output; 1: it uses its own continuation sample only */
+    int32_t cell_shift;     /* uniform-grid cell = 2^cell_shift quantisation steps per axis,
+                               11..20; 0 = choose from N */
+    int32_t schedule;       /* propagation schedule, same result: 0 = default,
+                               PG_SCHED_TWO_PASS or PG_SCHED_SHIFTED */
+    uint32_t flags;         /* PG_FLAG_* */
+} pg_params;
+
+/* Optional outputs of pg_render; any pointer may be NULL. */
+typedef struct pg_graph_out {
+    int64_t* row_ptr;       /* [N+1]  = i*K */
+    int32_t* col;           /* [N*K]  neighbour ids (path-order ids) */
+    float* w_ind;           /* [N*K]  indirect aggregation weights */
+    float* w_ph;            /* [N*K]  direct weights of the phase-sampled records */
+    float* w_env;           /* [N*K]  direct weights of the emitter-sampled records */
+    float* b;               /* [N][3] albedo x aggregated direct radiance */
+    float* d_pt;            /* [N][3] non-aggregated (path-traced) direct term */
+    float* lplus;           /* [N][3] incoming indirect radiance after D iterations */
+} pg_graph_out;
+
+/* ---- utilities ---------------------------------------------------------- */
+
+/* Library version string (static storage). */
+const char* pg_version(void);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* pg_last_error(void);
+
+/* Cell shift chosen when params->cell_shift == 0, for N vertices. */
+int32_t pg_default_cell_shift(int64_t n_vertices);
+
+/* ---- instrumentation ------------------------------------------------------
+ * Between pg_profile_start and pg_profile_stop, every kernel step that calls
+ * on the calling thread enqueue is bracketed by two HIP events recorded on
+ * the caller's stream.  pg_profile_stop waits for the events, aggregates the
+ * elapsed times by step name into out[0 .. *n_entries-1] (at most
+ * max_entries) and stops recording.  Off by default; costs two event records
+ * per step when on. */
+typedef struct pg_profile_entry {
+    char name[32];        /* step, e.g. "spmv", "shift", "knn", "edges" */
+    int32_t count;        /* launches recorded */
+    double total_ms;      /* summed event-to-event time */
+    double max_ms;
+} pg_profile_entry;
+pg_status pg_profile_start(void);
+pg_status pg_profile_stop(int32_t max_entries, pg_profile_entry* out, int32_t* n_entries);
+
+/* ---- step 1: path graph neighbour edges ---------------------------------
+ * Paper Sec. "Path Graph Framework" (neighbour edges connect each shading
+ * point with the points in its spatial neighbourhood) and Sec. "Rendering
+ * System" (a hash grid over the shading points and a search through
+ * neighbouring bins).  Neighbourhoods here are exact k nearest neighbours on
+ * positions quantised to 20 bits per axis, q = min(floor(x * 2^20), 2^20-1):
+ * row i lists i first, then the K-1 nearest j != i ordered by (squared integer
+ * distance, j).  The result is unique and reproducible bit for bit.
+ * Writes row_ptr[N+1] (= i*K) and col[N*K]. */
+pg_status pg_knn_workspace_size(const pg_paths* paths, int32_t k, int32_t cell_shift, size_t* bytes);
+pg_status pg_knn(const pg_paths* paths, int32_t k, int32_t cell_shift, int64_t* row_ptr, int32_t* col,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* ---- step 2: aggregation operators ---------------------------------------
+ * Paper Sec. "Path Graph Operators", eqs. (indirect-weight), (ag-indirect),
+ * (ag-direct).  For receiver i and neighbour j (K = row length):
+ *   M+_ij = sum_{l in N(i)} p_l(w_j),  p_l = HG_{g_s} about dir_in[l]
+ *   w_ind_ij = rho_i(w_j) / M+_ij,      rho_i = HG_g about dir_in[i]
+ *   w_ph_ij  = rho_i(w_j) / (M+_ij + K env_pdf)
+ *   w_env_ij = rho_i(we_j) / (sum_l p_l(we_j) + K env_pdf)
+ *   b_i = albedo_i (rho_i(sun) mean_j l_sun_j + sum_j w_env_ij l_env_j + w_ph_ij l_phase_j)
+ *   d_pt_i = rho_i(sun) l_sun_i + rho_i(we_i) l_env_i / (p_i(we_i) + env_pdf)
+ *            + rho_i(w_i) l_phase_i / (p_i(w_i) + env_pdf)
+ * and the initial incoming indirect radiance lplus0 (paper Sec. "Rendering
+ * System": the path tracer's own estimate, or zero): for v with successor u,
+ * lplus0(v) = albedo_u (d_pt_u + rho_u(w_u)/p_u(w_u) lplus0(u)); 0 at a path's end.
+ * Inputs row_ptr/col as produced by pg_knn (row i starting with i).
+ * Any of the outputs may be NULL. */
+pg_status pg_edges_workspace_size(const pg_paths* paths, const pg_params* params, size_t* bytes);
+pg_status pg_edges(const pg_paths* paths, const pg_params* params, const int64_t* row_ptr, const int32_t* col,
+                   float* w_ind, float* w_ph, float* w_env, float* b, float* d_pt, float* lplus0,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* ---- step 3: iterated aggregation and propagation ------------------------
+ * Paper eqs. (ag-mf), (rte-pg), (rte-mff).  For t = 1..D:
+ *   y_i = b_i + albedo_i sum_j w_ind_ij L(j);  L(v) = y(v+1) inside a path, 0 at its end.
+ * (Under delta tracking the propagation factor transmittance / free-flight pdf
+ * is 1/sigma_t at the collision, which turns sigma_s * phase into albedo *
+ * phase, so propagation is the shift to the predecessor.)
+ * lplus holds L_0 on entry and L_D on return.  traj, if not NULL, receives
+ * L_1..L_D as [D][N][3]. */
+pg_status pg_propagate_workspace_size(const pg_paths* paths, const pg_params* params, size_t* bytes);
+pg_status pg_propagate(const pg_paths* paths, const pg_params* params, const int64_t* row_ptr,
+                       const int32_t* col, const float* w_ind, const float* b, float* lplus, float* traj,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* ---- step 4: output to pixels --------------------------------------------
+ * Paper Sec. "Rendering System", "Handling direct Light" and "Final output":
+ * path p with first vertex v0 outputs
+ *   o_p = albedo_v0 (d_pt_v0 + sum_j w_ind_v0j L(j))        (final_gather = 0)
+ *   o_p = albedo_v0 (d_pt_v0 + rho_v0(w_v0)/p_v0(w_v0) L(v0)) (final_gather = 1)
+ * (0 for an empty path) and image[pixel] = mean over its spp paths of
+ * (e_cam_p + o_p).  image is [height][width][3].  No workspace. */
+pg_status pg_gather(const pg_paths* paths, const pg_params* params, const int64_t* row_ptr, const int32_t* col,
+                    const float* w_ind, const float* d_pt, const float* lplus, float* image, void* stream);
+
+/* ---- all four steps -------------------------------------------------------
+ * pg_knn + pg_edges + pg_propagate + pg_gather in one call, with the graph
+ * kept in a spatially sorted internal layout.  `out` may be NULL. */
+pg_status pg_render_workspace_size(const pg_paths* paths, const pg_params* params, size_t* bytes);
+pg_status pg_render(const pg_paths* paths, const pg_params* params, float* image, const pg_graph_out* out,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* ---- reverse mode (project addition; not in the paper) --------------------
+ * Gradient of  sum_px <grad_image[px], image[px]>  with respect to the albedo
+ * grid (paths->albedo_grid, required) and the receiver-side HG parameter g,
+ * with the recorded paths and the sampling pdfs (g_s) held fixed:
+ * d rho/d g = rho * (-2g/(1-g^2) - 3(g - cos)/(1 + g^2 - 2 g cos)).
+ * If params->flags has PG_FLAG_TAPE, `ws` must hold the tape of a pg_render
+ * call with the same paths and params (PG_FLAG_TAPE set) and must not have
+ * been used since; otherwise the forward pass is recomputed first.
+ * grad_grid is [R][R][R]; grad_albedo ([N], per vertex) may be NULL;
+ * grad_g is one float. */
+pg_status pg_backward_workspace_size(const pg_paths* paths, const pg_params* params, size_t* bytes);
+pg_status pg_backward(const pg_paths* paths, const pg_params* params, const float* grad_image,
+                      float* grad_grid, float* grad_albedo, float* grad_g, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* ---- batching (project addition; not in the paper) ------------------------
+ * Renders n_scenes independent scenes (each with its own paths and params)
+ * with every step launched once for all scenes; images[s] receives scene s.
+ * The same result as n_scenes pg_render calls. */
+pg_status pg_render_batched_workspace_size(int32_t n_scenes, const pg_paths* paths, const pg_params* params,
+                                           size_t* bytes);
+pg_status pg_render_batched(int32_t n_scenes, const pg_paths* paths, const pg_params* params,
+                            float* const* images, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PATHGRAPH_H */

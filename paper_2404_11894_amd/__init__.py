@@ -1,0 +1,302 @@
+"""MI355X (gfx950) path-graph rendering of participating media.
+
+Thin Python binding of the C ABI in ``include/pathgraph.h``: the functions
+below carry the same names as the C entry points and only marshal arguments
+(torch device tensors -> pointers, the current HIP stream, a workspace
+tensor).  Every step runs in the HIP kernels of ``libpathgraph.so``; there is
+no fallback.  Build the library with :func:`build` (``__graft_entry__.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+from ._build import LIB_PATH, build  # noqa: F401
+
+PG_OK, PG_ERR_ARG, PG_ERR_WORKSPACE, PG_ERR_HIP, PG_ERR_INPUT, PG_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+PG_INIT_PT, PG_INIT_ZERO = 0, 1
+PG_FLAG_CHECK, PG_FLAG_TAPE = 1, 2
+PG_SCHED_TWO_PASS, PG_SCHED_SHIFTED = 1, 2
+PG_MAX_K = 64
+
+EXPORTS = ("pg_version", "pg_last_error", "pg_default_cell_shift", "pg_profile_start", "pg_profile_stop",
+           "pg_knn_workspace_size", "pg_knn", "pg_edges_workspace_size", "pg_edges",
+           "pg_propagate_workspace_size", "pg_propagate", "pg_gather",
+           "pg_render_workspace_size", "pg_render", "pg_backward_workspace_size", "pg_backward",
+           "pg_render_batched_workspace_size", "pg_render_batched")
+
+
+class PathGraphError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pathgraph error {code}: {msg}")
+        self.code = code
+
+
+class Paths(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("n_paths", ctypes.c_int64),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("spp", ctypes.c_int32),
+                ("albedo_grid_res", ctypes.c_int32)] + [
+        (n, ctypes.c_void_p) for n in ("path_offsets", "pos", "dir_in", "dir_out", "albedo", "l_sun",
+                                       "dir_env", "l_env", "l_phase", "e_cam", "albedo_grid")]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("D", ctypes.c_int32), ("g", ctypes.c_float), ("g_s", ctypes.c_float),
+                ("sun_dir", ctypes.c_float * 3), ("env_pdf", ctypes.c_float), ("init", ctypes.c_int32),
+                ("final_gather", ctypes.c_int32), ("cell_shift", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class ProfileEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("count", ctypes.c_int32), ("total_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double)]
+
+
+class GraphOut(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("row_ptr", "col", "w_ind", "w_ph", "w_env", "b", "d_pt", "lplus")]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: the HIP library has not been built "
+                               "(run __graft_entry__.build() or paper_2404_11894_amd.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)
+        P, Q = ctypes.POINTER(Paths), ctypes.POINTER(Params)
+        sig = {
+            "pg_version": (ctypes.c_char_p, []),
+            "pg_last_error": (ctypes.c_char_p, []),
+            "pg_default_cell_shift": (i32, [i64]),
+            "pg_profile_start": (i32, []),
+            "pg_profile_stop": (i32, [i32, ctypes.POINTER(ProfileEntry), ctypes.POINTER(ctypes.c_int32)]),
+            "pg_knn_workspace_size": (i32, [P, i32, i32, sz]),
+            "pg_knn": (i32, [P, i32, i32, vp, vp, vp, ctypes.c_size_t, vp]),
+            "pg_edges_workspace_size": (i32, [P, Q, sz]),
+            "pg_edges": (i32, [P, Q, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+            "pg_propagate_workspace_size": (i32, [P, Q, sz]),
+            "pg_propagate": (i32, [P, Q, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+            "pg_gather": (i32, [P, Q, vp, vp, vp, vp, vp, vp, vp]),
+            "pg_render_workspace_size": (i32, [P, Q, sz]),
+            "pg_render": (i32, [P, Q, vp, ctypes.POINTER(GraphOut), vp, ctypes.c_size_t, vp]),
+            "pg_backward_workspace_size": (i32, [P, Q, sz]),
+            "pg_backward": (i32, [P, Q, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+            "pg_render_batched_workspace_size": (i32, [i32, P, Q, sz]),
+            "pg_render_batched": (i32, [i32, P, Q, vp, vp, ctypes.c_size_t, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != PG_OK:
+        raise PathGraphError(rc, lib().pg_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _workspace(nbytes: int, device):
+    torch = _torch()
+    # 256-byte aligned view into a byte tensor
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf[off:off + int(nbytes)], int(nbytes)
+
+
+class DevicePaths:
+    """The path records of one image as device tensors, plus the C struct
+    pointing at them.  ``scene`` is any object with the record arrays (numpy or
+    torch) and width / height / spp attributes."""
+
+    ARRAYS = ("path_offsets", "pos", "dir_in", "dir_out", "albedo", "l_sun", "dir_env", "l_env", "l_phase",
+              "e_cam")
+
+    def __init__(self, scene, device="cuda", albedo_grid=None):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.tensors = {}
+        for name in self.ARRAYS:
+            a = getattr(scene, name)
+            t = torch.as_tensor(a)
+            dt = torch.int64 if name == "path_offsets" else torch.float32
+            self.tensors[name] = t.to(device=self.device, dtype=dt).contiguous()
+        self.width, self.height, self.spp = int(scene.width), int(scene.height), int(scene.spp)
+        self.n_vertices = int(self.tensors["pos"].shape[0])
+        self.n_paths = int(self.tensors["path_offsets"].shape[0]) - 1
+        self.albedo_grid = None
+        self.set_albedo_grid(albedo_grid)
+
+    def set_albedo_grid(self, grid):
+        torch = _torch()
+        self.albedo_grid = None if grid is None else torch.as_tensor(grid).to(
+            device=self.device, dtype=torch.float32).contiguous()
+
+    def struct(self) -> Paths:
+        s = Paths()
+        s.n_vertices, s.n_paths = self.n_vertices, self.n_paths
+        s.width, s.height, s.spp = self.width, self.height, self.spp
+        for name, t in self.tensors.items():
+            setattr(s, name, t.data_ptr() if t.numel() else None)
+        if self.albedo_grid is not None:
+            s.albedo_grid = self.albedo_grid.data_ptr()
+            s.albedo_grid_res = int(self.albedo_grid.shape[0])
+        return s
+
+
+def params(k=8, D=8, g=0.5, g_s=None, sun_dir=None, env_pdf=None, init="pt", final_gather=0, cell_shift=0,
+           schedule=0, flags=0) -> Params:
+    """Method parameters (defaults of the small workload)."""
+    q = Params()
+    q.k, q.D = int(k), int(D)
+    q.g = float(g)
+    q.g_s = float(g if g_s is None else g_s)
+    if sun_dir is None:
+        n = math.sqrt(0.3 ** 2 + 1.0 + 0.4 ** 2)
+        sun_dir = (0.3 / n, 1.0 / n, -0.4 / n)
+    q.sun_dir[:] = [float(v) for v in sun_dir]
+    q.env_pdf = float(1.0 / (4.0 * math.pi) if env_pdf is None else env_pdf)
+    q.init = {"pt": PG_INIT_PT, "zero": PG_INIT_ZERO}[init] if isinstance(init, str) else int(init)
+    q.final_gather = int(final_gather)
+    q.cell_shift = int(cell_shift)
+    q.schedule = int(schedule)
+    q.flags = int(flags)
+    return q
+
+
+def resolved_schedule(q: Params) -> str:
+    """Name of the propagation schedule a call with these params uses."""
+    return {PG_SCHED_SHIFTED: "shifted"}.get(q.schedule, "two-pass")
+
+
+def _K(paths: DevicePaths, k: int) -> int:
+    return min(int(k), paths.n_vertices)
+
+
+def pg_version() -> str:
+    return lib().pg_version().decode()
+
+
+def pg_default_cell_shift(n_vertices: int) -> int:
+    return int(lib().pg_default_cell_shift(int(n_vertices)))
+
+
+def pg_knn(paths: DevicePaths, k: int, cell_shift: int = 0):
+    """Neighbour lists: (row_ptr int64[N+1], col int32[N*K])."""
+    torch = _torch()
+    L, s = lib(), paths.struct()
+    nb = ctypes.c_size_t()
+    _check(L.pg_knn_workspace_size(ctypes.byref(s), int(k), int(cell_shift), ctypes.byref(nb)))
+    _, ws, n = _workspace(nb.value, paths.device)
+    N, K = paths.n_vertices, _K(paths, k)
+    row_ptr = torch.empty(N + 1, dtype=torch.int64, device=paths.device)
+    col = torch.empty(N * K, dtype=torch.int32, device=paths.device)
+    _check(L.pg_knn(ctypes.byref(s), int(k), int(cell_shift), _ptr(row_ptr), _ptr(col), _ptr(ws), n,
+                    _stream(paths.device)))
+    return row_ptr, col
+
+
+def pg_edges(paths: DevicePaths, q: Params, row_ptr, col):
+    """Aggregation weights and direct terms: dict of w_ind, w_ph, w_env [N*K],
+    b, d_pt, lplus0 [N,3]."""
+    torch = _torch()
+    L, s = lib(), paths.struct()
+    nb = ctypes.c_size_t()
+    _check(L.pg_edges_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)))
+    _, ws, n = _workspace(nb.value, paths.device)
+    N, K = paths.n_vertices, _K(paths, q.k)
+    f = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=paths.device)  # noqa: E731
+    out = {"w_ind": f(N * K), "w_ph": f(N * K), "w_env": f(N * K), "b": f(N, 3), "d_pt": f(N, 3),
+           "lplus0": f(N, 3)}
+    _check(L.pg_edges(ctypes.byref(s), ctypes.byref(q), _ptr(row_ptr), _ptr(col), _ptr(out["w_ind"]),
+                      _ptr(out["w_ph"]), _ptr(out["w_env"]), _ptr(out["b"]), _ptr(out["d_pt"]),
+                      _ptr(out["lplus0"]), _ptr(ws), n, _stream(paths.device)))
+    return out
+
+
+def pg_propagate(paths: DevicePaths, q: Params, row_ptr, col, w_ind, b, lplus, traj: bool = False):
+    """D iterations of aggregation + propagation.  lplus (L_0, [N,3]) is
+    updated in place to L_D; with traj also returns L_1..L_D [D,N,3]."""
+    torch = _torch()
+    L, s = lib(), paths.struct()
+    nb = ctypes.c_size_t()
+    _check(L.pg_propagate_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)))
+    _, ws, n = _workspace(nb.value, paths.device)
+    tr = torch.empty(q.D, paths.n_vertices, 3, dtype=torch.float32, device=paths.device) if traj else None
+    _check(L.pg_propagate(ctypes.byref(s), ctypes.byref(q), _ptr(row_ptr), _ptr(col), _ptr(w_ind), _ptr(b),
+                          _ptr(lplus), _ptr(tr), _ptr(ws), n, _stream(paths.device)))
+    return (lplus, tr) if traj else lplus
+
+
+def pg_gather(paths: DevicePaths, q: Params, row_ptr, col, w_ind, d_pt, lplus):
+    """Pixel radiance [H, W, 3]."""
+    torch = _torch()
+    s = paths.struct()
+    image = torch.empty(paths.height, paths.width, 3, dtype=torch.float32, device=paths.device)
+    _check(lib().pg_gather(ctypes.byref(s), ctypes.byref(q), _ptr(row_ptr), _ptr(col), _ptr(w_ind), _ptr(d_pt),
+                           _ptr(lplus), _ptr(image), _stream(paths.device)))
+    return image
+
+
+class Renderer:
+    """Holds the workspace of repeated pg_render calls on one set of paths."""
+
+    def __init__(self, paths: DevicePaths, q: Params):
+        L = lib()
+        self.paths, self.q = paths, q
+        self.s = paths.struct()
+        nb = ctypes.c_size_t()
+        _check(L.pg_render_workspace_size(ctypes.byref(self.s), ctypes.byref(q), ctypes.byref(nb)))
+        self._buf, self.ws, self.ws_bytes = _workspace(nb.value, paths.device)
+
+    def __call__(self, image=None, graph: dict | None = None):
+        torch = _torch()
+        if image is None:
+            image = torch.empty(self.paths.height, self.paths.width, 3, dtype=torch.float32,
+                                device=self.paths.device)
+        out = None
+        if graph is not None:
+            out = GraphOut()
+            for name, t in graph.items():
+                setattr(out, name, t.data_ptr())
+        _check(lib().pg_render(ctypes.byref(self.s), ctypes.byref(self.q), _ptr(image),
+                               ctypes.byref(out) if out is not None else None, _ptr(self.ws), self.ws_bytes,
+                               _stream(self.paths.device)))
+        return image
+
+
+def pg_render(paths: DevicePaths, q: Params, graph: bool = False):
+    """Image [H, W, 3]; with graph=True also the path-order graph
+    (row_ptr, col, w_ind, w_ph, w_env, b, d_pt, lplus)."""
+    torch = _torch()
+    g = None
+    if graph:
+        N, K = paths.n_vertices, _K(paths, q.k)
+        f = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=paths.device)  # noqa: E731
+        g = {"row_ptr": torch.empty(N + 1, dtype=torch.int64, device=paths.device),
+             "col": torch.empty(N * K, dtype=torch.int32, device=paths.device),
+             "w_ind": f(N * K), "w_ph": f(N * K), "w_env": f(N * K), "b": f(N, 3), "d_pt": f(N, 3),
+             "lplus": f(N, 3)}
+    image = Renderer(paths, q)(graph=g)
+    return (image, g) if graph else image

@@ -1,0 +1,94 @@
+// pg_api_common.h -- host-side helpers shared by the entry points: error
+// reporting, workspace carving and the render pipeline used by pg_render,
+// pg_backward and pg_render_batched.
+#pragma once
+
+#include <string>
+
+#include "pg_internal.h"
+
+namespace pg {
+
+extern thread_local std::string g_error;
+pg_status fail(pg_status code, const char* fmt, ...);
+pg_status hip_fail(hipError_t e, const char* where);
+pg_status validate_paths(const pg_paths* p, bool need_records);
+pg_status validate_params(const pg_params* q);
+pg_status check_ws(void* ws, size_t ws_bytes, size_t need);
+pg_status finish(hipStream_t s, const pg_params* q, const int32_t* dflag, uint32_t flags);
+Consts make_consts(const pg_params* q, int K);
+int32_t default_shift(int64_t N);
+int shift_of(const pg_params* q, int64_t N);
+
+// Brackets one kernel step with HIP events on its stream while profiling is on.
+struct ProfScope {
+    int slot = -1;
+    hipStream_t s;
+    ProfScope(hipStream_t stream, const char* name);
+    ~ProfScope();
+};
+
+// Sub-allocates a workspace in 256-byte aligned pieces.  With a NULL base it
+// only measures.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+    template <class T>
+    T* take(int64_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += (size_t)(count > 0 ? count : 0) * sizeof(T);
+        return p;
+    }
+    size_t size() const { return (off + 255) & ~(size_t)255; }
+};
+
+struct GridBufs {
+    int shift = 0;
+    int64_t ncells = 0;
+    int32_t* flag = nullptr;
+    uint32_t* cells = nullptr;     // counts, then cell_start (ncells + 1)
+    uint32_t* partials = nullptr;
+    uint32_t* cellid = nullptr;
+    uint32_t* rank = nullptr;
+    int32_t* perm = nullptr;       // sorted -> path order
+    int32_t* inv = nullptr;        // path order -> sorted
+    uint64_t* qs = nullptr;        // sorted packed quantised positions
+};
+
+void carve_grid(Carver& cv, GridBufs& g, int64_t N, int shift);
+hipError_t run_grid(const pg_paths* p, GridBufs& g, VRec* rec, hipStream_t s);
+
+// Every buffer of one render in the internal (spatially sorted) order.
+struct RenderBufs {
+    GridBufs g;
+    int64_t N = 0, P = 0;
+    int K = 0, D = 0, schedule = 0;
+    bool tape = false;
+    VRec* rec = nullptr;
+    int32_t* col = nullptr;   // [N*K] sorted ids, row-major
+    float* w = nullptr;       // [N*K]
+    float* gw = nullptr;      // [N*K] dw/dg (tape)
+    float* b = nullptr;       // [N*3]
+    float* dpt = nullptr;     // [N*3]
+    float* r = nullptr;       // [N]
+    float* alpha = nullptr;   // [N]
+    int32_t* succ = nullptr;  // [N]
+    int32_t* pred = nullptr;  // [N] (tape)
+    float* x = nullptr;       // [N*3]
+    float* y = nullptr;       // [N*3]
+    int32_t* mcol = nullptr;  // shifted schedule
+    float* mw = nullptr;
+    float* c = nullptr;
+    float* traj = nullptr;    // [(D+1)*N*3] (tape)
+};
+
+int resolve_schedule(const pg_params* q);
+void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params* q);
+// Runs grid, kNN, edges, paths, D iterations and pixels; fills `out` if given.
+// *final_x receives the buffer holding L_D (sorted order).
+hipError_t run_render(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out, float* image,
+                      hipStream_t s, float** final_x = nullptr);
+
+}  // namespace pg

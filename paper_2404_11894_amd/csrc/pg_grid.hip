@@ -1,0 +1,386 @@
+// pg_grid.hip -- uniform-grid build (counting sort) and exact k-nearest-
+// neighbour query on quantised integer coordinates.
+//
+// The paper builds a hash grid over the shading points and searches the
+// neighbouring bins (Sec. "Rendering System", path graph solver).  Here the
+// neighbourhood of vertex i is exact: i first, then the K-1 nearest others by
+// (squared distance of the 20-bit quantised positions, path-order id).
+//
+// Grid: cell = q >> shift per axis, G = 2^(20-shift) cells per axis, cells
+// numbered in Morton order so that a sort by cell keeps space-filling-curve
+// locality.  Counting sort = atomic histogram (which also yields each
+// vertex's rank inside its cell) + exclusive scan + scatter.  The order of
+// vertices inside a cell is not deterministic; nothing downstream depends on
+// it (every comparison breaks ties by path-order id).
+#include "pg_internal.h"
+
+namespace pg {
+
+__device__ inline uint32_t quant(float x) {
+    float s = floorf(x * 1048576.0f);   // exact: scaling by 2^20
+    if (!(s >= 0.0f)) s = 0.0f;          // also NaN
+    if (s > (float)kQMax) s = (float)kQMax;
+    return (uint32_t)s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_quantize_count(int64_t N, const float* __restrict__ pos, int shift,
+                                                           uint32_t* __restrict__ count,
+                                                           uint32_t* __restrict__ cellid,
+                                                           uint32_t* __restrict__ rank, int32_t* flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    if (!(x >= 0.0f && x <= 1.0f && y >= 0.0f && y <= 1.0f && z >= 0.0f && z <= 1.0f)) set_flag(flag, kFlagPos);
+    uint32_t c = morton3(quant(x) >> shift, quant(y) >> shift, quant(z) >> shift);
+    cellid[i] = c;
+    rank[i] = atomicAdd(&count[c], 1u);
+}
+
+hipError_t launch_quantize_count(int64_t N, const float* pos, int shift, uint32_t* count, uint32_t* cellid,
+                                 uint32_t* rank, int32_t* flag, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_quantize_count, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, pos, shift,
+                       count, cellid, rank, flag);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ scan ---
+// Exclusive prefix sum of uint32 counts, out[n] = total.  Three passes:
+// per-block totals, a scan of the block totals, per-block scans with offset.
+// Inside a block: per-thread serial sums, a wave-level inclusive scan with
+// lane shuffles, and a scan of the wave totals through LDS.
+
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ inline uint32_t wave_inclusive(uint32_t v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, kWave);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// exclusive scan across the block of one value per thread; returns the
+// thread's exclusive prefix and the block total.
+__device__ inline uint32_t block_exclusive(uint32_t v, uint32_t& total) {
+    __shared__ uint32_t wsum[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    uint32_t inc = wave_inclusive(v);
+    if (lane == kWave - 1) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        uint32_t x = wsum[w];
+        if (w < wid) off += x;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                        uint32_t* __restrict__ partials) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) s += in[base + k];
+    uint32_t total;
+    block_exclusive(s, total);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+// one block scans nb partials in tiles, carrying the running offset
+__global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* __restrict__ partials, int64_t nb) {
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nb; base += kScanTile) {
+        int64_t i0 = base + (int64_t)threadIdx.x * kScanItems;
+        uint32_t v[kScanItems];
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = (i0 + k < nb) ? partials[i0 + k] : 0u;
+            s += v[k];
+        }
+        uint32_t total;
+        uint32_t ex = block_exclusive(s, total) + carry;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (i0 + k < nb) partials[i0 + k] = ex;
+            ex += v[k];
+        }
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* in, uint32_t* out, int64_t n,
+                                                      const uint32_t* __restrict__ partials) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t total;
+    uint32_t ex = block_exclusive(s, total) + partials[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+    // the last element of the last block closes the prefix sum
+    if (base < n && base + kScanItems >= n) out[n] = ex;
+}
+
+size_t scan_partials_bytes(int64_t n) { return (size_t)(div_up(n, kScanTile) + 1) * sizeof(uint32_t); }
+
+hipError_t launch_scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials,
+                                 hipStream_t s) {
+    if (n <= 0) return hipErrorInvalidValue;
+    int64_t nb = div_up(n, kScanTile);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, partials, nb);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, partials);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- scatter ---
+
+// Cell-centred trilinear albedo of a grid [R][R][R] (z, y, x).
+__device__ inline float trilerp_alpha(const float* grid, int R, float px, float py, float pz) {
+    uint32_t idx[8];
+    float w[8];
+    trilerp_corners(R, px, py, pz, idx, w);
+    float a = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) a = fmaf(w[c], grid[idx[c]], a);
+    return a;
+}
+
+__device__ inline void fill_record(const pg_paths& P, int64_t v, VRec& r) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.t[a] = P.dir_in[3 * v + a];
+        r.w[a] = P.dir_out[3 * v + a];
+        r.we[a] = P.dir_env[3 * v + a];
+        r.ls[a] = P.l_sun[3 * v + a];
+        r.le[a] = P.l_env[3 * v + a];
+        r.lp[a] = P.l_phase[3 * v + a];
+    }
+    r.alpha = P.albedo_grid ? trilerp_alpha(P.albedo_grid, P.albedo_grid_res, P.pos[3 * v], P.pos[3 * v + 1],
+                                            P.pos[3 * v + 2])
+                            : P.albedo[v];
+    r.pad = 0.0f;
+}
+
+__device__ inline void store_record(VRec* dst, const VRec& r) {
+    const float4* s4 = reinterpret_cast<const float4*>(&r);
+    float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) d4[k] = s4[k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(int64_t N, pg_paths P, int shift,
+                                                    const uint32_t* __restrict__ cellid,
+                                                    const uint32_t* __restrict__ rank,
+                                                    const uint32_t* __restrict__ cell_start,
+                                                    int32_t* __restrict__ perm, int32_t* __restrict__ inv,
+                                                    uint64_t* __restrict__ qsorted, VRec* __restrict__ rec) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    (void)shift;
+    int64_t s = (int64_t)cell_start[cellid[v]] + rank[v];
+    perm[s] = (int32_t)v;
+    inv[v] = (int32_t)s;
+    qsorted[s] = qpack(quant(P.pos[3 * v]), quant(P.pos[3 * v + 1]), quant(P.pos[3 * v + 2]));
+    if (rec) {
+        VRec r;
+        fill_record(P, v, r);
+        store_record(rec + s, r);
+    }
+}
+
+hipError_t launch_scatter(int64_t N, const pg_paths& paths, int shift, const uint32_t* cellid,
+                          const uint32_t* rank, const uint32_t* cell_start, int32_t* perm, int32_t* inv,
+                          uint64_t* qsorted, VRec* rec, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, paths, shift, cellid,
+                       rank, cell_start, perm, inv, qsorted, rec);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_records(int64_t N, pg_paths P, VRec* __restrict__ rec,
+                                                         int32_t* flag) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    float x = P.pos[3 * v], y = P.pos[3 * v + 1], z = P.pos[3 * v + 2];
+    if (!(x >= 0.0f && x <= 1.0f && y >= 0.0f && y <= 1.0f && z >= 0.0f && z <= 1.0f)) set_flag(flag, kFlagPos);
+    VRec r;
+    fill_record(P, v, r);
+    store_record(rec + v, r);
+}
+
+__global__ __launch_bounds__(kBlock) void k_alpha(int64_t N, pg_paths P, float* __restrict__ alpha) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    alpha[v] = P.albedo_grid ? trilerp_alpha(P.albedo_grid, P.albedo_grid_res, P.pos[3 * v], P.pos[3 * v + 1],
+                                             P.pos[3 * v + 2])
+                             : P.albedo[v];
+}
+
+hipError_t launch_alpha(int64_t N, const pg_paths& paths, float* alpha, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_alpha, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, paths, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_records(int64_t N, const pg_paths& paths, VRec* rec, int32_t* flag, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_records, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, paths, rec,
+                       flag);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- kNN ---
+// One query per thread, queries in cell (Morton) order so that the lanes of a
+// wave visit the same cells.  The K-1 best candidates live in registers,
+// sorted ascending by (d2, id) and right-aligned in an array of KM slots; the
+// KM-(K-1) leading slots hold (0, 0), which no candidate can move past, so the
+// current worst is always slot KM-1 and every index is a compile-time
+// constant.  Cells are searched in Chebyshev shells r = 0, 1, 2, ...; after a
+// shell every unvisited vertex is at least `gap` quantisation steps away on
+// some axis, so the search stops once the worst kept distance is < gap^2 (a
+// candidate at exactly gap could still win on a smaller id).
+
+__device__ inline bool key_less(uint64_t d1, uint32_t o1, uint64_t d2, uint32_t o2) {
+    return d1 < d2 || (d1 == d2 && o1 < o2);
+}
+
+template <int KM>
+__global__ __launch_bounds__(kBlock) void k_knn(int64_t N, int K, int shift, const uint64_t* __restrict__ qs,
+                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ inv,
+                                                const uint32_t* __restrict__ cell_start,
+                                                int32_t* __restrict__ col_sorted, int32_t* __restrict__ col_canon,
+                                                int64_t* __restrict__ row_ptr) {
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t s = tile * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const int m = K - 1;
+    const int G = 1 << (kQBits - shift);
+    int32_t qx, qy, qz;
+    qunpack(qs[s], qx, qy, qz);
+    const uint32_t self = (uint32_t)perm[s];
+
+    uint64_t d[KM];
+    uint32_t o[KM];
+#pragma unroll
+    for (int p = 0; p < KM; ++p) {
+        const bool sentinel = p < KM - m;
+        d[p] = sentinel ? 0ull : ~0ull;
+        o[p] = sentinel ? 0u : ~0u;
+    }
+
+    if (m > 0) {
+        const int cx = qx >> shift, cy = qy >> shift, cz = qz >> shift;
+        for (int r = 0;; ++r) {
+            for (int dz = -r; dz <= r; ++dz) {
+                const int z = cz + dz;
+                if (z < 0 || z >= G) continue;
+                for (int dy = -r; dy <= r; ++dy) {
+                    const int y = cy + dy;
+                    if (y < 0 || y >= G) continue;
+                    const bool face = (dz == -r || dz == r || dy == -r || dy == r);
+                    const int step = (face || r == 0) ? 1 : 2 * r;
+                    for (int dx = -r; dx <= r; dx += step) {
+                        const int x = cx + dx;
+                        if (x < 0 || x >= G) continue;
+                        const uint32_t cell = morton3((uint32_t)x, (uint32_t)y, (uint32_t)z);
+                        const uint32_t beg = cell_start[cell], end = cell_start[cell + 1];
+                        for (uint32_t t = beg; t < end; ++t) {
+                            if ((int64_t)t == s) continue;
+                            int32_t ax, ay, az;
+                            qunpack(qs[t], ax, ay, az);
+                            const int64_t ex = ax - qx, ey = ay - qy, ez = az - qz;
+                            const uint64_t d2 = (uint64_t)(ex * ex + ey * ey + ez * ez);
+                            const uint32_t oid = (uint32_t)perm[t];
+                            if (key_less(d2, oid, d[KM - 1], o[KM - 1])) {
+                                d[KM - 1] = d2;
+                                o[KM - 1] = oid;
+#pragma unroll
+                                for (int p = KM - 1; p > 0; --p) {
+                                    const bool sw = key_less(d[p], o[p], d[p - 1], o[p - 1]);
+                                    const uint64_t td = d[p];
+                                    const uint32_t to = o[p];
+                                    d[p] = sw ? d[p - 1] : d[p];
+                                    o[p] = sw ? o[p - 1] : o[p];
+                                    d[p - 1] = sw ? td : d[p - 1];
+                                    o[p - 1] = sw ? to : o[p - 1];
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            // smallest per-axis distance from q to a cell outside the searched cube
+            int64_t gap = INT64_MAX;
+            const int c3[3] = {cx, cy, cz};
+            const int64_t q3[3] = {qx, qy, qz};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (c3[a] - r > 0) gap = min(gap, q3[a] - ((int64_t)(c3[a] - r) << shift) + 1);
+                if (c3[a] + r < G - 1) gap = min(gap, ((int64_t)(c3[a] + r + 1) << shift) - q3[a]);
+            }
+            if (gap == INT64_MAX) break;                    // the whole grid was searched
+            if (d[KM - 1] < (uint64_t)(gap * gap)) break;   // list full and provably final
+        }
+    }
+
+    if (col_sorted) {
+        int32_t* row = col_sorted + s * K;
+        row[0] = (int32_t)s;
+#pragma unroll
+        for (int p = 0; p < KM; ++p)
+            if (p >= KM - m) row[1 + p - (KM - m)] = inv[o[p]];
+    }
+    if (col_canon) {
+        int32_t* row = col_canon + (int64_t)self * K;
+        row[0] = (int32_t)self;
+#pragma unroll
+        for (int p = 0; p < KM; ++p)
+            if (p >= KM - m) row[1 + p - (KM - m)] = (int32_t)o[p];
+    }
+    if (row_ptr) {
+        row_ptr[self] = (int64_t)self * K;
+        if (s == 0) row_ptr[N] = N * (int64_t)K;
+    }
+}
+
+hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, const int32_t* perm,
+                      const int32_t* inv, const uint32_t* cell_start, int32_t* col_sorted, int32_t* col_canon,
+                      int64_t* row_ptr, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    dim3 grid((unsigned)div_up(N, kBlock)), block(kBlock);
+    const int m = K - 1;
+    if (m <= 8)
+        hipLaunchKernelGGL(k_knn<8>, grid, block, 0, s, N, K, shift, qsorted, perm, inv, cell_start, col_sorted,
+                           col_canon, row_ptr);
+    else if (m <= 16)
+        hipLaunchKernelGGL(k_knn<16>, grid, block, 0, s, N, K, shift, qsorted, perm, inv, cell_start, col_sorted,
+                           col_canon, row_ptr);
+    else if (m <= 32)
+        hipLaunchKernelGGL(k_knn<32>, grid, block, 0, s, N, K, shift, qsorted, perm, inv, cell_start, col_sorted,
+                           col_canon, row_ptr);
+    else
+        hipLaunchKernelGGL(k_knn<64>, grid, block, 0, s, N, K, shift, qsorted, perm, inv, cell_start, col_sorted,
+                           col_canon, row_ptr);
+    return hipGetLastError();
+}
+
+}  // namespace pg

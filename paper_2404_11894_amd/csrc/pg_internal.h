@@ -1,0 +1,242 @@
+// pg_internal.h -- device helpers and launch wrappers shared by the HIP
+// translation units of the path-graph library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <type_traits>
+
+#include "../../include/pathgraph.h"
+
+namespace pg {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kQBits = 20;                    // quantisation bits per axis
+constexpr uint32_t kQMax = (1u << kQBits) - 1u;
+constexpr int kMinShift = 11;                 // finest grid: 2^(20-11) = 512 cells per axis
+constexpr float kPi = 3.14159265358979323846f;
+
+// Device error flags (bit mask in one int32 of the workspace).
+enum : int32_t {
+    kFlagPos = 1,       // non-finite or out-of-range position
+    kFlagOffsets = 2,   // path offsets not monotone / out of range
+    kFlagIndex = 4,     // neighbour id out of range in caller-provided CSR
+};
+
+// ---------------------------------------------------------------- helpers --
+
+__host__ __device__ inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// XCD-aware block order.  The hardware hands block b to XCD b % 8; remap so
+// every XCD works on one contiguous range of tiles, which keeps the spatially
+// sorted rows that share neighbours on the same L2.
+__device__ inline int64_t xcd_tile(int64_t b, int64_t nb) {
+    const int64_t q = nb >> 3, rem = nb & 7;
+    const int64_t x = b & 7, k = b >> 3;
+    return x < rem ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
+}
+
+// Spread the low 10 bits of v to every third bit.
+__host__ __device__ inline uint32_t part1by2(uint32_t v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__host__ __device__ inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return part1by2(x) | (part1by2(y) << 1) | (part1by2(z) << 2);
+}
+
+// Quantised coordinates packed 21 bits apart.
+__device__ inline uint64_t qpack(uint32_t x, uint32_t y, uint32_t z) {
+    return (uint64_t)x | ((uint64_t)y << 21) | ((uint64_t)z << 42);
+}
+__device__ inline void qunpack(uint64_t p, int32_t& x, int32_t& y, int32_t& z) {
+    x = (int32_t)(p & 0x1fffffu);
+    y = (int32_t)((p >> 21) & 0x1fffffu);
+    z = (int32_t)((p >> 42) & 0x1fffffu);
+}
+
+struct f3 { float x, y, z; };
+
+__device__ inline f3 ld3(const float* p, int64_t i) { return f3{p[3 * i], p[3 * i + 1], p[3 * i + 2]}; }
+__device__ inline void st3(float* p, int64_t i, f3 v) { p[3 * i] = v.x; p[3 * i + 1] = v.y; p[3 * i + 2] = v.z; }
+
+// Henyey-Greenstein density as a function of u = 1 - cos between unit
+// vectors, u = |a - b|^2 / 2:  HG = (1-g^2) / (4 pi ((1-g)^2 + 2 g u)^(3/2)).
+struct HG {
+    float c;    // (1 - g^2) / (4 pi)
+    float a;    // (1 - g)^2
+    float two_g;
+    __host__ __device__ static HG make(float g) {
+        HG h;
+        h.c = (1.0f - g * g) / (4.0f * kPi);
+        h.a = (1.0f - g) * (1.0f - g);
+        h.two_g = 2.0f * g;
+        return h;
+    }
+    __device__ float operator()(float u) const {
+        float den = fmaf(two_g, u, a);
+        float r = __frsqrt_rn(den);
+        return c * r * r * r;
+    }
+};
+
+__device__ inline float one_minus_cos(f3 a, f3 b) {
+    float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    return 0.5f * fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
+
+// d ln HG / d g at u:  -2g/(1-g^2) - 3 (g - cos) / ((1-g)^2 + 2 g u).
+__device__ inline float hg_dlog(float g, float u) {
+    float den = fmaf(2.0f * g, u, (1.0f - g) * (1.0f - g));
+    return -2.0f * g / (1.0f - g * g) - 3.0f * (g - (1.0f - u)) / den;
+}
+
+// Cell-centred trilinear interpolation weights on an R^3 grid ([z][y][x]):
+// per axis u = R x - 0.5, i0 = floor(u), f = u - i0; corner indices i0 and
+// i0+1 are each clamped to [0, R-1], the weights (1-f, f) are kept.
+__device__ inline void trilerp_corners(int R, float px, float py, float pz, uint32_t idx[8], float w[8]) {
+    const float p[3] = {px, py, pz};
+    int lo[3], hi[3];
+    float f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float u = (float)R * p[a] - 0.5f;
+        float fl = floorf(u);
+        f[a] = u - fl;
+        int l = (int)fl;
+        lo[a] = min(max(l, 0), R - 1);
+        hi[a] = min(max(l + 1, 0), R - 1);
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+        const uint32_t ix = bx ? hi[0] : lo[0], iy = by ? hi[1] : lo[1], iz = bz ? hi[2] : lo[2];
+        idx[c] = (iz * (uint32_t)R + iy) * (uint32_t)R + ix;
+        w[c] = (bx ? f[0] : 1.0f - f[0]) * (by ? f[1] : 1.0f - f[1]) * (bz ? f[2] : 1.0f - f[2]);
+    }
+}
+
+// Record a device-detected input error (flag may be NULL).
+__device__ inline void set_flag(int32_t* flag, int32_t bit) {
+    if (flag) atomicOr(flag, bit);
+}
+
+// Calls go(std::integral_constant<int, KP>) with KP the smallest power of two >= K.
+template <typename F>
+inline void dispatch_kp(int K, F&& go) {
+    if (K <= 1) go(std::integral_constant<int, 1>{});
+    else if (K <= 2) go(std::integral_constant<int, 2>{});
+    else if (K <= 4) go(std::integral_constant<int, 4>{});
+    else if (K <= 8) go(std::integral_constant<int, 8>{});
+    else if (K <= 16) go(std::integral_constant<int, 16>{});
+    else if (K <= 32) go(std::integral_constant<int, 32>{});
+    else go(std::integral_constant<int, 64>{});
+}
+
+// Sum over aligned groups of KP lanes (KP a power of two <= 64).
+template <int KP>
+__device__ inline float group_sum(float v) {
+#pragma unroll
+    for (int o = KP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Vertex record in the internal (spatially sorted) order: everything the
+// aggregation step reads about a neighbour, 80 bytes, 16-byte aligned.
+struct alignas(16) VRec {
+    float t[3];      // dir_in
+    float w[3];      // dir_out
+    float we[3];     // dir_env
+    float ls[3];     // l_sun
+    float le[3];     // l_env
+    float lp[3];     // l_phase
+    float alpha;     // albedo
+    float pad;
+};
+static_assert(sizeof(VRec) == 80, "VRec layout");
+
+// Uniform method constants for the kernels.
+struct Consts {
+    HG rho;          // receiver phase (g)
+    HG pdf;          // sampling pdf (g_s)
+    float g;
+    float env_pdf;
+    f3 sun;
+    int32_t K;
+    int32_t init;
+    int32_t final_gather;
+};
+
+// ------------------------------------------------------- launch wrappers ---
+// Each returns hipSuccess or the launch error.  All take the stream last.
+
+// grid build: quantise + histogram, exclusive scan, scatter into cell order
+hipError_t launch_quantize_count(int64_t N, const float* pos, int shift, uint32_t* count, uint32_t* cellid,
+                                 uint32_t* rank, int32_t* flag, hipStream_t s);
+size_t scan_partials_bytes(int64_t n);
+hipError_t launch_scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials,
+                                 hipStream_t s);
+hipError_t launch_scatter(int64_t N, const pg_paths& paths, int shift, const uint32_t* cellid,
+                          const uint32_t* rank, const uint32_t* cell_start, int32_t* perm, int32_t* inv,
+                          uint64_t* qsorted, VRec* rec, hipStream_t s);
+hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, const int32_t* perm,
+                      const int32_t* inv, const uint32_t* cell_start, int32_t* col_sorted, int32_t* col_canon,
+                      int64_t* row_ptr, hipStream_t s);
+
+// records in path order (no permutation)
+hipError_t launch_pack_records(int64_t N, const pg_paths& paths, VRec* rec, int32_t* flag, hipStream_t s);
+
+// aggregation operators over row-major CSR in the records' id space.
+// canon_row (nullable) maps local row -> path-order row for the optional
+// path-order outputs.
+struct EdgeOut {
+    float* w;            // [N*K] local order (required)
+    float* gw;           // [N*K] dw/dg, or NULL
+    float* b;            // [N] f3 local
+    float* dpt;          // [N] f3 local
+    float* r;            // [N] local
+    float* alpha;        // [N] local
+    const int32_t* canon_row;
+    float* w_ind;        // path order, nullable
+    float* w_ph;
+    float* w_env;
+    float* b_canon;
+    float* dpt_canon;
+};
+hipError_t launch_edges(int64_t N, const Consts& c, const int32_t* col, const VRec* rec, const EdgeOut& o,
+                        int32_t* flag, hipStream_t s);
+
+// per-path pass: successor / predecessor in local ids and the initial L
+hipError_t launch_paths(int64_t P, int64_t N, const int64_t* off, const int32_t* inv, const float* alpha,
+                        const float* dpt, const float* r, int init, int32_t* succ, int32_t* pred, float* x0,
+                        int32_t* flag, hipStream_t s);
+
+// propagation
+hipError_t launch_spmv(int64_t N, int K, const int32_t* col, const float* w, const float* x, const float* b,
+                       const float* alpha, float* y, hipStream_t s);
+hipError_t launch_shift(int64_t N, const int32_t* succ, const float* y, float* x, hipStream_t s);
+hipError_t launch_shifted_build(int64_t N, int K, const int32_t* succ, const int32_t* col, const float* w,
+                                const float* b, const float* alpha, int32_t* mcol, float* mw, float* c,
+                                hipStream_t s);
+hipError_t launch_spmv_shifted(int64_t N, int K, const int32_t* succ, const int32_t* mcol, const float* mw,
+                               const float* c, const float* x, float* xn, hipStream_t s);
+
+// output to pixels; inv (nullable) maps path-order vertex -> local id
+hipError_t launch_pixels(const pg_paths& paths, const Consts& c, const int32_t* inv, const int32_t* col,
+                         const float* w, const float* x, const float* dpt, const float* r, const float* alpha,
+                         float* image, int32_t* flag, hipStream_t s);
+
+// small utilities
+hipError_t launch_permute3(int64_t N, const int32_t* idx, const float* src, float* dst, int gather,
+                           hipStream_t s);
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_fill_value(void* p, size_t bytes, uint32_t v, hipStream_t s);
+hipError_t launch_alpha(int64_t N, const pg_paths& paths, float* alpha, hipStream_t s);
+
+}  // namespace pg

@@ -1,0 +1,125 @@
+// pg_render.hip -- the forward pipeline in the internal, spatially sorted
+// layout: grid build and kNN, aggregation operators, per-path pass, D
+// iterations of aggregation + propagation, output to pixels.  Host code.
+#include "pg_api_common.h"
+
+namespace pg {
+
+int resolve_schedule(const pg_params* q) { return q->schedule ? q->schedule : PG_SCHED_TWO_PASS; }
+
+void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params* q) {
+    const int64_t N = p->n_vertices;
+    r.N = N;
+    r.P = p->n_paths;
+    r.K = (int)(N < q->k ? N : q->k);
+    r.D = q->D;
+    r.schedule = resolve_schedule(q);
+    r.tape = (q->flags & PG_FLAG_TAPE) != 0;
+    const int64_t E = N * (int64_t)r.K;
+    carve_grid(cv, r.g, N, shift_of(q, N));
+    r.rec = cv.take<VRec>(N);
+    r.col = cv.take<int32_t>(E);
+    r.w = cv.take<float>(E);
+    r.gw = r.tape ? cv.take<float>(E) : nullptr;
+    r.b = cv.take<float>(3 * N);
+    r.dpt = cv.take<float>(3 * N);
+    r.r = cv.take<float>(N);
+    r.alpha = cv.take<float>(N);
+    r.succ = cv.take<int32_t>(N);
+    r.pred = r.tape ? cv.take<int32_t>(N) : nullptr;
+    r.x = cv.take<float>(3 * N);
+    r.y = cv.take<float>(3 * N);
+    if (r.schedule == PG_SCHED_SHIFTED) {
+        r.mcol = cv.take<int32_t>(E);
+        r.mw = cv.take<float>(E);
+        r.c = cv.take<float>(3 * N);
+    }
+    r.traj = r.tape ? cv.take<float>((int64_t)(r.D + 1) * 3 * N) : nullptr;
+}
+
+#define PG_TRY(x)                              \
+    do {                                       \
+        hipError_t e_ = (x);                   \
+        if (e_ != hipSuccess) return e_;       \
+    } while (0)
+
+hipError_t run_render(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out, float* image,
+                      hipStream_t s, float** final_x) {
+    const int64_t N = r.N;
+    const int K = r.K;
+    GridBufs& g = r.g;
+    {
+        ProfScope ps(s, "grid");
+        PG_TRY(run_grid(p, g, r.rec, s));
+    }
+    if (N == 0) {
+        if (out && out->row_ptr) PG_TRY(launch_fill(out->row_ptr, sizeof(int64_t), s));
+    } else {
+        ProfScope ps(s, "knn");
+        PG_TRY(launch_knn(N, K, g.shift, g.qs, g.perm, g.inv, g.cells, r.col, out ? out->col : nullptr,
+                          out ? out->row_ptr : nullptr, s));
+    }
+    const Consts c = make_consts(q, K);
+    EdgeOut o{};
+    o.w = r.w;
+    o.gw = r.gw;
+    o.b = r.b;
+    o.dpt = r.dpt;
+    o.r = r.r;
+    o.alpha = r.alpha;
+    o.canon_row = g.perm;
+    if (out) {
+        o.w_ind = out->w_ind;
+        o.w_ph = out->w_ph;
+        o.w_env = out->w_env;
+        o.b_canon = out->b;
+        o.dpt_canon = out->d_pt;
+    }
+    {
+        ProfScope ps(s, "edges");
+        PG_TRY(launch_edges(N, c, r.col, r.rec, o, g.flag, s));
+    }
+
+    float* x0 = r.tape ? r.traj : r.x;
+    PG_TRY(launch_fill_value(r.succ, (size_t)N * 4, 0xffffffffu, s));
+    if (r.pred) PG_TRY(launch_fill_value(r.pred, (size_t)N * 4, 0xffffffffu, s));
+    PG_TRY(launch_fill(x0, (size_t)N * 12, s));
+    {
+        ProfScope ps(s, "paths");
+        PG_TRY(launch_paths(r.P, N, p->path_offsets, g.inv, r.alpha, r.dpt, r.r, q->init, r.succ, r.pred, x0,
+                            g.flag, s));
+    }
+
+    float* cur = x0;
+    if (r.schedule == PG_SCHED_SHIFTED) {
+        ProfScope ps(s, "shifted_build");
+        PG_TRY(launch_shifted_build(N, K, r.succ, r.col, r.w, r.b, r.alpha, r.mcol, r.mw, r.c, s));
+    }
+    for (int t = 1; t <= r.D; ++t) {
+        float* nxt;
+        if (r.tape) nxt = r.traj + (size_t)t * N * 3;
+        else if (r.schedule == PG_SCHED_SHIFTED) nxt = (cur == r.x) ? r.y : r.x;
+        else nxt = r.x;
+        if (r.schedule == PG_SCHED_SHIFTED) {
+            ProfScope ps(s, "spmv_shifted");
+            PG_TRY(launch_spmv_shifted(N, K, r.succ, r.mcol, r.mw, r.c, cur, nxt, s));
+        } else {
+            {
+                ProfScope ps(s, "spmv");
+                PG_TRY(launch_spmv(N, K, r.col, r.w, cur, r.b, r.alpha, r.y, s));
+            }
+            ProfScope ps(s, "shift");
+            PG_TRY(launch_shift(N, r.succ, r.y, nxt, s));
+        }
+        cur = nxt;
+    }
+    {
+        ProfScope ps(s, "pixels");
+        PG_TRY(launch_pixels(*p, c, g.inv, r.col, r.w, cur, r.dpt, r.r, r.alpha, image, g.flag, s));
+    }
+    if (out && out->lplus) PG_TRY(launch_permute3(N, g.perm, cur, out->lplus, 0, s));
+    if (final_x) *final_x = cur;
+    return hipSuccess;
+}
+
+}  // namespace pg

@@ -1,0 +1,132 @@
+"""The C ABI library on the CPU: it loads, exports every symbol the header
+declares, and rejects invalid arguments on the host before touching a GPU."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_2404_11894_amd as pg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pathgraph.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]*?\b(pg_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared()
+    assert "pg_render" in names and "pg_backward" in names and "pg_render_batched" in names
+    lib = pg.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(pg.EXPORTS)
+
+
+def test_version_and_default_shift():
+    assert pg.pg_version().startswith("pathgraph-gfx950")
+    assert pg.pg_default_cell_shift(0) == 20
+    assert pg.pg_default_cell_shift(30000) == 16      # 16^3 <= 30000 < 32^3
+    assert pg.pg_default_cell_shift(22_000_000) == 12
+    assert pg.pg_default_cell_shift(10 ** 12) == 11   # capped at 512 cells per axis
+
+
+def fake_paths(N=100, P=16, w=4, h=4, spp=1):
+    """A paths struct with non-NULL dummy pointers; never dereferenced on the host."""
+    s = pg.Paths()
+    s.n_vertices, s.n_paths, s.width, s.height, s.spp = N, P, w, h, spp
+    for name in ("path_offsets", "pos", "dir_in", "dir_out", "albedo", "l_sun", "dir_env", "l_env",
+                 "l_phase", "e_cam"):
+        setattr(s, name, 0x1000)
+    return s
+
+
+def status(fn, *args):
+    rc = fn(*args)
+    return rc, pg.lib().pg_last_error().decode()
+
+
+def test_workspace_queries_validate_arguments():
+    L = pg.lib()
+    s, q = fake_paths(), pg.params(k=8, D=4)
+    nb = ctypes.c_size_t()
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == 0
+    assert nb.value > 0 and nb.value % 256 == 0
+    small = nb.value
+    q.flags = pg.PG_FLAG_TAPE
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == 0
+    assert nb.value > small                 # the tape keeps every iterate
+    for bad in (dict(k=0), dict(k=65), dict(D=-1), dict(g=1.0), dict(g=0.3, g_s=-1.0), dict(env_pdf=0.0),
+                dict(init=2), dict(final_gather=3), dict(cell_shift=5), dict(schedule=9), dict(flags=64)):
+        kw = dict(k=8, D=4)
+        kw.update(bad)
+        qq = pg.params(**{k: v for k, v in kw.items() if k in ("k", "D", "g", "g_s", "env_pdf", "init",
+                                                                "final_gather", "cell_shift", "schedule",
+                                                                "flags")})
+        rc, msg = status(L.pg_render_workspace_size, ctypes.byref(s), ctypes.byref(qq), ctypes.byref(nb))
+        assert rc == pg.PG_ERR_ARG, (bad, rc)
+        assert msg
+    qq = pg.params(k=8, D=4)
+    qq.sun_dir[1] = math.nan
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(qq), ctypes.byref(nb)) == pg.PG_ERR_ARG
+
+
+def test_paths_validation():
+    L = pg.lib()
+    q = pg.params()
+    nb = ctypes.c_size_t()
+    s = fake_paths(P=15)          # P != w*h*spp
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == pg.PG_ERR_ARG
+    s = fake_paths(N=-1)
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == pg.PG_ERR_ARG
+    s = fake_paths(N=2 ** 31)
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == pg.PG_ERR_ARG
+    s = fake_paths()
+    s.dir_env = None
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == pg.PG_ERR_ARG
+    s = fake_paths()
+    s.albedo = None               # neither per-vertex albedo nor a grid
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == pg.PG_ERR_ARG
+    s.albedo_grid, s.albedo_grid_res = 0x2000, 64
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == 0
+    s = fake_paths(N=0)
+    s.pos = s.dir_in = None       # nothing to read when there are no vertices
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == 0
+    assert L.pg_render_workspace_size(None, ctypes.byref(q), ctypes.byref(nb)) == pg.PG_ERR_ARG
+    assert L.pg_render_workspace_size(ctypes.byref(s), None, ctypes.byref(nb)) == pg.PG_ERR_ARG
+
+
+def test_calls_reject_bad_workspace_before_launching():
+    L = pg.lib()
+    s, q = fake_paths(), pg.params(k=8, D=4)
+    nb = ctypes.c_size_t()
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == 0
+    img = ctypes.c_void_p(0x3000)
+    rc, msg = status(L.pg_render, ctypes.byref(s), ctypes.byref(q), img, None, None, nb.value, None)
+    assert rc == pg.PG_ERR_WORKSPACE and "NULL" in msg
+    rc, msg = status(L.pg_render, ctypes.byref(s), ctypes.byref(q), img, None, ctypes.c_void_p(0x10100),
+                     nb.value - 1, None)
+    assert rc == pg.PG_ERR_WORKSPACE and "too small" in msg
+    rc, msg = status(L.pg_render, ctypes.byref(s), ctypes.byref(q), img, None, ctypes.c_void_p(0x10010),
+                     nb.value, None)
+    assert rc == pg.PG_ERR_WORKSPACE and "aligned" in msg
+    rc, _ = status(L.pg_render, ctypes.byref(s), ctypes.byref(q), None, None, ctypes.c_void_p(0x10100),
+                   nb.value, None)
+    assert rc == pg.PG_ERR_ARG
+    rc, _ = status(L.pg_knn, ctypes.byref(s), 0, 0, ctypes.c_void_p(0x4000), ctypes.c_void_p(0x5000), None, 0,
+                   None)
+    assert rc == pg.PG_ERR_ARG
+    rc, _ = status(L.pg_gather, ctypes.byref(s), ctypes.byref(q), None, None, None, None, None,
+                   ctypes.c_void_p(0x3000), None)
+    assert rc == pg.PG_ERR_ARG
+
+
+def test_product_path_refuses_to_run_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(pg, "_lib", None)
+    monkeypatch.setattr(pg, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="has not been built"):
+        pg.lib()

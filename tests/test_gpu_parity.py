@@ -1,0 +1,195 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Neighbour lists and CSR layout must match bit for bit; weights and direct
+terms within one FP32 evaluation; propagated radiance and pixels within
+|err| <= max(1e-4 |ref|, 1e-5).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+import paper_2404_11894_amd as pg
+from tests.gpu_util import (PIX_ABS, PIX_REL, W_ABS, W_REL, assert_within, crop, synthetic)
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_render(scene, k, D, g, g_s=None, init="pt", fg=0, schedule=0, shift=0, grid=None):
+    paths = pg.DevicePaths(scene, albedo_grid=grid)
+    q = pg.params(k=k, D=D, g=g, g_s=g_s, init=init, final_gather=fg, schedule=schedule, cell_shift=shift,
+                  flags=pg.PG_FLAG_CHECK)
+    img, gr = pg.pg_render(paths, q, graph=True)
+    torch.cuda.synchronize()
+    return img.cpu().numpy(), {n: t.cpu().numpy() for n, t in gr.items()}
+
+
+def compare_all(scene, k, img, gr, ref_img, ref, what=""):
+    N = scene.n_vertices
+    K = min(k, N)
+    assert np.array_equal(gr["row_ptr"], np.arange(N + 1, dtype=np.int64) * K), what
+    assert np.array_equal(gr["col"].reshape(N, K), ref["col"]), what + " col"
+    for name in ("w_ind", "w_ph", "w_env"):
+        assert_within(gr[name].reshape(N, K), ref[name], W_REL, W_ABS, f"{what} {name}")
+    assert_within(gr["b"], ref["b"], W_REL, W_ABS, f"{what} b")
+    assert_within(gr["d_pt"], ref["d_pt"], W_REL, W_ABS, f"{what} d_pt")
+    assert_within(gr["lplus"], ref["lplus"], PIX_REL, PIX_ABS, f"{what} lplus")
+    assert_within(img, ref_img, PIX_REL, PIX_ABS, f"{what} image")
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return scenegen.generate(scenegen.WORKLOADS["tiny"].scene)
+
+
+@pytest.mark.parametrize("schedule", [pg.PG_SCHED_TWO_PASS, pg.PG_SCHED_SHIFTED])
+def test_render_tiny_matches_oracle(tiny, schedule):
+    w = scenegen.WORKLOADS["tiny"]
+    print(f"tiny N={tiny.n_vertices} schedule={schedule}", flush=True)
+    img, gr = gpu_render(tiny, w.k, w.D, w.g, schedule=schedule)
+    ref_img, ref = oracle.render(tiny, oracle.params(k=w.k, D=w.D, g=w.g), trace=True)
+    compare_all(tiny, w.k, img, gr, ref_img, ref, f"tiny/sched{schedule}")
+
+
+@pytest.mark.parametrize("init,fg,g_s", [("zero", 0, None), ("pt", 1, None), ("pt", 0, 0.3), ("zero", 1, 0.7)])
+def test_render_variants(init, fg, g_s):
+    sc = crop("tiny", 32, 32, 2)
+    print(f"variant init={init} fg={fg} g_s={g_s} N={sc.n_vertices}", flush=True)
+    img, gr = gpu_render(sc, 8, 6, 0.5, g_s=g_s, init=init, fg=fg)
+    ref_img, ref = oracle.render(sc, oracle.params(k=8, D=6, g=0.5, g_s=g_s, init=init, final_gather=fg),
+                                 trace=True)
+    compare_all(sc, 8, img, gr, ref_img, ref, f"{init}/{fg}/{g_s}")
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 12, 16, 33, 64])
+def test_neighbour_counts(k):
+    sc = crop("tiny", 24, 24, 2)
+    print(f"k={k} N={sc.n_vertices}", flush=True)
+    img, gr = gpu_render(sc, k, 4, 0.5)
+    ref_img, ref = oracle.render(sc, oracle.params(k=k, D=4, g=0.5), trace=True)
+    compare_all(sc, k, img, gr, ref_img, ref, f"k={k}")
+
+
+def test_neighbours_invariant_to_cell_size(tiny):
+    ref = None
+    for shift in (12, 14, 15, 16, 17, 18, 20):
+        print(f"shift={shift}", flush=True)
+        paths = pg.DevicePaths(tiny)
+        rp, col = pg.pg_knn(paths, 8, shift)
+        col = col.cpu().numpy()
+        if ref is None:
+            ref = oracle.knn(tiny.pos, 8).ravel()
+        assert np.array_equal(col, ref), f"shift {shift}"
+
+
+def test_entry_points_compose(tiny):
+    """pg_knn -> pg_edges -> pg_propagate -> pg_gather equals pg_render and the oracle."""
+    w = scenegen.WORKLOADS["tiny"]
+    paths = pg.DevicePaths(tiny)
+    q = pg.params(k=w.k, D=w.D, g=w.g, flags=pg.PG_FLAG_CHECK)
+    rp, col = pg.pg_knn(paths, w.k)
+    e = pg.pg_edges(paths, q, rp, col)
+    lplus = e["lplus0"].clone()
+    lplus, traj = pg.pg_propagate(paths, q, rp, col, e["w_ind"], e["b"], lplus, traj=True)
+    # pg_gather takes no workspace, so it has no device flag to report through
+    img = pg.pg_gather(paths, pg.params(k=w.k, D=w.D, g=w.g), rp, col, e["w_ind"], e["d_pt"], lplus)
+    torch.cuda.synchronize()
+    ref_img, ref = oracle.render(tiny, oracle.params(k=w.k, D=w.D, g=w.g), trace=True, traj=True)
+    N, K = tiny.n_vertices, w.k
+    assert np.array_equal(col.cpu().numpy().reshape(N, K), ref["col"])
+    assert_within(e["w_ind"].cpu().numpy().reshape(N, K), ref["w_ind"], W_REL, W_ABS, "w_ind")
+    assert_within(e["b"].cpu().numpy(), ref["b"], W_REL, W_ABS, "b")
+    assert_within(e["lplus0"].cpu().numpy(), ref["lplus0"], W_REL, W_ABS, "lplus0")
+    assert_within(traj.cpu().numpy(), ref["traj"][1:], PIX_REL, PIX_ABS, "trajectory")
+    assert_within(img.cpu().numpy(), ref_img, PIX_REL, PIX_ABS, "image")
+    img2 = pg.pg_render(paths, q)
+    torch.cuda.synchronize()
+    assert_within(img.cpu().numpy(), img2.cpu().numpy(), 1e-6, 1e-9, "render vs composed")
+
+
+def test_render_is_deterministic(tiny):
+    w = scenegen.WORKLOADS["tiny"]
+    a = gpu_render(tiny, w.k, w.D, w.g)
+    b = gpu_render(tiny, w.k, w.D, w.g)
+    assert np.array_equal(a[0], b[0])
+    for n in a[1]:
+        assert np.array_equal(a[1][n], b[1][n]), n
+
+
+def test_albedo_grid_render(tiny):
+    rng = np.random.default_rng(2)
+    grid = rng.uniform(0.6, 0.99, size=(16, 16, 16)).astype(np.float32)
+    w = scenegen.WORKLOADS["tiny"]
+    img, gr = gpu_render(tiny, w.k, w.D, w.g, grid=grid)
+    alpha = oracle.albedo_from_grid(tiny.pos, grid)
+    ref_img, ref = oracle.render(tiny, oracle.params(k=w.k, D=w.D, g=w.g), alpha=alpha, trace=True)
+    compare_all(tiny, w.k, img, gr, ref_img, ref, "albedo grid")
+
+
+# ------------------------------------------------------------ edge cases ---
+
+def test_hand_derived_example():
+    from tests.golden.fixtures import load
+    sc, d = load("two_paths_isotropic.json")
+    for case in d["cases"]:
+        img, gr = gpu_render(sc, d["k"], case["D"], d["g"], init=case["init"], fg=case["final_gather"])
+        assert gr["col"].reshape(3, 2).tolist() == d["expected_col"]
+        assert np.allclose(img[0, :, 1], case["image"], rtol=1e-6), case
+
+
+def test_no_vertices():
+    rng = np.random.default_rng(0)
+    P = 4 * 4 * 2
+    z = np.zeros((0, 3), np.float32)
+    sc = scenegen.Scene(width=4, height=4, spp=2, path_offsets=np.zeros(P + 1, np.int64), pos=z, dir_in=z,
+                        dir_out=z, albedo=np.zeros(0, np.float32), l_sun=z, dir_env=z, l_env=z, l_phase=z,
+                        e_cam=rng.random((P, 3), dtype=np.float32))
+    paths = pg.DevicePaths(sc)
+    img = pg.pg_render(paths, pg.params(k=8, D=3, flags=pg.PG_FLAG_CHECK))
+    torch.cuda.synchronize()
+    assert_within(img.cpu().numpy(), sc.e_cam.reshape(4, 4, 2, 3).mean(2), 1e-6, 1e-7, "empty")
+
+
+def test_fewer_vertices_than_k():
+    rng = np.random.default_rng(1)
+    sc = synthetic(rng.random((5, 3)), rng)
+    img, gr = gpu_render(sc, 8, 3, 0.4)
+    ref_img, ref = oracle.render(sc, oracle.params(k=8, D=3, g=0.4), trace=True)
+    compare_all(sc, 8, img, gr, ref_img, ref, "N<k")
+
+
+def test_duplicate_positions():
+    rng = np.random.default_rng(2)
+    sc = synthetic(np.full((300, 3), 0.37), rng, lengths=np.full(30, 10))
+    img, gr = gpu_render(sc, 8, 5, 0.6)
+    ref_img, ref = oracle.render(sc, oracle.params(k=8, D=5, g=0.6), trace=True)
+    compare_all(sc, 8, img, gr, ref_img, ref, "duplicates")
+
+
+def test_lattice_ties():
+    rng = np.random.default_rng(3)
+    g = np.array([(x, y, z) for z in range(8) for y in range(8) for x in range(8)], np.float64)
+    pos = ((g + 0.5) / 8.0).astype(np.float32)
+    sc = synthetic(pos, rng, lengths=np.full(64, 8))
+    for k in (7, 19, 27):
+        img, gr = gpu_render(sc, k, 4, 0.3)
+        ref_img, ref = oracle.render(sc, oracle.params(k=k, D=4, g=0.3), trace=True)
+        compare_all(sc, k, img, gr, ref_img, ref, f"lattice k={k}")
+
+
+def test_device_input_errors_are_reported():
+    rng = np.random.default_rng(4)
+    sc = synthetic(rng.random((64, 3)), rng, lengths=np.full(8, 8))
+    sc.pos[5, 1] = np.nan
+    paths = pg.DevicePaths(sc)
+    with pytest.raises(pg.PathGraphError) as e:
+        pg.pg_render(paths, pg.params(k=4, D=2, flags=pg.PG_FLAG_CHECK))
+    assert e.value.code == pg.PG_ERR_INPUT
+    sc = synthetic(rng.random((64, 3)), rng, lengths=np.full(8, 8))
+    sc.path_offsets[3] = 40   # path 2 = [16, 40), path 3 = [40, 32): not monotone
+    paths = pg.DevicePaths(sc)
+    with pytest.raises(pg.PathGraphError) as e:
+        pg.pg_render(paths, pg.params(k=4, D=2, flags=pg.PG_FLAG_CHECK))
+    assert e.value.code == pg.PG_ERR_INPUT
+    torch.cuda.synchronize()
