@@ -332,10 +332,18 @@ int or_albedo_from_grid(int64_t n, const float* pos, int32_t R, const float* gri
 
 typedef struct {
     int64_t N, P, K;
+    int keep;       /* 1: traj holds every iterate t = 0..D; 0: three rotating slots */
     int32_t* col;
     double *wi, *wp, *we, *dagg, *b, *dpt, *r, *alpha;
-    double* traj;   /* (D+1) * N * 3 */
+    double* traj;   /* (D+1) * N * 3 when keep, else 3 * N * 3 */
 } fwd_state;
+
+/* iterate t inside the state's storage */
+static double* iterate(const fwd_state* f, int t, int D) {
+    (void)D;
+    size_t slot = f->keep ? (size_t)t : (t == 0 ? 0u : (size_t)(1 + (t & 1)));
+    return f->traj + slot * (size_t)f->N * 3;
+}
 
 static void free_state(fwd_state* f) {
     free(f->col); free(f->wi); free(f->wp); free(f->we); free(f->dagg); free(f->b);
@@ -356,7 +364,7 @@ static int validate(const or_scene* s, const or_params* p) {
 
 /* Runs steps 1-7.  alpha_override (N doubles) replaces the scene albedo when
  * not NULL.  Fills the forward state (every iterate kept) and the image. */
-static int forward(const or_scene* s, const or_params* p, const double* alpha_override,
+static int forward(const or_scene* s, const or_params* p, const double* alpha_override, int keep,
                    fwd_state* f, double* image, double* out_path) {
     int rc = validate(s, p);
     if (rc) return rc;
@@ -364,7 +372,7 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
     const int64_t K = N == 0 ? 0 : (p->k < N ? p->k : N);
     const int D = p->D;
     memset(f, 0, sizeof(*f));
-    f->N = N; f->P = P; f->K = K;
+    f->N = N; f->P = P; f->K = K; f->keep = keep;
     size_t nE = (size_t)(N * K > 0 ? N * K : 1), n3 = (size_t)(N > 0 ? N * 3 : 1);
     f->col = (int32_t*)malloc(nE * sizeof(int32_t));
     f->wi = (double*)malloc(nE * sizeof(double));
@@ -375,7 +383,7 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
     f->dpt = (double*)malloc(n3 * sizeof(double));
     f->r = (double*)malloc((N > 0 ? N : 1) * sizeof(double));
     f->alpha = (double*)malloc((N > 0 ? N : 1) * sizeof(double));
-    f->traj = (double*)calloc((size_t)(D + 1) * n3, sizeof(double));
+    f->traj = (double*)calloc((size_t)(keep ? D + 1 : 3) * n3, sizeof(double));
     if (!f->col || !f->wi || !f->wp || !f->we || !f->dagg || !f->b || !f->dpt || !f->r || !f->alpha || !f->traj) {
         free_state(f);
         return OR_ERR_NOMEM;
@@ -413,8 +421,8 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
     double* y = (double*)malloc(n3 * sizeof(double));
     if (!y) { free_state(f); return OR_ERR_NOMEM; }
     for (int t = 1; t <= D; ++t) {
-        const double* Lp = f->traj + (size_t)(t - 1) * N * 3;
-        double* Ln = f->traj + (size_t)t * N * 3;
+        const double* Lp = iterate(f, t - 1, D);
+        double* Ln = iterate(f, t, D);
         for (int64_t i = 0; i < N; ++i) {
             double z[3] = {0.0, 0.0, 0.0};
             for (int64_t a = 0; a < K; ++a) {
@@ -433,7 +441,7 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
     /* step 7: output of each path's first continuation edge, then pixels.
      * o_p = alpha_v0 (d_pt_v0 + sum_j w+_v0j L+_D(j))   (final_gather == 0)
      * o_p = alpha_v0 (d_pt_v0 + r_v0 L+_D(v0))          (final_gather == 1) */
-    const double* LD = f->traj + (size_t)D * N * 3;
+    const double* LD = iterate(f, D, D);
     const int64_t npix = (int64_t)s->width * s->height;
     for (int64_t px = 0; px < npix * 3; ++px) image[px] = 0.0;
     for (int64_t q = 0; q < P; ++q) {
@@ -463,7 +471,7 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
 int or_render(const or_scene* s, const or_params* p, const double* alpha_override, double* image,
               or_trace* tr) {
     fwd_state f;
-    int rc = forward(s, p, alpha_override, &f, image, tr ? tr->out_path : NULL);
+    int rc = forward(s, p, alpha_override, tr && tr->traj ? 1 : 0, &f, image, tr ? tr->out_path : NULL);
     if (rc) return rc;
     if (tr) {
         const int64_t N = f.N, K = f.K;
@@ -476,7 +484,7 @@ int or_render(const or_scene* s, const or_params* p, const double* alpha_overrid
         if (tr->d_pt) memcpy(tr->d_pt, f.dpt, (size_t)(N * 3) * sizeof(double));
         if (tr->r) memcpy(tr->r, f.r, (size_t)N * sizeof(double));
         if (tr->lplus0) memcpy(tr->lplus0, f.traj, (size_t)(N * 3) * sizeof(double));
-        if (tr->lplus) memcpy(tr->lplus, f.traj + (size_t)p->D * N * 3, (size_t)(N * 3) * sizeof(double));
+        if (tr->lplus) memcpy(tr->lplus, iterate(&f, p->D, p->D), (size_t)(N * 3) * sizeof(double));
         if (tr->traj) memcpy(tr->traj, f.traj, (size_t)(p->D + 1) * N * 3 * sizeof(double));
     }
     free_state(&f);
@@ -505,7 +513,7 @@ int or_backward(const or_scene* s, const or_params* p, int32_t R, const float* g
         or_albedo_from_grid(N, s->pos, R, grid, alpha);
     }
     fwd_state f;
-    int rc = forward(s, p, alpha, &f, image, NULL);
+    int rc = forward(s, p, alpha, 1, &f, image, NULL);
     if (rc) { free(alpha); return rc; }
     const int64_t P = s->n_paths, K = f.K;
     const int D = p->D;
