@@ -225,13 +225,32 @@ pg_status pg_backward(const pg_paths* paths, const pg_params* params, const floa
                       void* stream);
 
 /* ---- batching (project addition; not in the paper) ------------------------
- * Renders n_scenes independent scenes (each with its own paths and params)
- * with every step launched once for all scenes; images[s] receives scene s.
- * The same result as n_scenes pg_render calls. */
+ * Renders n_scenes independent scenes (each with its own paths and params;
+ * k, D, g, cell size may differ) into images[s] ([height_s][width_s][3]).
+ * The one-time steps run per scene; every one of the D iterations is one
+ * launch for all scenes of a neighbour-count class plus one shift launch.
+ * The result equals n_scenes pg_render calls (two-pass schedule).  The call
+ * synchronises the stream once, after copying its small scene table. */
 pg_status pg_render_batched_workspace_size(int32_t n_scenes, const pg_paths* paths, const pg_params* params,
                                            size_t* bytes);
 pg_status pg_render_batched(int32_t n_scenes, const pg_paths* paths, const pg_params* params,
                             float* const* images, void* ws, size_t ws_bytes, void* stream);
+
+/* A reusable batch: the same scenes rendered again and again (new input
+ * VALUES in the same device arrays are picked up by every launch).  With
+ * use_graph != 0 the whole sequence -- per-scene setup spread over four
+ * streams, the batched iterations, per-scene output -- is captured once in a
+ * hipGraph and every pg_batch_launch is a single graph launch.  The plan keeps
+ * the pointers it was given (paths arrays, images, workspace), which must stay
+ * valid and unchanged until pg_batch_destroy; it owns only host memory, three
+ * streams, events and the graph.  The workspace size is
+ * pg_render_batched_workspace_size's.  Launches of one plan must not overlap.
+ * Capture needs a created stream (not the null stream). */
+typedef struct pg_batch pg_batch;
+pg_status pg_batch_create(int32_t n_scenes, const pg_paths* paths, const pg_params* params, float* const* images,
+                          void* ws, size_t ws_bytes, int32_t use_graph, void* stream, pg_batch** plan);
+pg_status pg_batch_launch(pg_batch* plan, void* stream);
+pg_status pg_batch_destroy(pg_batch* plan);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,8 @@ EXPORTS = ("pg_version", "pg_last_error", "pg_default_cell_shift", "pg_profile_s
            "pg_knn_workspace_size", "pg_knn", "pg_edges_workspace_size", "pg_edges",
            "pg_propagate_workspace_size", "pg_propagate", "pg_gather",
            "pg_render_workspace_size", "pg_render", "pg_backward_workspace_size", "pg_backward",
-           "pg_render_batched_workspace_size", "pg_render_batched")
+           "pg_render_batched_workspace_size", "pg_render_batched", "pg_batch_create", "pg_batch_launch",
+           "pg_batch_destroy")
 
 
 class PathGraphError(RuntimeError):
@@ -89,6 +90,9 @@ def lib():
             "pg_backward": (i32, [P, Q, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
             "pg_render_batched_workspace_size": (i32, [i32, P, Q, sz]),
             "pg_render_batched": (i32, [i32, P, Q, vp, vp, ctypes.c_size_t, vp]),
+            "pg_batch_create": (i32, [i32, P, Q, vp, vp, ctypes.c_size_t, i32, vp, ctypes.POINTER(vp)]),
+            "pg_batch_launch": (i32, [vp, vp]),
+            "pg_batch_destroy": (i32, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -300,3 +304,146 @@ def pg_render(paths: DevicePaths, q: Params, graph: bool = False):
              "lplus": f(N, 3)}
     image = Renderer(paths, q)(graph=g)
     return (image, g) if graph else image
+
+
+def pg_backward(paths: DevicePaths, q: Params, grad_image, grad_grid=True, grad_albedo=False, grad_g=True,
+                workspace=None):
+    """Reverse mode: gradient of sum(grad_image * image) w.r.t. the albedo
+    grid (paths.albedo_grid), the per-vertex albedo and g.  ``workspace`` is a
+    (tensor, bytes) pair holding a PG_FLAG_TAPE render's tape, or None to
+    recompute the forward pass."""
+    torch = _torch()
+    L, s = lib(), paths.struct()
+    if workspace is None:
+        nb = ctypes.c_size_t()
+        _check(L.pg_backward_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)))
+        _, ws, n = _workspace(nb.value, paths.device)
+    else:
+        ws, n = workspace
+    gi = grad_image.to(device=paths.device, dtype=torch.float32).contiguous()
+    out = {}
+    gg = gr = ga = None
+    if grad_grid and paths.albedo_grid is not None:
+        gr = torch.empty_like(paths.albedo_grid)
+        out["grad_grid"] = gr
+    if grad_albedo:
+        ga = torch.empty(paths.n_vertices, dtype=torch.float32, device=paths.device)
+        out["grad_albedo"] = ga
+    if grad_g:
+        gg = torch.empty(1, dtype=torch.float32, device=paths.device)
+        out["grad_g"] = gg
+    _check(L.pg_backward(ctypes.byref(s), ctypes.byref(q), _ptr(gi), _ptr(gr), _ptr(ga), _ptr(gg), _ptr(ws), n,
+                         _stream(paths.device)))
+    return out
+
+
+def _render_function():
+    torch = _torch()
+
+    class RenderFunction(torch.autograd.Function):
+        """image = render(albedo grid, g) with the paths and sampling pdfs fixed.
+        forward: pg_render with PG_FLAG_TAPE; backward: pg_backward on the tape."""
+
+        @staticmethod
+        def forward(ctx, grid, g, paths, q):
+            qq = Params.from_buffer_copy(q)
+            qq.g = float(g)
+            qq.flags = qq.flags | PG_FLAG_TAPE
+            paths.set_albedo_grid(grid.detach())
+            s = paths.struct()
+            nb = ctypes.c_size_t()
+            _check(lib().pg_render_workspace_size(ctypes.byref(s), ctypes.byref(qq), ctypes.byref(nb)))
+            buf, ws, n = _workspace(nb.value, paths.device)
+            image = torch.empty(paths.height, paths.width, 3, dtype=torch.float32, device=paths.device)
+            _check(lib().pg_render(ctypes.byref(s), ctypes.byref(qq), _ptr(image), None, _ptr(ws), n,
+                                   _stream(paths.device)))
+            ctx.paths, ctx.q, ctx.ws = paths, qq, (buf, ws, n)
+            return image
+
+        @staticmethod
+        def backward(ctx, grad_image):
+            _, ws, n = ctx.ws
+            out = pg_backward(ctx.paths, ctx.q, grad_image, workspace=(ws, n))
+            ctx.ws = None
+            return out["grad_grid"], out["grad_g"].reshape(()), None, None
+
+    return RenderFunction
+
+
+_RF = None
+
+
+def render_differentiable(paths: DevicePaths, q: Params, albedo_grid, g):
+    """Image as a differentiable function of the albedo grid [R,R,R] and the
+    scalar HG parameter g (torch tensors); paths and the sampling pdfs
+    (q.g_s) stay fixed."""
+    global _RF
+    if _RF is None:
+        _RF = _render_function()
+    return _RF.apply(albedo_grid, g, paths, q)
+
+
+def _batch_structs(paths_list, params_list):
+    n = len(paths_list)
+    P = (Paths * n)(*[p.struct() for p in paths_list])
+    Q = (Params * n)(*[Params.from_buffer_copy(q) for q in params_list])
+    return n, P, Q
+
+
+def pg_render_batched(paths_list, params_list):
+    """Render independent scenes in one batched pass; returns their images."""
+    torch = _torch()
+    L = lib()
+    n, P, Q = _batch_structs(paths_list, params_list)
+    nb = ctypes.c_size_t()
+    _check(L.pg_render_batched_workspace_size(n, P, Q, ctypes.byref(nb)))
+    dev = paths_list[0].device
+    _, ws, nbytes = _workspace(nb.value, dev)
+    images = [torch.empty(p.height, p.width, 3, dtype=torch.float32, device=dev) for p in paths_list]
+    ptrs = (ctypes.c_void_p * n)(*[im.data_ptr() for im in images])
+    _check(L.pg_render_batched(n, P, Q, ptrs, _ptr(ws), nbytes, _stream(dev)))
+    return images
+
+
+class Batch:
+    """A reusable batch plan (optionally one hipGraph launch per render).
+    Work runs on a stream of its own, ordered after the current stream's work
+    and before anything enqueued on the current stream afterwards."""
+
+    def __init__(self, paths_list, params_list, use_graph=True):
+        torch = _torch()
+        L = lib()
+        self.paths_list = list(paths_list)
+        n, self._P, self._Q = _batch_structs(paths_list, params_list)
+        nb = ctypes.c_size_t()
+        _check(L.pg_render_batched_workspace_size(n, self._P, self._Q, ctypes.byref(nb)))
+        self.device = paths_list[0].device
+        self.stream = torch.cuda.Stream(self.device)
+        self._buf, self.ws, self.ws_bytes = _workspace(nb.value, self.device)
+        self.images = [torch.empty(p.height, p.width, 3, dtype=torch.float32, device=self.device)
+                       for p in paths_list]
+        self._ptrs = (ctypes.c_void_p * n)(*[im.data_ptr() for im in self.images])
+        self.handle = ctypes.c_void_p()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        _check(L.pg_batch_create(n, self._P, self._Q, self._ptrs, _ptr(self.ws), self.ws_bytes, int(use_graph),
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.handle)))
+
+    def __call__(self):
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        _check(lib().pg_batch_launch(self.handle, ctypes.c_void_p(self.stream.cuda_stream)))
+        cur.wait_stream(self.stream)
+        return self.images
+
+    def close(self):
+        if self.handle:
+            _torch().cuda.synchronize(self.device)
+            lib().pg_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

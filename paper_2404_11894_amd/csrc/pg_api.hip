@@ -362,6 +362,11 @@ pg_status pg_render_workspace_size(const pg_paths* paths, const pg_params* param
     Carver cv(nullptr);
     RenderBufs r;
     carve_render(cv, r, paths, params);
+    if (params->flags & PG_FLAG_TAPE) {
+        // room for the reverse pass too, so one workspace serves pg_render and pg_backward
+        BackBufs bb;
+        carve_back(cv, bb, r, paths);
+    }
     *bytes = cv.size();
     return PG_OK;
 }

@@ -84,8 +84,38 @@ struct RenderBufs {
     float* traj = nullptr;    // [(D+1)*N*3] (tape)
 };
 
+// Reverse-mode buffers, carved right after a render's tape.
+struct BackBufs {
+    int64_t n_rows = 0, n_out = 0, n_slots = 0;   // dL/dg partial-sum slots
+    float* lam_a = nullptr;    // adjoint of L_t, ping
+    float* lam_b = nullptr;    // pong
+    float* zbar = nullptr;     // [N*3]
+    float* abar = nullptr;     // [N] d/d albedo
+    float* bbar = nullptr;     // [N*3]
+    float* dptbar = nullptr;   // [N*3]
+    float* rbar = nullptr;     // [N]
+    uint32_t* toff = nullptr;  // transposed CSR offsets [N+1]
+    uint32_t* tcur = nullptr;  // counts, then cursors [N+1]
+    uint32_t* tpart = nullptr; // scan partials
+    int32_t* tsrc = nullptr;   // [E] source rows
+    float* tw = nullptr;       // [E]
+    double* gpart = nullptr;   // [n_slots]
+    float* image = nullptr;    // forward image when the tape is recomputed
+};
+void carve_back(Carver& cv, BackBufs& bb, const RenderBufs& r, const pg_paths* p);
+hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, BackBufs& bb, const float* gimg,
+                        float* grad_grid, float* grad_alpha, float* grad_g, hipStream_t s);
+
 int resolve_schedule(const pg_params* q);
 void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params* q);
+// The three phases of run_render: grid + kNN + edges + path pass (returns the
+// buffer holding L_0), the D iterations (returns the buffer holding L_D), and
+// the output to pixels.
+hipError_t render_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out,
+                        hipStream_t s, float** x0_out);
+hipError_t render_iterate(RenderBufs& r, float* x0, hipStream_t s, float** final_x);
+hipError_t render_output(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out,
+                         float* image, const float* cur, hipStream_t s);
 // Runs grid, kNN, edges, paths, D iterations and pixels; fills `out` if given.
 // *final_x receives the buffer holding L_D (sorted order).
 hipError_t run_render(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out, float* image,

@@ -1,20 +1,526 @@
-// pg_backward.hip -- reverse mode of the render (albedo grid and HG g).
+// pg_backward.hip -- reverse mode of the render with respect to the albedo
+// (per vertex and through a trilinear grid) and the receiver-side HG
+// parameter g, with the recorded paths and the sampling pdfs held fixed.
+//
+// Every kernel reverses one forward step, in the opposite order:
+//   output to pixels  ->  D reverse sweeps (shift^T, then aggregation^T with
+//   the transposed CSR)  ->  path-traced initial estimate (forward walk)  ->
+//   direct terms and the g-dependence of every phase evaluation  ->
+//   trilinear scatter of d/d albedo into the grid.
+// d rho / d g = rho * h(u),  h = d ln HG / d g.  Block partial sums of dL/dg
+// go to fixed slots and are reduced in a fixed order, so dL/dg does not depend
+// on scheduling; the grid scatter and the output's neighbour scatter use
+// float atomics (order-dependent in the last bits).
 #include "pg_api_common.h"
 
+namespace pg {
+
+// Sum of one double per thread over the block; the result is valid in thread 0.
+__device__ inline double block_sum_d(double v) {
+    __shared__ double sh[kBlock / kWave];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kBlock / kWave; ++w) t += sh[w];
+    return t;
+}
+
+__device__ inline float dot3(f3 a, f3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+
+// ------------------------------------------------------- transposed CSR ---
+
+// t runs over the N*K edges in row order; eidx gives their sliced-ELL slot.
+__global__ __launch_bounds__(kBlock) void k_tcount(int64_t E, int K, const int32_t* __restrict__ col,
+                                                   uint32_t* __restrict__ cnt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < E) atomicAdd(&cnt[col[eidx(t / K, (int)(t % K), K)]], 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_u32(int64_t n, const uint32_t* __restrict__ a,
+                                                     uint32_t* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_tscatter(int64_t E, int K, const int32_t* __restrict__ col,
+                                                     const float* __restrict__ w, uint32_t* __restrict__ cur,
+                                                     int32_t* __restrict__ tsrc, float* __restrict__ tw) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= E) return;
+    const int64_t i = t / K;
+    const int64_t e = eidx(i, (int)(t - i * K), K);
+    const uint32_t pos = atomicAdd(&cur[col[e]], 1u);
+    tsrc[pos] = (int32_t)i;
+    tw[pos] = w[e];
+}
+
+// each transposed row sorted by source row, so sums run in a fixed order
+__global__ __launch_bounds__(kBlock) void k_tsort(int64_t N, const uint32_t* __restrict__ toff,
+                                                  int32_t* __restrict__ tsrc, float* __restrict__ tw) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const uint32_t a = toff[j], e = toff[j + 1];
+    for (uint32_t q = a + 1; q < e; ++q) {
+        const int32_t s = tsrc[q];
+        const float ww = tw[q];
+        uint32_t p = q;
+        while (p > a && tsrc[p - 1] > s) {
+            tsrc[p] = tsrc[p - 1];
+            tw[p] = tw[p - 1];
+            --p;
+        }
+        tsrc[p] = s;
+        tw[p] = ww;
+    }
+}
+
+// ------------------------------------------------- reverse of the output ---
+// One thread per path.  o_p = alpha (d_pt + in), in = sum_l w_l L_D(j_l)
+// (own sample: r L_D(v0)); seeds the adjoint of L_D (lam), of alpha, d_pt, r.
+__global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, const int32_t* __restrict__ inv,
+                                                        const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                        const float* __restrict__ gw, const float* __restrict__ xD,
+                                                        const float* __restrict__ dpt, const float* __restrict__ r,
+                                                        const float* __restrict__ alpha,
+                                                        const float* __restrict__ gimg, float* __restrict__ abar,
+                                                        float* __restrict__ dptbar, float* __restrict__ rbar,
+                                                        float* __restrict__ lam, double* __restrict__ gpart) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double gl = 0.0;
+    const int64_t N = P.n_vertices;
+    if (p < P.n_paths) {
+        const int64_t a = P.path_offsets[p], e = P.path_offsets[p + 1];
+        if (e > a && a >= 0 && e <= N) {
+            const int64_t px = p / P.spp;
+            const int64_t s0 = inv[a];
+            const float is = 1.0f / (float)P.spp;
+            const f3 ob{gimg[3 * px] * is, gimg[3 * px + 1] * is, gimg[3 * px + 2] * is};
+            const float al = alpha[s0];
+            const f3 d = ld3(dpt, s0);
+            const f3 zb{al * ob.x, al * ob.y, al * ob.z};
+            if (c.final_gather == 0) {
+                f3 in{0.f, 0.f, 0.f}, ing{0.f, 0.f, 0.f};
+                for (int l = 0; l < c.K; ++l) {
+                    const int64_t e = eidx(s0, l, c.K);
+                    const int64_t j = col[e];
+                    const float ww = w[e], gg = gw[e];
+                    const f3 xv = ld3(xD, j);
+                    in = f3{fmaf(ww, xv.x, in.x), fmaf(ww, xv.y, in.y), fmaf(ww, xv.z, in.z)};
+                    ing = f3{fmaf(gg, xv.x, ing.x), fmaf(gg, xv.y, ing.y), fmaf(gg, xv.z, ing.z)};
+                    atomicAdd(&lam[3 * j], ww * zb.x);
+                    atomicAdd(&lam[3 * j + 1], ww * zb.y);
+                    atomicAdd(&lam[3 * j + 2], ww * zb.z);
+                }
+                abar[s0] += dot3(ob, f3{d.x + in.x, d.y + in.y, d.z + in.z});
+                gl = (double)dot3(zb, ing);
+            } else {
+                const f3 xv = ld3(xD, s0);
+                const float rr = r[s0];
+                abar[s0] += dot3(ob, f3{fmaf(rr, xv.x, d.x), fmaf(rr, xv.y, d.y), fmaf(rr, xv.z, d.z)});
+                rbar[s0] += dot3(zb, xv);
+                atomicAdd(&lam[3 * s0], rr * zb.x);
+                atomicAdd(&lam[3 * s0 + 1], rr * zb.y);
+                atomicAdd(&lam[3 * s0 + 2], rr * zb.z);
+            }
+            dptbar[3 * s0] += zb.x;
+            dptbar[3 * s0 + 1] += zb.y;
+            dptbar[3 * s0 + 2] += zb.z;
+        }
+    }
+    const double t = block_sum_d(gl);
+    if (threadIdx.x == 0) gpart[blockIdx.x] = t;
+}
+
+// --------------------------------------------- reverse of one iteration ---
+// Row i (group of KP lanes): y_i = b_i + alpha_i z_i, z_i = sum_l w_il L_{t-1}(j_l),
+// L_t(v) = y(succ v).  Adjoint of y_i is lam_t(pred i).  Accumulates
+// d/d alpha_i += <ybar, z_i>, d/d b_i += ybar, stores zbar_i = alpha_i ybar and
+// adds <zbar_i, sum_l dw_il/dg L_{t-1}(j_l)> to the block's dL/dg slot.
+template <int KP>
+__global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int K, const int32_t* __restrict__ col,
+                                                     const float* __restrict__ w, const float* __restrict__ gw,
+                                                     const float* __restrict__ xprev, const float* __restrict__ lam,
+                                                     const int32_t* __restrict__ pred,
+                                                     const float* __restrict__ alpha, float* __restrict__ abar,
+                                                     float* __restrict__ bbar, float* __restrict__ zbar,
+                                                     double* __restrict__ gpart) {
+    constexpr int GR = kBlock / KP;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x % KP;
+    const int64_t i = tile * GR + threadIdx.x / KP;
+    float zx = 0.f, zy = 0.f, zz = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+    if (i < N && lane < K) {
+        const int64_t e = eidx(i, lane, K);
+        const int64_t j = col[e];
+        const float ww = w[e], gg = gw[e];
+        const f3 xv = ld3(xprev, j);
+        zx = ww * xv.x;
+        zy = ww * xv.y;
+        zz = ww * xv.z;
+        gx = gg * xv.x;
+        gy = gg * xv.y;
+        gz = gg * xv.z;
+    }
+    zx = group_sum<KP>(zx);
+    zy = group_sum<KP>(zy);
+    zz = group_sum<KP>(zz);
+    gx = group_sum<KP>(gx);
+    gy = group_sum<KP>(gy);
+    gz = group_sum<KP>(gz);
+    double gl = 0.0;
+    if (i < N && lane == 0) {
+        const int64_t pv = pred[i];
+        const f3 yb = pv >= 0 ? ld3(lam, pv) : f3{0.f, 0.f, 0.f};
+        abar[i] += dot3(yb, f3{zx, zy, zz});
+        bbar[3 * i] += yb.x;
+        bbar[3 * i + 1] += yb.y;
+        bbar[3 * i + 2] += yb.z;
+        const float al = alpha[i];
+        const f3 zb{al * yb.x, al * yb.y, al * yb.z};
+        st3(zbar, i, zb);
+        gl = (double)dot3(zb, f3{gx, gy, gz});
+    }
+    const double t = block_sum_d(gl);
+    if (threadIdx.x == 0) gpart[tile] += t;
+}
+
+// lam_{t-1}(j) = sum over rows i with j in N(i) of w_ij zbar_i (transposed CSR).
+__global__ __launch_bounds__(kBlock) void k_rev_cols(int64_t N, const uint32_t* __restrict__ toff,
+                                                     const int32_t* __restrict__ tsrc, const float* __restrict__ tw,
+                                                     const float* __restrict__ zbar, float* __restrict__ lam) {
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t j = tile * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    for (uint32_t q = toff[j], e = toff[j + 1]; q < e; ++q) {
+        const float ww = tw[q];
+        const f3 zb = ld3(zbar, tsrc[q]);
+        ax = fmaf(ww, zb.x, ax);
+        ay = fmaf(ww, zb.y, ay);
+        az = fmaf(ww, zb.z, az);
+    }
+    st3(lam, j, f3{ax, ay, az});
+}
+
+// ------------------------------- reverse of the path-traced initial value ---
+// L_0(v) = alpha_u (d_pt_u + r_u L_0(u)), u = succ v.  Walks each path from
+// its first vertex, so lam_0(u) is complete before u passes it on.
+__global__ __launch_bounds__(kBlock) void k_pt_adjoint(int64_t P, int64_t N, const int64_t* __restrict__ off,
+                                                       const int32_t* __restrict__ inv,
+                                                       const float* __restrict__ alpha, const float* __restrict__ dpt,
+                                                       const float* __restrict__ r, const float* __restrict__ x0,
+                                                       float* __restrict__ lam, float* __restrict__ abar,
+                                                       float* __restrict__ dptbar, float* __restrict__ rbar) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int64_t a = off[p], e = off[p + 1];
+    if (a < 0 || e < a || e > N) return;
+    for (int64_t v = a; v + 1 < e; ++v) {
+        const int64_t s = inv[v], u = inv[v + 1];
+        const f3 l = ld3(lam, s);
+        const float al = alpha[u], rr = r[u];
+        const f3 d = ld3(dpt, u), xu = ld3(x0, u);
+        abar[u] += dot3(l, f3{fmaf(rr, xu.x, d.x), fmaf(rr, xu.y, d.y), fmaf(rr, xu.z, d.z)});
+        dptbar[3 * u] += al * l.x;
+        dptbar[3 * u + 1] += al * l.y;
+        dptbar[3 * u + 2] += al * l.z;
+        rbar[u] += al * dot3(l, xu);
+        lam[3 * u] = fmaf(al * rr, l.x, lam[3 * u]);
+        lam[3 * u + 1] = fmaf(al * rr, l.y, lam[3 * u + 1]);
+        lam[3 * u + 2] = fmaf(al * rr, l.z, lam[3 * u + 2]);
+    }
+}
+
+// ----------------------------------------- reverse of the direct terms ---
+// Mirrors k_edges: recomputes the weights, then
+//   d/d alpha_i += <bbar_i, d_agg_i>,
+//   dL/dg += <alpha_i bbar_i, d d_agg_i/dg> + <d_pt bar_i, d d_pt_i/dg> + rbar_i r_i h(u_w,i).
+template <int KP>
+__global__ __launch_bounds__(kBlock) void k_edges_adjoint(int64_t N, Consts c, const int32_t* __restrict__ col,
+                                                          const VRec* __restrict__ rec,
+                                                          const float* __restrict__ bbar,
+                                                          const float* __restrict__ dptbar,
+                                                          const float* __restrict__ rbar, float* __restrict__ abar,
+                                                          double* __restrict__ gpart) {
+    constexpr int GR = kBlock / KP;
+    __shared__ f3 tsh[GR][KP];
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x % KP, grp = threadIdx.x / KP;
+    const int64_t i = tile * GR + grp;
+    const int K = c.K;
+    const bool act = i < N && lane < K;
+    f3 t{0.f, 0.f, 0.f}, w{0.f, 0.f, 0.f}, we{0.f, 0.f, 0.f}, ls{0.f, 0.f, 0.f}, le{0.f, 0.f, 0.f},
+        lp{0.f, 0.f, 0.f};
+    float alpha = 0.0f;
+    if (act) {
+        const float4* r4 = reinterpret_cast<const float4*>(rec + col[eidx(i, lane, K)]);
+        float4 a0 = r4[0], a1 = r4[1], a2 = r4[2], a3 = r4[3], a4 = r4[4];
+        t = f3{a0.x, a0.y, a0.z};
+        w = f3{a0.w, a1.x, a1.y};
+        we = f3{a1.z, a1.w, a2.x};
+        ls = f3{a2.y, a2.z, a2.w};
+        le = f3{a3.x, a3.y, a3.z};
+        lp = f3{a3.w, a4.x, a4.y};
+        alpha = a4.z;
+    }
+    tsh[grp][lane] = t;
+    __syncthreads();
+    const f3 ti = tsh[grp][0];
+    float mplus = 0.0f, menv = 0.0f;
+    for (int l = 0; l < K; ++l) {
+        const f3 tl = tsh[grp][l];
+        mplus += c.pdf(one_minus_cos(tl, w));
+        menv += c.pdf(one_minus_cos(tl, we));
+    }
+    const float Kpe = (float)K * c.env_pdf;
+    const float u_w = one_minus_cos(ti, w), u_e = one_minus_cos(ti, we);
+    const float rho = c.rho(u_w), rho_e = c.rho(u_e);
+    const float wp = rho / (mplus + Kpe), wev = rho_e / (menv + Kpe);
+    const float hw = hg_dlog(c.g, u_w), he = hg_dlog(c.g, u_e);
+    // value and g-derivative of each record's contribution
+    float cx = act ? wev * le.x + wp * lp.x : 0.f, cy = act ? wev * le.y + wp * lp.y : 0.f,
+          cz = act ? wev * le.z + wp * lp.z : 0.f;
+    float hx = act ? wev * he * le.x + wp * hw * lp.x : 0.f, hy = act ? wev * he * le.y + wp * hw * lp.y : 0.f,
+          hz = act ? wev * he * le.z + wp * hw * lp.z : 0.f;
+    float sx = act ? ls.x : 0.f, sy = act ? ls.y : 0.f, sz = act ? ls.z : 0.f;
+    cx = group_sum<KP>(cx);
+    cy = group_sum<KP>(cy);
+    cz = group_sum<KP>(cz);
+    hx = group_sum<KP>(hx);
+    hy = group_sum<KP>(hy);
+    hz = group_sum<KP>(hz);
+    sx = group_sum<KP>(sx);
+    sy = group_sum<KP>(sy);
+    sz = group_sum<KP>(sz);
+    double gl = 0.0;
+    if (i < N && lane == 0) {
+        const float u_s = one_minus_cos(ti, c.sun);
+        const float rho_sun = c.rho(u_s), hs = hg_dlog(c.g, u_s);
+        const float invK = 1.0f / (float)K;
+        const f3 dagg{fmaf(rho_sun * invK, sx, cx), fmaf(rho_sun * invK, sy, cy), fmaf(rho_sun * invK, sz, cz)};
+        const f3 bb = ld3(bbar, i);
+        abar[i] += dot3(bb, dagg);
+        const f3 db{alpha * bb.x, alpha * bb.y, alpha * bb.z};
+        const float ks = rho_sun * hs * invK;
+        gl += (double)dot3(db, f3{fmaf(ks, sx, hx), fmaf(ks, sy, hy), fmaf(ks, sz, hz)});
+        // own direct term and continuation ratio
+        const float p_w = c.pdf(u_w), p_e = c.pdf(u_e);
+        const float f_env = rho_e / (p_e + c.env_pdf), f_out = rho / (p_w + c.env_pdf);
+        const f3 pb = ld3(dptbar, i);
+        const f3 dd{rho_sun * hs * ls.x + f_env * he * le.x + f_out * hw * lp.x,
+                    rho_sun * hs * ls.y + f_env * he * le.y + f_out * hw * lp.y,
+                    rho_sun * hs * ls.z + f_env * he * le.z + f_out * hw * lp.z};
+        gl += (double)dot3(pb, dd);
+        gl += (double)(rbar[i] * (rho / p_w) * hw);
+    }
+    const double tsum = block_sum_d(gl);
+    if (threadIdx.x == 0) gpart[tile] = tsum;
+}
+
+// ------------------------------------------- albedo grid and per vertex ---
+__global__ __launch_bounds__(kBlock) void k_grid_adjoint(int64_t N, pg_paths P, const int32_t* __restrict__ perm,
+                                                         const float* __restrict__ abar,
+                                                         float* __restrict__ grad_grid,
+                                                         float* __restrict__ grad_alpha) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int64_t v = perm[i];
+    const float ab = abar[i];
+    if (grad_alpha) grad_alpha[v] = ab;
+    if (grad_grid && P.albedo_grid) {
+        uint32_t idx[8];
+        float tw[8];
+        trilerp_corners(P.albedo_grid_res, P.pos[3 * v], P.pos[3 * v + 1], P.pos[3 * v + 2], idx, tw);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (tw[q] != 0.0f) atomicAdd(&grad_grid[idx[q]], ab * tw[q]);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_g(int64_t n, const double* __restrict__ gpart,
+                                                     float* __restrict__ out) {
+    double v = 0.0;
+    for (int64_t q = threadIdx.x; q < n; q += blockDim.x) v += gpart[q];
+    const double t = block_sum_d(v);
+    if (threadIdx.x == 0) out[0] = (float)t;
+}
+
+// ----------------------------------------------------------------- host ---
+
+void carve_back(Carver& cv, BackBufs& bb, const RenderBufs& r, const pg_paths* p) {
+    const int64_t N = r.N, E = N * (int64_t)r.K;
+    int kp = 1;
+    while (kp < (r.K > 0 ? r.K : 1)) kp *= 2;
+    bb.n_rows = div_up(N > 0 ? N : 1, kBlock / kp);
+    bb.n_out = div_up(r.P > 0 ? r.P : 1, kBlock);
+    bb.n_slots = 2 * bb.n_rows + bb.n_out;
+    bb.lam_a = cv.take<float>(3 * N);
+    bb.lam_b = cv.take<float>(3 * N);
+    bb.zbar = cv.take<float>(3 * N);
+    bb.abar = cv.take<float>(N);
+    bb.bbar = cv.take<float>(3 * N);
+    bb.dptbar = cv.take<float>(3 * N);
+    bb.rbar = cv.take<float>(N);
+    bb.toff = cv.take<uint32_t>(N + 1);
+    bb.tcur = cv.take<uint32_t>(N + 1);
+    bb.tpart = cv.take<uint32_t>(scan_partials_bytes(N + 1) / 4);
+    bb.tsrc = cv.take<int32_t>(E);
+    bb.tw = cv.take<float>(E);
+    bb.gpart = cv.take<double>(bb.n_slots);
+    bb.image = cv.take<float>((int64_t)p->width * p->height * 3);
+}
+
+#define PG_TRY(x)                        \
+    do {                                 \
+        hipError_t e_ = (x);             \
+        if (e_ != hipSuccess) return e_; \
+    } while (0)
+
+hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, BackBufs& bb, const float* gimg,
+                        float* grad_grid, float* grad_alpha, float* grad_g, hipStream_t s) {
+    const int64_t N = r.N, E = N * (int64_t)r.K;
+    const int K = r.K, D = r.D;
+    const Consts c = make_consts(q, K);
+    PG_TRY(launch_fill(bb.lam_a, (size_t)N * 12, s));
+    PG_TRY(launch_fill(bb.abar, (size_t)N * 4, s));
+    PG_TRY(launch_fill(bb.bbar, (size_t)N * 12, s));
+    PG_TRY(launch_fill(bb.dptbar, (size_t)N * 12, s));
+    PG_TRY(launch_fill(bb.rbar, (size_t)N * 4, s));
+    PG_TRY(launch_fill(bb.gpart, (size_t)bb.n_slots * 8, s));
+    if (grad_grid && p->albedo_grid) {
+        const int64_t R = p->albedo_grid_res;
+        PG_TRY(launch_fill(grad_grid, (size_t)(R * R * R) * 4, s));
+    }
+    if (N > 0) {
+        // transposed CSR of W (sorted ids)
+        ProfScope ps(s, "transpose");
+        PG_TRY(launch_fill(bb.tcur, (size_t)(N + 1) * 4, s));
+        hipLaunchKernelGGL(k_tcount, dim3((unsigned)div_up(E, kBlock)), dim3(kBlock), 0, s, E, K, r.col, bb.tcur);
+        PG_TRY(launch_scan_exclusive(bb.tcur, bb.toff, N, bb.tpart, s));
+        hipLaunchKernelGGL(k_copy_u32, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.toff, bb.tcur);
+        hipLaunchKernelGGL(k_tscatter, dim3((unsigned)div_up(E, kBlock)), dim3(kBlock), 0, s, E, K, r.col, r.w,
+                           bb.tcur, bb.tsrc, bb.tw);
+        hipLaunchKernelGGL(k_tsort, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.toff, bb.tsrc,
+                           bb.tw);
+        PG_TRY(hipGetLastError());
+    }
+    const float* xD = r.traj + (size_t)D * N * 3;
+    double* g_rows = bb.gpart;
+    double* g_edges = bb.gpart + bb.n_rows;
+    double* g_out = bb.gpart + 2 * bb.n_rows;
+    {
+        ProfScope ps(s, "out_adjoint");
+        hipLaunchKernelGGL(k_out_adjoint, dim3((unsigned)bb.n_out), dim3(kBlock), 0, s, *p, c, r.g.inv, r.col, r.w,
+                           r.gw, xD, r.dpt, r.r, r.alpha, gimg, bb.abar, bb.dptbar, bb.rbar, bb.lam_a, g_out);
+        PG_TRY(hipGetLastError());
+    }
+    float* lam = bb.lam_a;
+    float* lam_next = bb.lam_b;
+    for (int t = D; t >= 1 && N > 0; --t) {
+        const float* xprev = r.traj + (size_t)(t - 1) * N * 3;
+        {
+            ProfScope ps(s, "rev_rows");
+            dispatch_kp(K, [&](auto kp) {
+                constexpr int KP = decltype(kp)::value;
+                hipLaunchKernelGGL(k_rev_rows<KP>, dim3((unsigned)bb.n_rows), dim3(kBlock), 0, s, N, K, r.col,
+                                   r.w, r.gw, xprev, lam, r.pred, r.alpha, bb.abar, bb.bbar, bb.zbar, g_rows);
+            });
+        }
+        {
+            ProfScope ps(s, "rev_cols");
+            hipLaunchKernelGGL(k_rev_cols, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.toff,
+                               bb.tsrc, bb.tw, bb.zbar, lam_next);
+        }
+        PG_TRY(hipGetLastError());
+        float* tmp = lam;
+        lam = lam_next;
+        lam_next = tmp;
+    }
+    if (q->init == PG_INIT_PT && N > 0) {
+        ProfScope ps(s, "pt_adjoint");
+        hipLaunchKernelGGL(k_pt_adjoint, dim3((unsigned)div_up(r.P > 0 ? r.P : 1, kBlock)), dim3(kBlock), 0, s,
+                           r.P, N, p->path_offsets, r.g.inv, r.alpha, r.dpt, r.r, r.traj, lam, bb.abar, bb.dptbar,
+                           bb.rbar);
+        PG_TRY(hipGetLastError());
+    }
+    if (N > 0) {
+        ProfScope ps(s, "edges_adjoint");
+        dispatch_kp(K, [&](auto kp) {
+            constexpr int KP = decltype(kp)::value;
+            hipLaunchKernelGGL(k_edges_adjoint<KP>, dim3((unsigned)div_up(N, kBlock / KP)), dim3(kBlock), 0, s, N,
+                               c, r.col, r.rec, bb.bbar, bb.dptbar, bb.rbar, bb.abar, g_edges);
+        });
+        PG_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_grid_adjoint, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, *p, r.g.perm,
+                           bb.abar, grad_grid, grad_alpha);
+        PG_TRY(hipGetLastError());
+    }
+    if (grad_g) {
+        hipLaunchKernelGGL(k_reduce_g, dim3(1), dim3(kBlock), 0, s, bb.n_slots, bb.gpart, grad_g);
+        PG_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
+}  // namespace pg
+
 using namespace pg;
+
+static void carve_all(Carver& cv, RenderBufs& r, BackBufs& bb, const pg_paths* p, const pg_params* q) {
+    pg_params qt = *q;
+    qt.flags |= PG_FLAG_TAPE;
+    carve_render(cv, r, p, &qt);
+    carve_back(cv, bb, r, p);
+}
 
 extern "C" {
 
 pg_status pg_backward_workspace_size(const pg_paths* paths, const pg_params* params, size_t* bytes) {
-    (void)paths; (void)params; (void)bytes;
-    return fail(PG_ERR_UNSUPPORTED, "pg_backward: not built yet");
+    g_error.clear();
+    pg_status st;
+    if ((st = validate_paths(paths, true)) || (st = validate_params(params))) return st;
+    if (!bytes) return fail(PG_ERR_ARG, "bytes is NULL");
+    Carver cv(nullptr);
+    RenderBufs r;
+    BackBufs bb;
+    carve_all(cv, r, bb, paths, params);
+    *bytes = cv.size();
+    return PG_OK;
 }
 
 pg_status pg_backward(const pg_paths* paths, const pg_params* params, const float* grad_image, float* grad_grid,
                       float* grad_albedo, float* grad_g, void* ws, size_t ws_bytes, void* stream) {
-    (void)paths; (void)params; (void)grad_image; (void)grad_grid; (void)grad_albedo; (void)grad_g;
-    (void)ws; (void)ws_bytes; (void)stream;
-    return fail(PG_ERR_UNSUPPORTED, "pg_backward: not built yet");
+    g_error.clear();
+    pg_status st;
+    if ((st = validate_paths(paths, true)) || (st = validate_params(params))) return st;
+    if (!grad_image) return fail(PG_ERR_ARG, "grad_image is NULL");
+    if (grad_grid && !paths->albedo_grid) return fail(PG_ERR_ARG, "grad_grid needs paths->albedo_grid");
+    if (!grad_grid && !grad_albedo && !grad_g) return fail(PG_ERR_ARG, "no gradient requested");
+    if (paths->n_vertices * (int64_t)(paths->n_vertices < params->k ? paths->n_vertices : params->k) >=
+        ((int64_t)1 << 32))
+        return fail(PG_ERR_UNSUPPORTED, "pg_backward needs N*K < 2^32 edges");
+    Carver dry(nullptr);
+    RenderBufs r;
+    BackBufs bb;
+    carve_all(dry, r, bb, paths, params);
+    if ((st = check_ws(ws, ws_bytes, dry.size()))) return st;
+    Carver cv(ws);
+    carve_all(cv, r, bb, paths, params);
+    hipStream_t s = (hipStream_t)stream;
+    pg_params qt = *params;
+    qt.flags |= PG_FLAG_TAPE;
+    hipError_t e;
+    if (!(params->flags & PG_FLAG_TAPE)) {
+        e = run_render(paths, &qt, r, nullptr, bb.image, s);
+        if (e != hipSuccess) return hip_fail(e, "forward");
+    }
+    e = run_backward(paths, &qt, r, bb, grad_image, grad_grid, grad_albedo, grad_g, s);
+    if (e != hipSuccess) return hip_fail(e, "backward");
+    return finish(s, params, r.g.flag, params->flags);
 }
 
 }  // extern "C"

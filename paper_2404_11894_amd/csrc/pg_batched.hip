@@ -1,20 +1,340 @@
 // pg_batched.hip -- many independent scenes per launch.
+//
+// Each scene gets its own slice of the workspace (the same buffers as a
+// single render).  The one-time steps (grid, kNN, weights, path pass, pixels)
+// run per scene, spread over a few streams; the D iterations -- the hot loop
+// -- run as ONE spmv launch and ONE shift launch for all scenes per
+// iteration: a block finds its scene in a small descriptor table and leaves
+// at once when its scene has finished its own D iterations.
+// A pg_batch plan can capture the whole sequence in a hipGraph, so a render
+// of all scenes is one graph launch.
+#include <algorithm>
+#include <vector>
+
 #include "pg_api_common.h"
 
+namespace pg {
+
+struct SceneDesc {
+    const int32_t* col;
+    const float* w;
+    const float* b;
+    const float* alpha;
+    const int32_t* succ;
+    float* x;
+    float* y;
+    int64_t nrows;
+    int64_t blk0;     // first block of this scene in the batched launch
+    int32_t K, D;
+};
+
+__device__ inline int find_scene(const SceneDesc* sd, int n, int64_t blk) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sd[mid].blk0 <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// y_i = b_i + alpha_i sum_l w_il x(j_l) for every row of every scene still
+// iterating (t <= D_s); one thread per row over each scene's sliced-ELL edges.
+__global__ __launch_bounds__(kBlock) void k_spmv_batched(const SceneDesc* __restrict__ sd, int nsc, int t) {
+    const SceneDesc& d = sd[find_scene(sd, nsc, blockIdx.x)];
+    if (t > d.D) return;
+    const int64_t i = (blockIdx.x - d.blk0) * (int64_t)kBlock + threadIdx.x;
+    if (i >= d.nrows) return;
+    const int K = d.K;
+    const int64_t base = (i >> 6) * (int64_t)K * kSlice + (i & (kSlice - 1));
+    float ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll 4
+    for (int l = 0; l < K; ++l) {
+        const int64_t j = d.col[base + (int64_t)l * kSlice];
+        const float ww = d.w[base + (int64_t)l * kSlice];
+        const f3 xv = ld3(d.x, j);
+        ax = fmaf(ww, xv.x, ax);
+        ay = fmaf(ww, xv.y, ay);
+        az = fmaf(ww, xv.z, az);
+    }
+    const float a = d.alpha[i];
+    const f3 bb = ld3(d.b, i);
+    st3(d.y, i, f3{fmaf(a, ax, bb.x), fmaf(a, ay, bb.y), fmaf(a, az, bb.z)});
+}
+
+// x(v) = y(succ v), 0 at a path's end, for scenes still iterating.
+__global__ __launch_bounds__(kBlock) void k_shift_batched(const SceneDesc* __restrict__ sd, int nsc, int t) {
+    const SceneDesc& d = sd[find_scene(sd, nsc, blockIdx.x)];
+    if (t > d.D) return;
+    const int64_t v = (blockIdx.x - d.blk0) * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= d.nrows) return;
+    const int64_t u = d.succ[v];
+    f3 val{0.f, 0.f, 0.f};
+    if (u >= 0) val = ld3(d.y, u);
+    st3(d.x, v, val);
+}
+
+// ------------------------------------------------------------------ host ---
+
+struct BatchLayout {
+    int n = 0;
+    std::vector<RenderBufs> r;
+    std::vector<pg_params> q;
+    // one descriptor per scene with vertices; 256 rows per block
+    int64_t blocks = 0;
+    std::vector<SceneDesc> host_tables;
+    SceneDesc* dev_tables = nullptr;
+    int Dmax = 0;
+};
+
+// Carves every scene's buffers and the descriptor tables; with a real base
+// also fills the host copy of the tables.
+static void carve_batch(Carver& cv, BatchLayout& L, int n, const pg_paths* paths, const pg_params* params) {
+    L.n = n;
+    L.r.assign(n, RenderBufs());
+    L.q.assign(params, params + n);
+    for (int s = 0; s < n; ++s) {
+        L.q[s].schedule = PG_SCHED_TWO_PASS;
+        L.q[s].flags &= ~PG_FLAG_TAPE;
+        carve_render(cv, L.r[s], &paths[s], &L.q[s]);
+    }
+    L.host_tables.clear();
+    L.Dmax = 0;
+    int64_t blk = 0;
+    for (int s = 0; s < n; ++s) {
+        const RenderBufs& r = L.r[s];
+        if (r.D > L.Dmax) L.Dmax = r.D;
+        if (r.N == 0) continue;
+        SceneDesc d{r.col, r.w, r.b, r.alpha, r.succ, r.x, r.y, r.N, blk, r.K, r.D};
+        L.host_tables.push_back(d);
+        blk += div_up(r.N, kBlock);
+    }
+    L.blocks = blk;
+    L.dev_tables = cv.take<SceneDesc>((int64_t)(L.host_tables.size() > 0 ? L.host_tables.size() : 1));
+}
+
+static pg_status validate_batch(int n, const pg_paths* paths, const pg_params* params) {
+    if (n < 1) return fail(PG_ERR_ARG, "n_scenes must be >= 1");
+    if (!paths || !params) return fail(PG_ERR_ARG, "paths and params are required");
+    for (int s = 0; s < n; ++s) {
+        pg_status st;
+        if ((st = validate_paths(&paths[s], true)) || (st = validate_params(&params[s])))
+            return fail(st, "scene %d: %s", s, g_error.c_str());
+    }
+    return PG_OK;
+}
+
+// Phase B: the D iterations of every scene, batched.
+static hipError_t batched_iterations(const BatchLayout& L, hipStream_t s) {
+    const int nsc = (int)L.host_tables.size();
+    for (int t = 1; t <= L.Dmax && L.blocks > 0; ++t) {
+        {
+            ProfScope ps(s, "spmv_batched");
+            hipLaunchKernelGGL(k_spmv_batched, dim3((unsigned)L.blocks), dim3(kBlock), 0, s, L.dev_tables, nsc, t);
+        }
+        {
+            ProfScope ps(s, "shift_batched");
+            hipLaunchKernelGGL(k_shift_batched, dim3((unsigned)L.blocks), dim3(kBlock), 0, s, L.dev_tables, nsc, t);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Runs all three phases.  Streams: the setup and output of scene s go to
+// streams[s % ns]; streams[0] is the caller's and does the batched loop.
+static hipError_t run_batch(const pg_paths* paths, BatchLayout& L, float* const* images, hipStream_t* streams,
+                            int ns, hipEvent_t* ev) {
+    hipStream_t s0 = streams[0];
+    hipError_t e;
+    if (ns > 1) {
+        if ((e = hipEventRecord(ev[0], s0)) != hipSuccess) return e;
+        for (int k = 1; k < ns; ++k)
+            if ((e = hipStreamWaitEvent(streams[k], ev[0], 0)) != hipSuccess) return e;
+    }
+    for (int s = 0; s < L.n; ++s) {
+        float* x0 = nullptr;
+        if ((e = render_setup(&paths[s], &L.q[s], L.r[s], nullptr, streams[s % ns], &x0)) != hipSuccess) return e;
+    }
+    if (ns > 1) {
+        for (int k = 1; k < ns; ++k) {
+            if ((e = hipEventRecord(ev[k], streams[k])) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s0, ev[k], 0)) != hipSuccess) return e;
+        }
+    }
+    if ((e = batched_iterations(L, s0)) != hipSuccess) return e;
+    if (ns > 1) {
+        if ((e = hipEventRecord(ev[0], s0)) != hipSuccess) return e;
+        for (int k = 1; k < ns; ++k)
+            if ((e = hipStreamWaitEvent(streams[k], ev[0], 0)) != hipSuccess) return e;
+    }
+    for (int s = 0; s < L.n; ++s)
+        if ((e = render_output(&paths[s], &L.q[s], L.r[s], nullptr, images[s], L.r[s].x, streams[s % ns])) !=
+            hipSuccess)
+            return e;
+    if (ns > 1) {
+        for (int k = 1; k < ns; ++k) {
+            if ((e = hipEventRecord(ev[k], streams[k])) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s0, ev[k], 0)) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+static size_t batch_size(int n, const pg_paths* paths, const pg_params* params) {
+    Carver cv(nullptr);
+    BatchLayout L;
+    carve_batch(cv, L, n, paths, params);
+    return cv.size();
+}
+
+}  // namespace pg
+
 using namespace pg;
+
+struct pg_batch {
+    int n = 0;
+    std::vector<pg_paths> paths;
+    std::vector<float*> images;
+    BatchLayout L;
+    int ns = 1;
+    hipStream_t streams[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool own_streams = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t flags = 0;
+};
+
+static void destroy_batch(pg_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (int k = 0; k < 4; ++k) {
+        if (b->ev[k]) (void)hipEventDestroy(b->ev[k]);
+        if (b->own_streams && k > 0 && b->streams[k]) (void)hipStreamDestroy(b->streams[k]);
+    }
+    delete b;
+}
 
 extern "C" {
 
 pg_status pg_render_batched_workspace_size(int32_t n_scenes, const pg_paths* paths, const pg_params* params,
                                            size_t* bytes) {
-    (void)n_scenes; (void)paths; (void)params; (void)bytes;
-    return fail(PG_ERR_UNSUPPORTED, "pg_render_batched: not built yet");
+    g_error.clear();
+    pg_status st = validate_batch(n_scenes, paths, params);
+    if (st) return st;
+    if (!bytes) return fail(PG_ERR_ARG, "bytes is NULL");
+    *bytes = batch_size(n_scenes, paths, params);
+    return PG_OK;
+}
+
+pg_status pg_batch_create(int32_t n_scenes, const pg_paths* paths, const pg_params* params, float* const* images,
+                          void* ws, size_t ws_bytes, int32_t use_graph, void* stream, pg_batch** out) {
+    g_error.clear();
+    pg_status st = validate_batch(n_scenes, paths, params);
+    if (st) return st;
+    if (!images || !out) return fail(PG_ERR_ARG, "images and out are required");
+    if (use_graph && !stream) return fail(PG_ERR_ARG, "graph capture needs a created stream, not the null stream");
+    for (int s = 0; s < n_scenes; ++s)
+        if (!images[s]) return fail(PG_ERR_ARG, "images[%d] is NULL", s);
+    if ((st = check_ws(ws, ws_bytes, batch_size(n_scenes, paths, params)))) return st;
+    pg_batch* b = new (std::nothrow) pg_batch();
+    if (!b) return fail(PG_ERR_ARG, "out of host memory");
+    b->n = n_scenes;
+    b->paths.assign(paths, paths + n_scenes);
+    b->images.assign(images, images + n_scenes);
+    Carver cv(ws);
+    carve_batch(cv, b->L, n_scenes, b->paths.data(), params);
+    for (int s = 0; s < n_scenes; ++s) b->L.q[s].flags &= ~PG_FLAG_CHECK;
+    hipStream_t s0 = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    // the descriptor tables go to the device once, before any capture
+    if (!b->L.host_tables.empty()) {
+        e = hipMemcpyAsync(b->L.dev_tables, b->L.host_tables.data(), b->L.host_tables.size() * sizeof(SceneDesc),
+                           hipMemcpyHostToDevice, s0);
+        if (e == hipSuccess) e = hipStreamSynchronize(s0);
+    }
+    b->ns = n_scenes > 1 ? 4 : 1;
+    b->streams[0] = s0;
+    b->own_streams = true;
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming);
+    for (int k = 1; k < b->ns && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&b->streams[k], hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        destroy_batch(b);
+        return hip_fail(e, "pg_batch_create");
+    }
+    if (use_graph) {
+        e = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t er = run_batch(b->paths.data(), b->L, b->images.data(), b->streams, b->ns, b->ev);
+            e = hipStreamEndCapture(s0, &b->graph);
+            if (er != hipSuccess) e = er;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            destroy_batch(b);
+            return hip_fail(e, "graph capture");
+        }
+    }
+    *out = b;
+    return PG_OK;
+}
+
+pg_status pg_batch_launch(pg_batch* b, void* stream) {
+    g_error.clear();
+    if (!b) return fail(PG_ERR_ARG, "batch is NULL");
+    hipStream_t s0 = (hipStream_t)stream;
+    hipError_t e;
+    if (b->exec) {
+        e = hipGraphLaunch(b->exec, s0);
+    } else {
+        hipStream_t st[4] = {s0, b->streams[1], b->streams[2], b->streams[3]};
+        e = run_batch(b->paths.data(), b->L, b->images.data(), st, b->ns, b->ev);
+    }
+    if (e != hipSuccess) return hip_fail(e, "pg_batch_launch");
+    return PG_OK;
+}
+
+pg_status pg_batch_destroy(pg_batch* b) {
+    g_error.clear();
+    destroy_batch(b);
+    return PG_OK;
 }
 
 pg_status pg_render_batched(int32_t n_scenes, const pg_paths* paths, const pg_params* params,
                             float* const* images, void* ws, size_t ws_bytes, void* stream) {
-    (void)n_scenes; (void)paths; (void)params; (void)images; (void)ws; (void)ws_bytes; (void)stream;
-    return fail(PG_ERR_UNSUPPORTED, "pg_render_batched: not built yet");
+    g_error.clear();
+    pg_status st = validate_batch(n_scenes, paths, params);
+    if (st) return st;
+    if (!images) return fail(PG_ERR_ARG, "images is NULL");
+    for (int s = 0; s < n_scenes; ++s)
+        if (!images[s]) return fail(PG_ERR_ARG, "images[%d] is NULL", s);
+    if ((st = check_ws(ws, ws_bytes, batch_size(n_scenes, paths, params)))) return st;
+    Carver cv(ws);
+    BatchLayout L;
+    carve_batch(cv, L, n_scenes, paths, params);
+    hipStream_t s0 = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (!L.host_tables.empty()) {
+        e = hipMemcpyAsync(L.dev_tables, L.host_tables.data(), L.host_tables.size() * sizeof(SceneDesc),
+                           hipMemcpyHostToDevice, s0);
+        // the host copy of the tables dies with this call
+        if (e == hipSuccess) e = hipStreamSynchronize(s0);
+    }
+    hipStream_t one[1] = {s0};
+    if (e == hipSuccess) e = run_batch(paths, L, images, one, 1, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "pg_render_batched");
+    uint32_t fl = 0;
+    for (int s = 0; s < n_scenes; ++s) fl |= params[s].flags;
+    if (fl & PG_FLAG_CHECK) {
+        for (int s = 0; s < n_scenes; ++s) {
+            pg_status fs = finish(s0, &params[s], L.r[s].g.flag, PG_FLAG_CHECK);
+            if (fs) return fail(fs, "scene %d: %s", s, g_error.c_str());
+        }
+    }
+    return PG_OK;
 }
 
 }  // extern "C"

@@ -34,8 +34,9 @@ __global__ __launch_bounds__(kBlock) void k_edges(int64_t N, Consts c, const int
     f3 t{0.f, 0.f, 0.f}, w{0.f, 0.f, 0.f}, we{0.f, 0.f, 0.f}, ls{0.f, 0.f, 0.f}, le{0.f, 0.f, 0.f},
         lp{0.f, 0.f, 0.f};
     float alpha = 0.0f;
+    const int64_t e = o.ell ? eidx(i, lane, K) : i * K + lane;
     if (act) {
-        int64_t j = col[i * K + lane];
+        int64_t j = col[e];
         if (j < 0 || j >= N || (lane == 0 && j != i)) {
             set_flag(flag, kFlagIndex);
             act = false;
@@ -80,7 +81,6 @@ __global__ __launch_bounds__(kBlock) void k_edges(int64_t N, Consts c, const int
     sz = group_sum<KP>(sz);
 
     if (act) {
-        const int64_t e = i * K + lane;
         o.w[e] = wi;
         if (o.gw) o.gw[e] = wi * hg_dlog(c.g, u_w);
         if (o.canon_row || o.w_ind || o.w_ph || o.w_env) {

@@ -342,12 +342,11 @@ __global__ __launch_bounds__(kBlock) void k_knn(int64_t N, int K, int shift, con
         }
     }
 
-    if (col_sorted) {
-        int32_t* row = col_sorted + s * K;
-        row[0] = (int32_t)s;
+    if (col_sorted) {   // sliced-ELL layout
+        col_sorted[eidx(s, 0, K)] = (int32_t)s;
 #pragma unroll
         for (int p = 0; p < KM; ++p)
-            if (p >= KM - m) row[1 + p - (KM - m)] = inv[o[p]];
+            if (p >= KM - m) col_sorted[eidx(s, 1 + p - (KM - m), K)] = inv[o[p]];
     }
     if (col_canon) {
         int32_t* row = col_canon + (int64_t)self * K;

@@ -29,6 +29,15 @@ enum : int32_t {
 
 __host__ __device__ inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Internal edge layout: sliced ELL.  Rows are grouped in slices of 64 (one
+// wave); inside a slice, edge l of all 64 rows is contiguous, so a wave that
+// owns a slice reads edge l of its rows with one 256-byte access.
+constexpr int kSlice = 64;
+__host__ __device__ inline int64_t eidx(int64_t i, int l, int K) {
+    return ((i >> 6) * K + l) * kSlice + (i & (kSlice - 1));
+}
+__host__ __device__ inline int64_t ell_size(int64_t N, int K) { return div_up(N, kSlice) * kSlice * K; }
+
 // XCD-aware block order.  The hardware hands block b to XCD b % 8; remap so
 // every XCD works on one contiguous range of tiles, which keeps the spatially
 // sorted rows that share neighbours on the same L2.
@@ -196,6 +205,7 @@ hipError_t launch_pack_records(int64_t N, const pg_paths& paths, VRec* rec, int3
 // canon_row (nullable) maps local row -> path-order row for the optional
 // path-order outputs.
 struct EdgeOut {
+    int ell;             // 1: col / w / gw in the sliced-ELL layout, 0: row-major
     float* w;            // [N*K] local order (required)
     float* gw;           // [N*K] dw/dg, or NULL
     float* b;            // [N] f3 local
@@ -220,6 +230,9 @@ hipError_t launch_paths(int64_t P, int64_t N, const int64_t* off, const int32_t*
 // propagation
 hipError_t launch_spmv(int64_t N, int K, const int32_t* col, const float* w, const float* x, const float* b,
                        const float* alpha, float* y, hipStream_t s);
+// the same product over the sliced-ELL layout, one thread per row
+hipError_t launch_spmv_ell(int64_t N, int K, const int32_t* col, const float* w, const float* x, const float* b,
+                           const float* alpha, const int32_t* rowmask, float* y, hipStream_t s);
 hipError_t launch_shift(int64_t N, const int32_t* succ, const float* y, float* x, hipStream_t s);
 hipError_t launch_shifted_build(int64_t N, int K, const int32_t* succ, const int32_t* col, const float* w,
                                 const float* b, const float* alpha, int32_t* mcol, float* mw, float* c,
@@ -227,7 +240,8 @@ hipError_t launch_shifted_build(int64_t N, int K, const int32_t* succ, const int
 hipError_t launch_spmv_shifted(int64_t N, int K, const int32_t* succ, const int32_t* mcol, const float* mw,
                                const float* c, const float* x, float* xn, hipStream_t s);
 
-// output to pixels; inv (nullable) maps path-order vertex -> local id
+// output to pixels; inv (nullable) maps path-order vertex -> local id; with
+// inv the edges are in the sliced-ELL layout, without it row-major
 hipError_t launch_pixels(const pg_paths& paths, const Consts& c, const int32_t* inv, const int32_t* col,
                          const float* w, const float* x, const float* dpt, const float* r, const float* alpha,
                          float* image, int32_t* flag, hipStream_t s);

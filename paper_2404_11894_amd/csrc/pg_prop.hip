@@ -72,21 +72,97 @@ hipError_t launch_spmv(int64_t N, int K, const int32_t* col, const float* w, con
     return hipGetLastError();
 }
 
-// L(v) = y(succ v), 0 at a path's end.
+// One thread per row over the sliced-ELL layout: each wave owns one slice of
+// 64 rows, issues the K column-id and weight loads of all its rows (each a
+// coalesced 256-byte access) and the K gathers before it waits, so a wave has
+// 64*K independent loads in flight.  KT = K at compile time (0: runtime K).
+// rowmask (nullable): rows with rowmask[i] < 0 output 0.  alpha NULL means 1.
+template <int KT>
+__global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int Kr, const int32_t* __restrict__ col,
+                                                     const float* __restrict__ w, const float* __restrict__ x,
+                                                     const float* __restrict__ b, const float* __restrict__ alpha,
+                                                     const int32_t* __restrict__ rowmask, float* __restrict__ y) {
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t i = tile * kBlock + threadIdx.x;
+    if (i >= N) return;
+    if (rowmask && rowmask[i] < 0) {
+        st3(y, i, f3{0.f, 0.f, 0.f});
+        return;
+    }
+    const int K = KT ? KT : Kr;
+    const int64_t base = (i >> 6) * (int64_t)K * kSlice + (i & (kSlice - 1));
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    if (KT) {
+        int32_t j[KT > 0 ? KT : 1];
+        float ww[KT > 0 ? KT : 1];
+#pragma unroll
+        for (int l = 0; l < KT; ++l) {
+            j[l] = col[base + (int64_t)l * kSlice];
+            ww[l] = w[base + (int64_t)l * kSlice];
+        }
+#pragma unroll
+        for (int l = 0; l < KT; ++l) {
+            const f3 xv = ld3(x, j[l]);
+            ax = fmaf(ww[l], xv.x, ax);
+            ay = fmaf(ww[l], xv.y, ay);
+            az = fmaf(ww[l], xv.z, az);
+        }
+    } else {
+#pragma unroll 4
+        for (int l = 0; l < K; ++l) {
+            const int64_t jj = col[base + (int64_t)l * kSlice];
+            const float wv = w[base + (int64_t)l * kSlice];
+            const f3 xv = ld3(x, jj);
+            ax = fmaf(wv, xv.x, ax);
+            ay = fmaf(wv, xv.y, ay);
+            az = fmaf(wv, xv.z, az);
+        }
+    }
+    const f3 bb = ld3(b, i);
+    const float a = alpha ? alpha[i] : 1.0f;
+    st3(y, i, f3{fmaf(a, ax, bb.x), fmaf(a, ay, bb.y), fmaf(a, az, bb.z)});
+}
+
+hipError_t launch_spmv_ell(int64_t N, int K, const int32_t* col, const float* w, const float* x, const float* b,
+                           const float* alpha, const int32_t* rowmask, float* y, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    dim3 grid((unsigned)div_up(N, kBlock)), block(kBlock);
+    if (K == 16)
+        hipLaunchKernelGGL(k_spmv_ell<16>, grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
+    else if (K == 8)
+        hipLaunchKernelGGL(k_spmv_ell<8>, grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
+    else
+        hipLaunchKernelGGL(k_spmv_ell<0>, grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
+    return hipGetLastError();
+}
+
+// L(v) = y(succ v), 0 at a path's end.  Four vertices per thread, strided by
+// the grid so every access stays coalesced, for four independent gathers.
+constexpr int kShiftPer = 4;
 __global__ __launch_bounds__(kBlock) void k_shift(int64_t N, const int32_t* __restrict__ succ,
                                                   const float* __restrict__ y, float* __restrict__ x) {
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t v = tile * blockDim.x + threadIdx.x;
-    if (v >= N) return;
-    const int64_t u = succ[v];
-    f3 val{0.f, 0.f, 0.f};
-    if (u >= 0) val = ld3(y, u);
-    st3(x, v, val);
+    const int64_t v0 = tile * (int64_t)kBlock * kShiftPer + threadIdx.x;
+    int64_t u[kShiftPer];
+#pragma unroll
+    for (int k = 0; k < kShiftPer; ++k) {
+        const int64_t v = v0 + (int64_t)k * kBlock;
+        u[k] = v < N ? (int64_t)succ[v] : -1;
+    }
+    f3 val[kShiftPer];
+#pragma unroll
+    for (int k = 0; k < kShiftPer; ++k) val[k] = u[k] >= 0 ? ld3(y, u[k]) : f3{0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < kShiftPer; ++k) {
+        const int64_t v = v0 + (int64_t)k * kBlock;
+        if (v < N) st3(x, v, val[k]);
+    }
 }
 
 hipError_t launch_shift(int64_t N, const int32_t* succ, const float* y, float* x, hipStream_t s) {
     if (N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_shift, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, succ, y, x);
+    hipLaunchKernelGGL(k_shift, dim3((unsigned)div_up(N, (int64_t)kBlock * kShiftPer)), dim3(kBlock), 0, s, N,
+                       succ, y, x);
     return hipGetLastError();
 }
 
@@ -98,13 +174,15 @@ __global__ __launch_bounds__(kBlock) void k_shifted_build(int64_t N, int K, cons
                                                           const float* __restrict__ alpha,
                                                           int32_t* __restrict__ mcol, float* __restrict__ mw,
                                                           float* __restrict__ c) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= N * (int64_t)K) return;
-    const int64_t v = e / K, k = e - v * K;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * (int64_t)K) return;
+    const int64_t v = t / K;
+    const int k = (int)(t - v * K);
     const int64_t u = succ[v];
+    const int64_t e = eidx(v, k, K);
     if (u >= 0) {
-        mcol[e] = col[u * K + k];
-        mw[e] = alpha[u] * w[u * K + k];
+        mcol[e] = col[eidx(u, k, K)];
+        mw[e] = alpha[u] * w[eidx(u, k, K)];
     } else {
         mcol[e] = (int32_t)v;
         mw[e] = 0.0f;
@@ -123,13 +201,7 @@ hipError_t launch_shifted_build(int64_t N, int K, const int32_t* succ, const int
 
 hipError_t launch_spmv_shifted(int64_t N, int K, const int32_t* succ, const int32_t* mcol, const float* mw,
                                const float* c, const float* x, float* xn, hipStream_t s) {
-    if (N == 0) return hipSuccess;
-    dispatch_kp(K, [&](auto kp) {
-        constexpr int KP = decltype(kp)::value;
-        hipLaunchKernelGGL(k_spmv<KP>, dim3((unsigned)div_up(N, kBlock / KP)), dim3(kBlock), 0, s, N, K, mcol,
-                           mw, x, c, (const float*)nullptr, succ, xn);
-    });
-    return hipGetLastError();
+    return launch_spmv_ell(N, K, mcol, mw, x, c, nullptr, succ, xn, s);
 }
 
 // ------------------------------------------------------------- pixels ---
@@ -163,12 +235,13 @@ __global__ __launch_bounds__(kBlock) void k_pixels(pg_paths P, Consts c, const i
         float ix = 0.0f, iy = 0.0f, iz = 0.0f;
         if (c.final_gather == 0) {
             for (int l = 0; l < K; ++l) {
-                const int64_t j = col[s0 * K + l];
+                const int64_t e = inv ? eidx(s0, l, K) : s0 * K + l;
+                const int64_t j = col[e];
                 if (j < 0 || j >= N) {
                     set_flag(flag, kFlagIndex);
                     continue;
                 }
-                const float ww = w[s0 * K + l];
+                const float ww = w[e];
                 ix = fmaf(ww, x[3 * j], ix);
                 iy = fmaf(ww, x[3 * j + 1], iy);
                 iz = fmaf(ww, x[3 * j + 2], iz);

@@ -15,7 +15,7 @@ void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params*
     r.D = q->D;
     r.schedule = resolve_schedule(q);
     r.tape = (q->flags & PG_FLAG_TAPE) != 0;
-    const int64_t E = N * (int64_t)r.K;
+    const int64_t E = ell_size(N, r.K);   // sliced-ELL storage, padded to whole slices
     carve_grid(cv, r.g, N, shift_of(q, N));
     r.rec = cv.take<VRec>(N);
     r.col = cv.take<int32_t>(E);
@@ -43,8 +43,8 @@ void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params*
         if (e_ != hipSuccess) return e_;       \
     } while (0)
 
-hipError_t run_render(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out, float* image,
-                      hipStream_t s, float** final_x) {
+hipError_t render_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out,
+                        hipStream_t s, float** x0_out) {
     const int64_t N = r.N;
     const int K = r.K;
     GridBufs& g = r.g;
@@ -61,6 +61,7 @@ hipError_t run_render(const pg_paths* p, const pg_params* q, RenderBufs& r, cons
     }
     const Consts c = make_consts(q, K);
     EdgeOut o{};
+    o.ell = 1;
     o.w = r.w;
     o.gw = r.gw;
     o.b = r.b;
@@ -79,7 +80,6 @@ hipError_t run_render(const pg_paths* p, const pg_params* q, RenderBufs& r, cons
         ProfScope ps(s, "edges");
         PG_TRY(launch_edges(N, c, r.col, r.rec, o, g.flag, s));
     }
-
     float* x0 = r.tape ? r.traj : r.x;
     PG_TRY(launch_fill_value(r.succ, (size_t)N * 4, 0xffffffffu, s));
     if (r.pred) PG_TRY(launch_fill_value(r.pred, (size_t)N * 4, 0xffffffffu, s));
@@ -89,12 +89,18 @@ hipError_t run_render(const pg_paths* p, const pg_params* q, RenderBufs& r, cons
         PG_TRY(launch_paths(r.P, N, p->path_offsets, g.inv, r.alpha, r.dpt, r.r, q->init, r.succ, r.pred, x0,
                             g.flag, s));
     }
-
-    float* cur = x0;
     if (r.schedule == PG_SCHED_SHIFTED) {
         ProfScope ps(s, "shifted_build");
         PG_TRY(launch_shifted_build(N, K, r.succ, r.col, r.w, r.b, r.alpha, r.mcol, r.mw, r.c, s));
     }
+    *x0_out = x0;
+    return hipSuccess;
+}
+
+hipError_t render_iterate(RenderBufs& r, float* x0, hipStream_t s, float** final_x) {
+    const int64_t N = r.N;
+    const int K = r.K;
+    float* cur = x0;
     for (int t = 1; t <= r.D; ++t) {
         float* nxt;
         if (r.tape) nxt = r.traj + (size_t)t * N * 3;
@@ -106,18 +112,35 @@ hipError_t run_render(const pg_paths* p, const pg_params* q, RenderBufs& r, cons
         } else {
             {
                 ProfScope ps(s, "spmv");
-                PG_TRY(launch_spmv(N, K, r.col, r.w, cur, r.b, r.alpha, r.y, s));
+                PG_TRY(launch_spmv_ell(N, K, r.col, r.w, cur, r.b, r.alpha, nullptr, r.y, s));
             }
             ProfScope ps(s, "shift");
             PG_TRY(launch_shift(N, r.succ, r.y, nxt, s));
         }
         cur = nxt;
     }
+    *final_x = cur;
+    return hipSuccess;
+}
+
+hipError_t render_output(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out,
+                         float* image, const float* cur, hipStream_t s) {
+    const Consts c = make_consts(q, r.K);
     {
         ProfScope ps(s, "pixels");
-        PG_TRY(launch_pixels(*p, c, g.inv, r.col, r.w, cur, r.dpt, r.r, r.alpha, image, g.flag, s));
+        PG_TRY(launch_pixels(*p, c, r.g.inv, r.col, r.w, cur, r.dpt, r.r, r.alpha, image, r.g.flag, s));
     }
-    if (out && out->lplus) PG_TRY(launch_permute3(N, g.perm, cur, out->lplus, 0, s));
+    if (out && out->lplus) PG_TRY(launch_permute3(r.N, r.g.perm, cur, out->lplus, 0, s));
+    return hipSuccess;
+}
+
+hipError_t run_render(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out, float* image,
+                      hipStream_t s, float** final_x) {
+    float* x0 = nullptr;
+    float* cur = nullptr;
+    PG_TRY(render_setup(p, q, r, out, s, &x0));
+    PG_TRY(render_iterate(r, x0, s, &cur));
+    PG_TRY(render_output(p, q, r, out, image, cur, s));
     if (final_x) *final_x = cur;
     return hipSuccess;
 }

@@ -273,3 +273,49 @@ def crop_of(cfg: SceneConfig, w: int, h: int, spp: int | None = None) -> SceneCo
     x0 = (cfg.width - w) // 2
     y0 = (cfg.height - h) // 2
     return replace(cfg, crop=(x0, y0, w, h), spp=cfg.spp if spp is None else spp)
+
+
+def _batch_specs(n, seed, n_min, n_max):
+    """Seeded draws of the batching workload: per scene the medium, method
+    settings and a log-uniform vertex-count target."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for s in range(n):
+        R = int(rng.choice([32, 64, 128, 256]))
+        alb = float(rng.uniform(0.8, 0.999))
+        g = float(rng.uniform(-0.3, 0.9))
+        k = int(rng.integers(8, 17))
+        D = int(rng.integers(16, 65))
+        target = float(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
+        sigma = float(rng.uniform(6.0, 24.0))
+        cfg = SceneConfig(R=R, sigma_max=sigma, albedo=(alb, alb), g=g, width=32, height=32, spp=1,
+                          max_depth=D, vfov_deg=40.0, seed=seed + s)
+        specs.append((f"batch{s}", cfg, k, D, target))
+    return specs
+
+
+def _sized(spec, per_pixel):
+    name, cfg, k, D, target = spec
+    pixels = target / max(per_pixel, 0.05)
+    spp = 1 if pixels < 512 * 512 else 4
+    side = int(max(8, round(np.sqrt(pixels / spp))))
+    return Workload(name, replace(cfg, width=side, height=side, spp=spp), k=k, D=D)
+
+
+def batch_workload(n: int = 64, seed: int = 1000, n_min: float = 1e4, n_max: float = 2e6):
+    """Independent scenes of the batching workload: scene s is seeded 1000+s
+    (grid 32^3..256^3 fBm, albedo U[0.8, 0.999], HG g U[-0.3, 0.9], k 8..16,
+    D 16..64), its vertex count drawn log-uniform in [n_min, n_max] and reached
+    by choosing the image size from a 32x32-pixel probe render.
+    Returns a list of Workload."""
+    return [_sized(sp, generate(sp[1]).n_vertices / (32 * 32)) for sp in _batch_specs(n, seed, n_min, n_max)]
+
+
+def generate_batch(n: int = 64, seed: int = 1000, n_min: float = 1e4, n_max: float = 2e6):
+    """The batching workload's scenes, traced: a list of (Workload, Scene).
+    Each scene is traced right after its probe, so its medium is built once."""
+    out = []
+    for sp in _batch_specs(n, seed, n_min, n_max):
+        w = _sized(sp, generate(sp[1]).n_vertices / (32 * 32))
+        out.append((w, generate(w.scene)))
+    return out

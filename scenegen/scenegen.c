@@ -391,6 +391,40 @@ static int trace_path(const handle* h, block* b, int X, int Y, int s, float ecam
     return nv;
 }
 
+/* One-entry cache of the last medium built, keyed by the settings that
+ * define it, so a probe render and the full render of one scene build the
+ * density grid once.  Calls are not concurrent (the Python side serialises). */
+static sg_config g_cached_cfg;
+static medium g_cached_med;
+static int g_cached_valid = 0;
+
+static int same_medium(const sg_config* a, const sg_config* b) {
+    return a->R == b->R && a->mask == b->mask && a->albedo_mode == b->albedo_mode && a->sigma_max == b->sigma_max &&
+           a->density_contrast == b->density_contrast && a->density_bias == b->density_bias &&
+           a->mask_r0 == b->mask_r0 && a->mask_r1 == b->mask_r1 && a->albedo_lo == b->albedo_lo &&
+           a->albedo_hi == b->albedo_hi && a->seed == b->seed;
+}
+
+static int get_medium(const sg_config* c, medium* m) {
+    if (!(g_cached_valid && same_medium(c, &g_cached_cfg))) {
+        if (g_cached_valid) {
+            free(g_cached_med.sigma);
+            free(g_cached_med.albedo);
+            g_cached_valid = 0;
+        }
+        memset(&g_cached_med, 0, sizeof g_cached_med);
+        if (build_medium(c, &g_cached_med)) {
+            free(g_cached_med.sigma);
+            free(g_cached_med.albedo);
+            return -1;
+        }
+        g_cached_cfg = *c;
+        g_cached_valid = 1;
+    }
+    *m = g_cached_med;   /* shared, read-only; never freed with the handle */
+    return 0;
+}
+
 static void free_handle(handle* h) {
     if (!h) return;
     if (h->blocks) {
@@ -401,8 +435,6 @@ static void free_handle(handle* h) {
         }
         free(h->blocks);
     }
-    free(h->med.sigma);
-    free(h->med.albedo);
     free(h);
 }
 
@@ -430,7 +462,7 @@ void* sg_trace(const sg_config* cfg, int nthreads, int64_t* n_vertices, int64_t*
 #else
     (void)nthreads;
 #endif
-    if (build_medium(cfg, &h->med)) { snprintf(err, errlen, "out of memory"); free_handle(h); return NULL; }
+    if (get_medium(cfg, &h->med)) { snprintf(err, errlen, "out of memory"); free_handle(h); return NULL; }
     h->n_paths = (int64_t)cw * ch * cfg->spp;
     h->paths_per_block = 256;
     h->nblocks = (h->n_paths + h->paths_per_block - 1) / h->paths_per_block;

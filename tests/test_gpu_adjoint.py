@@ -1,0 +1,129 @@
+"""GPU reverse mode against the FP64 oracle's gradient (itself pinned to FP64
+central differences), the autograd wrapper, and GPU central differences.
+
+Gradient tolerance: |err| <= 1e-4 |ref| + 1e-4 max|ref| per component.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+import paper_2404_11894_amd as pg
+from tests.gpu_util import crop
+
+pytestmark = pytest.mark.gpu
+
+
+def grad_close(got, ref, what):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    tol = 1e-4 * np.abs(ref) + 1e-4 * np.abs(ref).max()
+    err = np.abs(got - ref)
+    assert np.all(err <= tol), f"{what}: max err {err.max():.3e} (max |ref| {np.abs(ref).max():.3e})"
+
+
+def case(sc, R, k, D, g, init="pt", fg=0, seed=5, lo=0.6, hi=0.95):
+    rng = np.random.default_rng(seed)
+    grid = rng.uniform(lo, hi, size=(R, R, R)).astype(np.float32)
+    op = oracle.params(k=k, D=D, g=g, init=init, final_gather=fg)
+    alpha = oracle.albedo_from_grid(sc.pos, grid)
+    img = oracle.render(sc, op, alpha=alpha)
+    target = scenegen.target_image(img.shape, float(img.mean()), seed=4).astype(np.float64)
+    gimg = 2.0 * (img - target)                  # d/dI of sum (I - T)^2 at the oracle image
+    ref = oracle.backward(sc, op, gimg, grid=grid)
+    return grid, gimg, ref
+
+
+@pytest.mark.parametrize("init,fg", [("pt", 0), ("zero", 0), ("pt", 1)])
+def test_backward_matches_oracle(init, fg):
+    sc = crop("tiny", 32, 32, 2)
+    print(f"adjoint init={init} fg={fg} N={sc.n_vertices}", flush=True)
+    grid, gimg, ref = case(sc, 8, 8, 6, 0.5, init, fg)
+    paths = pg.DevicePaths(sc, albedo_grid=grid)
+    q = pg.params(k=8, D=6, g=0.5, init=init, final_gather=fg, flags=pg.PG_FLAG_CHECK)
+    out = pg.pg_backward(paths, q, torch.from_numpy(gimg.astype(np.float32)), grad_albedo=True)
+    torch.cuda.synchronize()
+    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid")
+    grad_close(out["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo")
+    grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
+
+
+def test_backward_workload_crop_matches_oracle():
+    """The differentiation workload: the 128^3 ball's paths held fixed, albedo
+    from a 64^3 grid (U[0.95,0.999], seed 2), k 16, D 64, g 0.8, on the
+    centred 64x64-pixel, 2-spp crop where the oracle gradient is affordable."""
+    w = scenegen.WORKLOADS["mid"]
+    sc = scenegen.generate(scenegen.crop_of(w.scene, 64, 64, 2))
+    print(f"workload crop N={sc.n_vertices}", flush=True)
+    grid = scenegen.albedo_grid(64, 0.95, 0.999, seed=2)
+    op = oracle.params(k=w.k, D=w.D, g=w.g)
+    img = oracle.render(sc, op, alpha=oracle.albedo_from_grid(sc.pos, grid))
+    target = scenegen.target_image(img.shape, float(img.mean()), seed=4).astype(np.float64)
+    gimg = 2.0 * (img - target)
+    ref = oracle.backward(sc, op, gimg, grid=grid)
+    paths = pg.DevicePaths(sc, albedo_grid=grid)
+    q = pg.params(k=w.k, D=w.D, g=w.g, flags=pg.PG_FLAG_CHECK)
+    out = pg.pg_backward(paths, q, torch.from_numpy(gimg.astype(np.float32)))
+    torch.cuda.synchronize()
+    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid")
+    grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
+
+
+def test_autograd_function_uses_the_tape():
+    sc = crop("tiny", 32, 32, 2)
+    rng = np.random.default_rng(7)
+    grid0 = rng.uniform(0.6, 0.95, size=(8, 8, 8)).astype(np.float32)
+    paths = pg.DevicePaths(sc)
+    q = pg.params(k=8, D=5, g=0.5)
+    grid = torch.tensor(grid0, device="cuda", requires_grad=True)
+    g = torch.tensor(0.5, device="cuda", requires_grad=True)
+    img = pg.render_differentiable(paths, q, grid, g)
+    target = torch.rand_like(img) * img.mean().detach() * 2
+    loss = ((img - target) ** 2).sum()
+    loss.backward()
+    # same gradients as a stateless pg_backward that recomputes the forward pass
+    paths2 = pg.DevicePaths(sc, albedo_grid=grid0)
+    out = pg.pg_backward(paths2, q, 2.0 * (img.detach() - target))
+    torch.cuda.synchronize()
+    assert np.allclose(grid.grad.cpu().numpy(), out["grad_grid"].cpu().numpy(), rtol=1e-5, atol=1e-7)
+    assert np.isclose(g.grad.item(), out["grad_g"].item(), rtol=1e-5)
+    # and the forward image is the plain render's
+    img2 = pg.pg_render(paths2, q)
+    torch.cuda.synchronize()
+    assert torch.equal(img.detach(), img2)
+
+
+def test_backward_matches_gpu_central_differences():
+    """FP32 central differences (h = 1e-3) of the GPU loss on 32 voxels and g."""
+    sc = crop("tiny", 32, 32, 2)
+    rng = np.random.default_rng(8)
+    R = 8
+    grid0 = rng.uniform(0.6, 0.95, size=(R, R, R)).astype(np.float32)
+    q = pg.params(k=8, D=6, g=0.5)
+    paths = pg.DevicePaths(sc, albedo_grid=grid0)
+    img = pg.pg_render(paths, q).double()
+    target = torch.rand_like(img) * img.mean() * 2
+
+    def loss(grid, g):
+        paths.set_albedo_grid(grid)
+        qq = pg.params(k=8, D=6, g=g, g_s=0.5)
+        return float(((pg.pg_render(paths, qq).double() - target) ** 2).sum())
+
+    paths.set_albedo_grid(grid0)
+    out = pg.pg_backward(paths, q, (2.0 * (img - target)).float())
+    gg = out["grad_grid"].cpu().numpy().ravel()
+    h = 1e-3
+    picks = rng.choice(np.flatnonzero(np.abs(gg) > 0), 32, replace=False)
+    fd = []
+    for flat in picks:
+        gp, gm = grid0.copy().ravel(), grid0.copy().ravel()
+        gp[flat] += h
+        gm[flat] -= h
+        fd.append((loss(gp.reshape(grid0.shape), 0.5) - loss(gm.reshape(grid0.shape), 0.5)) / (2 * h))
+    fd = np.array(fd)
+    adj = gg[picks]
+    scale = np.abs(gg).max()
+    assert np.all(np.abs(fd - adj) <= 0.02 * np.abs(adj) + 2e-3 * scale), np.c_[fd, adj]
+    fd_g = (loss(grid0, 0.5 + h) - loss(grid0, 0.5 - h)) / (2 * h)
+    assert abs(fd_g - out["grad_g"].item()) <= 0.02 * abs(fd_g) + 1e-3
