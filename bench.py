@@ -32,14 +32,18 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(step, N, K):
+def algorithmic_bytes(step, N, K, starts):
     """Compulsory HBM bytes of one launch of a propagation step (every input
     read once, every output written once):
       spmv / spmv_shifted: col + weight per edge (8 B), one x gather, b (or c)
       and albedo or row mask per row, one y write: N (8K + 12 + 12 + 4 + 12)
+      spmv_scatter: the same plus the predecessor id, for the N - starts rows
+      that have a predecessor; a path's first vertex reads only that id
       shift: successor id, one y gather, one x write: N (4 + 12 + 12)."""
     if step in ("spmv", "spmv_shifted"):
         return N * (8 * K + 40)
+    if step == "spmv_scatter":
+        return (N - starts) * (8 * K + 44) + starts * 4
     if step == "shift":
         return N * 28
     return None
@@ -93,7 +97,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large"])
-    ap.add_argument("--schedule", type=int, default=0, help="0 default, 1 two-pass, 2 shifted")
+    ap.add_argument("--schedule", type=int, default=0, help="0 default, 1 two-pass, 2 shifted, 3 scatter")
     ap.add_argument("--cell-shift", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -151,12 +155,13 @@ def main():
         return
 
     phases = {k: round(v[1] / args.steps, 4) for k, v in prof.items()}
-    prop_steps = [s for s in ("spmv", "shift", "spmv_shifted") if s in prof]
+    prop_steps = [s for s in ("spmv", "shift", "spmv_shifted", "spmv_scatter") if s in prof]
     prop_ms = sum(prof[s][1] for s in prop_steps) / args.steps
     dom = max(prop_steps, key=lambda s: prof[s][1])
     cnt, tot, _ = prof[dom]
     avg_s = tot / cnt / 1e3
-    ab = algorithmic_bytes(dom, N, K)
+    starts = int((sc.path_offsets[1:] > sc.path_offsets[:-1]).sum())
+    ab = algorithmic_bytes(dom, N, K, starts)
     achieved = ab / avg_s / 1e9
     traffic = read_traffic(dom, args.workload)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -60,6 +60,7 @@ typedef int32_t pg_status;
 
 #define PG_SCHED_TWO_PASS 1  /* aggregate over spatially sorted rows, then shift along paths */
 #define PG_SCHED_SHIFTED  2  /* rows pre-arranged in predecessor order: one pass per iteration */
+#define PG_SCHED_SCATTER  3  /* sorted rows; each writes its result straight to its predecessor */
 
 #define PG_MAX_K 64
 
@@ -103,7 +104,7 @@ typedef struct pg_params {
     int32_t cell_shift;     /* uniform-grid cell = 2^cell_shift quantisation steps per axis,
                                11..20; 0 = choose from N */
     int32_t schedule;       /* propagation schedule, same result: 0 = default,
-                               PG_SCHED_TWO_PASS or PG_SCHED_SHIFTED */
+                               PG_SCHED_TWO_PASS, PG_SCHED_SHIFTED or PG_SCHED_SCATTER */
     uint32_t flags;         /* PG_FLAG_* */
 } pg_params;
 

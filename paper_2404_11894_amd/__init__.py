@@ -17,7 +17,7 @@ from ._build import LIB_PATH, build  # noqa: F401
 PG_OK, PG_ERR_ARG, PG_ERR_WORKSPACE, PG_ERR_HIP, PG_ERR_INPUT, PG_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 PG_INIT_PT, PG_INIT_ZERO = 0, 1
 PG_FLAG_CHECK, PG_FLAG_TAPE = 1, 2
-PG_SCHED_TWO_PASS, PG_SCHED_SHIFTED = 1, 2
+PG_SCHED_TWO_PASS, PG_SCHED_SHIFTED, PG_SCHED_SCATTER = 1, 2, 3
 PG_MAX_K = 64
 
 EXPORTS = ("pg_version", "pg_last_error", "pg_default_cell_shift", "pg_profile_start", "pg_profile_stop",
@@ -191,7 +191,7 @@ def params(k=8, D=8, g=0.5, g_s=None, sun_dir=None, env_pdf=None, init="pt", fin
 
 def resolved_schedule(q: Params) -> str:
     """Name of the propagation schedule a call with these params uses."""
-    return {PG_SCHED_SHIFTED: "shifted"}.get(q.schedule, "two-pass")
+    return {PG_SCHED_SHIFTED: "shifted", PG_SCHED_SCATTER: "scatter"}.get(q.schedule, "two-pass")
 
 
 def _K(paths: DevicePaths, k: int) -> int:

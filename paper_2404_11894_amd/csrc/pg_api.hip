@@ -69,7 +69,7 @@ pg_status validate_params(const pg_params* q) {
     if (q->final_gather != 0 && q->final_gather != 1) return fail(PG_ERR_ARG, "final_gather must be 0 or 1");
     if (q->cell_shift != 0 && (q->cell_shift < kMinShift || q->cell_shift > kQBits))
         return fail(PG_ERR_ARG, "cell_shift must be 0 or in [%d, %d]", kMinShift, kQBits);
-    if (q->schedule < 0 || q->schedule > PG_SCHED_SHIFTED) return fail(PG_ERR_ARG, "unknown schedule");
+    if (q->schedule < 0 || q->schedule > PG_SCHED_SCATTER) return fail(PG_ERR_ARG, "unknown schedule");
     if (q->flags & ~(PG_FLAG_CHECK | PG_FLAG_TAPE)) return fail(PG_ERR_ARG, "unknown flag bits");
     return PG_OK;
 }

@@ -263,85 +263,111 @@ __device__ inline bool key_less(uint64_t d1, uint32_t o1, uint64_t d2, uint32_t 
     return d1 < d2 || (d1 == d2 && o1 < o2);
 }
 
+// Insert (d2, oid) into the sorted, right-aligned list if it beats the worst.
 template <int KM>
-__global__ __launch_bounds__(kBlock) void k_knn(int64_t N, int K, int shift, const uint64_t* __restrict__ qs,
-                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ inv,
-                                                const uint32_t* __restrict__ cell_start,
-                                                int32_t* __restrict__ col_sorted, int32_t* __restrict__ col_canon,
-                                                int64_t* __restrict__ row_ptr) {
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t s = tile * blockDim.x + threadIdx.x;
-    if (s >= N) return;
-    const int m = K - 1;
-    const int G = 1 << (kQBits - shift);
-    int32_t qx, qy, qz;
-    qunpack(qs[s], qx, qy, qz);
-    const uint32_t self = (uint32_t)perm[s];
+__device__ __forceinline__ void list_insert(uint64_t (&d)[KM], uint32_t (&o)[KM], uint64_t d2, uint32_t oid) {
+    if (key_less(d2, oid, d[KM - 1], o[KM - 1])) {
+        d[KM - 1] = d2;
+        o[KM - 1] = oid;
+#pragma unroll
+        for (int p = KM - 1; p > 0; --p) {
+            const bool sw = key_less(d[p], o[p], d[p - 1], o[p - 1]);
+            const uint64_t td = d[p];
+            const uint32_t to = o[p];
+            d[p] = sw ? d[p - 1] : d[p];
+            o[p] = sw ? o[p - 1] : o[p];
+            d[p - 1] = sw ? td : d[p - 1];
+            o[p - 1] = sw ? to : o[p - 1];
+        }
+    }
+}
 
-    uint64_t d[KM];
-    uint32_t o[KM];
+template <int KM>
+__device__ __forceinline__ void list_reset(uint64_t (&d)[KM], uint32_t (&o)[KM], int m) {
 #pragma unroll
     for (int p = 0; p < KM; ++p) {
         const bool sentinel = p < KM - m;
         d[p] = sentinel ? 0ull : ~0ull;
         o[p] = sentinel ? 0u : ~0u;
     }
+}
 
-    if (m > 0) {
-        const int cx = qx >> shift, cy = qy >> shift, cz = qz >> shift;
-        for (int r = 0;; ++r) {
-            for (int dz = -r; dz <= r; ++dz) {
-                const int z = cz + dz;
-                if (z < 0 || z >= G) continue;
-                for (int dy = -r; dy <= r; ++dy) {
-                    const int y = cy + dy;
-                    if (y < 0 || y >= G) continue;
-                    const bool face = (dz == -r || dz == r || dy == -r || dy == r);
-                    const int step = (face || r == 0) ? 1 : 2 * r;
-                    for (int dx = -r; dx <= r; dx += step) {
-                        const int x = cx + dx;
-                        if (x < 0 || x >= G) continue;
-                        const uint32_t cell = morton3((uint32_t)x, (uint32_t)y, (uint32_t)z);
-                        const uint32_t beg = cell_start[cell], end = cell_start[cell + 1];
-                        for (uint32_t t = beg; t < end; ++t) {
-                            if ((int64_t)t == s) continue;
-                            int32_t ax, ay, az;
-                            qunpack(qs[t], ax, ay, az);
+// Exact search for query s by Chebyshev shells of cells around its own.  A
+// cell whose box is farther from q than the current (K-1)-th distance cannot
+// contribute and is skipped without reading it (only once the list is full:
+// before that the worst key is (inf, inf)); a cell at exactly that distance is
+// still read, since a tie may win on id.  Candidates are loaded two at a time.
+template <int KM>
+__device__ __forceinline__ void shell_search(int64_t s, int m, int shift, int32_t qx, int32_t qy, int32_t qz,
+                                             const uint64_t* __restrict__ qs, const int32_t* __restrict__ perm,
+                                             const uint32_t* __restrict__ cell_start, uint64_t (&d)[KM],
+                                             uint32_t (&o)[KM]) {
+    (void)m;
+    const int G = 1 << (kQBits - shift);
+    const int cx = qx >> shift, cy = qy >> shift, cz = qz >> shift;
+    const int64_t cs = (int64_t)1 << shift;
+    for (int r = 0;; ++r) {
+        for (int dz = -r; dz <= r; ++dz) {
+            const int z = cz + dz;
+            if (z < 0 || z >= G) continue;
+            const int64_t gz = dz < 0 ? (int64_t)qz - ((int64_t)(z + 1) * cs - 1) : (dz > 0 ? (int64_t)z * cs - qz : 0);
+            for (int dy = -r; dy <= r; ++dy) {
+                const int y = cy + dy;
+                if (y < 0 || y >= G) continue;
+                const int64_t gy = dy < 0 ? (int64_t)qy - ((int64_t)(y + 1) * cs - 1) : (dy > 0 ? (int64_t)y * cs - qy : 0);
+                const bool face = (dz == -r || dz == r || dy == -r || dy == r);
+                const int step = (face || r == 0) ? 1 : 2 * r;
+                for (int dx = -r; dx <= r; dx += step) {
+                    const int x = cx + dx;
+                    if (x < 0 || x >= G) continue;
+                    const int64_t gx = dx < 0 ? (int64_t)qx - ((int64_t)(x + 1) * cs - 1) : (dx > 0 ? (int64_t)x * cs - qx : 0);
+                    if ((uint64_t)(gx * gx + gy * gy + gz * gz) > d[KM - 1]) continue;   // whole cell too far
+                    const uint32_t cell = morton3((uint32_t)x, (uint32_t)y, (uint32_t)z);
+                    const uint32_t beg = cell_start[cell], end = cell_start[cell + 1];
+                    uint32_t t = beg;
+                    for (; t + 1 < end; t += 2) {
+                        const uint64_t p0 = qs[t], p1 = qs[t + 1];
+                        const uint32_t o0 = (uint32_t)perm[t], o1 = (uint32_t)perm[t + 1];
+                        int32_t ax, ay, az;
+                        if ((int64_t)t != s) {
+                            qunpack(p0, ax, ay, az);
                             const int64_t ex = ax - qx, ey = ay - qy, ez = az - qz;
-                            const uint64_t d2 = (uint64_t)(ex * ex + ey * ey + ez * ez);
-                            const uint32_t oid = (uint32_t)perm[t];
-                            if (key_less(d2, oid, d[KM - 1], o[KM - 1])) {
-                                d[KM - 1] = d2;
-                                o[KM - 1] = oid;
-#pragma unroll
-                                for (int p = KM - 1; p > 0; --p) {
-                                    const bool sw = key_less(d[p], o[p], d[p - 1], o[p - 1]);
-                                    const uint64_t td = d[p];
-                                    const uint32_t to = o[p];
-                                    d[p] = sw ? d[p - 1] : d[p];
-                                    o[p] = sw ? o[p - 1] : o[p];
-                                    d[p - 1] = sw ? td : d[p - 1];
-                                    o[p - 1] = sw ? to : o[p - 1];
-                                }
-                            }
+                            list_insert<KM>(d, o, (uint64_t)(ex * ex + ey * ey + ez * ez), o0);
                         }
+                        if ((int64_t)t + 1 != s) {
+                            qunpack(p1, ax, ay, az);
+                            const int64_t ex = ax - qx, ey = ay - qy, ez = az - qz;
+                            list_insert<KM>(d, o, (uint64_t)(ex * ex + ey * ey + ez * ez), o1);
+                        }
+                    }
+                    if (t < end && (int64_t)t != s) {
+                        int32_t ax, ay, az;
+                        qunpack(qs[t], ax, ay, az);
+                        const int64_t ex = ax - qx, ey = ay - qy, ez = az - qz;
+                        list_insert<KM>(d, o, (uint64_t)(ex * ex + ey * ey + ez * ez), (uint32_t)perm[t]);
                     }
                 }
             }
-            // smallest per-axis distance from q to a cell outside the searched cube
-            int64_t gap = INT64_MAX;
-            const int c3[3] = {cx, cy, cz};
-            const int64_t q3[3] = {qx, qy, qz};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                if (c3[a] - r > 0) gap = min(gap, q3[a] - ((int64_t)(c3[a] - r) << shift) + 1);
-                if (c3[a] + r < G - 1) gap = min(gap, ((int64_t)(c3[a] + r + 1) << shift) - q3[a]);
-            }
-            if (gap == INT64_MAX) break;                    // the whole grid was searched
-            if (d[KM - 1] < (uint64_t)(gap * gap)) break;   // list full and provably final
         }
+        // smallest per-axis distance from q to a cell outside the searched cube
+        int64_t gap = INT64_MAX;
+        const int c3[3] = {cx, cy, cz};
+        const int64_t q3[3] = {qx, qy, qz};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (c3[a] - r > 0) gap = min(gap, q3[a] - (int64_t)(c3[a] - r) * cs + 1);
+            if (c3[a] + r < G - 1) gap = min(gap, (int64_t)(c3[a] + r + 1) * cs - q3[a]);
+        }
+        if (gap == INT64_MAX) break;                    // the whole grid was searched
+        if (d[KM - 1] < (uint64_t)(gap * gap)) break;   // list full and provably final
     }
+}
 
+template <int KM>
+__device__ __forceinline__ void knn_write(int64_t s, int K, int m, uint32_t self, int64_t N, const int32_t* inv,
+                                          const uint64_t (&d)[KM], const uint32_t (&o)[KM], int32_t* col_sorted,
+                                          int32_t* col_canon, int64_t* row_ptr) {
+    (void)d;
     if (col_sorted) {   // sliced-ELL layout
         col_sorted[eidx(s, 0, K)] = (int32_t)s;
 #pragma unroll
@@ -361,24 +387,41 @@ __global__ __launch_bounds__(kBlock) void k_knn(int64_t N, int K, int shift, con
     }
 }
 
+template <int KM>
+__global__ __launch_bounds__(kBlock) void k_knn(int64_t N, int K, int shift, const uint64_t* __restrict__ qs,
+                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ inv,
+                                                const uint32_t* __restrict__ cell_start,
+                                                int32_t* __restrict__ col_sorted, int32_t* __restrict__ col_canon,
+                                                int64_t* __restrict__ row_ptr) {
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t s = tile * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const int m = K - 1;
+    int32_t qx, qy, qz;
+    qunpack(qs[s], qx, qy, qz);
+    const uint32_t self = (uint32_t)perm[s];
+    uint64_t d[KM];
+    uint32_t o[KM];
+    list_reset<KM>(d, o, m);
+    if (m > 0) shell_search<KM>(s, m, shift, qx, qy, qz, qs, perm, cell_start, d, o);
+    knn_write<KM>(s, K, m, self, N, inv, d, o, col_sorted, col_canon, row_ptr);
+}
+
 hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, const int32_t* perm,
                       const int32_t* inv, const uint32_t* cell_start, int32_t* col_sorted, int32_t* col_canon,
                       int64_t* row_ptr, hipStream_t s) {
     if (N == 0) return hipSuccess;
     dim3 grid((unsigned)div_up(N, kBlock)), block(kBlock);
     const int m = K - 1;
-    if (m <= 8)
-        hipLaunchKernelGGL(k_knn<8>, grid, block, 0, s, N, K, shift, qsorted, perm, inv, cell_start, col_sorted,
+    auto go = [&](auto km) {
+        constexpr int KM = decltype(km)::value;
+        hipLaunchKernelGGL(k_knn<KM>, grid, block, 0, s, N, K, shift, qsorted, perm, inv, cell_start, col_sorted,
                            col_canon, row_ptr);
-    else if (m <= 16)
-        hipLaunchKernelGGL(k_knn<16>, grid, block, 0, s, N, K, shift, qsorted, perm, inv, cell_start, col_sorted,
-                           col_canon, row_ptr);
-    else if (m <= 32)
-        hipLaunchKernelGGL(k_knn<32>, grid, block, 0, s, N, K, shift, qsorted, perm, inv, cell_start, col_sorted,
-                           col_canon, row_ptr);
-    else
-        hipLaunchKernelGGL(k_knn<64>, grid, block, 0, s, N, K, shift, qsorted, perm, inv, cell_start, col_sorted,
-                           col_canon, row_ptr);
+    };
+    if (m <= 8) go(std::integral_constant<int, 8>{});
+    else if (m <= 16) go(std::integral_constant<int, 16>{});
+    else if (m <= 32) go(std::integral_constant<int, 32>{});
+    else go(std::integral_constant<int, 64>{});
     return hipGetLastError();
 }
 

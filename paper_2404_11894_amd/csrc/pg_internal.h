@@ -233,6 +233,10 @@ hipError_t launch_spmv(int64_t N, int K, const int32_t* col, const float* w, con
 // the same product over the sliced-ELL layout, one thread per row
 hipError_t launch_spmv_ell(int64_t N, int K, const int32_t* col, const float* w, const float* x, const float* b,
                            const float* alpha, const int32_t* rowmask, float* y, hipStream_t s);
+// aggregation fused with propagation: row i's result goes to x_new[pred i];
+// rows without a predecessor are skipped
+hipError_t launch_spmv_scatter(int64_t N, int K, const int32_t* col, const float* w, const float* x,
+                               const float* b, const float* alpha, const int32_t* pred, float* xn, hipStream_t s);
 hipError_t launch_shift(int64_t N, const int32_t* succ, const float* y, float* x, hipStream_t s);
 hipError_t launch_shifted_build(int64_t N, int K, const int32_t* succ, const int32_t* col, const float* w,
                                 const float* b, const float* alpha, int32_t* mcol, float* mw, float* c,

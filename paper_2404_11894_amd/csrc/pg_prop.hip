@@ -77,7 +77,9 @@ hipError_t launch_spmv(int64_t N, int K, const int32_t* col, const float* w, con
 // coalesced 256-byte access) and the K gathers before it waits, so a wave has
 // 64*K independent loads in flight.  KT = K at compile time (0: runtime K).
 // rowmask (nullable): rows with rowmask[i] < 0 output 0.  alpha NULL means 1.
-template <int KT>
+// SCATTER: the row's result is stored at y[rowmask[i]] (the predecessor) and
+// rows with rowmask[i] < 0 are skipped; otherwise such rows store 0 at y[i].
+template <int KT, bool SCATTER>
 __global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int Kr, const int32_t* __restrict__ col,
                                                      const float* __restrict__ w, const float* __restrict__ x,
                                                      const float* __restrict__ b, const float* __restrict__ alpha,
@@ -85,9 +87,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int Kr, const in
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t i = tile * kBlock + threadIdx.x;
     if (i >= N) return;
-    if (rowmask && rowmask[i] < 0) {
-        st3(y, i, f3{0.f, 0.f, 0.f});
-        return;
+    int64_t dst = i;
+    if (rowmask) {
+        dst = rowmask[i];
+        if (dst < 0) {
+            if (!SCATTER) st3(y, i, f3{0.f, 0.f, 0.f});
+            return;
+        }
+        if (!SCATTER) dst = i;
     }
     const int K = KT ? KT : Kr;
     const int64_t base = (i >> 6) * (int64_t)K * kSlice + (i & (kSlice - 1));
@@ -120,19 +127,32 @@ __global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int Kr, const in
     }
     const f3 bb = ld3(b, i);
     const float a = alpha ? alpha[i] : 1.0f;
-    st3(y, i, f3{fmaf(a, ax, bb.x), fmaf(a, ay, bb.y), fmaf(a, az, bb.z)});
+    st3(y, dst, f3{fmaf(a, ax, bb.x), fmaf(a, ay, bb.y), fmaf(a, az, bb.z)});
+}
+
+template <bool SCATTER>
+static void go_spmv_ell(int64_t N, int K, const int32_t* col, const float* w, const float* x, const float* b,
+                        const float* alpha, const int32_t* rowmask, float* y, hipStream_t s) {
+    dim3 grid((unsigned)div_up(N, kBlock)), block(kBlock);
+    if (K == 16)
+        hipLaunchKernelGGL((k_spmv_ell<16, SCATTER>), grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
+    else if (K == 8)
+        hipLaunchKernelGGL((k_spmv_ell<8, SCATTER>), grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
+    else
+        hipLaunchKernelGGL((k_spmv_ell<0, SCATTER>), grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
 }
 
 hipError_t launch_spmv_ell(int64_t N, int K, const int32_t* col, const float* w, const float* x, const float* b,
                            const float* alpha, const int32_t* rowmask, float* y, hipStream_t s) {
     if (N == 0) return hipSuccess;
-    dim3 grid((unsigned)div_up(N, kBlock)), block(kBlock);
-    if (K == 16)
-        hipLaunchKernelGGL(k_spmv_ell<16>, grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
-    else if (K == 8)
-        hipLaunchKernelGGL(k_spmv_ell<8>, grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
-    else
-        hipLaunchKernelGGL(k_spmv_ell<0>, grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
+    go_spmv_ell<false>(N, K, col, w, x, b, alpha, rowmask, y, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_scatter(int64_t N, int K, const int32_t* col, const float* w, const float* x,
+                               const float* b, const float* alpha, const int32_t* pred, float* xn, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    go_spmv_ell<true>(N, K, col, w, x, b, alpha, pred, xn, s);
     return hipGetLastError();
 }
 

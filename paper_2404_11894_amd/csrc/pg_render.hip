@@ -26,7 +26,7 @@ void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params*
     r.r = cv.take<float>(N);
     r.alpha = cv.take<float>(N);
     r.succ = cv.take<int32_t>(N);
-    r.pred = r.tape ? cv.take<int32_t>(N) : nullptr;
+    r.pred = (r.tape || r.schedule == PG_SCHED_SCATTER) ? cv.take<int32_t>(N) : nullptr;
     r.x = cv.take<float>(3 * N);
     r.y = cv.take<float>(3 * N);
     if (r.schedule == PG_SCHED_SHIFTED) {
@@ -89,6 +89,11 @@ hipError_t render_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, co
         PG_TRY(launch_paths(r.P, N, p->path_offsets, g.inv, r.alpha, r.dpt, r.r, q->init, r.succ, r.pred, x0,
                             g.flag, s));
     }
+    if (r.schedule == PG_SCHED_SCATTER) {
+        // path ends are never written by the scatter: they stay 0 in every buffer
+        if (r.tape) PG_TRY(launch_fill(r.traj + (size_t)N * 3, (size_t)r.D * N * 12, s));
+        else PG_TRY(launch_fill(r.y, (size_t)N * 12, s));
+    }
     if (r.schedule == PG_SCHED_SHIFTED) {
         ProfScope ps(s, "shifted_build");
         PG_TRY(launch_shifted_build(N, K, r.succ, r.col, r.w, r.b, r.alpha, r.mcol, r.mw, r.c, s));
@@ -104,11 +109,14 @@ hipError_t render_iterate(RenderBufs& r, float* x0, hipStream_t s, float** final
     for (int t = 1; t <= r.D; ++t) {
         float* nxt;
         if (r.tape) nxt = r.traj + (size_t)t * N * 3;
-        else if (r.schedule == PG_SCHED_SHIFTED) nxt = (cur == r.x) ? r.y : r.x;
+        else if (r.schedule != PG_SCHED_TWO_PASS) nxt = (cur == r.x) ? r.y : r.x;
         else nxt = r.x;
         if (r.schedule == PG_SCHED_SHIFTED) {
             ProfScope ps(s, "spmv_shifted");
             PG_TRY(launch_spmv_shifted(N, K, r.succ, r.mcol, r.mw, r.c, cur, nxt, s));
+        } else if (r.schedule == PG_SCHED_SCATTER) {
+            ProfScope ps(s, "spmv_scatter");
+            PG_TRY(launch_spmv_scatter(N, K, r.col, r.w, cur, r.b, r.alpha, r.pred, nxt, s));
         } else {
             {
                 ProfScope ps(s, "spmv");

@@ -32,6 +32,7 @@ def test_version_and_default_shift():
     assert pg.pg_default_cell_shift(0) == 20
     assert pg.pg_default_cell_shift(30000) == 16      # 16^3 <= 30000 < 32^3
     assert pg.pg_default_cell_shift(22_000_000) == 12
+    assert pg.pg_default_cell_shift(1000) == 17       # 8^3 <= 1000 < 16^3
     assert pg.pg_default_cell_shift(10 ** 12) == 11   # capped at 512 cells per axis
 
 

@@ -43,7 +43,7 @@ def tiny():
     return scenegen.generate(scenegen.WORKLOADS["tiny"].scene)
 
 
-@pytest.mark.parametrize("schedule", [pg.PG_SCHED_TWO_PASS, pg.PG_SCHED_SHIFTED])
+@pytest.mark.parametrize("schedule", [pg.PG_SCHED_TWO_PASS, pg.PG_SCHED_SHIFTED, pg.PG_SCHED_SCATTER])
 def test_render_tiny_matches_oracle(tiny, schedule):
     w = scenegen.WORKLOADS["tiny"]
     print(f"tiny N={tiny.n_vertices} schedule={schedule}", flush=True)
