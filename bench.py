@@ -49,6 +49,14 @@ def algorithmic_bytes(step, N, K, starts):
     return None
 
 
+def kernel_source_hash():
+    """sha256 over the propagation kernels' source and the header they include."""
+    hsh = hashlib.sha256()
+    for f in ("pg_prop.hip", "pg_internal.h"):
+        hsh.update(open(os.path.join(ROOT, "paper_2404_11894_amd", "csrc", f), "rb").read())
+    return hsh.hexdigest()
+
+
 def read_traffic(kernel, workload):
     """HBM bytes per launch measured with rocprofv3 counters, if the summary
     under profiles/ was taken from the current kernel source."""
@@ -60,8 +68,7 @@ def read_traffic(kernel, workload):
     h = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
     if not m or not h:
         return None
-    src = os.path.join(ROOT, "paper_2404_11894_amd", "csrc", "pg_prop.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+    if kernel_source_hash() != h.group(1):
         return None
     return float(m.group(1))
 
@@ -91,6 +98,89 @@ def cpu_baseline(workload, k, D, g):
                       f"whole pipeline (kNN, weights, {D} iterations, pixels) in {dt:.2f} s"}
 
 
+def time_fwd_adjoint(pg, torch, sc, w, steps, warmup):
+    """The differentiation workload: the same paths, albedo from a 64^3 grid
+    (U[0.95, 0.999], seed 2), loss = sum (I - T)^2 against a seeded target.
+    One step = pg_render with the tape + pg_backward on it.  Counts 2 E D."""
+    import ctypes as C
+    import scenegen
+    dev = torch.device("cuda:0")
+    grid = scenegen.albedo_grid(64, 0.95, 0.999, seed=2)
+    paths = pg.DevicePaths(sc, device=dev, albedo_grid=grid)
+    q = pg.params(k=w.k, D=w.D, g=w.g, flags=pg.PG_FLAG_TAPE)
+    s = paths.struct()
+    nb = C.c_size_t()
+    pg._check(pg.lib().pg_render_workspace_size(C.byref(s), C.byref(q), C.byref(nb)))
+    _, ws, n = pg._workspace(nb.value, dev)
+    image = torch.empty(sc.height, sc.width, 3, device=dev)
+    target = torch.from_numpy(scenegen.target_image((sc.height, sc.width, 3), 0.3, seed=4)).to(dev)
+
+    def step():
+        pg._check(pg.lib().pg_render(C.byref(s), C.byref(q), pg._ptr(image), None, pg._ptr(ws), n,
+                                     pg._stream(dev)))
+        gi = 2.0 * (image - target)
+        return pg.pg_backward(paths, q, gi, workspace=(ws, n))
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    E = sc.n_vertices * min(w.k, sc.n_vertices)
+    ok = bool(torch.isfinite(out["grad_grid"]).all().item()) and bool(torch.isfinite(out["grad_g"]).all().item())
+    del ws, paths
+    torch.cuda.empty_cache()
+    return {"value": round(2 * E * w.D / (ms / 1e3) / 1e9, 2), "unit": "Gedge-updates/s", "ms_per_step": round(ms, 3),
+            "counts": "2*E*D per step (forward + reverse sweep)", "finite": ok,
+            "workload": "same paths, albedo = trilinear 64^3 grid, L2 loss, grad wrt grid and g"}
+
+
+def time_batched(pg, torch, steps):
+    """64 independent scenes: one hipGraph launch of a batch plan vs 64
+    sequential pg_render calls.  Counts sum_s E_s D_s."""
+    import scenegen
+    dev = torch.device("cuda:0")
+    log("generating the 64-scene batch")
+    t0 = time.perf_counter()
+    items = scenegen.generate_batch(64)
+    log(f"batch generated in {time.perf_counter() - t0:.1f} s")
+    paths = [pg.DevicePaths(sc, device=dev) for _, sc in items]
+    params = [pg.params(k=w.k, D=w.D, g=w.g) for w, _ in items]
+    work = sum(p.n_vertices * min(w.k, p.n_vertices) * w.D for (w, _), p in zip(items, paths))
+    nverts = sum(p.n_vertices for p in paths)
+    # per scene: one Renderer (workspace allocated once), launched one after another
+    rends = [pg.Renderer(p, q) for p, q in zip(paths, params)]
+    imgs = [torch.empty(p.height, p.width, 3, device=dev) for p in paths]
+
+    def per_scene():
+        for r, im in zip(rends, imgs):
+            r(im)
+
+    plan = pg.Batch(paths, params, use_graph=True)
+    for f in (per_scene, plan):
+        f()
+    torch.cuda.synchronize()
+    res = {}
+    for name, f in (("per_scene", per_scene), ("batched", plan)):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) * 1e3 / steps
+    same = all(torch.equal(a, b) for a, b in zip(imgs, plan.images))
+    plan.close()
+    del rends, plan
+    torch.cuda.empty_cache()
+    return {"value": round(work / (res["batched"] / 1e3) / 1e9, 2), "unit": "Gedge-updates/s",
+            "ms_batched": round(res["batched"], 3), "ms_per_scene_sequential": round(res["per_scene"], 3),
+            "speedup": round(res["per_scene"] / res["batched"], 3),
+            "per_scene_value": round(work / (res["per_scene"] / 1e3) / 1e9, 2), "images_equal": same,
+            "workload": f"64 scenes, sum N = {nverts}, sum E*D = {work}, k 8-16, D 16-64 (one hipGraph launch)"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +190,8 @@ def main():
     ap.add_argument("--schedule", type=int, default=0, help="0 default, 1 two-pass, 2 shifted, 3 scatter")
     ap.add_argument("--cell-shift", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run a 1 GiB device copy then the render steps (for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -180,6 +272,17 @@ def main():
         "phases_ms": phases,
         "roofline": roof,
     }
+    del render
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        log("timing forward + adjoint")
+        out["fwd_adjoint"] = time_fwd_adjoint(pg, torch, sc, w, max(2, args.steps // 2), 1)
+        log(f"fwd+adjoint {out['fwd_adjoint']['ms_per_step']} ms/step")
+    if not args.no_batched:
+        del paths
+        torch.cuda.empty_cache()
+        out["batched"] = time_batched(pg, torch, max(2, args.steps // 2))
+        log(f"batched {out['batched']['ms_batched']} ms vs per-scene {out['batched']['ms_per_scene_sequential']} ms")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, w.k, w.D, w.g)
     print(json.dumps(out), flush=True)

@@ -129,6 +129,8 @@ void carve_grid(Carver& cv, GridBufs& g, int64_t N, int shift) {
     g.perm = cv.take<int32_t>(N);
     g.inv = cv.take<int32_t>(N);
     g.qs = cv.take<uint64_t>(N);
+    g.redo = cv.take<uint32_t>(N);
+    g.nredo = cv.take<uint32_t>(64);
 }
 
 // quantise, count, scan, scatter.  rec may be NULL.
@@ -198,7 +200,8 @@ pg_status pg_knn(const pg_paths* paths, int32_t k, int32_t cell_shift, int64_t* 
         return finish(s, nullptr, nullptr, 0);
     }
     if ((e = run_grid(paths, g, nullptr, s)) != hipSuccess) return hip_fail(e, "grid build");
-    if ((e = launch_knn(N, K, shift, g.qs, g.perm, g.inv, g.cells, nullptr, col, row_ptr, s)) != hipSuccess)
+    if ((e = launch_knn(N, K, shift, g.qs, g.perm, g.inv, g.cells, nullptr, col, row_ptr, g.redo, g.nredo, s)) !=
+        hipSuccess)
         return hip_fail(e, "knn");
     return finish(s, nullptr, g.flag, 0);
 }

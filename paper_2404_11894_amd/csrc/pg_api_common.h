@@ -55,6 +55,8 @@ struct GridBufs {
     int32_t* perm = nullptr;       // sorted -> path order
     int32_t* inv = nullptr;        // path order -> sorted
     uint64_t* qs = nullptr;        // sorted packed quantised positions
+    uint32_t* redo = nullptr;      // kNN queries handed to the exact search
+    uint32_t* nredo = nullptr;
 };
 
 void carve_grid(Carver& cv, GridBufs& g, int64_t N, int shift);

@@ -387,12 +387,84 @@ __device__ __forceinline__ void knn_write(int64_t s, int K, int m, uint32_t self
     }
 }
 
+// ---- fast path: one 64-bit key per candidate --------------------------
+// key = (min(d2, 2^33 - 1) << 31) | id orders exactly like (d2, id) as long as
+// d2 < 2^33 - 1 (a distance below ~8.8% of the unit cube); a k-th neighbour
+// that far saturates the key, and that query is redone by the exact search.
+constexpr uint64_t kD2Sat = (1ull << 33) - 1;
+
+__device__ __forceinline__ uint64_t make_key(uint64_t d2, uint32_t oid) {
+    return ((d2 < kD2Sat ? d2 : kD2Sat) << 31) | (uint64_t)oid;
+}
+
+template <int KM>
+__device__ __forceinline__ void key_insert(uint64_t (&k)[KM], uint64_t c) {
+    if (c < k[KM - 1]) {
+        k[KM - 1] = c;
+#pragma unroll
+        for (int p = KM - 1; p > 0; --p) {
+            const uint64_t a = k[p - 1], b = k[p];
+            k[p - 1] = b < a ? b : a;
+            k[p] = b < a ? a : b;
+        }
+    }
+}
+
+template <int KM>
+__device__ __forceinline__ void key_shell_search(int64_t s, int shift, int32_t qx, int32_t qy, int32_t qz,
+                                                 const uint64_t* __restrict__ qs, const int32_t* __restrict__ perm,
+                                                 const uint32_t* __restrict__ cell_start, uint64_t (&k)[KM]) {
+    const int G = 1 << (kQBits - shift);
+    const int cx = qx >> shift, cy = qy >> shift, cz = qz >> shift;
+    const int64_t cs = (int64_t)1 << shift;
+    for (int r = 0;; ++r) {
+        for (int dz = -r; dz <= r; ++dz) {
+            const int z = cz + dz;
+            if (z < 0 || z >= G) continue;
+            const int64_t gz = dz < 0 ? (int64_t)qz - ((int64_t)(z + 1) * cs - 1) : (dz > 0 ? (int64_t)z * cs - qz : 0);
+            for (int dy = -r; dy <= r; ++dy) {
+                const int y = cy + dy;
+                if (y < 0 || y >= G) continue;
+                const int64_t gy = dy < 0 ? (int64_t)qy - ((int64_t)(y + 1) * cs - 1) : (dy > 0 ? (int64_t)y * cs - qy : 0);
+                const bool face = (dz == -r || dz == r || dy == -r || dy == r);
+                const int step = (face || r == 0) ? 1 : 2 * r;
+                for (int dx = -r; dx <= r; dx += step) {
+                    const int x = cx + dx;
+                    if (x < 0 || x >= G) continue;
+                    const int64_t gx = dx < 0 ? (int64_t)qx - ((int64_t)(x + 1) * cs - 1) : (dx > 0 ? (int64_t)x * cs - qx : 0);
+                    if ((uint64_t)(gx * gx + gy * gy + gz * gz) > (k[KM - 1] >> 31)) continue;   // cell too far
+                    const uint32_t cell = morton3((uint32_t)x, (uint32_t)y, (uint32_t)z);
+                    const uint32_t beg = cell_start[cell], end = cell_start[cell + 1];
+                    for (uint32_t t = beg; t < end; ++t) {
+                        if ((int64_t)t == s) continue;
+                        int32_t ax, ay, az;
+                        qunpack(qs[t], ax, ay, az);
+                        const int64_t ex = ax - qx, ey = ay - qy, ez = az - qz;
+                        key_insert<KM>(k, make_key((uint64_t)(ex * ex + ey * ey + ez * ez), (uint32_t)perm[t]));
+                    }
+                }
+            }
+        }
+        int64_t gap = INT64_MAX;
+        const int c3[3] = {cx, cy, cz};
+        const int64_t q3[3] = {qx, qy, qz};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (c3[a] - r > 0) gap = min(gap, q3[a] - (int64_t)(c3[a] - r) * cs + 1);
+            if (c3[a] + r < G - 1) gap = min(gap, (int64_t)(c3[a] + r + 1) * cs - q3[a]);
+        }
+        if (gap == INT64_MAX) break;
+        if ((k[KM - 1] >> 31) < (uint64_t)(gap * gap)) break;
+    }
+}
+
 template <int KM>
 __global__ __launch_bounds__(kBlock) void k_knn(int64_t N, int K, int shift, const uint64_t* __restrict__ qs,
                                                 const int32_t* __restrict__ perm, const int32_t* __restrict__ inv,
                                                 const uint32_t* __restrict__ cell_start,
                                                 int32_t* __restrict__ col_sorted, int32_t* __restrict__ col_canon,
-                                                int64_t* __restrict__ row_ptr) {
+                                                int64_t* __restrict__ row_ptr, uint32_t* __restrict__ redo,
+                                                uint32_t* __restrict__ nredo) {
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t s = tile * blockDim.x + threadIdx.x;
     if (s >= N) return;
@@ -400,23 +472,75 @@ __global__ __launch_bounds__(kBlock) void k_knn(int64_t N, int K, int shift, con
     int32_t qx, qy, qz;
     qunpack(qs[s], qx, qy, qz);
     const uint32_t self = (uint32_t)perm[s];
-    uint64_t d[KM];
-    uint32_t o[KM];
-    list_reset<KM>(d, o, m);
-    if (m > 0) shell_search<KM>(s, m, shift, qx, qy, qz, qs, perm, cell_start, d, o);
-    knn_write<KM>(s, K, m, self, N, inv, d, o, col_sorted, col_canon, row_ptr);
+    uint64_t k[KM];
+#pragma unroll
+    for (int p = 0; p < KM; ++p) k[p] = p < KM - m ? 0ull : ~0ull;
+    if (m > 0) {
+        key_shell_search<KM>(s, shift, qx, qy, qz, qs, perm, cell_start, k);
+        if ((k[KM - 1] >> 31) >= kD2Sat) {   // a kept distance saturated: redo exactly
+            redo[atomicAdd(nredo, 1u)] = (uint32_t)s;
+            return;
+        }
+    }
+    if (col_sorted) {   // sliced-ELL layout
+        col_sorted[eidx(s, 0, K)] = (int32_t)s;
+#pragma unroll
+        for (int p = 0; p < KM; ++p)
+            if (p >= KM - m) col_sorted[eidx(s, 1 + p - (KM - m), K)] = inv[(uint32_t)(k[p] & 0x7fffffffu)];
+    }
+    if (col_canon) {
+        int32_t* row = col_canon + (int64_t)self * K;
+        row[0] = (int32_t)self;
+#pragma unroll
+        for (int p = 0; p < KM; ++p)
+            if (p >= KM - m) row[1 + p - (KM - m)] = (int32_t)(k[p] & 0x7fffffffu);
+    }
+    if (row_ptr) {
+        row_ptr[self] = (int64_t)self * K;
+        if (s == 0) row_ptr[N] = N * (int64_t)K;
+    }
+}
+
+// Exact (d2, id) search for the queries the fast path handed over.
+template <int KM>
+__global__ __launch_bounds__(kBlock) void k_knn_exact(int64_t N, int K, int shift, const uint64_t* __restrict__ qs,
+                                                      const int32_t* __restrict__ perm,
+                                                      const int32_t* __restrict__ inv,
+                                                      const uint32_t* __restrict__ cell_start,
+                                                      int32_t* __restrict__ col_sorted,
+                                                      int32_t* __restrict__ col_canon,
+                                                      int64_t* __restrict__ row_ptr,
+                                                      const uint32_t* __restrict__ redo,
+                                                      const uint32_t* __restrict__ nredo) {
+    const uint32_t n = *nredo;
+    const int m = K - 1;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x) {
+        const int64_t s = redo[idx];
+        int32_t qx, qy, qz;
+        qunpack(qs[s], qx, qy, qz);
+        const uint32_t self = (uint32_t)perm[s];
+        uint64_t d[KM];
+        uint32_t o[KM];
+        list_reset<KM>(d, o, m);
+        shell_search<KM>(s, m, shift, qx, qy, qz, qs, perm, cell_start, d, o);
+        knn_write<KM>(s, K, m, self, N, inv, d, o, col_sorted, col_canon, row_ptr);
+    }
 }
 
 hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, const int32_t* perm,
                       const int32_t* inv, const uint32_t* cell_start, int32_t* col_sorted, int32_t* col_canon,
-                      int64_t* row_ptr, hipStream_t s) {
+                      int64_t* row_ptr, uint32_t* redo, uint32_t* nredo, hipStream_t s) {
     if (N == 0) return hipSuccess;
-    dim3 grid((unsigned)div_up(N, kBlock)), block(kBlock);
     const int m = K - 1;
+    hipError_t e = launch_fill(nredo, sizeof(uint32_t), s);
+    if (e != hipSuccess) return e;
     auto go = [&](auto km) {
         constexpr int KM = decltype(km)::value;
-        hipLaunchKernelGGL(k_knn<KM>, grid, block, 0, s, N, K, shift, qsorted, perm, inv, cell_start, col_sorted,
-                           col_canon, row_ptr);
+        hipLaunchKernelGGL(k_knn<KM>, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, K, shift, qsorted,
+                           perm, inv, cell_start, col_sorted, col_canon, row_ptr, redo, nredo);
+        hipLaunchKernelGGL(k_knn_exact<KM>, dim3(256), dim3(kBlock), 0, s, N, K, shift, qsorted, perm, inv,
+                           cell_start, col_sorted, col_canon, row_ptr, (const uint32_t*)redo,
+                           (const uint32_t*)nredo);
     };
     if (m <= 8) go(std::integral_constant<int, 8>{});
     else if (m <= 16) go(std::integral_constant<int, 16>{});

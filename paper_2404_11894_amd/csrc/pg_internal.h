@@ -194,9 +194,11 @@ hipError_t launch_scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, u
 hipError_t launch_scatter(int64_t N, const pg_paths& paths, int shift, const uint32_t* cellid,
                           const uint32_t* rank, const uint32_t* cell_start, int32_t* perm, int32_t* inv,
                           uint64_t* qsorted, VRec* rec, hipStream_t s);
+// redo: [N] scratch list, nredo: one counter (queries the fast 64-bit-key
+// search hands to the exact one)
 hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, const int32_t* perm,
                       const int32_t* inv, const uint32_t* cell_start, int32_t* col_sorted, int32_t* col_canon,
-                      int64_t* row_ptr, hipStream_t s);
+                      int64_t* row_ptr, uint32_t* redo, uint32_t* nredo, hipStream_t s);
 
 // records in path order (no permutation)
 hipError_t launch_pack_records(int64_t N, const pg_paths& paths, VRec* rec, int32_t* flag, hipStream_t s);
