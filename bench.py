@@ -124,17 +124,19 @@ def time_fwd_adjoint(pg, torch, sc, w, steps, warmup):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    pg._check(pg.lib().pg_profile_start())
     t0 = time.perf_counter()
     for _ in range(steps):
         out = step()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    phases = {k: round(v[1] / steps, 3) for k, v in profile_entries(pg).items()}
     E = sc.n_vertices * min(w.k, sc.n_vertices)
     ok = bool(torch.isfinite(out["grad_grid"]).all().item()) and bool(torch.isfinite(out["grad_g"]).all().item())
     del ws, paths
     torch.cuda.empty_cache()
     return {"value": round(2 * E * w.D / (ms / 1e3) / 1e9, 2), "unit": "Gedge-updates/s", "ms_per_step": round(ms, 3),
-            "counts": "2*E*D per step (forward + reverse sweep)", "finite": ok,
+            "counts": "2*E*D per step (forward + reverse sweep)", "finite": ok, "phases_ms": phases,
             "workload": "same paths, albedo = trilinear 64^3 grid, L2 loss, grad wrt grid and g"}
 
 

@@ -88,7 +88,7 @@ struct RenderBufs {
 
 // Reverse-mode buffers, carved right after a render's tape.
 struct BackBufs {
-    int64_t n_rows = 0, n_out = 0, n_slots = 0;   // dL/dg partial-sum slots
+    int64_t n_rows = 0, n_edge = 0, n_out = 0, n_slots = 0;   // dL/dg partial-sum slots
     float* lam_a = nullptr;    // adjoint of L_t, ping
     float* lam_b = nullptr;    // pong
     float* zbar = nullptr;     // [N*3]

@@ -136,43 +136,59 @@ __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, co
 }
 
 // --------------------------------------------- reverse of one iteration ---
-// Row i (group of KP lanes): y_i = b_i + alpha_i z_i, z_i = sum_l w_il L_{t-1}(j_l),
-// L_t(v) = y(succ v).  Adjoint of y_i is lam_t(pred i).  Accumulates
-// d/d alpha_i += <ybar, z_i>, d/d b_i += ybar, stores zbar_i = alpha_i ybar and
-// adds <zbar_i, sum_l dw_il/dg L_{t-1}(j_l)> to the block's dL/dg slot.
-template <int KP>
-__global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int K, const int32_t* __restrict__ col,
+// Row i: y_i = b_i + alpha_i z_i, z_i = sum_l w_il L_{t-1}(j_l), L_t(v) = y(succ v).
+// The adjoint of y_i is lam_t(pred i).  Accumulates d/d alpha_i += <ybar, z_i>
+// and d/d b_i += ybar, stores zbar_i = alpha_i ybar and adds
+// <zbar_i, sum_l dw_il/dg L_{t-1}(j_l)> to the block's dL/dg slot.  One thread
+// per row over the sliced-ELL edges (all K loads issued before the gathers),
+// as in the forward product.  KT = K at compile time, 0: runtime K.
+template <int KT>
+__global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const int32_t* __restrict__ col,
                                                      const float* __restrict__ w, const float* __restrict__ gw,
                                                      const float* __restrict__ xprev, const float* __restrict__ lam,
                                                      const int32_t* __restrict__ pred,
                                                      const float* __restrict__ alpha, float* __restrict__ abar,
                                                      float* __restrict__ bbar, float* __restrict__ zbar,
                                                      double* __restrict__ gpart) {
-    constexpr int GR = kBlock / KP;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x % KP;
-    const int64_t i = tile * GR + threadIdx.x / KP;
-    float zx = 0.f, zy = 0.f, zz = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-    if (i < N && lane < K) {
-        const int64_t e = eidx(i, lane, K);
-        const int64_t j = col[e];
-        const float ww = w[e], gg = gw[e];
-        const f3 xv = ld3(xprev, j);
-        zx = ww * xv.x;
-        zy = ww * xv.y;
-        zz = ww * xv.z;
-        gx = gg * xv.x;
-        gy = gg * xv.y;
-        gz = gg * xv.z;
-    }
-    zx = group_sum<KP>(zx);
-    zy = group_sum<KP>(zy);
-    zz = group_sum<KP>(zz);
-    gx = group_sum<KP>(gx);
-    gy = group_sum<KP>(gy);
-    gz = group_sum<KP>(gz);
+    const int64_t i = tile * kBlock + threadIdx.x;
+    const int K = KT ? KT : Kr;
     double gl = 0.0;
-    if (i < N && lane == 0) {
+    if (i < N) {
+        const int64_t base = (i >> 6) * (int64_t)K * kSlice + (i & (kSlice - 1));
+        float zx = 0.f, zy = 0.f, zz = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        if (KT) {
+            int32_t j[KT > 0 ? KT : 1];
+            float ww[KT > 0 ? KT : 1], gg[KT > 0 ? KT : 1];
+#pragma unroll
+            for (int l = 0; l < KT; ++l) {
+                j[l] = col[base + (int64_t)l * kSlice];
+                ww[l] = w[base + (int64_t)l * kSlice];
+                gg[l] = gw[base + (int64_t)l * kSlice];
+            }
+#pragma unroll
+            for (int l = 0; l < KT; ++l) {
+                const f3 xv = ld3(xprev, j[l]);
+                zx = fmaf(ww[l], xv.x, zx);
+                zy = fmaf(ww[l], xv.y, zy);
+                zz = fmaf(ww[l], xv.z, zz);
+                gx = fmaf(gg[l], xv.x, gx);
+                gy = fmaf(gg[l], xv.y, gy);
+                gz = fmaf(gg[l], xv.z, gz);
+            }
+        } else {
+            for (int l = 0; l < K; ++l) {
+                const int64_t e = base + (int64_t)l * kSlice;
+                const f3 xv = ld3(xprev, col[e]);
+                const float ww = w[e], gg = gw[e];
+                zx = fmaf(ww, xv.x, zx);
+                zy = fmaf(ww, xv.y, zy);
+                zz = fmaf(ww, xv.z, zz);
+                gx = fmaf(gg, xv.x, gx);
+                gy = fmaf(gg, xv.y, gy);
+                gz = fmaf(gg, xv.z, gz);
+            }
+        }
         const int64_t pv = pred[i];
         const f3 yb = pv >= 0 ? ld3(lam, pv) : f3{0.f, 0.f, 0.f};
         abar[i] += dot3(yb, f3{zx, zy, zz});
@@ -355,9 +371,10 @@ void carve_back(Carver& cv, BackBufs& bb, const RenderBufs& r, const pg_paths* p
     const int64_t N = r.N, E = N * (int64_t)r.K;
     int kp = 1;
     while (kp < (r.K > 0 ? r.K : 1)) kp *= 2;
-    bb.n_rows = div_up(N > 0 ? N : 1, kBlock / kp);
+    bb.n_rows = div_up(N > 0 ? N : 1, kBlock);          // reverse sweep: one thread per row
+    bb.n_edge = div_up(N > 0 ? N : 1, kBlock / kp);     // direct-term adjoint: KP lanes per row
     bb.n_out = div_up(r.P > 0 ? r.P : 1, kBlock);
-    bb.n_slots = 2 * bb.n_rows + bb.n_out;
+    bb.n_slots = bb.n_rows + bb.n_edge + bb.n_out;
     bb.lam_a = cv.take<float>(3 * N);
     bb.lam_b = cv.take<float>(3 * N);
     bb.zbar = cv.take<float>(3 * N);
@@ -411,7 +428,7 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
     const float* xD = r.traj + (size_t)D * N * 3;
     double* g_rows = bb.gpart;
     double* g_edges = bb.gpart + bb.n_rows;
-    double* g_out = bb.gpart + 2 * bb.n_rows;
+    double* g_out = bb.gpart + bb.n_rows + bb.n_edge;
     {
         ProfScope ps(s, "out_adjoint");
         hipLaunchKernelGGL(k_out_adjoint, dim3((unsigned)bb.n_out), dim3(kBlock), 0, s, *p, c, r.g.inv, r.col, r.w,
@@ -424,11 +441,14 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
         const float* xprev = r.traj + (size_t)(t - 1) * N * 3;
         {
             ProfScope ps(s, "rev_rows");
-            dispatch_kp(K, [&](auto kp) {
-                constexpr int KP = decltype(kp)::value;
-                hipLaunchKernelGGL(k_rev_rows<KP>, dim3((unsigned)bb.n_rows), dim3(kBlock), 0, s, N, K, r.col,
+            auto go = [&](auto kt) {
+                constexpr int KT = decltype(kt)::value;
+                hipLaunchKernelGGL(k_rev_rows<KT>, dim3((unsigned)bb.n_rows), dim3(kBlock), 0, s, N, K, r.col,
                                    r.w, r.gw, xprev, lam, r.pred, r.alpha, bb.abar, bb.bbar, bb.zbar, g_rows);
-            });
+            };
+            if (K == 16) go(std::integral_constant<int, 16>{});
+            else if (K == 8) go(std::integral_constant<int, 8>{});
+            else go(std::integral_constant<int, 0>{});
         }
         {
             ProfScope ps(s, "rev_cols");
