@@ -96,11 +96,18 @@ struct BackBufs {
     float* bbar = nullptr;     // [N*3]
     float* dptbar = nullptr;   // [N*3]
     float* rbar = nullptr;     // [N]
-    uint32_t* toff = nullptr;  // transposed CSR offsets [N+1]
-    uint32_t* tcur = nullptr;  // counts, then cursors [N+1]
+    // W^T as sliced ELL (slices of 64 T-rows, at most cap entries per T-row)
+    uint32_t cap = 0;
+    int64_t nslices = 0;
+    uint32_t* tdeg = nullptr;  // in-degree [N+1]
+    uint32_t* tcur = nullptr;  // slice lengths, then cursors [N+1]
+    uint32_t* soff = nullptr;  // slice offsets [nslices+1]
     uint32_t* tpart = nullptr; // scan partials
-    int32_t* tsrc = nullptr;   // [E] source rows
-    float* tw = nullptr;       // [E]
+    int32_t* tsrc = nullptr;   // [nslices*64*cap] source rows
+    float* tw = nullptr;       // [nslices*64*cap]
+    int32_t* ovf = nullptr;    // overflow (j, i) pairs [2E]
+    float* ovw = nullptr;      // overflow weights [E]
+    uint32_t* novf = nullptr;
     double* gpart = nullptr;   // [n_slots]
     float* image = nullptr;    // forward image when the tape is recomputed
 };

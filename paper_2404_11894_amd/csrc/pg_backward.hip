@@ -31,50 +31,78 @@ __device__ inline double block_sum_d(double v) {
 
 __device__ inline float dot3(f3 a, f3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
 
-// ------------------------------------------------------- transposed CSR ---
-
-// t runs over the N*K edges in row order; eidx gives their sliced-ELL slot.
+// ------------------------------------------------- transposed operator ---
+// W^T in a sliced ELL: T-row j (the rows i that have j as a neighbour) lives in
+// slice j/64; entry q of the 64 T-rows of a slice is contiguous, and a slice
+// is as long as its longest T-row, capped at `cap` entries.  Entries past the
+// cap go to an overflow list of (j, i, w) applied with atomics (none for
+// ordinary neighbour graphs; degenerate inputs such as many coincident points
+// can have a few).  t runs over the N*K edges in row order.
 __global__ __launch_bounds__(kBlock) void k_tcount(int64_t E, int K, const int32_t* __restrict__ col,
                                                    uint32_t* __restrict__ cnt) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < E) atomicAdd(&cnt[col[eidx(t / K, (int)(t % K), K)]], 1u);
 }
 
-__global__ __launch_bounds__(kBlock) void k_copy_u32(int64_t n, const uint32_t* __restrict__ a,
-                                                     uint32_t* __restrict__ b) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = a[i];
+// slice length = 64 * min(max in-degree of its 64 T-rows, cap); one wave per slice
+__global__ __launch_bounds__(kBlock) void k_tslice_len(int64_t N, int64_t nslices, uint32_t cap,
+                                                       const uint32_t* __restrict__ deg,
+                                                       uint32_t* __restrict__ len) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t d = j < N ? min(deg[j], cap) : 0u;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) d = max(d, (uint32_t)__shfl_xor((int)d, o, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0 && (j >> 6) < nslices) len[j >> 6] = d * (uint32_t)kSlice;
 }
 
-__global__ __launch_bounds__(kBlock) void k_tscatter(int64_t E, int K, const int32_t* __restrict__ col,
-                                                     const float* __restrict__ w, uint32_t* __restrict__ cur,
-                                                     int32_t* __restrict__ tsrc, float* __restrict__ tw) {
+__global__ __launch_bounds__(kBlock) void k_tscatter(int64_t E, int K, uint32_t cap, const int32_t* __restrict__ col,
+                                                     const float* __restrict__ w, const uint32_t* __restrict__ soff,
+                                                     uint32_t* __restrict__ cur, int32_t* __restrict__ tsrc,
+                                                     float* __restrict__ tw, int32_t* __restrict__ ovf,
+                                                     float* __restrict__ ovw, uint32_t* __restrict__ novf) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= E) return;
     const int64_t i = t / K;
     const int64_t e = eidx(i, (int)(t - i * K), K);
-    const uint32_t pos = atomicAdd(&cur[col[e]], 1u);
-    tsrc[pos] = (int32_t)i;
-    tw[pos] = w[e];
+    const int64_t j = col[e];
+    const uint32_t q = atomicAdd(&cur[j], 1u);
+    if (q < cap) {
+        const int64_t p = (int64_t)soff[j >> 6] + (int64_t)q * kSlice + (j & (kSlice - 1));
+        tsrc[p] = (int32_t)i;
+        tw[p] = w[e];
+    } else {
+        const uint32_t o = atomicAdd(novf, 1u);
+        ovf[2 * (int64_t)o] = (int32_t)j;
+        ovf[2 * (int64_t)o + 1] = (int32_t)i;
+        ovw[o] = w[e];
+    }
 }
 
-// each transposed row sorted by source row, so sums run in a fixed order
-__global__ __launch_bounds__(kBlock) void k_tsort(int64_t N, const uint32_t* __restrict__ toff,
-                                                  int32_t* __restrict__ tsrc, float* __restrict__ tw) {
+// each T-row sorted by source row (a fixed summation order), then padded with
+// zero-weight self entries up to its slice's length
+__global__ __launch_bounds__(kBlock) void k_tsort(int64_t N, uint32_t cap, const uint32_t* __restrict__ soff,
+                                                  const uint32_t* __restrict__ deg, int32_t* __restrict__ tsrc,
+                                                  float* __restrict__ tw) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
-    const uint32_t a = toff[j], e = toff[j + 1];
-    for (uint32_t q = a + 1; q < e; ++q) {
-        const int32_t s = tsrc[q];
-        const float ww = tw[q];
+    const int64_t base = (int64_t)soff[j >> 6] + (j & (kSlice - 1));
+    const uint32_t len = (soff[(j >> 6) + 1] - soff[j >> 6]) / kSlice;
+    const uint32_t n = min(deg[j], cap);
+    for (uint32_t q = 1; q < n; ++q) {
+        const int32_t sv = tsrc[base + (int64_t)q * kSlice];
+        const float wv = tw[base + (int64_t)q * kSlice];
         uint32_t p = q;
-        while (p > a && tsrc[p - 1] > s) {
-            tsrc[p] = tsrc[p - 1];
-            tw[p] = tw[p - 1];
+        while (p > 0 && tsrc[base + (int64_t)(p - 1) * kSlice] > sv) {
+            tsrc[base + (int64_t)p * kSlice] = tsrc[base + (int64_t)(p - 1) * kSlice];
+            tw[base + (int64_t)p * kSlice] = tw[base + (int64_t)(p - 1) * kSlice];
             --p;
         }
-        tsrc[p] = s;
-        tw[p] = ww;
+        tsrc[base + (int64_t)p * kSlice] = sv;
+        tw[base + (int64_t)p * kSlice] = wv;
+    }
+    for (uint32_t q = n; q < len; ++q) {
+        tsrc[base + (int64_t)q * kSlice] = (int32_t)j;
+        tw[base + (int64_t)q * kSlice] = 0.0f;
     }
 }
 
@@ -204,22 +232,56 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const in
     if (threadIdx.x == 0) gpart[tile] += t;
 }
 
-// lam_{t-1}(j) = sum over rows i with j in N(i) of w_ij zbar_i (transposed CSR).
-__global__ __launch_bounds__(kBlock) void k_rev_cols(int64_t N, const uint32_t* __restrict__ toff,
+// lam_{t-1}(j) = sum over rows i with j in N(i) of w_ij zbar_i: one thread per
+// T-row over the sliced-ELL transpose (every lane of a wave runs its slice's
+// length), four entries loaded ahead.
+__global__ __launch_bounds__(kBlock) void k_rev_cols(int64_t N, const uint32_t* __restrict__ soff,
                                                      const int32_t* __restrict__ tsrc, const float* __restrict__ tw,
                                                      const float* __restrict__ zbar, float* __restrict__ lam) {
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t j = tile * blockDim.x + threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
+    const int64_t base = (int64_t)soff[j >> 6] + (j & (kSlice - 1));
+    const uint32_t len = (soff[(j >> 6) + 1] - soff[j >> 6]) / kSlice;
     float ax = 0.f, ay = 0.f, az = 0.f;
-    for (uint32_t q = toff[j], e = toff[j + 1]; q < e; ++q) {
-        const float ww = tw[q];
-        const f3 zb = ld3(zbar, tsrc[q]);
+    uint32_t q = 0;
+    for (; q + 4 <= len; q += 4) {
+        int32_t src[4];
+        float ww[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            src[u] = __builtin_nontemporal_load(tsrc + base + (int64_t)(q + u) * kSlice);
+            ww[u] = __builtin_nontemporal_load(tw + base + (int64_t)(q + u) * kSlice);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const f3 zb = ld3(zbar, src[u]);
+            ax = fmaf(ww[u], zb.x, ax);
+            ay = fmaf(ww[u], zb.y, ay);
+            az = fmaf(ww[u], zb.z, az);
+        }
+    }
+    for (; q < len; ++q) {
+        const f3 zb = ld3(zbar, tsrc[base + (int64_t)q * kSlice]);
+        const float ww = tw[base + (int64_t)q * kSlice];
         ax = fmaf(ww, zb.x, ax);
         ay = fmaf(ww, zb.y, ay);
         az = fmaf(ww, zb.z, az);
     }
     st3(lam, j, f3{ax, ay, az});
+}
+
+__global__ __launch_bounds__(kBlock) void k_rev_overflow(const int32_t* __restrict__ ovf, const float* __restrict__ ovw,
+                                                         const uint32_t* __restrict__ novf,
+                                                         const float* __restrict__ zbar, float* __restrict__ lam) {
+    const uint32_t n = *novf;
+    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < n; o += gridDim.x * blockDim.x) {
+        const int64_t j = ovf[2 * (int64_t)o], i = ovf[2 * (int64_t)o + 1];
+        const float ww = ovw[o];
+        const f3 zb = ld3(zbar, i);
+        atomicAdd(&lam[3 * j], ww * zb.x);
+        atomicAdd(&lam[3 * j + 1], ww * zb.y);
+        atomicAdd(&lam[3 * j + 2], ww * zb.z);
+    }
 }
 
 // ------------------------------- reverse of the path-traced initial value ---
@@ -338,23 +400,57 @@ __global__ __launch_bounds__(kBlock) void k_edges_adjoint(int64_t N, Consts c, c
 }
 
 // ------------------------------------------- albedo grid and per vertex ---
+// The 256 vertices of a block are consecutive in the spatial order, so their
+// 8 x 256 trilinear contributions fall on a few dozen voxels: they are summed
+// in an LDS hash table (open addressing on the voxel index) and each distinct
+// voxel is added to the grid once.  A contribution that finds no free slot
+// within kProbe probes goes to the grid directly.
+constexpr int kHash = 1024;
+constexpr int kProbe = 32;
+constexpr uint32_t kEmpty = 0xffffffffu;
+
 __global__ __launch_bounds__(kBlock) void k_grid_adjoint(int64_t N, pg_paths P, const int32_t* __restrict__ perm,
                                                          const float* __restrict__ abar,
                                                          float* __restrict__ grad_grid,
                                                          float* __restrict__ grad_alpha) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int64_t v = perm[i];
-    const float ab = abar[i];
-    if (grad_alpha) grad_alpha[v] = ab;
-    if (grad_grid && P.albedo_grid) {
-        uint32_t idx[8];
-        float tw[8];
-        trilerp_corners(P.albedo_grid_res, P.pos[3 * v], P.pos[3 * v + 1], P.pos[3 * v + 2], idx, tw);
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (tw[q] != 0.0f) atomicAdd(&grad_grid[idx[q]], ab * tw[q]);
+    __shared__ uint32_t hkey[kHash];
+    __shared__ float hval[kHash];
+    for (int h = threadIdx.x; h < kHash; h += kBlock) {
+        hkey[h] = kEmpty;
+        hval[h] = 0.0f;
     }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool grid = grad_grid && P.albedo_grid;
+    if (i < N) {
+        const int64_t v = perm[i];
+        const float ab = abar[i];
+        if (grad_alpha) grad_alpha[v] = ab;
+        if (grid) {
+            uint32_t idx[8];
+            float tw[8];
+            trilerp_corners(P.albedo_grid_res, P.pos[3 * v], P.pos[3 * v + 1], P.pos[3 * v + 2], idx, tw);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (tw[q] == 0.0f) continue;
+                const float val = ab * tw[q];
+                uint32_t h = (idx[q] * 2654435761u) >> 22;   // 10-bit multiplicative hash
+                bool done = false;
+                for (int probe = 0; probe < kProbe && !done; ++probe, h = (h + 1) & (kHash - 1)) {
+                    const uint32_t k = atomicCAS(&hkey[h], kEmpty, idx[q]);
+                    if (k == kEmpty || k == idx[q]) {
+                        atomicAdd(&hval[h], val);
+                        done = true;
+                    }
+                }
+                if (!done) atomicAdd(&grad_grid[idx[q]], val);
+            }
+        }
+    }
+    __syncthreads();
+    if (grid)
+        for (int h = threadIdx.x; h < kHash; h += kBlock)
+            if (hkey[h] != kEmpty) atomicAdd(&grad_grid[hkey[h]], hval[h]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce_g(int64_t n, const double* __restrict__ gpart,
@@ -382,11 +478,17 @@ void carve_back(Carver& cv, BackBufs& bb, const RenderBufs& r, const pg_paths* p
     bb.bbar = cv.take<float>(3 * N);
     bb.dptbar = cv.take<float>(3 * N);
     bb.rbar = cv.take<float>(N);
-    bb.toff = cv.take<uint32_t>(N + 1);
+    bb.cap = (uint32_t)(2 * (r.K > 0 ? r.K : 1));
+    bb.nslices = div_up(N > 0 ? N : 1, kSlice);
+    bb.tdeg = cv.take<uint32_t>(N + 1);
     bb.tcur = cv.take<uint32_t>(N + 1);
-    bb.tpart = cv.take<uint32_t>(scan_partials_bytes(N + 1) / 4);
-    bb.tsrc = cv.take<int32_t>(E);
-    bb.tw = cv.take<float>(E);
+    bb.soff = cv.take<uint32_t>(bb.nslices + 1);
+    bb.tpart = cv.take<uint32_t>(scan_partials_bytes(bb.nslices + 1) / 4);
+    bb.tsrc = cv.take<int32_t>(bb.nslices * kSlice * (int64_t)bb.cap);
+    bb.tw = cv.take<float>(bb.nslices * kSlice * (int64_t)bb.cap);
+    bb.ovf = cv.take<int32_t>(2 * E);
+    bb.ovw = cv.take<float>(E);
+    bb.novf = cv.take<uint32_t>(64);
     bb.gpart = cv.take<double>(bb.n_slots);
     bb.image = cv.take<float>((int64_t)p->width * p->height * 3);
 }
@@ -413,16 +515,20 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
         PG_TRY(launch_fill(grad_grid, (size_t)(R * R * R) * 4, s));
     }
     if (N > 0) {
-        // transposed CSR of W (sorted ids)
+        // sliced-ELL transpose of W (sorted ids)
         ProfScope ps(s, "transpose");
+        PG_TRY(launch_fill(bb.tdeg, (size_t)(N + 1) * 4, s));
         PG_TRY(launch_fill(bb.tcur, (size_t)(N + 1) * 4, s));
-        hipLaunchKernelGGL(k_tcount, dim3((unsigned)div_up(E, kBlock)), dim3(kBlock), 0, s, E, K, r.col, bb.tcur);
-        PG_TRY(launch_scan_exclusive(bb.tcur, bb.toff, N, bb.tpart, s));
-        hipLaunchKernelGGL(k_copy_u32, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.toff, bb.tcur);
-        hipLaunchKernelGGL(k_tscatter, dim3((unsigned)div_up(E, kBlock)), dim3(kBlock), 0, s, E, K, r.col, r.w,
-                           bb.tcur, bb.tsrc, bb.tw);
-        hipLaunchKernelGGL(k_tsort, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.toff, bb.tsrc,
-                           bb.tw);
+        PG_TRY(launch_fill(bb.novf, 4, s));
+        hipLaunchKernelGGL(k_tcount, dim3((unsigned)div_up(E, kBlock)), dim3(kBlock), 0, s, E, K, r.col, bb.tdeg);
+        hipLaunchKernelGGL(k_tslice_len, dim3((unsigned)div_up(bb.nslices * kSlice, kBlock)), dim3(kBlock), 0, s,
+                           N, bb.nslices, bb.cap, bb.tdeg, bb.tcur);
+        PG_TRY(launch_scan_exclusive(bb.tcur, bb.soff, bb.nslices, bb.tpart, s));
+        PG_TRY(launch_fill(bb.tcur, (size_t)(N + 1) * 4, s));
+        hipLaunchKernelGGL(k_tscatter, dim3((unsigned)div_up(E, kBlock)), dim3(kBlock), 0, s, E, K, bb.cap, r.col,
+                           r.w, bb.soff, bb.tcur, bb.tsrc, bb.tw, bb.ovf, bb.ovw, bb.novf);
+        hipLaunchKernelGGL(k_tsort, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.cap, bb.soff,
+                           bb.tdeg, bb.tsrc, bb.tw);
         PG_TRY(hipGetLastError());
     }
     const float* xD = r.traj + (size_t)D * N * 3;
@@ -452,8 +558,10 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
         }
         {
             ProfScope ps(s, "rev_cols");
-            hipLaunchKernelGGL(k_rev_cols, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.toff,
+            hipLaunchKernelGGL(k_rev_cols, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.soff,
                                bb.tsrc, bb.tw, bb.zbar, lam_next);
+            hipLaunchKernelGGL(k_rev_overflow, dim3(64), dim3(kBlock), 0, s, bb.ovf, bb.ovw, bb.novf, bb.zbar,
+                               lam_next);
         }
         PG_TRY(hipGetLastError());
         float* tmp = lam;
@@ -475,6 +583,9 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
                                c, r.col, r.rec, bb.bbar, bb.dptbar, bb.rbar, bb.abar, g_edges);
         });
         PG_TRY(hipGetLastError());
+    }
+    if (N > 0) {
+        ProfScope ps(s, "grid_adjoint");
         hipLaunchKernelGGL(k_grid_adjoint, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, *p, r.g.perm,
                            bb.abar, grad_grid, grad_alpha);
         PG_TRY(hipGetLastError());
@@ -520,9 +631,11 @@ pg_status pg_backward(const pg_paths* paths, const pg_params* params, const floa
     if (!grad_image) return fail(PG_ERR_ARG, "grad_image is NULL");
     if (grad_grid && !paths->albedo_grid) return fail(PG_ERR_ARG, "grad_grid needs paths->albedo_grid");
     if (!grad_grid && !grad_albedo && !grad_g) return fail(PG_ERR_ARG, "no gradient requested");
-    if (paths->n_vertices * (int64_t)(paths->n_vertices < params->k ? paths->n_vertices : params->k) >=
-        ((int64_t)1 << 32))
-        return fail(PG_ERR_UNSUPPORTED, "pg_backward needs N*K < 2^32 edges");
+    {
+        const int64_t N = paths->n_vertices, K = N < params->k ? N : params->k;
+        if (N * K >= ((int64_t)1 << 32) || div_up(N, kSlice) * kSlice * 2 * K >= ((int64_t)1 << 32))
+            return fail(PG_ERR_UNSUPPORTED, "pg_backward needs N*K < 2^31 edges");
+    }
     Carver dry(nullptr);
     RenderBufs r;
     BackBufs bb;

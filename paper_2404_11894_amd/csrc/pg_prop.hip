@@ -79,12 +79,17 @@ hipError_t launch_spmv(int64_t N, int K, const int32_t* col, const float* w, con
 // rowmask (nullable): rows with rowmask[i] < 0 output 0.  alpha NULL means 1.
 // SCATTER: the row's result is stored at y[rowmask[i]] (the predecessor) and
 // rows with rowmask[i] < 0 are skipped; otherwise such rows store 0 at y[i].
+//
+// Blocks run in plain launch order (all XCDs sweep the same region of the
+// sorted rows together, which measured faster here than giving each XCD its
+// own contiguous range), and the edge ids and weights, read exactly once, are
+// loaded non-temporally so they do not displace the gathered vector in L2.
 template <int KT, bool SCATTER>
 __global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int Kr, const int32_t* __restrict__ col,
                                                      const float* __restrict__ w, const float* __restrict__ x,
                                                      const float* __restrict__ b, const float* __restrict__ alpha,
                                                      const int32_t* __restrict__ rowmask, float* __restrict__ y) {
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t tile = blockIdx.x;
     const int64_t i = tile * kBlock + threadIdx.x;
     if (i >= N) return;
     int64_t dst = i;
@@ -104,8 +109,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int Kr, const in
         float ww[KT > 0 ? KT : 1];
 #pragma unroll
         for (int l = 0; l < KT; ++l) {
-            j[l] = col[base + (int64_t)l * kSlice];
-            ww[l] = w[base + (int64_t)l * kSlice];
+            j[l] = __builtin_nontemporal_load(col + base + (int64_t)l * kSlice);
+            ww[l] = __builtin_nontemporal_load(w + base + (int64_t)l * kSlice);
         }
 #pragma unroll
         for (int l = 0; l < KT; ++l) {
