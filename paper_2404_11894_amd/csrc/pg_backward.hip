@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const in
                                                      const float* __restrict__ alpha, float* __restrict__ abar,
                                                      float* __restrict__ bbar, float* __restrict__ zbar,
                                                      double* __restrict__ gpart) {
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t tile = blockIdx.x;   // launch order, as the forward product
     const int64_t i = tile * kBlock + threadIdx.x;
     const int K = KT ? KT : Kr;
     double gl = 0.0;
@@ -190,9 +190,9 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const in
             float ww[KT > 0 ? KT : 1], gg[KT > 0 ? KT : 1];
 #pragma unroll
             for (int l = 0; l < KT; ++l) {
-                j[l] = col[base + (int64_t)l * kSlice];
-                ww[l] = w[base + (int64_t)l * kSlice];
-                gg[l] = gw[base + (int64_t)l * kSlice];
+                j[l] = __builtin_nontemporal_load(col + base + (int64_t)l * kSlice);
+                ww[l] = __builtin_nontemporal_load(w + base + (int64_t)l * kSlice);
+                gg[l] = __builtin_nontemporal_load(gw + base + (int64_t)l * kSlice);
             }
 #pragma unroll
             for (int l = 0; l < KT; ++l) {
