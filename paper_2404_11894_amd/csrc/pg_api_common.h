@@ -69,9 +69,9 @@ struct RenderBufs {
     int K = 0, D = 0, schedule = 0;
     bool tape = false;
     VRec* rec = nullptr;
-    int32_t* col = nullptr;   // [N*K] sorted ids, row-major
-    float* w = nullptr;       // [N*K]
-    float* gw = nullptr;      // [N*K] dw/dg (tape)
+    int32_t* col = nullptr;   // [ell_size(N, K)] sorted ids, sliced ELL
+    float* w = nullptr;       // [ell_size(N, K)]
+    float* gw = nullptr;      // [ell_size(N, K)] dw/dg (tape)
     float* b = nullptr;       // [N*3]
     float* dpt = nullptr;     // [N*3]
     float* r = nullptr;       // [N]

@@ -183,38 +183,40 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const in
     const int K = KT ? KT : Kr;
     double gl = 0.0;
     if (i < N) {
-        const int64_t base = (i >> 6) * (int64_t)K * kSlice + (i & (kSlice - 1));
+        const int64_t base = ell_row(i, K);
         float zx = 0.f, zy = 0.f, zz = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        auto acc = [&](int32_t jl, float wl, float gl_) {
+            const f3 xv = ld3(xprev, jl);
+            zx = fmaf(wl, xv.x, zx);
+            zy = fmaf(wl, xv.y, zy);
+            zz = fmaf(wl, xv.z, zz);
+            gx = fmaf(gl_, xv.x, gx);
+            gy = fmaf(gl_, xv.y, gy);
+            gz = fmaf(gl_, xv.z, gz);
+        };
         if (KT) {
-            int32_t j[KT > 0 ? KT : 1];
-            float ww[KT > 0 ? KT : 1], gg[KT > 0 ? KT : 1];
+            constexpr int NQ = KT > 0 ? KT / 4 : 1;
+            i32x4 j[NQ];
+            f32x4 ww[NQ], gg[NQ];
 #pragma unroll
-            for (int l = 0; l < KT; ++l) {
-                j[l] = __builtin_nontemporal_load(col + base + (int64_t)l * kSlice);
-                ww[l] = __builtin_nontemporal_load(w + base + (int64_t)l * kSlice);
-                gg[l] = __builtin_nontemporal_load(gw + base + (int64_t)l * kSlice);
+            for (int q = 0; q < NQ; ++q) {
+                j[q] = ld_quad_nt(col + base + q * kQuadStride);
+                ww[q] = ld_quad_nt(w + base + q * kQuadStride);
+                gg[q] = ld_quad_nt(gw + base + q * kQuadStride);
             }
 #pragma unroll
-            for (int l = 0; l < KT; ++l) {
-                const f3 xv = ld3(xprev, j[l]);
-                zx = fmaf(ww[l], xv.x, zx);
-                zy = fmaf(ww[l], xv.y, zy);
-                zz = fmaf(ww[l], xv.z, zz);
-                gx = fmaf(gg[l], xv.x, gx);
-                gy = fmaf(gg[l], xv.y, gy);
-                gz = fmaf(gg[l], xv.z, gz);
+            for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc(j[q][c], ww[q][c], gg[q][c]);
             }
         } else {
-            for (int l = 0; l < K; ++l) {
-                const int64_t e = base + (int64_t)l * kSlice;
-                const f3 xv = ld3(xprev, col[e]);
-                const float ww = w[e], gg = gw[e];
-                zx = fmaf(ww, xv.x, zx);
-                zy = fmaf(ww, xv.y, zy);
-                zz = fmaf(ww, xv.z, zz);
-                gx = fmaf(gg, xv.x, gx);
-                gy = fmaf(gg, xv.y, gy);
-                gz = fmaf(gg, xv.z, gz);
+            for (int q = 0; 4 * q < K; ++q) {
+                const i32x4 jq = ld_quad_nt(col + base + q * kQuadStride);
+                const f32x4 wq = ld_quad_nt(w + base + q * kQuadStride);
+                const f32x4 gq = ld_quad_nt(gw + base + q * kQuadStride);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (4 * q + c < K) acc(jq[c], wq[c], gq[c]);
             }
         }
         const int64_t pv = pred[i];

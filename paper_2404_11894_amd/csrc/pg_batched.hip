@@ -46,16 +46,20 @@ __global__ __launch_bounds__(kBlock) void k_spmv_batched(const SceneDesc* __rest
     const int64_t i = (blockIdx.x - d.blk0) * (int64_t)kBlock + threadIdx.x;
     if (i >= d.nrows) return;
     const int K = d.K;
-    const int64_t base = (i >> 6) * (int64_t)K * kSlice + (i & (kSlice - 1));
+    const int64_t base = ell_row(i, K);
     float ax = 0.f, ay = 0.f, az = 0.f;
-#pragma unroll 4
-    for (int l = 0; l < K; ++l) {
-        const int64_t j = d.col[base + (int64_t)l * kSlice];
-        const float ww = d.w[base + (int64_t)l * kSlice];
-        const f3 xv = ld3(d.x, j);
-        ax = fmaf(ww, xv.x, ax);
-        ay = fmaf(ww, xv.y, ay);
-        az = fmaf(ww, xv.z, az);
+    for (int q = 0; 4 * q < K; ++q) {
+        const i32x4 jq = ld_quad_nt(d.col + base + q * kQuadStride);
+        const f32x4 wq = ld_quad_nt(d.w + base + q * kQuadStride);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (4 * q + c < K) {
+                const f3 xv = ld3(d.x, jq[c]);
+                ax = fmaf(wq[c], xv.x, ax);
+                ay = fmaf(wq[c], xv.y, ay);
+                az = fmaf(wq[c], xv.z, az);
+            }
+        }
     }
     const float a = d.alpha[i];
     const f3 bb = ld3(d.b, i);

@@ -410,38 +410,6 @@ __device__ __forceinline__ void key_insert(uint64_t (&k)[KM], uint64_t c) {
     }
 }
 
-// The 26 cells of the first shell, nearest kinds first (6 faces, 12 edges,
-// 8 corners): the list fills from the closer cells, so the box test prunes
-// more of the corners and edges.
-__constant__ int8_t kShell1[26][3] = {
-    {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1},
-    {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 1, 0}, {-1, 0, -1}, {1, 0, -1},
-    {-1, 0, 1}, {1, 0, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}, {0, 1, 1},
-    {-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, 1}, {1, 1, 1}};
-
-// Visits cell (x, y, z) unless its box is farther than the current worst key.
-template <int KM>
-__device__ __forceinline__ void key_visit_cell(int64_t s, int shift, int x, int y, int z, int32_t qx, int32_t qy,
-                                               int32_t qz, const uint64_t* __restrict__ qs,
-                                               const int32_t* __restrict__ perm,
-                                               const uint32_t* __restrict__ cell_start, uint64_t (&k)[KM]) {
-    const int64_t cs = (int64_t)1 << shift;
-    const int64_t lx = (int64_t)x * cs, ly = (int64_t)y * cs, lz = (int64_t)z * cs;
-    const int64_t gx = qx < lx ? lx - qx : (qx > lx + cs - 1 ? qx - (lx + cs - 1) : 0);
-    const int64_t gy = qy < ly ? ly - qy : (qy > ly + cs - 1 ? qy - (ly + cs - 1) : 0);
-    const int64_t gz = qz < lz ? lz - qz : (qz > lz + cs - 1 ? qz - (lz + cs - 1) : 0);
-    if ((uint64_t)(gx * gx + gy * gy + gz * gz) > (k[KM - 1] >> 31)) return;   // whole cell too far
-    const uint32_t cell = morton3((uint32_t)x, (uint32_t)y, (uint32_t)z);
-    const uint32_t beg = cell_start[cell], end = cell_start[cell + 1];
-    for (uint32_t t = beg; t < end; ++t) {
-        if ((int64_t)t == s) continue;
-        int32_t ax, ay, az;
-        qunpack(qs[t], ax, ay, az);
-        const int64_t ex = ax - qx, ey = ay - qy, ez = az - qz;
-        key_insert<KM>(k, make_key((uint64_t)(ex * ex + ey * ey + ez * ez), (uint32_t)perm[t]));
-    }
-}
-
 template <int KM>
 __device__ __forceinline__ void key_shell_search(int64_t s, int shift, int32_t qx, int32_t qy, int32_t qz,
                                                  const uint64_t* __restrict__ qs, const int32_t* __restrict__ perm,
@@ -450,27 +418,29 @@ __device__ __forceinline__ void key_shell_search(int64_t s, int shift, int32_t q
     const int cx = qx >> shift, cy = qy >> shift, cz = qz >> shift;
     const int64_t cs = (int64_t)1 << shift;
     for (int r = 0;; ++r) {
-        if (r == 0) {
-            key_visit_cell<KM>(s, shift, cx, cy, cz, qx, qy, qz, qs, perm, cell_start, k);
-        } else if (r == 1) {
-            for (int c = 0; c < 26; ++c) {
-                const int x = cx + kShell1[c][0], y = cy + kShell1[c][1], z = cz + kShell1[c][2];
-                if (x < 0 || x >= G || y < 0 || y >= G || z < 0 || z >= G) continue;
-                key_visit_cell<KM>(s, shift, x, y, z, qx, qy, qz, qs, perm, cell_start, k);
-            }
-        } else {
-            for (int dz = -r; dz <= r; ++dz) {
-                const int z = cz + dz;
-                if (z < 0 || z >= G) continue;
-                for (int dy = -r; dy <= r; ++dy) {
-                    const int y = cy + dy;
-                    if (y < 0 || y >= G) continue;
-                    const bool face = (dz == -r || dz == r || dy == -r || dy == r);
-                    const int step = face ? 1 : 2 * r;
-                    for (int dx = -r; dx <= r; dx += step) {
-                        const int x = cx + dx;
-                        if (x < 0 || x >= G) continue;
-                        key_visit_cell<KM>(s, shift, x, y, z, qx, qy, qz, qs, perm, cell_start, k);
+        for (int dz = -r; dz <= r; ++dz) {
+            const int z = cz + dz;
+            if (z < 0 || z >= G) continue;
+            const int64_t gz = dz < 0 ? (int64_t)qz - ((int64_t)(z + 1) * cs - 1) : (dz > 0 ? (int64_t)z * cs - qz : 0);
+            for (int dy = -r; dy <= r; ++dy) {
+                const int y = cy + dy;
+                if (y < 0 || y >= G) continue;
+                const int64_t gy = dy < 0 ? (int64_t)qy - ((int64_t)(y + 1) * cs - 1) : (dy > 0 ? (int64_t)y * cs - qy : 0);
+                const bool face = (dz == -r || dz == r || dy == -r || dy == r);
+                const int step = (face || r == 0) ? 1 : 2 * r;
+                for (int dx = -r; dx <= r; dx += step) {
+                    const int x = cx + dx;
+                    if (x < 0 || x >= G) continue;
+                    const int64_t gx = dx < 0 ? (int64_t)qx - ((int64_t)(x + 1) * cs - 1) : (dx > 0 ? (int64_t)x * cs - qx : 0);
+                    if ((uint64_t)(gx * gx + gy * gy + gz * gz) > (k[KM - 1] >> 31)) continue;   // cell too far
+                    const uint32_t cell = morton3((uint32_t)x, (uint32_t)y, (uint32_t)z);
+                    const uint32_t beg = cell_start[cell], end = cell_start[cell + 1];
+                    for (uint32_t t = beg; t < end; ++t) {
+                        if ((int64_t)t == s) continue;
+                        int32_t ax, ay, az;
+                        qunpack(qs[t], ax, ay, az);
+                        const int64_t ex = ax - qx, ey = ay - qy, ez = az - qz;
+                        key_insert<KM>(k, make_key((uint64_t)(ex * ex + ey * ey + ez * ez), (uint32_t)perm[t]));
                     }
                 }
             }

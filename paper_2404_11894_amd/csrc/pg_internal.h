@@ -29,14 +29,32 @@ enum : int32_t {
 
 __host__ __device__ inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Internal edge layout: sliced ELL.  Rows are grouped in slices of 64 (one
-// wave); inside a slice, edge l of all 64 rows is contiguous, so a wave that
-// owns a slice reads edge l of its rows with one 256-byte access.
+// Internal edge layout: sliced ELL with quads.  Rows are grouped in slices
+// of 64 (one wave) and a row's edges in quads of four; the row stride is K
+// rounded up to a multiple of 4 (the padding slots are never read).  Inside a
+// slice, quad q of all 64 rows is contiguous and each row's quad is 16 bytes,
+// so a wave that owns a slice reads four edges of each of its rows with one
+// 16-byte load per lane, 1 KiB contiguous per wave.
 constexpr int kSlice = 64;
-__host__ __device__ inline int64_t eidx(int64_t i, int l, int K) {
-    return ((i >> 6) * K + l) * kSlice + (i & (kSlice - 1));
+constexpr int64_t kQuadStride = 4 * kSlice;   // elements between quads q and q+1 of a row
+__host__ __device__ inline int ell_k4(int K) { return (K + 3) & ~3; }
+__host__ __device__ inline int64_t ell_row(int64_t i, int K) {   // element of edge 0 of row i
+    return (i >> 6) * (int64_t)ell_k4(K) * kSlice + (i & (kSlice - 1)) * 4;
 }
-__host__ __device__ inline int64_t ell_size(int64_t N, int K) { return div_up(N, kSlice) * kSlice * K; }
+__host__ __device__ inline int64_t eidx(int64_t i, int l, int K) {
+    return ell_row(i, K) + (l >> 2) * kQuadStride + (l & 3);
+}
+__host__ __device__ inline int64_t ell_size(int64_t N, int K) { return div_up(N, kSlice) * kSlice * ell_k4(K); }
+
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+// One quad of edge ids / weights, streamed past the caches (read once).
+__device__ inline i32x4 ld_quad_nt(const int32_t* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const i32x4*>(p));
+}
+__device__ inline f32x4 ld_quad_nt(const float* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+}
 
 // XCD-aware block order.  The hardware hands block b to XCD b % 8; remap so
 // every XCD works on one contiguous range of tiles, which keeps the spatially
@@ -208,8 +226,8 @@ hipError_t launch_pack_records(int64_t N, const pg_paths& paths, VRec* rec, int3
 // path-order outputs.
 struct EdgeOut {
     int ell;             // 1: col / w / gw in the sliced-ELL layout, 0: row-major
-    float* w;            // [N*K] local order (required)
-    float* gw;           // [N*K] dw/dg, or NULL
+    float* w;            // local order (required): ell_size(N, K) or N*K elements
+    float* gw;           // dw/dg in the same layout, or NULL
     float* b;            // [N] f3 local
     float* dpt;          // [N] f3 local
     float* r;            // [N] local

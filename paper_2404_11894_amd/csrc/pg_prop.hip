@@ -73,9 +73,10 @@ hipError_t launch_spmv(int64_t N, int K, const int32_t* col, const float* w, con
 }
 
 // One thread per row over the sliced-ELL layout: each wave owns one slice of
-// 64 rows, issues the K column-id and weight loads of all its rows (each a
-// coalesced 256-byte access) and the K gathers before it waits, so a wave has
-// 64*K independent loads in flight.  KT = K at compile time (0: runtime K).
+// 64 rows, issues the column-id and weight loads of all its rows (one 16-byte
+// load per quad of edges, 1 KiB contiguous per wave) and the K gathers before
+// it waits, so a wave has 64*K independent gathers in flight.  KT = K at
+// compile time, a multiple of 4 (0: runtime K).
 // rowmask (nullable): rows with rowmask[i] < 0 output 0.  alpha NULL means 1.
 // SCATTER: the row's result is stored at y[rowmask[i]] (the predecessor) and
 // rows with rowmask[i] < 0 are skipped; otherwise such rows store 0 at y[i].
@@ -89,6 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int Kr, const in
                                                      const float* __restrict__ w, const float* __restrict__ x,
                                                      const float* __restrict__ b, const float* __restrict__ alpha,
                                                      const int32_t* __restrict__ rowmask, float* __restrict__ y) {
+    static_assert(KT % 4 == 0, "compile-time K must fill whole quads");
     const int64_t tile = blockIdx.x;
     const int64_t i = tile * kBlock + threadIdx.x;
     if (i >= N) return;
@@ -102,32 +104,40 @@ __global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int Kr, const in
         if (!SCATTER) dst = i;
     }
     const int K = KT ? KT : Kr;
-    const int64_t base = (i >> 6) * (int64_t)K * kSlice + (i & (kSlice - 1));
+    const int64_t base = ell_row(i, K);
     float ax = 0.f, ay = 0.f, az = 0.f;
     if (KT) {
-        int32_t j[KT > 0 ? KT : 1];
-        float ww[KT > 0 ? KT : 1];
+        constexpr int NQ = KT > 0 ? KT / 4 : 1;
+        i32x4 j[NQ];
+        f32x4 ww[NQ];
 #pragma unroll
-        for (int l = 0; l < KT; ++l) {
-            j[l] = __builtin_nontemporal_load(col + base + (int64_t)l * kSlice);
-            ww[l] = __builtin_nontemporal_load(w + base + (int64_t)l * kSlice);
+        for (int q = 0; q < NQ; ++q) {
+            j[q] = ld_quad_nt(col + base + q * kQuadStride);
+            ww[q] = ld_quad_nt(w + base + q * kQuadStride);
         }
 #pragma unroll
-        for (int l = 0; l < KT; ++l) {
-            const f3 xv = ld3(x, j[l]);
-            ax = fmaf(ww[l], xv.x, ax);
-            ay = fmaf(ww[l], xv.y, ay);
-            az = fmaf(ww[l], xv.z, az);
+        for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const f3 xv = ld3(x, j[q][c]);
+                ax = fmaf(ww[q][c], xv.x, ax);
+                ay = fmaf(ww[q][c], xv.y, ay);
+                az = fmaf(ww[q][c], xv.z, az);
+            }
         }
     } else {
-#pragma unroll 4
-        for (int l = 0; l < K; ++l) {
-            const int64_t jj = col[base + (int64_t)l * kSlice];
-            const float wv = w[base + (int64_t)l * kSlice];
-            const f3 xv = ld3(x, jj);
-            ax = fmaf(wv, xv.x, ax);
-            ay = fmaf(wv, xv.y, ay);
-            az = fmaf(wv, xv.z, az);
+        for (int q = 0; 4 * q < K; ++q) {
+            const i32x4 jq = ld_quad_nt(col + base + q * kQuadStride);
+            const f32x4 wq = ld_quad_nt(w + base + q * kQuadStride);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (4 * q + c < K) {
+                    const f3 xv = ld3(x, jq[c]);
+                    ax = fmaf(wq[c], xv.x, ax);
+                    ay = fmaf(wq[c], xv.y, ay);
+                    az = fmaf(wq[c], xv.z, az);
+                }
+            }
         }
     }
     const f3 bb = ld3(b, i);
