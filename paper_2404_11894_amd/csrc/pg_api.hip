@@ -123,6 +123,7 @@ void carve_grid(Carver& cv, GridBufs& g, int64_t N, int shift) {
     g.ncells = (int64_t)G * G * G;
     g.flag = cv.take<int32_t>(64);
     g.cells = cv.take<uint32_t>(g.ncells + 1);
+    g.range = cv.take<uint2>(g.ncells);
     g.partials = cv.take<uint32_t>(scan_partials_bytes(g.ncells) / 4);
     g.cellid = cv.take<uint32_t>(N);
     g.rank = cv.take<uint32_t>(N);
@@ -141,6 +142,7 @@ hipError_t run_grid(const pg_paths* p, GridBufs& g, VRec* rec, hipStream_t s) {
     if ((e = launch_fill(g.cells, (size_t)(g.ncells + 1) * 4, s)) != hipSuccess) return e;
     if ((e = launch_quantize_count(N, p->pos, g.shift, g.cells, g.cellid, g.rank, g.flag, s)) != hipSuccess) return e;
     if ((e = launch_scan_exclusive(g.cells, g.cells, g.ncells, g.partials, s)) != hipSuccess) return e;
+    if ((e = launch_cell_range(g.ncells, g.shift, g.cells, g.range, s)) != hipSuccess) return e;
     return launch_scatter(N, *p, g.shift, g.cellid, g.rank, g.cells, g.perm, g.inv, g.qs, rec, s);
 }
 
@@ -200,7 +202,7 @@ pg_status pg_knn(const pg_paths* paths, int32_t k, int32_t cell_shift, int64_t* 
         return finish(s, nullptr, nullptr, 0);
     }
     if ((e = run_grid(paths, g, nullptr, s)) != hipSuccess) return hip_fail(e, "grid build");
-    if ((e = launch_knn(N, K, shift, g.qs, g.perm, g.inv, g.cells, nullptr, col, row_ptr, g.redo, g.nredo, s)) !=
+    if ((e = launch_knn(N, K, shift, g.qs, g.perm, g.inv, g.range, nullptr, col, row_ptr, g.redo, g.nredo, s)) !=
         hipSuccess)
         return hip_fail(e, "knn");
     return finish(s, nullptr, g.flag, 0);

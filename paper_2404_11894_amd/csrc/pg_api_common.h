@@ -48,7 +48,8 @@ struct GridBufs {
     int shift = 0;
     int64_t ncells = 0;
     int32_t* flag = nullptr;
-    uint32_t* cells = nullptr;     // counts, then cell_start (ncells + 1)
+    uint32_t* cells = nullptr;     // counts, then start by Hilbert position (ncells + 1)
+    uint2* range = nullptr;        // [start, end) of each cell by Morton number (ncells)
     uint32_t* partials = nullptr;
     uint32_t* cellid = nullptr;
     uint32_t* rank = nullptr;

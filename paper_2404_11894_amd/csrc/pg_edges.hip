@@ -128,7 +128,10 @@ hipError_t launch_edges(int64_t N, const Consts& c, const int32_t* col, const VR
 // succ(v) / pred(v) (-1 at the ends) and the initial incoming indirect
 // radiance: 0 at the last vertex, else albedo_u (d_pt_u + r_u L(u)) with u the
 // successor -- the path tracer's own estimate (init PT) -- or 0 (init zero).
+// The path is taken in chunks of kPathChunk vertices whose scattered loads
+// are all issued before the recurrence consumes them.
 // succ, pred and x0 must be pre-filled with -1, -1, 0.
+constexpr int kPathChunk = 8;
 __global__ __launch_bounds__(kBlock) void k_paths(int64_t P, int64_t N, const int64_t* __restrict__ off,
                                                   const int32_t* __restrict__ inv, const float* __restrict__ alpha,
                                                   const float* __restrict__ dpt, const float* __restrict__ r,
@@ -142,19 +145,44 @@ __global__ __launch_bounds__(kBlock) void k_paths(int64_t P, int64_t N, const in
         set_flag(flag, kFlagOffsets);
         return;
     }
+    const bool pt = init == PG_INIT_PT && x0;
     f3 L{0.f, 0.f, 0.f};
-    int64_t next = -1;   // local id of the successor
-    for (int64_t v = e - 1; v >= a; --v) {
-        const int64_t s = inv ? (int64_t)inv[v] : v;
-        if (succ) succ[s] = (int32_t)next;
-        if (pred) pred[s] = v > a ? (inv ? inv[v - 1] : (int32_t)(v - 1)) : -1;
-        if (x0 && init == PG_INIT_PT) st3(x0, s, L);
-        if (init == PG_INIT_PT && x0) {
-            const float al = alpha[s], rr = r[s];
-            const f3 d = ld3(dpt, s);
-            L = f3{al * fmaf(rr, L.x, d.x), al * fmaf(rr, L.y, d.y), al * fmaf(rr, L.z, d.z)};
+    int32_t next = -1;   // local id of the successor
+    for (int64_t v = e - 1; v >= a; v -= kPathChunk) {
+        // chunk: vertices v, v-1, ..., v-n+1 (n <= kPathChunk)
+        const int n = v - a + 1 < kPathChunk ? (int)(v - a + 1) : kPathChunk;
+        int32_t sv[kPathChunk + 1];
+        float al[kPathChunk], rr[kPathChunk];
+        f3 d[kPathChunk];
+#pragma unroll
+        for (int c = 0; c <= kPathChunk; ++c) {
+            const int64_t u = v - c;   // c == n: the predecessor of the chunk's first vertex
+            sv[c] = (c <= n && u >= a) ? (inv ? inv[u] : (int32_t)u) : -1;
         }
-        next = s;
+        if (pt) {
+#pragma unroll
+            for (int c = 0; c < kPathChunk; ++c) {
+                if (c < n) {
+                    al[c] = alpha[sv[c]];
+                    rr[c] = r[sv[c]];
+                    d[c] = ld3(dpt, sv[c]);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kPathChunk; ++c) {
+            if (c < n) {
+                const int64_t s = sv[c];
+                if (succ) succ[s] = next;
+                if (pred) pred[s] = sv[c + 1];
+                if (pt) {
+                    st3(x0, s, L);
+                    L = f3{al[c] * fmaf(rr[c], L.x, d[c].x), al[c] * fmaf(rr[c], L.y, d[c].y),
+                           al[c] * fmaf(rr[c], L.z, d[c].z)};
+                }
+                next = (int32_t)s;
+            }
+        }
     }
 }
 

@@ -6,12 +6,16 @@
 // neighbourhood of vertex i is exact: i first, then the K-1 nearest others by
 // (squared distance of the 20-bit quantised positions, path-order id).
 //
-// Grid: cell = q >> shift per axis, G = 2^(20-shift) cells per axis, cells
-// numbered in Morton order so that a sort by cell keeps space-filling-curve
-// locality.  Counting sort = atomic histogram (which also yields each
-// vertex's rank inside its cell) + exclusive scan + scatter.  The order of
-// vertices inside a cell is not deterministic; nothing downstream depends on
-// it (every comparison breaks ties by path-order id).
+// Grid: cell = q >> shift per axis, G = 2^(20-shift) cells per axis.  The
+// vertices are sorted by the position of their cell along the Hilbert curve,
+// so neighbouring cells are close in memory (the gathers of the kNN, the
+// edge weights and every propagation step stay in a small window); a table
+// indexed by the cell's Morton number gives each cell's [start, end) in that
+// order without re-encoding during the search.  Counting sort = atomic
+// histogram (which also yields each vertex's rank inside its cell) +
+// exclusive scan + scatter.  The order of vertices inside a cell is not
+// deterministic; nothing downstream depends on it (every comparison breaks
+// ties by path-order id).
 #include "pg_internal.h"
 
 namespace pg {
@@ -31,7 +35,7 @@ __global__ __launch_bounds__(kBlock) void k_quantize_count(int64_t N, const floa
     if (i >= N) return;
     float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
     if (!(x >= 0.0f && x <= 1.0f && y >= 0.0f && y <= 1.0f && z >= 0.0f && z <= 1.0f)) set_flag(flag, kFlagPos);
-    uint32_t c = morton3(quant(x) >> shift, quant(y) >> shift, quant(z) >> shift);
+    uint32_t c = hilbert3(quant(x) >> shift, quant(y) >> shift, quant(z) >> shift, kQBits - shift);
     cellid[i] = c;
     rank[i] = atomicAdd(&count[c], 1u);
 }
@@ -41,6 +45,23 @@ hipError_t launch_quantize_count(int64_t N, const float* pos, int shift, uint32_
     if (N == 0) return hipSuccess;
     hipLaunchKernelGGL(k_quantize_count, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, pos, shift,
                        count, cellid, rank, flag);
+    return hipGetLastError();
+}
+
+// range[m] = [start, end) of the cell with Morton number m, from the
+// exclusive scan `start` of the counts in Hilbert order.
+__global__ __launch_bounds__(kBlock) void k_cell_range(int64_t ncells, int shift, const uint32_t* __restrict__ start,
+                                                       uint2* __restrict__ range) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= ncells) return;
+    const uint32_t u = (uint32_t)m;
+    const uint32_t h = hilbert3(compact1by2(u), compact1by2(u >> 1), compact1by2(u >> 2), kQBits - shift);
+    range[m] = make_uint2(start[h], start[h + 1]);
+}
+
+hipError_t launch_cell_range(int64_t ncells, int shift, const uint32_t* start, uint2* range, hipStream_t s) {
+    hipLaunchKernelGGL(k_cell_range, dim3((unsigned)div_up(ncells, kBlock)), dim3(kBlock), 0, s, ncells, shift,
+                       start, range);
     return hipGetLastError();
 }
 
@@ -300,7 +321,7 @@ __device__ __forceinline__ void list_reset(uint64_t (&d)[KM], uint32_t (&o)[KM],
 template <int KM>
 __device__ __forceinline__ void shell_search(int64_t s, int m, int shift, int32_t qx, int32_t qy, int32_t qz,
                                              const uint64_t* __restrict__ qs, const int32_t* __restrict__ perm,
-                                             const uint32_t* __restrict__ cell_start, uint64_t (&d)[KM],
+                                             const uint2* __restrict__ cell_range, uint64_t (&d)[KM],
                                              uint32_t (&o)[KM]) {
     (void)m;
     const int G = 1 << (kQBits - shift);
@@ -323,7 +344,8 @@ __device__ __forceinline__ void shell_search(int64_t s, int m, int shift, int32_
                     const int64_t gx = dx < 0 ? (int64_t)qx - ((int64_t)(x + 1) * cs - 1) : (dx > 0 ? (int64_t)x * cs - qx : 0);
                     if ((uint64_t)(gx * gx + gy * gy + gz * gz) > d[KM - 1]) continue;   // whole cell too far
                     const uint32_t cell = morton3((uint32_t)x, (uint32_t)y, (uint32_t)z);
-                    const uint32_t beg = cell_start[cell], end = cell_start[cell + 1];
+                    const uint2 cr = cell_range[cell];
+                    const uint32_t beg = cr.x, end = cr.y;
                     uint32_t t = beg;
                     for (; t + 1 < end; t += 2) {
                         const uint64_t p0 = qs[t], p1 = qs[t + 1];
@@ -413,7 +435,7 @@ __device__ __forceinline__ void key_insert(uint64_t (&k)[KM], uint64_t c) {
 template <int KM>
 __device__ __forceinline__ void key_shell_search(int64_t s, int shift, int32_t qx, int32_t qy, int32_t qz,
                                                  const uint64_t* __restrict__ qs, const int32_t* __restrict__ perm,
-                                                 const uint32_t* __restrict__ cell_start, uint64_t (&k)[KM]) {
+                                                 const uint2* __restrict__ cell_range, uint64_t (&k)[KM]) {
     const int G = 1 << (kQBits - shift);
     const int cx = qx >> shift, cy = qy >> shift, cz = qz >> shift;
     const int64_t cs = (int64_t)1 << shift;
@@ -434,7 +456,8 @@ __device__ __forceinline__ void key_shell_search(int64_t s, int shift, int32_t q
                     const int64_t gx = dx < 0 ? (int64_t)qx - ((int64_t)(x + 1) * cs - 1) : (dx > 0 ? (int64_t)x * cs - qx : 0);
                     if ((uint64_t)(gx * gx + gy * gy + gz * gz) > (k[KM - 1] >> 31)) continue;   // cell too far
                     const uint32_t cell = morton3((uint32_t)x, (uint32_t)y, (uint32_t)z);
-                    const uint32_t beg = cell_start[cell], end = cell_start[cell + 1];
+                    const uint2 cr = cell_range[cell];
+                    const uint32_t beg = cr.x, end = cr.y;
                     for (uint32_t t = beg; t < end; ++t) {
                         if ((int64_t)t == s) continue;
                         int32_t ax, ay, az;
@@ -458,10 +481,14 @@ __device__ __forceinline__ void key_shell_search(int64_t s, int shift, int32_t q
     }
 }
 
-template <int KM>
-__global__ __launch_bounds__(kBlock) void k_knn(int64_t N, int K, int shift, const uint64_t* __restrict__ qs,
+// WPE: the minimum waves per SIMD the compiler must fit the search in.  For
+// the short key lists (k = 8, 16) a bound of 6 or 8 fits it in 64-70
+// registers without spilling, 7-8 resident waves instead of 4, which hides
+// more of the candidate loads' latency; longer lists take no bound (1).
+template <int KM, int WPE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_knn(int64_t N, int K, int shift, const uint64_t* __restrict__ qs,
                                                 const int32_t* __restrict__ perm, const int32_t* __restrict__ inv,
-                                                const uint32_t* __restrict__ cell_start,
+                                                const uint2* __restrict__ cell_range,
                                                 int32_t* __restrict__ col_sorted, int32_t* __restrict__ col_canon,
                                                 int64_t* __restrict__ row_ptr, uint32_t* __restrict__ redo,
                                                 uint32_t* __restrict__ nredo) {
@@ -476,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_knn(int64_t N, int K, int shift, con
 #pragma unroll
     for (int p = 0; p < KM; ++p) k[p] = p < KM - m ? 0ull : ~0ull;
     if (m > 0) {
-        key_shell_search<KM>(s, shift, qx, qy, qz, qs, perm, cell_start, k);
+        key_shell_search<KM>(s, shift, qx, qy, qz, qs, perm, cell_range, k);
         if ((k[KM - 1] >> 31) >= kD2Sat) {   // a kept distance saturated: redo exactly
             redo[atomicAdd(nredo, 1u)] = (uint32_t)s;
             return;
@@ -506,7 +533,7 @@ template <int KM>
 __global__ __launch_bounds__(kBlock) void k_knn_exact(int64_t N, int K, int shift, const uint64_t* __restrict__ qs,
                                                       const int32_t* __restrict__ perm,
                                                       const int32_t* __restrict__ inv,
-                                                      const uint32_t* __restrict__ cell_start,
+                                                      const uint2* __restrict__ cell_range,
                                                       int32_t* __restrict__ col_sorted,
                                                       int32_t* __restrict__ col_canon,
                                                       int64_t* __restrict__ row_ptr,
@@ -522,13 +549,13 @@ __global__ __launch_bounds__(kBlock) void k_knn_exact(int64_t N, int K, int shif
         uint64_t d[KM];
         uint32_t o[KM];
         list_reset<KM>(d, o, m);
-        shell_search<KM>(s, m, shift, qx, qy, qz, qs, perm, cell_start, d, o);
+        shell_search<KM>(s, m, shift, qx, qy, qz, qs, perm, cell_range, d, o);
         knn_write<KM>(s, K, m, self, N, inv, d, o, col_sorted, col_canon, row_ptr);
     }
 }
 
 hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, const int32_t* perm,
-                      const int32_t* inv, const uint32_t* cell_start, int32_t* col_sorted, int32_t* col_canon,
+                      const int32_t* inv, const uint2* cell_range, int32_t* col_sorted, int32_t* col_canon,
                       int64_t* row_ptr, uint32_t* redo, uint32_t* nredo, hipStream_t s) {
     if (N == 0) return hipSuccess;
     const int m = K - 1;
@@ -536,13 +563,16 @@ hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, cons
     if (e != hipSuccess) return e;
     auto go = [&](auto km) {
         constexpr int KM = decltype(km)::value;
-        hipLaunchKernelGGL(k_knn<KM>, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, K, shift, qsorted,
-                           perm, inv, cell_start, col_sorted, col_canon, row_ptr, redo, nredo);
+        constexpr int WPE = KM == 15 ? 8 : (KM <= 16 ? 6 : 1);
+        hipLaunchKernelGGL((k_knn<KM, WPE>), dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, K, shift, qsorted,
+                           perm, inv, cell_range, col_sorted, col_canon, row_ptr, redo, nredo);
         hipLaunchKernelGGL(k_knn_exact<KM>, dim3(256), dim3(kBlock), 0, s, N, K, shift, qsorted, perm, inv,
-                           cell_start, col_sorted, col_canon, row_ptr, (const uint32_t*)redo,
+                           cell_range, col_sorted, col_canon, row_ptr, (const uint32_t*)redo,
                            (const uint32_t*)nredo);
     };
-    if (m <= 8) go(std::integral_constant<int, 8>{});
+    if (m == 7) go(std::integral_constant<int, 7>{});          // k = 8 and 16: no sentinel slot
+    else if (m <= 8) go(std::integral_constant<int, 8>{});
+    else if (m == 15) go(std::integral_constant<int, 15>{});
     else if (m <= 16) go(std::integral_constant<int, 16>{});
     else if (m <= 32) go(std::integral_constant<int, 32>{});
     else go(std::integral_constant<int, 64>{});

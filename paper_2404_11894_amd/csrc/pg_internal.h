@@ -77,6 +77,45 @@ __host__ __device__ inline uint32_t part1by2(uint32_t v) {
 __host__ __device__ inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
     return part1by2(x) | (part1by2(y) << 1) | (part1by2(z) << 2);
 }
+// Inverse of part1by2: gather every third bit into the low 10 bits.
+__host__ __device__ inline uint32_t compact1by2(uint32_t v) {
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030c30c3u;
+    v = (v | (v >> 4)) & 0x0300f00fu;
+    v = (v | (v >> 8)) & 0x030000ffu;
+    v = (v | (v >> 16)) & 0x000003ffu;
+    return v;
+}
+
+// Position of cell (x, y, z) along the 3-D Hilbert curve over a 2^b grid
+// (b <= 10), after Skilling's transpose form of the curve (J. Skilling,
+// "Programming the Hilbert curve", 2004): undo the excess work of the
+// recursive rotations, Gray-encode, then interleave the bits with x most
+// significant.  Consecutive positions are face-adjacent cells, unlike the
+// Morton order, whose steps jump at every octant boundary.
+__host__ __device__ inline uint32_t hilbert3(uint32_t x, uint32_t y, uint32_t z, int b) {
+    if (b <= 0) return 0;
+    uint32_t X[3] = {x, y, z};
+    const uint32_t M = 1u << (b - 1);
+    for (uint32_t Q = M; Q > 1; Q >>= 1) {
+        const uint32_t P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                const uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t t = 0;
+    for (uint32_t Q = M; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    return morton3(X[2] ^ t, X[1] ^ t, X[0] ^ t);
+}
 
 // Quantised coordinates packed 21 bits apart.
 __device__ inline uint64_t qpack(uint32_t x, uint32_t y, uint32_t z) {
@@ -214,8 +253,9 @@ hipError_t launch_scatter(int64_t N, const pg_paths& paths, int shift, const uin
                           uint64_t* qsorted, VRec* rec, hipStream_t s);
 // redo: [N] scratch list, nredo: one counter (queries the fast 64-bit-key
 // search hands to the exact one)
+hipError_t launch_cell_range(int64_t ncells, int shift, const uint32_t* start, uint2* range, hipStream_t s);
 hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, const int32_t* perm,
-                      const int32_t* inv, const uint32_t* cell_start, int32_t* col_sorted, int32_t* col_canon,
+                      const int32_t* inv, const uint2* cell_range, int32_t* col_sorted, int32_t* col_canon,
                       int64_t* row_ptr, uint32_t* redo, uint32_t* nredo, hipStream_t s);
 
 // records in path order (no permutation)

@@ -56,7 +56,7 @@ hipError_t render_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, co
         if (out && out->row_ptr) PG_TRY(launch_fill(out->row_ptr, sizeof(int64_t), s));
     } else {
         ProfScope ps(s, "knn");
-        PG_TRY(launch_knn(N, K, g.shift, g.qs, g.perm, g.inv, g.cells, r.col, out ? out->col : nullptr,
+        PG_TRY(launch_knn(N, K, g.shift, g.qs, g.perm, g.inv, g.range, r.col, out ? out->col : nullptr,
                           out ? out->row_ptr : nullptr, g.redo, g.nredo, s));
     }
     const Consts c = make_consts(q, K);
