@@ -101,7 +101,8 @@ struct BackBufs {
     uint32_t cap = 0;
     int64_t nslices = 0;
     uint32_t* tdeg = nullptr;  // in-degree [N+1]
-    uint32_t* tcur = nullptr;  // slice lengths, then cursors [N+1]
+    uint32_t* tlen = nullptr;  // slice lengths [nslices+1]
+    uint8_t* trank = nullptr;  // arrival rank of each edge at its T-row [ell_size(N, K)]
     uint32_t* soff = nullptr;  // slice offsets [nslices+1]
     uint32_t* tpart = nullptr; // scan partials
     int32_t* tsrc = nullptr;   // [nslices*64*cap] source rows
@@ -110,6 +111,7 @@ struct BackBufs {
     float* ovw = nullptr;      // overflow weights [E]
     uint32_t* novf = nullptr;
     double* gpart = nullptr;   // [n_slots]
+    double* gchunk = nullptr;   // per-chunk totals of gpart
     float* image = nullptr;    // forward image when the tape is recomputed
 };
 void carve_back(Carver& cv, BackBufs& bb, const RenderBufs& r, const pg_paths* p);

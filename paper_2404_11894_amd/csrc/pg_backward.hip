@@ -38,10 +38,20 @@ __device__ inline float dot3(f3 a, f3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, 
 // cap go to an overflow list of (j, i, w) applied with atomics (none for
 // ordinary neighbour graphs; degenerate inputs such as many coincident points
 // can have a few).  t runs over the N*K edges in row order.
+//
+// Built in four passes: in-degrees with atomics, which also give every edge
+// its arrival rank at its T-row (one byte); slice lengths and their scan;
+// every edge stored at its rank (no atomics); each T-row sorted by source row
+// in registers, so the reverse sums run in a fixed order.
+
+// in-degree, and each edge's arrival rank at its T-row (255 = past any cap)
 __global__ __launch_bounds__(kBlock) void k_tcount(int64_t E, int K, const int32_t* __restrict__ col,
-                                                   uint32_t* __restrict__ cnt) {
+                                                   uint32_t* __restrict__ cnt, uint8_t* __restrict__ rank) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < E) atomicAdd(&cnt[col[eidx(t / K, (int)(t % K), K)]], 1u);
+    if (t >= E) return;
+    const int64_t e = eidx(t / K, (int)(t % K), K);
+    const uint32_t q = atomicAdd(&cnt[col[e]], 1u);
+    rank[e] = (uint8_t)(q < 255u ? q : 255u);
 }
 
 // slice length = 64 * min(max in-degree of its 64 T-rows, cap); one wave per slice
@@ -56,8 +66,8 @@ __global__ __launch_bounds__(kBlock) void k_tslice_len(int64_t N, int64_t nslice
 }
 
 __global__ __launch_bounds__(kBlock) void k_tscatter(int64_t E, int K, uint32_t cap, const int32_t* __restrict__ col,
-                                                     const float* __restrict__ w, const uint32_t* __restrict__ soff,
-                                                     uint32_t* __restrict__ cur, int32_t* __restrict__ tsrc,
+                                                     const float* __restrict__ w, const uint8_t* __restrict__ rank,
+                                                     const uint32_t* __restrict__ soff, int32_t* __restrict__ tsrc,
                                                      float* __restrict__ tw, int32_t* __restrict__ ovf,
                                                      float* __restrict__ ovw, uint32_t* __restrict__ novf) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -65,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_tscatter(int64_t E, int K, uint32_t 
     const int64_t i = t / K;
     const int64_t e = eidx(i, (int)(t - i * K), K);
     const int64_t j = col[e];
-    const uint32_t q = atomicAdd(&cur[j], 1u);
+    const uint32_t q = rank[e];
     if (q < cap) {
         const int64_t p = (int64_t)soff[j >> 6] + (int64_t)q * kSlice + (j & (kSlice - 1));
         tsrc[p] = (int32_t)i;
@@ -78,8 +88,11 @@ __global__ __launch_bounds__(kBlock) void k_tscatter(int64_t E, int K, uint32_t 
     }
 }
 
-// each T-row sorted by source row (a fixed summation order), then padded with
-// zero-weight self entries up to its slice's length
+// Each T-row sorted by source row (a fixed summation order), then padded with
+// zero-weight self entries up to its slice's length.  C >= cap: a bitonic
+// network over C register slots (unused slots hold INT_MAX); C = 0: insertion
+// sort in place, for long rows.
+template <int C>
 __global__ __launch_bounds__(kBlock) void k_tsort(int64_t N, uint32_t cap, const uint32_t* __restrict__ soff,
                                                   const uint32_t* __restrict__ deg, int32_t* __restrict__ tsrc,
                                                   float* __restrict__ tw) {
@@ -88,17 +101,55 @@ __global__ __launch_bounds__(kBlock) void k_tsort(int64_t N, uint32_t cap, const
     const int64_t base = (int64_t)soff[j >> 6] + (j & (kSlice - 1));
     const uint32_t len = (soff[(j >> 6) + 1] - soff[j >> 6]) / kSlice;
     const uint32_t n = min(deg[j], cap);
+    if (C > 0) {
+        constexpr int CC = C > 0 ? C : 1;
+        int32_t k[CC];
+        float v[CC];
+#pragma unroll
+        for (int q = 0; q < CC; ++q) {
+            k[q] = (uint32_t)q < n ? tsrc[base + (int64_t)q * kSlice] : INT32_MAX;
+            v[q] = (uint32_t)q < n ? tw[base + (int64_t)q * kSlice] : 0.0f;
+        }
+#pragma unroll
+        for (int size = 2; size <= CC; size <<= 1) {
+#pragma unroll
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+                for (int a = 0; a < CC; ++a) {
+                    const int b2 = a ^ stride;
+                    if (b2 > a) {
+                        const bool up = (a & size) == 0;
+                        const bool sw = up ? k[a] > k[b2] : k[a] < k[b2];
+                        const int32_t tk = k[a];
+                        const float tv = v[a];
+                        k[a] = sw ? k[b2] : k[a];
+                        v[a] = sw ? v[b2] : v[a];
+                        k[b2] = sw ? tk : k[b2];
+                        v[b2] = sw ? tv : v[b2];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < CC; ++q) {
+            if ((uint32_t)q < len) {
+                tsrc[base + (int64_t)q * kSlice] = (uint32_t)q < n ? k[q] : (int32_t)j;
+                tw[base + (int64_t)q * kSlice] = (uint32_t)q < n ? v[q] : 0.0f;
+            }
+        }
+        return;
+    }
     for (uint32_t q = 1; q < n; ++q) {
         const int32_t sv = tsrc[base + (int64_t)q * kSlice];
         const float wv = tw[base + (int64_t)q * kSlice];
-        uint32_t p = q;
-        while (p > 0 && tsrc[base + (int64_t)(p - 1) * kSlice] > sv) {
-            tsrc[base + (int64_t)p * kSlice] = tsrc[base + (int64_t)(p - 1) * kSlice];
-            tw[base + (int64_t)p * kSlice] = tw[base + (int64_t)(p - 1) * kSlice];
-            --p;
+        uint32_t r = q;
+        while (r > 0 && tsrc[base + (int64_t)(r - 1) * kSlice] > sv) {
+            tsrc[base + (int64_t)r * kSlice] = tsrc[base + (int64_t)(r - 1) * kSlice];
+            tw[base + (int64_t)r * kSlice] = tw[base + (int64_t)(r - 1) * kSlice];
+            --r;
         }
-        tsrc[base + (int64_t)p * kSlice] = sv;
-        tw[base + (int64_t)p * kSlice] = wv;
+        tsrc[base + (int64_t)r * kSlice] = sv;
+        tw[base + (int64_t)r * kSlice] = wv;
     }
     for (uint32_t q = n; q < len; ++q) {
         tsrc[base + (int64_t)q * kSlice] = (int32_t)j;
@@ -236,7 +287,8 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const in
 
 // lam_{t-1}(j) = sum over rows i with j in N(i) of w_ij zbar_i: one thread per
 // T-row over the sliced-ELL transpose (every lane of a wave runs its slice's
-// length), four entries loaded ahead.
+// length, the zero-weight padding included: a per-lane bound measured slower),
+// four entries loaded ahead.
 __global__ __launch_bounds__(kBlock) void k_rev_cols(int64_t N, const uint32_t* __restrict__ soff,
                                                      const int32_t* __restrict__ tsrc, const float* __restrict__ tw,
                                                      const float* __restrict__ zbar, float* __restrict__ lam) {
@@ -455,12 +507,21 @@ __global__ __launch_bounds__(kBlock) void k_grid_adjoint(int64_t N, pg_paths P, 
             if (hkey[h] != kEmpty) atomicAdd(&grad_grid[hkey[h]], hval[h]);
 }
 
+// dL/dg = the sum of the fixed slots, in two fixed-order levels: each block
+// sums one chunk of kReduceChunk slots, then one block sums the chunk totals
+// (out_f == NULL: write the block totals to out_d instead).
+constexpr int kReduceChunk = 4096;
 __global__ __launch_bounds__(kBlock) void k_reduce_g(int64_t n, const double* __restrict__ gpart,
-                                                     float* __restrict__ out) {
+                                                     double* __restrict__ out_d, float* __restrict__ out_f) {
+    const int64_t lo = out_f ? 0 : (int64_t)blockIdx.x * kReduceChunk;
+    const int64_t hi = out_f ? n : (lo + kReduceChunk < n ? lo + kReduceChunk : n);
     double v = 0.0;
-    for (int64_t q = threadIdx.x; q < n; q += blockDim.x) v += gpart[q];
+    for (int64_t q = lo + threadIdx.x; q < hi; q += blockDim.x) v += gpart[q];
     const double t = block_sum_d(v);
-    if (threadIdx.x == 0) out[0] = (float)t;
+    if (threadIdx.x == 0) {
+        if (out_f) out_f[0] = (float)t;
+        else out_d[blockIdx.x] = t;
+    }
 }
 
 // ----------------------------------------------------------------- host ---
@@ -483,7 +544,8 @@ void carve_back(Carver& cv, BackBufs& bb, const RenderBufs& r, const pg_paths* p
     bb.cap = (uint32_t)(2 * (r.K > 0 ? r.K : 1));
     bb.nslices = div_up(N > 0 ? N : 1, kSlice);
     bb.tdeg = cv.take<uint32_t>(N + 1);
-    bb.tcur = cv.take<uint32_t>(N + 1);
+    bb.tlen = cv.take<uint32_t>(bb.nslices + 1);
+    bb.trank = cv.take<uint8_t>(ell_size(N, r.K));
     bb.soff = cv.take<uint32_t>(bb.nslices + 1);
     bb.tpart = cv.take<uint32_t>(scan_partials_bytes(bb.nslices + 1) / 4);
     bb.tsrc = cv.take<int32_t>(bb.nslices * kSlice * (int64_t)bb.cap);
@@ -492,6 +554,7 @@ void carve_back(Carver& cv, BackBufs& bb, const RenderBufs& r, const pg_paths* p
     bb.ovw = cv.take<float>(E);
     bb.novf = cv.take<uint32_t>(64);
     bb.gpart = cv.take<double>(bb.n_slots);
+    bb.gchunk = cv.take<double>(div_up(bb.n_slots, kReduceChunk));
     bb.image = cv.take<float>((int64_t)p->width * p->height * 3);
 }
 
@@ -520,17 +583,24 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
         // sliced-ELL transpose of W (sorted ids)
         ProfScope ps(s, "transpose");
         PG_TRY(launch_fill(bb.tdeg, (size_t)(N + 1) * 4, s));
-        PG_TRY(launch_fill(bb.tcur, (size_t)(N + 1) * 4, s));
+        PG_TRY(launch_fill(bb.tlen, (size_t)(bb.nslices + 1) * 4, s));
         PG_TRY(launch_fill(bb.novf, 4, s));
-        hipLaunchKernelGGL(k_tcount, dim3((unsigned)div_up(E, kBlock)), dim3(kBlock), 0, s, E, K, r.col, bb.tdeg);
+        hipLaunchKernelGGL(k_tcount, dim3((unsigned)div_up(E, kBlock)), dim3(kBlock), 0, s, E, K, r.col, bb.tdeg,
+                           bb.trank);
         hipLaunchKernelGGL(k_tslice_len, dim3((unsigned)div_up(bb.nslices * kSlice, kBlock)), dim3(kBlock), 0, s,
-                           N, bb.nslices, bb.cap, bb.tdeg, bb.tcur);
-        PG_TRY(launch_scan_exclusive(bb.tcur, bb.soff, bb.nslices, bb.tpart, s));
-        PG_TRY(launch_fill(bb.tcur, (size_t)(N + 1) * 4, s));
+                           N, bb.nslices, bb.cap, bb.tdeg, bb.tlen);
+        PG_TRY(launch_scan_exclusive(bb.tlen, bb.soff, bb.nslices, bb.tpart, s));
         hipLaunchKernelGGL(k_tscatter, dim3((unsigned)div_up(E, kBlock)), dim3(kBlock), 0, s, E, K, bb.cap, r.col,
-                           r.w, bb.soff, bb.tcur, bb.tsrc, bb.tw, bb.ovf, bb.ovw, bb.novf);
-        hipLaunchKernelGGL(k_tsort, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.cap, bb.soff,
-                           bb.tdeg, bb.tsrc, bb.tw);
+                           r.w, bb.trank, bb.soff, bb.tsrc, bb.tw, bb.ovf, bb.ovw, bb.novf);
+        auto sort = [&](auto c) {
+            constexpr int C = decltype(c)::value;
+            hipLaunchKernelGGL(k_tsort<C>, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.cap,
+                               (const uint32_t*)bb.soff, (const uint32_t*)bb.tdeg, bb.tsrc, bb.tw);
+        };
+        if (bb.cap <= 8) sort(std::integral_constant<int, 8>{});
+        else if (bb.cap <= 16) sort(std::integral_constant<int, 16>{});
+        else if (bb.cap <= 32) sort(std::integral_constant<int, 32>{});
+        else sort(std::integral_constant<int, 0>{});
         PG_TRY(hipGetLastError());
     }
     const float* xD = r.traj + (size_t)D * N * 3;
@@ -593,7 +663,11 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
         PG_TRY(hipGetLastError());
     }
     if (grad_g) {
-        hipLaunchKernelGGL(k_reduce_g, dim3(1), dim3(kBlock), 0, s, bb.n_slots, bb.gpart, grad_g);
+        const int64_t nchunk = div_up(bb.n_slots, kReduceChunk);
+        hipLaunchKernelGGL(k_reduce_g, dim3((unsigned)nchunk), dim3(kBlock), 0, s, bb.n_slots, bb.gpart, bb.gchunk,
+                           (float*)nullptr);
+        hipLaunchKernelGGL(k_reduce_g, dim3(1), dim3(kBlock), 0, s, nchunk, (const double*)bb.gchunk,
+                           (double*)nullptr, grad_g);
         PG_TRY(hipGetLastError());
     }
     return hipSuccess;
