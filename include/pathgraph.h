@@ -229,7 +229,7 @@ pg_status pg_backward(const pg_paths* paths, const pg_params* params, const floa
  * Renders n_scenes independent scenes (each with its own paths and params;
  * k, D, g, cell size may differ) into images[s] ([height_s][width_s][3]).
  * The one-time steps run per scene; every one of the D iterations is one
- * launch for all scenes of a neighbour-count class plus one shift launch.
+ * aggregation launch and one shift launch for all scenes still iterating.
  * The result equals n_scenes pg_render calls (two-pass schedule).  The call
  * synchronises the stream once, after copying its small scene table. */
 pg_status pg_render_batched_workspace_size(int32_t n_scenes, const pg_paths* paths, const pg_params* params,

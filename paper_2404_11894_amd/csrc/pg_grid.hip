@@ -270,7 +270,7 @@ hipError_t launch_pack_records(int64_t N, const pg_paths& paths, VRec* rec, int3
 }
 
 // ------------------------------------------------------------------- kNN ---
-// One query per thread, queries in cell (Morton) order so that the lanes of a
+// One query per thread, queries in cell (Hilbert) order so that the lanes of a
 // wave visit the same cells.  The K-1 best candidates live in registers,
 // sorted ascending by (d2, id) and right-aligned in an array of KM slots; the
 // KM-(K-1) leading slots hold (0, 0), which no candidate can move past, so the
