@@ -57,6 +57,9 @@ typedef int32_t pg_status;
 #define PG_FLAG_CHECK 1u  /* synchronise and report device-detected input errors */
 #define PG_FLAG_TAPE  2u  /* pg_render keeps the graph and every iterate in the workspace
                              for a following pg_backward on the same workspace */
+#define PG_FLAG_EXACT_KNN 4u  /* every neighbour query takes the exact (d^2, id) search instead
+                                 of the packed-key fast path: the same neighbours, slower; for
+                                 validating the fallback the fast path hands rare queries to */
 
 #define PG_SCHED_TWO_PASS 1  /* aggregate over spatially sorted rows, then shift along paths */
 #define PG_SCHED_SHIFTED  2  /* rows pre-arranged in predecessor order: one pass per iteration */

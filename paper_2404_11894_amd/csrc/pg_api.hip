@@ -70,7 +70,7 @@ pg_status validate_params(const pg_params* q) {
     if (q->cell_shift != 0 && (q->cell_shift < kMinShift || q->cell_shift > kQBits))
         return fail(PG_ERR_ARG, "cell_shift must be 0 or in [%d, %d]", kMinShift, kQBits);
     if (q->schedule < 0 || q->schedule > PG_SCHED_SCATTER) return fail(PG_ERR_ARG, "unknown schedule");
-    if (q->flags & ~(PG_FLAG_CHECK | PG_FLAG_TAPE)) return fail(PG_ERR_ARG, "unknown flag bits");
+    if (q->flags & ~(PG_FLAG_CHECK | PG_FLAG_TAPE | PG_FLAG_EXACT_KNN)) return fail(PG_ERR_ARG, "unknown flag bits");
     return PG_OK;
 }
 
@@ -202,9 +202,8 @@ pg_status pg_knn(const pg_paths* paths, int32_t k, int32_t cell_shift, int64_t* 
         return finish(s, nullptr, nullptr, 0);
     }
     if ((e = run_grid(paths, g, nullptr, s)) != hipSuccess) return hip_fail(e, "grid build");
-    if ((e = launch_knn(N, K, shift, g.qs, g.perm, g.inv, g.range, nullptr, col, row_ptr, g.redo, g.nredo, s)) !=
-        hipSuccess)
-        return hip_fail(e, "knn");
+    e = launch_knn(N, K, shift, g.qs, g.perm, g.inv, g.range, nullptr, col, row_ptr, g.redo, g.nredo, false, s);
+    if (e != hipSuccess) return hip_fail(e, "knn");
     return finish(s, nullptr, g.flag, 0);
 }
 

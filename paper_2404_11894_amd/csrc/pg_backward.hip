@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, co
 // and d/d b_i += ybar, stores zbar_i = alpha_i ybar and adds
 // <zbar_i, sum_l dw_il/dg L_{t-1}(j_l)> to the block's dL/dg slot.  One thread
 // per row over the sliced-ELL edges (all K loads issued before the gathers),
-// as in the forward product.  KT = K at compile time, 0: runtime K.
+// as in the forward product.  KT = ell_k4(K) at compile time, 0: runtime.
 template <int KT>
 __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const int32_t* __restrict__ col,
                                                      const float* __restrict__ w, const float* __restrict__ gw,
@@ -261,13 +261,12 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const in
                 for (int c = 0; c < 4; ++c) acc(j[q][c], ww[q][c], gg[q][c]);
             }
         } else {
-            for (int q = 0; 4 * q < K; ++q) {
+            for (int q = 0; 4 * q < K; ++q) {   // every slot of the last quad: the padding adds +0
                 const i32x4 jq = ld_quad_nt(col + base + q * kQuadStride);
                 const f32x4 wq = ld_quad_nt(w + base + q * kQuadStride);
                 const f32x4 gq = ld_quad_nt(gw + base + q * kQuadStride);
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (4 * q + c < K) acc(jq[c], wq[c], gq[c]);
+                for (int c = 0; c < 4; ++c) acc(jq[c], wq[c], gq[c]);
             }
         }
         const int64_t pv = pred[i];
@@ -624,9 +623,12 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
                 hipLaunchKernelGGL(k_rev_rows<KT>, dim3((unsigned)bb.n_rows), dim3(kBlock), 0, s, N, K, r.col,
                                    r.w, r.gw, xprev, lam, r.pred, r.alpha, bb.abar, bb.bbar, bb.zbar, g_rows);
             };
-            if (K == 16) go(std::integral_constant<int, 16>{});
-            else if (K == 8) go(std::integral_constant<int, 8>{});
-            else go(std::integral_constant<int, 0>{});
+            switch (ell_k4(K)) {
+            case 8: go(std::integral_constant<int, 8>{}); break;
+            case 12: go(std::integral_constant<int, 12>{}); break;
+            case 16: go(std::integral_constant<int, 16>{}); break;
+            default: go(std::integral_constant<int, 0>{}); break;
+            }
         }
         {
             ProfScope ps(s, "rev_cols");

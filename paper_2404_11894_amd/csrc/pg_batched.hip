@@ -39,31 +39,28 @@ __device__ inline int find_scene(const SceneDesc* sd, int n, int64_t blk) {
 }
 
 // y_i = b_i + alpha_i sum_l w_il x(j_l) for every row of every scene still
-// iterating (t <= D_s); one thread per row over each scene's sliced-ELL edges.
+// iterating (t <= D_s); one thread per row over each scene's sliced-ELL
+// edges.  A block belongs to one scene, so the branch on the scene's K4 is
+// uniform: K4 = 8, 12, 16 take the unrolled row sum, other counts the loop.
+template <int KT>
+__device__ __forceinline__ void spmv_batched_row(const SceneDesc& d, int64_t i) {
+    const f3 z = ell_row_sum<KT>(i, d.K, d.col, d.w, d.x);
+    const float a = d.alpha[i];
+    const f3 bb = ld3(d.b, i);
+    st3(d.y, i, f3{fmaf(a, z.x, bb.x), fmaf(a, z.y, bb.y), fmaf(a, z.z, bb.z)});
+}
+
 __global__ __launch_bounds__(kBlock) void k_spmv_batched(const SceneDesc* __restrict__ sd, int nsc, int t) {
     const SceneDesc& d = sd[find_scene(sd, nsc, blockIdx.x)];
     if (t > d.D) return;
     const int64_t i = (blockIdx.x - d.blk0) * (int64_t)kBlock + threadIdx.x;
     if (i >= d.nrows) return;
-    const int K = d.K;
-    const int64_t base = ell_row(i, K);
-    float ax = 0.f, ay = 0.f, az = 0.f;
-    for (int q = 0; 4 * q < K; ++q) {
-        const i32x4 jq = ld_quad_nt(d.col + base + q * kQuadStride);
-        const f32x4 wq = ld_quad_nt(d.w + base + q * kQuadStride);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (4 * q + c < K) {
-                const f3 xv = ld3(d.x, jq[c]);
-                ax = fmaf(wq[c], xv.x, ax);
-                ay = fmaf(wq[c], xv.y, ay);
-                az = fmaf(wq[c], xv.z, az);
-            }
-        }
+    switch (ell_k4(d.K)) {
+    case 8: spmv_batched_row<8>(d, i); break;
+    case 12: spmv_batched_row<12>(d, i); break;
+    case 16: spmv_batched_row<16>(d, i); break;
+    default: spmv_batched_row<0>(d, i); break;
     }
-    const float a = d.alpha[i];
-    const f3 bb = ld3(d.b, i);
-    st3(d.y, i, f3{fmaf(a, ax, bb.x), fmaf(a, ay, bb.y), fmaf(a, az, bb.z)});
 }
 
 // x(v) = y(succ v), 0 at a path's end, for scenes still iterating.

@@ -80,6 +80,12 @@ __global__ __launch_bounds__(kBlock) void k_edges(int64_t N, Consts c, const int
     sy = group_sum<KP>(sy);
     sz = group_sum<KP>(sz);
 
+    if (o.ell && row_ok && lane == 0) {   // padding slots of the last quad: weight 0
+        for (int l = K; l < ell_k4(K); ++l) {
+            o.w[eidx(i, l, K)] = 0.0f;
+            if (o.gw) o.gw[eidx(i, l, K)] = 0.0f;
+        }
+    }
     if (act) {
         o.w[e] = wi;
         if (o.gw) o.gw[e] = wi * hg_dlog(c.g, u_w);

@@ -390,11 +390,12 @@ __device__ __forceinline__ void knn_write(int64_t s, int K, int m, uint32_t self
                                           const uint64_t (&d)[KM], const uint32_t (&o)[KM], int32_t* col_sorted,
                                           int32_t* col_canon, int64_t* row_ptr) {
     (void)d;
-    if (col_sorted) {   // sliced-ELL layout
+    if (col_sorted) {   // sliced-ELL layout; the padding slots of the row's last quad point at itself
         col_sorted[eidx(s, 0, K)] = (int32_t)s;
 #pragma unroll
         for (int p = 0; p < KM; ++p)
             if (p >= KM - m) col_sorted[eidx(s, 1 + p - (KM - m), K)] = inv[o[p]];
+        for (int l = K; l < ell_k4(K); ++l) col_sorted[eidx(s, l, K)] = (int32_t)s;
     }
     if (col_canon) {
         int32_t* row = col_canon + (int64_t)self * K;
@@ -410,13 +411,25 @@ __device__ __forceinline__ void knn_write(int64_t s, int K, int m, uint32_t self
 }
 
 // ---- fast path: one 64-bit key per candidate --------------------------
-// key = (min(d2, 2^33 - 1) << 31) | id orders exactly like (d2, id) as long as
-// d2 < 2^33 - 1 (a distance below ~8.8% of the unit cube); a k-th neighbour
-// that far saturates the key, and that query is redone by the exact search.
-constexpr uint64_t kD2Sat = (1ull << 33) - 1;
+// key = (min(d2, sat) << idb) | id, with idb = the bits ids of this scene need
+// (N - 1 < 2^idb) and sat = 2^(64 - idb) - 1, orders exactly like (d2, id) as
+// long as d2 < sat.  Every scene below 2^25 vertices keeps 39 distance bits
+// (no saturation below ~70% of the unit cube); at 2^31 vertices 33 bits
+// (~8.8%).  A k-th neighbour that far saturates the key, and that query is
+// redone by the exact search.
+struct KeyFmt {
+    int idb;
+    uint64_t sat, idmask;
+};
 
-__device__ __forceinline__ uint64_t make_key(uint64_t d2, uint32_t oid) {
-    return ((d2 < kD2Sat ? d2 : kD2Sat) << 31) | (uint64_t)oid;
+inline KeyFmt key_fmt(int64_t N) {
+    int idb = 1;
+    while (idb < 31 && ((int64_t)1 << idb) < N) ++idb;
+    return KeyFmt{idb, (~0ull) >> idb, ((uint64_t)1 << idb) - 1};
+}
+
+__device__ __forceinline__ uint64_t make_key(uint64_t d2, uint32_t oid, const KeyFmt& f) {
+    return ((d2 < f.sat ? d2 : f.sat) << f.idb) | (uint64_t)oid;
 }
 
 template <int KM>
@@ -435,7 +448,8 @@ __device__ __forceinline__ void key_insert(uint64_t (&k)[KM], uint64_t c) {
 template <int KM>
 __device__ __forceinline__ void key_shell_search(int64_t s, int shift, int32_t qx, int32_t qy, int32_t qz,
                                                  const uint64_t* __restrict__ qs, const int32_t* __restrict__ perm,
-                                                 const uint2* __restrict__ cell_range, uint64_t (&k)[KM]) {
+                                                 const uint2* __restrict__ cell_range, const KeyFmt f,
+                                                 uint64_t (&k)[KM]) {
     const int G = 1 << (kQBits - shift);
     const int cx = qx >> shift, cy = qy >> shift, cz = qz >> shift;
     const int64_t cs = (int64_t)1 << shift;
@@ -454,7 +468,7 @@ __device__ __forceinline__ void key_shell_search(int64_t s, int shift, int32_t q
                     const int x = cx + dx;
                     if (x < 0 || x >= G) continue;
                     const int64_t gx = dx < 0 ? (int64_t)qx - ((int64_t)(x + 1) * cs - 1) : (dx > 0 ? (int64_t)x * cs - qx : 0);
-                    if ((uint64_t)(gx * gx + gy * gy + gz * gz) > (k[KM - 1] >> 31)) continue;   // cell too far
+                    if ((uint64_t)(gx * gx + gy * gy + gz * gz) > (k[KM - 1] >> f.idb)) continue;   // cell too far
                     const uint32_t cell = morton3((uint32_t)x, (uint32_t)y, (uint32_t)z);
                     const uint2 cr = cell_range[cell];
                     const uint32_t beg = cr.x, end = cr.y;
@@ -463,7 +477,7 @@ __device__ __forceinline__ void key_shell_search(int64_t s, int shift, int32_t q
                         int32_t ax, ay, az;
                         qunpack(qs[t], ax, ay, az);
                         const int64_t ex = ax - qx, ey = ay - qy, ez = az - qz;
-                        key_insert<KM>(k, make_key((uint64_t)(ex * ex + ey * ey + ez * ez), (uint32_t)perm[t]));
+                        key_insert<KM>(k, make_key((uint64_t)(ex * ex + ey * ey + ez * ez), (uint32_t)perm[t], f));
                     }
                 }
             }
@@ -477,7 +491,7 @@ __device__ __forceinline__ void key_shell_search(int64_t s, int shift, int32_t q
             if (c3[a] + r < G - 1) gap = min(gap, (int64_t)(c3[a] + r + 1) * cs - q3[a]);
         }
         if (gap == INT64_MAX) break;
-        if ((k[KM - 1] >> 31) < (uint64_t)(gap * gap)) break;
+        if ((k[KM - 1] >> f.idb) < (uint64_t)(gap * gap)) break;
     }
 }
 
@@ -491,7 +505,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
                                                 const uint2* __restrict__ cell_range,
                                                 int32_t* __restrict__ col_sorted, int32_t* __restrict__ col_canon,
                                                 int64_t* __restrict__ row_ptr, uint32_t* __restrict__ redo,
-                                                uint32_t* __restrict__ nredo) {
+                                                uint32_t* __restrict__ nredo, const KeyFmt f) {
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t s = tile * blockDim.x + threadIdx.x;
     if (s >= N) return;
@@ -503,24 +517,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 #pragma unroll
     for (int p = 0; p < KM; ++p) k[p] = p < KM - m ? 0ull : ~0ull;
     if (m > 0) {
-        key_shell_search<KM>(s, shift, qx, qy, qz, qs, perm, cell_range, k);
-        if ((k[KM - 1] >> 31) >= kD2Sat) {   // a kept distance saturated: redo exactly
+        key_shell_search<KM>(s, shift, qx, qy, qz, qs, perm, cell_range, f, k);
+        if ((k[KM - 1] >> f.idb) >= f.sat) {   // a kept distance saturated: redo exactly
             redo[atomicAdd(nredo, 1u)] = (uint32_t)s;
             return;
         }
     }
-    if (col_sorted) {   // sliced-ELL layout
+    if (col_sorted) {   // sliced-ELL layout; the padding slots of the row's last quad point at itself
         col_sorted[eidx(s, 0, K)] = (int32_t)s;
 #pragma unroll
         for (int p = 0; p < KM; ++p)
-            if (p >= KM - m) col_sorted[eidx(s, 1 + p - (KM - m), K)] = inv[(uint32_t)(k[p] & 0x7fffffffu)];
+            if (p >= KM - m) col_sorted[eidx(s, 1 + p - (KM - m), K)] = inv[(uint32_t)(k[p] & f.idmask)];
+        for (int l = K; l < ell_k4(K); ++l) col_sorted[eidx(s, l, K)] = (int32_t)s;
     }
     if (col_canon) {
         int32_t* row = col_canon + (int64_t)self * K;
         row[0] = (int32_t)self;
 #pragma unroll
         for (int p = 0; p < KM; ++p)
-            if (p >= KM - m) row[1 + p - (KM - m)] = (int32_t)(k[p] & 0x7fffffffu);
+            if (p >= KM - m) row[1 + p - (KM - m)] = (int32_t)(k[p] & f.idmask);
     }
     if (row_ptr) {
         row_ptr[self] = (int64_t)self * K;
@@ -554,18 +569,31 @@ __global__ __launch_bounds__(kBlock) void k_knn_exact(int64_t N, int K, int shif
     }
 }
 
+// Every query handed to the exact search (PG_FLAG_EXACT_KNN).
+__global__ __launch_bounds__(kBlock) void k_redo_all(int64_t N, uint32_t* __restrict__ redo,
+                                                     uint32_t* __restrict__ nredo) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) redo[i] = (uint32_t)i;
+    if (i == 0) *nredo = (uint32_t)N;
+}
+
 hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, const int32_t* perm,
                       const int32_t* inv, const uint2* cell_range, int32_t* col_sorted, int32_t* col_canon,
-                      int64_t* row_ptr, uint32_t* redo, uint32_t* nredo, hipStream_t s) {
+                      int64_t* row_ptr, uint32_t* redo, uint32_t* nredo, bool exact_only, hipStream_t s) {
     if (N == 0) return hipSuccess;
     const int m = K - 1;
     hipError_t e = launch_fill(nredo, sizeof(uint32_t), s);
     if (e != hipSuccess) return e;
+    const KeyFmt f = key_fmt(N);
     auto go = [&](auto km) {
         constexpr int KM = decltype(km)::value;
         constexpr int WPE = KM == 15 ? 8 : (KM <= 16 ? 6 : 1);
-        hipLaunchKernelGGL((k_knn<KM, WPE>), dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, K, shift, qsorted,
-                           perm, inv, cell_range, col_sorted, col_canon, row_ptr, redo, nredo);
+        if (exact_only)
+            hipLaunchKernelGGL(k_redo_all, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, redo, nredo);
+        else
+            hipLaunchKernelGGL((k_knn<KM, WPE>), dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, K,
+                               shift, qsorted, perm, inv, cell_range, col_sorted, col_canon, row_ptr, redo, nredo,
+                               f);
         hipLaunchKernelGGL(k_knn_exact<KM>, dim3(256), dim3(kBlock), 0, s, N, K, shift, qsorted, perm, inv,
                            cell_range, col_sorted, col_canon, row_ptr, (const uint32_t*)redo,
                            (const uint32_t*)nredo);

@@ -31,7 +31,9 @@ __host__ __device__ inline int64_t div_up(int64_t a, int64_t b) { return (a + b 
 
 // Internal edge layout: sliced ELL with quads.  Rows are grouped in slices
 // of 64 (one wave) and a row's edges in quads of four; the row stride is K
-// rounded up to a multiple of 4 (the padding slots are never read).  Inside a
+// rounded up to a multiple of 4, and the padding slots hold the row itself
+// with weight 0, so a sum over all slots of the last quad adds exactly +0
+// (weights and radiance are non-negative).  Inside a
 // slice, quad q of all 64 rows is contiguous and each row's quad is 16 bytes,
 // so a wave that owns a slice reads four edges of each of its rows with one
 // 16-byte load per lane, 1 KiB contiguous per wave.
@@ -131,6 +133,67 @@ struct f3 { float x, y, z; };
 
 __device__ inline f3 ld3(const float* p, int64_t i) { return f3{p[3 * i], p[3 * i + 1], p[3 * i + 2]}; }
 __device__ inline void st3(float* p, int64_t i, f3 v) { p[3 * i] = v.x; p[3 * i + 1] = v.y; p[3 * i + 2] = v.z; }
+
+// sum_l w_il x(j_l) for row i of the sliced ELL, over all K4 = ell_k4(K)
+// slots (the padding slots add +0).  KT = K4 at compile time: every quad's id
+// and weight load is issued before the K4 gathers, so a wave has 64*K4
+// gathers in flight; KT = 0: runtime K4, quad by quad.
+template <int KT>
+__device__ __forceinline__ f3 ell_row_sum(int64_t i, int K, const int32_t* __restrict__ col,
+                                          const float* __restrict__ w, const float* __restrict__ x) {
+    static_assert(KT % 4 == 0, "compile-time K4 must fill whole quads");
+    const int64_t base = ell_row(i, K);
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    if (KT) {
+        constexpr int NQ = KT > 0 ? KT / 4 : 1;
+        i32x4 j[NQ];
+        f32x4 ww[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            j[q] = ld_quad_nt(col + base + q * kQuadStride);
+            ww[q] = ld_quad_nt(w + base + q * kQuadStride);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const f3 xv = ld3(x, j[q][c]);
+                ax = fmaf(ww[q][c], xv.x, ax);
+                ay = fmaf(ww[q][c], xv.y, ay);
+                az = fmaf(ww[q][c], xv.z, az);
+            }
+        }
+    } else {
+        for (int q = 0; 4 * q < K; ++q) {
+            const i32x4 jq = ld_quad_nt(col + base + q * kQuadStride);
+            const f32x4 wq = ld_quad_nt(w + base + q * kQuadStride);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const f3 xv = ld3(x, jq[c]);
+                ax = fmaf(wq[c], xv.x, ax);
+                ay = fmaf(wq[c], xv.y, ay);
+                az = fmaf(wq[c], xv.z, az);
+            }
+        }
+    }
+    return f3{ax, ay, az};
+}
+
+// Compile-time K4 for the common neighbour counts, else runtime.
+template <class F>
+__host__ __device__ inline void dispatch_k4(int K, F&& go) {
+    switch (ell_k4(K)) {
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    case 8: go(std::integral_constant<int, 8>{}); break;
+    case 12: go(std::integral_constant<int, 12>{}); break;
+    case 16: go(std::integral_constant<int, 16>{}); break;
+    case 20: go(std::integral_constant<int, 20>{}); break;
+    case 24: go(std::integral_constant<int, 24>{}); break;
+    case 28: go(std::integral_constant<int, 28>{}); break;
+    case 32: go(std::integral_constant<int, 32>{}); break;
+    default: go(std::integral_constant<int, 0>{}); break;
+    }
+}
 
 // Henyey-Greenstein density as a function of u = 1 - cos between unit
 // vectors, u = |a - b|^2 / 2:  HG = (1-g^2) / (4 pi ((1-g)^2 + 2 g u)^(3/2)).
@@ -256,7 +319,7 @@ hipError_t launch_scatter(int64_t N, const pg_paths& paths, int shift, const uin
 hipError_t launch_cell_range(int64_t ncells, int shift, const uint32_t* start, uint2* range, hipStream_t s);
 hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, const int32_t* perm,
                       const int32_t* inv, const uint2* cell_range, int32_t* col_sorted, int32_t* col_canon,
-                      int64_t* row_ptr, uint32_t* redo, uint32_t* nredo, hipStream_t s);
+                      int64_t* row_ptr, uint32_t* redo, uint32_t* nredo, bool exact_only, hipStream_t s);
 
 // records in path order (no permutation)
 hipError_t launch_pack_records(int64_t N, const pg_paths& paths, VRec* rec, int32_t* flag, hipStream_t s);

@@ -73,24 +73,21 @@ hipError_t launch_spmv(int64_t N, int K, const int32_t* col, const float* w, con
 }
 
 // One thread per row over the sliced-ELL layout: each wave owns one slice of
-// 64 rows, issues the column-id and weight loads of all its rows (one 16-byte
-// load per quad of edges, 1 KiB contiguous per wave) and the K gathers before
-// it waits, so a wave has 64*K independent gathers in flight.  KT = K at
-// compile time, a multiple of 4 (0: runtime K).
-// rowmask (nullable): rows with rowmask[i] < 0 output 0.  alpha NULL means 1.
-// SCATTER: the row's result is stored at y[rowmask[i]] (the predecessor) and
-// rows with rowmask[i] < 0 are skipped; otherwise such rows store 0 at y[i].
+// 64 rows and reads four edges of each of its rows per 16-byte load (1 KiB
+// contiguous per wave).  rowmask (nullable): rows with rowmask[i] < 0 output
+// 0.  alpha NULL means 1.  SCATTER: the row's result is stored at
+// y[rowmask[i]] (the predecessor) and rows with rowmask[i] < 0 are skipped;
+// otherwise such rows store 0 at y[i].
 //
 // Blocks run in plain launch order (all XCDs sweep the same region of the
 // sorted rows together, which measured faster here than giving each XCD its
 // own contiguous range), and the edge ids and weights, read exactly once, are
 // loaded non-temporally so they do not displace the gathered vector in L2.
 template <int KT, bool SCATTER>
-__global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int Kr, const int32_t* __restrict__ col,
+__global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int K, const int32_t* __restrict__ col,
                                                      const float* __restrict__ w, const float* __restrict__ x,
                                                      const float* __restrict__ b, const float* __restrict__ alpha,
                                                      const int32_t* __restrict__ rowmask, float* __restrict__ y) {
-    static_assert(KT % 4 == 0, "compile-time K must fill whole quads");
     const int64_t tile = blockIdx.x;
     const int64_t i = tile * kBlock + threadIdx.x;
     if (i >= N) return;
@@ -103,58 +100,20 @@ __global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int Kr, const in
         }
         if (!SCATTER) dst = i;
     }
-    const int K = KT ? KT : Kr;
-    const int64_t base = ell_row(i, K);
-    float ax = 0.f, ay = 0.f, az = 0.f;
-    if (KT) {
-        constexpr int NQ = KT > 0 ? KT / 4 : 1;
-        i32x4 j[NQ];
-        f32x4 ww[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            j[q] = ld_quad_nt(col + base + q * kQuadStride);
-            ww[q] = ld_quad_nt(w + base + q * kQuadStride);
-        }
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const f3 xv = ld3(x, j[q][c]);
-                ax = fmaf(ww[q][c], xv.x, ax);
-                ay = fmaf(ww[q][c], xv.y, ay);
-                az = fmaf(ww[q][c], xv.z, az);
-            }
-        }
-    } else {
-        for (int q = 0; 4 * q < K; ++q) {
-            const i32x4 jq = ld_quad_nt(col + base + q * kQuadStride);
-            const f32x4 wq = ld_quad_nt(w + base + q * kQuadStride);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (4 * q + c < K) {
-                    const f3 xv = ld3(x, jq[c]);
-                    ax = fmaf(wq[c], xv.x, ax);
-                    ay = fmaf(wq[c], xv.y, ay);
-                    az = fmaf(wq[c], xv.z, az);
-                }
-            }
-        }
-    }
+    const f3 z = ell_row_sum<KT>(i, K, col, w, x);
     const f3 bb = ld3(b, i);
     const float a = alpha ? alpha[i] : 1.0f;
-    st3(y, dst, f3{fmaf(a, ax, bb.x), fmaf(a, ay, bb.y), fmaf(a, az, bb.z)});
+    st3(y, dst, f3{fmaf(a, z.x, bb.x), fmaf(a, z.y, bb.y), fmaf(a, z.z, bb.z)});
 }
 
 template <bool SCATTER>
 static void go_spmv_ell(int64_t N, int K, const int32_t* col, const float* w, const float* x, const float* b,
                         const float* alpha, const int32_t* rowmask, float* y, hipStream_t s) {
     dim3 grid((unsigned)div_up(N, kBlock)), block(kBlock);
-    if (K == 16)
-        hipLaunchKernelGGL((k_spmv_ell<16, SCATTER>), grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
-    else if (K == 8)
-        hipLaunchKernelGGL((k_spmv_ell<8, SCATTER>), grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
-    else
-        hipLaunchKernelGGL((k_spmv_ell<0, SCATTER>), grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
+    dispatch_k4(K, [&](auto kt) {
+        constexpr int KT = decltype(kt)::value;
+        hipLaunchKernelGGL((k_spmv_ell<KT, SCATTER>), grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
+    });
 }
 
 hipError_t launch_spmv_ell(int64_t N, int K, const int32_t* col, const float* w, const float* x, const float* b,
@@ -203,16 +162,19 @@ hipError_t launch_shift(int64_t N, const int32_t* succ, const float* y, float* x
 
 // Row v of the shifted operator = albedo_u * row u of W, constant c_v = b_u,
 // u = succ(v); a row without successor keeps zero weights (self columns).
+// All slots of the row's quads are written (the padding slots of W hold
+// (u, 0), so they become weight-0 slots here too).
 __global__ __launch_bounds__(kBlock) void k_shifted_build(int64_t N, int K, const int32_t* __restrict__ succ,
                                                           const int32_t* __restrict__ col,
                                                           const float* __restrict__ w, const float* __restrict__ b,
                                                           const float* __restrict__ alpha,
                                                           int32_t* __restrict__ mcol, float* __restrict__ mw,
                                                           float* __restrict__ c) {
+    const int K4 = ell_k4(K);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N * (int64_t)K) return;
-    const int64_t v = t / K;
-    const int k = (int)(t - v * K);
+    if (t >= N * (int64_t)K4) return;
+    const int64_t v = t / K4;
+    const int k = (int)(t - v * K4);
     const int64_t u = succ[v];
     const int64_t e = eidx(v, k, K);
     if (u >= 0) {
@@ -229,8 +191,8 @@ hipError_t launch_shifted_build(int64_t N, int K, const int32_t* succ, const int
                                 const float* b, const float* alpha, int32_t* mcol, float* mw, float* c,
                                 hipStream_t s) {
     if (N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_shifted_build, dim3((unsigned)div_up(N * (int64_t)K, kBlock)), dim3(kBlock), 0, s, N, K,
-                       succ, col, w, b, alpha, mcol, mw, c);
+    hipLaunchKernelGGL(k_shifted_build, dim3((unsigned)div_up(N * (int64_t)ell_k4(K), kBlock)), dim3(kBlock), 0, s,
+                       N, K, succ, col, w, b, alpha, mcol, mw, c);
     return hipGetLastError();
 }
 

@@ -57,7 +57,7 @@ hipError_t render_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, co
     } else {
         ProfScope ps(s, "knn");
         PG_TRY(launch_knn(N, K, g.shift, g.qs, g.perm, g.inv, g.range, r.col, out ? out->col : nullptr,
-                          out ? out->row_ptr : nullptr, g.redo, g.nredo, s));
+                          out ? out->row_ptr : nullptr, g.redo, g.nredo, (q->flags & PG_FLAG_EXACT_KNN) != 0, s));
     }
     const Consts c = make_consts(q, K);
     EdgeOut o{};

@@ -61,6 +61,9 @@ def test_workspace_queries_validate_arguments():
     q.flags = pg.PG_FLAG_TAPE
     assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == 0
     assert nb.value > small                 # the tape keeps every iterate
+    q.flags = pg.PG_FLAG_CHECK | pg.PG_FLAG_EXACT_KNN
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == 0
+    assert nb.value == small
     for bad in (dict(k=0), dict(k=65), dict(D=-1), dict(g=1.0), dict(g=0.3, g_s=-1.0), dict(env_pdf=0.0),
                 dict(init=2), dict(final_gather=3), dict(cell_shift=5), dict(schedule=9), dict(flags=64)):
         kw = dict(k=8, D=4)

@@ -10,7 +10,7 @@ import torch
 import oracle
 import scenegen
 import paper_2404_11894_amd as pg
-from tests.gpu_util import crop
+from tests.gpu_util import crop, synthetic
 
 pytestmark = pytest.mark.gpu
 
@@ -42,6 +42,25 @@ def test_backward_matches_oracle(init, fg):
     grid, gimg, ref = case(sc, 8, 8, 6, 0.5, init, fg)
     paths = pg.DevicePaths(sc, albedo_grid=grid)
     q = pg.params(k=8, D=6, g=0.5, init=init, final_gather=fg, flags=pg.PG_FLAG_CHECK)
+    out = pg.pg_backward(paths, q, torch.from_numpy(gimg.astype(np.float32)), grad_albedo=True)
+    torch.cuda.synchronize()
+    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid")
+    grad_close(out["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo")
+    grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
+
+
+def test_backward_with_transpose_overflow():
+    """200 coincident points: the lowest ids among them are everyone's
+    tie-broken neighbours, so their in-degree (about 200) exceeds the 2k
+    entries a row of the transposed operator holds and the excess takes the
+    overflow list."""
+    rng = np.random.default_rng(7)
+    pos = np.concatenate([np.full((200, 3), 0.41), rng.random((100, 3))])
+    sc = synthetic(pos, rng, lengths=np.full(30, 10))
+    print(f"overflow N={sc.n_vertices}", flush=True)
+    grid, gimg, ref = case(sc, 4, 4, 5, 0.6)
+    paths = pg.DevicePaths(sc, albedo_grid=grid)
+    q = pg.params(k=4, D=5, g=0.6, flags=pg.PG_FLAG_CHECK)
     out = pg.pg_backward(paths, q, torch.from_numpy(gimg.astype(np.float32)), grad_albedo=True)
     torch.cuda.synchronize()
     grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid")

@@ -178,6 +178,28 @@ def test_lattice_ties():
         compare_all(sc, k, img, gr, ref_img, ref, f"lattice k={k}")
 
 
+def test_exact_search_fallback_matches_fast_path(tiny):
+    """The exact (d^2, id) search the fast path hands saturated queries to,
+    forced for every query: same neighbours and bit-identical images, and the
+    oracle's neighbour lists, on the scene, a tie-heavy lattice and a pile of
+    coincident points."""
+    rng = np.random.default_rng(9)
+    g = np.array([(x, y, z) for z in range(6) for y in range(6) for x in range(6)], np.float64)
+    lattice = synthetic(((g + 0.5) / 6.0).astype(np.float32), rng, lengths=np.full(27, 8))
+    pile = synthetic(np.concatenate([np.full((120, 3), 0.6), rng.random((40, 3))]), rng, lengths=np.full(16, 10))
+    for name, sc, k in (("tiny", tiny, 8), ("lattice", lattice, 19), ("pile", pile, 12)):
+        print(f"exact fallback {name} N={sc.n_vertices} k={k}", flush=True)
+        paths = pg.DevicePaths(sc)
+        fast, gf = pg.pg_render(paths, pg.params(k=k, D=4, g=0.5, flags=pg.PG_FLAG_CHECK), graph=True)
+        exact, ge = pg.pg_render(paths, pg.params(k=k, D=4, g=0.5, flags=pg.PG_FLAG_CHECK | pg.PG_FLAG_EXACT_KNN),
+                                 graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(gf["col"], ge["col"]), name
+        assert torch.equal(fast, exact), name
+        ref_img, ref = oracle.render(sc, oracle.params(k=k, D=4, g=0.5), trace=True)
+        assert np.array_equal(ge["col"].cpu().numpy().reshape(sc.n_vertices, -1), ref["col"]), name
+
+
 def test_device_input_errors_are_reported():
     rng = np.random.default_rng(4)
     sc = synthetic(rng.random((64, 3)), rng, lengths=np.full(8, 8))
