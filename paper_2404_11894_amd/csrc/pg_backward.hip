@@ -76,12 +76,12 @@ __global__ __launch_bounds__(kBlock) void k_tscatter(int64_t E, int K, uint32_t 
     const int64_t e = eidx(i, (int)(t - i * K), K);
     const int64_t j = col[e];
     const uint32_t q = rank[e];
+    const uint32_t o = wave_append(novf, q >= cap);
     if (q < cap) {
         const int64_t p = (int64_t)soff[j >> 6] + (int64_t)q * kSlice + (j & (kSlice - 1));
         tsrc[p] = (int32_t)i;
         tw[p] = w[e];
     } else {
-        const uint32_t o = atomicAdd(novf, 1u);
         ovf[2 * (int64_t)o] = (int32_t)j;
         ovf[2 * (int64_t)o + 1] = (int32_t)i;
         ovw[o] = w[e];

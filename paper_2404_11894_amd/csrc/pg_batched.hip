@@ -143,12 +143,30 @@ static hipError_t batched_iterations(const BatchLayout& L, hipStream_t s) {
     return hipSuccess;
 }
 
-// Runs all three phases.  Streams: the setup and output of scene s go to
-// streams[s % ns]; streams[0] is the caller's and does the batched loop.
+// Stream of each scene's setup and output: largest first (by N K, the cost
+// of its kNN and weights) onto the least-loaded of the ns streams.
+static std::vector<int> stream_of_scene(const BatchLayout& L, int ns) {
+    std::vector<int> order(L.n), which(L.n, 0);
+    for (int s = 0; s < L.n; ++s) order[s] = s;
+    auto cost = [&](int s) { return (double)L.r[s].N * (double)(L.r[s].K > 0 ? L.r[s].K : 1); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    std::vector<double> load(ns, 0.0);
+    for (int s : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        which[s] = k;
+        load[k] += cost(s);
+    }
+    return which;
+}
+
+// Runs all three phases.  Streams: the setup and output of each scene go to
+// the stream stream_of_scene picks; streams[0] is the caller's and does the
+// batched loop.
 static hipError_t run_batch(const pg_paths* paths, BatchLayout& L, float* const* images, hipStream_t* streams,
                             int ns, hipEvent_t* ev) {
     hipStream_t s0 = streams[0];
     hipError_t e;
+    const std::vector<int> which = stream_of_scene(L, ns);
     if (ns > 1) {
         if ((e = hipEventRecord(ev[0], s0)) != hipSuccess) return e;
         for (int k = 1; k < ns; ++k)
@@ -156,7 +174,8 @@ static hipError_t run_batch(const pg_paths* paths, BatchLayout& L, float* const*
     }
     for (int s = 0; s < L.n; ++s) {
         float* x0 = nullptr;
-        if ((e = render_setup(&paths[s], &L.q[s], L.r[s], nullptr, streams[s % ns], &x0)) != hipSuccess) return e;
+        if ((e = render_setup(&paths[s], &L.q[s], L.r[s], nullptr, streams[which[s]], &x0)) != hipSuccess)
+            return e;
     }
     if (ns > 1) {
         for (int k = 1; k < ns; ++k) {
@@ -171,7 +190,7 @@ static hipError_t run_batch(const pg_paths* paths, BatchLayout& L, float* const*
             if ((e = hipStreamWaitEvent(streams[k], ev[0], 0)) != hipSuccess) return e;
     }
     for (int s = 0; s < L.n; ++s)
-        if ((e = render_output(&paths[s], &L.q[s], L.r[s], nullptr, images[s], L.r[s].x, streams[s % ns])) !=
+        if ((e = render_output(&paths[s], &L.q[s], L.r[s], nullptr, images[s], L.r[s].x, streams[which[s]])) !=
             hipSuccess)
             return e;
     if (ns > 1) {

@@ -516,12 +516,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     uint64_t k[KM];
 #pragma unroll
     for (int p = 0; p < KM; ++p) k[p] = p < KM - m ? 0ull : ~0ull;
-    if (m > 0) {
-        key_shell_search<KM>(s, shift, qx, qy, qz, qs, perm, cell_range, f, k);
-        if ((k[KM - 1] >> f.idb) >= f.sat) {   // a kept distance saturated: redo exactly
-            redo[atomicAdd(nredo, 1u)] = (uint32_t)s;
-            return;
-        }
+    if (m > 0) key_shell_search<KM>(s, shift, qx, qy, qz, qs, perm, cell_range, f, k);
+    const bool sat = m > 0 && (k[KM - 1] >> f.idb) >= f.sat;   // a kept distance saturated: redo exactly
+    const uint32_t slot = wave_append(nredo, sat);
+    if (sat) {
+        redo[slot] = (uint32_t)s;
+        return;
     }
     if (col_sorted) {   // sliced-ELL layout; the padding slots of the row's last quad point at itself
         col_sorted[eidx(s, 0, K)] = (int32_t)s;

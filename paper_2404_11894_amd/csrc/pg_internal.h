@@ -251,6 +251,22 @@ __device__ inline void trilerp_corners(int R, float px, float py, float pz, uint
     }
 }
 
+// Appends one item for every active lane with `take` set to a list whose
+// length is *counter and returns the lane's slot (meaningful where take is
+// set): one atomic per wave for the wave's total, each lane's offset from a
+// ballot and the count of taking lanes below it.  All active lanes of the wave
+// must call it together.
+__device__ inline uint32_t wave_append(uint32_t* counter, bool take) {
+    const uint64_t m = __ballot(take);
+    if (m == 0) return 0;
+    const int lane = (int)__lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, leader, kWave);
+    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
 // Record a device-detected input error (flag may be NULL).
 __device__ inline void set_flag(int32_t* flag, int32_t bit) {
     if (flag) atomicOr(flag, bit);
