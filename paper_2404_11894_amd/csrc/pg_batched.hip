@@ -47,7 +47,7 @@ __device__ __forceinline__ void spmv_batched_row(const SceneDesc& d, int64_t i) 
     const f3 z = ell_row_sum<KT>(i, d.K, d.col, d.w, d.x);
     const float a = d.alpha[i];
     const f3 bb = ld3(d.b, i);
-    st3(d.y, i, f3{fmaf(a, z.x, bb.x), fmaf(a, z.y, bb.y), fmaf(a, z.z, bb.z)});
+    st3_nt(d.y, i, f3{fmaf(a, z.x, bb.x), fmaf(a, z.y, bb.y), fmaf(a, z.z, bb.z)});
 }
 
 __global__ __launch_bounds__(kBlock) void k_spmv_batched(const SceneDesc* __restrict__ sd, int nsc, int t) {
@@ -69,10 +69,10 @@ __global__ __launch_bounds__(kBlock) void k_shift_batched(const SceneDesc* __res
     if (t > d.D) return;
     const int64_t v = (blockIdx.x - d.blk0) * (int64_t)blockDim.x + threadIdx.x;
     if (v >= d.nrows) return;
-    const int64_t u = d.succ[v];
+    const int64_t u = __builtin_nontemporal_load(d.succ + v);
     f3 val{0.f, 0.f, 0.f};
     if (u >= 0) val = ld3(d.y, u);
-    st3(d.x, v, val);
+    st3_nt(d.x, v, val);
 }
 
 // ------------------------------------------------------------------ host ---

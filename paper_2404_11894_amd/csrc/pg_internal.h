@@ -133,6 +133,14 @@ struct f3 { float x, y, z; };
 
 __device__ inline f3 ld3(const float* p, int64_t i) { return f3{p[3 * i], p[3 * i + 1], p[3 * i + 2]}; }
 __device__ inline void st3(float* p, int64_t i, f3 v) { p[3 * i] = v.x; p[3 * i + 1] = v.y; p[3 * i + 2] = v.z; }
+// Store with the non-temporal hint: the propagation's output vectors are
+// consumed by the next kernel's gathers, which measured faster when these
+// stores do not allocate in the caches on the way out.
+__device__ inline void st3_nt(float* p, int64_t i, f3 v) {
+    __builtin_nontemporal_store(v.x, p + 3 * i);
+    __builtin_nontemporal_store(v.y, p + 3 * i + 1);
+    __builtin_nontemporal_store(v.z, p + 3 * i + 2);
+}
 
 // sum_l w_il x(j_l) for row i of the sliced ELL, over all K4 = ell_k4(K)
 // slots (the padding slots add +0).  KT = K4 at compile time: every quad's id

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int K, const int
     const f3 z = ell_row_sum<KT>(i, K, col, w, x);
     const f3 bb = ld3(b, i);
     const float a = alpha ? alpha[i] : 1.0f;
-    st3(y, dst, f3{fmaf(a, z.x, bb.x), fmaf(a, z.y, bb.y), fmaf(a, z.z, bb.z)});
+    st3_nt(y, dst, f3{fmaf(a, z.x, bb.x), fmaf(a, z.y, bb.y), fmaf(a, z.z, bb.z)});
 }
 
 template <bool SCATTER>
@@ -130,9 +130,10 @@ hipError_t launch_spmv_scatter(int64_t N, int K, const int32_t* col, const float
     return hipGetLastError();
 }
 
-// L(v) = y(succ v), 0 at a path's end.  Four vertices per thread, strided by
-// the grid so every access stays coalesced, for four independent gathers.
-constexpr int kShiftPer = 4;
+// L(v) = y(succ v), 0 at a path's end.  Two vertices per thread, strided by
+// the grid so every access stays coalesced, for two independent gathers; the
+// successor ids (read once) are streamed and L is stored non-temporally.
+constexpr int kShiftPer = 2;
 __global__ __launch_bounds__(kBlock) void k_shift(int64_t N, const int32_t* __restrict__ succ,
                                                   const float* __restrict__ y, float* __restrict__ x) {
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_shift(int64_t N, const int32_t* __re
 #pragma unroll
     for (int k = 0; k < kShiftPer; ++k) {
         const int64_t v = v0 + (int64_t)k * kBlock;
-        u[k] = v < N ? (int64_t)succ[v] : -1;
+        u[k] = v < N ? (int64_t)__builtin_nontemporal_load(succ + v) : -1;
     }
     f3 val[kShiftPer];
 #pragma unroll
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_shift(int64_t N, const int32_t* __re
 #pragma unroll
     for (int k = 0; k < kShiftPer; ++k) {
         const int64_t v = v0 + (int64_t)k * kBlock;
-        if (v < N) st3(x, v, val[k]);
+        if (v < N) st3_nt(x, v, val[k]);
     }
 }
 
