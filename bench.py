@@ -95,7 +95,22 @@ def cpu_baseline(workload, k, D, g):
     E = sc.n_vertices * K
     return {"value": E * D / dt / 1e9, "unit": "Gedge-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"centred 64x64-pixel crop of the same image, 4 spp: N={sc.n_vertices}, E={E}, D={D}; "
-                      f"whole pipeline (kNN, weights, {D} iterations, pixels) in {dt:.2f} s"}
+                      f"whole pipeline (kNN, weights, {D} iterations, pixels) in {dt:.2f} s",
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """The host's CPU model and logical CPU count (the oracle uses one core)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
 
 
 def time_fwd_adjoint(pg, torch, sc, w, steps, warmup):

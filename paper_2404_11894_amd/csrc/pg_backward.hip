@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const in
                 for (int c = 0; c < 4; ++c) acc(jq[c], wq[c], gq[c]);
             }
         }
-        const int64_t pv = pred[i];
+        const int64_t pv = __builtin_nontemporal_load(pred + i);
         const f3 yb = pv >= 0 ? ld3(lam, pv) : f3{0.f, 0.f, 0.f};
         abar[i] += dot3(yb, f3{zx, zy, zz});
         bbar[3 * i] += yb.x;
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const in
         bbar[3 * i + 2] += yb.z;
         const float al = alpha[i];
         const f3 zb{al * yb.x, al * yb.y, al * yb.z};
-        st3(zbar, i, zb);
+        st3_nt(zbar, i, zb);
         gl = (double)dot3(zb, f3{gx, gy, gz});
     }
     const double t = block_sum_d(gl);
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_rev_cols(int64_t N, const uint32_t* 
         ay = fmaf(ww, zb.y, ay);
         az = fmaf(ww, zb.z, az);
     }
-    st3(lam, j, f3{ax, ay, az});
+    st3_nt(lam, j, f3{ax, ay, az});
 }
 
 __global__ __launch_bounds__(kBlock) void k_rev_overflow(const int32_t* __restrict__ ovf, const float* __restrict__ ovw,

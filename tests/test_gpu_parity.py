@@ -200,6 +200,30 @@ def test_exact_search_fallback_matches_fast_path(tiny):
         assert np.array_equal(ge["col"].cpu().numpy().reshape(sc.n_vertices, -1), ref["col"]), name
 
 
+def test_phase_profiler_records_every_phase(tiny):
+    """pg_profile_start / pg_profile_stop: HIP events around each phase of a
+    render, on the launch stream; every phase of the two-pass schedule shows
+    up with its launch count."""
+    import ctypes
+    L = pg.lib()
+    paths = pg.DevicePaths(tiny)
+    q = pg.params(k=8, D=5, g=0.5)
+    pg.pg_render(paths, q)
+    torch.cuda.synchronize()
+    assert L.pg_profile_start() == 0
+    pg.pg_render(paths, q)
+    pg.pg_render(paths, q)
+    torch.cuda.synchronize()
+    arr = (pg.ProfileEntry * 64)()
+    n = ctypes.c_int32()
+    assert L.pg_profile_stop(64, arr, ctypes.byref(n)) == 0
+    got = {arr[i].name.decode(): (arr[i].count, arr[i].total_ms) for i in range(n.value)}
+    for name, count in (("grid", 2), ("knn", 2), ("edges", 2), ("paths", 2), ("spmv", 10), ("shift", 10),
+                        ("pixels", 2)):
+        assert name in got, (name, sorted(got))
+        assert got[name][0] == count and got[name][1] > 0.0, (name, got[name])
+
+
 def test_device_input_errors_are_reported():
     rng = np.random.default_rng(4)
     sc = synthetic(rng.random((64, 3)), rng, lengths=np.full(8, 8))
