@@ -37,19 +37,32 @@ __device__ inline float dot3(f3 a, f3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, 
 // is as long as its longest T-row, capped at `cap` entries.  Entries past the
 // cap go to an overflow list of (j, i, w) applied with atomics (none for
 // ordinary neighbour graphs; degenerate inputs such as many coincident points
-// can have a few).  t runs over the N*K edges in row order.
+// can have a few).
 //
 // Built in four passes: in-degrees with atomics, which also give every edge
 // its arrival rank at its T-row (one byte); slice lengths and their scan;
 // every edge stored at its rank (no atomics); each T-row sorted by source row
 // in registers, so the reverse sums run in a fixed order.
 
-// in-degree, and each edge's arrival rank at its T-row (255 = past any cap)
-__global__ __launch_bounds__(kBlock) void k_tcount(int64_t E, int K, const int32_t* __restrict__ col,
+// Row i and slot l of ELL position e (inverse of eidx); l >= K is padding.
+__device__ inline void ell_slot(int64_t e, int K, int64_t& i, int& l) {
+    const int64_t per_slice = (int64_t)ell_k4(K) * kSlice;
+    const int64_t sl = e / per_slice, off = e - sl * per_slice;
+    const int q = (int)(off / kQuadStride), in = (int)(off - (int64_t)q * kQuadStride);
+    i = sl * kSlice + (in >> 2);
+    l = 4 * q + (in & 3);
+}
+
+// in-degree, and each edge's arrival rank at its T-row (255 = past any cap);
+// one thread per ELL position, in storage order.
+__global__ __launch_bounds__(kBlock) void k_tcount(int64_t N, int K, int64_t EL, const int32_t* __restrict__ col,
                                                    uint32_t* __restrict__ cnt, uint8_t* __restrict__ rank) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= E) return;
-    const int64_t e = eidx(t / K, (int)(t % K), K);
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= EL) return;
+    int64_t i;
+    int l;
+    ell_slot(e, K, i, l);
+    if (i >= N || l >= K) return;
     const uint32_t q = atomicAdd(&cnt[col[e]], 1u);
     rank[e] = (uint8_t)(q < 255u ? q : 255u);
 }
@@ -65,15 +78,18 @@ __global__ __launch_bounds__(kBlock) void k_tslice_len(int64_t N, int64_t nslice
     if ((threadIdx.x & (kWave - 1)) == 0 && (j >> 6) < nslices) len[j >> 6] = d * (uint32_t)kSlice;
 }
 
-__global__ __launch_bounds__(kBlock) void k_tscatter(int64_t E, int K, uint32_t cap, const int32_t* __restrict__ col,
-                                                     const float* __restrict__ w, const uint8_t* __restrict__ rank,
+__global__ __launch_bounds__(kBlock) void k_tscatter(int64_t N, int K, int64_t EL, uint32_t cap,
+                                                     const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                     const uint8_t* __restrict__ rank,
                                                      const uint32_t* __restrict__ soff, int32_t* __restrict__ tsrc,
                                                      float* __restrict__ tw, int32_t* __restrict__ ovf,
                                                      float* __restrict__ ovw, uint32_t* __restrict__ novf) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= E) return;
-    const int64_t i = t / K;
-    const int64_t e = eidx(i, (int)(t - i * K), K);
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= EL) return;
+    int64_t i;
+    int l;
+    ell_slot(e, K, i, l);
+    if (i >= N || l >= K) return;
     const int64_t j = col[e];
     const uint32_t q = rank[e];
     const uint32_t o = wave_append(novf, q >= cap);
@@ -584,13 +600,14 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
         PG_TRY(launch_fill(bb.tdeg, (size_t)(N + 1) * 4, s));
         PG_TRY(launch_fill(bb.tlen, (size_t)(bb.nslices + 1) * 4, s));
         PG_TRY(launch_fill(bb.novf, 4, s));
-        hipLaunchKernelGGL(k_tcount, dim3((unsigned)div_up(E, kBlock)), dim3(kBlock), 0, s, E, K, r.col, bb.tdeg,
-                           bb.trank);
+        const int64_t EL = ell_size(N, K);
+        hipLaunchKernelGGL(k_tcount, dim3((unsigned)div_up(EL, kBlock)), dim3(kBlock), 0, s, N, K, EL, r.col,
+                           bb.tdeg, bb.trank);
         hipLaunchKernelGGL(k_tslice_len, dim3((unsigned)div_up(bb.nslices * kSlice, kBlock)), dim3(kBlock), 0, s,
                            N, bb.nslices, bb.cap, bb.tdeg, bb.tlen);
         PG_TRY(launch_scan_exclusive(bb.tlen, bb.soff, bb.nslices, bb.tpart, s));
-        hipLaunchKernelGGL(k_tscatter, dim3((unsigned)div_up(E, kBlock)), dim3(kBlock), 0, s, E, K, bb.cap, r.col,
-                           r.w, bb.trank, bb.soff, bb.tsrc, bb.tw, bb.ovf, bb.ovw, bb.novf);
+        hipLaunchKernelGGL(k_tscatter, dim3((unsigned)div_up(EL, kBlock)), dim3(kBlock), 0, s, N, K, EL, bb.cap,
+                           r.col, r.w, bb.trank, bb.soff, bb.tsrc, bb.tw, bb.ovf, bb.ovw, bb.novf);
         auto sort = [&](auto c) {
             constexpr int C = decltype(c)::value;
             hipLaunchKernelGGL(k_tsort<C>, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.cap,
