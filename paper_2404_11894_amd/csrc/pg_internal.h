@@ -348,9 +348,10 @@ hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, cons
 // records in path order (no permutation)
 hipError_t launch_pack_records(int64_t N, const pg_paths& paths, VRec* rec, int32_t* flag, hipStream_t s);
 
-// aggregation operators over row-major CSR in the records' id space.
-// canon_row (nullable) maps local row -> path-order row for the optional
-// path-order outputs.
+// aggregation operators (edge weights, direct terms) in the records' id
+// space, into the sliced-ELL layout (ell = 1, the internal render) or a
+// row-major CSR (ell = 0, the pg_edges entry point).  canon_row (nullable)
+// maps local row -> path-order row for the optional path-order outputs.
 struct EdgeOut {
     int ell;             // 1: col / w / gw in the sliced-ELL layout, 0: row-major
     float* w;            // local order (required): ell_size(N, K) or N*K elements
