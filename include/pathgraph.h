@@ -52,7 +52,8 @@ typedef int32_t pg_status;
 #define PG_ERR_UNSUPPORTED -5   /* valid request the library does not support */
 
 #define PG_INIT_PT   0  /* start from the path tracer's own incoming-indirect estimate */
-#define PG_INIT_ZERO 1  /* start from zero */
+#define PG_INIT_ZERO 1  /* start the indirect part from zero (L+_0 = the emission collected at
+                           the successor, 0 without l_emit) */
 
 #define PG_FLAG_CHECK 1u  /* synchronise and report device-detected input errors */
 #define PG_FLAG_TAPE  2u  /* pg_render keeps the graph and every iterate in the workspace
@@ -90,6 +91,14 @@ typedef struct pg_paths {
     const float* e_cam;           /* [P][3] environment radiance if the camera ray escaped, else 0 */
     const float* albedo_grid;     /* [R][R][R] (z,y,x) or NULL: albedo = cell-centred trilinear
                                      interpolation of the grid at pos (indices clamped to [0,R-1]) */
+    const float* l_emit;          /* [N][3] or NULL (no emission): volume emission at v divided by
+                                     sigma_t(v), the delta-tracking estimate of the emission term of
+                                     the RTE (Sec. "Radiative Transfer Equation in a Medium", the
+                                     operator G applied to the volume emission).  It is radiance that
+                                     leaves v toward its predecessor unscattered: it is added to the
+                                     constant b_v, to the path-traced L+_0 of the predecessor and, at
+                                     a path's first vertex, to the pixel.  A constant input: the
+                                     reverse mode does not differentiate it. */
 } pg_paths;
 
 /* Method parameters. */
@@ -170,12 +179,14 @@ pg_status pg_knn(const pg_paths* paths, int32_t k, int32_t cell_shift, int64_t* 
  *   w_ind_ij = rho_i(w_j) / M+_ij,      rho_i = HG_g about dir_in[i]
  *   w_ph_ij  = rho_i(w_j) / (M+_ij + K env_pdf)
  *   w_env_ij = rho_i(we_j) / (sum_l p_l(we_j) + K env_pdf)
- *   b_i = albedo_i (rho_i(sun) mean_j l_sun_j + sum_j w_env_ij l_env_j + w_ph_ij l_phase_j)
+ *   b_i = e_i + albedo_i (rho_i(sun) mean_j l_sun_j + sum_j w_env_ij l_env_j + w_ph_ij l_phase_j)
+ *         (e = l_emit, 0 if NULL)
  *   d_pt_i = rho_i(sun) l_sun_i + rho_i(we_i) l_env_i / (p_i(we_i) + env_pdf)
  *            + rho_i(w_i) l_phase_i / (p_i(w_i) + env_pdf)
- * and the initial incoming indirect radiance lplus0 (paper Sec. "Rendering
- * System": the path tracer's own estimate, or zero): for v with successor u,
- * lplus0(v) = albedo_u (d_pt_u + rho_u(w_u)/p_u(w_u) lplus0(u)); 0 at a path's end.
+ * and the initial radiance arriving along the continuation, lplus0 (paper Sec.
+ * "Rendering System": the path tracer's own estimate, or zero): for v with
+ * successor u, lplus0(v) = e_u + albedo_u (d_pt_u + rho_u(w_u)/p_u(w_u) lplus0(u))
+ * with PG_INIT_PT, e_u with PG_INIT_ZERO; 0 at a path's end.
  * Inputs row_ptr/col as produced by pg_knn (row i starting with i).
  * Any of the outputs may be NULL. */
 pg_status pg_edges_workspace_size(const pg_paths* paths, const pg_params* params, size_t* bytes);
@@ -199,8 +210,8 @@ pg_status pg_propagate(const pg_paths* paths, const pg_params* params, const int
 /* ---- step 4: output to pixels --------------------------------------------
  * Paper Sec. "Rendering System", "Handling direct Light" and "Final output":
  * path p with first vertex v0 outputs
- *   o_p = albedo_v0 (d_pt_v0 + sum_j w_ind_v0j L(j))        (final_gather = 0)
- *   o_p = albedo_v0 (d_pt_v0 + rho_v0(w_v0)/p_v0(w_v0) L(v0)) (final_gather = 1)
+ *   o_p = e_v0 + albedo_v0 (d_pt_v0 + sum_j w_ind_v0j L(j))        (final_gather = 0)
+ *   o_p = e_v0 + albedo_v0 (d_pt_v0 + rho_v0(w_v0)/p_v0(w_v0) L(v0)) (final_gather = 1)
  * (0 for an empty path) and image[pixel] = mean over its spp paths of
  * (e_cam_p + o_p).  image is [height][width][3].  No workspace. */
 pg_status pg_gather(const pg_paths* paths, const pg_params* params, const int64_t* row_ptr, const int32_t* col,

@@ -49,7 +49,8 @@ class _Scene(ctypes.Structure):
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("spp", ctypes.c_int32),
                 ("pad_", ctypes.c_int32)] + [
         (name, ctypes.c_void_p) for name in ("path_offsets", "pos", "dir_in", "dir_out", "albedo",
-                                             "l_sun", "dir_env", "l_env", "l_phase", "e_cam")]
+                                             "l_sun", "dir_env", "l_env", "l_phase", "e_cam",
+                                             "l_emit")]
 
 
 class _Params(ctypes.Structure):
@@ -132,6 +133,8 @@ class _Bound:
             "l_env": _f32(scene.l_env, (N, 3)), "l_phase": _f32(scene.l_phase, (N, 3)),
             "e_cam": _f32(scene.e_cam, (P, 3)),
         }
+        if getattr(scene, "l_emit", None) is not None:   # volume emission, optional
+            self.arrays["l_emit"] = _f32(scene.l_emit, (N, 3))
         s = _Scene()
         s.n_vertices, s.n_paths = N, P
         s.width, s.height, s.spp = int(scene.width), int(scene.height), int(scene.spp)

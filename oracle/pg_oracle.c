@@ -39,7 +39,20 @@
  *     is averaged with weight 1/K;
  *   - with delta tracking the propagation factor transmittance / free-flight
  *     pdf equals 1/sigma_t at the collision, which turns sigma_s * phase into
- *     albedo * phase; propagation therefore is a shift along the path.
+ *     albedo * phase; propagation therefore is a shift along the path;
+ *   - volume emission (Sec. "Radiative Transfer Equation in a Medium"): the
+ *     direct incoming radiance is Q + G L_v.  With delta tracking, G L_v
+ *     along the segment from v to its successor u is estimated at the
+ *     collision u by L_v(u) / sigma_t(u) =: e_u, an input per vertex
+ *     (l_emit).  e_u is a phase-sampled direct sample at v, so it is
+ *     aggregated with the same weights as the indirect sample arriving from
+ *     u; adding e_u to the radiance leaving u toward its predecessor,
+ *     y_u = e_u + alpha_u (d_agg_u + aggregated indirect), gives exactly
+ *     that, and the pixel gets the e of the camera ray's first collision.
+ *     The propagated vector L+ then holds the emission arriving from the
+ *     successor plus the indirect radiance; with init zero it starts at the
+ *     former (known before any iteration), so every iterate equals the one
+ *     of the decomposition L = L^o + L^+ with the emission inside L^o.
  */
 #include <math.h>
 #include <stdint.h>
@@ -64,6 +77,7 @@ typedef struct or_scene {
     const float* l_env;            /* [N][3] */
     const float* l_phase;          /* [N][3] */
     const float* e_cam;            /* [P][3] */
+    const float* l_emit;           /* [N][3] or NULL: volume emission at the vertex */
 } or_scene;
 
 typedef struct or_params {
@@ -330,6 +344,11 @@ int or_albedo_from_grid(int64_t n, const float* pos, int32_t R, const float* gri
 
 /* ---------------------------------------------------------- forward render */
 
+/* Volume emission leaving vertex i toward its predecessor, channel c. */
+static double emit(const or_scene* s, int64_t i, int c) {
+    return s->l_emit ? (double)s->l_emit[i * 3 + c] : 0.0;
+}
+
 typedef struct {
     int64_t N, P, K;
     int keep;       /* 1: traj holds every iterate t = 0..D; 0: three rotating slots */
@@ -399,24 +418,27 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
     for (int64_t i = 0; i < N; ++i) {
         receiver_weights(s, p, i, f->col + i * K, K, f->wi + i * K, f->wp + i * K, f->we + i * K, f->dagg + i * 3);
         own_direct(s, p, i, f->dpt + i * 3, f->r + i);
-        for (int c = 0; c < 3; ++c) f->b[i * 3 + c] = f->alpha[i] * f->dagg[i * 3 + c];
+        for (int c = 0; c < 3; ++c)
+            f->b[i * 3 + c] = emit(s, i, c) + f->alpha[i] * f->dagg[i * 3 + c];
     }
-    /* step 5: initial incoming indirect radiance L+_0 (traj[0]).  The path
-     * tracer's estimate at v is what arrives from its successor u:
-     * alpha_u (d_pt_u + r_u L+_0(u)); the last vertex of a path has none. */
+    /* step 5: initial L+_0 (traj[0]), the radiance arriving at v from its
+     * successor u along the continuation (the last vertex of a path has none):
+     *   init PT:   the path tracer's estimate e_u + alpha_u (d_pt_u + r_u L+_0(u));
+     *   init zero: the unknown indirect part starts at 0, which leaves e_u, the
+     *              emission collected at u (part of the known direct radiance). */
     double* L0 = f->traj;
-    if (p->init == 0) {
-        for (int64_t q = 0; q < P; ++q) {
-            int64_t a = s->path_offsets[q], e = s->path_offsets[q + 1];
-            for (int64_t v = e - 2; v >= a; --v) {
-                int64_t u = v + 1;
-                for (int c = 0; c < 3; ++c)
-                    L0[v * 3 + c] = f->alpha[u] * (f->dpt[u * 3 + c] + f->r[u] * L0[u * 3 + c]);
-            }
+    for (int64_t q = 0; q < P; ++q) {
+        int64_t a = s->path_offsets[q], e = s->path_offsets[q + 1];
+        for (int64_t v = e - 2; v >= a; --v) {
+            int64_t u = v + 1;
+            for (int c = 0; c < 3; ++c)
+                L0[v * 3 + c] = p->init == 0
+                    ? emit(s, u, c) + f->alpha[u] * (f->dpt[u * 3 + c] + f->r[u] * L0[u * 3 + c])
+                    : emit(s, u, c);
         }
     }
     /* step 6: D iterations.  Aggregation at every vertex i:
-     *   y_i = b_i + alpha_i sum_j w+_ij L+(j)
+     *   y_i = b_i + alpha_i sum_j w+_ij L+(j)      (b_i = e_i + alpha_i d_agg_i)
      * then propagation: L+(v) = y(succ v), 0 at a path's last vertex. */
     double* y = (double*)malloc(n3 * sizeof(double));
     if (!y) { free_state(f); return OR_ERR_NOMEM; }
@@ -439,8 +461,8 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
     }
     free(y);
     /* step 7: output of each path's first continuation edge, then pixels.
-     * o_p = alpha_v0 (d_pt_v0 + sum_j w+_v0j L+_D(j))   (final_gather == 0)
-     * o_p = alpha_v0 (d_pt_v0 + r_v0 L+_D(v0))          (final_gather == 1) */
+     * o_p = e_v0 + alpha_v0 (d_pt_v0 + sum_j w+_v0j L+_D(j))   (final_gather == 0)
+     * o_p = e_v0 + alpha_v0 (d_pt_v0 + r_v0 L+_D(v0))          (final_gather == 1) */
     const double* LD = iterate(f, D, D);
     const int64_t npix = (int64_t)s->width * s->height;
     for (int64_t px = 0; px < npix * 3; ++px) image[px] = 0.0;
@@ -457,7 +479,7 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
             } else {
                 for (int c = 0; c < 3; ++c) in[c] = f->r[v0] * LD[v0 * 3 + c];
             }
-            for (int c = 0; c < 3; ++c) o[c] = f->alpha[v0] * (f->dpt[v0 * 3 + c] + in[c]);
+            for (int c = 0; c < 3; ++c) o[c] = emit(s, v0, c) + f->alpha[v0] * (f->dpt[v0 * 3 + c] + in[c]);
         }
         if (out_path)
             for (int c = 0; c < 3; ++c) out_path[q * 3 + c] = o[c];

@@ -39,7 +39,7 @@ class Paths(ctypes.Structure):
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("spp", ctypes.c_int32),
                 ("albedo_grid_res", ctypes.c_int32)] + [
         (n, ctypes.c_void_p) for n in ("path_offsets", "pos", "dir_in", "dir_out", "albedo", "l_sun",
-                                       "dir_env", "l_env", "l_phase", "e_cam", "albedo_grid")]
+                                       "dir_env", "l_env", "l_phase", "e_cam", "albedo_grid", "l_emit")]
 
 
 class Params(ctypes.Structure):
@@ -132,7 +132,8 @@ def _workspace(nbytes: int, device):
 class DevicePaths:
     """The path records of one image as device tensors, plus the C struct
     pointing at them.  ``scene`` is any object with the record arrays (numpy or
-    torch) and width / height / spp attributes."""
+    torch) and width / height / spp attributes; an optional ``l_emit`` [N,3]
+    attribute (None: no emission) carries the per-vertex volume emission."""
 
     ARRAYS = ("path_offsets", "pos", "dir_in", "dir_out", "albedo", "l_sun", "dir_env", "l_env", "l_phase",
               "e_cam")
@@ -149,6 +150,9 @@ class DevicePaths:
         self.width, self.height, self.spp = int(scene.width), int(scene.height), int(scene.spp)
         self.n_vertices = int(self.tensors["pos"].shape[0])
         self.n_paths = int(self.tensors["path_offsets"].shape[0]) - 1
+        em = getattr(scene, "l_emit", None)
+        self.l_emit = None if em is None else torch.as_tensor(em).to(
+            device=self.device, dtype=torch.float32).contiguous()
         self.albedo_grid = None
         self.set_albedo_grid(albedo_grid)
 
@@ -166,6 +170,8 @@ class DevicePaths:
         if self.albedo_grid is not None:
             s.albedo_grid = self.albedo_grid.data_ptr()
             s.albedo_grid_res = int(self.albedo_grid.shape[0])
+        if self.l_emit is not None and self.l_emit.numel():
+            s.l_emit = self.l_emit.data_ptr()
         return s
 
 

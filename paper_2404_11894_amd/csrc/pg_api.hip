@@ -268,11 +268,12 @@ pg_status pg_edges(const pg_paths* paths, const pg_params* params, const int64_t
     o.w_env = w_env;
     o.b_canon = b;
     o.dpt_canon = d_pt;
+    o.emit = paths->l_emit;
     Consts c = make_consts(params, K);
     if ((e = launch_edges(N, c, col, rec, o, flag, s)) != hipSuccess) return hip_fail(e, "edges");
     if (lplus0) {
         if ((e = launch_fill(lplus0, (size_t)N * 12, s)) != hipSuccess) return hip_fail(e, "fill");
-        if ((e = launch_paths(paths->n_paths, N, paths->path_offsets, nullptr, al, dl, rl, params->init, nullptr,
+        if ((e = launch_paths(paths->n_paths, N, paths->path_offsets, nullptr, al, dl, rl, paths->l_emit, params->init, nullptr,
                               nullptr, lplus0, flag, s)) != hipSuccess)
             return hip_fail(e, "paths");
     }
@@ -322,7 +323,7 @@ pg_status pg_propagate(const pg_paths* paths, const pg_params* params, const int
     if ((e = launch_fill(flag, 64 * 4, s)) != hipSuccess) return hip_fail(e, "fill");
     if (N == 0) return finish(s, params, flag, params->flags);
     if ((e = launch_fill_value(succ, (size_t)N * 4, 0xffffffffu, s)) != hipSuccess) return hip_fail(e, "fill");
-    if ((e = launch_paths(paths->n_paths, N, paths->path_offsets, nullptr, nullptr, nullptr, nullptr, PG_INIT_ZERO,
+    if ((e = launch_paths(paths->n_paths, N, paths->path_offsets, nullptr, nullptr, nullptr, nullptr, nullptr, PG_INIT_ZERO,
                           succ, nullptr, nullptr, flag, s)) != hipSuccess)
         return hip_fail(e, "paths");
     if ((e = launch_alpha(N, *paths, alpha, s)) != hipSuccess) return hip_fail(e, "alpha");

@@ -174,8 +174,9 @@ __global__ __launch_bounds__(kBlock) void k_tsort(int64_t N, uint32_t cap, const
 }
 
 // ------------------------------------------------- reverse of the output ---
-// One thread per path.  o_p = alpha (d_pt + in), in = sum_l w_l L_D(j_l)
-// (own sample: r L_D(v0)); seeds the adjoint of L_D (lam), of alpha, d_pt, r.
+// One thread per path.  o_p = e + alpha (d_pt + in), in = sum_l w_l L_D(j_l)
+// (own sample: r L_D(v0)), e the constant emission; seeds the adjoint of L_D
+// (lam), of alpha, d_pt, r.
 __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, const int32_t* __restrict__ inv,
                                                         const int32_t* __restrict__ col, const float* __restrict__ w,
                                                         const float* __restrict__ gw, const float* __restrict__ xD,

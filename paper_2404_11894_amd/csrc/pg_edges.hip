@@ -101,7 +101,10 @@ __global__ __launch_bounds__(kBlock) void k_edges(int64_t N, Consts c, const int
         const float rho_sun = c.rho(one_minus_cos(ti, c.sun));
         const float invK = 1.0f / (float)K;
         const f3 dagg{fmaf(rho_sun * invK, sx, cx), fmaf(rho_sun * invK, sy, cy), fmaf(rho_sun * invK, sz, cz)};
-        const f3 b{alpha * dagg.x, alpha * dagg.y, alpha * dagg.z};
+        // constant of the row: the vertex's own volume emission (not scattered) + alpha d_agg
+        f3 em{0.f, 0.f, 0.f};
+        if (o.emit) em = ld3(o.emit, o.canon_row ? (int64_t)o.canon_row[i] : i);
+        const f3 b{fmaf(alpha, dagg.x, em.x), fmaf(alpha, dagg.y, em.y), fmaf(alpha, dagg.z, em.z)};
         // own (path-traced) direct: one sun sample, environment and phase samples by the balance heuristic
         const float p_w = c.pdf(u_w), p_e = c.pdf(u_e);
         const float f_env = rho_e / (p_e + c.env_pdf), f_out = rho / (p_w + c.env_pdf);
@@ -131,9 +134,11 @@ hipError_t launch_edges(int64_t N, const Consts& c, const int32_t* col, const VR
 }
 
 // One thread per path, walking it backwards.  Writes, in local ids,
-// succ(v) / pred(v) (-1 at the ends) and the initial incoming indirect
-// radiance: 0 at the last vertex, else albedo_u (d_pt_u + r_u L(u)) with u the
-// successor -- the path tracer's own estimate (init PT) -- or 0 (init zero).
+// succ(v) / pred(v) (-1 at the ends) and the initial radiance arriving from
+// the successor u along the continuation: 0 at the last vertex, else
+// e_u + albedo_u (d_pt_u + r_u L(u)) -- the path tracer's own estimate (init
+// PT) -- or e_u alone (init zero: the indirect part starts at 0), e_u being
+// the volume emission collected at u (emit, path order, nullable: 0).
 // The path is taken in chunks of kPathChunk vertices whose scattered loads
 // are all issued before the recurrence consumes them.
 // succ, pred and x0 must be pre-filled with -1, -1, 0.
@@ -141,7 +146,8 @@ constexpr int kPathChunk = 8;
 __global__ __launch_bounds__(kBlock) void k_paths(int64_t P, int64_t N, const int64_t* __restrict__ off,
                                                   const int32_t* __restrict__ inv, const float* __restrict__ alpha,
                                                   const float* __restrict__ dpt, const float* __restrict__ r,
-                                                  int init, int32_t* __restrict__ succ, int32_t* __restrict__ pred,
+                                                  const float* __restrict__ emit, int init,
+                                                  int32_t* __restrict__ succ, int32_t* __restrict__ pred,
                                                   float* __restrict__ x0, int32_t* flag) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p == 0 && (off[0] != 0 || off[P] != N)) set_flag(flag, kFlagOffsets);
@@ -152,6 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_paths(int64_t P, int64_t N, const in
         return;
     }
     const bool pt = init == PG_INIT_PT && x0;
+    const bool ez = !pt && emit && x0;   // init zero with emission
     f3 L{0.f, 0.f, 0.f};
     int32_t next = -1;   // local id of the successor
     for (int64_t v = e - 1; v >= a; v -= kPathChunk) {
@@ -159,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_paths(int64_t P, int64_t N, const in
         const int n = v - a + 1 < kPathChunk ? (int)(v - a + 1) : kPathChunk;
         int32_t sv[kPathChunk + 1];
         float al[kPathChunk], rr[kPathChunk];
-        f3 d[kPathChunk];
+        f3 d[kPathChunk], em[kPathChunk];
 #pragma unroll
         for (int c = 0; c <= kPathChunk; ++c) {
             const int64_t u = v - c;   // c == n: the predecessor of the chunk's first vertex
@@ -172,8 +179,13 @@ __global__ __launch_bounds__(kBlock) void k_paths(int64_t P, int64_t N, const in
                     al[c] = alpha[sv[c]];
                     rr[c] = r[sv[c]];
                     d[c] = ld3(dpt, sv[c]);
+                    em[c] = emit ? ld3(emit, v - c) : f3{0.f, 0.f, 0.f};
                 }
             }
+        } else if (ez) {
+#pragma unroll
+            for (int c = 0; c < kPathChunk; ++c)
+                if (c < n) em[c] = ld3(emit, v - c);
         }
 #pragma unroll
         for (int c = 0; c < kPathChunk; ++c) {
@@ -183,8 +195,12 @@ __global__ __launch_bounds__(kBlock) void k_paths(int64_t P, int64_t N, const in
                 if (pred) pred[s] = sv[c + 1];
                 if (pt) {
                     st3(x0, s, L);
-                    L = f3{al[c] * fmaf(rr[c], L.x, d[c].x), al[c] * fmaf(rr[c], L.y, d[c].y),
-                           al[c] * fmaf(rr[c], L.z, d[c].z)};
+                    L = f3{fmaf(al[c], fmaf(rr[c], L.x, d[c].x), em[c].x),
+                           fmaf(al[c], fmaf(rr[c], L.y, d[c].y), em[c].y),
+                           fmaf(al[c], fmaf(rr[c], L.z, d[c].z), em[c].z)};
+                } else if (ez) {
+                    st3(x0, s, L);
+                    L = em[c];
                 }
                 next = (int32_t)s;
             }
@@ -193,11 +209,11 @@ __global__ __launch_bounds__(kBlock) void k_paths(int64_t P, int64_t N, const in
 }
 
 hipError_t launch_paths(int64_t P, int64_t N, const int64_t* off, const int32_t* inv, const float* alpha,
-                        const float* dpt, const float* r, int init, int32_t* succ, int32_t* pred, float* x0,
-                        int32_t* flag, hipStream_t s) {
+                        const float* dpt, const float* r, const float* emit, int init, int32_t* succ, int32_t* pred,
+                        float* x0, int32_t* flag, hipStream_t s) {
     const int64_t n = P > 0 ? P : 1;
     hipLaunchKernelGGL(k_paths, dim3((unsigned)div_up(n, kBlock)), dim3(kBlock), 0, s, P, N, off, inv, alpha, dpt,
-                       r, init, succ, pred, x0, flag);
+                       r, emit, init, succ, pred, x0, flag);
     return hipGetLastError();
 }
 

@@ -361,6 +361,7 @@ struct EdgeOut {
     float* r;            // [N] local
     float* alpha;        // [N] local
     const int32_t* canon_row;
+    const float* emit;   // volume emission e, [N] f3 in canonical (path) order, nullable
     float* w_ind;        // path order, nullable
     float* w_ph;
     float* w_env;
@@ -372,7 +373,8 @@ hipError_t launch_edges(int64_t N, const Consts& c, const int32_t* col, const VR
 
 // per-path pass: successor / predecessor in local ids and the initial L
 hipError_t launch_paths(int64_t P, int64_t N, const int64_t* off, const int32_t* inv, const float* alpha,
-                        const float* dpt, const float* r, int init, int32_t* succ, int32_t* pred, float* x0,
+                        const float* dpt, const float* r, const float* emit, int init, int32_t* succ, int32_t* pred,
+                        float* x0,
                         int32_t* flag, hipStream_t s);
 
 // propagation

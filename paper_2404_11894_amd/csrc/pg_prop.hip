@@ -205,7 +205,7 @@ hipError_t launch_spmv_shifted(int64_t N, int K, const int32_t* succ, const int3
 // ------------------------------------------------------------- pixels ---
 // One thread per pixel; its spp paths are consecutive.  o_p as in the
 // "Final output" paragraph with the non-aggregated direct term at the first
-// vertex ("Handling direct Light").  inv == NULL: local ids are path-order
+// vertex ("Handling direct Light") and that vertex's volume emission.  inv == NULL: local ids are path-order
 // ids; r == NULL / alpha == NULL: computed from the path records.
 __global__ __launch_bounds__(kBlock) void k_pixels(pg_paths P, Consts c, const int32_t* __restrict__ inv,
                                                    const int32_t* __restrict__ col, const float* __restrict__ w,
@@ -268,6 +268,11 @@ __global__ __launch_bounds__(kBlock) void k_pixels(pg_paths P, Consts c, const i
             for (int q = 0; q < 8; ++q) al = fmaf(tw[q], P.albedo_grid[idx[q]], al);
         } else {
             al = P.albedo[a];
+        }
+        if (P.l_emit) {   // volume emission of the first vertex, seen by the camera unscattered
+            sx += P.l_emit[3 * a];
+            sy += P.l_emit[3 * a + 1];
+            sz += P.l_emit[3 * a + 2];
         }
         sx = fmaf(al, dpt[3 * s0] + ix, sx);
         sy = fmaf(al, dpt[3 * s0 + 1] + iy, sy);

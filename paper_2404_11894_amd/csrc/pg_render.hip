@@ -69,6 +69,7 @@ hipError_t render_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, co
     o.r = r.r;
     o.alpha = r.alpha;
     o.canon_row = g.perm;
+    o.emit = p->l_emit;
     if (out) {
         o.w_ind = out->w_ind;
         o.w_ph = out->w_ph;
@@ -86,7 +87,7 @@ hipError_t render_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, co
     PG_TRY(launch_fill(x0, (size_t)N * 12, s));
     {
         ProfScope ps(s, "paths");
-        PG_TRY(launch_paths(r.P, N, p->path_offsets, g.inv, r.alpha, r.dpt, r.r, q->init, r.succ, r.pred, x0,
+        PG_TRY(launch_paths(r.P, N, p->path_offsets, g.inv, r.alpha, r.dpt, r.r, p->l_emit, q->init, r.succ, r.pred, x0,
                             g.flag, s));
     }
     if (r.schedule == PG_SCHED_SCATTER) {

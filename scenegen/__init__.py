@@ -15,7 +15,10 @@ paragraph of Sec. "Rendering System"):
   the shadow-ray transmittance estimate), ``dir_env`` [N,3] and ``l_env`` [N,3]
   (uniform-sphere environment shadow ray and its transmitted radiance),
   ``l_phase`` [N,3] (environment radiance if the continuation ray escaped);
-* per path: ``e_cam`` [P,3] (environment radiance if the camera ray escaped).
+* per path: ``e_cam`` [P,3] (environment radiance if the camera ray escaped);
+* optionally ``l_emit`` [N,3]: the volume emission collected at the collision,
+  L_v / sigma_t = (1 - albedo) L_e(pos) for an emissive medium whose emitted
+  radiance L_e is a smooth blob (``SceneConfig.emit_L`` nonzero), else None.
 """
 from __future__ import annotations
 
@@ -113,6 +116,10 @@ class SceneConfig:
     sun_E: tuple = (2.0, 1.9, 1.7)
     env_L: tuple = (0.25, 0.35, 0.5)
     seed: int = 1
+    # emissive blob: L_e(x) = emit_L * (1 - |x - emit_center|^2 / emit_radius^2)^2 inside the radius
+    emit_L: tuple = (0.0, 0.0, 0.0)
+    emit_center: tuple = (0.5, 0.55, 0.5)
+    emit_radius: float = 0.25
 
     def _c(self) -> _Config:
         c = _Config()
@@ -158,6 +165,7 @@ class Scene:
     l_phase: np.ndarray
     e_cam: np.ndarray
     config: SceneConfig | None = None
+    l_emit: np.ndarray | None = None
     sun_dir: tuple = SUN_DIR
     env_pdf: float = 1.0 / (4.0 * math.pi)
 
@@ -200,7 +208,19 @@ def generate(cfg: SceneConfig, threads: int = 0) -> Scene:
     w, hgt = cfg.image_size
     return Scene(width=w, height=hgt, spp=cfg.spp, path_offsets=off, pos=pos, dir_in=din,
                  dir_out=dout, albedo=alb, l_sun=ls, dir_env=denv, l_env=le, l_phase=lp,
-                 e_cam=ecam, config=cfg, sun_dir=tuple(cfg.sun_dir))
+                 e_cam=ecam, config=cfg, sun_dir=tuple(cfg.sun_dir), l_emit=emission(cfg, pos, alb))
+
+
+def emission(cfg: SceneConfig, pos: np.ndarray, albedo: np.ndarray) -> np.ndarray | None:
+    """Per-vertex collected volume emission (1 - albedo) L_e(pos) [N,3], or None
+    when the medium does not emit.  With delta tracking a real collision
+    estimates the emission integral by L_v / sigma_t, and L_v = sigma_a L_e."""
+    if not any(cfg.emit_L):
+        return None
+    d2 = ((pos.astype(np.float64) - np.asarray(cfg.emit_center)) ** 2).sum(1)
+    prof = np.clip(1.0 - d2 / cfg.emit_radius ** 2, 0.0, None) ** 2
+    le = prof[:, None] * np.asarray(cfg.emit_L, np.float64)[None, :]
+    return ((1.0 - albedo.astype(np.float64))[:, None] * le).astype(np.float32)
 
 
 def density(cfg: SceneConfig) -> tuple[np.ndarray, float]:

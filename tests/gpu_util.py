@@ -1,5 +1,6 @@
 """Helpers shared by the GPU tests: tolerances and small synthetic scenes."""
 import math
+from dataclasses import replace
 
 import numpy as np
 
@@ -25,8 +26,11 @@ def assert_within(got, ref, rel, abs_, what=""):
     assert ok, f"{what}: max abs err {emax:.3e}, max rel err {rmax:.3e}"
 
 
-def crop(name, w, h, spp=None):
-    return scenegen.generate(scenegen.crop_of(scenegen.WORKLOADS[name].scene, w, h, spp))
+def crop(name, w, h, spp=None, emit_L=None):
+    cfg = scenegen.crop_of(scenegen.WORKLOADS[name].scene, w, h, spp)
+    if emit_L is not None:
+        cfg = replace(cfg, emit_L=tuple(emit_L))
+    return scenegen.generate(cfg)
 
 
 def unit(rng, n):

@@ -4,6 +4,7 @@ import ctypes
 import math
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -25,6 +26,34 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(pg.EXPORTS)
+
+
+STRUCTS = {"pg_paths": "Paths", "pg_params": "Params", "pg_graph_out": "GraphOut",
+           "pg_profile_entry": "ProfileEntry"}
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field offsets
+    (a C program built against the header prints them); equal sizes also mean
+    no header field is missing from the binding."""
+    lines = ['#include <stdio.h>', '#include "pathgraph.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for field, _ in getattr(pg, pyname)._fields_:
+            lines.append(f'printf("{cname}.{field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(pg, pyname)
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert int(got[f"{cname}.{field}"]) == getattr(cls, field).offset, f"{cname}.{field}"
 
 
 def test_version_and_default_shift():

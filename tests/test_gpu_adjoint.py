@@ -35,10 +35,11 @@ def case(sc, R, k, D, g, init="pt", fg=0, seed=5, lo=0.6, hi=0.95):
     return grid, gimg, ref
 
 
-@pytest.mark.parametrize("init,fg", [("pt", 0), ("zero", 0), ("pt", 1)])
-def test_backward_matches_oracle(init, fg):
-    sc = crop("tiny", 32, 32, 2)
-    print(f"adjoint init={init} fg={fg} N={sc.n_vertices}", flush=True)
+@pytest.mark.parametrize("init,fg,emit", [("pt", 0, False), ("zero", 0, False), ("pt", 1, False),
+                                           ("pt", 0, True), ("zero", 1, True)])
+def test_backward_matches_oracle(init, fg, emit):
+    sc = crop("tiny", 32, 32, 2, emit_L=(3.0, 2.0, 1.0) if emit else None)
+    print(f"adjoint init={init} fg={fg} emission={emit} N={sc.n_vertices}", flush=True)
     grid, gimg, ref = case(sc, 8, 8, 6, 0.5, init, fg)
     paths = pg.DevicePaths(sc, albedo_grid=grid)
     q = pg.params(k=8, D=6, g=0.5, init=init, final_gather=fg, flags=pg.PG_FLAG_CHECK)

@@ -4,6 +4,8 @@ Neighbour lists and CSR layout must match bit for bit; weights and direct
 terms within one FP32 evaluation; propagated radiance and pixels within
 |err| <= max(1e-4 |ref|, 1e-5).
 """
+from dataclasses import replace
+
 import numpy as np
 import pytest
 import torch
@@ -60,6 +62,40 @@ def test_render_variants(init, fg, g_s):
     ref_img, ref = oracle.render(sc, oracle.params(k=8, D=6, g=0.5, g_s=g_s, init=init, final_gather=fg),
                                  trace=True)
     compare_all(sc, 8, img, gr, ref_img, ref, f"{init}/{fg}/{g_s}")
+
+
+EMIT_L = (3.0, 2.0, 1.0)
+
+
+@pytest.mark.parametrize("init,fg,schedule", [("pt", 0, pg.PG_SCHED_TWO_PASS), ("zero", 0, pg.PG_SCHED_SHIFTED),
+                                              ("zero", 1, pg.PG_SCHED_SCATTER), ("pt", 1, pg.PG_SCHED_TWO_PASS)])
+def test_render_with_volume_emission(init, fg, schedule):
+    sc = crop("tiny", 32, 32, 2, emit_L=EMIT_L)
+    assert (sc.l_emit > 0).any()
+    print(f"emission init={init} fg={fg} schedule={schedule} N={sc.n_vertices}", flush=True)
+    img, gr = gpu_render(sc, 8, 6, 0.5, init=init, fg=fg, schedule=schedule)
+    ref_img, ref = oracle.render(sc, oracle.params(k=8, D=6, g=0.5, init=init, final_gather=fg), trace=True)
+    compare_all(sc, 8, img, gr, ref_img, ref, f"emission {init}/{fg}/{schedule}")
+    dark, _ = gpu_render(replace(sc, l_emit=None), 8, 6, 0.5, init=init, fg=fg, schedule=schedule)
+    assert not np.allclose(img, dark)
+
+
+@pytest.mark.parametrize("init", ["pt", "zero"])
+def test_entry_points_compose_with_emission(init):
+    sc = crop("tiny", 24, 24, 2, emit_L=EMIT_L)
+    print(f"compose emission init={init} N={sc.n_vertices}", flush=True)
+    paths = pg.DevicePaths(sc)
+    q = pg.params(k=8, D=5, g=0.5, init=init, flags=pg.PG_FLAG_CHECK)
+    rp, col = pg.pg_knn(paths, 8)
+    e = pg.pg_edges(paths, q, rp, col)
+    lplus = pg.pg_propagate(paths, q, rp, col, e["w_ind"], e["b"], e["lplus0"].clone())
+    img = pg.pg_gather(paths, pg.params(k=8, D=5, g=0.5, init=init), rp, col, e["w_ind"], e["d_pt"], lplus)
+    torch.cuda.synchronize()
+    ref_img, ref = oracle.render(sc, oracle.params(k=8, D=5, g=0.5, init=init), trace=True)
+    assert_within(e["b"].cpu().numpy(), ref["b"], W_REL, W_ABS, "b")
+    assert_within(e["lplus0"].cpu().numpy(), ref["lplus0"], W_REL, W_ABS, "lplus0")
+    assert_within(lplus.cpu().numpy(), ref["lplus"], PIX_REL, PIX_ABS, "lplus")
+    assert_within(img.cpu().numpy(), ref_img, PIX_REL, PIX_ABS, "image")
 
 
 @pytest.mark.parametrize("k", [1, 2, 5, 12, 16, 33, 64])

@@ -6,6 +6,7 @@ dense linear-algebra restatement -- chosen so that a dropped term, a wrong
 sign, index or operand fails at least one of them.
 """
 import math
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -278,14 +279,21 @@ def test_single_neighbour_reduces_to_path_tracing_weights():
 
 # ------------------------------------------------------ whole pipeline ---
 
-def small_scene(w=16, h=16, spp=2, name="tiny"):
-    return scenegen.generate(scenegen.crop_of(scenegen.WORKLOADS[name].scene, w, h, spp))
+EMIT_L = (3.0, 2.0, 1.0)
+
+
+def small_scene(w=16, h=16, spp=2, name="tiny", emit=False):
+    cfg = scenegen.crop_of(scenegen.WORKLOADS[name].scene, w, h, spp)
+    if emit:
+        cfg = replace(cfg, emit_L=EMIT_L)
+    return scenegen.generate(cfg)
 
 
 def path_traced_image(sc, g, g_s, sun_dir, pe=1 / FOUR_PI):
     """Plain volumetric path tracing estimate of each pixel from the records:
-    I = E_cam + sum_m (prod_{u<=m} alpha_u)(prod_{u<m} rho_u/p_u) d_m, with the
-    textbook HG form (written independently of the oracle)."""
+    I = E_cam + sum_m (prod_{u<m} alpha_u rho_u/p_u) (e_m + alpha_m d_m), with
+    the textbook HG form (written independently of the oracle); e_m is the
+    emission collected at the collision (collision estimator)."""
     din, dout, denv = (a.astype(np.float64) for a in (sc.dir_in, sc.dir_out, sc.dir_env))
     sd = np.asarray(sun_dir, np.float64)
     f = lambda gg, a, b: hg_textbook(gg, np.clip((a * b).sum(-1), -1, 1))  # noqa: E731
@@ -298,6 +306,8 @@ def path_traced_image(sc, g, g_s, sun_dir, pe=1 / FOUR_PI):
     for p in range(sc.n_paths):
         L, beta = np.zeros(3), 1.0
         for v in range(off[p], off[p + 1]):
+            if sc.l_emit is not None:
+                L += beta * sc.l_emit[v]
             beta *= sc.albedo[v]
             L += beta * d[v]
             beta *= ratio[v]
@@ -318,6 +328,81 @@ def test_single_neighbour_reproduces_path_tracing(init, D):
     # and the own-sample output (final gather) is the same estimator at K = 1
     p["final_gather"] = 1
     assert np.allclose(oracle.render(sc, p), ref, rtol=2e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("init,D", [("pt", 0), ("pt", 4), ("zero", 12)])
+def test_single_neighbour_with_volume_emission_reproduces_path_tracing(init, D):
+    sc = small_scene(emit=True)
+    assert sc.l_emit is not None and (sc.l_emit > 0).any() and (sc.l_emit == 0).any()
+    g, g_s = 0.5, 0.3
+    p = oracle.params(k=1, D=D, g=g, g_s=g_s, init=init)
+    ref = path_traced_image(sc, g, g_s, p["sun_dir"])
+    assert np.allclose(oracle.render(sc, p), ref, rtol=2e-6, atol=1e-12)
+    p["final_gather"] = 1
+    assert np.allclose(oracle.render(sc, p), ref, rtol=2e-6, atol=1e-12)
+
+
+def test_zero_albedo_sees_first_collision_emission():
+    # no scattering: a pixel averages what its camera rays see directly, the
+    # environment if they escape and the emission of their first collision
+    sc = small_scene(emit=True)
+    sc.albedo[:] = 0.0
+    img = oracle.render(sc, oracle.params(k=8, D=4))
+    first = np.zeros((sc.n_paths, 3))
+    has = np.diff(sc.path_offsets) > 0
+    first[has] = sc.l_emit[sc.path_offsets[:-1][has]]
+    expect = (sc.e_cam + first).reshape(sc.height, sc.width, sc.spp, 3).mean(2)
+    assert np.allclose(img, expect, rtol=1e-15, atol=0)
+
+
+def test_emission_inside_direct_radiance_decomposition():
+    """The paper splits L = L^o + L^+ with the volume emission inside the known
+    direct part L^o: the emission e_u collected at a vertex's successor is a
+    phase-sampled direct sample, aggregated with the indirect weights, and the
+    unknown L^+ starts from zero.  Written with dense operators from an
+    emission-free trace, this must equal the render with l_emit."""
+    sc = small_scene(10, 10, 2, emit=True)
+    D = 7
+    for init in ("zero", "pt"):
+        p = oracle.params(k=6, D=D, g=0.5, init=init)
+        img, tr = oracle.render(sc, p, trace=True)
+        dark = replace(sc, l_emit=None)
+        _, tr0 = oracle.render(dark, p, trace=True)
+        M, c0, W = dense_operator(dark, tr0)
+        N = sc.n_vertices
+        # E_s(v): emission collected at v's successor (0 at a path's end)
+        Es = np.zeros((N, 3))
+        off = sc.path_offsets
+        for q in range(sc.n_paths):
+            Es[off[q]:off[q + 1] - 1] = sc.l_emit[off[q] + 1:off[q + 1]]
+        alpha = sc.albedo.astype(np.float64)[:, None]
+        shift = np.zeros((N, N))
+        for q in range(sc.n_paths):
+            for v in range(off[q], off[q + 1] - 1):
+                shift[v, v + 1] = 1.0
+        # scattered direct L-bar^o = alpha (d_agg + W E_s); L^+_t = M L^+_{t-1} + S L-bar^o
+        c = c0 + shift @ (alpha * (W @ Es))
+        Lp = (tr["lplus0"] - Es) if init == "pt" else np.zeros((N, 3))
+        for _ in range(D):
+            Lp = M @ Lp + c
+        assert np.allclose(tr["lplus"], Es + Lp, rtol=1e-11, atol=1e-13), init
+        first = off[:-1]
+        has = np.diff(off) > 0
+        o = np.zeros((sc.n_paths, 3))
+        o[has] = (sc.l_emit[first[has]]
+                  + alpha[first[has]] * (tr0["d_pt"][first[has]] + (W @ (Es + Lp))[first[has]]))
+        expect = (sc.e_cam + o).reshape(sc.height, sc.width, sc.spp, 3).mean(2)
+        assert np.allclose(img, expect, rtol=1e-11, atol=1e-14), init
+
+
+def test_affine_in_volume_emission():
+    sc = small_scene(12, 12, 2, emit=True)
+    p = oracle.params(k=8, D=6, g=0.5)
+    dark = oracle.render(replace(sc, l_emit=None), p)
+    one = oracle.render(sc, p)
+    two = oracle.render(replace(sc, l_emit=sc.l_emit * np.float32(2.0)), p)
+    assert not np.allclose(one, dark)
+    assert np.allclose(two - one, one - dark, rtol=1e-10, atol=1e-14)
 
 
 def test_zero_albedo_leaves_camera_emission_only():
@@ -392,9 +477,10 @@ def loss_and_grad(sc, p, grid, target):
     return out
 
 
-@pytest.mark.parametrize("init,fg", [("pt", 0), ("zero", 0), ("pt", 1)])
-def test_adjoint_matches_central_differences(init, fg):
-    sc = small_scene(8, 8, 2)
+@pytest.mark.parametrize("init,fg,emit", [("pt", 0, False), ("zero", 0, False), ("pt", 1, False),
+                                           ("pt", 0, True), ("zero", 0, True)])
+def test_adjoint_matches_central_differences(init, fg, emit):
+    sc = small_scene(8, 8, 2, emit=emit)
     rng = np.random.default_rng(5)
     R = 6
     grid = rng.uniform(0.6, 0.95, size=(R, R, R)).astype(np.float32)
