@@ -50,18 +50,19 @@ class _Scene(ctypes.Structure):
                 ("pad_", ctypes.c_int32)] + [
         (name, ctypes.c_void_p) for name in ("path_offsets", "pos", "dir_in", "dir_out", "albedo",
                                              "l_sun", "dir_env", "l_env", "l_phase", "e_cam",
-                                             "l_emit")]
+                                             "l_emit", "cluster_key")]
 
 
 class _Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("D", ctypes.c_int32), ("init", ctypes.c_int32),
-                ("final_gather", ctypes.c_int32), ("g", ctypes.c_double), ("g_s", ctypes.c_double),
+                ("final_gather", ctypes.c_int32), ("neighbours", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("g", ctypes.c_double), ("g_s", ctypes.c_double),
                 ("env_pdf", ctypes.c_double), ("sun_dir", ctypes.c_double * 3)]
 
 
 class _Trace(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in
-                ("col", "w_ind", "w_ph", "w_env", "d_agg", "b", "d_pt", "r", "lplus0", "lplus",
+                ("row_ptr", "col", "w_ind", "w_ph", "w_env", "d_agg", "b", "d_pt", "r", "lplus0", "lplus",
                  "traj", "out_path")]
 
 
@@ -81,6 +82,7 @@ def _load():
         lib.or_hg_dlog.argtypes = [ctypes.c_double, ctypes.c_double]
         lib.or_quantize.argtypes = [i64, vp, vp]
         lib.or_knn.argtypes = [i64, vp, i32, i64, vp, vp]
+        lib.or_clusters.argtypes = [i64, vp, vp, i32, vp]
         lib.or_edges.argtypes = [ctypes.POINTER(_Scene), ctypes.POINTER(_Params), i32, i64, vp, vp,
                                  vp, vp, vp, vp, vp, vp]
         lib.or_albedo_from_grid.argtypes = [i64, vp, i32, vp, vp]
@@ -88,7 +90,7 @@ def _load():
                                   ctypes.POINTER(_Trace)]
         lib.or_backward.argtypes = [ctypes.POINTER(_Scene), ctypes.POINTER(_Params), i32, vp, vp, vp,
                                     vp, vp, vp]
-        for f in ("or_quantize", "or_knn", "or_edges", "or_albedo_from_grid", "or_render", "or_backward"):
+        for f in ("or_quantize", "or_knn", "or_clusters", "or_edges", "or_albedo_from_grid", "or_render", "or_backward"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -135,6 +137,8 @@ class _Bound:
         }
         if getattr(scene, "l_emit", None) is not None:   # volume emission, optional
             self.arrays["l_emit"] = _f32(scene.l_emit, (N, 3))
+        if getattr(scene, "cluster_key", None) is not None:   # cluster neighbour relation
+            self.arrays["cluster_key"] = np.ascontiguousarray(scene.cluster_key, dtype=np.uint32).reshape(N)
         s = _Scene()
         s.n_vertices, s.n_paths = N, P
         s.width, s.height, s.spp = int(scene.width), int(scene.height), int(scene.spp)
@@ -144,14 +148,17 @@ class _Bound:
         self.N, self.P = N, P
 
 
-def params(k=8, D=8, g=0.5, g_s=None, init="pt", final_gather=0, sun_dir=None, env_pdf=None) -> dict:
-    """Method parameters as a plain dict (defaults of the small workload)."""
+def params(k=8, D=8, g=0.5, g_s=None, init="pt", final_gather=0, sun_dir=None, env_pdf=None,
+           neighbours="knn") -> dict:
+    """Method parameters as a plain dict (defaults of the small workload).
+    neighbours: "knn" (k nearest) or "clusters" (the scene's cluster_key
+    chooses the centres, k is the expected cluster size)."""
     if sun_dir is None:
         n = math.sqrt(0.3 ** 2 + 1.0 + 0.4 ** 2)
         sun_dir = (0.3 / n, 1.0 / n, -0.4 / n)
     return {"k": k, "D": D, "g": g, "g_s": g if g_s is None else g_s, "init": init,
             "final_gather": final_gather, "sun_dir": tuple(sun_dir),
-            "env_pdf": 1.0 / (4.0 * math.pi) if env_pdf is None else env_pdf}
+            "env_pdf": 1.0 / (4.0 * math.pi) if env_pdf is None else env_pdf, "neighbours": neighbours}
 
 
 def _params(p: dict) -> _Params:
@@ -159,6 +166,7 @@ def _params(p: dict) -> _Params:
     c.k, c.D = int(p["k"]), int(p["D"])
     c.init = {"pt": 0, "zero": 1}[p.get("init", "pt")]
     c.final_gather = int(p.get("final_gather", 0))
+    c.neighbours = {"knn": 0, "clusters": 1}[p.get("neighbours", "knn")]
     c.g = float(p["g"])
     c.g_s = float(p.get("g_s", p["g"]) if p.get("g_s") is not None else p["g"])
     c.env_pdf = float(p.get("env_pdf", 1.0 / (4.0 * math.pi)))
@@ -207,6 +215,40 @@ def knn(pos, k: int, rows=None) -> np.ndarray:
     return col
 
 
+def clusters(pos, key, k: int) -> np.ndarray:
+    """Centre id [N] of every vertex's cluster (or_clusters): centres where
+    key < 2^32 // k (and the smallest key), nearest centre by (squared
+    quantised distance, id), clusters above 2k members split again."""
+    lib = _load()
+    pos = _f32(pos).reshape(-1, 3)
+    key = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1)
+    n = pos.shape[0]
+    assert key.shape[0] == n
+    out = np.empty(n, np.int32)
+    rc = lib.or_clusters(n, _p(pos), _p(key), int(k), _p(out))
+    if rc not in (0, -4):
+        _check(rc, "clusters")
+    return out
+
+
+def cluster_rows(centre) -> tuple[np.ndarray, np.ndarray]:
+    """CSR of the cluster neighbour relation: row i lists the members of i's
+    cluster in ascending id.  Returns (row_ptr [N+1], col [E])."""
+    centre = np.asarray(centre)
+    n = centre.shape[0]
+    order = np.lexsort((np.arange(n), centre))
+    size = np.bincount(centre, minlength=n) if n else np.zeros(0, np.int64)
+    start = np.zeros(n + 1, np.int64)
+    start[1:] = np.cumsum(size)
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum(size[centre]) if n else []
+    col = np.empty(int(rp[-1]), np.int32)
+    for i in range(n):
+        c = centre[i]
+        col[rp[i]:rp[i + 1]] = order[start[c]:start[c + 1]]
+    return rp, col
+
+
 def albedo_from_grid(pos, grid) -> np.ndarray:
     """Per-vertex albedo: cell-centred trilinear interpolation of grid [R,R,R] (z,y,x)."""
     lib = _load()
@@ -246,8 +288,13 @@ def render(scene, p: dict, alpha=None, trace: bool = False, traj: bool = False):
     out = None
     tr = None
     if trace:
-        out = {"col": np.empty((N, K), np.int32), "w_ind": np.empty((N, K)), "w_ph": np.empty((N, K)),
-               "w_env": np.empty((N, K)), "d_agg": np.empty((N, 3)), "b": np.empty((N, 3)),
+        if p.get("neighbours", "knn") == "clusters":
+            E = int(cluster_rows(clusters(scene.pos, scene.cluster_key, p["k"]))[0][-1]) if N else 0
+            shape = (E,)
+        else:
+            shape = (N, K)
+        out = {"row_ptr": np.empty(N + 1, np.int64), "col": np.empty(shape, np.int32), "w_ind": np.empty(shape),
+               "w_ph": np.empty(shape), "w_env": np.empty(shape), "d_agg": np.empty((N, 3)), "b": np.empty((N, 3)),
                "d_pt": np.empty((N, 3)), "r": np.empty(N), "lplus0": np.empty((N, 3)),
                "lplus": np.empty((N, 3)), "out_path": np.empty((P, 3))}
         if traj:

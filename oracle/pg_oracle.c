@@ -78,6 +78,7 @@ typedef struct or_scene {
     const float* l_phase;          /* [N][3] */
     const float* e_cam;            /* [P][3] */
     const float* l_emit;           /* [N][3] or NULL: volume emission at the vertex */
+    const uint32_t* cluster_key;   /* [N] uniform random keys (cluster neighbour relation) */
 } or_scene;
 
 typedef struct or_params {
@@ -85,6 +86,8 @@ typedef struct or_params {
     int32_t D;            /* propagation iterations */
     int32_t init;         /* 0: path-traced initial estimate, 1: zero */
     int32_t final_gather; /* 0: aggregate at the first vertex, 1: own sample only */
+    int32_t neighbours;   /* 0: k nearest neighbours, 1: clusters (or_clusters) */
+    int32_t pad_;
     double g;             /* HG parameter of the receiver's phase function */
     double g_s;           /* HG parameter of the sampling pdfs */
     double env_pdf;       /* solid-angle pdf of environment sampling (1/(4 pi)) */
@@ -93,10 +96,11 @@ typedef struct or_params {
 
 /* Optional intermediate outputs of or_render (any pointer may be NULL). */
 typedef struct or_trace {
-    int32_t* col;      /* [N*K] neighbour lists */
-    double* w_ind;     /* [N*K] indirect weights */
-    double* w_ph;      /* [N*K] direct, phase-sampled weights */
-    double* w_env;     /* [N*K] direct, emitter-sampled weights */
+    int64_t* row_ptr;  /* [N+1] rows of the neighbour lists (i*K for kNN) */
+    int32_t* col;      /* [E] neighbour lists, E = row_ptr[N] */
+    double* w_ind;     /* [E] indirect weights */
+    double* w_ph;      /* [E] direct, phase-sampled weights */
+    double* w_env;     /* [E] direct, emitter-sampled weights */
     double* d_agg;     /* [N][3] aggregated direct */
     double* b;         /* [N][3] albedo * aggregated direct */
     double* d_pt;      /* [N][3] path-traced direct */
@@ -234,6 +238,116 @@ int or_knn(int64_t n, const float* pos, int32_t k, int64_t nq, const int64_t* ro
     return rc;
 }
 
+/* ---------------------------------------------------------- clusters */
+
+#define OR_CLUSTER_ROUNDS 4
+
+static int64_t qdist2(const int64_t* q, int64_t a, int64_t b) {
+    int64_t d2 = 0;
+    for (int c = 0; c < 3; ++c) {
+        int64_t d = q[a * 3 + c] - q[b * 3 + c];
+        d2 += d * d;
+    }
+    return d2;
+}
+
+static const uint32_t* g_sort_key;   /* used only by the qsort comparators */
+static const int32_t* g_sort_centre;
+static int cmp_by_key(const void* pa, const void* pb) {
+    int64_t a = *(const int64_t*)pa, b = *(const int64_t*)pb;
+    uint32_t ka = g_sort_key[a], kb = g_sort_key[b];
+    if (ka != kb) return ka < kb ? -1 : 1;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+static int cmp_by_centre(const void* pa, const void* pb) {
+    int64_t a = *(const int64_t*)pa, b = *(const int64_t*)pb;
+    int32_t ca = g_sort_centre[a], cb = g_sort_centre[b];
+    if (ca != cb) return ca < cb ? -1 : 1;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* The paper's neighbour relation (Sec. "Path Graph Framework"; Sec.
+ * "Rendering System", path graph solver): disjoint clusters around randomly
+ * chosen centres, large clusters split again.  Readings:
+ *   - the random choice is a uniform 32-bit key per vertex, an input; vertex
+ *     i is a centre when key_i < floor(2^32 / K), so each vertex is one with
+ *     probability 1/K and there are about N/K centres; the vertex with the
+ *     smallest (key, id) always is one;
+ *   - every vertex joins the nearest centre, nearest by (squared distance of
+ *     the quantised positions, centre id);
+ *   - a cluster is large when it has more than 2K members.  A large cluster
+ *     of s members takes its ceil(s/K) members of smallest (key, id) as new
+ *     centres and each of its members joins the nearest of those, as above.
+ *     This repeats, for the clusters still large, up to OR_CLUSTER_ROUNDS
+ *     rounds.
+ * centre[i] receives the id of the centre of i's cluster. */
+int or_clusters(int64_t n, const float* pos, const uint32_t* key, int32_t K, int32_t* centre) {
+    if (n < 0 || K < 1 || (n > 0 && (!pos || !key || !centre))) return OR_ERR_ARG;
+    if (n == 0) return OR_OK;
+    int64_t* q = (int64_t*)malloc((size_t)n * 3 * sizeof(int64_t));
+    int64_t* ctr = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    int64_t* order = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    int64_t* mem = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    if (!q || !ctr || !order || !mem) {
+        free(q); free(ctr); free(order); free(mem);
+        return OR_ERR_NOMEM;
+    }
+    int rc = or_quantize(n, pos, q);
+    const uint64_t thr = ((uint64_t)1 << 32) / (uint64_t)K;
+    int64_t first = 0;
+    for (int64_t i = 1; i < n; ++i)
+        if (key[i] < key[first]) first = i;
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if ((uint64_t)key[i] < thr || i == first) ctr[m++] = i;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t best = -1, bd = 0;
+        for (int64_t c = 0; c < m; ++c) {
+            int64_t d2 = qdist2(q, i, ctr[c]);
+            if (best < 0 || key_less(d2, ctr[c], bd, best)) {
+                bd = d2;
+                best = ctr[c];
+            }
+        }
+        centre[i] = (int32_t)best;
+    }
+    for (int round = 0; round < OR_CLUSTER_ROUNDS; ++round) {
+        /* group by centre: order[] lists the vertices by (centre, id) */
+        for (int64_t i = 0; i < n; ++i) order[i] = i;
+        g_sort_centre = centre;
+        qsort(order, (size_t)n, sizeof(int64_t), cmp_by_centre);
+        int split = 0;
+        for (int64_t a = 0; a < n;) {
+            int64_t e = a;
+            while (e < n && centre[order[e]] == centre[order[a]]) ++e;
+            int64_t sz = e - a;
+            if (sz > 2 * (int64_t)K) {
+                split = 1;
+                for (int64_t t = 0; t < sz; ++t) mem[t] = order[a + t];
+                g_sort_key = key;
+                qsort(mem, (size_t)sz, sizeof(int64_t), cmp_by_key);
+                int64_t nc = (sz + K - 1) / K;
+                /* mem[0..nc) are the new centres; assign every member */
+                for (int64_t t = 0; t < sz; ++t) {
+                    int64_t i = mem[t], best = -1, bd = 0;
+                    for (int64_t c = 0; c < nc; ++c) {
+                        int64_t d2 = qdist2(q, i, mem[c]);
+                        if (best < 0 || key_less(d2, mem[c], bd, best)) {
+                            bd = d2;
+                            best = mem[c];
+                        }
+                    }
+                    centre[i] = (int32_t)best;
+                }
+            }
+            a = e;
+        }
+        if (!split) break;
+    }
+    free(q); free(ctr); free(order); free(mem);
+    return rc;
+}
+
 /* ---------------------------------------------------------- edge weights */
 
 /* Per receiver i with neighbour list nb[0..K-1] (nb[0] == i):
@@ -350,8 +464,9 @@ static double emit(const or_scene* s, int64_t i, int c) {
 }
 
 typedef struct {
-    int64_t N, P, K;
+    int64_t N, P, K, E;
     int keep;       /* 1: traj holds every iterate t = 0..D; 0: three rotating slots */
+    int64_t* rp;    /* [N+1] row i = edges rp[i] .. rp[i+1]-1 */
     int32_t* col;
     double *wi, *wp, *we, *dagg, *b, *dpt, *r, *alpha;
     double* traj;   /* (D+1) * N * 3 when keep, else 3 * N * 3 */
@@ -365,7 +480,7 @@ static double* iterate(const fwd_state* f, int t, int D) {
 }
 
 static void free_state(fwd_state* f) {
-    free(f->col); free(f->wi); free(f->wp); free(f->we); free(f->dagg); free(f->b);
+    free(f->rp); free(f->col); free(f->wi); free(f->wp); free(f->we); free(f->dagg); free(f->b);
     free(f->dpt); free(f->r); free(f->alpha); free(f->traj);
     memset(f, 0, sizeof(*f));
 }
@@ -375,6 +490,8 @@ static int validate(const or_scene* s, const or_params* p) {
     if (s->width < 1 || s->height < 1 || s->spp < 1) return OR_ERR_ARG;
     if ((int64_t)s->width * s->height * s->spp != s->n_paths) return OR_ERR_ARG;
     if (!(fabs(p->g) < 1.0) || !(fabs(p->g_s) < 1.0) || !(p->env_pdf > 0.0)) return OR_ERR_ARG;
+    if (p->neighbours != 0 && p->neighbours != 1) return OR_ERR_ARG;
+    if (p->neighbours == 1 && s->n_vertices > 0 && !s->cluster_key) return OR_ERR_ARG;
     if (s->path_offsets[0] != 0 || s->path_offsets[s->n_paths] != s->n_vertices) return OR_ERR_ARG;
     for (int64_t q = 0; q < s->n_paths; ++q)
         if (s->path_offsets[q + 1] < s->path_offsets[q]) return OR_ERR_ARG;
@@ -392,8 +509,43 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
     const int D = p->D;
     memset(f, 0, sizeof(*f));
     f->N = N; f->P = P; f->K = K; f->keep = keep;
-    size_t nE = (size_t)(N * K > 0 ? N * K : 1), n3 = (size_t)(N > 0 ? N * 3 : 1);
-    f->col = (int32_t*)malloc(nE * sizeof(int32_t));
+    size_t n3 = (size_t)(N > 0 ? N * 3 : 1);
+
+    /* steps 1-2: neighbour sets as rows of a CSR (row i: i's neighbours) */
+    f->rp = (int64_t*)malloc((size_t)(N + 1) * sizeof(int64_t));
+    if (!f->rp) { free_state(f); return OR_ERR_NOMEM; }
+    f->rp[0] = 0;
+    if (p->neighbours == 0) {
+        for (int64_t i = 0; i < N; ++i) f->rp[i + 1] = (i + 1) * K;
+        f->col = (int32_t*)malloc((size_t)(N * K > 0 ? N * K : 1) * sizeof(int32_t));
+        if (!f->col) { free_state(f); return OR_ERR_NOMEM; }
+        if (N > 0 && (rc = or_knn(N, s->pos, p->k, N, NULL, f->col))) { free_state(f); return rc; }
+    } else {
+        /* clusters: row i lists the members of i's cluster, ids ascending */
+        int32_t* ctr = (int32_t*)malloc((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
+        int64_t* order = (int64_t*)malloc((size_t)(N > 0 ? N : 1) * sizeof(int64_t));
+        int64_t* size = (int64_t*)calloc((size_t)(N > 0 ? N : 1), sizeof(int64_t));
+        int64_t* first = (int64_t*)malloc((size_t)(N > 0 ? N : 1) * sizeof(int64_t));
+        if (!ctr || !order || !size || !first) {
+            free(ctr); free(order); free(size); free(first); free_state(f);
+            return OR_ERR_NOMEM;
+        }
+        rc = or_clusters(N, s->pos, s->cluster_key, p->k, ctr);
+        if (rc) { free(ctr); free(order); free(size); free(first); free_state(f); return rc; }
+        for (int64_t i = 0; i < N; ++i) order[i] = i;
+        g_sort_centre = ctr;
+        qsort(order, (size_t)N, sizeof(int64_t), cmp_by_centre);
+        for (int64_t i = 0; i < N; ++i) ++size[ctr[i]];
+        for (int64_t t = N - 1; t >= 0; --t) first[ctr[order[t]]] = t;   /* members start in order[] */
+        for (int64_t i = 0; i < N; ++i) f->rp[i + 1] = f->rp[i] + size[ctr[i]];
+        f->col = (int32_t*)malloc((size_t)(f->rp[N] > 0 ? f->rp[N] : 1) * sizeof(int32_t));
+        if (!f->col) { free(ctr); free(order); free(size); free(first); free_state(f); return OR_ERR_NOMEM; }
+        for (int64_t i = 0; i < N; ++i)
+            for (int64_t a = 0; a < size[ctr[i]]; ++a) f->col[f->rp[i] + a] = (int32_t)order[first[ctr[i]] + a];
+        free(ctr); free(order); free(size); free(first);
+    }
+    f->E = f->rp[N];
+    size_t nE = (size_t)(f->E > 0 ? f->E : 1);
     f->wi = (double*)malloc(nE * sizeof(double));
     f->wp = (double*)malloc(nE * sizeof(double));
     f->we = (double*)malloc(nE * sizeof(double));
@@ -403,20 +555,16 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
     f->r = (double*)malloc((N > 0 ? N : 1) * sizeof(double));
     f->alpha = (double*)malloc((N > 0 ? N : 1) * sizeof(double));
     f->traj = (double*)calloc((size_t)(keep ? D + 1 : 3) * n3, sizeof(double));
-    if (!f->col || !f->wi || !f->wp || !f->we || !f->dagg || !f->b || !f->dpt || !f->r || !f->alpha || !f->traj) {
+    if (!f->wi || !f->wp || !f->we || !f->dagg || !f->b || !f->dpt || !f->r || !f->alpha || !f->traj) {
         free_state(f);
         return OR_ERR_NOMEM;
     }
     for (int64_t i = 0; i < N; ++i) f->alpha[i] = alpha_override ? alpha_override[i] : (double)s->albedo[i];
 
-    /* steps 1-2: neighbour sets */
-    if (N > 0) {
-        rc = or_knn(N, s->pos, p->k, N, NULL, f->col);
-        if (rc) { free_state(f); return rc; }
-    }
     /* steps 3-4: weights, direct terms, b = alpha * d_agg */
     for (int64_t i = 0; i < N; ++i) {
-        receiver_weights(s, p, i, f->col + i * K, K, f->wi + i * K, f->wp + i * K, f->we + i * K, f->dagg + i * 3);
+        const int64_t e0 = f->rp[i], ki = f->rp[i + 1] - e0;
+        receiver_weights(s, p, i, f->col + e0, ki, f->wi + e0, f->wp + e0, f->we + e0, f->dagg + i * 3);
         own_direct(s, p, i, f->dpt + i * 3, f->r + i);
         for (int c = 0; c < 3; ++c)
             f->b[i * 3 + c] = emit(s, i, c) + f->alpha[i] * f->dagg[i * 3 + c];
@@ -447,9 +595,9 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
         double* Ln = iterate(f, t, D);
         for (int64_t i = 0; i < N; ++i) {
             double z[3] = {0.0, 0.0, 0.0};
-            for (int64_t a = 0; a < K; ++a) {
-                int64_t j = f->col[i * K + a];
-                for (int c = 0; c < 3; ++c) z[c] += f->wi[i * K + a] * Lp[j * 3 + c];
+            for (int64_t a = f->rp[i]; a < f->rp[i + 1]; ++a) {
+                int64_t j = f->col[a];
+                for (int c = 0; c < 3; ++c) z[c] += f->wi[a] * Lp[j * 3 + c];
             }
             for (int c = 0; c < 3; ++c) y[i * 3 + c] = f->b[i * 3 + c] + f->alpha[i] * z[c];
         }
@@ -472,9 +620,9 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
         if (s->path_offsets[q + 1] > v0) {
             double in[3] = {0.0, 0.0, 0.0};
             if (p->final_gather == 0) {
-                for (int64_t a = 0; a < K; ++a) {
-                    int64_t j = f->col[v0 * K + a];
-                    for (int c = 0; c < 3; ++c) in[c] += f->wi[v0 * K + a] * LD[j * 3 + c];
+                for (int64_t a = f->rp[v0]; a < f->rp[v0 + 1]; ++a) {
+                    int64_t j = f->col[a];
+                    for (int c = 0; c < 3; ++c) in[c] += f->wi[a] * LD[j * 3 + c];
                 }
             } else {
                 for (int c = 0; c < 3; ++c) in[c] = f->r[v0] * LD[v0 * 3 + c];
@@ -496,11 +644,12 @@ int or_render(const or_scene* s, const or_params* p, const double* alpha_overrid
     int rc = forward(s, p, alpha_override, tr && tr->traj ? 1 : 0, &f, image, tr ? tr->out_path : NULL);
     if (rc) return rc;
     if (tr) {
-        const int64_t N = f.N, K = f.K;
-        if (tr->col) memcpy(tr->col, f.col, (size_t)(N * K) * sizeof(int32_t));
-        if (tr->w_ind) memcpy(tr->w_ind, f.wi, (size_t)(N * K) * sizeof(double));
-        if (tr->w_ph) memcpy(tr->w_ph, f.wp, (size_t)(N * K) * sizeof(double));
-        if (tr->w_env) memcpy(tr->w_env, f.we, (size_t)(N * K) * sizeof(double));
+        const int64_t N = f.N, E = f.E;
+        if (tr->row_ptr) memcpy(tr->row_ptr, f.rp, (size_t)(N + 1) * sizeof(int64_t));
+        if (tr->col) memcpy(tr->col, f.col, (size_t)E * sizeof(int32_t));
+        if (tr->w_ind) memcpy(tr->w_ind, f.wi, (size_t)E * sizeof(double));
+        if (tr->w_ph) memcpy(tr->w_ph, f.wp, (size_t)E * sizeof(double));
+        if (tr->w_env) memcpy(tr->w_env, f.we, (size_t)E * sizeof(double));
         if (tr->d_agg) memcpy(tr->d_agg, f.dagg, (size_t)(N * 3) * sizeof(double));
         if (tr->b) memcpy(tr->b, f.b, (size_t)(N * 3) * sizeof(double));
         if (tr->d_pt) memcpy(tr->d_pt, f.dpt, (size_t)(N * 3) * sizeof(double));
@@ -537,7 +686,8 @@ int or_backward(const or_scene* s, const or_params* p, int32_t R, const float* g
     fwd_state f;
     int rc = forward(s, p, alpha, 1, &f, image, NULL);
     if (rc) { free(alpha); return rc; }
-    const int64_t P = s->n_paths, K = f.K;
+    const int64_t P = s->n_paths;
+    const int64_t* rp = f.rp;
     const int D = p->D;
     size_t n3 = (size_t)(N > 0 ? N * 3 : 1);
     double* abar = (double*)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
@@ -546,7 +696,7 @@ int or_backward(const or_scene* s, const or_params* p, int32_t R, const float* g
     double* bbar = (double*)calloc(n3, sizeof(double));
     double* lam = (double*)calloc(n3, sizeof(double));     /* adjoint of L+_t */
     double* lam2 = (double*)calloc(n3, sizeof(double));
-    double* wbar = (double*)calloc((size_t)(N * K > 0 ? N * K : 1), sizeof(double));
+    double* wbar = (double*)calloc((size_t)(f.E > 0 ? f.E : 1), sizeof(double));
     if (!abar || !dptbar || !rbar || !bbar || !lam || !lam2 || !wbar) {
         free(abar); free(dptbar); free(rbar); free(bbar); free(lam); free(lam2); free(wbar);
         free_state(&f); free(alpha);
@@ -563,9 +713,9 @@ int or_backward(const or_scene* s, const or_params* p, int32_t R, const float* g
         for (int c = 0; c < 3; ++c) ob[c] = grad_image[px * 3 + c] / (double)s->spp;
         double in[3] = {0.0, 0.0, 0.0};
         if (p->final_gather == 0) {
-            for (int64_t a = 0; a < K; ++a) {
-                int64_t j = f.col[v0 * K + a];
-                for (int c = 0; c < 3; ++c) in[c] += f.wi[v0 * K + a] * LD[j * 3 + c];
+            for (int64_t a = rp[v0]; a < rp[v0 + 1]; ++a) {
+                int64_t j = f.col[a];
+                for (int c = 0; c < 3; ++c) in[c] += f.wi[a] * LD[j * 3 + c];
             }
         } else {
             for (int c = 0; c < 3; ++c) in[c] = f.r[v0] * LD[v0 * 3 + c];
@@ -575,12 +725,12 @@ int or_backward(const or_scene* s, const or_params* p, int32_t R, const float* g
             dptbar[v0 * 3 + c] += f.alpha[v0] * ob[c];
         }
         if (p->final_gather == 0) {
-            for (int64_t a = 0; a < K; ++a) {
-                int64_t j = f.col[v0 * K + a];
+            for (int64_t a = rp[v0]; a < rp[v0 + 1]; ++a) {
+                int64_t j = f.col[a];
                 for (int c = 0; c < 3; ++c) {
                     double zb = f.alpha[v0] * ob[c];
-                    lam[j * 3 + c] += f.wi[v0 * K + a] * zb;
-                    wbar[v0 * K + a] += zb * LD[j * 3 + c];
+                    lam[j * 3 + c] += f.wi[a] * zb;
+                    wbar[a] += zb * LD[j * 3 + c];
                 }
             }
         } else {
@@ -606,20 +756,20 @@ int or_backward(const or_scene* s, const or_params* p, int32_t R, const float* g
         for (size_t e = 0; e < n3; ++e) lam2[e] = 0.0;
         for (int64_t i = 0; i < N; ++i) {
             double z[3] = {0.0, 0.0, 0.0};
-            for (int64_t a = 0; a < K; ++a) {
-                int64_t j = f.col[i * K + a];
-                for (int c = 0; c < 3; ++c) z[c] += f.wi[i * K + a] * Lp[j * 3 + c];
+            for (int64_t a = rp[i]; a < rp[i + 1]; ++a) {
+                int64_t j = f.col[a];
+                for (int c = 0; c < 3; ++c) z[c] += f.wi[a] * Lp[j * 3 + c];
             }
             for (int c = 0; c < 3; ++c) {
                 bbar[i * 3 + c] += ybar[i * 3 + c];
                 abar[i] += ybar[i * 3 + c] * z[c];
             }
-            for (int64_t a = 0; a < K; ++a) {
-                int64_t j = f.col[i * K + a];
+            for (int64_t a = rp[i]; a < rp[i + 1]; ++a) {
+                int64_t j = f.col[a];
                 for (int c = 0; c < 3; ++c) {
                     double zb = f.alpha[i] * ybar[i * 3 + c];
-                    lam2[j * 3 + c] += f.wi[i * K + a] * zb;
-                    wbar[i * K + a] += zb * Lp[j * 3 + c];
+                    lam2[j * 3 + c] += f.wi[a] * zb;
+                    wbar[a] += zb * Lp[j * 3 + c];
                 }
             }
         }
@@ -654,20 +804,20 @@ int or_backward(const or_scene* s, const or_params* p, int32_t R, const float* g
         }
         /* d/dg of rho_i(w) is rho_i(w) h(u); pdfs do not depend on g */
         double sum_ls[3] = {0.0, 0.0, 0.0};
-        for (int64_t a = 0; a < K; ++a) {
-            int64_t j = f.col[i * K + a];
+        for (int64_t a = rp[i]; a < rp[i + 1]; ++a) {
+            int64_t j = f.col[a];
             double h_out = or_hg_dlog(p->g, one_minus_cos(ti, s->dir_out + j * 3));
             double h_env = or_hg_dlog(p->g, one_minus_cos(ti, s->dir_env + j * 3));
-            gg += wbar[i * K + a] * f.wi[i * K + a] * h_out;
+            gg += wbar[a] * f.wi[a] * h_out;
             for (int c = 0; c < 3; ++c) {
-                gg += daggbar[c] * (f.we[i * K + a] * h_env * s->l_env[j * 3 + c] +
-                                    f.wp[i * K + a] * h_out * s->l_phase[j * 3 + c]);
+                gg += daggbar[c] * (f.we[a] * h_env * s->l_env[j * 3 + c] +
+                                    f.wp[a] * h_out * s->l_phase[j * 3 + c]);
                 sum_ls[c] += s->l_sun[j * 3 + c];
             }
         }
         double u_sun = one_minus_cos_d(ti, p->sun_dir);
         double rho_sun = or_hg(p->g, u_sun), h_sun = or_hg_dlog(p->g, u_sun);
-        for (int c = 0; c < 3; ++c) gg += daggbar[c] * rho_sun * h_sun * sum_ls[c] / (double)K;
+        for (int c = 0; c < 3; ++c) gg += daggbar[c] * rho_sun * h_sun * sum_ls[c] / (double)(rp[i + 1] - rp[i]);
         /* own direct term and continuation ratio */
         double u_env = one_minus_cos(ti, s->dir_env + i * 3);
         double u_out = one_minus_cos(ti, s->dir_out + i * 3);

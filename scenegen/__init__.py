@@ -166,6 +166,7 @@ class Scene:
     e_cam: np.ndarray
     config: SceneConfig | None = None
     l_emit: np.ndarray | None = None
+    cluster_key: np.ndarray | None = None   # uint32 [N], see cluster_keys
     sun_dir: tuple = SUN_DIR
     env_pdf: float = 1.0 / (4.0 * math.pi)
 
@@ -239,6 +240,13 @@ def density(cfg: SceneConfig) -> tuple[np.ndarray, float]:
     finally:
         lib.sg_release(h)
     return out, maj
+
+
+def cluster_keys(n: int, seed: int = 7) -> np.ndarray:
+    """Seeded uniform 32-bit keys [n]: the random draw that picks the cluster
+    centres of the cluster neighbour relation."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 2 ** 32, size=n, dtype=np.uint32)
 
 
 def albedo_grid(res: int = 64, lo: float = 0.95, hi: float = 0.999, seed: int = 2) -> np.ndarray:

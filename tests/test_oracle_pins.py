@@ -425,9 +425,9 @@ def test_linear_in_light_radiance():
 def dense_operator(sc, tr):
     """M = S diag(alpha) W and c = S b as dense matrices (S: shift to predecessor)."""
     N = sc.n_vertices
-    K = tr["col"].shape[1]
+    rows = np.repeat(np.arange(N), np.diff(tr["row_ptr"]))
     W = np.zeros((N, N))
-    np.add.at(W, (np.repeat(np.arange(N), K), tr["col"].ravel()), tr["w_ind"].ravel())
+    np.add.at(W, (rows, tr["col"].ravel()), tr["w_ind"].ravel())
     A = sc.albedo.astype(np.float64)[:, None] * W
     S = np.zeros((N, N))
     off = sc.path_offsets
@@ -467,6 +467,163 @@ def test_iteration_converges_to_linear_solve():
     assert max(abs(np.linalg.eigvals(M))) < 0.95
     Lstar = np.linalg.solve(np.eye(len(c)) - M, c)
     assert np.allclose(tr["lplus"], Lstar, rtol=1e-9, atol=1e-12)
+
+
+# ------------------------------------------------ cluster neighbours ---
+
+def keyed(sc, seed=7):
+    return replace(sc, cluster_key=scenegen.cluster_keys(sc.n_vertices, seed))
+
+
+def test_cluster_centres_and_nearest_assignment():
+    # K = 64 on 3000 uniform points: the ~47 initial clusters average 64
+    # members, under 2K, so nothing is split and every vertex's centre is the
+    # nearest centre -- checked with scipy's kd-tree on the quantised positions
+    rng = np.random.default_rng(3)
+    pos = rng.random((3000, 3), dtype=np.float32)
+    key = scenegen.cluster_keys(3000, 5)
+    K = 64
+    ctr = oracle.clusters(pos, key, K)
+    is_c = (key.astype(np.uint64) < (2 ** 32) // K)
+    is_c[np.argmin(key)] = True
+    centres = np.flatnonzero(is_c)
+    assert set(np.unique(ctr)) <= set(centres)
+    sizes = np.bincount(ctr, minlength=3000)[centres]
+    if sizes.max() <= 2 * K:
+        q, _ = oracle.quantize(pos)
+        _, nn = spatial.cKDTree(q[centres].astype(np.float64)).query(q.astype(np.float64))
+        assert np.array_equal(ctr, centres[nn])
+    else:
+        pytest.fail("seed gives a large cluster; pick another")
+    assert np.array_equal(ctr[centres], centres)      # a centre is in its own cluster
+    # about N/K centres: binomial(3000, 1/64) within 5 sigma
+    assert abs(len(centres) - 3000 / K) < 5 * math.sqrt(3000 / K)
+
+
+def test_cluster_split_refines_and_evens_out():
+    # clustered input: one dense blob gets few centres' worth of points, so
+    # large clusters appear and are split; the result refines the initial
+    # nearest-centre partition and leaves no cluster above 2K
+    rng = np.random.default_rng(9)
+    pos = np.concatenate([rng.random((2000, 3)) * 0.05 + 0.5, rng.random((2000, 3))]).astype(np.float32)
+    key = scenegen.cluster_keys(4000, 11)
+    K = 8
+    ctr = oracle.clusters(pos, key, K)
+    is_c = key.astype(np.uint64) < (2 ** 32) // K
+    is_c[np.argmin(key)] = True
+    centres = np.flatnonzero(is_c)
+    q, _ = oracle.quantize(pos)
+    _, nn = spatial.cKDTree(q[centres].astype(np.float64)).query(q.astype(np.float64))
+    init = centres[nn]
+    big = np.bincount(init, minlength=4000).max()
+    assert big > 2 * K                                   # the split is exercised
+    # refinement: members of a final cluster share their initial cluster
+    for c in np.unique(ctr):
+        assert len(np.unique(init[ctr == c])) == 1
+    assert np.bincount(ctr, minlength=4000).max() <= 2 * K
+    # relabelling invariance (distinct keys, generic positions)
+    perm = rng.permutation(4000)
+    ctr_p = oracle.clusters(pos[perm], key[perm], K)
+    assert np.array_equal(perm[ctr_p], ctr[perm])
+
+
+def test_cluster_weights_equal_knn_weights_on_separated_groups():
+    # groups of K coincident points, far apart, one centre each: the cluster
+    # of a vertex is exactly its k nearest set, so the cluster relation must
+    # give the kNN relation's (pinned) weights and direct terms, row by row
+    rng = np.random.default_rng(4)
+    K, trials = 6, 40
+    sc, _, _ = clustered(rng, trials, K, 0.4, lambda d: np.repeat((d[:, 2:3] + 2.0), 3, axis=1))
+    key = np.full(sc.n_vertices, 2 ** 32 - 1, np.uint32)
+    key[::K] = np.arange(trials, dtype=np.uint32)         # the first of each group is its centre
+    sc = replace(sc, cluster_key=key)
+    assert np.array_equal(oracle.clusters(sc.pos, key, K), np.repeat(np.arange(0, trials * K, K), K))
+    pk = oracle.params(k=K, D=3, g=0.6, g_s=0.4)
+    pc = dict(pk, neighbours="clusters")
+    img_k, tk = oracle.render(sc, pk, trace=True)
+    img_c, tc = oracle.render(sc, pc, trace=True)
+    assert np.array_equal(tc["row_ptr"], np.arange(sc.n_vertices + 1) * K)
+    for i in range(sc.n_vertices):
+        a, b = tc["row_ptr"][i], tc["row_ptr"][i + 1]
+        order_k = np.argsort(tk["col"][i])
+        assert np.array_equal(tc["col"][a:b], tk["col"][i][order_k])
+        for name in ("w_ind", "w_ph", "w_env"):
+            assert np.allclose(tc[name][a:b], tk[name][i][order_k], rtol=1e-13, atol=0)
+    for name in ("b", "d_pt", "lplus"):
+        assert np.allclose(tc[name], tk[name], rtol=1e-12, atol=1e-15)
+    assert np.allclose(img_c, img_k, rtol=1e-12, atol=1e-15)
+
+
+def test_cluster_rows_share_one_marginal():
+    # every receiver of a cluster combines the same techniques, so for a
+    # sample j the weight w+_ij times rho_i(w_j)^-1 (textbook HG) is the same
+    # for all receivers i of the cluster: 1 / sum_l p_l(w_j)
+    sc = keyed(small_scene(10, 10, 2))
+    g, g_s = 0.5, 0.3
+    p = oracle.params(k=8, D=2, g=g, g_s=g_s, neighbours="clusters")
+    _, tr = oracle.render(sc, p, trace=True)
+    rp, col = tr["row_ptr"], tr["col"]
+    ctr = oracle.clusters(sc.pos, sc.cluster_key, 8)
+    assert np.array_equal((rp, col)[1], oracle.cluster_rows(ctr)[1])
+    din, dout = sc.dir_in.astype(np.float64), sc.dir_out.astype(np.float64)
+    inv_m = {}
+    for i in range(sc.n_vertices):
+        js = col[rp[i]:rp[i + 1]]
+        assert i in js and np.all(np.diff(js) > 0)
+        rho = hg_textbook(g, np.clip((din[i] * dout[js]).sum(1), -1, 1))
+        for j, v in zip(js, tr["w_ind"][rp[i]:rp[i + 1]] / rho):
+            if j in inv_m:
+                assert abs(v - inv_m[j]) <= 1e-6 * inv_m[j]
+            else:
+                inv_m[j] = v
+    for j, v in inv_m.items():
+        members = col[rp[j]:rp[j + 1]]
+        m = hg_textbook(g_s, np.clip((din[members] * dout[j]).sum(1), -1, 1)).sum()
+        assert abs(v * m - 1.0) <= 1e-6
+
+
+@pytest.mark.parametrize("init", ["pt", "zero"])
+def test_cluster_single_member_reproduces_path_tracing(init):
+    # k = 1: every key is below 2^32, every vertex is its own cluster
+    sc = keyed(small_scene())
+    g, g_s = 0.5, 0.3
+    p = oracle.params(k=1, D=12, g=g, g_s=g_s, init=init, neighbours="clusters")
+    ref = path_traced_image(sc, g, g_s, p["sun_dir"])
+    assert np.allclose(oracle.render(sc, p), ref, rtol=2e-6, atol=1e-12)
+
+
+def test_cluster_iteration_is_truncated_neumann_series():
+    sc = keyed(small_scene(12, 12, 2))
+    D = 8
+    p = oracle.params(k=6, D=D, g=0.5, init="zero", neighbours="clusters")
+    img, tr = oracle.render(sc, p, trace=True)
+    M, c, W = dense_operator(sc, tr)
+    # block structure: W's pattern is symmetric
+    assert np.array_equal(W != 0, (W != 0).T)
+    L = sum(np.linalg.matrix_power(M, t) @ c for t in range(D))
+    assert np.allclose(tr["lplus"], L, rtol=1e-12, atol=1e-14)
+
+
+def test_cluster_adjoint_matches_central_differences():
+    sc = keyed(small_scene(8, 8, 2))
+    rng = np.random.default_rng(6)
+    p = oracle.params(k=6, D=4, g=0.6, g_s=0.6, neighbours="clusters")
+    alpha = rng.uniform(0.6, 0.95, sc.n_vertices)
+    img = oracle.render(sc, p, alpha=alpha)
+    target = rng.uniform(0, 2 * img.mean(), size=img.shape)
+    sc2 = replace(sc, albedo=alpha.astype(np.float32))
+    alpha = sc2.albedo.astype(np.float64)
+    img = oracle.render(sc2, p)
+    out = oracle.backward(sc2, p, 2.0 * (img - target))
+    h = 1e-5
+    loss = lambda q, a: ((oracle.render(sc2, q, alpha=a) - target) ** 2).sum()  # noqa: E731
+    fd_g = (loss(dict(p, g=p["g"] + h), alpha) - loss(dict(p, g=p["g"] - h), alpha)) / (2 * h)
+    assert abs(out["grad_g"] - fd_g) <= 1e-6 * abs(fd_g) + 1e-9
+    for i in np.argsort(-np.abs(out["grad_alpha"]))[:5]:
+        e = np.zeros_like(alpha)
+        e[i] = h
+        fd = (loss(p, alpha + e) - loss(p, alpha - e)) / (2 * h)
+        assert abs(out["grad_alpha"][i] - fd) <= 1e-6 * abs(fd) + 1e-9
 
 
 # ------------------------------------------------------------- adjoint ---
