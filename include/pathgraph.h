@@ -61,6 +61,10 @@ typedef int32_t pg_status;
 #define PG_FLAG_EXACT_KNN 4u  /* every neighbour query takes the exact (d^2, id) search instead
                                  of the packed-key fast path: the same neighbours, slower; for
                                  validating the fallback the fast path hands rare queries to */
+#define PG_FLAG_CLUSTERS 8u  /* pg_render: neighbours are the disjoint clusters of pg_clusters
+                                (k = expected cluster size) instead of the k nearest.  Two-pass
+                                schedule only; not with PG_FLAG_TAPE, pg_backward or batching.
+                                The call synchronises the stream once to report device checks. */
 
 #define PG_SCHED_TWO_PASS 1  /* aggregate over spatially sorted rows, then shift along paths */
 #define PG_SCHED_SHIFTED  2  /* rows pre-arranged in predecessor order: one pass per iteration */
@@ -99,6 +103,9 @@ typedef struct pg_paths {
                                      constant b_v, to the path-traced L+_0 of the predecessor and, at
                                      a path's first vertex, to the pixel.  A constant input: the
                                      reverse mode does not differentiate it. */
+    const uint32_t* cluster_key;  /* [N] or NULL: uniform random 32-bit keys drawn by the caller, one
+                                     per vertex; they choose the cluster centres of pg_clusters and of
+                                     PG_FLAG_CLUSTERS (required there) */
 } pg_paths;
 
 /* Method parameters. */
@@ -122,14 +129,17 @@ typedef struct pg_params {
 
 /* Optional outputs of pg_render; any pointer may be NULL. */
 typedef struct pg_graph_out {
-    int64_t* row_ptr;       /* [N+1]  = i*K */
-    int32_t* col;           /* [N*K]  neighbour ids (path-order ids) */
-    float* w_ind;           /* [N*K]  indirect aggregation weights */
-    float* w_ph;            /* [N*K]  direct weights of the phase-sampled records */
-    float* w_env;           /* [N*K]  direct weights of the emitter-sampled records */
+    int64_t* row_ptr;       /* [N+1]  = i*K (clusters: row i = its cluster's members) */
+    int32_t* col;           /* [E]    neighbour ids (path-order ids); E = N*K, or with
+                               PG_FLAG_CLUSTERS the sum over clusters of size^2, ids ascending */
+    float* w_ind;           /* [E]    indirect aggregation weights */
+    float* w_ph;            /* [E]    direct weights of the phase-sampled records */
+    float* w_env;           /* [E]    direct weights of the emitter-sampled records */
     float* b;               /* [N][3] albedo x aggregated direct radiance */
     float* d_pt;            /* [N][3] non-aggregated (path-traced) direct term */
     float* lplus;           /* [N][3] incoming indirect radiance after D iterations */
+    int64_t edge_capacity;  /* PG_FLAG_CLUSTERS: entries col / w_* hold; a larger E writes no
+                               edges and returns PG_ERR_INPUT (E from pg_clusters' centres) */
 } pg_graph_out;
 
 /* ---- utilities ---------------------------------------------------------- */
@@ -171,6 +181,25 @@ pg_status pg_profile_stop(int32_t max_entries, pg_profile_entry* out, int32_t* n
 pg_status pg_knn_workspace_size(const pg_paths* paths, int32_t k, int32_t cell_shift, size_t* bytes);
 pg_status pg_knn(const pg_paths* paths, int32_t k, int32_t cell_shift, int64_t* row_ptr, int32_t* col,
                  void* ws, size_t ws_bytes, void* stream);
+
+/* ---- step 1, the paper's relation: clusters ---------------------------------
+ * Paper Sec. "Path Graph Framework" (disjoint clusters of about K points
+ * around randomly chosen centres, large clusters split again) and Sec.
+ * "Rendering System" (path graph solver: centres chosen at random, nearest
+ * centre through neighbouring bins of a grid).  Readings:
+ *   - vertex i is a centre when cluster_key[i] < floor(2^32 / k), so about
+ *     N/k of them; the vertex of smallest (key, id) always is one;
+ *   - every vertex joins the nearest centre by (squared distance of the 20-bit
+ *     quantised positions, centre id);
+ *   - a cluster of s > 2k members takes its ceil(s/k) members of smallest
+ *     (key, id) as new centres and its members join the nearest of those;
+ *     up to 4 rounds, for the clusters still above 2k.
+ * Writes centre[N] (path order): the id of the centre of each vertex's
+ * cluster.  Requires paths->cluster_key.  Synchronises the stream once;
+ * returns PG_ERR_INPUT if a cluster exceeds 4096 members (non-uniform keys). */
+pg_status pg_clusters_workspace_size(const pg_paths* paths, int32_t k, int32_t cell_shift, size_t* bytes);
+pg_status pg_clusters(const pg_paths* paths, int32_t k, int32_t cell_shift, int32_t* centre, void* ws,
+                      size_t ws_bytes, void* stream);
 
 /* ---- step 2: aggregation operators ---------------------------------------
  * Paper Sec. "Path Graph Operators", eqs. (indirect-weight), (ag-indirect),

@@ -12,16 +12,19 @@ import ctypes
 import math
 import os
 
+import numpy as np
+
 from ._build import LIB_PATH, build  # noqa: F401
 
 PG_OK, PG_ERR_ARG, PG_ERR_WORKSPACE, PG_ERR_HIP, PG_ERR_INPUT, PG_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 PG_INIT_PT, PG_INIT_ZERO = 0, 1
-PG_FLAG_CHECK, PG_FLAG_TAPE, PG_FLAG_EXACT_KNN = 1, 2, 4
+PG_FLAG_CHECK, PG_FLAG_TAPE, PG_FLAG_EXACT_KNN, PG_FLAG_CLUSTERS = 1, 2, 4, 8
 PG_SCHED_TWO_PASS, PG_SCHED_SHIFTED, PG_SCHED_SCATTER = 1, 2, 3
 PG_MAX_K = 64
 
 EXPORTS = ("pg_version", "pg_last_error", "pg_default_cell_shift", "pg_profile_start", "pg_profile_stop",
-           "pg_knn_workspace_size", "pg_knn", "pg_edges_workspace_size", "pg_edges",
+           "pg_knn_workspace_size", "pg_knn", "pg_clusters_workspace_size", "pg_clusters",
+           "pg_edges_workspace_size", "pg_edges",
            "pg_propagate_workspace_size", "pg_propagate", "pg_gather",
            "pg_render_workspace_size", "pg_render", "pg_backward_workspace_size", "pg_backward",
            "pg_render_batched_workspace_size", "pg_render_batched", "pg_batch_create", "pg_batch_launch",
@@ -39,7 +42,8 @@ class Paths(ctypes.Structure):
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("spp", ctypes.c_int32),
                 ("albedo_grid_res", ctypes.c_int32)] + [
         (n, ctypes.c_void_p) for n in ("path_offsets", "pos", "dir_in", "dir_out", "albedo", "l_sun",
-                                       "dir_env", "l_env", "l_phase", "e_cam", "albedo_grid", "l_emit")]
+                                       "dir_env", "l_env", "l_phase", "e_cam", "albedo_grid", "l_emit",
+                                       "cluster_key")]
 
 
 class Params(ctypes.Structure):
@@ -55,7 +59,8 @@ class ProfileEntry(ctypes.Structure):
 
 
 class GraphOut(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_void_p) for n in ("row_ptr", "col", "w_ind", "w_ph", "w_env", "b", "d_pt", "lplus")]
+    _fields_ = [(n, ctypes.c_void_p) for n in ("row_ptr", "col", "w_ind", "w_ph", "w_env", "b", "d_pt", "lplus")] + [
+        ("edge_capacity", ctypes.c_int64)]
 
 
 _lib = None
@@ -79,6 +84,8 @@ def lib():
             "pg_profile_stop": (i32, [i32, ctypes.POINTER(ProfileEntry), ctypes.POINTER(ctypes.c_int32)]),
             "pg_knn_workspace_size": (i32, [P, i32, i32, sz]),
             "pg_knn": (i32, [P, i32, i32, vp, vp, vp, ctypes.c_size_t, vp]),
+            "pg_clusters_workspace_size": (i32, [P, i32, i32, sz]),
+            "pg_clusters": (i32, [P, i32, i32, vp, vp, ctypes.c_size_t, vp]),
             "pg_edges_workspace_size": (i32, [P, Q, sz]),
             "pg_edges": (i32, [P, Q, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
             "pg_propagate_workspace_size": (i32, [P, Q, sz]),
@@ -133,7 +140,8 @@ class DevicePaths:
     """The path records of one image as device tensors, plus the C struct
     pointing at them.  ``scene`` is any object with the record arrays (numpy or
     torch) and width / height / spp attributes; an optional ``l_emit`` [N,3]
-    attribute (None: no emission) carries the per-vertex volume emission."""
+    attribute (None: no emission) carries the per-vertex volume emission and
+    an optional ``cluster_key`` [N] (uint32) the keys of the cluster relation."""
 
     ARRAYS = ("path_offsets", "pos", "dir_in", "dir_out", "albedo", "l_sun", "dir_env", "l_env", "l_phase",
               "e_cam")
@@ -153,8 +161,20 @@ class DevicePaths:
         em = getattr(scene, "l_emit", None)
         self.l_emit = None if em is None else torch.as_tensor(em).to(
             device=self.device, dtype=torch.float32).contiguous()
+        self.cluster_key = None
+        self.set_cluster_key(getattr(scene, "cluster_key", None))
         self.albedo_grid = None
         self.set_albedo_grid(albedo_grid)
+
+    def set_cluster_key(self, key):
+        """uint32 keys [N] (numpy) or an int32 tensor holding their bits."""
+        torch = _torch()
+        if key is None:
+            self.cluster_key = None
+            return
+        if not isinstance(key, torch.Tensor):
+            key = torch.from_numpy(np.ascontiguousarray(key, dtype=np.uint32).view(np.int32))
+        self.cluster_key = key.to(device=self.device, dtype=torch.int32).contiguous()
 
     def set_albedo_grid(self, grid):
         torch = _torch()
@@ -172,6 +192,8 @@ class DevicePaths:
             s.albedo_grid_res = int(self.albedo_grid.shape[0])
         if self.l_emit is not None and self.l_emit.numel():
             s.l_emit = self.l_emit.data_ptr()
+        if self.cluster_key is not None and self.cluster_key.numel():
+            s.cluster_key = self.cluster_key.data_ptr()
         return s
 
 
@@ -225,6 +247,29 @@ def pg_knn(paths: DevicePaths, k: int, cell_shift: int = 0):
     _check(L.pg_knn(ctypes.byref(s), int(k), int(cell_shift), _ptr(row_ptr), _ptr(col), _ptr(ws), n,
                     _stream(paths.device)))
     return row_ptr, col
+
+
+def pg_clusters(paths: DevicePaths, k: int, cell_shift: int = 0):
+    """Centre id (path order) of every vertex's cluster, int32 [N]."""
+    torch = _torch()
+    L, s = lib(), paths.struct()
+    nb = ctypes.c_size_t()
+    _check(L.pg_clusters_workspace_size(ctypes.byref(s), int(k), int(cell_shift), ctypes.byref(nb)))
+    _, ws, n = _workspace(nb.value, paths.device)
+    centre = torch.empty(paths.n_vertices, dtype=torch.int32, device=paths.device)
+    _check(L.pg_clusters(ctypes.byref(s), int(k), int(cell_shift), _ptr(centre), _ptr(ws), n,
+                         _stream(paths.device)))
+    return centre
+
+
+def cluster_edge_count(centre) -> int:
+    """Edges of the cluster relation: the sum over clusters of size^2."""
+    torch = _torch()
+    c = torch.as_tensor(centre).to(torch.int64)
+    if c.numel() == 0:
+        return 0
+    size = torch.bincount(c, minlength=c.numel())
+    return int((size * size).sum().item())
 
 
 def pg_edges(paths: DevicePaths, q: Params, row_ptr, col):
@@ -290,6 +335,7 @@ class Renderer:
             out = GraphOut()
             for name, t in graph.items():
                 setattr(out, name, t.data_ptr())
+            out.edge_capacity = int(graph["col"].numel()) if "col" in graph else 0
         _check(lib().pg_render(ctypes.byref(self.s), ctypes.byref(self.q), _ptr(image),
                                ctypes.byref(out) if out is not None else None, _ptr(self.ws), self.ws_bytes,
                                _stream(self.paths.device)))
@@ -302,11 +348,15 @@ def pg_render(paths: DevicePaths, q: Params, graph: bool = False):
     torch = _torch()
     g = None
     if graph:
-        N, K = paths.n_vertices, _K(paths, q.k)
+        N = paths.n_vertices
+        if q.flags & PG_FLAG_CLUSTERS:
+            E = cluster_edge_count(pg_clusters(paths, q.k, q.cell_shift)) if N else 0
+        else:
+            E = N * _K(paths, q.k)
         f = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=paths.device)  # noqa: E731
         g = {"row_ptr": torch.empty(N + 1, dtype=torch.int64, device=paths.device),
-             "col": torch.empty(N * K, dtype=torch.int32, device=paths.device),
-             "w_ind": f(N * K), "w_ph": f(N * K), "w_env": f(N * K), "b": f(N, 3), "d_pt": f(N, 3),
+             "col": torch.empty(E, dtype=torch.int32, device=paths.device),
+             "w_ind": f(E), "w_ph": f(E), "w_env": f(E), "b": f(N, 3), "d_pt": f(N, 3),
              "lplus": f(N, 3)}
     image = Renderer(paths, q)(graph=g)
     return (image, g) if graph else image

@@ -70,7 +70,17 @@ pg_status validate_params(const pg_params* q) {
     if (q->cell_shift != 0 && (q->cell_shift < kMinShift || q->cell_shift > kQBits))
         return fail(PG_ERR_ARG, "cell_shift must be 0 or in [%d, %d]", kMinShift, kQBits);
     if (q->schedule < 0 || q->schedule > PG_SCHED_SCATTER) return fail(PG_ERR_ARG, "unknown schedule");
-    if (q->flags & ~(PG_FLAG_CHECK | PG_FLAG_TAPE | PG_FLAG_EXACT_KNN)) return fail(PG_ERR_ARG, "unknown flag bits");
+    if (q->flags & ~(PG_FLAG_CHECK | PG_FLAG_TAPE | PG_FLAG_EXACT_KNN | PG_FLAG_CLUSTERS))
+        return fail(PG_ERR_ARG, "unknown flag bits");
+    return PG_OK;
+}
+
+pg_status validate_clusters(const pg_paths* p, const pg_params* q) {
+    if (!(q->flags & PG_FLAG_CLUSTERS)) return PG_OK;
+    if (q->flags & PG_FLAG_TAPE) return fail(PG_ERR_UNSUPPORTED, "the reverse mode does not support PG_FLAG_CLUSTERS");
+    if (q->schedule != 0 && q->schedule != PG_SCHED_TWO_PASS)
+        return fail(PG_ERR_UNSUPPORTED, "PG_FLAG_CLUSTERS runs the two-pass schedule only");
+    if (p->n_vertices > 0 && !p->cluster_key) return fail(PG_ERR_ARG, "PG_FLAG_CLUSTERS needs paths->cluster_key");
     return PG_OK;
 }
 
@@ -110,6 +120,8 @@ pg_status finish(hipStream_t s, const pg_params* q, const int32_t* dflag, uint32
         if (h & kFlagPos) m += " position non-finite or outside [0,1];";
         if (h & kFlagOffsets) m += " path offsets not monotone or out of range;";
         if (h & kFlagIndex) m += " neighbour id out of range or row not starting with itself;";
+        if (h & kFlagCluster) m += " a cluster has more than 4096 members (cluster_key not uniform?);";
+        if (h & kFlagCapacity) m += " the cluster edges exceed out->edge_capacity (or 2^32);";
         return fail(PG_ERR_INPUT, "%s", m.c_str());
     }
     return PG_OK;
@@ -205,6 +217,53 @@ pg_status pg_knn(const pg_paths* paths, int32_t k, int32_t cell_shift, int64_t* 
     e = launch_knn(N, K, shift, g.qs, g.perm, g.inv, g.range, nullptr, col, row_ptr, g.redo, g.nredo, false, s);
     if (e != hipSuccess) return hip_fail(e, "knn");
     return finish(s, nullptr, g.flag, 0);
+}
+
+// ------------------------------------------------------------- clusters ---
+
+static size_t clusters_size(const pg_paths* p, int32_t k, int shift) {
+    Carver cv(nullptr);
+    GridBufs g;
+    carve_grid(cv, g, p->n_vertices, shift);
+    ClusterBufs cb;
+    carve_clusters(cv, cb, p->n_vertices, k);
+    return cv.size();
+}
+
+pg_status pg_clusters_workspace_size(const pg_paths* paths, int32_t k, int32_t cell_shift, size_t* bytes) {
+    g_error.clear();
+    pg_status st = validate_paths(paths, false);
+    if (st) return st;
+    if (!bytes) return fail(PG_ERR_ARG, "bytes is NULL");
+    if (k < 1 || k > PG_MAX_K) return fail(PG_ERR_ARG, "k = %d outside [1, %d]", k, PG_MAX_K);
+    if (cell_shift != 0 && (cell_shift < kMinShift || cell_shift > kQBits)) return fail(PG_ERR_ARG, "bad cell_shift");
+    *bytes = clusters_size(paths, k, cell_shift ? cell_shift : default_shift(paths->n_vertices));
+    return PG_OK;
+}
+
+pg_status pg_clusters(const pg_paths* paths, int32_t k, int32_t cell_shift, int32_t* centre, void* ws,
+                      size_t ws_bytes, void* stream) {
+    g_error.clear();
+    pg_status st = validate_paths(paths, false);
+    if (st) return st;
+    if (k < 1 || k > PG_MAX_K) return fail(PG_ERR_ARG, "k = %d outside [1, %d]", k, PG_MAX_K);
+    if (cell_shift != 0 && (cell_shift < kMinShift || cell_shift > kQBits)) return fail(PG_ERR_ARG, "bad cell_shift");
+    const int64_t N = paths->n_vertices;
+    if (N > 0 && (!centre || !paths->cluster_key)) return fail(PG_ERR_ARG, "centre and paths->cluster_key are required");
+    const int shift = cell_shift ? cell_shift : default_shift(N);
+    if ((st = check_ws(ws, ws_bytes, clusters_size(paths, k, shift)))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Carver cv(ws);
+    GridBufs g;
+    carve_grid(cv, g, N, shift);
+    ClusterBufs cb;
+    carve_clusters(cv, cb, N, k);
+    if (N == 0) return finish(s, nullptr, nullptr, 0);
+    hipError_t e;
+    if ((e = run_grid(paths, g, nullptr, s)) != hipSuccess) return hip_fail(e, "grid build");
+    if ((e = run_clusters(paths, g, cb, s)) != hipSuccess) return hip_fail(e, "clusters");
+    if ((e = launch_centre_out(N, g, cb, centre, s)) != hipSuccess) return hip_fail(e, "centre output");
+    return finish(s, nullptr, g.flag, PG_FLAG_CHECK);
 }
 
 // ---------------------------------------------------------------- edges ---
@@ -362,7 +421,8 @@ pg_status pg_gather(const pg_paths* paths, const pg_params* params, const int64_
 pg_status pg_render_workspace_size(const pg_paths* paths, const pg_params* params, size_t* bytes) {
     g_error.clear();
     pg_status st;
-    if ((st = validate_paths(paths, true)) || (st = validate_params(params))) return st;
+    if ((st = validate_paths(paths, true)) || (st = validate_params(params)) || (st = validate_clusters(paths, params)))
+        return st;
     if (!bytes) return fail(PG_ERR_ARG, "bytes is NULL");
     Carver cv(nullptr);
     RenderBufs r;
@@ -380,7 +440,8 @@ pg_status pg_render(const pg_paths* paths, const pg_params* params, float* image
                     size_t ws_bytes, void* stream) {
     g_error.clear();
     pg_status st;
-    if ((st = validate_paths(paths, true)) || (st = validate_params(params))) return st;
+    if ((st = validate_paths(paths, true)) || (st = validate_params(params)) || (st = validate_clusters(paths, params)))
+        return st;
     if (!image) return fail(PG_ERR_ARG, "image is NULL");
     Carver dry(nullptr);
     RenderBufs r;
@@ -391,7 +452,9 @@ pg_status pg_render(const pg_paths* paths, const pg_params* params, float* image
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = run_render(paths, params, r, out, image, s);
     if (e != hipSuccess) return hip_fail(e, "render");
-    return finish(s, params, r.g.flag, params->flags);
+    // the cluster relation always reports its device checks (one synchronisation)
+    const uint32_t fl = r.clusters ? params->flags | PG_FLAG_CHECK : params->flags;
+    return finish(s, params, r.g.flag, fl);
 }
 
 }  // extern "C"

@@ -14,6 +14,7 @@ pg_status fail(pg_status code, const char* fmt, ...);
 pg_status hip_fail(hipError_t e, const char* where);
 pg_status validate_paths(const pg_paths* p, bool need_records);
 pg_status validate_params(const pg_params* q);
+pg_status validate_clusters(const pg_paths* p, const pg_params* q);
 pg_status check_ws(void* ws, size_t ws_bytes, size_t need);
 pg_status finish(hipStream_t s, const pg_params* q, const int32_t* dflag, uint32_t flags);
 Consts make_consts(const pg_params* q, int K);
@@ -63,6 +64,52 @@ struct GridBufs {
 void carve_grid(Carver& cv, GridBufs& g, int64_t N, int shift);
 hipError_t run_grid(const pg_paths* p, GridBufs& g, VRec* rec, hipStream_t s);
 
+// The cluster neighbour relation (pg_clusters.hip).  Arrays indexed by a
+// sorted id unless noted; "position" is the place in cluster order.
+struct ClusterBufs {
+    int K = 0;                       // expected cluster size (the k parameter)
+    int bits = 0;                    // centre grid: 2^bits cells per axis
+    int64_t ncells = 0;
+    unsigned long long* kmin = nullptr;   // min (key << 32 | path id)
+    unsigned long long* nedge = nullptr;  // sum of the squared cluster sizes
+    uint32_t* ncent = nullptr;
+    int32_t* live = nullptr;         // [0] = 1, [r+1]: round r split a cluster
+    int32_t* clist = nullptr;        // centres (sorted ids)
+    uint32_t* gcount = nullptr;      // centre grid: counts, then starts
+    uint32_t* gpart = nullptr;
+    uint32_t* gcell = nullptr;
+    uint32_t* grank = nullptr;
+    uint64_t* gq = nullptr;          // centres in grid order: packed position,
+    int32_t* gs = nullptr;           //   sorted id
+    int32_t* gpid = nullptr;         //   path id
+    int32_t* cid = nullptr;          // sorted id of the vertex's centre
+    uint32_t* ccount = nullptr;      // members per centre [N+1]
+    uint32_t* cstart = nullptr;      // first member of each centre's group [N+1]
+    uint32_t* cpart = nullptr;
+    uint32_t* cfill = nullptr;
+    int32_t* members = nullptr;      // sorted ids grouped by centre
+    uint32_t* mslot = nullptr;       // each vertex's slot in members
+    uint8_t* newc = nullptr;         // new centre in the current split round
+    int32_t* cperm = nullptr;        // position -> sorted id
+    int32_t* cinv = nullptr;         // path id -> position
+    uint2* crange = nullptr;         // position -> [first, end) position of its cluster
+};
+void carve_clusters(Carver& cv, ClusterBufs& cb, int64_t N, int K);
+hipError_t run_clusters(const pg_paths* p, GridBufs& g, ClusterBufs& cb, hipStream_t s);
+hipError_t launch_centre_out(int64_t N, const GridBufs& g, const ClusterBufs& cb, int32_t* out, hipStream_t s);
+
+// Per-vertex data of the render in cluster order.
+struct ClusterRender {
+    VRec* crec = nullptr;      // records
+    float4* tq = nullptr;      // (arriving direction, albedo)
+    float4* wq = nullptr;      // (continuation direction, 1 / M+ of it)
+    float* mp = nullptr;       // M+ + C p_e
+    float* me = nullptr;       // Me of the environment sample
+    uint32_t* rowlen = nullptr;   // export: row lengths, then row starts [N+1]
+    uint32_t* rowpart = nullptr;
+};
+void carve_cluster_render(Carver& cv, ClusterRender& cr, int64_t N);
+
 // Every buffer of one render in the internal (spatially sorted) order.
 struct RenderBufs {
     GridBufs g;
@@ -85,6 +132,9 @@ struct RenderBufs {
     float* mw = nullptr;
     float* c = nullptr;
     float* traj = nullptr;    // [(D+1)*N*3] (tape)
+    bool clusters = false;    // cluster neighbour relation: the render runs in cluster order
+    ClusterBufs cl;
+    ClusterRender cr;
 };
 
 // Reverse-mode buffers, carved right after a render's tape.
@@ -128,6 +178,12 @@ hipError_t render_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, co
 hipError_t render_iterate(RenderBufs& r, float* x0, hipStream_t s, float** final_x);
 hipError_t render_output(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out,
                          float* image, const float* cur, hipStream_t s);
+// The same three phases with the cluster neighbour relation (cluster order).
+hipError_t cluster_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out,
+                         hipStream_t s, float** x0_out);
+hipError_t cluster_iterate(RenderBufs& r, const pg_params* q, float* x0, hipStream_t s, float** final_x);
+hipError_t cluster_output(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out,
+                          float* image, const float* cur, hipStream_t s);
 // Runs grid, kNN, edges, paths, D iterations and pixels; fills `out` if given.
 // *final_x receives the buffer holding L_D (sorted order).
 hipError_t run_render(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out, float* image,

@@ -711,6 +711,8 @@ pg_status pg_backward_workspace_size(const pg_paths* paths, const pg_params* par
     pg_status st;
     if ((st = validate_paths(paths, true)) || (st = validate_params(params))) return st;
     if (!bytes) return fail(PG_ERR_ARG, "bytes is NULL");
+    if (params->flags & PG_FLAG_CLUSTERS)
+        return fail(PG_ERR_UNSUPPORTED, "the reverse mode does not support PG_FLAG_CLUSTERS");
     Carver cv(nullptr);
     RenderBufs r;
     BackBufs bb;
@@ -725,6 +727,8 @@ pg_status pg_backward(const pg_paths* paths, const pg_params* params, const floa
     pg_status st;
     if ((st = validate_paths(paths, true)) || (st = validate_params(params))) return st;
     if (!grad_image) return fail(PG_ERR_ARG, "grad_image is NULL");
+    if (params->flags & PG_FLAG_CLUSTERS)
+        return fail(PG_ERR_UNSUPPORTED, "the reverse mode does not support PG_FLAG_CLUSTERS");
     if (grad_grid && !paths->albedo_grid) return fail(PG_ERR_ARG, "grad_grid needs paths->albedo_grid");
     if (!grad_grid && !grad_albedo && !grad_g) return fail(PG_ERR_ARG, "no gradient requested");
     {

@@ -121,6 +121,8 @@ static pg_status validate_batch(int n, const pg_paths* paths, const pg_params* p
         pg_status st;
         if ((st = validate_paths(&paths[s], true)) || (st = validate_params(&params[s])))
             return fail(st, "scene %d: %s", s, g_error.c_str());
+        if (params[s].flags & PG_FLAG_CLUSTERS)
+            return fail(PG_ERR_UNSUPPORTED, "scene %d: batching does not support PG_FLAG_CLUSTERS", s);
     }
     return PG_OK;
 }

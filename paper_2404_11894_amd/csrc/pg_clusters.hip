@@ -1,0 +1,721 @@
+// pg_clusters.hip -- the paper's own neighbour relation: disjoint clusters
+// around random centres (Sec. "Path Graph Framework"; Sec. "Rendering
+// System", path graph solver), and the aggregation over them.
+//
+// Clusters.  Vertex i is a centre when its caller-drawn uniform 32-bit key is
+// below floor(2^32 / K) (about N/K centres); the vertex with the smallest
+// (key, path id) always is one.  Every vertex joins the nearest centre by
+// (squared distance of the 20-bit quantised positions, centre path id),
+// found by a ring search over a uniform grid of the centres alone.  A
+// cluster with more than 2K members takes its ceil(s/K) members of smallest
+// (key, path id) as new centres and its members join the nearest of those;
+// this repeats up to kClusterRounds rounds for the clusters still large.
+//
+// Layout.  The render then runs in "cluster order": clusters one after the
+// other (ordered by their centre's place in the spatially sorted order), the
+// members of a cluster by ascending path id.  A row's neighbours are exactly
+// its cluster's members, a contiguous range [a, e).
+//
+// Aggregation.  All receivers of a cluster combine the same techniques, so
+// the marginal density of a sample is one number per sample (first pass,
+// O(C) per vertex), and the weight w+_ij = rho_i(w_j) / M+(w_j) is
+// recomputed in every iteration from the receiver's arriving direction and
+// the member's (w_j, 1/M+_j) instead of being stored: per iteration a row
+// reads 16 + 12 + 12 bytes of its own and its cluster's members' 16 + 12
+// bytes from L1/L2 (the members are contiguous and shared by the wave's
+// rows), against 8 bytes per edge plus a gather for the stored sliced ELL.
+#include "pg_api_common.h"
+
+namespace pg {
+
+namespace {
+
+__device__ inline int64_t qdist2(uint64_t a, uint64_t b) {
+    int32_t ax, ay, az, bx, by, bz;
+    qunpack(a, ax, ay, az);
+    qunpack(b, bx, by, bz);
+    const int64_t dx = ax - bx, dy = ay - by, dz = az - bz;
+    return dx * dx + dy * dy + dz * dz;
+}
+
+__device__ inline bool near_less(int64_t d1, int32_t p1, int64_t d2, int32_t p2) {
+    return d1 < d2 || (d1 == d2 && p1 < p2);
+}
+
+// ------------------------------------------------------------- centres ---
+
+// min over all vertices of (key << 32 | path id): one atomic per wave
+__global__ __launch_bounds__(kBlock) void k_key_min(int64_t N, const uint32_t* __restrict__ key,
+                                                    unsigned long long* __restrict__ kmin) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long m = v < N ? ((unsigned long long)key[v] << 32) | (unsigned long long)v : ~0ull;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const unsigned long long t = __shfl_xor(m, o, kWave);
+        m = t < m ? t : m;
+    }
+    if (__lane_id() == 0 && m != ~0ull) atomicMin(kmin, m);
+}
+
+// centre flags in sorted order, compacted into clist (sorted ids)
+__global__ __launch_bounds__(kBlock) void k_centres(int64_t N, const int32_t* __restrict__ perm,
+                                                    const uint32_t* __restrict__ key, unsigned long long thr,
+                                                    const unsigned long long* __restrict__ kmin,
+                                                    int32_t* __restrict__ clist, uint32_t* __restrict__ ncent) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const int32_t pid = perm[s];
+    const bool c = (unsigned long long)key[pid] < thr || (uint32_t)(*kmin & 0xffffffffull) == (uint32_t)pid;
+    const uint32_t slot = wave_append(ncent, c);
+    if (c) clist[slot] = (int32_t)s;
+}
+
+__device__ inline uint32_t cg_cell(uint64_t q, int b) {
+    int32_t x, y, z;
+    qunpack(q, x, y, z);
+    const int sh = kQBits - b;
+    return ((uint32_t)(z >> sh) << (2 * b)) | ((uint32_t)(y >> sh) << b) | (uint32_t)(x >> sh);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_count(const uint32_t* __restrict__ ncent,
+                                                     const int32_t* __restrict__ clist,
+                                                     const uint64_t* __restrict__ qs, int b,
+                                                     uint32_t* __restrict__ gcount, uint32_t* __restrict__ gcell,
+                                                     uint32_t* __restrict__ grank) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)*ncent) return;
+    const uint32_t cell = cg_cell(qs[clist[t]], b);
+    gcell[t] = cell;
+    grank[t] = atomicAdd(&gcount[cell], 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_scatter(const uint32_t* __restrict__ ncent,
+                                                       const int32_t* __restrict__ clist,
+                                                       const uint64_t* __restrict__ qs,
+                                                       const int32_t* __restrict__ perm,
+                                                       const uint32_t* __restrict__ gcell,
+                                                       const uint32_t* __restrict__ grank,
+                                                       const uint32_t* __restrict__ gstart, uint64_t* __restrict__ gq,
+                                                       int32_t* __restrict__ gs, int32_t* __restrict__ gpid) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)*ncent) return;
+    const int32_t s = clist[t];
+    const uint32_t pos = gstart[gcell[t]] + grank[t];
+    gq[pos] = qs[s];
+    gs[pos] = s;
+    gpid[pos] = perm[s];
+}
+
+// Nearest centre of every vertex: rings of cells at Chebyshev distance r
+// around the vertex's cell, r = 0, 1, ...; a cell at ring r+1 is farther
+// than r cell widths in every coordinate, so the search ends after ring r
+// once the best squared distance is at most (r * width)^2.
+__global__ __launch_bounds__(kBlock) void k_nearest_centre(int64_t N, const uint64_t* __restrict__ qs, int b,
+                                                           const uint32_t* __restrict__ gstart,
+                                                           const uint64_t* __restrict__ gq,
+                                                           const int32_t* __restrict__ gs,
+                                                           const int32_t* __restrict__ gpid,
+                                                           int32_t* __restrict__ cid, int32_t* flag) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const uint64_t q = qs[s];
+    int32_t qx, qy, qz;
+    qunpack(q, qx, qy, qz);
+    const int sh = kQBits - b;
+    const int side = 1 << b;
+    const int cx = qx >> sh, cy = qy >> sh, cz = qz >> sh;
+    int64_t bd = INT64_MAX;
+    int32_t bp = INT32_MAX, bs = -1;
+    for (int r = 0; r < side; ++r) {
+        for (int dz = -r; dz <= r; ++dz) {
+            const int z = cz + dz;
+            if (z < 0 || z >= side) continue;
+            for (int dy = -r; dy <= r; ++dy) {
+                const int y = cy + dy;
+                if (y < 0 || y >= side) continue;
+                const bool face = dz == -r || dz == r || dy == -r || dy == r;
+                const int step = face ? 1 : 2 * r;
+                for (int dx = -r; dx <= r; dx += step) {
+                    const int x = cx + dx;
+                    if (x < 0 || x >= side) continue;
+                    const uint32_t cell = ((uint32_t)z << (2 * b)) | ((uint32_t)y << b) | (uint32_t)x;
+                    const uint32_t e1 = gstart[cell + 1];
+                    for (uint32_t e = gstart[cell]; e < e1; ++e) {
+                        const int64_t d2 = qdist2(q, gq[e]);
+                        const int32_t p = gpid[e];
+                        if (near_less(d2, p, bd, bp)) {
+                            bd = d2;
+                            bp = p;
+                            bs = gs[e];
+                        }
+                    }
+                }
+            }
+        }
+        const int64_t lim = (int64_t)r << sh;
+        if (bs >= 0 && bd <= lim * lim) break;
+    }
+    if (bs < 0) set_flag(flag, kFlagCluster);
+    cid[s] = bs < 0 ? (int32_t)s : bs;
+}
+
+// ------------------------------------------------------------ grouping ---
+
+__global__ __launch_bounds__(kBlock) void k_ccount(int64_t N, const int32_t* __restrict__ cid,
+                                                   uint32_t* __restrict__ ccount, const int32_t* __restrict__ live) {
+    if (live && *live == 0) return;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < N) atomicAdd(&ccount[cid[s]], 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cgroup(int64_t N, const int32_t* __restrict__ cid,
+                                                   const uint32_t* __restrict__ cstart, uint32_t* __restrict__ cfill,
+                                                   int32_t* __restrict__ members, uint32_t* __restrict__ mslot,
+                                                   const int32_t* __restrict__ live) {
+    if (live && *live == 0) return;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const int32_t c = cid[s];
+    const uint32_t slot = cstart[c] + atomicAdd(&cfill[c], 1u);
+    members[slot] = (int32_t)s;
+    mslot[s] = slot;
+}
+
+// A cluster above kClusterMax members is reported (kFlagCluster) and its
+// rows are left empty, so that no loop runs over it.
+__device__ inline uint2 bounded(uint2 rg) {
+    if (rg.y - rg.x > (uint32_t)kClusterMax) rg.y = rg.x;
+    return rg;
+}
+
+// ----------------------------------------------------------- splitting ---
+
+// Members of a large cluster: the ceil(s/K) of smallest (key, path id)
+// become centres (newc).  O(s) per member.
+__global__ __launch_bounds__(kBlock) void k_split_mark(int64_t N, int K, const int32_t* __restrict__ cid,
+                                                       const uint32_t* __restrict__ ccount,
+                                                       const uint32_t* __restrict__ cstart,
+                                                       const int32_t* __restrict__ members,
+                                                       const int32_t* __restrict__ perm,
+                                                       const uint32_t* __restrict__ key, uint8_t* __restrict__ newc,
+                                                       const int32_t* __restrict__ live, int32_t* __restrict__ split,
+                                                       int32_t* flag) {
+    if (live && *live == 0) return;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const int32_t c = cid[s];
+    const uint32_t sz = ccount[c];
+    if (sz <= 2u * (uint32_t)K) return;
+    if (sz > (uint32_t)kClusterMax) {
+        set_flag(flag, kFlagCluster);
+        return;
+    }
+    const int32_t pid = perm[s];
+    const unsigned long long mine = ((unsigned long long)key[pid] << 32) | (uint32_t)pid;
+    const uint32_t a = cstart[c];
+    uint32_t rank = 0;
+    for (uint32_t e = a; e < a + sz; ++e) {
+        const int32_t pj = perm[members[e]];
+        rank += (((unsigned long long)key[pj] << 32) | (uint32_t)pj) < mine;
+    }
+    newc[s] = rank < (sz + (uint32_t)K - 1u) / (uint32_t)K;
+    *split = 1;
+}
+
+// Members of a large cluster join the nearest of its new centres.
+__global__ __launch_bounds__(kBlock) void k_split_assign(int64_t N, int K, const uint64_t* __restrict__ qs,
+                                                         int32_t* __restrict__ cid, const uint32_t* __restrict__ ccount,
+                                                         const uint32_t* __restrict__ cstart,
+                                                         const int32_t* __restrict__ members,
+                                                         const int32_t* __restrict__ perm,
+                                                         const uint8_t* __restrict__ newc,
+                                                         const int32_t* __restrict__ live) {
+    if (live && *live == 0) return;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const int32_t c = cid[s];
+    const uint32_t sz = ccount[c];
+    if (sz <= 2u * (uint32_t)K || sz > (uint32_t)kClusterMax) return;
+    const uint64_t q = qs[s];
+    const uint32_t a = cstart[c];
+    int64_t bd = INT64_MAX;
+    int32_t bp = INT32_MAX, bs = c;
+    for (uint32_t e = a; e < a + sz; ++e) {
+        const int32_t j = members[e];
+        if (!newc[j]) continue;
+        const int64_t d2 = qdist2(q, qs[j]);
+        const int32_t p = perm[j];
+        if (near_less(d2, p, bd, bp)) {
+            bd = d2;
+            bp = p;
+            bs = j;
+        }
+    }
+    cid[s] = bs;
+}
+
+// ----------------------------------------------------------- the order ---
+
+// Cluster order: position = cluster start + rank of the path id among the
+// members.  Writes cperm (position -> sorted id), cinv (path id -> position)
+// and each position's member range.
+__global__ __launch_bounds__(kBlock) void k_corder(int64_t N, const int32_t* __restrict__ cid,
+                                                   const uint32_t* __restrict__ ccount,
+                                                   const uint32_t* __restrict__ cstart,
+                                                   const int32_t* __restrict__ members,
+                                                   const uint32_t* __restrict__ mslot,
+                                                   const int32_t* __restrict__ perm, int32_t* __restrict__ cperm,
+                                                   int32_t* __restrict__ cinv, uint2* __restrict__ crange,
+                                                   unsigned long long* __restrict__ nedge, int32_t* flag) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t sz = 0;
+    if (s < N) {
+        const int32_t c = cid[s];
+        sz = ccount[c];
+        const uint32_t a = cstart[c];
+        const int32_t pid = perm[s];
+        uint32_t rank = 0;
+        if (sz > (uint32_t)kClusterMax) {
+            set_flag(flag, kFlagCluster);   // not ranked: the result is reported invalid
+            rank = mslot[s] - a;
+        } else {
+            for (uint32_t e = a; e < a + sz; ++e) rank += perm[members[e]] < pid;
+        }
+        const uint32_t pos = a + rank;
+        cperm[pos] = (int32_t)s;
+        cinv[pid] = (int32_t)pos;
+        crange[pos] = make_uint2(a, a + sz);
+    }
+    // total edge count (each vertex's row has sz entries)
+    unsigned long long e = sz;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) e += __shfl_xor(e, o, kWave);
+    if (__lane_id() == 0 && e) atomicAdd(nedge, e);
+}
+
+// Records in cluster order, plus (t, alpha) packed for the iteration.
+__global__ __launch_bounds__(kBlock) void k_crec(int64_t N, const int32_t* __restrict__ cperm,
+                                                 const VRec* __restrict__ rec, VRec* __restrict__ crec,
+                                                 float4* __restrict__ tq, float* __restrict__ alpha) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const float4* src = reinterpret_cast<const float4*>(rec + cperm[i]);
+    float4* dst = reinterpret_cast<float4*>(crec + i);
+    float4 a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3], a4 = src[4];
+    dst[0] = a0;
+    dst[1] = a1;
+    dst[2] = a2;
+    dst[3] = a3;
+    dst[4] = a4;
+    tq[i] = make_float4(a0.x, a0.y, a0.z, a4.z);
+    alpha[i] = a4.z;
+}
+
+// --------------------------------------------------------- the weights ---
+
+// First pass: the marginals of every vertex's own samples over its cluster,
+//   M+(w_i) = sum_l p_l(w_i),  Me(we_i) = sum_l p_l(we_i) + C p_e,
+// stored as wq = (w_i, 1/M+), mp = M+ + C p_e, me = Me.
+__global__ __launch_bounds__(kBlock) void k_cmarg(int64_t N, Consts c, const uint2* __restrict__ crange,
+                                                  const VRec* __restrict__ crec, const float4* __restrict__ tq,
+                                                  float4* __restrict__ wq, float* __restrict__ mp,
+                                                  float* __restrict__ me) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const uint2 rg = bounded(crange[i]);
+    const VRec& ri = crec[i];
+    const f3 w{ri.w[0], ri.w[1], ri.w[2]}, we{ri.we[0], ri.we[1], ri.we[2]};
+    float mplus = 0.0f, menv = 0.0f;
+    for (uint32_t l = rg.x; l < rg.y; ++l) {
+        const float4 t4 = tq[l];
+        const f3 tl{t4.x, t4.y, t4.z};
+        mplus += c.pdf(one_minus_cos(tl, w));
+        menv += c.pdf(one_minus_cos(tl, we));
+    }
+    const float Cpe = (float)(rg.y - rg.x) * c.env_pdf;
+    wq[i] = make_float4(w.x, w.y, w.z, 1.0f / mplus);
+    mp[i] = mplus + Cpe;
+    me[i] = menv + Cpe;
+}
+
+// Second pass, per receiver i over its cluster's samples j:
+//   d_agg_i = rho_i(sun)/C sum_j Ls_j + sum_j rho_i(we_j) Le_j / Me_j + rho_i(w_j) Lp_j / (M+_j + C p_e)
+//   b_i = e_i + alpha_i d_agg_i,  and the own (path-traced) direct term and ratio.
+__global__ __launch_bounds__(kBlock) void k_cedges(int64_t N, Consts c, const uint2* __restrict__ crange,
+                                                   const VRec* __restrict__ crec, const float4* __restrict__ tq,
+                                                   const float* __restrict__ mp, const float* __restrict__ me,
+                                                   const float* __restrict__ emit, const int32_t* __restrict__ cperm,
+                                                   const int32_t* __restrict__ perm, float* __restrict__ b,
+                                                   float* __restrict__ dpt, float* __restrict__ r) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const uint2 rg = bounded(crange[i]);
+    const float4 t4 = tq[i];
+    const f3 ti{t4.x, t4.y, t4.z};
+    float cx = 0.f, cy = 0.f, cz = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+    for (uint32_t j = rg.x; j < rg.y; ++j) {
+        const VRec& rj = crec[j];
+        const f3 wj{rj.w[0], rj.w[1], rj.w[2]}, wej{rj.we[0], rj.we[1], rj.we[2]};
+        const float fp = c.rho(one_minus_cos(ti, wj)) / mp[j];
+        const float fe = c.rho(one_minus_cos(ti, wej)) / me[j];
+        cx += fe * rj.le[0] + fp * rj.lp[0];
+        cy += fe * rj.le[1] + fp * rj.lp[1];
+        cz += fe * rj.le[2] + fp * rj.lp[2];
+        sx += rj.ls[0];
+        sy += rj.ls[1];
+        sz += rj.ls[2];
+    }
+    const float rho_sun = c.rho(one_minus_cos(ti, c.sun));
+    const float invC = 1.0f / (float)(rg.y - rg.x);
+    const f3 dagg{fmaf(rho_sun * invC, sx, cx), fmaf(rho_sun * invC, sy, cy), fmaf(rho_sun * invC, sz, cz)};
+    f3 em{0.f, 0.f, 0.f};
+    if (emit) em = ld3(emit, perm[cperm[i]]);
+    const float al = t4.w;
+    st3(b, i, f3{fmaf(al, dagg.x, em.x), fmaf(al, dagg.y, em.y), fmaf(al, dagg.z, em.z)});
+    const VRec& ri = crec[i];
+    const f3 w{ri.w[0], ri.w[1], ri.w[2]}, we{ri.we[0], ri.we[1], ri.we[2]};
+    const float u_w = one_minus_cos(ti, w), u_e = one_minus_cos(ti, we);
+    const float rho = c.rho(u_w), rho_e = c.rho(u_e);
+    const float p_w = c.pdf(u_w), p_e = c.pdf(u_e);
+    const float f_env = rho_e / (p_e + c.env_pdf), f_out = rho / (p_w + c.env_pdf);
+    st3(dpt, i,
+        f3{rho_sun * ri.ls[0] + f_env * ri.le[0] + f_out * ri.lp[0],
+           rho_sun * ri.ls[1] + f_env * ri.le[1] + f_out * ri.lp[1],
+           rho_sun * ri.ls[2] + f_env * ri.le[2] + f_out * ri.lp[2]});
+    r[i] = rho / p_w;
+}
+
+// ------------------------------------------------------- the iteration ---
+
+// sum_j rho_i(w_j) (1/M+_j) x_j over the cluster [a, e)
+__device__ __forceinline__ f3 cluster_gather(const HG& rho, f3 ti, uint2 rg, const float4* __restrict__ wq,
+                                             const float* __restrict__ x) {
+    float zx = 0.f, zy = 0.f, zz = 0.f;
+    for (uint32_t j = rg.x; j < rg.y; ++j) {
+        const float4 w4 = wq[j];
+        const float f = rho(one_minus_cos(ti, f3{w4.x, w4.y, w4.z})) * w4.w;
+        const f3 xv = ld3(x, j);
+        zx = fmaf(f, xv.x, zx);
+        zy = fmaf(f, xv.y, zy);
+        zz = fmaf(f, xv.z, zz);
+    }
+    return f3{zx, zy, zz};
+}
+
+// y_i = b_i + alpha_i sum_j w+_ij x_j, the weights recomputed (one thread per row)
+__global__ __launch_bounds__(kBlock) void k_cagg(int64_t N, HG rho, const uint2* __restrict__ crange,
+                                                 const float4* __restrict__ tq, const float4* __restrict__ wq,
+                                                 const float* __restrict__ b, const float* __restrict__ x,
+                                                 float* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const float4 t4 = tq[i];
+    const f3 z = cluster_gather(rho, f3{t4.x, t4.y, t4.z}, bounded(crange[i]), wq, x);
+    const f3 bb = ld3(b, i);
+    st3_nt(y, i, f3{fmaf(t4.w, z.x, bb.x), fmaf(t4.w, z.y, bb.y), fmaf(t4.w, z.z, bb.z)});
+}
+
+// One thread per pixel, as the sliced-ELL output but gathering over the
+// first vertex's cluster.
+__global__ __launch_bounds__(kBlock) void k_cpixels(pg_paths P, Consts c, const int32_t* __restrict__ cinv,
+                                                    const uint2* __restrict__ crange, const float4* __restrict__ tq,
+                                                    const float4* __restrict__ wq, const float* __restrict__ x,
+                                                    const float* __restrict__ dpt, const float* __restrict__ r,
+                                                    float* __restrict__ image) {
+    const int64_t px = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t npix = (int64_t)P.width * P.height;
+    if (px >= npix) return;
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    for (int k = 0; k < P.spp; ++k) {
+        const int64_t p = px * P.spp + k;
+        sx += P.e_cam[3 * p];
+        sy += P.e_cam[3 * p + 1];
+        sz += P.e_cam[3 * p + 2];
+        const int64_t a = P.path_offsets[p], e = P.path_offsets[p + 1];
+        if (e <= a || a < 0 || e > P.n_vertices) continue;
+        const int64_t i = cinv[a];
+        const float4 t4 = tq[i];
+        f3 in;
+        if (c.final_gather == 0) {
+            in = cluster_gather(c.rho, f3{t4.x, t4.y, t4.z}, bounded(crange[i]), wq, x);
+        } else {
+            const float rr = r[i];
+            in = f3{rr * x[3 * i], rr * x[3 * i + 1], rr * x[3 * i + 2]};
+        }
+        if (P.l_emit) {
+            sx += P.l_emit[3 * a];
+            sy += P.l_emit[3 * a + 1];
+            sz += P.l_emit[3 * a + 2];
+        }
+        sx = fmaf(t4.w, dpt[3 * i] + in.x, sx);
+        sy = fmaf(t4.w, dpt[3 * i + 1] + in.y, sy);
+        sz = fmaf(t4.w, dpt[3 * i + 2] + in.z, sz);
+    }
+    const float inv_spp = 1.0f / (float)P.spp;
+    image[3 * px] = sx * inv_spp;
+    image[3 * px + 1] = sy * inv_spp;
+    image[3 * px + 2] = sz * inv_spp;
+}
+
+// ---------------------------------------------------------- the export ---
+
+__global__ __launch_bounds__(kBlock) void k_crow_len(int64_t N, const int32_t* __restrict__ cinv,
+                                                     const uint2* __restrict__ crange, uint32_t* __restrict__ len) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    const uint2 rg = crange[cinv[v]];
+    len[v] = rg.y - rg.x;
+}
+
+// Row v (path order) of the exported CSR: its cluster's members, ascending
+// path id, with the three weights.  Writes nothing if the edges exceed the
+// caller's capacity or 2^32.
+__global__ __launch_bounds__(kBlock) void k_cexport(int64_t N, Consts c, const uint32_t* __restrict__ start,
+                                                    const unsigned long long* __restrict__ nedge, int64_t capacity,
+                                                    const int32_t* __restrict__ cinv, const uint2* __restrict__ crange,
+                                                    const int32_t* __restrict__ cperm,
+                                                    const int32_t* __restrict__ perm, const VRec* __restrict__ crec,
+                                                    const float4* __restrict__ tq, const float4* __restrict__ wq,
+                                                    const float* __restrict__ mp, const float* __restrict__ me,
+                                                    int64_t* __restrict__ row_ptr, int32_t* __restrict__ col,
+                                                    float* __restrict__ w_ind, float* __restrict__ w_ph,
+                                                    float* __restrict__ w_env, int32_t* flag) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long E = *nedge;
+    const bool fits = E <= (unsigned long long)capacity && E < (1ull << 32);
+    if (v == 0 && !fits) set_flag(flag, kFlagCapacity);
+    if (v > N) return;
+    if (row_ptr) row_ptr[v] = v == N ? (int64_t)E : (int64_t)start[v];
+    if (v == N || !fits || !col) return;
+    const int64_t i = cinv[v];
+    const uint2 rg = bounded(crange[i]);
+    const float4 t4 = tq[i];
+    const f3 ti{t4.x, t4.y, t4.z};
+    const int64_t base = start[v];
+    for (uint32_t j = rg.x; j < rg.y; ++j) {
+        const int64_t e = base + (j - rg.x);
+        col[e] = perm[cperm[j]];
+        const float4 w4 = wq[j];
+        const float rho = c.rho(one_minus_cos(ti, f3{w4.x, w4.y, w4.z}));
+        if (w_ind) w_ind[e] = rho * w4.w;
+        if (w_ph) w_ph[e] = rho / mp[j];
+        if (w_env) {
+            const VRec& rj = crec[j];
+            w_env[e] = c.rho(one_minus_cos(ti, f3{rj.we[0], rj.we[1], rj.we[2]})) / me[j];
+        }
+    }
+}
+
+}  // namespace
+
+int cluster_grid_bits(int64_t N, int K) {
+    const double m = (double)(N / (K > 0 ? K : 1));
+    int b = m > 1.0 ? (int)std::lround(std::log2(m) / 3.0) : 0;
+    return b < 0 ? 0 : (b > 9 ? 9 : b);
+}
+
+void carve_clusters(Carver& cv, ClusterBufs& cb, int64_t N, int K) {
+    cb.K = K;
+    cb.bits = cluster_grid_bits(N, K);
+    cb.ncells = (int64_t)1 << (3 * cb.bits);
+    cb.kmin = cv.take<unsigned long long>(32);
+    cb.nedge = cv.take<unsigned long long>(32);
+    cb.ncent = cv.take<uint32_t>(64);
+    cb.live = cv.take<int32_t>(64);   // [0] = 1, [1 + r] = a cluster was split in round r
+    cb.clist = cv.take<int32_t>(N);
+    cb.gcount = cv.take<uint32_t>(cb.ncells + 1);
+    cb.gpart = cv.take<uint32_t>(scan_partials_bytes(cb.ncells + 1) / 4);
+    cb.gcell = cv.take<uint32_t>(N);
+    cb.grank = cv.take<uint32_t>(N);
+    cb.gq = cv.take<uint64_t>(N);
+    cb.gs = cv.take<int32_t>(N);
+    cb.gpid = cv.take<int32_t>(N);
+    cb.cid = cv.take<int32_t>(N);
+    cb.ccount = cv.take<uint32_t>(N + 1);
+    cb.cstart = cv.take<uint32_t>(N + 1);
+    cb.cpart = cv.take<uint32_t>(scan_partials_bytes(N + 1) / 4);
+    cb.cfill = cv.take<uint32_t>(N);
+    cb.members = cv.take<int32_t>(N);
+    cb.mslot = cv.take<uint32_t>(N);
+    cb.newc = cv.take<uint8_t>(N);
+    cb.cperm = cv.take<int32_t>(N);
+    cb.cinv = cv.take<int32_t>(N);
+    cb.crange = cv.take<uint2>(N);
+}
+
+#define PG_TRY(x)                              \
+    do {                                       \
+        hipError_t e_ = (x);                   \
+        if (e_ != hipSuccess) return e_;       \
+    } while (0)
+
+static dim3 grid_of(int64_t n) { return dim3((unsigned)div_up(n > 0 ? n : 1, kBlock)); }
+
+// (Re)builds the grouping of the vertices by cluster: counts, starts, members.
+static hipError_t group(int64_t N, ClusterBufs& cb, const int32_t* live, hipStream_t s) {
+    PG_TRY(launch_fill(cb.ccount, (size_t)(N + 1) * 4, s));
+    PG_TRY(launch_fill(cb.cfill, (size_t)N * 4, s));
+    hipLaunchKernelGGL(k_ccount, grid_of(N), dim3(kBlock), 0, s, N, cb.cid, cb.ccount, live);
+    PG_TRY(hipGetLastError());
+    PG_TRY(launch_scan_exclusive(cb.ccount, cb.cstart, N + 1, cb.cpart, s));
+    hipLaunchKernelGGL(k_cgroup, grid_of(N), dim3(kBlock), 0, s, N, cb.cid, cb.cstart, cb.cfill, cb.members,
+                       cb.mslot, live);
+    return hipGetLastError();
+}
+
+hipError_t run_clusters(const pg_paths* p, GridBufs& g, ClusterBufs& cb, hipStream_t s) {
+    const int64_t N = p->n_vertices;
+    const int K = cb.K;
+    PG_TRY(launch_fill(cb.nedge, 8, s));
+    if (N == 0) return hipSuccess;
+    PG_TRY(launch_fill_value(cb.kmin, 8, 0xffffffffu, s));
+    PG_TRY(launch_fill(cb.ncent, 4, s));
+    PG_TRY(launch_fill(cb.live, 64 * 4, s));
+    PG_TRY(launch_fill_value(cb.live, 4, 1u, s));
+    hipLaunchKernelGGL(k_key_min, grid_of(N), dim3(kBlock), 0, s, N, p->cluster_key, cb.kmin);
+    PG_TRY(hipGetLastError());
+    const unsigned long long thr = (1ull << 32) / (unsigned long long)K;
+    hipLaunchKernelGGL(k_centres, grid_of(N), dim3(kBlock), 0, s, N, g.perm, p->cluster_key, thr, cb.kmin,
+                       cb.clist, cb.ncent);
+    PG_TRY(hipGetLastError());
+    // uniform grid of the centres
+    PG_TRY(launch_fill(cb.gcount, (size_t)(cb.ncells + 1) * 4, s));
+    hipLaunchKernelGGL(k_cg_count, grid_of(N), dim3(kBlock), 0, s, cb.ncent, cb.clist, g.qs, cb.bits, cb.gcount,
+                       cb.gcell, cb.grank);
+    PG_TRY(hipGetLastError());
+    PG_TRY(launch_scan_exclusive(cb.gcount, cb.gcount, cb.ncells + 1, cb.gpart, s));
+    hipLaunchKernelGGL(k_cg_scatter, grid_of(N), dim3(kBlock), 0, s, cb.ncent, cb.clist, g.qs, g.perm, cb.gcell,
+                       cb.grank, cb.gcount, cb.gq, cb.gs, cb.gpid);
+    PG_TRY(hipGetLastError());
+    {
+        ProfScope ps(s, "nearest_centre");
+        hipLaunchKernelGGL(k_nearest_centre, grid_of(N), dim3(kBlock), 0, s, N, g.qs, cb.bits, cb.gcount, cb.gq,
+                           cb.gs, cb.gpid, cb.cid, g.flag);
+        PG_TRY(hipGetLastError());
+    }
+    // split rounds; round r runs only if round r-1 split something
+    {
+        ProfScope ps(s, "split");
+        for (int r = 0; r < kClusterRounds; ++r) {
+            const int32_t* live = cb.live + r;
+            PG_TRY(group(N, cb, live, s));
+            hipLaunchKernelGGL(k_split_mark, grid_of(N), dim3(kBlock), 0, s, N, K, cb.cid, cb.ccount, cb.cstart,
+                               cb.members, g.perm, p->cluster_key, cb.newc, live, cb.live + r + 1, g.flag);
+            PG_TRY(hipGetLastError());
+            hipLaunchKernelGGL(k_split_assign, grid_of(N), dim3(kBlock), 0, s, N, K, g.qs, cb.cid, cb.ccount,
+                               cb.cstart, cb.members, g.perm, cb.newc, live);
+            PG_TRY(hipGetLastError());
+        }
+    }
+    ProfScope ps(s, "cluster_order");
+    PG_TRY(group(N, cb, nullptr, s));
+    hipLaunchKernelGGL(k_corder, grid_of(N), dim3(kBlock), 0, s, N, cb.cid, cb.ccount, cb.cstart, cb.members,
+                       cb.mslot, g.perm, cb.cperm, cb.cinv, cb.crange, cb.nedge, g.flag);
+    return hipGetLastError();
+}
+
+// Path id of each vertex's cluster centre, path order.
+__global__ __launch_bounds__(kBlock) void k_centre_out(int64_t N, const int32_t* __restrict__ inv,
+                                                       const int32_t* __restrict__ cid,
+                                                       const int32_t* __restrict__ perm, int32_t* __restrict__ out) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < N) out[v] = perm[cid[inv[v]]];
+}
+
+hipError_t launch_centre_out(int64_t N, const GridBufs& g, const ClusterBufs& cb, int32_t* out, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_centre_out, grid_of(N), dim3(kBlock), 0, s, N, g.inv, cb.cid, g.perm, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ cluster render ---
+
+void carve_cluster_render(Carver& cv, ClusterRender& cr, int64_t N) {
+    cr.crec = cv.take<VRec>(N);
+    cr.tq = cv.take<float4>(N);
+    cr.wq = cv.take<float4>(N);
+    cr.mp = cv.take<float>(N);
+    cr.me = cv.take<float>(N);
+    cr.rowlen = cv.take<uint32_t>(N + 1);
+    cr.rowpart = cv.take<uint32_t>(scan_partials_bytes(N + 1) / 4);
+}
+
+hipError_t cluster_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out,
+                         hipStream_t s, float** x0_out) {
+    const int64_t N = r.N;
+    GridBufs& g = r.g;
+    ClusterBufs& cb = r.cl;
+    ClusterRender& cr = r.cr;
+    {
+        ProfScope ps(s, "grid");
+        PG_TRY(run_grid(p, g, r.rec, s));
+    }
+    PG_TRY(run_clusters(p, g, cb, s));
+    const Consts c = make_consts(q, r.K);
+    if (N > 0) {
+        ProfScope ps(s, "edges");
+        hipLaunchKernelGGL(k_crec, grid_of(N), dim3(kBlock), 0, s, N, cb.cperm, r.rec, cr.crec, cr.tq, r.alpha);
+        PG_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_cmarg, grid_of(N), dim3(kBlock), 0, s, N, c, cb.crange, cr.crec, cr.tq, cr.wq, cr.mp,
+                           cr.me);
+        PG_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_cedges, grid_of(N), dim3(kBlock), 0, s, N, c, cb.crange, cr.crec, cr.tq, cr.mp, cr.me,
+                           p->l_emit, cb.cperm, g.perm, r.b, r.dpt, r.r);
+        PG_TRY(hipGetLastError());
+    }
+    if (out && (out->row_ptr || out->col)) {
+        hipLaunchKernelGGL(k_crow_len, grid_of(N), dim3(kBlock), 0, s, N, cb.cinv, cb.crange, cr.rowlen);
+        PG_TRY(hipGetLastError());
+        PG_TRY(launch_fill(cr.rowlen + N, 4, s));
+        PG_TRY(launch_scan_exclusive(cr.rowlen, cr.rowlen, N + 1, cr.rowpart, s));
+        hipLaunchKernelGGL(k_cexport, grid_of(N + 1), dim3(kBlock), 0, s, N, c, cr.rowlen, cb.nedge,
+                           out->edge_capacity, cb.cinv, cb.crange, cb.cperm, g.perm, cr.crec, cr.tq, cr.wq, cr.mp,
+                           cr.me, out->row_ptr, out->col, out->w_ind, out->w_ph, out->w_env, g.flag);
+        PG_TRY(hipGetLastError());
+    }
+    if (out && out->b) PG_TRY(launch_permute3(N, cb.cinv, r.b, out->b, 1, s));
+    if (out && out->d_pt) PG_TRY(launch_permute3(N, cb.cinv, r.dpt, out->d_pt, 1, s));
+    float* x0 = r.x;
+    PG_TRY(launch_fill_value(r.succ, (size_t)N * 4, 0xffffffffu, s));
+    PG_TRY(launch_fill(x0, (size_t)N * 12, s));
+    {
+        ProfScope ps(s, "paths");
+        PG_TRY(launch_paths(r.P, N, p->path_offsets, cb.cinv, r.alpha, r.dpt, r.r, p->l_emit, q->init, r.succ,
+                            nullptr, x0, g.flag, s));
+    }
+    *x0_out = x0;
+    return hipSuccess;
+}
+
+hipError_t cluster_iterate(RenderBufs& r, const pg_params* q, float* x0, hipStream_t s, float** final_x) {
+    const int64_t N = r.N;
+    const HG rho = HG::make(q->g);
+    for (int t = 1; t <= r.D; ++t) {
+        {
+            ProfScope ps(s, "spmv");
+            hipLaunchKernelGGL(k_cagg, grid_of(N), dim3(kBlock), 0, s, N, rho, r.cl.crange, r.cr.tq, r.cr.wq, r.b,
+                               x0, r.y);
+            PG_TRY(hipGetLastError());
+        }
+        ProfScope ps(s, "shift");
+        PG_TRY(launch_shift(N, r.succ, r.y, x0, s));
+    }
+    *final_x = x0;
+    return hipSuccess;
+}
+
+hipError_t cluster_output(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out,
+                          float* image, const float* cur, hipStream_t s) {
+    const Consts c = make_consts(q, r.K);
+    const int64_t npix = (int64_t)p->width * p->height;
+    if (npix > 0) {
+        ProfScope ps(s, "pixels");
+        hipLaunchKernelGGL(k_cpixels, grid_of(npix), dim3(kBlock), 0, s, *p, c, r.cl.cinv, r.cl.crange, r.cr.tq,
+                           r.cr.wq, cur, r.dpt, r.r, image);
+        PG_TRY(hipGetLastError());
+    }
+    if (out && out->lplus) PG_TRY(launch_permute3(r.N, r.cl.cinv, cur, out->lplus, 1, s));
+    return hipSuccess;
+}
+
+}  // namespace pg

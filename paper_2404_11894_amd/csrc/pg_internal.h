@@ -23,7 +23,14 @@ enum : int32_t {
     kFlagPos = 1,       // non-finite or out-of-range position
     kFlagOffsets = 2,   // path offsets not monotone / out of range
     kFlagIndex = 4,     // neighbour id out of range in caller-provided CSR
+    kFlagCluster = 8,   // a cluster above kClusterMax members (keys not uniform)
+    kFlagCapacity = 16, // exported cluster edges exceed the caller's capacity
 };
+
+// Cluster neighbour relation: rounds of splitting large clusters, and the
+// largest cluster the kernels accept (far beyond what uniform keys produce).
+constexpr int kClusterRounds = 4;
+constexpr int kClusterMax = 4096;
 
 // ---------------------------------------------------------------- helpers --
 

@@ -15,6 +15,21 @@ void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params*
     r.D = q->D;
     r.schedule = resolve_schedule(q);
     r.tape = (q->flags & PG_FLAG_TAPE) != 0;
+    r.clusters = (q->flags & PG_FLAG_CLUSTERS) != 0;
+    if (r.clusters) {   // no stored edges: the weights are recomputed from the cluster order
+        carve_grid(cv, r.g, N, shift_of(q, N));
+        r.rec = cv.take<VRec>(N);
+        r.b = cv.take<float>(3 * N);
+        r.dpt = cv.take<float>(3 * N);
+        r.r = cv.take<float>(N);
+        r.alpha = cv.take<float>(N);
+        r.succ = cv.take<int32_t>(N);
+        r.x = cv.take<float>(3 * N);
+        r.y = cv.take<float>(3 * N);
+        carve_clusters(cv, r.cl, N, q->k);
+        carve_cluster_render(cv, r.cr, N);
+        return;
+    }
     const int64_t E = ell_size(N, r.K);   // sliced-ELL storage, padded to whole slices
     carve_grid(cv, r.g, N, shift_of(q, N));
     r.rec = cv.take<VRec>(N);
@@ -147,6 +162,13 @@ hipError_t run_render(const pg_paths* p, const pg_params* q, RenderBufs& r, cons
                       hipStream_t s, float** final_x) {
     float* x0 = nullptr;
     float* cur = nullptr;
+    if (r.clusters) {
+        PG_TRY(cluster_setup(p, q, r, out, s, &x0));
+        PG_TRY(cluster_iterate(r, q, x0, s, &cur));
+        PG_TRY(cluster_output(p, q, r, out, image, cur, s));
+        if (final_x) *final_x = cur;
+        return hipSuccess;
+    }
     PG_TRY(render_setup(p, q, r, out, s, &x0));
     PG_TRY(render_iterate(r, x0, s, &cur));
     PG_TRY(render_output(p, q, r, out, image, cur, s));

@@ -133,6 +133,28 @@ def test_paths_validation():
     assert L.pg_render_workspace_size(ctypes.byref(s), None, ctypes.byref(nb)) == pg.PG_ERR_ARG
 
 
+def test_cluster_flag_validation():
+    L = pg.lib()
+    nb = ctypes.c_size_t()
+    s = fake_paths()
+    q = pg.params(k=8, D=4, flags=pg.PG_FLAG_CLUSTERS)
+    rc, msg = status(L.pg_render_workspace_size, ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb))
+    assert rc == pg.PG_ERR_ARG and "cluster_key" in msg
+    s.cluster_key = 0x1000
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == 0
+    for flags, sched in ((pg.PG_FLAG_CLUSTERS | pg.PG_FLAG_TAPE, 0), (pg.PG_FLAG_CLUSTERS, pg.PG_SCHED_SHIFTED)):
+        qq = pg.params(k=8, D=4, flags=flags, schedule=sched)
+        rc, _ = status(L.pg_render_workspace_size, ctypes.byref(s), ctypes.byref(qq), ctypes.byref(nb))
+        assert rc == pg.PG_ERR_UNSUPPORTED
+    rc, _ = status(L.pg_backward_workspace_size, ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb))
+    assert rc == pg.PG_ERR_UNSUPPORTED
+    assert L.pg_clusters_workspace_size(ctypes.byref(s), 8, 0, ctypes.byref(nb)) == 0 and nb.value > 0
+    s.cluster_key = None
+    rc, _ = status(L.pg_clusters, ctypes.byref(s), 8, 0, ctypes.c_void_p(0x4000), ctypes.c_void_p(0x10000),
+                   nb.value, None)
+    assert rc == pg.PG_ERR_ARG
+
+
 def test_calls_reject_bad_workspace_before_launching():
     L = pg.lib()
     s, q = fake_paths(), pg.params(k=8, D=4)

@@ -1,0 +1,156 @@
+"""GPU parity of the cluster neighbour relation (PG_FLAG_CLUSTERS, pg_clusters)
+against the FP64 oracle: centres bit-exact, the exported CSR bit-exact,
+weights and direct terms within one FP32 evaluation, radiance and pixels
+within |err| <= max(1e-4 |ref|, 1e-5)."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+import paper_2404_11894_amd as pg
+from tests.gpu_util import PIX_ABS, PIX_REL, W_ABS, W_REL, assert_within, crop, synthetic
+
+pytestmark = pytest.mark.gpu
+
+
+def keyed(sc, seed=7):
+    return replace(sc, cluster_key=scenegen.cluster_keys(sc.n_vertices, seed))
+
+
+def gpu_centres(sc, k, shift=0):
+    c = pg.pg_clusters(pg.DevicePaths(sc), k, shift)
+    torch.cuda.synchronize()
+    return c.cpu().numpy()
+
+
+def gpu_cluster_render(sc, k, D, g, init="pt", fg=0):
+    paths = pg.DevicePaths(sc)
+    q = pg.params(k=k, D=D, g=g, init=init, final_gather=fg, flags=pg.PG_FLAG_CHECK | pg.PG_FLAG_CLUSTERS)
+    img, gr = pg.pg_render(paths, q, graph=True)
+    torch.cuda.synchronize()
+    return img.cpu().numpy(), {n: t.cpu().numpy() for n, t in gr.items()}
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return keyed(scenegen.generate(scenegen.WORKLOADS["tiny"].scene))
+
+
+@pytest.mark.parametrize("k", [1, 4, 8, 16, 64])
+def test_centres_match_oracle(tiny, k):
+    print(f"centres tiny N={tiny.n_vertices} k={k}", flush=True)
+    got = gpu_centres(tiny, k)
+    ref = oracle.clusters(tiny.pos, tiny.cluster_key, k)
+    assert np.array_equal(got, ref)
+
+
+def test_centres_with_splits_and_cell_sizes():
+    # a dense blob makes large initial clusters, so the split rounds run
+    rng = np.random.default_rng(9)
+    pos = np.concatenate([rng.random((3000, 3)) * 0.05 + 0.5, rng.random((3000, 3))]).astype(np.float32)
+    sc = synthetic(pos, rng)
+    sc = replace(sc, cluster_key=scenegen.cluster_keys(len(pos), 11))
+    ref = oracle.clusters(sc.pos, sc.cluster_key, 8)
+    assert np.bincount(ref).max() <= 16
+    for shift in (0, 12, 16, 20):
+        print(f"split case shift={shift}", flush=True)
+        assert np.array_equal(gpu_centres(sc, 8, shift), ref), shift
+
+
+def test_centres_duplicates_and_small_inputs():
+    rng = np.random.default_rng(2)
+    base = rng.random((50, 3)).astype(np.float32)
+    pos = np.repeat(base, 8, axis=0)                       # 8 coincident copies each: distance ties
+    sc = synthetic(pos, rng)
+    sc = replace(sc, cluster_key=scenegen.cluster_keys(len(pos), 3))
+    for k in (2, 8, 30):
+        print(f"duplicates k={k}", flush=True)
+        assert np.array_equal(gpu_centres(sc, k), oracle.clusters(sc.pos, sc.cluster_key, k)), k
+    for n in (1, 2, 5):
+        p = rng.random((n, 3)).astype(np.float32)
+        s2 = replace(synthetic(p, rng), cluster_key=scenegen.cluster_keys(n, 4))
+        assert np.array_equal(gpu_centres(s2, 16), oracle.clusters(p, s2.cluster_key, 16)), n
+
+
+def compare_graph(sc, img, gr, ref_img, ref, what):
+    assert np.array_equal(gr["row_ptr"], ref["row_ptr"]), what + " row_ptr"
+    assert np.array_equal(gr["col"], ref["col"]), what + " col"
+    for name in ("w_ind", "w_ph", "w_env"):
+        assert_within(gr[name], ref[name], W_REL, W_ABS, f"{what} {name}")
+    assert_within(gr["b"], ref["b"], W_REL, W_ABS, f"{what} b")
+    assert_within(gr["d_pt"], ref["d_pt"], W_REL, W_ABS, f"{what} d_pt")
+    assert_within(gr["lplus"], ref["lplus"], PIX_REL, PIX_ABS, f"{what} lplus")
+    assert_within(img, ref_img, PIX_REL, PIX_ABS, f"{what} image")
+
+
+def test_cluster_render_tiny_matches_oracle(tiny):
+    w = scenegen.WORKLOADS["tiny"]
+    print(f"cluster render tiny N={tiny.n_vertices}", flush=True)
+    img, gr = gpu_cluster_render(tiny, w.k, w.D, w.g)
+    ref_img, ref = oracle.render(tiny, oracle.params(k=w.k, D=w.D, g=w.g, neighbours="clusters"), trace=True)
+    compare_graph(tiny, img, gr, ref_img, ref, "tiny")
+
+
+@pytest.mark.parametrize("init,fg,k,emit", [("zero", 0, 8, False), ("pt", 1, 6, False), ("pt", 0, 16, True),
+                                            ("zero", 1, 3, True), ("pt", 0, 1, False)])
+def test_cluster_render_variants(init, fg, k, emit):
+    sc = keyed(crop("tiny", 32, 32, 2, emit_L=(3.0, 2.0, 1.0) if emit else None), seed=k)
+    print(f"cluster variant init={init} fg={fg} k={k} emit={emit} N={sc.n_vertices}", flush=True)
+    img, gr = gpu_cluster_render(sc, k, 6, 0.5, init=init, fg=fg)
+    ref_img, ref = oracle.render(sc, oracle.params(k=k, D=6, g=0.5, init=init, final_gather=fg,
+                                                   neighbours="clusters"), trace=True)
+    compare_graph(sc, img, gr, ref_img, ref, f"{init}/{fg}/{k}/{emit}")
+
+
+def test_cluster_render_is_deterministic(tiny):
+    a = gpu_cluster_render(tiny, 8, 8, 0.5)
+    b = gpu_cluster_render(tiny, 8, 8, 0.5)
+    assert np.array_equal(a[0], b[0])
+    for n in a[1]:
+        assert np.array_equal(a[1][n], b[1][n]), n
+
+
+def test_cluster_render_equals_knn_on_separated_groups():
+    # groups of K coincident points far apart, one centre each: the cluster
+    # relation and the k nearest relation are the same graph
+    rng = np.random.default_rng(4)
+    K, groups = 6, 60
+    centres = rng.random((groups, 3)) * 0.9 + 0.05
+    pos = np.repeat(centres, K, axis=0).astype(np.float32)
+    sc = synthetic(pos, rng, lengths=np.full(groups * K // 3, 3))
+    key = np.full(len(pos), 2 ** 32 - 1, np.uint32)
+    key[::K] = np.arange(groups, dtype=np.uint32)
+    sc = replace(sc, cluster_key=key)
+    paths = pg.DevicePaths(sc)
+    qk = pg.params(k=K, D=4, g=0.6, g_s=0.4, flags=pg.PG_FLAG_CHECK)
+    qc = pg.params(k=K, D=4, g=0.6, g_s=0.4, flags=pg.PG_FLAG_CHECK | pg.PG_FLAG_CLUSTERS)
+    ik = pg.pg_render(paths, qk)
+    ic = pg.pg_render(paths, qc)
+    torch.cuda.synchronize()
+    assert_within(ic.cpu().numpy(), ik.cpu().numpy(), 1e-5, 1e-7, "clusters vs knn")
+
+
+def test_cluster_empty_and_errors():
+    rng = np.random.default_rng(5)
+    P = 4 * 4 * 2
+    z = np.zeros((0, 3), np.float32)
+    sc = scenegen.Scene(width=4, height=4, spp=2, path_offsets=np.zeros(P + 1, np.int64), pos=z, dir_in=z,
+                        dir_out=z, albedo=np.zeros(0, np.float32), l_sun=z, dir_env=z, l_env=z, l_phase=z,
+                        e_cam=rng.random((P, 3), dtype=np.float32), cluster_key=np.zeros(0, np.uint32))
+    img, gr = gpu_cluster_render(sc, 8, 3, 0.5)
+    assert_within(img, sc.e_cam.reshape(4, 4, 2, 3).mean(2), 1e-6, 1e-7, "empty")
+    assert gr["row_ptr"].tolist() == [0]
+    # an export buffer smaller than the edges is refused, nothing written past it
+    s2 = keyed(crop("tiny", 16, 16, 1))
+    paths = pg.DevicePaths(s2)
+    q = pg.params(k=8, D=2, g=0.5, flags=pg.PG_FLAG_CLUSTERS)
+    N = s2.n_vertices
+    g = {"row_ptr": torch.empty(N + 1, dtype=torch.int64, device="cuda"),
+         "col": torch.full((N,), -7, dtype=torch.int32, device="cuda")}
+    with pytest.raises(pg.PathGraphError, match="edge_capacity"):
+        pg.Renderer(paths, q)(graph=g)
+    torch.cuda.synchronize()
+    assert (g["col"] == -7).all()
