@@ -13,6 +13,7 @@ value = E * D / step time  (E = N * K edges), in Gedge-updates/s.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
+import dataclasses
 import ctypes
 import hashlib
 import json
@@ -155,6 +156,55 @@ def time_fwd_adjoint(pg, torch, sc, w, steps, warmup):
             "workload": "same paths, albedo = trilinear 64^3 grid, L2 loss, grad wrt grid and g"}
 
 
+def time_clusters(pg, torch, sc, w, steps, warmup, knn_ms):
+    """The paper's own neighbour relation on the same paths: clusters of
+    expected size k around centres drawn by seeded uniform keys (seed 7).
+    One step = pg_render with PG_FLAG_CLUSTERS.  Counts E_c D, E_c = the sum
+    over clusters of size^2 (every member aggregates every member)."""
+    import scenegen
+    dev = torch.device("cuda:0")
+    sck = dataclasses.replace(sc, cluster_key=scenegen.cluster_keys(sc.n_vertices, 7))
+    paths = pg.DevicePaths(sck, device=dev)
+    centre = pg.pg_clusters(paths, w.k)
+    torch.cuda.synchronize()
+    size = torch.bincount(centre.to(torch.int64), minlength=sc.n_vertices)
+    nz = size[size > 0]
+    E = int((nz * nz).sum().item())
+    q = pg.params(k=w.k, D=w.D, g=w.g, flags=pg.PG_FLAG_CLUSTERS)
+    render = pg.Renderer(paths, q)
+    image = torch.empty(sc.height, sc.width, 3, device=dev)
+    for _ in range(warmup):
+        render(image)
+    torch.cuda.synchronize()
+    pg._check(pg.lib().pg_profile_start())
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        render(image)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    prof = profile_entries(pg)
+    phases = {k: round(v[1] / steps, 4) for k, v in prof.items()}
+    cnt, tot, _ = prof["spmv"]
+    avg_s = tot / cnt / 1e3
+    N = sc.n_vertices
+    # per row: (t, albedo) 16, range 8, b 12, y 12; each member's (w, 1/M+) 16 once, and its x: 12 read
+    # (first iteration) or successor id 4 + gathered y 12 (the others, propagation folded in)
+    ab = N * (76 + 80 * (w.D - 1)) / w.D
+    flops = 22 * E  # per edge: 1 - cos 9, HG 7 (one rsqrt), 1/M+ 1, accumulate 6 (FMA = 2)
+    del render, paths
+    torch.cuda.empty_cache()
+    return {"value": round(E * w.D / (ms / 1e3) / 1e9, 2), "unit": "Gedge-updates/s", "ms_per_step": round(ms, 3),
+            "vs_knn_render": round(knn_ms / ms, 3), "E": E, "clusters": int(nz.numel()),
+            "mean_size": round(N / max(1, int(nz.numel())), 2), "max_size": int(nz.max().item()),
+            "phases_ms": phases,
+            "aggregation": {"kernel": "k_cagg", "avg_launch_ms": round(avg_s * 1e3, 4),
+                            "algorithmic_bytes_per_launch": int(ab),
+                            "algorithmic_GBs": round(ab / avg_s / 1e9, 1), "hbm_frac": round(ab / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+                            "TFLOPs": round(flops / avg_s / 1e12, 2), "fp32_frac": round(flops / avg_s / 1e12 / 157.3, 4),
+                            "gedge_per_s_per_launch": round(E / avg_s / 1e9, 1)},
+            "workload": "same paths, cluster relation (k = expected cluster size), keys seed 7"}
+
+
 def time_batched(pg, torch, steps):
     """64 independent scenes: one hipGraph launch of a batch plan vs 64
     sequential pg_render calls.  Counts sum_s E_s D_s."""
@@ -209,6 +259,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-clusters", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run a 1 GiB device copy then the render steps (for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -291,6 +342,10 @@ def main():
     }
     del render
     torch.cuda.empty_cache()
+    if not args.no_clusters:
+        log("timing the cluster relation")
+        out["clusters"] = time_clusters(pg, torch, sc, w, args.steps, max(1, args.warmup), ms)
+        log(f"clusters {out['clusters']['ms_per_step']} ms/step, E = {out['clusters']['E']}")
     if not args.no_adjoint:
         log("timing forward + adjoint")
         out["fwd_adjoint"] = time_fwd_adjoint(pg, torch, sc, w, max(2, args.steps // 2), 1)

@@ -71,13 +71,12 @@ struct ClusterBufs {
     int bits = 0;                    // centre grid: 2^bits cells per axis
     int64_t ncells = 0;
     unsigned long long* kmin = nullptr;   // min (key << 32 | path id)
-    unsigned long long* nedge = nullptr;  // sum of the squared cluster sizes
-    uint32_t* ncent = nullptr;
+    unsigned long long* nedge = nullptr;  // sum of the squared cluster sizes (graph export)
+    unsigned long long* part = nullptr;   // per-block partials of the two reductions
     int32_t* live = nullptr;         // [0] = 1, [r+1]: round r split a cluster
-    int32_t* clist = nullptr;        // centres (sorted ids)
     uint32_t* gcount = nullptr;      // centre grid: counts, then starts
     uint32_t* gpart = nullptr;
-    uint32_t* gcell = nullptr;
+    uint32_t* gcell = nullptr;       // by sorted id (centres only): grid cell, rank in it
     uint32_t* grank = nullptr;
     uint64_t* gq = nullptr;          // centres in grid order: packed position,
     int32_t* gs = nullptr;           //   sorted id
@@ -89,7 +88,9 @@ struct ClusterBufs {
     uint32_t* cfill = nullptr;
     int32_t* members = nullptr;      // sorted ids grouped by centre
     uint32_t* mslot = nullptr;       // each vertex's slot in members
-    uint8_t* newc = nullptr;         // new centre in the current split round
+    unsigned long long* mkey = nullptr;   // by slot: key << 32 | path id
+    uint64_t* mq = nullptr;          // by slot: packed quantised position
+    uint8_t* newc = nullptr;         // by slot: new centre in the current split round
     int32_t* cperm = nullptr;        // position -> sorted id
     int32_t* cinv = nullptr;         // path id -> position
     uint2* crange = nullptr;         // position -> [first, end) position of its cluster
@@ -105,6 +106,7 @@ struct ClusterRender {
     float4* wq = nullptr;      // (continuation direction, 1 / M+ of it)
     float* mp = nullptr;       // M+ + C p_e
     float* me = nullptr;       // Me of the environment sample
+    float* y2 = nullptr;       // second aggregation buffer [N*3]
     uint32_t* rowlen = nullptr;   // export: row lengths, then row starts [N+1]
     uint32_t* rowpart = nullptr;
 };

@@ -24,6 +24,8 @@
 // reads 16 + 12 + 12 bytes of its own and its cluster's members' 16 + 12
 // bytes from L1/L2 (the members are contiguous and shared by the wave's
 // rows), against 8 bytes per edge plus a gather for the stored sliced ELL.
+#include <utility>
+
 #include "pg_api_common.h"
 
 namespace pg {
@@ -44,30 +46,69 @@ __device__ inline bool near_less(int64_t d1, int32_t p1, int64_t d2, int32_t p2)
 
 // ------------------------------------------------------------- centres ---
 
-// min over all vertices of (key << 32 | path id): one atomic per wave
-__global__ __launch_bounds__(kBlock) void k_key_min(int64_t N, const uint32_t* __restrict__ key,
-                                                    unsigned long long* __restrict__ kmin) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long m = v < N ? ((unsigned long long)key[v] << 32) | (unsigned long long)v : ~0ull;
+__device__ inline unsigned long long wave_min(unsigned long long m) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
         const unsigned long long t = __shfl_xor(m, o, kWave);
         m = t < m ? t : m;
     }
-    if (__lane_id() == 0 && m != ~0ull) atomicMin(kmin, m);
+    return m;
 }
 
-// centre flags in sorted order, compacted into clist (sorted ids)
-__global__ __launch_bounds__(kBlock) void k_centres(int64_t N, const int32_t* __restrict__ perm,
-                                                    const uint32_t* __restrict__ key, unsigned long long thr,
-                                                    const unsigned long long* __restrict__ kmin,
-                                                    int32_t* __restrict__ clist, uint32_t* __restrict__ ncent) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= N) return;
-    const int32_t pid = perm[s];
-    const bool c = (unsigned long long)key[pid] < thr || (uint32_t)(*kmin & 0xffffffffull) == (uint32_t)pid;
-    const uint32_t slot = wave_append(ncent, c);
-    if (c) clist[slot] = (int32_t)s;
+// min over all vertices of (key << 32 | path id): one partial per block ...
+__global__ __launch_bounds__(kBlock) void k_key_min(int64_t N, const uint32_t* __restrict__ key,
+                                                    unsigned long long* __restrict__ part) {
+    __shared__ unsigned long long sm[kBlock / kWave];
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long m = v < N ? ((unsigned long long)key[v] << 32) | (unsigned long long)v : ~0ull;
+    m = wave_min(m);
+    if (__lane_id() == 0) sm[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / kWave; ++w) m = sm[w] < m ? sm[w] : m;
+        part[blockIdx.x] = m;
+    }
+}
+
+// ... then one block over the partials
+__global__ __launch_bounds__(1024) void k_key_min_final(int64_t n, const unsigned long long* __restrict__ part,
+                                                        unsigned long long* __restrict__ kmin) {
+    __shared__ unsigned long long sm[1024 / kWave];
+    unsigned long long m = ~0ull;
+    for (int64_t t = threadIdx.x; t < n; t += 1024) m = part[t] < m ? part[t] : m;
+    m = wave_min(m);
+    if (__lane_id() == 0) sm[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 1024 / kWave; ++w) m = sm[w] < m ? sm[w] : m;
+        *kmin = m;
+    }
+}
+
+// Is sorted vertex s a centre?
+__device__ inline bool is_centre(int32_t pid, const uint32_t* __restrict__ key, unsigned long long thr,
+                                 const unsigned long long* __restrict__ kmin) {
+    return (unsigned long long)key[pid] < thr || (uint32_t)(*kmin & 0xffffffffull) == (uint32_t)pid;
+}
+
+// Adds one to counter[k] for every active lane and returns the lane's slot:
+// the counter's old value plus the lane's rank among the lanes with the
+// same k.  One atomic per distinct k in the wave (ballots group the lanes).
+__device__ inline uint32_t wave_count(uint32_t* counter, int32_t k) {
+    uint64_t todo = __ballot(1);
+    const int lane = (int)__lane_id();
+    uint32_t mine = 0;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int32_t kl = __shfl(k, leader, kWave);
+        const uint64_t m = __ballot(k == kl) & todo;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&counter[kl], (uint32_t)__popcll(m));
+        base = (uint32_t)__shfl((int)base, leader, kWave);
+        if ((m >> lane) & 1ull) mine = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        todo &= ~m;
+    }
+    return mine;
 }
 
 __device__ inline uint32_t cg_cell(uint64_t q, int b) {
@@ -77,33 +118,35 @@ __device__ inline uint32_t cg_cell(uint64_t q, int b) {
     return ((uint32_t)(z >> sh) << (2 * b)) | ((uint32_t)(y >> sh) << b) | (uint32_t)(x >> sh);
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_count(const uint32_t* __restrict__ ncent,
-                                                     const int32_t* __restrict__ clist,
+__global__ __launch_bounds__(kBlock) void k_cg_count(int64_t N, const int32_t* __restrict__ perm,
+                                                     const uint32_t* __restrict__ key, unsigned long long thr,
+                                                     const unsigned long long* __restrict__ kmin,
                                                      const uint64_t* __restrict__ qs, int b,
                                                      uint32_t* __restrict__ gcount, uint32_t* __restrict__ gcell,
                                                      uint32_t* __restrict__ grank) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)*ncent) return;
-    const uint32_t cell = cg_cell(qs[clist[t]], b);
-    gcell[t] = cell;
-    grank[t] = atomicAdd(&gcount[cell], 1u);
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N || !is_centre(perm[s], key, thr, kmin)) return;
+    const uint32_t cell = cg_cell(qs[s], b);
+    gcell[s] = cell;
+    grank[s] = atomicAdd(&gcount[cell], 1u);
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_scatter(const uint32_t* __restrict__ ncent,
-                                                       const int32_t* __restrict__ clist,
+__global__ __launch_bounds__(kBlock) void k_cg_scatter(int64_t N, const int32_t* __restrict__ perm,
+                                                       const uint32_t* __restrict__ key, unsigned long long thr,
+                                                       const unsigned long long* __restrict__ kmin,
                                                        const uint64_t* __restrict__ qs,
-                                                       const int32_t* __restrict__ perm,
                                                        const uint32_t* __restrict__ gcell,
                                                        const uint32_t* __restrict__ grank,
                                                        const uint32_t* __restrict__ gstart, uint64_t* __restrict__ gq,
                                                        int32_t* __restrict__ gs, int32_t* __restrict__ gpid) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)*ncent) return;
-    const int32_t s = clist[t];
-    const uint32_t pos = gstart[gcell[t]] + grank[t];
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const int32_t pid = perm[s];
+    if (!is_centre(pid, key, thr, kmin)) return;
+    const uint32_t pos = gstart[gcell[s]] + grank[s];
     gq[pos] = qs[s];
-    gs[pos] = s;
-    gpid[pos] = perm[s];
+    gs[pos] = (int32_t)s;
+    gpid[pos] = pid;
 }
 
 // Nearest centre of every vertex: rings of cells at Chebyshev distance r
@@ -165,20 +208,28 @@ __global__ __launch_bounds__(kBlock) void k_ccount(int64_t N, const int32_t* __r
                                                    uint32_t* __restrict__ ccount, const int32_t* __restrict__ live) {
     if (live && *live == 0) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < N) atomicAdd(&ccount[cid[s]], 1u);
+    if (s < N) (void)wave_count(ccount, cid[s]);
 }
 
+// Groups the vertices by centre.  Besides the sorted id, each slot keeps
+// the member's (key << 32 | path id) and packed position, so that the loops
+// over a group read contiguous memory.
 __global__ __launch_bounds__(kBlock) void k_cgroup(int64_t N, const int32_t* __restrict__ cid,
                                                    const uint32_t* __restrict__ cstart, uint32_t* __restrict__ cfill,
-                                                   int32_t* __restrict__ members, uint32_t* __restrict__ mslot,
-                                                   const int32_t* __restrict__ live) {
+                                                   const int32_t* __restrict__ perm, const uint32_t* __restrict__ key,
+                                                   const uint64_t* __restrict__ qs, int32_t* __restrict__ members,
+                                                   uint32_t* __restrict__ mslot, unsigned long long* __restrict__ mkey,
+                                                   uint64_t* __restrict__ mq, const int32_t* __restrict__ live) {
     if (live && *live == 0) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
     const int32_t c = cid[s];
-    const uint32_t slot = cstart[c] + atomicAdd(&cfill[c], 1u);
+    const uint32_t slot = cstart[c] + wave_count(cfill, c);
+    const int32_t pid = perm[s];
     members[slot] = (int32_t)s;
     mslot[s] = slot;
+    mkey[slot] = ((unsigned long long)key[pid] << 32) | (uint32_t)pid;
+    mq[slot] = qs[s];
 }
 
 // A cluster above kClusterMax members is reported (kFlagCluster) and its
@@ -191,15 +242,14 @@ __device__ inline uint2 bounded(uint2 rg) {
 // ----------------------------------------------------------- splitting ---
 
 // Members of a large cluster: the ceil(s/K) of smallest (key, path id)
-// become centres (newc).  O(s) per member.
+// become centres (newc, by group slot).  O(s) per member.
 __global__ __launch_bounds__(kBlock) void k_split_mark(int64_t N, int K, const int32_t* __restrict__ cid,
                                                        const uint32_t* __restrict__ ccount,
                                                        const uint32_t* __restrict__ cstart,
-                                                       const int32_t* __restrict__ members,
-                                                       const int32_t* __restrict__ perm,
-                                                       const uint32_t* __restrict__ key, uint8_t* __restrict__ newc,
-                                                       const int32_t* __restrict__ live, int32_t* __restrict__ split,
-                                                       int32_t* flag) {
+                                                       const uint32_t* __restrict__ mslot,
+                                                       const unsigned long long* __restrict__ mkey,
+                                                       uint8_t* __restrict__ newc, const int32_t* __restrict__ live,
+                                                       int32_t* __restrict__ split, int32_t* flag) {
     if (live && *live == 0) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
@@ -210,16 +260,13 @@ __global__ __launch_bounds__(kBlock) void k_split_mark(int64_t N, int K, const i
         set_flag(flag, kFlagCluster);
         return;
     }
-    const int32_t pid = perm[s];
-    const unsigned long long mine = ((unsigned long long)key[pid] << 32) | (uint32_t)pid;
+    const uint32_t me = mslot[s];
+    const unsigned long long mine = mkey[me];
     const uint32_t a = cstart[c];
     uint32_t rank = 0;
-    for (uint32_t e = a; e < a + sz; ++e) {
-        const int32_t pj = perm[members[e]];
-        rank += (((unsigned long long)key[pj] << 32) | (uint32_t)pj) < mine;
-    }
-    newc[s] = rank < (sz + (uint32_t)K - 1u) / (uint32_t)K;
-    *split = 1;
+    for (uint32_t e = a; e < a + sz; ++e) rank += mkey[e] < mine;
+    newc[me] = rank < (sz + (uint32_t)K - 1u) / (uint32_t)K;
+    if (__lane_id() == (uint32_t)(__ffsll((unsigned long long)__ballot(1)) - 1)) *split = 1;
 }
 
 // Members of a large cluster join the nearest of its new centres.
@@ -227,7 +274,8 @@ __global__ __launch_bounds__(kBlock) void k_split_assign(int64_t N, int K, const
                                                          int32_t* __restrict__ cid, const uint32_t* __restrict__ ccount,
                                                          const uint32_t* __restrict__ cstart,
                                                          const int32_t* __restrict__ members,
-                                                         const int32_t* __restrict__ perm,
+                                                         const unsigned long long* __restrict__ mkey,
+                                                         const uint64_t* __restrict__ mq,
                                                          const uint8_t* __restrict__ newc,
                                                          const int32_t* __restrict__ live) {
     if (live && *live == 0) return;
@@ -239,19 +287,19 @@ __global__ __launch_bounds__(kBlock) void k_split_assign(int64_t N, int K, const
     const uint64_t q = qs[s];
     const uint32_t a = cstart[c];
     int64_t bd = INT64_MAX;
-    int32_t bp = INT32_MAX, bs = c;
+    int32_t bp = INT32_MAX;
+    uint32_t be = a;
     for (uint32_t e = a; e < a + sz; ++e) {
-        const int32_t j = members[e];
-        if (!newc[j]) continue;
-        const int64_t d2 = qdist2(q, qs[j]);
-        const int32_t p = perm[j];
+        if (!newc[e]) continue;
+        const int64_t d2 = qdist2(q, mq[e]);
+        const int32_t p = (int32_t)(mkey[e] & 0xffffffffull);
         if (near_less(d2, p, bd, bp)) {
             bd = d2;
             bp = p;
-            bs = j;
+            be = e;
         }
     }
-    cid[s] = bs;
+    cid[s] = members[be];
 }
 
 // ----------------------------------------------------------- the order ---
@@ -262,11 +310,11 @@ __global__ __launch_bounds__(kBlock) void k_split_assign(int64_t N, int K, const
 __global__ __launch_bounds__(kBlock) void k_corder(int64_t N, const int32_t* __restrict__ cid,
                                                    const uint32_t* __restrict__ ccount,
                                                    const uint32_t* __restrict__ cstart,
-                                                   const int32_t* __restrict__ members,
                                                    const uint32_t* __restrict__ mslot,
+                                                   const unsigned long long* __restrict__ mkey,
                                                    const int32_t* __restrict__ perm, int32_t* __restrict__ cperm,
                                                    int32_t* __restrict__ cinv, uint2* __restrict__ crange,
-                                                   unsigned long long* __restrict__ nedge, int32_t* flag) {
+                                                   int32_t* flag) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t sz = 0;
     if (s < N) {
@@ -279,18 +327,13 @@ __global__ __launch_bounds__(kBlock) void k_corder(int64_t N, const int32_t* __r
             set_flag(flag, kFlagCluster);   // not ranked: the result is reported invalid
             rank = mslot[s] - a;
         } else {
-            for (uint32_t e = a; e < a + sz; ++e) rank += perm[members[e]] < pid;
+            for (uint32_t e = a; e < a + sz; ++e) rank += (int32_t)(mkey[e] & 0xffffffffull) < pid;
         }
         const uint32_t pos = a + rank;
         cperm[pos] = (int32_t)s;
         cinv[pid] = (int32_t)pos;
         crange[pos] = make_uint2(a, a + sz);
     }
-    // total edge count (each vertex's row has sz entries)
-    unsigned long long e = sz;
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) e += __shfl_xor(e, o, kWave);
-    if (__lane_id() == 0 && e) atomicAdd(nedge, e);
 }
 
 // Records in cluster order, plus (t, alpha) packed for the iteration.
@@ -315,7 +358,8 @@ __global__ __launch_bounds__(kBlock) void k_crec(int64_t N, const int32_t* __res
 
 // First pass: the marginals of every vertex's own samples over its cluster,
 //   M+(w_i) = sum_l p_l(w_i),  Me(we_i) = sum_l p_l(we_i) + C p_e,
-// stored as wq = (w_i, 1/M+), mp = M+ + C p_e, me = Me.
+// stored as wq = (w_i, c_g / M+) with c_g = (1 - g^2) / (4 pi) the HG
+// constant, mp = M+ + C p_e, me = Me.
 __global__ __launch_bounds__(kBlock) void k_cmarg(int64_t N, Consts c, const uint2* __restrict__ crange,
                                                   const VRec* __restrict__ crec, const float4* __restrict__ tq,
                                                   float4* __restrict__ wq, float* __restrict__ mp,
@@ -333,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_cmarg(int64_t N, Consts c, const uin
         menv += c.pdf(one_minus_cos(tl, we));
     }
     const float Cpe = (float)(rg.y - rg.x) * c.env_pdf;
-    wq[i] = make_float4(w.x, w.y, w.z, 1.0f / mplus);
+    wq[i] = make_float4(w.x, w.y, w.z, c.rho.c / mplus);
     mp[i] = mplus + Cpe;
     me[i] = menv + Cpe;
 }
@@ -387,13 +431,22 @@ __global__ __launch_bounds__(kBlock) void k_cedges(int64_t N, Consts c, const ui
 
 // ------------------------------------------------------- the iteration ---
 
+// HG_g(t, w) / c_g = ((1-g)^2 + g |t - w|^2)^(-3/2), the receiver's phase
+// without its constant (which the member's wq.w carries).
+__device__ __forceinline__ float hg_shape(const HG& rho, f3 t, float wx, float wy, float wz) {
+    const float dx = t.x - wx, dy = t.y - wy, dz = t.z - wz;
+    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float r = __frsqrt_rn(fmaf(0.5f * rho.two_g, d2, rho.a));
+    return r * r * r;
+}
+
 // sum_j rho_i(w_j) (1/M+_j) x_j over the cluster [a, e)
 __device__ __forceinline__ f3 cluster_gather(const HG& rho, f3 ti, uint2 rg, const float4* __restrict__ wq,
                                              const float* __restrict__ x) {
     float zx = 0.f, zy = 0.f, zz = 0.f;
     for (uint32_t j = rg.x; j < rg.y; ++j) {
         const float4 w4 = wq[j];
-        const float f = rho(one_minus_cos(ti, f3{w4.x, w4.y, w4.z})) * w4.w;
+        const float f = hg_shape(rho, ti, w4.x, w4.y, w4.z) * w4.w;
         const f3 xv = ld3(x, j);
         zx = fmaf(f, xv.x, zx);
         zy = fmaf(f, xv.y, zy);
@@ -402,15 +455,73 @@ __device__ __forceinline__ f3 cluster_gather(const HG& rho, f3 ti, uint2 rg, con
     return f3{zx, zy, zz};
 }
 
-// y_i = b_i + alpha_i sum_j w+_ij x_j, the weights recomputed (one thread per row)
+// y_i = b_i + alpha_i sum_j w+_ij x_j, the weights recomputed; one thread
+// per row.  The clusters of a block's rows cover one contiguous span of
+// positions (its rows plus the parts of the first and last cluster outside
+// the block); when the span fits kSpan, the members' (w, 1/M+) and x are
+// staged in LDS once, with coalesced loads, and every row sums from there.
+//
+// With SHIFTED the propagation is folded in: x is not stored, the members'
+// values are gathered as x_j = y_prev(succ j) (0 at a path's end), so one
+// launch per iteration replaces the aggregation and the shift.
+constexpr int kSpan = 512;
+template <bool SHIFTED>
 __global__ __launch_bounds__(kBlock) void k_cagg(int64_t N, HG rho, const uint2* __restrict__ crange,
                                                  const float4* __restrict__ tq, const float4* __restrict__ wq,
                                                  const float* __restrict__ b, const float* __restrict__ x,
-                                                 float* __restrict__ y) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                 const int32_t* __restrict__ succ, float* __restrict__ y) {
+    __shared__ float4 sw[kSpan];
+    __shared__ float sx[3 * kSpan];
+    const int64_t i0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t i = i0 + threadIdx.x;
+    const int64_t ilast = i0 + kBlock - 1 < N ? i0 + kBlock - 1 : N - 1;
+    const uint32_t lo = crange[i0].x, hi = crange[ilast].y;
+    const bool staged = hi - lo <= (uint32_t)kSpan;   // uniform over the block
+    if (staged) {
+        for (uint32_t t = threadIdx.x; t < hi - lo; t += kBlock) {
+            sw[t] = wq[lo + t];
+            if (SHIFTED) {
+                const int32_t sj = __builtin_nontemporal_load(succ + lo + t);
+                const f3 v = sj >= 0 ? ld3(x, sj) : f3{0.f, 0.f, 0.f};
+                sx[3 * t] = v.x;
+                sx[3 * t + 1] = v.y;
+                sx[3 * t + 2] = v.z;
+            }
+        }
+        if (!SHIFTED)
+            for (uint32_t t = threadIdx.x; t < 3 * (hi - lo); t += kBlock) sx[t] = x[3 * (int64_t)lo + t];
+        __syncthreads();
+    }
     if (i >= N) return;
     const float4 t4 = tq[i];
-    const f3 z = cluster_gather(rho, f3{t4.x, t4.y, t4.z}, bounded(crange[i]), wq, x);
+    const f3 ti{t4.x, t4.y, t4.z};
+    const uint2 rg = bounded(crange[i]);
+    f3 z;
+    if (staged) {
+        float zx = 0.f, zy = 0.f, zz = 0.f;
+        for (uint32_t j = rg.x - lo; j < rg.y - lo; ++j) {
+            const float4 w4 = sw[j];
+            const float f = hg_shape(rho, ti, w4.x, w4.y, w4.z) * w4.w;
+            zx = fmaf(f, sx[3 * j], zx);
+            zy = fmaf(f, sx[3 * j + 1], zy);
+            zz = fmaf(f, sx[3 * j + 2], zz);
+        }
+        z = f3{zx, zy, zz};
+    } else if (SHIFTED) {
+        float zx = 0.f, zy = 0.f, zz = 0.f;
+        for (uint32_t j = rg.x; j < rg.y; ++j) {
+            const float4 w4 = wq[j];
+            const float f = hg_shape(rho, ti, w4.x, w4.y, w4.z) * w4.w;
+            const int32_t sj = succ[j];
+            const f3 xv = sj >= 0 ? ld3(x, sj) : f3{0.f, 0.f, 0.f};
+            zx = fmaf(f, xv.x, zx);
+            zy = fmaf(f, xv.y, zy);
+            zz = fmaf(f, xv.z, zz);
+        }
+        z = f3{zx, zy, zz};
+    } else {
+        z = cluster_gather(rho, ti, rg, wq, x);
+    }
     const f3 bb = ld3(b, i);
     st3_nt(y, i, f3{fmaf(t4.w, z.x, bb.x), fmaf(t4.w, z.y, bb.y), fmaf(t4.w, z.z, bb.z)});
 }
@@ -459,12 +570,41 @@ __global__ __launch_bounds__(kBlock) void k_cpixels(pg_paths P, Consts c, const 
 
 // ---------------------------------------------------------- the export ---
 
+// Row lengths (path order) and one partial sum of them per block, in 64 bits.
 __global__ __launch_bounds__(kBlock) void k_crow_len(int64_t N, const int32_t* __restrict__ cinv,
-                                                     const uint2* __restrict__ crange, uint32_t* __restrict__ len) {
+                                                     const uint2* __restrict__ crange, uint32_t* __restrict__ len,
+                                                     unsigned long long* __restrict__ part) {
+    __shared__ unsigned long long sm[kBlock / kWave];
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= N) return;
-    const uint2 rg = crange[cinv[v]];
-    len[v] = rg.y - rg.x;
+    unsigned long long e = 0;
+    if (v < N) {
+        const uint2 rg = crange[cinv[v]];
+        len[v] = rg.y - rg.x;
+        e = rg.y - rg.x;
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) e += __shfl_xor(e, o, kWave);
+    if (__lane_id() == 0) sm[threadIdx.x / kWave] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / kWave; ++w) e += sm[w];
+        part[blockIdx.x] = e;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_sum_final(int64_t n, const unsigned long long* __restrict__ part,
+                                                    unsigned long long* __restrict__ total) {
+    __shared__ unsigned long long sm[1024 / kWave];
+    unsigned long long e = 0;
+    for (int64_t t = threadIdx.x; t < n; t += 1024) e += part[t];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) e += __shfl_xor(e, o, kWave);
+    if (__lane_id() == 0) sm[threadIdx.x / kWave] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 1024 / kWave; ++w) e += sm[w];
+        *total = e;
+    }
 }
 
 // Row v (path order) of the exported CSR: its cluster's members, ascending
@@ -497,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_cexport(int64_t N, Consts c, const u
         col[e] = perm[cperm[j]];
         const float4 w4 = wq[j];
         const float rho = c.rho(one_minus_cos(ti, f3{w4.x, w4.y, w4.z}));
-        if (w_ind) w_ind[e] = rho * w4.w;
+        if (w_ind) w_ind[e] = hg_shape(c.rho, ti, w4.x, w4.y, w4.z) * w4.w;
         if (w_ph) w_ph[e] = rho / mp[j];
         if (w_env) {
             const VRec& rj = crec[j];
@@ -520,9 +660,8 @@ void carve_clusters(Carver& cv, ClusterBufs& cb, int64_t N, int K) {
     cb.ncells = (int64_t)1 << (3 * cb.bits);
     cb.kmin = cv.take<unsigned long long>(32);
     cb.nedge = cv.take<unsigned long long>(32);
-    cb.ncent = cv.take<uint32_t>(64);
+    cb.part = cv.take<unsigned long long>(div_up(N, kBlock) + 1);
     cb.live = cv.take<int32_t>(64);   // [0] = 1, [1 + r] = a cluster was split in round r
-    cb.clist = cv.take<int32_t>(N);
     cb.gcount = cv.take<uint32_t>(cb.ncells + 1);
     cb.gpart = cv.take<uint32_t>(scan_partials_bytes(cb.ncells + 1) / 4);
     cb.gcell = cv.take<uint32_t>(N);
@@ -537,6 +676,8 @@ void carve_clusters(Carver& cv, ClusterBufs& cb, int64_t N, int K) {
     cb.cfill = cv.take<uint32_t>(N);
     cb.members = cv.take<int32_t>(N);
     cb.mslot = cv.take<uint32_t>(N);
+    cb.mkey = cv.take<unsigned long long>(N);
+    cb.mq = cv.take<uint64_t>(N);
     cb.newc = cv.take<uint8_t>(N);
     cb.cperm = cv.take<int32_t>(N);
     cb.cinv = cv.take<int32_t>(N);
@@ -552,14 +693,15 @@ void carve_clusters(Carver& cv, ClusterBufs& cb, int64_t N, int K) {
 static dim3 grid_of(int64_t n) { return dim3((unsigned)div_up(n > 0 ? n : 1, kBlock)); }
 
 // (Re)builds the grouping of the vertices by cluster: counts, starts, members.
-static hipError_t group(int64_t N, ClusterBufs& cb, const int32_t* live, hipStream_t s) {
+static hipError_t group(const pg_paths* p, const GridBufs& g, int64_t N, ClusterBufs& cb, const int32_t* live,
+                        hipStream_t s) {
     PG_TRY(launch_fill(cb.ccount, (size_t)(N + 1) * 4, s));
     PG_TRY(launch_fill(cb.cfill, (size_t)N * 4, s));
     hipLaunchKernelGGL(k_ccount, grid_of(N), dim3(kBlock), 0, s, N, cb.cid, cb.ccount, live);
     PG_TRY(hipGetLastError());
     PG_TRY(launch_scan_exclusive(cb.ccount, cb.cstart, N + 1, cb.cpart, s));
-    hipLaunchKernelGGL(k_cgroup, grid_of(N), dim3(kBlock), 0, s, N, cb.cid, cb.cstart, cb.cfill, cb.members,
-                       cb.mslot, live);
+    hipLaunchKernelGGL(k_cgroup, grid_of(N), dim3(kBlock), 0, s, N, cb.cid, cb.cstart, cb.cfill, g.perm,
+                       p->cluster_key, g.qs, cb.members, cb.mslot, cb.mkey, cb.mq, live);
     return hipGetLastError();
 }
 
@@ -568,24 +710,22 @@ hipError_t run_clusters(const pg_paths* p, GridBufs& g, ClusterBufs& cb, hipStre
     const int K = cb.K;
     PG_TRY(launch_fill(cb.nedge, 8, s));
     if (N == 0) return hipSuccess;
-    PG_TRY(launch_fill_value(cb.kmin, 8, 0xffffffffu, s));
-    PG_TRY(launch_fill(cb.ncent, 4, s));
     PG_TRY(launch_fill(cb.live, 64 * 4, s));
     PG_TRY(launch_fill_value(cb.live, 4, 1u, s));
-    hipLaunchKernelGGL(k_key_min, grid_of(N), dim3(kBlock), 0, s, N, p->cluster_key, cb.kmin);
+    const int64_t nb = div_up(N, kBlock);
+    hipLaunchKernelGGL(k_key_min, dim3((unsigned)nb), dim3(kBlock), 0, s, N, p->cluster_key, cb.part);
+    PG_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_key_min_final, dim3(1), dim3(1024), 0, s, nb, cb.part, cb.kmin);
     PG_TRY(hipGetLastError());
     const unsigned long long thr = (1ull << 32) / (unsigned long long)K;
-    hipLaunchKernelGGL(k_centres, grid_of(N), dim3(kBlock), 0, s, N, g.perm, p->cluster_key, thr, cb.kmin,
-                       cb.clist, cb.ncent);
-    PG_TRY(hipGetLastError());
     // uniform grid of the centres
     PG_TRY(launch_fill(cb.gcount, (size_t)(cb.ncells + 1) * 4, s));
-    hipLaunchKernelGGL(k_cg_count, grid_of(N), dim3(kBlock), 0, s, cb.ncent, cb.clist, g.qs, cb.bits, cb.gcount,
-                       cb.gcell, cb.grank);
+    hipLaunchKernelGGL(k_cg_count, grid_of(N), dim3(kBlock), 0, s, N, g.perm, p->cluster_key, thr, cb.kmin, g.qs,
+                       cb.bits, cb.gcount, cb.gcell, cb.grank);
     PG_TRY(hipGetLastError());
     PG_TRY(launch_scan_exclusive(cb.gcount, cb.gcount, cb.ncells + 1, cb.gpart, s));
-    hipLaunchKernelGGL(k_cg_scatter, grid_of(N), dim3(kBlock), 0, s, cb.ncent, cb.clist, g.qs, g.perm, cb.gcell,
-                       cb.grank, cb.gcount, cb.gq, cb.gs, cb.gpid);
+    hipLaunchKernelGGL(k_cg_scatter, grid_of(N), dim3(kBlock), 0, s, N, g.perm, p->cluster_key, thr, cb.kmin, g.qs,
+                       cb.gcell, cb.grank, cb.gcount, cb.gq, cb.gs, cb.gpid);
     PG_TRY(hipGetLastError());
     {
         ProfScope ps(s, "nearest_centre");
@@ -598,19 +738,19 @@ hipError_t run_clusters(const pg_paths* p, GridBufs& g, ClusterBufs& cb, hipStre
         ProfScope ps(s, "split");
         for (int r = 0; r < kClusterRounds; ++r) {
             const int32_t* live = cb.live + r;
-            PG_TRY(group(N, cb, live, s));
+            PG_TRY(group(p, g, N, cb, live, s));
             hipLaunchKernelGGL(k_split_mark, grid_of(N), dim3(kBlock), 0, s, N, K, cb.cid, cb.ccount, cb.cstart,
-                               cb.members, g.perm, p->cluster_key, cb.newc, live, cb.live + r + 1, g.flag);
+                               cb.mslot, cb.mkey, cb.newc, live, cb.live + r + 1, g.flag);
             PG_TRY(hipGetLastError());
             hipLaunchKernelGGL(k_split_assign, grid_of(N), dim3(kBlock), 0, s, N, K, g.qs, cb.cid, cb.ccount,
-                               cb.cstart, cb.members, g.perm, cb.newc, live);
+                               cb.cstart, cb.members, cb.mkey, cb.mq, cb.newc, live);
             PG_TRY(hipGetLastError());
         }
     }
     ProfScope ps(s, "cluster_order");
-    PG_TRY(group(N, cb, nullptr, s));
-    hipLaunchKernelGGL(k_corder, grid_of(N), dim3(kBlock), 0, s, N, cb.cid, cb.ccount, cb.cstart, cb.members,
-                       cb.mslot, g.perm, cb.cperm, cb.cinv, cb.crange, cb.nedge, g.flag);
+    PG_TRY(group(p, g, N, cb, nullptr, s));
+    hipLaunchKernelGGL(k_corder, grid_of(N), dim3(kBlock), 0, s, N, cb.cid, cb.ccount, cb.cstart, cb.mslot,
+                       cb.mkey, g.perm, cb.cperm, cb.cinv, cb.crange, g.flag);
     return hipGetLastError();
 }
 
@@ -636,6 +776,7 @@ void carve_cluster_render(Carver& cv, ClusterRender& cr, int64_t N) {
     cr.wq = cv.take<float4>(N);
     cr.mp = cv.take<float>(N);
     cr.me = cv.take<float>(N);
+    cr.y2 = cv.take<float>(3 * N);
     cr.rowlen = cv.take<uint32_t>(N + 1);
     cr.rowpart = cv.take<uint32_t>(scan_partials_bytes(N + 1) / 4);
 }
@@ -664,8 +805,12 @@ hipError_t cluster_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, c
         PG_TRY(hipGetLastError());
     }
     if (out && (out->row_ptr || out->col)) {
-        hipLaunchKernelGGL(k_crow_len, grid_of(N), dim3(kBlock), 0, s, N, cb.cinv, cb.crange, cr.rowlen);
+        hipLaunchKernelGGL(k_crow_len, grid_of(N), dim3(kBlock), 0, s, N, cb.cinv, cb.crange, cr.rowlen, cb.part);
         PG_TRY(hipGetLastError());
+        if (N > 0) {
+            hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(1024), 0, s, div_up(N, kBlock), cb.part, cb.nedge);
+            PG_TRY(hipGetLastError());
+        }
         PG_TRY(launch_fill(cr.rowlen + N, 4, s));
         PG_TRY(launch_scan_exclusive(cr.rowlen, cr.rowlen, N + 1, cr.rowpart, s));
         hipLaunchKernelGGL(k_cexport, grid_of(N + 1), dim3(kBlock), 0, s, N, c, cr.rowlen, cb.nedge,
@@ -687,19 +832,31 @@ hipError_t cluster_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, c
     return hipSuccess;
 }
 
+// Iteration 1 aggregates the stored L_0; iterations 2..D gather L_{t-1} =
+// y_{t-1}(succ) inside the aggregation (y ping-pongs between y and x); one
+// shift at the end materialises L_D.
 hipError_t cluster_iterate(RenderBufs& r, const pg_params* q, float* x0, hipStream_t s, float** final_x) {
     const int64_t N = r.N;
     const HG rho = HG::make(q->g);
-    for (int t = 1; t <= r.D; ++t) {
-        {
-            ProfScope ps(s, "spmv");
-            hipLaunchKernelGGL(k_cagg, grid_of(N), dim3(kBlock), 0, s, N, rho, r.cl.crange, r.cr.tq, r.cr.wq, r.b,
-                               x0, r.y);
-            PG_TRY(hipGetLastError());
-        }
-        ProfScope ps(s, "shift");
-        PG_TRY(launch_shift(N, r.succ, r.y, x0, s));
+    if (r.D == 0 || N == 0) {
+        *final_x = x0;
+        return hipSuccess;
     }
+    float* yp = r.y;      // y_1
+    float* yq = r.cr.y2;
+    for (int t = 1; t <= r.D; ++t) {
+        ProfScope ps(s, "spmv");
+        if (t == 1)
+            hipLaunchKernelGGL(k_cagg<false>, grid_of(N), dim3(kBlock), 0, s, N, rho, r.cl.crange, r.cr.tq, r.cr.wq,
+                               r.b, x0, r.succ, yp);
+        else
+            hipLaunchKernelGGL(k_cagg<true>, grid_of(N), dim3(kBlock), 0, s, N, rho, r.cl.crange, r.cr.tq, r.cr.wq,
+                               r.b, yp, r.succ, yq);
+        PG_TRY(hipGetLastError());
+        if (t > 1) std::swap(yp, yq);
+    }
+    ProfScope ps(s, "shift");
+    PG_TRY(launch_shift(N, r.succ, yp, x0, s));
     *final_x = x0;
     return hipSuccess;
 }
