@@ -205,6 +205,87 @@ def time_clusters(pg, torch, sc, w, steps, warmup, knn_ms):
             "workload": "same paths, cluster relation (k = expected cluster size), keys seed 7"}
 
 
+def study(pg, torch, w):
+    """Convergence and quality of the path graph on the workload's medium.
+
+    Convergence: with the paths of the workload fixed, the relative change of
+    the image and of L+ between iteration counts, for both initialisations.
+    Quality: at 1 spp over the full image, the mean squared error over the
+    centred 64x64 crop of plain path tracing (k = 1, D = 0), the path graph
+    (k nearest and clusters) and its iteration count, against a 1024-spp
+    path-traced reference of that crop (independent seed); mean of 4 seeds."""
+    import numpy as np
+    import scenegen
+    dev = torch.device("cuda:0")
+    res = {}
+
+    def render(paths, k, D, init="pt", clusters=False, lplus=False):
+        fl = pg.PG_FLAG_CLUSTERS if clusters else 0
+        q = pg.params(k=k, D=D, g=w.g, init=init, flags=fl)
+        if lplus:
+            r = pg.Renderer(paths, q)
+            img = torch.empty(paths.height, paths.width, 3, device=dev)
+            lp = torch.empty(paths.n_vertices, 3, device=dev)
+            r(img, graph={"lplus": lp})
+            return img.cpu().numpy().astype(np.float64), lp.cpu().numpy()
+        return pg.pg_render(paths, q).cpu().numpy().astype(np.float64)
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+    log("study: convergence")
+    sc = scenegen.generate(w.scene)
+    sck = pg.DevicePaths(dataclasses.replace(sc, cluster_key=scenegen.cluster_keys(sc.n_vertices, 7)), device=dev)
+    del sc
+    ts = [0, 1, 2, 3, 4, 6, 8, 10, 12, 16, 24, 32, 48, 64]
+    conv = {}
+    for init in ("pt", "zero"):
+        for clusters in (False, True):
+            imgs, lps = {}, {}
+            for t in ts:
+                imgs[t], lps[t] = render(sck, w.k, t, init, clusters, lplus=True)
+            last = ts[-1]
+            conv[f"{init}/{'clusters' if clusters else 'knn'}"] = {
+                "image_change_vs_D64": {t: round(rel(imgs[t], imgs[last]), 6) for t in ts[:-1]},
+                "lplus_step_change": {t: round(rel(lps[t], lps[ts[i - 1]]), 6) for i, t in enumerate(ts) if i > 0}}
+    res["convergence"] = conv
+    del sck, imgs, lps
+    torch.cuda.empty_cache()
+
+    log("study: 1-spp error against a 1024-spp reference")
+    x0, y0 = (w.scene.width - 64) // 2, (w.scene.height - 64) // 2
+    ref_cfg = dataclasses.replace(w.scene, spp=1024, crop=(x0, y0, 64, 64), seed=w.scene.seed + 1000)
+    ref_paths = pg.DevicePaths(scenegen.generate(ref_cfg), device=dev)
+    ref = render(ref_paths, 1, 0)
+    del ref_paths
+    torch.cuda.empty_cache()
+    Ds = [0, 1, 2, 4, 8, 16, 64]
+    mse = {"pt": []}
+    for D in Ds:
+        mse[f"knn_D{D}"] = []
+        mse[f"clusters_D{D}"] = []
+    for seed in range(4):
+        cfg = dataclasses.replace(w.scene, spp=1, seed=w.scene.seed + 2000 + seed)
+        s1 = scenegen.generate(cfg)
+        s1 = pg.DevicePaths(dataclasses.replace(s1, cluster_key=scenegen.cluster_keys(s1.n_vertices, 100 + seed)),
+                            device=dev)
+        crop = lambda im: im[y0:y0 + 64, x0:x0 + 64]  # noqa: E731
+        err = lambda im: float(((crop(im) - ref) ** 2).mean())  # noqa: E731
+        mse["pt"].append(err(render(s1, 1, 0)))
+        for D in Ds:
+            mse[f"knn_D{D}"].append(err(render(s1, w.k, D)))
+            mse[f"clusters_D{D}"].append(err(render(s1, w.k, D, clusters=True)))
+        del s1
+        torch.cuda.empty_cache()
+    m = {k: float(np.mean(v)) for k, v in mse.items()}
+    res["quality"] = {"mse": {k: round(v, 8) for k, v in m.items()},
+                      "mse_over_pt": {k: round(v / m["pt"], 4) for k, v in m.items()},
+                      "reference_mean": round(float(ref.mean()), 6), "seeds": 4,
+                      "setup": f"1 spp {w.scene.width}x{w.scene.height}, error on the centred 64x64 crop, "
+                               f"reference 1024 spp path tracing, k {w.k}"}
+    return res
+
+
 def time_batched(pg, torch, steps):
     """64 independent scenes: one hipGraph launch of a batch plan vs 64
     sequential pg_render calls.  Counts sum_s E_s D_s."""
@@ -260,6 +341,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-clusters", action="store_true")
+    ap.add_argument("--study", action="store_true",
+                    help="convergence and 1-spp error study instead of the timing (one JSON line)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run a 1 GiB device copy then the render steps (for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -274,6 +357,9 @@ def main():
     import paper_2404_11894_amd as pg
 
     w = scenegen.WORKLOADS[args.workload]
+    if args.study:
+        print(json.dumps({"study": args.workload, **study(pg, torch, w)}), flush=True)
+        return
     log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
     sc = scenegen.generate(w.scene)

@@ -105,6 +105,22 @@ def test_cluster_render_variants(init, fg, k, emit):
     compare_graph(sc, img, gr, ref_img, ref, f"{init}/{fg}/{k}/{emit}")
 
 
+def test_cluster_weights_column_stochastic_and_long_iteration_bounded(tiny):
+    # g = g_s: each sample's weights over its cluster's receivers sum to 1, so
+    # the iteration is a contraction (albedo < 1) and stays bounded at large D
+    paths = pg.DevicePaths(tiny)
+    q = pg.params(k=8, D=200, g=0.8, g_s=0.8, flags=pg.PG_FLAG_CHECK | pg.PG_FLAG_CLUSTERS)
+    img, gr = pg.pg_render(paths, q, graph=True)
+    torch.cuda.synchronize()
+    col, w = gr["col"].cpu().numpy(), gr["w_ind"].cpu().numpy().astype(np.float64)
+    colsum = np.bincount(col, weights=w, minlength=tiny.n_vertices)
+    assert np.abs(colsum - 1.0).max() < 2e-5
+    img = img.cpu().numpy()
+    ref = oracle.render(tiny, oracle.params(k=8, D=200, g=0.8, g_s=0.8, neighbours="clusters"))
+    assert_within(img, ref, PIX_REL, PIX_ABS, "D=200")
+    assert np.isfinite(img).all() and img.max() < 50.0
+
+
 def test_cluster_render_is_deterministic(tiny):
     a = gpu_cluster_render(tiny, 8, 8, 0.5)
     b = gpu_cluster_render(tiny, 8, 8, 0.5)

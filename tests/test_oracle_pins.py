@@ -582,6 +582,24 @@ def test_cluster_rows_share_one_marginal():
         assert abs(v * m - 1.0) <= 1e-6
 
 
+def test_cluster_weights_are_column_stochastic_when_g_equals_g_s():
+    # every receiver of a cluster is also one of its techniques, so with
+    # rho = p (g = g_s) the weights a sample gets over the cluster's
+    # receivers sum to exactly 1: sum_i rho_i(w_j) / sum_l p_l(w_j) = 1.
+    # The k nearest relation lacks this (neighbour sets are not shared).
+    sc = keyed(small_scene(12, 12, 2))
+    N = sc.n_vertices
+    for g in (0.8, 0.3, -0.2):
+        for neigh in ("clusters", "knn"):
+            _, tr = oracle.render(sc, oracle.params(k=8, D=1, g=g, g_s=g, neighbours=neigh), trace=True)
+            colsum = np.zeros(N)
+            np.add.at(colsum, tr["col"].ravel(), tr["w_ind"].ravel())
+            if neigh == "clusters":
+                assert np.allclose(colsum, 1.0, rtol=0, atol=1e-12), g
+            else:
+                assert colsum.max() > 1.2, g     # hubs: samples shared by many receivers
+
+
 @pytest.mark.parametrize("init", ["pt", "zero"])
 def test_cluster_single_member_reproduces_path_tracing(init):
     # k = 1: every key is below 2^32, every vertex is its own cluster
