@@ -205,6 +205,35 @@ def time_clusters(pg, torch, sc, w, steps, warmup, knn_ms):
             "workload": "same paths, cluster relation (k = expected cluster size), keys seed 7"}
 
 
+def time_tracer(pg, torch, w, host_gen_s, host_copy_s):
+    """Generating the workload's records on the GPU (pg_trace: count pass,
+    scan, record pass) against the host generator plus the copy to HBM."""
+    import scenegen
+    dev = torch.device("cuda:0")
+    sigma, alb, maj = scenegen.medium(w.scene)
+    st = scenegen.tracer_settings(w.scene)
+    rec = pg.pg_trace(st, sigma, alb, maj, device=dev)        # warm-up (and the grid upload)
+    torch.cuda.synchronize()
+    sg = torch.as_tensor(sigma).to(dev)
+    ag = None if alb is None else torch.as_tensor(alb).to(dev)
+    times = []
+    for _ in range(3):
+        del rec
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec = pg.pg_trace(st, sg, ag, maj, device=dev)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms = min(times) * 1e3
+    n = rec.n_vertices
+    del rec, sg, ag
+    torch.cuda.empty_cache()
+    return {"ms_device": round(ms, 2), "n_vertices": n, "paths": w.scene.width * w.scene.height * w.scene.spp,
+            "ms_host_generate": round(host_gen_s * 1e3, 1), "ms_host_to_device_copy": round(host_copy_s * 1e3, 1),
+            "speedup_vs_host_plus_copy": round((host_gen_s + host_copy_s) * 1e3 / ms, 2),
+            "note": "records traced twice on the device (count, then write); host: all cores of the box"}
+
+
 def study(pg, torch, w):
     """Convergence and quality of the path graph on the workload's medium.
 
@@ -341,6 +370,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-clusters", action="store_true")
+    ap.add_argument("--no-tracer", action="store_true")
     ap.add_argument("--study", action="store_true",
                     help="convergence and 1-spp error study instead of the timing (one JSON line)")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -363,9 +393,14 @@ def main():
     log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
     sc = scenegen.generate(w.scene)
-    log(f"N={sc.n_vertices} P={sc.n_paths} generated in {time.perf_counter() - t0:.1f} s")
+    host_gen_s = time.perf_counter() - t0
+    log(f"N={sc.n_vertices} P={sc.n_paths} generated in {host_gen_s:.1f} s")
     dev = torch.device("cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     paths = pg.DevicePaths(sc, device=dev)
+    torch.cuda.synchronize()
+    host_copy_s = time.perf_counter() - t0
     q = pg.params(k=w.k, D=w.D, g=w.g, schedule=args.schedule, cell_shift=args.cell_shift)
     N = sc.n_vertices
     K = min(w.k, N)
@@ -428,6 +463,10 @@ def main():
     }
     del render
     torch.cuda.empty_cache()
+    if not args.no_tracer:
+        log("timing the GPU path tracer")
+        out["tracer"] = time_tracer(pg, torch, w, host_gen_s, host_copy_s)
+        log(f"tracer {out['tracer']['ms_device']} ms on the device, N = {out['tracer']['n_vertices']}")
     if not args.no_clusters:
         log("timing the cluster relation")
         out["clusters"] = time_clusters(pg, torch, sc, w, args.steps, max(1, args.warmup), ms)

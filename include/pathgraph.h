@@ -182,6 +182,57 @@ pg_status pg_knn_workspace_size(const pg_paths* paths, int32_t k, int32_t cell_s
 pg_status pg_knn(const pg_paths* paths, int32_t k, int32_t cell_shift, int64_t* row_ptr, int32_t* col,
                  void* ws, size_t ws_bytes, void* stream);
 
+/* ---- upstream: the instrumented path tracer --------------------------------
+ * Paper Sec. "Volume Path Tracing" and Sec. "Rendering System" (instrumented
+ * path tracer), on the GPU: traces every path of a (cropped) image through a
+ * grid medium and writes the path-ordered vertex records that pg_paths
+ * describes, in HBM.  Medium: extinction sigma on an R^3 grid over [0,1]^3
+ * (nearest voxel, x fastest), vacuum outside; albedo per voxel or constant.
+ * Lights: a directional (delta) sun and a constant environment.  Per path: a
+ * jittered camera ray, analog delta tracking against `majorant`; at every
+ * collision a sun shadow ray and one uniform-sphere environment shadow ray
+ * (ratio-tracking transmittance) and a continuation sampled from HG(g) about
+ * the arriving direction; at most max_depth vertices; no Russian roulette.
+ * Random numbers: PCG32, one stream per pixel of the full image, seeded from
+ * (seed, sample) through splitmix64 (the pixel jitter takes the stream's
+ * first two numbers, y first; sphere and HG samples draw the azimuth number
+ * first).  Double precision, no contraction.  Paths are numbered pixel-major
+ * over the crop window, spp consecutive paths per pixel. */
+typedef struct pg_tracer {
+    int32_t R;                 /* grid resolution per axis */
+    int32_t width, height;     /* full image */
+    int32_t spp, max_depth;
+    int32_t crop_x0, crop_y0, crop_w, crop_h;   /* traced window; crop_w == 0: full image */
+    int32_t pad_;
+    const float* sigma;        /* [R^3] device: extinction coefficients */
+    const float* albedo;       /* [R^3] device, or NULL: albedo_const everywhere */
+    double albedo_const;
+    double majorant;           /* >= every sigma (the grid maximum); 0: no medium */
+    double g;                  /* HG parameter of the continuation sampling */
+    double cam_pos[3], look_at[3], vfov_deg;   /* pinhole camera, world up +y */
+    double sun_dir[3];         /* unit vector toward the sun */
+    double sun_E[3];           /* sun irradiance */
+    double env_L[3];           /* environment radiance */
+    uint64_t seed;
+} pg_tracer;
+
+/* Device output arrays of pg_trace_records ([N][3], albedo [N], e_cam [P][3]). */
+typedef struct pg_records {
+    float *pos, *dir_in, *dir_out, *albedo, *l_sun, *dir_env, *l_env, *l_phase, *e_cam;
+} pg_records;
+
+/* Pass 1: traces every path and writes path_offsets[P+1] (device); N to
+ * *n_vertices (host; the call synchronises the stream once). */
+pg_status pg_trace_workspace_size(const pg_tracer* t, size_t* bytes);
+pg_status pg_trace_count(const pg_tracer* t, int64_t* path_offsets, int64_t* n_vertices, void* ws,
+                         size_t ws_bytes, void* stream);
+/* Pass 2: traces the same paths again and writes their records at the
+ * offsets of pass 1 (same tracer settings and medium).  Offsets that do not
+ * match the paths return PG_ERR_INPUT; no record is written outside a path's
+ * slots.  Synchronises the stream once. */
+pg_status pg_trace_records(const pg_tracer* t, const int64_t* path_offsets, const pg_records* out, void* ws,
+                           size_t ws_bytes, void* stream);
+
 /* ---- step 1, the paper's relation: clusters ---------------------------------
  * Paper Sec. "Path Graph Framework" (disjoint clusters of about K points
  * around randomly chosen centres, large clusters split again) and Sec.

@@ -23,6 +23,7 @@ PG_SCHED_TWO_PASS, PG_SCHED_SHIFTED, PG_SCHED_SCATTER = 1, 2, 3
 PG_MAX_K = 64
 
 EXPORTS = ("pg_version", "pg_last_error", "pg_default_cell_shift", "pg_profile_start", "pg_profile_stop",
+           "pg_trace_workspace_size", "pg_trace_count", "pg_trace_records",
            "pg_knn_workspace_size", "pg_knn", "pg_clusters_workspace_size", "pg_clusters",
            "pg_edges_workspace_size", "pg_edges",
            "pg_propagate_workspace_size", "pg_propagate", "pg_gather",
@@ -44,6 +45,22 @@ class Paths(ctypes.Structure):
         (n, ctypes.c_void_p) for n in ("path_offsets", "pos", "dir_in", "dir_out", "albedo", "l_sun",
                                        "dir_env", "l_env", "l_phase", "e_cam", "albedo_grid", "l_emit",
                                        "cluster_key")]
+
+
+class Tracer(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("spp", ctypes.c_int32), ("max_depth", ctypes.c_int32), ("crop_x0", ctypes.c_int32),
+                ("crop_y0", ctypes.c_int32), ("crop_w", ctypes.c_int32), ("crop_h", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("sigma", ctypes.c_void_p), ("albedo", ctypes.c_void_p),
+                ("albedo_const", ctypes.c_double), ("majorant", ctypes.c_double), ("g", ctypes.c_double),
+                ("cam_pos", ctypes.c_double * 3), ("look_at", ctypes.c_double * 3), ("vfov_deg", ctypes.c_double),
+                ("sun_dir", ctypes.c_double * 3), ("sun_E", ctypes.c_double * 3), ("env_L", ctypes.c_double * 3),
+                ("seed", ctypes.c_uint64)]
+
+
+class Records(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("pos", "dir_in", "dir_out", "albedo", "l_sun", "dir_env", "l_env",
+                                               "l_phase", "e_cam")]
 
 
 class Params(ctypes.Structure):
@@ -84,6 +101,11 @@ def lib():
             "pg_profile_stop": (i32, [i32, ctypes.POINTER(ProfileEntry), ctypes.POINTER(ctypes.c_int32)]),
             "pg_knn_workspace_size": (i32, [P, i32, i32, sz]),
             "pg_knn": (i32, [P, i32, i32, vp, vp, vp, ctypes.c_size_t, vp]),
+            "pg_trace_workspace_size": (i32, [ctypes.POINTER(Tracer), sz]),
+            "pg_trace_count": (i32, [ctypes.POINTER(Tracer), vp, ctypes.POINTER(ctypes.c_int64), vp,
+                                     ctypes.c_size_t, vp]),
+            "pg_trace_records": (i32, [ctypes.POINTER(Tracer), vp, ctypes.POINTER(Records), vp, ctypes.c_size_t,
+                                       vp]),
             "pg_clusters_workspace_size": (i32, [P, i32, i32, sz]),
             "pg_clusters": (i32, [P, i32, i32, vp, vp, ctypes.c_size_t, vp]),
             "pg_edges_workspace_size": (i32, [P, Q, sz]),
@@ -247,6 +269,65 @@ def pg_knn(paths: DevicePaths, k: int, cell_shift: int = 0):
     _check(L.pg_knn(ctypes.byref(s), int(k), int(cell_shift), _ptr(row_ptr), _ptr(col), _ptr(ws), n,
                     _stream(paths.device)))
     return row_ptr, col
+
+
+class DeviceRecords:
+    """Path records traced on the GPU (pg_trace): device tensors with the
+    names DevicePaths reads, plus width / height / spp."""
+
+    def __init__(self, width, height, spp, tensors):
+        self.width, self.height, self.spp = width, height, spp
+        for name, t in tensors.items():
+            setattr(self, name, t)
+
+    @property
+    def n_vertices(self) -> int:
+        return int(self.pos.shape[0])
+
+
+def pg_trace(settings: dict, sigma, albedo=None, majorant=None, device="cuda") -> DeviceRecords:
+    """Trace every path of an image on the GPU (pg_trace_count, then
+    pg_trace_records).  ``settings``: R, width, height, spp, max_depth, crop
+    (x0, y0, w, h; w = 0 for the full image), albedo_const, g, cam_pos,
+    look_at, vfov_deg, sun_dir, sun_E, env_L, seed.  ``sigma`` / ``albedo``:
+    [R,R,R] (z, y, x) grids, numpy or torch; majorant defaults to sigma's max."""
+    torch = _torch()
+    dev = torch.device(device)
+    sg = torch.as_tensor(sigma).to(device=dev, dtype=torch.float32).contiguous()
+    al = None if albedo is None else torch.as_tensor(albedo).to(device=dev, dtype=torch.float32).contiguous()
+    t = Tracer()
+    t.R, t.width, t.height = int(settings["R"]), int(settings["width"]), int(settings["height"])
+    t.spp, t.max_depth = int(settings["spp"]), int(settings["max_depth"])
+    t.crop_x0, t.crop_y0, t.crop_w, t.crop_h = (int(v) for v in settings.get("crop", (0, 0, 0, 0)))
+    t.sigma = sg.data_ptr()
+    t.albedo = al.data_ptr() if al is not None else None
+    t.albedo_const = float(settings["albedo_const"])
+    t.majorant = float(sg.max().item()) if majorant is None else float(majorant)
+    t.g, t.vfov_deg = float(settings["g"]), float(settings["vfov_deg"])
+    for name in ("cam_pos", "look_at", "sun_dir", "sun_E", "env_L"):
+        getattr(t, name)[:] = [float(v) for v in settings[name]]
+    t.seed = int(settings["seed"])
+    w = t.crop_w if t.crop_w else t.width
+    h = t.crop_h if t.crop_w else t.height
+    P = w * h * t.spp
+    L = lib()
+    nb = ctypes.c_size_t()
+    _check(L.pg_trace_workspace_size(ctypes.byref(t), ctypes.byref(nb)))
+    _, ws, n = _workspace(nb.value, dev)
+    off = torch.empty(P + 1, dtype=torch.int64, device=dev)
+    N = ctypes.c_int64()
+    _check(L.pg_trace_count(ctypes.byref(t), _ptr(off), ctypes.byref(N), _ptr(ws), n, _stream(dev)))
+    N = int(N.value)
+    # at least one row each, so every pointer is valid (an empty tensor has none); the views keep n rows
+    f = lambda n, *sh: torch.empty(max(n, 1), *sh, dtype=torch.float32, device=dev)  # noqa: E731
+    base = {"pos": f(N, 3), "dir_in": f(N, 3), "dir_out": f(N, 3), "albedo": f(N), "l_sun": f(N, 3),
+            "dir_env": f(N, 3), "l_env": f(N, 3), "l_phase": f(N, 3), "e_cam": f(P, 3)}
+    r = Records()
+    for name, t_ in base.items():
+        setattr(r, name, t_.data_ptr())
+    ten = {"path_offsets": off, **{name: t_[:(P if name == "e_cam" else N)] for name, t_ in base.items()}}
+    _check(L.pg_trace_records(ctypes.byref(t), _ptr(off), ctypes.byref(r), _ptr(ws), n, _stream(dev)))
+    return DeviceRecords(w, h, t.spp, ten)
 
 
 def pg_clusters(paths: DevicePaths, k: int, cell_shift: int = 0):

@@ -219,6 +219,69 @@ pg_status pg_knn(const pg_paths* paths, int32_t k, int32_t cell_shift, int64_t* 
     return finish(s, nullptr, g.flag, 0);
 }
 
+// ---------------------------------------------------------------- trace ---
+
+static pg_status validate_tracer(const pg_tracer* t) {
+    if (!t) return fail(PG_ERR_ARG, "tracer is NULL");
+    if (t->R < 1 || t->R > 4096) return fail(PG_ERR_ARG, "R = %d outside [1, 4096]", t->R);
+    if (t->width < 1 || t->height < 1 || t->spp < 1 || t->max_depth < 1)
+        return fail(PG_ERR_ARG, "width, height, spp and max_depth must be >= 1");
+    if (t->crop_w && (t->crop_w < 1 || t->crop_h < 1 || t->crop_x0 < 0 || t->crop_y0 < 0 ||
+                      t->crop_x0 + t->crop_w > t->width || t->crop_y0 + t->crop_h > t->height))
+        return fail(PG_ERR_ARG, "invalid crop window");
+    if (!(std::fabs(t->g) < 1.0) || !(t->majorant >= 0.0) || !std::isfinite(t->majorant))
+        return fail(PG_ERR_ARG, "|g| < 1 and a finite majorant >= 0 are required");
+    if (!t->sigma) return fail(PG_ERR_ARG, "sigma is NULL");
+    const int64_t P = tracer_paths(t);
+    if (P >= (int64_t)INT32_MAX) return fail(PG_ERR_ARG, "too many paths");
+    if (P * (int64_t)t->max_depth >= (int64_t)UINT32_MAX)
+        return fail(PG_ERR_UNSUPPORTED, "paths x max_depth must stay below 2^32 vertices");
+    return PG_OK;
+}
+
+pg_status pg_trace_workspace_size(const pg_tracer* t, size_t* bytes) {
+    g_error.clear();
+    pg_status st = validate_tracer(t);
+    if (st) return st;
+    if (!bytes) return fail(PG_ERR_ARG, "bytes is NULL");
+    *bytes = trace_ws_size(t);
+    return PG_OK;
+}
+
+pg_status pg_trace_count(const pg_tracer* t, int64_t* path_offsets, int64_t* n_vertices, void* ws, size_t ws_bytes,
+                         void* stream) {
+    g_error.clear();
+    pg_status st = validate_tracer(t);
+    if (st) return st;
+    if (!path_offsets || !n_vertices) return fail(PG_ERR_ARG, "path_offsets and n_vertices are required");
+    if ((st = check_ws(ws, ws_bytes, trace_ws_size(t)))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = run_trace_count(t, path_offsets, nullptr, ws, s);
+    if (e != hipSuccess) return hip_fail(e, "trace");
+    if ((e = hipMemcpyAsync(n_vertices, path_offsets + tracer_paths(t), sizeof(int64_t), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return PG_OK;
+}
+
+pg_status pg_trace_records(const pg_tracer* t, const int64_t* path_offsets, const pg_records* out, void* ws,
+                           size_t ws_bytes, void* stream) {
+    g_error.clear();
+    pg_status st = validate_tracer(t);
+    if (st) return st;
+    if (!path_offsets || !out) return fail(PG_ERR_ARG, "path_offsets and out are required");
+    if (!out->pos || !out->dir_in || !out->dir_out || !out->albedo || !out->l_sun || !out->dir_env || !out->l_env ||
+        !out->l_phase || !out->e_cam)
+        return fail(PG_ERR_ARG, "every output array is required");
+    if ((st = check_ws(ws, ws_bytes, trace_ws_size(t)))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t* flag = nullptr;
+    hipError_t e = run_trace_write(t, path_offsets, *out, ws, s, &flag);
+    if (e != hipSuccess) return hip_fail(e, "trace");
+    return finish(s, nullptr, flag, PG_FLAG_CHECK);
+}
+
 // ------------------------------------------------------------- clusters ---
 
 static size_t clusters_size(const pg_paths* p, int32_t k, int shift) {

@@ -170,6 +170,13 @@ void carve_back(Carver& cv, BackBufs& bb, const RenderBufs& r, const pg_paths* p
 hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, BackBufs& bb, const float* gimg,
                         float* grad_grid, float* grad_alpha, float* grad_g, hipStream_t s);
 
+// The path tracer (pg_trace.hip).
+int64_t tracer_paths(const pg_tracer* t);
+size_t trace_ws_size(const pg_tracer* t);
+hipError_t run_trace_count(const pg_tracer* t, int64_t* path_offsets, float* e_cam, void* ws, hipStream_t s);
+hipError_t run_trace_write(const pg_tracer* t, const int64_t* path_offsets, const pg_records& o, void* ws,
+                           hipStream_t s, int32_t** flag_out);
+
 int resolve_schedule(const pg_params* q);
 void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params* q);
 // The three phases of run_render: grid + kNN + edges + path pass (returns the

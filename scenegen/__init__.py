@@ -84,6 +84,8 @@ def _load():
         lib.sg_fetch.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 10
         lib.sg_density.restype = ctypes.c_double
         lib.sg_density.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        lib.sg_albedo.restype = ctypes.c_int
+        lib.sg_albedo.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         lib.sg_release.restype = None
         lib.sg_release.argtypes = [ctypes.c_void_p]
         _lib = lib
@@ -240,6 +242,37 @@ def density(cfg: SceneConfig) -> tuple[np.ndarray, float]:
     finally:
         lib.sg_release(h)
     return out, maj
+
+
+def medium(cfg: SceneConfig) -> tuple[np.ndarray, np.ndarray | None, float]:
+    """The medium of ``cfg``: sigma_t [R,R,R] (z, y, x), the per-voxel albedo
+    grid (None when constant) and the majorant the tracer uses."""
+    lib = _load()
+    c = replace(cfg, width=1, height=1, spp=1, crop=(0, 0, 0, 0))._c()
+    nv = ctypes.c_int64()
+    npath = ctypes.c_int64()
+    err = ctypes.create_string_buffer(256)
+    h = lib.sg_trace(ctypes.byref(c), 0, ctypes.byref(nv), ctypes.byref(npath), err, 256)
+    if not h:
+        raise RuntimeError("scenegen: " + err.value.decode())
+    try:
+        sigma = np.empty((cfg.R, cfg.R, cfg.R), np.float32)
+        maj = lib.sg_density(h, sigma.ctypes.data_as(ctypes.c_void_p))
+        alb = np.empty((cfg.R, cfg.R, cfg.R), np.float32)
+        if lib.sg_albedo(h, alb.ctypes.data_as(ctypes.c_void_p)) != 0:
+            alb = None
+    finally:
+        lib.sg_release(h)
+    return sigma, alb, float(maj)
+
+
+def tracer_settings(cfg: SceneConfig) -> dict:
+    """Camera, lights, sampling and image settings of ``cfg`` as plain values
+    (the medium comes from ``medium``)."""
+    return {"R": cfg.R, "width": cfg.width, "height": cfg.height, "spp": cfg.spp, "max_depth": cfg.max_depth,
+            "crop": tuple(cfg.crop), "albedo_const": float(cfg.albedo[0]), "g": cfg.g,
+            "cam_pos": tuple(cfg.cam_pos), "look_at": tuple(cfg.look_at), "vfov_deg": cfg.vfov_deg,
+            "sun_dir": tuple(cfg.sun_dir), "sun_E": tuple(cfg.sun_E), "env_L": tuple(cfg.env_L), "seed": cfg.seed}
 
 
 def cluster_keys(n: int, seed: int = 7) -> np.ndarray:

@@ -353,7 +353,9 @@ static int trace_path(const handle* h, block* b, int X, int Y, int s, float ecam
     pcg32_seed(&rng, splitmix64(c->seed * 0x100000001B3ULL + (uint64_t)s), pixel);
 
     double d[3], o[3], p[3], t0, t1;
-    camera_ray(c, X, Y, rnd(&rng), rnd(&rng), d);
+    /* the pixel jitter takes the stream's first two numbers, y-jitter first */
+    double jy = rnd(&rng), jx = rnd(&rng);
+    camera_ray(c, X, Y, jx, jy, d);
     for (int a = 0; a < 3; ++a) o[a] = c->cam_pos[a];
     ecam[0] = ecam[1] = ecam[2] = 0.0f;
     if (!box_hit(o, d, &t0, &t1) || !delta_track(m, &rng, o, d, fmax(t0, 0.0), t1, p)) {
@@ -369,12 +371,14 @@ static int trace_path(const handle* h, block* b, int X, int Y, int s, float ecam
         /* sun shadow ray (delta light) */
         double Ts = ratio_track(m, &rng, p, c->sun_dir, exit_distance(p, c->sun_dir));
         for (int a = 0; a < 3; ++a) r[10 + a] = (float)(c->sun_E[a] * Ts);
-        /* environment shadow ray, uniform sphere */
-        sample_sphere(rnd(&rng), rnd(&rng), we);
+        /* environment shadow ray, uniform sphere (azimuth number drawn first) */
+        double v2 = rnd(&rng), v1 = rnd(&rng);
+        sample_sphere(v1, v2, we);
         double Te = ratio_track(m, &rng, p, we, exit_distance(p, we));
         for (int a = 0; a < 3; ++a) { r[13 + a] = (float)we[a]; r[16 + a] = (float)(c->env_L[a] * Te); }
-        /* phase-sampled continuation */
-        sample_hg(d, c->g, rnd(&rng), rnd(&rng), wo);
+        /* phase-sampled continuation (azimuth number drawn first) */
+        double h2 = rnd(&rng), h1 = rnd(&rng);
+        sample_hg(d, c->g, h1, h2, wo);
         for (int a = 0; a < 3; ++a) r[6 + a] = (float)wo[a];
         int last = (depth == c->max_depth - 1);
         int escaped = 0;
@@ -542,6 +546,15 @@ double sg_density(void* hp, float* sigma_out) {
     size_t n = (size_t)h->med.R * h->med.R * h->med.R;
     memcpy(sigma_out, h->med.sigma, n * sizeof(float));
     return h->med.majorant;
+}
+
+/* Copy the per-voxel albedo grid (R^3 floats, x fastest); 1 if the albedo is constant. */
+int sg_albedo(void* hp, float* albedo_out) {
+    handle* h = (handle*)hp;
+    if (!h->med.albedo) return 1;
+    size_t n = (size_t)h->med.R * h->med.R * h->med.R;
+    memcpy(albedo_out, h->med.albedo, n * sizeof(float));
+    return 0;
 }
 
 void sg_release(void* hp) { free_handle((handle*)hp); }

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 
 STRUCTS = {"pg_paths": "Paths", "pg_params": "Params", "pg_graph_out": "GraphOut",
-           "pg_profile_entry": "ProfileEntry"}
+           "pg_profile_entry": "ProfileEntry", "pg_tracer": "Tracer", "pg_records": "Records"}
 
 
 def test_ctypes_structs_match_the_header(tmp_path):
@@ -152,6 +152,25 @@ def test_cluster_flag_validation():
     s.cluster_key = None
     rc, _ = status(L.pg_clusters, ctypes.byref(s), 8, 0, ctypes.c_void_p(0x4000), ctypes.c_void_p(0x10000),
                    nb.value, None)
+    assert rc == pg.PG_ERR_ARG
+
+
+def test_tracer_validation():
+    L = pg.lib()
+    nb = ctypes.c_size_t()
+    t = pg.Tracer()
+    t.R, t.width, t.height, t.spp, t.max_depth = 8, 4, 4, 1, 3
+    t.sigma, t.majorant, t.g = 0x1000, 1.0, 0.5
+    assert L.pg_trace_workspace_size(ctypes.byref(t), ctypes.byref(nb)) == 0 and nb.value > 0
+    for field, bad in (("R", 0), ("spp", 0), ("max_depth", 0), ("g", 1.0), ("majorant", -1.0), ("sigma", None),
+                       ("crop_w", 5)):
+        tt = pg.Tracer.from_buffer_copy(t)
+        setattr(tt, field, bad)
+        if field == "crop_w":
+            tt.crop_h = 1
+        rc, msg = status(L.pg_trace_workspace_size, ctypes.byref(tt), ctypes.byref(nb))
+        assert rc == pg.PG_ERR_ARG and msg, field
+    rc, _ = status(L.pg_trace_count, ctypes.byref(t), None, None, None, 0, None)
     assert rc == pg.PG_ERR_ARG
 
 
