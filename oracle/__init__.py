@@ -50,7 +50,8 @@ class _Scene(ctypes.Structure):
                 ("pad_", ctypes.c_int32)] + [
         (name, ctypes.c_void_p) for name in ("path_offsets", "pos", "dir_in", "dir_out", "albedo",
                                              "l_sun", "dir_env", "l_env", "l_phase", "e_cam",
-                                             "l_emit", "cluster_key")]
+                                             "l_emit", "cluster_key", "fb_l_sun", "fb_dir_env",
+                                             "fb_l_env")] + [("n_extra", ctypes.c_int32), ("pad2_", ctypes.c_int32)]
 
 
 class _Params(ctypes.Structure):
@@ -139,11 +140,17 @@ class _Bound:
             self.arrays["l_emit"] = _f32(scene.l_emit, (N, 3))
         if getattr(scene, "cluster_key", None) is not None:   # cluster neighbour relation
             self.arrays["cluster_key"] = np.ascontiguousarray(scene.cluster_key, dtype=np.uint32).reshape(N)
+        M = 0
+        if getattr(scene, "fb_l_sun", None) is not None:       # extra first-vertex samples
+            M = int(np.asarray(scene.fb_l_sun).shape[1])
+            for name in ("fb_l_sun", "fb_dir_env", "fb_l_env"):
+                self.arrays[name] = _f32(getattr(scene, name), (P, M, 3))
         s = _Scene()
         s.n_vertices, s.n_paths = N, P
         s.width, s.height, s.spp = int(scene.width), int(scene.height), int(scene.spp)
         for name, arr in self.arrays.items():
             setattr(s, name, _p(arr))
+        s.n_extra = M
         self.c = s
         self.N, self.P = N, P
 

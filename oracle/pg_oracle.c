@@ -40,6 +40,14 @@
  *   - with delta tracking the propagation factor transmittance / free-flight
  *     pdf equals 1/sigma_t at the collision, which turns sigma_s * phase into
  *     albedo * phase; propagation therefore is a shift along the path;
+ *   - extra first-vertex samples (Sec. "Rendering System", handling direct
+ *     light): with M > 0 extra emitter samples recorded at a path's first
+ *     vertex, the pixel uses their emitter-sampling estimate
+ *       d_fb = (1/M) sum_m ( rho(sun) Ls_m + rho(we_m) Le_m / p_e )
+ *     in place of the non-aggregated direct term d_pt; the propagation keeps
+ *     using the aggregated direct term.  Emitter sampling alone is unbiased
+ *     for the sun and the environment, so the phase-sampled escape at v0
+ *     (part of d_pt) is not added again;
  *   - volume emission (Sec. "Radiative Transfer Equation in a Medium"): the
  *     direct incoming radiance is Q + G L_v.  With delta tracking, G L_v
  *     along the segment from v to its successor u is estimated at the
@@ -79,6 +87,11 @@ typedef struct or_scene {
     const float* e_cam;            /* [P][3] */
     const float* l_emit;           /* [N][3] or NULL: volume emission at the vertex */
     const uint32_t* cluster_key;   /* [N] uniform random keys (cluster neighbour relation) */
+    const float* fb_l_sun;         /* [P][M][3] extra first-vertex samples, or NULL: sun x transmittance */
+    const float* fb_dir_env;       /* [P][M][3] uniform-sphere environment directions */
+    const float* fb_l_env;         /* [P][M][3] environment radiance x transmittance */
+    int32_t n_extra;               /* M (0: no extra samples) */
+    int32_t pad2_;
 } or_scene;
 
 typedef struct or_params {
@@ -458,6 +471,33 @@ int or_albedo_from_grid(int64_t n, const float* pos, int32_t R, const float* gri
 
 /* ---------------------------------------------------------- forward render */
 
+/* Direct term of the pixel of path q with first vertex v0: the extra
+ * emitter samples' estimate when there are any, else d_pt (set by the
+ * caller).  With dg != NULL also its derivative with respect to g. */
+static void first_direct(const or_scene* s, const or_params* p, int64_t q, int64_t v0, double d[3], double dg[3]) {
+    const float* ti = s->dir_in + v0 * 3;
+    const int64_t M = s->n_extra;
+    double u_sun = one_minus_cos_d(ti, p->sun_dir);
+    double rs = or_hg(p->g, u_sun), hs = or_hg_dlog(p->g, u_sun);
+    for (int c = 0; c < 3; ++c) {
+        d[c] = 0.0;
+        if (dg) dg[c] = 0.0;
+    }
+    for (int64_t m = 0; m < M; ++m) {
+        const size_t o = ((size_t)q * M + m) * 3;
+        double u = one_minus_cos(ti, s->fb_dir_env + o);
+        double re = or_hg(p->g, u), he = or_hg_dlog(p->g, u);
+        for (int c = 0; c < 3; ++c) {
+            d[c] += (rs * s->fb_l_sun[o + c] + re * s->fb_l_env[o + c] / p->env_pdf) / (double)M;
+            if (dg) dg[c] += (rs * hs * s->fb_l_sun[o + c] + re * he * s->fb_l_env[o + c] / p->env_pdf) / (double)M;
+        }
+    }
+}
+
+static int has_extra(const or_scene* s) {
+    return s->n_extra > 0 && s->fb_l_sun && s->fb_dir_env && s->fb_l_env;
+}
+
 /* Volume emission leaving vertex i toward its predecessor, channel c. */
 static double emit(const or_scene* s, int64_t i, int c) {
     return s->l_emit ? (double)s->l_emit[i * 3 + c] : 0.0;
@@ -492,6 +532,7 @@ static int validate(const or_scene* s, const or_params* p) {
     if (!(fabs(p->g) < 1.0) || !(fabs(p->g_s) < 1.0) || !(p->env_pdf > 0.0)) return OR_ERR_ARG;
     if (p->neighbours != 0 && p->neighbours != 1) return OR_ERR_ARG;
     if (p->neighbours == 1 && s->n_vertices > 0 && !s->cluster_key) return OR_ERR_ARG;
+    if (s->n_extra < 0) return OR_ERR_ARG;
     if (s->path_offsets[0] != 0 || s->path_offsets[s->n_paths] != s->n_vertices) return OR_ERR_ARG;
     for (int64_t q = 0; q < s->n_paths; ++q)
         if (s->path_offsets[q + 1] < s->path_offsets[q]) return OR_ERR_ARG;
@@ -610,7 +651,8 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
     free(y);
     /* step 7: output of each path's first continuation edge, then pixels.
      * o_p = e_v0 + alpha_v0 (d_pt_v0 + sum_j w+_v0j L+_D(j))   (final_gather == 0)
-     * o_p = e_v0 + alpha_v0 (d_pt_v0 + r_v0 L+_D(v0))          (final_gather == 1) */
+     * o_p = e_v0 + alpha_v0 (d_pt_v0 + r_v0 L+_D(v0))          (final_gather == 1)
+     * (d_fb of the extra first-vertex samples in place of d_pt_v0 when given) */
     const double* LD = iterate(f, D, D);
     const int64_t npix = (int64_t)s->width * s->height;
     for (int64_t px = 0; px < npix * 3; ++px) image[px] = 0.0;
@@ -627,7 +669,9 @@ static int forward(const or_scene* s, const or_params* p, const double* alpha_ov
             } else {
                 for (int c = 0; c < 3; ++c) in[c] = f->r[v0] * LD[v0 * 3 + c];
             }
-            for (int c = 0; c < 3; ++c) o[c] = emit(s, v0, c) + f->alpha[v0] * (f->dpt[v0 * 3 + c] + in[c]);
+            double dd[3] = {f->dpt[v0 * 3], f->dpt[v0 * 3 + 1], f->dpt[v0 * 3 + 2]};
+            if (has_extra(s)) first_direct(s, p, q, v0, dd, NULL);
+            for (int c = 0; c < 3; ++c) o[c] = emit(s, v0, c) + f->alpha[v0] * (dd[c] + in[c]);
         }
         if (out_path)
             for (int c = 0; c < 3; ++c) out_path[q * 3 + c] = o[c];
@@ -703,6 +747,7 @@ int or_backward(const or_scene* s, const or_params* p, int32_t R, const float* g
         return OR_ERR_NOMEM;
     }
     const double* LD = f.traj + (size_t)D * N * 3;
+    double gfb = 0.0;   /* d/dg through the extra first-vertex samples */
 
     /* reverse of step 7 */
     for (int64_t q = 0; q < P; ++q) {
@@ -720,9 +765,18 @@ int or_backward(const or_scene* s, const or_params* p, int32_t R, const float* g
         } else {
             for (int c = 0; c < 3; ++c) in[c] = f.r[v0] * LD[v0 * 3 + c];
         }
-        for (int c = 0; c < 3; ++c) {
-            abar[v0] += ob[c] * (f.dpt[v0 * 3 + c] + in[c]);
-            dptbar[v0 * 3 + c] += f.alpha[v0] * ob[c];
+        if (has_extra(s)) {
+            double dd[3], ddg[3];
+            first_direct(s, p, q, v0, dd, ddg);
+            for (int c = 0; c < 3; ++c) {
+                abar[v0] += ob[c] * (dd[c] + in[c]);
+                gfb += f.alpha[v0] * ob[c] * ddg[c];
+            }
+        } else {
+            for (int c = 0; c < 3; ++c) {
+                abar[v0] += ob[c] * (f.dpt[v0 * 3 + c] + in[c]);
+                dptbar[v0 * 3 + c] += f.alpha[v0] * ob[c];
+            }
         }
         if (p->final_gather == 0) {
             for (int64_t a = rp[v0]; a < rp[v0 + 1]; ++a) {
@@ -794,7 +848,7 @@ int or_backward(const or_scene* s, const or_params* p, int32_t R, const float* g
         }
     }
     /* reverse of step 4 and of the weights' dependence on g */
-    double gg = 0.0;
+    double gg = gfb;
     for (int64_t i = 0; i < N && !rc; ++i) {
         const float* ti = s->dir_in + i * 3;
         double daggbar[3];

@@ -63,7 +63,7 @@ class _Config(ctypes.Structure):
         ("g", ctypes.c_double),
         ("cam_pos", ctypes.c_double * 3), ("look_at", ctypes.c_double * 3), ("vfov_deg", ctypes.c_double),
         ("sun_dir", ctypes.c_double * 3), ("sun_E", ctypes.c_double * 3), ("env_L", ctypes.c_double * 3),
-        ("seed", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64), ("extra_samples", ctypes.c_int32), ("pad2_", ctypes.c_int32),
     ]
 
 
@@ -84,6 +84,8 @@ def _load():
         lib.sg_fetch.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 10
         lib.sg_density.restype = ctypes.c_double
         lib.sg_density.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        lib.sg_fetch_extra.restype = ctypes.c_int
+        lib.sg_fetch_extra.argtypes = [ctypes.c_void_p] * 4
         lib.sg_albedo.restype = ctypes.c_int
         lib.sg_albedo.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         lib.sg_release.restype = None
@@ -122,6 +124,8 @@ class SceneConfig:
     emit_L: tuple = (0.0, 0.0, 0.0)
     emit_center: tuple = (0.5, 0.55, 0.5)
     emit_radius: float = 0.25
+    # extra emitter samples at each path's first vertex (sun + environment shadow rays, own stream)
+    extra_samples: int = 0
 
     def _c(self) -> _Config:
         c = _Config()
@@ -140,6 +144,7 @@ class SceneConfig:
         c.sun_E[:] = self.sun_E
         c.env_L[:] = self.env_L
         c.seed = self.seed
+        c.extra_samples = self.extra_samples
         return c
 
     @property
@@ -169,6 +174,10 @@ class Scene:
     config: SceneConfig | None = None
     l_emit: np.ndarray | None = None
     cluster_key: np.ndarray | None = None   # uint32 [N], see cluster_keys
+    # extra first-vertex emitter samples [P, M, 3] each (None: M = 0)
+    fb_l_sun: np.ndarray | None = None
+    fb_dir_env: np.ndarray | None = None
+    fb_l_env: np.ndarray | None = None
     sun_dir: tuple = SUN_DIR
     env_pdf: float = 1.0 / (4.0 * math.pi)
 
@@ -206,12 +215,18 @@ def generate(cfg: SceneConfig, threads: int = 0) -> Scene:
                           ptr(denv), ptr(le), ptr(lp), ptr(ecam))
         if rc != 0:
             raise RuntimeError("scenegen: fetch failed")
+        fb = None
+        if cfg.extra_samples > 0:
+            fb = tuple(np.zeros((P, cfg.extra_samples, 3), np.float32) for _ in range(3))
+            lib.sg_fetch_extra(h, *(ptr(a) for a in fb))
     finally:
         lib.sg_release(h)
     w, hgt = cfg.image_size
     return Scene(width=w, height=hgt, spp=cfg.spp, path_offsets=off, pos=pos, dir_in=din,
                  dir_out=dout, albedo=alb, l_sun=ls, dir_env=denv, l_env=le, l_phase=lp,
-                 e_cam=ecam, config=cfg, sun_dir=tuple(cfg.sun_dir), l_emit=emission(cfg, pos, alb))
+                 e_cam=ecam, config=cfg, sun_dir=tuple(cfg.sun_dir), l_emit=emission(cfg, pos, alb),
+                 fb_l_sun=fb[0] if fb else None, fb_dir_env=fb[1] if fb else None,
+                 fb_l_env=fb[2] if fb else None)
 
 
 def emission(cfg: SceneConfig, pos: np.ndarray, albedo: np.ndarray) -> np.ndarray | None:
@@ -272,7 +287,8 @@ def tracer_settings(cfg: SceneConfig) -> dict:
     return {"R": cfg.R, "width": cfg.width, "height": cfg.height, "spp": cfg.spp, "max_depth": cfg.max_depth,
             "crop": tuple(cfg.crop), "albedo_const": float(cfg.albedo[0]), "g": cfg.g,
             "cam_pos": tuple(cfg.cam_pos), "look_at": tuple(cfg.look_at), "vfov_deg": cfg.vfov_deg,
-            "sun_dir": tuple(cfg.sun_dir), "sun_E": tuple(cfg.sun_E), "env_L": tuple(cfg.env_L), "seed": cfg.seed}
+            "sun_dir": tuple(cfg.sun_dir), "sun_E": tuple(cfg.sun_E), "env_L": tuple(cfg.env_L), "seed": cfg.seed,
+            "extra_samples": cfg.extra_samples}
 
 
 def cluster_keys(n: int, seed: int = 7) -> np.ndarray:

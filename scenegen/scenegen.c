@@ -62,6 +62,8 @@ typedef struct sg_config {
     double sun_E[3];        /* sun irradiance (RGB) */
     double env_L[3];        /* constant environment radiance (RGB) */
     uint64_t seed;
+    int32_t extra_samples;  /* extra emitter samples at each path's first vertex */
+    int32_t pad2_;
 } sg_config;
 
 /* ------------------------------------------------------------------ RNG --- */
@@ -302,6 +304,7 @@ typedef struct {
     float* rec;       /* nv * REC */
     int32_t* count;   /* np */
     float* ecam;      /* np * 3 */
+    float* extra;     /* np * M * 9: (sun, env direction, env radiance) per extra sample, or NULL */
 } block;
 
 typedef struct {
@@ -344,8 +347,34 @@ static void camera_ray(const sg_config* c, int X, int Y, double u1, double u2, d
     normalize3(d);
 }
 
-/* Trace one path; appends its vertices to b and returns the vertex count (or -1). */
-static int trace_path(const handle* h, block* b, int X, int Y, int s, float ecam[3]) {
+/* Extra emitter samples at a path's first vertex p (paper, "Handling direct
+ * Light"): M pairs of a sun shadow ray and a uniform-sphere environment
+ * shadow ray, from their own PCG32 stream (the path's stream is untouched,
+ * so the paths do not depend on M).  Writes M * 9 floats. */
+static void extra_samples(const handle* h, uint64_t pixel, int s, const double p[3], float* out) {
+    const sg_config* c = &h->cfg;
+    const medium* m = &h->med;
+    pcg32 rng;
+    pcg32_seed(&rng, splitmix64(c->seed * 0x100000001B3ULL + (uint64_t)s) ^ 0x5851F42D4C957F2DULL, pixel);
+    for (int k = 0; k < c->extra_samples; ++k) {
+        float* o = out + (size_t)k * 9;
+        double Ts = ratio_track(m, &rng, p, c->sun_dir, exit_distance(p, c->sun_dir));
+        double v2 = rnd(&rng), v1 = rnd(&rng);
+        double we[3];
+        sample_sphere(v1, v2, we);
+        double Te = ratio_track(m, &rng, p, we, exit_distance(p, we));
+        for (int a = 0; a < 3; ++a) {
+            o[a] = (float)(c->sun_E[a] * Ts);
+            o[3 + a] = (float)we[a];
+            o[6 + a] = (float)(c->env_L[a] * Te);
+        }
+    }
+}
+
+/* Trace one path; appends its vertices to b and returns the vertex count (or -1).
+ * extra (M * 9 floats, zero-filled by the caller) receives the first vertex's
+ * extra emitter samples. */
+static int trace_path(const handle* h, block* b, int X, int Y, int s, float ecam[3], float* extra) {
     const sg_config* c = &h->cfg;
     const medium* m = &h->med;
     pcg32 rng;
@@ -362,6 +391,7 @@ static int trace_path(const handle* h, block* b, int X, int Y, int s, float ecam
         for (int a = 0; a < 3; ++a) ecam[a] = (float)c->env_L[a];
         return 0;
     }
+    if (extra && c->extra_samples > 0) extra_samples(h, pixel, s, p, extra);
     int nv = 0;
     for (int depth = 0; depth < c->max_depth; ++depth) {
         float r[REC];
@@ -436,6 +466,7 @@ static void free_handle(handle* h) {
             free(h->blocks[i].rec);
             free(h->blocks[i].count);
             free(h->blocks[i].ecam);
+            free(h->blocks[i].extra);
         }
         free(h->blocks);
     }
@@ -447,7 +478,7 @@ static void free_handle(handle* h) {
 void* sg_trace(const sg_config* cfg, int nthreads, int64_t* n_vertices, int64_t* n_paths,
                char* err, int errlen) {
     if (cfg->R < 1 || cfg->width < 1 || cfg->height < 1 || cfg->spp < 1 || cfg->max_depth < 1 ||
-        cfg->sigma_max < 0.0 || fabs(cfg->g) >= 1.0) {
+        cfg->sigma_max < 0.0 || fabs(cfg->g) >= 1.0 || cfg->extra_samples < 0 || cfg->extra_samples > 1024) {
         snprintf(err, errlen, "invalid scene configuration");
         return NULL;
     }
@@ -482,12 +513,14 @@ void* sg_trace(const sg_config* cfg, int nthreads, int64_t* n_vertices, int64_t*
         b->np = p1 - p0;
         b->count = (int32_t*)malloc((size_t)b->np * sizeof(int32_t));
         b->ecam = (float*)malloc((size_t)b->np * 3 * sizeof(float));
-        if (!b->count || !b->ecam) { fail = 1; continue; }
+        const size_t M9 = (size_t)cfg->extra_samples * 9;
+        b->extra = M9 ? (float*)calloc((size_t)b->np * M9, sizeof(float)) : NULL;
+        if (!b->count || !b->ecam || (M9 && !b->extra)) { fail = 1; continue; }
         for (int64_t p = p0; p < p1; ++p) {
             int64_t pix = p / cfg->spp;
             int s = (int)(p % cfg->spp);
             int X = cx0 + (int)(pix % cw), Y = cy0 + (int)(pix / cw);
-            int nv = trace_path(h, b, X, Y, s, b->ecam + (p - p0) * 3);
+            int nv = trace_path(h, b, X, Y, s, b->ecam + (p - p0) * 3, M9 ? b->extra + (p - p0) * M9 : NULL);
             if (nv < 0) { fail = 1; break; }
             b->count[p - p0] = nv;
         }
@@ -546,6 +579,30 @@ double sg_density(void* hp, float* sigma_out) {
     size_t n = (size_t)h->med.R * h->med.R * h->med.R;
     memcpy(sigma_out, h->med.sigma, n * sizeof(float));
     return h->med.majorant;
+}
+
+/* Copy the extra first-vertex emitter samples, [P][M] each of l_sun[3],
+ * dir_env[3], l_env[3] (zero for a path without vertices); 1 if M == 0. */
+int sg_fetch_extra(void* hp, float* fb_l_sun, float* fb_dir_env, float* fb_l_env) {
+    handle* h = (handle*)hp;
+    const int64_t M = h->cfg.extra_samples;
+    if (M == 0) return 1;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t bi = 0; bi < h->nblocks; ++bi) {
+        const block* b = &h->blocks[bi];
+        int64_t p0 = bi * h->paths_per_block;
+        for (int64_t i = 0; i < b->np; ++i)
+            for (int64_t k = 0; k < M; ++k) {
+                const float* e = b->extra + ((size_t)i * M + k) * 9;
+                const size_t o = ((size_t)(p0 + i) * M + k) * 3;
+                for (int a = 0; a < 3; ++a) {
+                    fb_l_sun[o + a] = e[a];
+                    fb_dir_env[o + a] = e[3 + a];
+                    fb_l_env[o + a] = e[6 + a];
+                }
+            }
+    }
+    return 0;
 }
 
 /* Copy the per-voxel albedo grid (R^3 floats, x fastest); 1 if the albedo is constant. */

@@ -342,6 +342,32 @@ def test_single_neighbour_with_volume_emission_reproduces_path_tracing(init, D):
     assert np.allclose(oracle.render(sc, p), ref, rtol=2e-6, atol=1e-12)
 
 
+def test_extra_first_vertex_samples_are_unbiased():
+    # one-vertex paths, nothing occluded, environment radiance (w_z + 2) and a
+    # sun of irradiance E: the pixel's direct term from M extra emitter
+    # samples estimates rho(sun) E + int rho (w_z + 2) = rho(sun) E + 2 + g t_z
+    rng = np.random.default_rng(21)
+    n, M, g = 20000, 3, 0.6
+    t = unit(rng, n)
+    pos = rng.random((n, 3)) * 0.9 + 0.05
+    sc = make_scene(pos, t, unit(rng, n), unit(rng, n))
+    dirs = unit(rng, n * M).reshape(n, M, 3)
+    E = np.array([0.7, 0.5, 0.3])
+    sc = replace(sc, fb_l_sun=np.broadcast_to(E, (n, M, 3)).astype(np.float32).copy(),
+                 fb_dir_env=dirs.astype(np.float32), fb_l_env=np.repeat(dirs[..., 2:3] + 2.0, 3, axis=2).astype(np.float32))
+    p = oracle.params(k=1, D=0, g=g, g_s=g)
+    img = oracle.render(sc, p).reshape(n, 3)
+    sd = np.asarray(p["sun_dir"])
+    rho_sun = hg_textbook(g, np.clip(t @ sd, -1, 1))
+    dev = img - rho_sun[:, None] * E[None, :] - (2.0 + g * t[:, 2])[:, None]
+    m, se = dev.mean(0), dev.std(0) / math.sqrt(n)
+    assert np.all(np.abs(m) < 5 * se + 1e-12), (m, se)
+    # the extra samples replace the path-traced direct term: without them the
+    # same pixels use d_pt, which these records (all zero) make 0
+    img0 = oracle.render(replace(sc, fb_l_sun=None, fb_dir_env=None, fb_l_env=None), p)
+    assert np.allclose(img0, 0.0)
+
+
 def test_zero_albedo_sees_first_collision_emission():
     # no scattering: a pixel averages what its camera rays see directly, the
     # environment if they escape and the emission of their first collision
@@ -653,9 +679,13 @@ def loss_and_grad(sc, p, grid, target):
 
 
 @pytest.mark.parametrize("init,fg,emit", [("pt", 0, False), ("zero", 0, False), ("pt", 1, False),
-                                           ("pt", 0, True), ("zero", 0, True)])
+                                           ("pt", 0, True), ("zero", 0, True), ("pt", 1, "extra")])
 def test_adjoint_matches_central_differences(init, fg, emit):
-    sc = small_scene(8, 8, 2, emit=emit)
+    if emit == "extra":
+        cfg = replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 8, 8, 2), extra_samples=3)
+        sc = scenegen.generate(cfg)
+    else:
+        sc = small_scene(8, 8, 2, emit=emit)
     rng = np.random.default_rng(5)
     R = 6
     grid = rng.uniform(0.6, 0.95, size=(R, R, R)).astype(np.float32)
