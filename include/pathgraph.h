@@ -106,6 +106,15 @@ typedef struct pg_paths {
     const uint32_t* cluster_key;  /* [N] or NULL: uniform random 32-bit keys drawn by the caller, one
                                      per vertex; they choose the cluster centres of pg_clusters and of
                                      PG_FLAG_CLUSTERS (required there) */
+    /* Extra emitter samples at each path's first vertex (Sec. "Rendering System", handling
+     * direct light), [P][n_extra][3] each, zero for a path without vertices: with n_extra > 0
+     * the pixel uses their estimate (1/M) sum_m (rho(sun) l_sun_m + rho(we_m) l_env_m / env_pdf)
+     * in place of the first vertex's d_pt; the propagation is unchanged. */
+    const float* fb_l_sun;        /* sun irradiance x shadow-ray transmittance */
+    const float* fb_dir_env;      /* unit uniform-sphere environment directions */
+    const float* fb_l_env;        /* environment radiance x shadow-ray transmittance */
+    int32_t n_extra;              /* M, 0..1024; 0: none (the three pointers are ignored) */
+    int32_t pad_;
 } pg_paths;
 
 /* Method parameters. */
@@ -203,7 +212,8 @@ typedef struct pg_tracer {
     int32_t width, height;     /* full image */
     int32_t spp, max_depth;
     int32_t crop_x0, crop_y0, crop_w, crop_h;   /* traced window; crop_w == 0: full image */
-    int32_t pad_;
+    int32_t extra_samples;     /* M extra emitter samples at each path's first vertex, 0..1024,
+                                  from a second stream per pixel (the paths do not depend on M) */
     const float* sigma;        /* [R^3] device: extinction coefficients */
     const float* albedo;       /* [R^3] device, or NULL: albedo_const everywhere */
     double albedo_const;
@@ -216,9 +226,11 @@ typedef struct pg_tracer {
     uint64_t seed;
 } pg_tracer;
 
-/* Device output arrays of pg_trace_records ([N][3], albedo [N], e_cam [P][3]). */
+/* Device output arrays of pg_trace_records ([N][3], albedo [N], e_cam [P][3],
+ * fb_* [P][M][3], required when extra_samples > 0, zero for an escaped path). */
 typedef struct pg_records {
     float *pos, *dir_in, *dir_out, *albedo, *l_sun, *dir_env, *l_env, *l_phase, *e_cam;
+    float *fb_l_sun, *fb_dir_env, *fb_l_env;
 } pg_records;
 
 /* Pass 1: traces every path and writes path_offsets[P+1] (device); N to
@@ -292,8 +304,9 @@ pg_status pg_propagate(const pg_paths* paths, const pg_params* params, const int
  * path p with first vertex v0 outputs
  *   o_p = e_v0 + albedo_v0 (d_pt_v0 + sum_j w_ind_v0j L(j))        (final_gather = 0)
  *   o_p = e_v0 + albedo_v0 (d_pt_v0 + rho_v0(w_v0)/p_v0(w_v0) L(v0)) (final_gather = 1)
- * (0 for an empty path) and image[pixel] = mean over its spp paths of
- * (e_cam_p + o_p).  image is [height][width][3].  No workspace. */
+ * (0 for an empty path; d_pt_v0 replaced by the extra first-vertex samples'
+ * estimate when paths->n_extra > 0) and image[pixel] = mean over its spp
+ * paths of (e_cam_p + o_p).  image is [height][width][3].  No workspace. */
 pg_status pg_gather(const pg_paths* paths, const pg_params* params, const int64_t* row_ptr, const int32_t* col,
                     const float* w_ind, const float* d_pt, const float* lplus, float* image, void* stream);
 

@@ -44,14 +44,15 @@ class Paths(ctypes.Structure):
                 ("albedo_grid_res", ctypes.c_int32)] + [
         (n, ctypes.c_void_p) for n in ("path_offsets", "pos", "dir_in", "dir_out", "albedo", "l_sun",
                                        "dir_env", "l_env", "l_phase", "e_cam", "albedo_grid", "l_emit",
-                                       "cluster_key")]
+                                       "cluster_key", "fb_l_sun", "fb_dir_env", "fb_l_env")] + [
+        ("n_extra", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class Tracer(ctypes.Structure):
     _fields_ = [("R", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("spp", ctypes.c_int32), ("max_depth", ctypes.c_int32), ("crop_x0", ctypes.c_int32),
                 ("crop_y0", ctypes.c_int32), ("crop_w", ctypes.c_int32), ("crop_h", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("sigma", ctypes.c_void_p), ("albedo", ctypes.c_void_p),
+                ("extra_samples", ctypes.c_int32), ("sigma", ctypes.c_void_p), ("albedo", ctypes.c_void_p),
                 ("albedo_const", ctypes.c_double), ("majorant", ctypes.c_double), ("g", ctypes.c_double),
                 ("cam_pos", ctypes.c_double * 3), ("look_at", ctypes.c_double * 3), ("vfov_deg", ctypes.c_double),
                 ("sun_dir", ctypes.c_double * 3), ("sun_E", ctypes.c_double * 3), ("env_L", ctypes.c_double * 3),
@@ -60,7 +61,7 @@ class Tracer(ctypes.Structure):
 
 class Records(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("pos", "dir_in", "dir_out", "albedo", "l_sun", "dir_env", "l_env",
-                                               "l_phase", "e_cam")]
+                                               "l_phase", "e_cam", "fb_l_sun", "fb_dir_env", "fb_l_env")]
 
 
 class Params(ctypes.Structure):
@@ -185,6 +186,10 @@ class DevicePaths:
             device=self.device, dtype=torch.float32).contiguous()
         self.cluster_key = None
         self.set_cluster_key(getattr(scene, "cluster_key", None))
+        self.fb = None   # extra first-vertex samples [P, M, 3] x 3
+        if getattr(scene, "fb_l_sun", None) is not None:
+            self.fb = {n: torch.as_tensor(getattr(scene, n)).to(device=self.device, dtype=torch.float32).contiguous()
+                       for n in ("fb_l_sun", "fb_dir_env", "fb_l_env")}
         self.albedo_grid = None
         self.set_albedo_grid(albedo_grid)
 
@@ -216,6 +221,10 @@ class DevicePaths:
             s.l_emit = self.l_emit.data_ptr()
         if self.cluster_key is not None and self.cluster_key.numel():
             s.cluster_key = self.cluster_key.data_ptr()
+        if self.fb is not None and self.fb["fb_l_sun"].numel():
+            for n, t in self.fb.items():
+                setattr(s, n, t.data_ptr())
+            s.n_extra = int(self.fb["fb_l_sun"].shape[1])
         return s
 
 
@@ -307,6 +316,7 @@ def pg_trace(settings: dict, sigma, albedo=None, majorant=None, device="cuda") -
     for name in ("cam_pos", "look_at", "sun_dir", "sun_E", "env_L"):
         getattr(t, name)[:] = [float(v) for v in settings[name]]
     t.seed = int(settings["seed"])
+    t.extra_samples = int(settings.get("extra_samples", 0))
     w = t.crop_w if t.crop_w else t.width
     h = t.crop_h if t.crop_w else t.height
     P = w * h * t.spp
@@ -322,10 +332,15 @@ def pg_trace(settings: dict, sigma, albedo=None, majorant=None, device="cuda") -
     f = lambda n, *sh: torch.empty(max(n, 1), *sh, dtype=torch.float32, device=dev)  # noqa: E731
     base = {"pos": f(N, 3), "dir_in": f(N, 3), "dir_out": f(N, 3), "albedo": f(N), "l_sun": f(N, 3),
             "dir_env": f(N, 3), "l_env": f(N, 3), "l_phase": f(N, 3), "e_cam": f(P, 3)}
+    M = t.extra_samples
+    if M > 0:
+        for name in ("fb_l_sun", "fb_dir_env", "fb_l_env"):
+            base[name] = torch.empty(max(P, 1), M, 3, dtype=torch.float32, device=dev)
     r = Records()
     for name, t_ in base.items():
         setattr(r, name, t_.data_ptr())
-    ten = {"path_offsets": off, **{name: t_[:(P if name == "e_cam" else N)] for name, t_ in base.items()}}
+    ten = {"path_offsets": off,
+           **{name: t_[:(P if name == "e_cam" or name.startswith("fb_") else N)] for name, t_ in base.items()}}
     _check(L.pg_trace_records(ctypes.byref(t), _ptr(off), ctypes.byref(r), _ptr(ws), n, _stream(dev)))
     return DeviceRecords(w, h, t.spp, ten)
 

@@ -54,6 +54,9 @@ pg_status validate_paths(const pg_paths* p, bool need_records) {
     }
     if (p->albedo_grid && (p->albedo_grid_res < 1 || p->albedo_grid_res > 1024))
         return fail(PG_ERR_ARG, "albedo_grid_res must be in [1, 1024]");
+    if (p->n_extra < 0 || p->n_extra > 1024) return fail(PG_ERR_ARG, "n_extra must be in [0, 1024]");
+    if (p->n_extra > 0 && p->n_paths > 0 && (!p->fb_l_sun || !p->fb_dir_env || !p->fb_l_env))
+        return fail(PG_ERR_ARG, "n_extra > 0 needs fb_l_sun, fb_dir_env and fb_l_env");
     return PG_OK;
 }
 
@@ -229,6 +232,7 @@ static pg_status validate_tracer(const pg_tracer* t) {
     if (t->crop_w && (t->crop_w < 1 || t->crop_h < 1 || t->crop_x0 < 0 || t->crop_y0 < 0 ||
                       t->crop_x0 + t->crop_w > t->width || t->crop_y0 + t->crop_h > t->height))
         return fail(PG_ERR_ARG, "invalid crop window");
+    if (t->extra_samples < 0 || t->extra_samples > 1024) return fail(PG_ERR_ARG, "extra_samples must be in [0, 1024]");
     if (!(std::fabs(t->g) < 1.0) || !(t->majorant >= 0.0) || !std::isfinite(t->majorant))
         return fail(PG_ERR_ARG, "|g| < 1 and a finite majorant >= 0 are required");
     if (!t->sigma) return fail(PG_ERR_ARG, "sigma is NULL");
@@ -274,6 +278,8 @@ pg_status pg_trace_records(const pg_tracer* t, const int64_t* path_offsets, cons
     if (!out->pos || !out->dir_in || !out->dir_out || !out->albedo || !out->l_sun || !out->dir_env || !out->l_env ||
         !out->l_phase || !out->e_cam)
         return fail(PG_ERR_ARG, "every output array is required");
+    if (t->extra_samples > 0 && (!out->fb_l_sun || !out->fb_dir_env || !out->fb_l_env))
+        return fail(PG_ERR_ARG, "extra_samples > 0 needs fb_l_sun, fb_dir_env and fb_l_env");
     if ((st = check_ws(ws, ws_bytes, trace_ws_size(t)))) return st;
     hipStream_t s = (hipStream_t)stream;
     int32_t* flag = nullptr;

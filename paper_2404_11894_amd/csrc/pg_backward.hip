@@ -174,9 +174,10 @@ __global__ __launch_bounds__(kBlock) void k_tsort(int64_t N, uint32_t cap, const
 }
 
 // ------------------------------------------------- reverse of the output ---
-// One thread per path.  o_p = e + alpha (d_pt + in), in = sum_l w_l L_D(j_l)
-// (own sample: r L_D(v0)), e the constant emission; seeds the adjoint of L_D
-// (lam), of alpha, d_pt, r.
+// One thread per path.  o_p = e + alpha (d + in), in = sum_l w_l L_D(j_l)
+// (own sample: r L_D(v0)), e the constant emission, d = d_pt or the extra
+// first-vertex samples' estimate; seeds the adjoint of L_D (lam), of alpha,
+// d_pt, r, and dL/dg through the extra samples.
 __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, const int32_t* __restrict__ inv,
                                                         const int32_t* __restrict__ col, const float* __restrict__ w,
                                                         const float* __restrict__ gw, const float* __restrict__ xD,
@@ -196,8 +197,12 @@ __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, co
             const float is = 1.0f / (float)P.spp;
             const f3 ob{gimg[3 * px] * is, gimg[3 * px + 1] * is, gimg[3 * px + 2] * is};
             const float al = alpha[s0];
-            const f3 d = ld3(dpt, s0);
+            const bool extra = P.n_extra > 0;
+            f3 ddg{0.f, 0.f, 0.f};
+            const f3 d = extra ? extra_direct(P, p, ld3(P.dir_in, a), c.rho, c.g, c.sun, c.env_pdf, &ddg)
+                               : ld3(dpt, s0);
             const f3 zb{al * ob.x, al * ob.y, al * ob.z};
+            if (extra) gl += (double)dot3(zb, ddg);
             if (c.final_gather == 0) {
                 f3 in{0.f, 0.f, 0.f}, ing{0.f, 0.f, 0.f};
                 for (int l = 0; l < c.K; ++l) {
@@ -212,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, co
                     atomicAdd(&lam[3 * j + 2], ww * zb.z);
                 }
                 abar[s0] += dot3(ob, f3{d.x + in.x, d.y + in.y, d.z + in.z});
-                gl = (double)dot3(zb, ing);
+                gl += (double)dot3(zb, ing);
             } else {
                 const f3 xv = ld3(xD, s0);
                 const float rr = r[s0];
@@ -222,9 +227,11 @@ __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, co
                 atomicAdd(&lam[3 * s0 + 1], rr * zb.y);
                 atomicAdd(&lam[3 * s0 + 2], rr * zb.z);
             }
-            dptbar[3 * s0] += zb.x;
-            dptbar[3 * s0 + 1] += zb.y;
-            dptbar[3 * s0 + 2] += zb.z;
+            if (!extra) {   // the extra samples replace d_pt in the output
+                dptbar[3 * s0] += zb.x;
+                dptbar[3 * s0 + 1] += zb.y;
+                dptbar[3 * s0 + 2] += zb.z;
+            }
         }
     }
     const double t = block_sum_d(gl);

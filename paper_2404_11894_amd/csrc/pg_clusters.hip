@@ -558,9 +558,11 @@ __global__ __launch_bounds__(kBlock) void k_cpixels(pg_paths P, Consts c, const 
             sy += P.l_emit[3 * a + 1];
             sz += P.l_emit[3 * a + 2];
         }
-        sx = fmaf(t4.w, dpt[3 * i] + in.x, sx);
-        sy = fmaf(t4.w, dpt[3 * i + 1] + in.y, sy);
-        sz = fmaf(t4.w, dpt[3 * i + 2] + in.z, sz);
+        f3 dd = ld3(dpt, i);
+        if (P.n_extra > 0) dd = extra_direct(P, p, f3{t4.x, t4.y, t4.z}, c.rho, c.g, c.sun, c.env_pdf, nullptr);
+        sx = fmaf(t4.w, dd.x + in.x, sx);
+        sy = fmaf(t4.w, dd.y + in.y, sy);
+        sz = fmaf(t4.w, dd.z + in.z, sz);
     }
     const float inv_spp = 1.0f / (float)P.spp;
     image[3 * px] = sx * inv_spp;

@@ -235,6 +235,38 @@ __device__ inline float one_minus_cos(f3 a, f3 b) {
     return 0.5f * fmaf(dx, dx, fmaf(dy, dy, dz * dz));
 }
 
+// The pixel's direct term from the extra first-vertex emitter samples of
+// path p (paths->n_extra = M > 0): (1/M) sum_m (rho(sun) Ls_m + rho(we_m)
+// Le_m / env_pdf), rho about the first vertex's arriving direction t; with
+// dg != NULL also its derivative with respect to g (rho h, h = d ln HG/dg).
+__device__ inline float hg_dlog(float g, float u);
+template <class Rho>
+__device__ inline f3 extra_direct(const pg_paths& P, int64_t p, f3 t, const Rho& rho, float g, f3 sun,
+                                  float env_pdf, f3* dg) {
+    const int M = P.n_extra;
+    const float us = one_minus_cos(t, sun);
+    const float rs = rho(us), hs = dg ? hg_dlog(g, us) : 0.0f;
+    f3 d{0.f, 0.f, 0.f}, e{0.f, 0.f, 0.f};
+    for (int m = 0; m < M; ++m) {
+        const int64_t o = ((int64_t)p * M + m) * 3;
+        const f3 we{P.fb_dir_env[o], P.fb_dir_env[o + 1], P.fb_dir_env[o + 2]};
+        const float u = one_minus_cos(t, we);
+        const float re = rho(u) / env_pdf;
+        d.x += rs * P.fb_l_sun[o] + re * P.fb_l_env[o];
+        d.y += rs * P.fb_l_sun[o + 1] + re * P.fb_l_env[o + 1];
+        d.z += rs * P.fb_l_sun[o + 2] + re * P.fb_l_env[o + 2];
+        if (dg) {
+            const float he = hg_dlog(g, u);
+            e.x += rs * hs * P.fb_l_sun[o] + re * he * P.fb_l_env[o];
+            e.y += rs * hs * P.fb_l_sun[o + 1] + re * he * P.fb_l_env[o + 1];
+            e.z += rs * hs * P.fb_l_sun[o + 2] + re * he * P.fb_l_env[o + 2];
+        }
+    }
+    const float inv = 1.0f / (float)M;
+    if (dg) *dg = f3{e.x * inv, e.y * inv, e.z * inv};
+    return f3{d.x * inv, d.y * inv, d.z * inv};
+}
+
 // d ln HG / d g at u:  -2g/(1-g^2) - 3 (g - cos) / ((1-g)^2 + 2 g u).
 __device__ inline float hg_dlog(float g, float u) {
     float den = fmaf(2.0f * g, u, (1.0f - g) * (1.0f - g));

@@ -205,7 +205,8 @@ hipError_t launch_spmv_shifted(int64_t N, int K, const int32_t* succ, const int3
 // ------------------------------------------------------------- pixels ---
 // One thread per pixel; its spp paths are consecutive.  o_p as in the
 // "Final output" paragraph with the non-aggregated direct term at the first
-// vertex ("Handling direct Light") and that vertex's volume emission.  inv == NULL: local ids are path-order
+// vertex ("Handling direct Light") -- or the estimate of the extra samples
+// recorded there -- and that vertex's volume emission.  inv == NULL: local ids are path-order
 // ids; r == NULL / alpha == NULL: computed from the path records.
 __global__ __launch_bounds__(kBlock) void k_pixels(pg_paths P, Consts c, const int32_t* __restrict__ inv,
                                                    const int32_t* __restrict__ col, const float* __restrict__ w,
@@ -274,9 +275,11 @@ __global__ __launch_bounds__(kBlock) void k_pixels(pg_paths P, Consts c, const i
             sy += P.l_emit[3 * a + 1];
             sz += P.l_emit[3 * a + 2];
         }
-        sx = fmaf(al, dpt[3 * s0] + ix, sx);
-        sy = fmaf(al, dpt[3 * s0 + 1] + iy, sy);
-        sz = fmaf(al, dpt[3 * s0 + 2] + iz, sz);
+        f3 dd = ld3(dpt, s0);
+        if (P.n_extra > 0) dd = extra_direct(P, p, ld3(P.dir_in, a), c.rho, c.g, c.sun, c.env_pdf, nullptr);
+        sx = fmaf(al, dd.x + ix, sx);
+        sy = fmaf(al, dd.y + iy, sy);
+        sz = fmaf(al, dd.z + iz, sz);
     }
     const float inv_spp = 1.0f / (float)P.spp;
     image[3 * px] = sx * inv_spp;

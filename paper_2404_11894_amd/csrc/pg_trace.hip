@@ -186,7 +186,30 @@ __device__ inline double ratio_track(const pg_tracer& t, Rng& rng, const D3& o, 
 
 struct Out {
     float *pos, *dir_in, *dir_out, *albedo, *l_sun, *dir_env, *l_env, *l_phase;
+    float *fb_l_sun, *fb_dir_env, *fb_l_env;   // [P][M][3]
 };
+
+// The M extra emitter samples at a path's first vertex pt (paper, handling
+// direct light): sun and uniform-sphere environment shadow rays from a
+// second stream of the pixel, so the path itself does not depend on M.
+__device__ void extra_samples(const pg_tracer& t, uint64_t pixel, int s, const D3& pt, int64_t p, const Out& o) {
+    Rng rng;
+    rng.seed(splitmix64(t.seed * 0x100000001B3ull + (uint64_t)s) ^ 0x5851F42D4C957F2Dull, pixel);
+    const D3 sun = d3(t.sun_dir[0], t.sun_dir[1], t.sun_dir[2]);
+    for (int k = 0; k < t.extra_samples; ++k) {
+        const double Ts = ratio_track(t, rng, pt, sun, exit_distance(pt, sun));
+        const double v2 = rng.uniform();   // azimuth number first
+        const double v1 = rng.uniform();
+        const D3 we = sample_sphere(v1, v2);
+        const double Te = ratio_track(t, rng, pt, we, exit_distance(pt, we));
+        const int64_t b = ((int64_t)p * t.extra_samples + k) * 3;
+        for (int a = 0; a < 3; ++a) {
+            o.fb_l_sun[b + a] = (float)(t.sun_E[a] * Ts);
+            o.fb_dir_env[b + a] = (float)comp(we, a);
+            o.fb_l_env[b + a] = (float)(t.env_L[a] * Te);
+        }
+    }
+}
 
 // Traces path p of the (cropped) image; with WRITE stores its records from
 // slot v0 on.  Returns the vertex count; ecam receives the camera ray's
@@ -211,8 +234,13 @@ __device__ int trace_path(const Tracer& tr, int64_t p, int64_t v0, int64_t vcap,
     D3 pt;
     if (!box_hit(cam, d, t0, t1) || !delta_track(t, rng, cam, d, fmax(t0, 0.0), t1, pt)) {
         for (int a = 0; a < 3; ++a) ecam[a] = (float)t.env_L[a];
+        if (WRITE && t.extra_samples > 0)   // no first vertex: zero samples
+            for (int64_t b = p * t.extra_samples * 3; b < (p + 1) * t.extra_samples * 3; ++b)
+                o.fb_l_sun[b] = o.fb_dir_env[b] = o.fb_l_env[b] = 0.0f;
         return 0;
     }
+    if (WRITE && t.extra_samples > 0)
+        extra_samples(t, (uint64_t)Y * (uint64_t)t.width + (uint64_t)X, s, pt, p, o);
     const D3 sun = d3(t.sun_dir[0], t.sun_dir[1], t.sun_dir[2]);
     int nv = 0;
     for (int depth = 0; depth < t.max_depth; ++depth) {
@@ -258,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_count(Tracer tr, int64_t P, ui
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     float ec[3];
-    count[p] = (uint32_t)trace_path<false>(tr, p, 0, 0, Out{}, ec);
+    count[p] = (uint32_t)trace_path<false>(tr, p, 0, 0, Out{}, ec);   // the count pass draws no extra samples
     if (e_cam)
         for (int a = 0; a < 3; ++a) e_cam[3 * p + a] = ec[a];
 }
@@ -356,7 +384,8 @@ hipError_t run_trace_write(const pg_tracer* t, const int64_t* path_offsets, cons
     if ((e = launch_fill(flag, 64 * 4, s)) != hipSuccess) return e;
     if (P == 0) return hipSuccess;
     const Tracer tr = make_tracer(t);
-    Out out{o.pos, o.dir_in, o.dir_out, o.albedo, o.l_sun, o.dir_env, o.l_env, o.l_phase};
+    Out out{o.pos, o.dir_in, o.dir_out, o.albedo, o.l_sun, o.dir_env, o.l_env, o.l_phase,
+            o.fb_l_sun, o.fb_dir_env, o.fb_l_env};
     ProfScope ps(s, "trace_write");
     hipLaunchKernelGGL(k_trace_write, dim3((unsigned)div_up(P, kBlock)), dim3(kBlock), 0, s, tr, P, path_offsets, out,
                        o.e_cam, flag);

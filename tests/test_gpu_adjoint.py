@@ -50,6 +50,21 @@ def test_backward_matches_oracle(init, fg, emit):
     grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
 
 
+def test_backward_with_extra_first_vertex_samples():
+    from dataclasses import replace
+    cfg = replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 32, 32, 2), extra_samples=3)
+    sc = scenegen.generate(cfg)
+    print(f"adjoint with extra samples N={sc.n_vertices}", flush=True)
+    grid, gimg, ref = case(sc, 8, 8, 6, 0.5, "pt", 0)
+    paths = pg.DevicePaths(sc, albedo_grid=grid)
+    q = pg.params(k=8, D=6, g=0.5, flags=pg.PG_FLAG_CHECK)
+    out = pg.pg_backward(paths, q, torch.from_numpy(gimg.astype(np.float32)), grad_albedo=True)
+    torch.cuda.synchronize()
+    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid")
+    grad_close(out["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo")
+    grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
+
+
 def test_backward_with_transpose_overflow():
     """200 coincident points: the lowest ids among them are everyone's
     tie-broken neighbours, so their in-degree (about 200) exceeds the 2k

@@ -98,6 +98,24 @@ def test_entry_points_compose_with_emission(init):
     assert_within(img.cpu().numpy(), ref_img, PIX_REL, PIX_ABS, "image")
 
 
+@pytest.mark.parametrize("fg,clusters", [(0, False), (1, False), (0, True)])
+def test_render_with_extra_first_vertex_samples(fg, clusters):
+    cfg = replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 32, 32, 2), extra_samples=4)
+    sc = scenegen.generate(cfg)
+    assert sc.fb_l_env.shape == (sc.n_paths, 4, 3)
+    if clusters:
+        sc = replace(sc, cluster_key=scenegen.cluster_keys(sc.n_vertices, 7))
+    print(f"extra samples fg={fg} clusters={clusters} N={sc.n_vertices}", flush=True)
+    fl = pg.PG_FLAG_CHECK | (pg.PG_FLAG_CLUSTERS if clusters else 0)
+    img = pg.pg_render(pg.DevicePaths(sc), pg.params(k=8, D=6, g=0.5, final_gather=fg, flags=fl))
+    torch.cuda.synchronize()
+    op = oracle.params(k=8, D=6, g=0.5, final_gather=fg, neighbours="clusters" if clusters else "knn")
+    ref = oracle.render(sc, op)
+    assert_within(img.cpu().numpy(), ref, PIX_REL, PIX_ABS, "extra samples")
+    plain = oracle.render(replace(sc, fb_l_sun=None, fb_dir_env=None, fb_l_env=None), op)
+    assert not np.allclose(ref, plain)
+
+
 @pytest.mark.parametrize("k", [1, 2, 5, 12, 16, 33, 64])
 def test_neighbour_counts(k):
     sc = crop("tiny", 24, 24, 2)

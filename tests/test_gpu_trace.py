@@ -83,6 +83,22 @@ def test_trace_variants(case):
         assert ref.n_vertices == 0 and rec.n_vertices == 0
 
 
+def test_trace_extra_first_vertex_samples():
+    cfg = replace(scenegen.crop_of(scenegen.WORKLOADS["mid"].scene, 48, 48, 2), extra_samples=3)
+    ref, rec = compare(cfg)
+    for name in ("fb_l_sun", "fb_dir_env", "fb_l_env"):
+        a = getattr(rec, name).cpu().numpy()
+        b = getattr(ref, name)
+        assert a.shape == b.shape, name
+        ulps = np.abs(a.view(np.int32).astype(np.int64) - b.view(np.int32).astype(np.int64))
+        far = (ulps > 2) & (a != b)
+        assert far.any(axis=(1, 2)).sum() <= max(2, int(1e-4 * a.shape[0])), name
+    # the paths do not depend on the extra samples
+    plain = traced(replace(cfg, extra_samples=0))
+    assert torch.equal(plain.path_offsets, rec.path_offsets)
+    assert torch.equal(plain.pos, rec.pos)
+
+
 def test_traced_records_render_like_host_records():
     cfg = scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 48, 48, 2)
     ref = scenegen.generate(cfg)
@@ -113,7 +129,7 @@ def test_trace_records_rejects_foreign_offsets():
     N = rec.n_vertices
     bufs = {f: torch.full((N * (1 if f == "albedo" else 3),), -3.0, device="cuda") for f in FIELDS}
     e_cam = torch.empty(64 * 3, device="cuda")
-    r = pg.Records(*(bufs[f].data_ptr() for f in FIELDS), e_cam.data_ptr())
+    r = pg.Records(*(bufs[f].data_ptr() for f in FIELDS), e_cam.data_ptr(), None, None, None)
     nb = ctypes.c_size_t()
     L = pg.lib()
     pg._check(L.pg_trace_workspace_size(ctypes.byref(t), ctypes.byref(nb)))
