@@ -51,7 +51,8 @@ class _Scene(ctypes.Structure):
         (name, ctypes.c_void_p) for name in ("path_offsets", "pos", "dir_in", "dir_out", "albedo",
                                              "l_sun", "dir_env", "l_env", "l_phase", "e_cam",
                                              "l_emit", "cluster_key", "fb_l_sun", "fb_dir_env",
-                                             "fb_l_env")] + [("n_extra", ctypes.c_int32), ("pad2_", ctypes.c_int32)]
+                                             "fb_l_env")] + [("n_extra", ctypes.c_int32), ("pad2_", ctypes.c_int32),
+                                                             ("dir_pl", ctypes.c_void_p), ("l_pl", ctypes.c_void_p)]
 
 
 class _Params(ctypes.Structure):
@@ -140,6 +141,9 @@ class _Bound:
             self.arrays["l_emit"] = _f32(scene.l_emit, (N, 3))
         if getattr(scene, "cluster_key", None) is not None:   # cluster neighbour relation
             self.arrays["cluster_key"] = np.ascontiguousarray(scene.cluster_key, dtype=np.uint32).reshape(N)
+        if getattr(scene, "dir_pl", None) is not None:         # point light
+            self.arrays["dir_pl"] = _f32(scene.dir_pl, (N, 3))
+            self.arrays["l_pl"] = _f32(scene.l_pl, (N, 3))
         M = 0
         if getattr(scene, "fb_l_sun", None) is not None:       # extra first-vertex samples
             M = int(np.asarray(scene.fb_l_sun).shape[1])

@@ -40,6 +40,11 @@
  *   - with delta tracking the propagation factor transmittance / free-flight
  *     pdf equals 1/sigma_t at the collision, which turns sigma_s * phase into
  *     albedo * phase; propagation therefore is a shift along the path;
+ *   - more light types (the constant terms only): a point light is a delta
+ *     light whose direction differs per vertex; like the sun it takes no MIS,
+ *     each neighbour's shadow-ray sample (its direction and irradiance)
+ *     counts with weight 1/K at the receiver, evaluated with the receiver's
+ *     phase function, and the own direct term adds the vertex's own sample;
  *   - extra first-vertex samples (Sec. "Rendering System", handling direct
  *     light): with M > 0 extra emitter samples recorded at a path's first
  *     vertex, the pixel uses their emitter-sampling estimate
@@ -92,6 +97,8 @@ typedef struct or_scene {
     const float* fb_l_env;         /* [P][M][3] environment radiance x transmittance */
     int32_t n_extra;               /* M (0: no extra samples) */
     int32_t pad2_;
+    const float* dir_pl;           /* [N][3] or NULL: unit direction toward a point light */
+    const float* l_pl;             /* [N][3]: its intensity x shadow-ray transmittance / distance^2 */
 } or_scene;
 
 typedef struct or_params {
@@ -400,6 +407,13 @@ static void receiver_weights(const or_scene* s, const or_params* p, int64_t i, c
     }
     double rho_sun = or_hg(p->g, one_minus_cos_d(ti, p->sun_dir));
     for (int c = 0; c < 3; ++c) dagg[c] += rho_sun * sum_ls[c] / (double)K;
+    if (s->dir_pl && s->l_pl) {   /* point light: delta, weight 1/K per neighbour sample */
+        for (int64_t a = 0; a < K; ++a) {
+            int64_t j = nb[a];
+            double rho_pl = or_hg(p->g, one_minus_cos(ti, s->dir_pl + j * 3));
+            for (int c = 0; c < 3; ++c) dagg[c] += rho_pl * s->l_pl[j * 3 + c] / (double)K;
+        }
+    }
 }
 
 /* Plain path-traced direct term of vertex i (one sun sample, one environment
@@ -415,6 +429,10 @@ static void own_direct(const or_scene* s, const or_params* p, int64_t i, double 
     double f_out = or_hg(p->g, u_out) / (or_hg(p->g_s, u_out) + p->env_pdf);
     for (int c = 0; c < 3; ++c)
         dpt[c] = f_sun * s->l_sun[i * 3 + c] + f_env * s->l_env[i * 3 + c] + f_out * s->l_phase[i * 3 + c];
+    if (s->dir_pl && s->l_pl) {
+        double f_pl = or_hg(p->g, one_minus_cos(ti, s->dir_pl + i * 3));
+        for (int c = 0; c < 3; ++c) dpt[c] += f_pl * s->l_pl[i * 3 + c];
+    }
     *r = or_hg(p->g, u_out) / or_hg(p->g_s, u_out);
 }
 
@@ -490,6 +508,14 @@ static void first_direct(const or_scene* s, const or_params* p, int64_t q, int64
         for (int c = 0; c < 3; ++c) {
             d[c] += (rs * s->fb_l_sun[o + c] + re * s->fb_l_env[o + c] / p->env_pdf) / (double)M;
             if (dg) dg[c] += (rs * hs * s->fb_l_sun[o + c] + re * he * s->fb_l_env[o + c] / p->env_pdf) / (double)M;
+        }
+    }
+    if (s->dir_pl && s->l_pl) {   /* a point light keeps the vertex's own sample */
+        double u = one_minus_cos(ti, s->dir_pl + v0 * 3);
+        double rp = or_hg(p->g, u), hp = or_hg_dlog(p->g, u);
+        for (int c = 0; c < 3; ++c) {
+            d[c] += rp * s->l_pl[v0 * 3 + c];
+            if (dg) dg[c] += rp * hp * s->l_pl[v0 * 3 + c];
         }
     }
 }
@@ -872,6 +898,17 @@ int or_backward(const or_scene* s, const or_params* p, int32_t R, const float* g
         double u_sun = one_minus_cos_d(ti, p->sun_dir);
         double rho_sun = or_hg(p->g, u_sun), h_sun = or_hg_dlog(p->g, u_sun);
         for (int c = 0; c < 3; ++c) gg += daggbar[c] * rho_sun * h_sun * sum_ls[c] / (double)(rp[i + 1] - rp[i]);
+        if (s->dir_pl && s->l_pl) {
+            for (int64_t a = rp[i]; a < rp[i + 1]; ++a) {
+                int64_t j = f.col[a];
+                double u = one_minus_cos(ti, s->dir_pl + j * 3);
+                double w = or_hg(p->g, u) * or_hg_dlog(p->g, u) / (double)(rp[i + 1] - rp[i]);
+                for (int c = 0; c < 3; ++c) gg += daggbar[c] * w * s->l_pl[j * 3 + c];
+            }
+            double u = one_minus_cos(ti, s->dir_pl + i * 3);
+            double w = or_hg(p->g, u) * or_hg_dlog(p->g, u);
+            for (int c = 0; c < 3; ++c) gg += dptbar[i * 3 + c] * w * s->l_pl[i * 3 + c];
+        }
         /* own direct term and continuation ratio */
         double u_env = one_minus_cos(ti, s->dir_env + i * 3);
         double u_out = one_minus_cos(ti, s->dir_out + i * 3);

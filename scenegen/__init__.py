@@ -16,6 +16,8 @@ paragraph of Sec. "Rendering System"):
   (uniform-sphere environment shadow ray and its transmitted radiance),
   ``l_phase`` [N,3] (environment radiance if the continuation ray escaped);
 * per path: ``e_cam`` [P,3] (environment radiance if the camera ray escaped);
+* optionally ``dir_pl``, ``l_pl`` [N,3]: a point light's shadow-ray direction
+  and irradiance (intensity x transmittance / distance^2);
 * optionally ``l_emit`` [N,3]: the volume emission collected at the collision,
   L_v / sigma_t = (1 - albedo) L_e(pos) for an emissive medium whose emitted
   radiance L_e is a smooth blob (``SceneConfig.emit_L`` nonzero), else None.
@@ -63,7 +65,8 @@ class _Config(ctypes.Structure):
         ("g", ctypes.c_double),
         ("cam_pos", ctypes.c_double * 3), ("look_at", ctypes.c_double * 3), ("vfov_deg", ctypes.c_double),
         ("sun_dir", ctypes.c_double * 3), ("sun_E", ctypes.c_double * 3), ("env_L", ctypes.c_double * 3),
-        ("seed", ctypes.c_uint64), ("extra_samples", ctypes.c_int32), ("pad2_", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("extra_samples", ctypes.c_int32), ("point_light", ctypes.c_int32),
+        ("pl_pos", ctypes.c_double * 3), ("pl_I", ctypes.c_double * 3),
     ]
 
 
@@ -84,6 +87,8 @@ def _load():
         lib.sg_fetch.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 10
         lib.sg_density.restype = ctypes.c_double
         lib.sg_density.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        lib.sg_fetch_point_light.restype = ctypes.c_int
+        lib.sg_fetch_point_light.argtypes = [ctypes.c_void_p] * 3
         lib.sg_fetch_extra.restype = ctypes.c_int
         lib.sg_fetch_extra.argtypes = [ctypes.c_void_p] * 4
         lib.sg_albedo.restype = ctypes.c_int
@@ -126,6 +131,9 @@ class SceneConfig:
     emit_radius: float = 0.25
     # extra emitter samples at each path's first vertex (sun + environment shadow rays, own stream)
     extra_samples: int = 0
+    # point light: intensity pl_I (all zero: none) at pl_pos
+    pl_I: tuple = (0.0, 0.0, 0.0)
+    pl_pos: tuple = (0.5, 1.1, 0.5)
 
     def _c(self) -> _Config:
         c = _Config()
@@ -145,6 +153,9 @@ class SceneConfig:
         c.env_L[:] = self.env_L
         c.seed = self.seed
         c.extra_samples = self.extra_samples
+        c.point_light = 1 if any(self.pl_I) else 0
+        c.pl_pos[:] = self.pl_pos
+        c.pl_I[:] = self.pl_I
         return c
 
     @property
@@ -178,6 +189,9 @@ class Scene:
     fb_l_sun: np.ndarray | None = None
     fb_dir_env: np.ndarray | None = None
     fb_l_env: np.ndarray | None = None
+    # point light [N, 3] each (None: no point light)
+    dir_pl: np.ndarray | None = None
+    l_pl: np.ndarray | None = None
     sun_dir: tuple = SUN_DIR
     env_pdf: float = 1.0 / (4.0 * math.pi)
 
@@ -215,6 +229,10 @@ def generate(cfg: SceneConfig, threads: int = 0) -> Scene:
                           ptr(denv), ptr(le), ptr(lp), ptr(ecam))
         if rc != 0:
             raise RuntimeError("scenegen: fetch failed")
+        pl = None
+        if any(cfg.pl_I):
+            pl = (a3(N), a3(N))
+            lib.sg_fetch_point_light(h, ptr(pl[0]), ptr(pl[1]))
         fb = None
         if cfg.extra_samples > 0:
             fb = tuple(np.zeros((P, cfg.extra_samples, 3), np.float32) for _ in range(3))
@@ -226,7 +244,7 @@ def generate(cfg: SceneConfig, threads: int = 0) -> Scene:
                  dir_out=dout, albedo=alb, l_sun=ls, dir_env=denv, l_env=le, l_phase=lp,
                  e_cam=ecam, config=cfg, sun_dir=tuple(cfg.sun_dir), l_emit=emission(cfg, pos, alb),
                  fb_l_sun=fb[0] if fb else None, fb_dir_env=fb[1] if fb else None,
-                 fb_l_env=fb[2] if fb else None)
+                 fb_l_env=fb[2] if fb else None, dir_pl=pl[0] if pl else None, l_pl=pl[1] if pl else None)
 
 
 def emission(cfg: SceneConfig, pos: np.ndarray, albedo: np.ndarray) -> np.ndarray | None:
@@ -288,7 +306,7 @@ def tracer_settings(cfg: SceneConfig) -> dict:
             "crop": tuple(cfg.crop), "albedo_const": float(cfg.albedo[0]), "g": cfg.g,
             "cam_pos": tuple(cfg.cam_pos), "look_at": tuple(cfg.look_at), "vfov_deg": cfg.vfov_deg,
             "sun_dir": tuple(cfg.sun_dir), "sun_E": tuple(cfg.sun_E), "env_L": tuple(cfg.env_L), "seed": cfg.seed,
-            "extra_samples": cfg.extra_samples}
+            "extra_samples": cfg.extra_samples, "pl_I": tuple(cfg.pl_I), "pl_pos": tuple(cfg.pl_pos)}
 
 
 def cluster_keys(n: int, seed: int = 7) -> np.ndarray:

@@ -63,7 +63,9 @@ typedef struct sg_config {
     double env_L[3];        /* constant environment radiance (RGB) */
     uint64_t seed;
     int32_t extra_samples;  /* extra emitter samples at each path's first vertex */
-    int32_t pad2_;
+    int32_t point_light;    /* 1: a point light at pl_pos with intensity pl_I */
+    double pl_pos[3];
+    double pl_I[3];
 } sg_config;
 
 /* ------------------------------------------------------------------ RNG --- */
@@ -296,7 +298,7 @@ static double exit_distance(const double o[3], const double d[3]) {
 }
 
 /* ---------------------------------------------------------------- paths --- */
-enum { REC = 22 }; /* floats per vertex record: pos3 din3 dout3 alb1 ls3 denv3 le3 lp3 */
+enum { REC = 28 }; /* floats per vertex record: pos3 din3 dout3 alb1 ls3 denv3 le3 lp3 dpl3 lpl3 */
 
 typedef struct {
     int64_t np;       /* paths in this block */
@@ -406,6 +408,18 @@ static int trace_path(const handle* h, block* b, int X, int Y, int s, float ecam
         sample_sphere(v1, v2, we);
         double Te = ratio_track(m, &rng, p, we, exit_distance(p, we));
         for (int a = 0; a < 3; ++a) { r[13 + a] = (float)we[a]; r[16 + a] = (float)(c->env_L[a] * Te); }
+        /* point light shadow ray (delta light): irradiance I T / r^2 */
+        for (int a = 0; a < 6; ++a) r[22 + a] = 0.0f;
+        if (c->point_light) {
+            double dl[3], r2 = 0.0;
+            for (int a = 0; a < 3; ++a) { dl[a] = c->pl_pos[a] - p[a]; r2 += dl[a] * dl[a]; }
+            double dist = sqrt(r2);
+            for (int a = 0; a < 3; ++a) dl[a] /= dist;
+            double tmax = exit_distance(p, dl);
+            if (dist < tmax) tmax = dist;
+            double Tp = ratio_track(m, &rng, p, dl, tmax);
+            for (int a = 0; a < 3; ++a) { r[22 + a] = (float)dl[a]; r[25 + a] = (float)(c->pl_I[a] * Tp / r2); }
+        }
         /* phase-sampled continuation (azimuth number drawn first) */
         double h2 = rnd(&rng), h1 = rnd(&rng);
         sample_hg(d, c->g, h1, h2, wo);
@@ -579,6 +593,31 @@ double sg_density(void* hp, float* sigma_out) {
     size_t n = (size_t)h->med.R * h->med.R * h->med.R;
     memcpy(sigma_out, h->med.sigma, n * sizeof(float));
     return h->med.majorant;
+}
+
+/* Copy the point-light records (direction, irradiance x transmittance),
+ * [N][3] each, path order; 1 if the scene has no point light. */
+int sg_fetch_point_light(void* hp, float* dir_pl, float* l_pl) {
+    handle* h = (handle*)hp;
+    if (!h->cfg.point_light) return 1;
+    int64_t* vstart = (int64_t*)malloc((size_t)(h->nblocks + 1) * sizeof(int64_t));
+    if (!vstart) return -1;
+    vstart[0] = 0;
+    for (int64_t bi = 0; bi < h->nblocks; ++bi) vstart[bi + 1] = vstart[bi] + h->blocks[bi].nv;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t bi = 0; bi < h->nblocks; ++bi) {
+        const block* b = &h->blocks[bi];
+        for (int64_t v = 0; v < b->nv; ++v) {
+            const float* r = b->rec + (size_t)v * REC;
+            int64_t gv = vstart[bi] + v;
+            for (int a = 0; a < 3; ++a) {
+                dir_pl[gv * 3 + a] = r[22 + a];
+                l_pl[gv * 3 + a] = r[25 + a];
+            }
+        }
+    }
+    free(vstart);
+    return 0;
 }
 
 /* Copy the extra first-vertex emitter samples, [P][M] each of l_sun[3],

@@ -300,6 +300,8 @@ def path_traced_image(sc, g, g_s, sun_dir, pe=1 / FOUR_PI):
     d = (f(g, din, sd[None])[:, None] * sc.l_sun
          + (f(g, din, denv) / (f(g_s, din, denv) + pe))[:, None] * sc.l_env
          + (f(g, din, dout) / (f(g_s, din, dout) + pe))[:, None] * sc.l_phase)
+    if sc.dir_pl is not None:      # point light: its own shadow-ray sample, no MIS
+        d = d + f(g, din, sc.dir_pl.astype(np.float64))[:, None] * sc.l_pl
     ratio = f(g, din, dout) / f(g_s, din, dout)
     img = np.zeros((sc.height * sc.width, 3))
     off = sc.path_offsets
@@ -366,6 +368,37 @@ def test_extra_first_vertex_samples_are_unbiased():
     # same pixels use d_pt, which these records (all zero) make 0
     img0 = oracle.render(replace(sc, fb_l_sun=None, fb_dir_env=None, fb_l_env=None), p)
     assert np.allclose(img0, 0.0)
+
+
+@pytest.mark.parametrize("init", ["pt", "zero"])
+def test_single_neighbour_with_point_light_reproduces_path_tracing(init):
+    sc = scenegen.generate(replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 16, 16, 2),
+                                   pl_I=(0.4, 0.3, 0.2)))
+    assert sc.l_pl is not None and (sc.l_pl > 0).any()
+    g, g_s = 0.5, 0.3
+    p = oracle.params(k=1, D=12, g=g, g_s=g_s, init=init)
+    ref = path_traced_image(sc, g, g_s, p["sun_dir"])
+    assert np.allclose(oracle.render(sc, p), ref, rtol=2e-6, atol=1e-12)
+
+
+def test_point_light_aggregates_as_a_delta_light():
+    # groups of coincident points: one light direction per group, so the
+    # aggregated point-light term is rho_i(d) times the group's mean irradiance
+    rng = np.random.default_rng(8)
+    K, trials, g = 5, 30, 0.7
+    centres = rng.random((trials, 3)) * 0.9 + 0.05
+    pos = np.repeat(centres, K, axis=0)
+    n = len(pos)
+    t = unit(rng, n)
+    dpl = np.repeat(unit(rng, trials), K, axis=0)
+    lpl = rng.random((n, 3))
+    sc = replace(make_scene(pos, t, unit(rng, n), unit(rng, n)), dir_pl=dpl.astype(np.float32),
+                 l_pl=lpl.astype(np.float32))
+    _, tr = oracle.render(sc, oracle.params(k=K, D=0, g=g, g_s=g), trace=True)
+    rho = hg_textbook(g, np.clip((t * dpl).sum(1), -1, 1))
+    mean = lpl.astype(np.float32).astype(np.float64).reshape(trials, K, 3).mean(1).repeat(K, axis=0)
+    assert np.allclose(tr["d_agg"], rho[:, None] * mean, rtol=2e-6, atol=1e-12)
+    assert np.allclose(tr["d_pt"], rho[:, None] * lpl.astype(np.float32), rtol=2e-6, atol=1e-12)
 
 
 def test_zero_albedo_sees_first_collision_emission():
@@ -440,10 +473,11 @@ def test_zero_albedo_leaves_camera_emission_only():
 
 
 def test_linear_in_light_radiance():
-    sc = small_scene()
+    sc = scenegen.generate(replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 16, 16, 2),
+                                   pl_I=(0.4, 0.3, 0.2)))
     p = oracle.params(k=8, D=5)
     a = oracle.render(sc, p)
-    for name in ("l_sun", "l_env", "l_phase", "e_cam"):
+    for name in ("l_sun", "l_env", "l_phase", "e_cam", "l_pl"):
         setattr(sc, name, getattr(sc, name) * np.float32(2.0))
     assert np.allclose(oracle.render(sc, p), 2 * a, rtol=1e-12)
 
@@ -679,10 +713,15 @@ def loss_and_grad(sc, p, grid, target):
 
 
 @pytest.mark.parametrize("init,fg,emit", [("pt", 0, False), ("zero", 0, False), ("pt", 1, False),
-                                           ("pt", 0, True), ("zero", 0, True), ("pt", 1, "extra")])
+                                           ("pt", 0, True), ("zero", 0, True), ("pt", 1, "extra"),
+                                           ("pt", 0, "point"), ("zero", 1, "extra+point")])
 def test_adjoint_matches_central_differences(init, fg, emit):
-    if emit == "extra":
-        cfg = replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 8, 8, 2), extra_samples=3)
+    if emit in ("extra", "point", "extra+point"):
+        cfg = scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 8, 8, 2)
+        if "extra" in emit:
+            cfg = replace(cfg, extra_samples=3)
+        if "point" in emit:
+            cfg = replace(cfg, pl_I=(0.4, 0.3, 0.2))
         sc = scenegen.generate(cfg)
     else:
         sc = small_scene(8, 8, 2, emit=emit)
