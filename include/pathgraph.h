@@ -115,6 +115,11 @@ typedef struct pg_paths {
     const float* fb_l_env;        /* environment radiance x shadow-ray transmittance */
     int32_t n_extra;              /* M, 0..1024; 0: none (the three pointers are ignored) */
     int32_t pad_;
+    /* A point light (a delta light whose direction differs per vertex; more light types enter
+     * only the constant terms): [N][3] each, both or neither.  Like the sun it takes no MIS:
+     * d_agg_i += (1/K) sum_j rho_i(dir_pl_j) l_pl_j and d_pt_i += rho_i(dir_pl_i) l_pl_i. */
+    const float* dir_pl;          /* unit direction toward the light */
+    const float* l_pl;            /* intensity x shadow-ray transmittance / distance^2 */
 } pg_paths;
 
 /* Method parameters. */
@@ -224,13 +229,19 @@ typedef struct pg_tracer {
     double sun_E[3];           /* sun irradiance */
     double env_L[3];           /* environment radiance */
     uint64_t seed;
+    double pl_pos[3];          /* point light position (may be outside the cube) */
+    double pl_I[3];            /* its intensity; all zero: no point light.  Its shadow ray
+                                  (ratio tracking up to the light or the cube's exit) is drawn
+                                  after the environment shadow ray */
 } pg_tracer;
 
 /* Device output arrays of pg_trace_records ([N][3], albedo [N], e_cam [P][3],
- * fb_* [P][M][3], required when extra_samples > 0, zero for an escaped path). */
+ * fb_* [P][M][3], required when extra_samples > 0, zero for an escaped path;
+ * a point light's records). */
 typedef struct pg_records {
     float *pos, *dir_in, *dir_out, *albedo, *l_sun, *dir_env, *l_env, *l_phase, *e_cam;
     float *fb_l_sun, *fb_dir_env, *fb_l_env;
+    float *dir_pl, *l_pl;      /* [N][3], required with a point light */
 } pg_records;
 
 /* Pass 1: traces every path and writes path_offsets[P+1] (device); N to
@@ -271,8 +282,9 @@ pg_status pg_clusters(const pg_paths* paths, int32_t k, int32_t cell_shift, int3
  *   w_ind_ij = rho_i(w_j) / M+_ij,      rho_i = HG_g about dir_in[i]
  *   w_ph_ij  = rho_i(w_j) / (M+_ij + K env_pdf)
  *   w_env_ij = rho_i(we_j) / (sum_l p_l(we_j) + K env_pdf)
- *   b_i = e_i + albedo_i (rho_i(sun) mean_j l_sun_j + sum_j w_env_ij l_env_j + w_ph_ij l_phase_j)
- *         (e = l_emit, 0 if NULL)
+ *   b_i = e_i + albedo_i (rho_i(sun) mean_j l_sun_j + sum_j w_env_ij l_env_j + w_ph_ij l_phase_j
+ *                         [+ mean_j rho_i(dir_pl_j) l_pl_j])
+ *         (e = l_emit, 0 if NULL; the point-light term only with dir_pl / l_pl)
  *   d_pt_i = rho_i(sun) l_sun_i + rho_i(we_i) l_env_i / (p_i(we_i) + env_pdf)
  *            + rho_i(w_i) l_phase_i / (p_i(w_i) + env_pdf)
  * and the initial radiance arriving along the continuation, lplus0 (paper Sec.

@@ -45,7 +45,7 @@ class Paths(ctypes.Structure):
         (n, ctypes.c_void_p) for n in ("path_offsets", "pos", "dir_in", "dir_out", "albedo", "l_sun",
                                        "dir_env", "l_env", "l_phase", "e_cam", "albedo_grid", "l_emit",
                                        "cluster_key", "fb_l_sun", "fb_dir_env", "fb_l_env")] + [
-        ("n_extra", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+        ("n_extra", ctypes.c_int32), ("pad_", ctypes.c_int32), ("dir_pl", ctypes.c_void_p), ("l_pl", ctypes.c_void_p)]
 
 
 class Tracer(ctypes.Structure):
@@ -56,12 +56,13 @@ class Tracer(ctypes.Structure):
                 ("albedo_const", ctypes.c_double), ("majorant", ctypes.c_double), ("g", ctypes.c_double),
                 ("cam_pos", ctypes.c_double * 3), ("look_at", ctypes.c_double * 3), ("vfov_deg", ctypes.c_double),
                 ("sun_dir", ctypes.c_double * 3), ("sun_E", ctypes.c_double * 3), ("env_L", ctypes.c_double * 3),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("pl_pos", ctypes.c_double * 3), ("pl_I", ctypes.c_double * 3)]
 
 
 class Records(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("pos", "dir_in", "dir_out", "albedo", "l_sun", "dir_env", "l_env",
-                                               "l_phase", "e_cam", "fb_l_sun", "fb_dir_env", "fb_l_env")]
+                                               "l_phase", "e_cam", "fb_l_sun", "fb_dir_env", "fb_l_env", "dir_pl",
+                                               "l_pl")]
 
 
 class Params(ctypes.Structure):
@@ -186,6 +187,10 @@ class DevicePaths:
             device=self.device, dtype=torch.float32).contiguous()
         self.cluster_key = None
         self.set_cluster_key(getattr(scene, "cluster_key", None))
+        self.pl = None   # point light records [N, 3] x 2
+        if getattr(scene, "dir_pl", None) is not None:
+            self.pl = {n: torch.as_tensor(getattr(scene, n)).to(device=self.device, dtype=torch.float32).contiguous()
+                       for n in ("dir_pl", "l_pl")}
         self.fb = None   # extra first-vertex samples [P, M, 3] x 3
         if getattr(scene, "fb_l_sun", None) is not None:
             self.fb = {n: torch.as_tensor(getattr(scene, n)).to(device=self.device, dtype=torch.float32).contiguous()
@@ -221,6 +226,9 @@ class DevicePaths:
             s.l_emit = self.l_emit.data_ptr()
         if self.cluster_key is not None and self.cluster_key.numel():
             s.cluster_key = self.cluster_key.data_ptr()
+        if self.pl is not None and self.pl["dir_pl"].numel():
+            for n, t in self.pl.items():
+                setattr(s, n, t.data_ptr())
         if self.fb is not None and self.fb["fb_l_sun"].numel():
             for n, t in self.fb.items():
                 setattr(s, n, t.data_ptr())
@@ -317,6 +325,9 @@ def pg_trace(settings: dict, sigma, albedo=None, majorant=None, device="cuda") -
         getattr(t, name)[:] = [float(v) for v in settings[name]]
     t.seed = int(settings["seed"])
     t.extra_samples = int(settings.get("extra_samples", 0))
+    t.pl_pos[:] = [float(v) for v in settings.get("pl_pos", (0.0, 0.0, 0.0))]
+    t.pl_I[:] = [float(v) for v in settings.get("pl_I", (0.0, 0.0, 0.0))]
+    point_light = any(v != 0.0 for v in t.pl_I)
     w = t.crop_w if t.crop_w else t.width
     h = t.crop_h if t.crop_w else t.height
     P = w * h * t.spp
@@ -332,6 +343,8 @@ def pg_trace(settings: dict, sigma, albedo=None, majorant=None, device="cuda") -
     f = lambda n, *sh: torch.empty(max(n, 1), *sh, dtype=torch.float32, device=dev)  # noqa: E731
     base = {"pos": f(N, 3), "dir_in": f(N, 3), "dir_out": f(N, 3), "albedo": f(N), "l_sun": f(N, 3),
             "dir_env": f(N, 3), "l_env": f(N, 3), "l_phase": f(N, 3), "e_cam": f(P, 3)}
+    if point_light:
+        base["dir_pl"], base["l_pl"] = f(N, 3), f(N, 3)
     M = t.extra_samples
     if M > 0:
         for name in ("fb_l_sun", "fb_dir_env", "fb_l_env"):

@@ -55,6 +55,7 @@ pg_status validate_paths(const pg_paths* p, bool need_records) {
     if (p->albedo_grid && (p->albedo_grid_res < 1 || p->albedo_grid_res > 1024))
         return fail(PG_ERR_ARG, "albedo_grid_res must be in [1, 1024]");
     if (p->n_extra < 0 || p->n_extra > 1024) return fail(PG_ERR_ARG, "n_extra must be in [0, 1024]");
+    if ((p->dir_pl == nullptr) != (p->l_pl == nullptr)) return fail(PG_ERR_ARG, "dir_pl and l_pl go together");
     if (p->n_extra > 0 && p->n_paths > 0 && (!p->fb_l_sun || !p->fb_dir_env || !p->fb_l_env))
         return fail(PG_ERR_ARG, "n_extra > 0 needs fb_l_sun, fb_dir_env and fb_l_env");
     return PG_OK;
@@ -280,6 +281,8 @@ pg_status pg_trace_records(const pg_tracer* t, const int64_t* path_offsets, cons
         return fail(PG_ERR_ARG, "every output array is required");
     if (t->extra_samples > 0 && (!out->fb_l_sun || !out->fb_dir_env || !out->fb_l_env))
         return fail(PG_ERR_ARG, "extra_samples > 0 needs fb_l_sun, fb_dir_env and fb_l_env");
+    if ((t->pl_I[0] != 0.0 || t->pl_I[1] != 0.0 || t->pl_I[2] != 0.0) && (!out->dir_pl || !out->l_pl))
+        return fail(PG_ERR_ARG, "a point light needs dir_pl and l_pl");
     if ((st = check_ws(ws, ws_bytes, trace_ws_size(t)))) return st;
     hipStream_t s = (hipStream_t)stream;
     int32_t* flag = nullptr;
@@ -397,6 +400,8 @@ pg_status pg_edges(const pg_paths* paths, const pg_params* params, const int64_t
     o.b_canon = b;
     o.dpt_canon = d_pt;
     o.emit = paths->l_emit;
+    o.dir_pl = paths->dir_pl;
+    o.l_pl = paths->l_pl;
     Consts c = make_consts(params, K);
     if ((e = launch_edges(N, c, col, rec, o, flag, s)) != hipSuccess) return hip_fail(e, "edges");
     if (lplus0) {

@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, co
             const float al = alpha[s0];
             const bool extra = P.n_extra > 0;
             f3 ddg{0.f, 0.f, 0.f};
-            const f3 d = extra ? extra_direct(P, p, ld3(P.dir_in, a), c.rho, c.g, c.sun, c.env_pdf, &ddg)
+            const f3 d = extra ? extra_direct(P, p, a, ld3(P.dir_in, a), c.rho, c.g, c.sun, c.env_pdf, &ddg)
                                : ld3(dpt, s0);
             const f3 zb{al * ob.x, al * ob.y, al * ob.z};
             if (extra) gl += (double)dot3(zb, ddg);
@@ -400,7 +400,9 @@ __global__ __launch_bounds__(kBlock) void k_edges_adjoint(int64_t N, Consts c, c
                                                           const float* __restrict__ bbar,
                                                           const float* __restrict__ dptbar,
                                                           const float* __restrict__ rbar, float* __restrict__ abar,
-                                                          double* __restrict__ gpart) {
+                                                          double* __restrict__ gpart, const int32_t* __restrict__ perm,
+                                                          const float* __restrict__ dir_pl,
+                                                          const float* __restrict__ l_pl) {
     constexpr int GR = kBlock / KP;
     __shared__ f3 tsh[GR][KP];
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -411,8 +413,14 @@ __global__ __launch_bounds__(kBlock) void k_edges_adjoint(int64_t N, Consts c, c
     f3 t{0.f, 0.f, 0.f}, w{0.f, 0.f, 0.f}, we{0.f, 0.f, 0.f}, ls{0.f, 0.f, 0.f}, le{0.f, 0.f, 0.f},
         lp{0.f, 0.f, 0.f};
     float alpha = 0.0f;
+    f3 dpl{0.f, 0.f, 0.f}, lpl{0.f, 0.f, 0.f};
     if (act) {
-        const float4* r4 = reinterpret_cast<const float4*>(rec + col[eidx(i, lane, K)]);
+        const int32_t jn = col[eidx(i, lane, K)];
+        if (dir_pl) {
+            dpl = ld3(dir_pl, perm[jn]);
+            lpl = ld3(l_pl, perm[jn]);
+        }
+        const float4* r4 = reinterpret_cast<const float4*>(rec + jn);
         float4 a0 = r4[0], a1 = r4[1], a2 = r4[2], a3 = r4[3], a4 = r4[4];
         t = f3{a0.x, a0.y, a0.z};
         w = f3{a0.w, a1.x, a1.y};
@@ -451,17 +459,36 @@ __global__ __launch_bounds__(kBlock) void k_edges_adjoint(int64_t N, Consts c, c
     sx = group_sum<KP>(sx);
     sy = group_sum<KP>(sy);
     sz = group_sum<KP>(sz);
+    // point light: value and g-derivative of the neighbours' delta samples
+    float rpl = 0.f, hpl = 0.f;
+    if (act && dir_pl) {
+        const float u = one_minus_cos(ti, dpl);
+        rpl = c.rho(u);
+        hpl = rpl * hg_dlog(c.g, u);
+    }
+    float qx = rpl * lpl.x, qy = rpl * lpl.y, qz = rpl * lpl.z;
+    float gx = hpl * lpl.x, gy = hpl * lpl.y, gz = hpl * lpl.z;
+    if (dir_pl) {
+        qx = group_sum<KP>(qx);
+        qy = group_sum<KP>(qy);
+        qz = group_sum<KP>(qz);
+        gx = group_sum<KP>(gx);
+        gy = group_sum<KP>(gy);
+        gz = group_sum<KP>(gz);
+    }
     double gl = 0.0;
     if (i < N && lane == 0) {
         const float u_s = one_minus_cos(ti, c.sun);
         const float rho_sun = c.rho(u_s), hs = hg_dlog(c.g, u_s);
         const float invK = 1.0f / (float)K;
-        const f3 dagg{fmaf(rho_sun * invK, sx, cx), fmaf(rho_sun * invK, sy, cy), fmaf(rho_sun * invK, sz, cz)};
+        f3 dagg{fmaf(rho_sun * invK, sx, cx), fmaf(rho_sun * invK, sy, cy), fmaf(rho_sun * invK, sz, cz)};
+        if (dir_pl) dagg = f3{fmaf(invK, qx, dagg.x), fmaf(invK, qy, dagg.y), fmaf(invK, qz, dagg.z)};
         const f3 bb = ld3(bbar, i);
         abar[i] += dot3(bb, dagg);
         const f3 db{alpha * bb.x, alpha * bb.y, alpha * bb.z};
         const float ks = rho_sun * hs * invK;
         gl += (double)dot3(db, f3{fmaf(ks, sx, hx), fmaf(ks, sy, hy), fmaf(ks, sz, hz)});
+        if (dir_pl) gl += (double)(invK * dot3(db, f3{gx, gy, gz}));
         // own direct term and continuation ratio
         const float p_w = c.pdf(u_w), p_e = c.pdf(u_e);
         const float f_env = rho_e / (p_e + c.env_pdf), f_out = rho / (p_w + c.env_pdf);
@@ -470,6 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_edges_adjoint(int64_t N, Consts c, c
                     rho_sun * hs * ls.y + f_env * he * le.y + f_out * hw * lp.y,
                     rho_sun * hs * ls.z + f_env * he * le.z + f_out * hw * lp.z};
         gl += (double)dot3(pb, dd);
+        if (dir_pl) gl += (double)(hpl * dot3(pb, lpl));   // lane 0: the receiver's own sample
         gl += (double)(rbar[i] * (rho / p_w) * hw);
     }
     const double tsum = block_sum_d(gl);
@@ -679,7 +707,8 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
         dispatch_kp(K, [&](auto kp) {
             constexpr int KP = decltype(kp)::value;
             hipLaunchKernelGGL(k_edges_adjoint<KP>, dim3((unsigned)div_up(N, kBlock / KP)), dim3(kBlock), 0, s, N,
-                               c, r.col, r.rec, bb.bbar, bb.dptbar, bb.rbar, bb.abar, g_edges);
+                               c, r.col, r.rec, bb.bbar, bb.dptbar, bb.rbar, bb.abar, g_edges, r.g.perm, p->dir_pl,
+                               p->l_pl);
         });
         PG_TRY(hipGetLastError());
     }

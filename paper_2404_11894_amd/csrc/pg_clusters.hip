@@ -389,14 +389,15 @@ __global__ __launch_bounds__(kBlock) void k_cedges(int64_t N, Consts c, const ui
                                                    const VRec* __restrict__ crec, const float4* __restrict__ tq,
                                                    const float* __restrict__ mp, const float* __restrict__ me,
                                                    const float* __restrict__ emit, const int32_t* __restrict__ cperm,
-                                                   const int32_t* __restrict__ perm, float* __restrict__ b,
+                                                   const int32_t* __restrict__ perm, const float* __restrict__ dir_pl,
+                                                   const float* __restrict__ l_pl, float* __restrict__ b,
                                                    float* __restrict__ dpt, float* __restrict__ r) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const uint2 rg = bounded(crange[i]);
     const float4 t4 = tq[i];
     const f3 ti{t4.x, t4.y, t4.z};
-    float cx = 0.f, cy = 0.f, cz = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+    float cx = 0.f, cy = 0.f, cz = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, qx = 0.f, qy = 0.f, qz = 0.f;
     for (uint32_t j = rg.x; j < rg.y; ++j) {
         const VRec& rj = crec[j];
         const f3 wj{rj.w[0], rj.w[1], rj.w[2]}, wej{rj.we[0], rj.we[1], rj.we[2]};
@@ -408,10 +409,19 @@ __global__ __launch_bounds__(kBlock) void k_cedges(int64_t N, Consts c, const ui
         sx += rj.ls[0];
         sy += rj.ls[1];
         sz += rj.ls[2];
+        if (dir_pl) {   // point light: a delta light per member sample, weight 1/C
+            const int64_t pj = perm[cperm[j]];
+            const float rp = c.rho(one_minus_cos(ti, ld3(dir_pl, pj)));
+            const f3 lq = ld3(l_pl, pj);
+            qx = fmaf(rp, lq.x, qx);
+            qy = fmaf(rp, lq.y, qy);
+            qz = fmaf(rp, lq.z, qz);
+        }
     }
     const float rho_sun = c.rho(one_minus_cos(ti, c.sun));
     const float invC = 1.0f / (float)(rg.y - rg.x);
-    const f3 dagg{fmaf(rho_sun * invC, sx, cx), fmaf(rho_sun * invC, sy, cy), fmaf(rho_sun * invC, sz, cz)};
+    f3 dagg{fmaf(rho_sun * invC, sx, cx), fmaf(rho_sun * invC, sy, cy), fmaf(rho_sun * invC, sz, cz)};
+    if (dir_pl) dagg = f3{fmaf(invC, qx, dagg.x), fmaf(invC, qy, dagg.y), fmaf(invC, qz, dagg.z)};
     f3 em{0.f, 0.f, 0.f};
     if (emit) em = ld3(emit, perm[cperm[i]]);
     const float al = t4.w;
@@ -422,10 +432,16 @@ __global__ __launch_bounds__(kBlock) void k_cedges(int64_t N, Consts c, const ui
     const float rho = c.rho(u_w), rho_e = c.rho(u_e);
     const float p_w = c.pdf(u_w), p_e = c.pdf(u_e);
     const float f_env = rho_e / (p_e + c.env_pdf), f_out = rho / (p_w + c.env_pdf);
-    st3(dpt, i,
-        f3{rho_sun * ri.ls[0] + f_env * ri.le[0] + f_out * ri.lp[0],
-           rho_sun * ri.ls[1] + f_env * ri.le[1] + f_out * ri.lp[1],
-           rho_sun * ri.ls[2] + f_env * ri.le[2] + f_out * ri.lp[2]});
+    f3 dp{rho_sun * ri.ls[0] + f_env * ri.le[0] + f_out * ri.lp[0],
+          rho_sun * ri.ls[1] + f_env * ri.le[1] + f_out * ri.lp[1],
+          rho_sun * ri.ls[2] + f_env * ri.le[2] + f_out * ri.lp[2]};
+    if (dir_pl) {
+        const int64_t pi = perm[cperm[i]];
+        const float rp = c.rho(one_minus_cos(ti, ld3(dir_pl, pi)));
+        const f3 lq = ld3(l_pl, pi);
+        dp = f3{fmaf(rp, lq.x, dp.x), fmaf(rp, lq.y, dp.y), fmaf(rp, lq.z, dp.z)};
+    }
+    st3(dpt, i, dp);
     r[i] = rho / p_w;
 }
 
@@ -559,7 +575,7 @@ __global__ __launch_bounds__(kBlock) void k_cpixels(pg_paths P, Consts c, const 
             sz += P.l_emit[3 * a + 2];
         }
         f3 dd = ld3(dpt, i);
-        if (P.n_extra > 0) dd = extra_direct(P, p, f3{t4.x, t4.y, t4.z}, c.rho, c.g, c.sun, c.env_pdf, nullptr);
+        if (P.n_extra > 0) dd = extra_direct(P, p, a, f3{t4.x, t4.y, t4.z}, c.rho, c.g, c.sun, c.env_pdf, nullptr);
         sx = fmaf(t4.w, dd.x + in.x, sx);
         sy = fmaf(t4.w, dd.y + in.y, sy);
         sz = fmaf(t4.w, dd.z + in.z, sz);
@@ -803,7 +819,7 @@ hipError_t cluster_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, c
                            cr.me);
         PG_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_cedges, grid_of(N), dim3(kBlock), 0, s, N, c, cb.crange, cr.crec, cr.tq, cr.mp, cr.me,
-                           p->l_emit, cb.cperm, g.perm, r.b, r.dpt, r.r);
+                           p->l_emit, cb.cperm, g.perm, p->dir_pl, p->l_pl, r.b, r.dpt, r.r);
         PG_TRY(hipGetLastError());
     }
     if (out && (out->row_ptr || out->col)) {

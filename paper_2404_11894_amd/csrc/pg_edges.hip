@@ -34,6 +34,7 @@ __global__ __launch_bounds__(kBlock) void k_edges(int64_t N, Consts c, const int
     f3 t{0.f, 0.f, 0.f}, w{0.f, 0.f, 0.f}, we{0.f, 0.f, 0.f}, ls{0.f, 0.f, 0.f}, le{0.f, 0.f, 0.f},
         lp{0.f, 0.f, 0.f};
     float alpha = 0.0f;
+    f3 dpl{0.f, 0.f, 0.f}, lpl{0.f, 0.f, 0.f};   // point light sample of the neighbour
     const int64_t e = o.ell ? eidx(i, lane, K) : i * K + lane;
     if (act) {
         int64_t j = col[e];
@@ -50,6 +51,11 @@ __global__ __launch_bounds__(kBlock) void k_edges(int64_t N, Consts c, const int
             le = f3{a3.x, a3.y, a3.z};
             lp = f3{a3.w, a4.x, a4.y};
             alpha = a4.z;
+            if (o.dir_pl) {
+                const int64_t cj = o.canon_row ? (int64_t)o.canon_row[j] : j;
+                dpl = ld3(o.dir_pl, cj);
+                lpl = ld3(o.l_pl, cj);
+            }
         }
     }
     tsh[grp][lane] = t;
@@ -79,6 +85,14 @@ __global__ __launch_bounds__(kBlock) void k_edges(int64_t N, Consts c, const int
     sx = group_sum<KP>(sx);
     sy = group_sum<KP>(sy);
     sz = group_sum<KP>(sz);
+    // point light: a delta light per neighbour sample, weight 1/K
+    const float rho_pl = (act && o.dir_pl) ? c.rho(one_minus_cos(ti, dpl)) : 0.0f;
+    float qx = rho_pl * lpl.x, qy = rho_pl * lpl.y, qz = rho_pl * lpl.z;
+    if (o.dir_pl) {
+        qx = group_sum<KP>(qx);
+        qy = group_sum<KP>(qy);
+        qz = group_sum<KP>(qz);
+    }
 
     if (o.ell && row_ok && lane == 0) {   // padding slots of the last quad: weight 0
         for (int l = K; l < ell_k4(K); ++l) {
@@ -100,7 +114,8 @@ __global__ __launch_bounds__(kBlock) void k_edges(int64_t N, Consts c, const int
         // aggregated direct: sun (delta light, weight 1/K per neighbour) + MIS'd records
         const float rho_sun = c.rho(one_minus_cos(ti, c.sun));
         const float invK = 1.0f / (float)K;
-        const f3 dagg{fmaf(rho_sun * invK, sx, cx), fmaf(rho_sun * invK, sy, cy), fmaf(rho_sun * invK, sz, cz)};
+        f3 dagg{fmaf(rho_sun * invK, sx, cx), fmaf(rho_sun * invK, sy, cy), fmaf(rho_sun * invK, sz, cz)};
+        if (o.dir_pl) dagg = f3{fmaf(invK, qx, dagg.x), fmaf(invK, qy, dagg.y), fmaf(invK, qz, dagg.z)};
         // constant of the row: the vertex's own volume emission (not scattered) + alpha d_agg
         f3 em{0.f, 0.f, 0.f};
         if (o.emit) em = ld3(o.emit, o.canon_row ? (int64_t)o.canon_row[i] : i);
@@ -108,8 +123,10 @@ __global__ __launch_bounds__(kBlock) void k_edges(int64_t N, Consts c, const int
         // own (path-traced) direct: one sun sample, environment and phase samples by the balance heuristic
         const float p_w = c.pdf(u_w), p_e = c.pdf(u_e);
         const float f_env = rho_e / (p_e + c.env_pdf), f_out = rho / (p_w + c.env_pdf);
-        const f3 dpt{rho_sun * ls.x + f_env * le.x + f_out * lp.x, rho_sun * ls.y + f_env * le.y + f_out * lp.y,
-                     rho_sun * ls.z + f_env * le.z + f_out * lp.z};
+        f3 dpt{rho_sun * ls.x + f_env * le.x + f_out * lp.x, rho_sun * ls.y + f_env * le.y + f_out * lp.y,
+               rho_sun * ls.z + f_env * le.z + f_out * lp.z};
+        if (o.dir_pl)   // lane 0 holds the receiver's own sample
+            dpt = f3{fmaf(rho_pl, lpl.x, dpt.x), fmaf(rho_pl, lpl.y, dpt.y), fmaf(rho_pl, lpl.z, dpt.z)};
         st3(o.b, i, b);
         st3(o.dpt, i, dpt);
         o.r[i] = rho / p_w;

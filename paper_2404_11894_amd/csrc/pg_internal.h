@@ -241,7 +241,7 @@ __device__ inline float one_minus_cos(f3 a, f3 b) {
 // dg != NULL also its derivative with respect to g (rho h, h = d ln HG/dg).
 __device__ inline float hg_dlog(float g, float u);
 template <class Rho>
-__device__ inline f3 extra_direct(const pg_paths& P, int64_t p, f3 t, const Rho& rho, float g, f3 sun,
+__device__ inline f3 extra_direct(const pg_paths& P, int64_t p, int64_t v0, f3 t, const Rho& rho, float g, f3 sun,
                                   float env_pdf, f3* dg) {
     const int M = P.n_extra;
     const float us = one_minus_cos(t, sun);
@@ -263,8 +263,20 @@ __device__ inline f3 extra_direct(const pg_paths& P, int64_t p, f3 t, const Rho&
         }
     }
     const float inv = 1.0f / (float)M;
-    if (dg) *dg = f3{e.x * inv, e.y * inv, e.z * inv};
-    return f3{d.x * inv, d.y * inv, d.z * inv};
+    d = f3{d.x * inv, d.y * inv, d.z * inv};
+    e = f3{e.x * inv, e.y * inv, e.z * inv};
+    if (P.dir_pl) {   // a point light keeps the vertex's own shadow-ray sample
+        const float u = one_minus_cos(t, f3{P.dir_pl[3 * v0], P.dir_pl[3 * v0 + 1], P.dir_pl[3 * v0 + 2]});
+        const float rp = rho(u), hp = dg ? rp * hg_dlog(g, u) : 0.0f;
+        d.x += rp * P.l_pl[3 * v0];
+        d.y += rp * P.l_pl[3 * v0 + 1];
+        d.z += rp * P.l_pl[3 * v0 + 2];
+        e.x += hp * P.l_pl[3 * v0];
+        e.y += hp * P.l_pl[3 * v0 + 1];
+        e.z += hp * P.l_pl[3 * v0 + 2];
+    }
+    if (dg) *dg = e;
+    return d;
 }
 
 // d ln HG / d g at u:  -2g/(1-g^2) - 3 (g - cos) / ((1-g)^2 + 2 g u).
@@ -401,6 +413,8 @@ struct EdgeOut {
     float* alpha;        // [N] local
     const int32_t* canon_row;
     const float* emit;   // volume emission e, [N] f3 in canonical (path) order, nullable
+    const float* dir_pl; // point light (canonical order), nullable
+    const float* l_pl;
     float* w_ind;        // path order, nullable
     float* w_ph;
     float* w_env;

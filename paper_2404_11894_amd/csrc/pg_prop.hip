@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_pixels(pg_paths P, Consts c, const i
             sz += P.l_emit[3 * a + 2];
         }
         f3 dd = ld3(dpt, s0);
-        if (P.n_extra > 0) dd = extra_direct(P, p, ld3(P.dir_in, a), c.rho, c.g, c.sun, c.env_pdf, nullptr);
+        if (P.n_extra > 0) dd = extra_direct(P, p, a, ld3(P.dir_in, a), c.rho, c.g, c.sun, c.env_pdf, nullptr);
         sx = fmaf(al, dd.x + ix, sx);
         sy = fmaf(al, dd.y + iy, sy);
         sz = fmaf(al, dd.z + iz, sz);

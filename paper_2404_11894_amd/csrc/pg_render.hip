@@ -85,6 +85,8 @@ hipError_t render_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, co
     o.alpha = r.alpha;
     o.canon_row = g.perm;
     o.emit = p->l_emit;
+    o.dir_pl = p->dir_pl;
+    o.l_pl = p->l_pl;
     if (out) {
         o.w_ind = out->w_ind;
         o.w_ph = out->w_ph;

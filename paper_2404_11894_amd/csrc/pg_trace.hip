@@ -69,6 +69,7 @@ __device__ inline D3 normalized(D3 v) {
 struct Tracer {
     pg_tracer t;
     int cw, ch, cx0, cy0;
+    int point_light;
     // camera frame
     D3 f, r, up;
     double th, aspect;
@@ -187,6 +188,7 @@ __device__ inline double ratio_track(const pg_tracer& t, Rng& rng, const D3& o, 
 struct Out {
     float *pos, *dir_in, *dir_out, *albedo, *l_sun, *dir_env, *l_env, *l_phase;
     float *fb_l_sun, *fb_dir_env, *fb_l_env;   // [P][M][3]
+    float *dir_pl, *l_pl;
 };
 
 // The M extra emitter samples at a path's first vertex pt (paper, handling
@@ -250,6 +252,21 @@ __device__ int trace_path(const Tracer& tr, int64_t p, int64_t v0, int64_t vcap,
         const double e1 = rng.uniform();
         const D3 we = sample_sphere(e1, e2);
         const double Te = ratio_track(t, rng, pt, we, exit_distance(pt, we));
+        // point light shadow ray (delta light): irradiance I T / r^2
+        D3 dl = d3(0.0, 0.0, 0.0);
+        double lpl[3] = {0.0, 0.0, 0.0};
+        bool pl_zero = true;
+        if (tr.point_light) {
+            D3 v = d3(t.pl_pos[0] - pt.x, t.pl_pos[1] - pt.y, t.pl_pos[2] - pt.z);
+            const double r2 = v.x * v.x + v.y * v.y + v.z * v.z;
+            const double dist = sqrt(r2);
+            dl = d3(v.x / dist, v.y / dist, v.z / dist);
+            double tmax = exit_distance(pt, dl);
+            if (dist < tmax) tmax = dist;
+            const double Tp = ratio_track(t, rng, pt, dl, tmax);
+            for (int a = 0; a < 3; ++a) lpl[a] = t.pl_I[a] * Tp / r2;
+            pl_zero = false;
+        }
         const double h2 = rng.uniform();   // azimuth number first
         const double h1 = rng.uniform();
         const D3 wo = sample_hg(d, t.g, h1, h2);
@@ -272,6 +289,11 @@ __device__ int trace_path(const Tracer& tr, int64_t p, int64_t v0, int64_t vcap,
                 o.l_phase[3 * v + a] = escaped ? (float)t.env_L[a] : 0.0f;
             }
             o.albedo[v] = (float)alb;
+            if (tr.point_light)
+                for (int a = 0; a < 3; ++a) {
+                    o.dir_pl[3 * v + a] = pl_zero ? 0.0f : (float)comp(dl, a);
+                    o.l_pl[3 * v + a] = (float)lpl[a];
+                }
         }
         ++nv;
         if (last || escaped) break;
@@ -318,6 +340,7 @@ static Tracer make_tracer(const pg_tracer* t) {
     tr.ch = t->crop_w ? t->crop_h : t->height;
     tr.cx0 = t->crop_w ? t->crop_x0 : 0;
     tr.cy0 = t->crop_w ? t->crop_y0 : 0;
+    tr.point_light = t->pl_I[0] != 0.0 || t->pl_I[1] != 0.0 || t->pl_I[2] != 0.0;
     // camera frame, as the device would compute it (host double, same order)
     double f[3], r[3], up[3];
     const double wup[3] = {0.0, 1.0, 0.0};
@@ -385,7 +408,7 @@ hipError_t run_trace_write(const pg_tracer* t, const int64_t* path_offsets, cons
     if (P == 0) return hipSuccess;
     const Tracer tr = make_tracer(t);
     Out out{o.pos, o.dir_in, o.dir_out, o.albedo, o.l_sun, o.dir_env, o.l_env, o.l_phase,
-            o.fb_l_sun, o.fb_dir_env, o.fb_l_env};
+            o.fb_l_sun, o.fb_dir_env, o.fb_l_env, o.dir_pl, o.l_pl};
     ProfScope ps(s, "trace_write");
     hipLaunchKernelGGL(k_trace_write, dim3((unsigned)div_up(P, kBlock)), dim3(kBlock), 0, s, tr, P, path_offsets, out,
                        o.e_cam, flag);

@@ -50,11 +50,14 @@ def test_backward_matches_oracle(init, fg, emit):
     grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
 
 
-def test_backward_with_extra_first_vertex_samples():
+@pytest.mark.parametrize("extra,point", [(3, False), (0, True), (2, True)])
+def test_backward_with_extra_samples_and_point_light(extra, point):
     from dataclasses import replace
-    cfg = replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 32, 32, 2), extra_samples=3)
+    cfg = replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 32, 32, 2), extra_samples=extra)
+    if point:
+        cfg = replace(cfg, pl_I=(0.4, 0.3, 0.2))
     sc = scenegen.generate(cfg)
-    print(f"adjoint with extra samples N={sc.n_vertices}", flush=True)
+    print(f"adjoint extra={extra} point={point} N={sc.n_vertices}", flush=True)
     grid, gimg, ref = case(sc, 8, 8, 6, 0.5, "pt", 0)
     paths = pg.DevicePaths(sc, albedo_grid=grid)
     q = pg.params(k=8, D=6, g=0.5, flags=pg.PG_FLAG_CHECK)

@@ -26,6 +26,7 @@ def small_batch():
         (replace(base, sigma_max=4.0, width=20, height=20, spp=1, seed=15), 12, 0, 0.3),
         (replace(base, width=16, height=24, spp=3, seed=16), 1, 5, 0.5),
         (replace(base, width=20, height=16, spp=2, emit_L=(2.0, 1.5, 1.0), seed=17), 8, 5, 0.5),   # emissive
+        (replace(base, width=16, height=16, spp=2, pl_I=(0.4, 0.3, 0.2), extra_samples=2, seed=18), 8, 4, 0.5),
     ]
     scenes, params, oparams = [], [], []
     for cfg, k, D, g in specs:

@@ -116,6 +116,46 @@ def test_render_with_extra_first_vertex_samples(fg, clusters):
     assert not np.allclose(ref, plain)
 
 
+@pytest.mark.parametrize("fg,clusters,extra", [(0, False, 0), (1, False, 0), (0, True, 0), (0, False, 3)])
+def test_render_with_point_light(fg, clusters, extra):
+    cfg = replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 32, 32, 2), pl_I=(0.4, 0.3, 0.2),
+                  extra_samples=extra)
+    sc = scenegen.generate(cfg)
+    assert sc.l_pl is not None
+    if clusters:
+        sc = replace(sc, cluster_key=scenegen.cluster_keys(sc.n_vertices, 7))
+    print(f"point light fg={fg} clusters={clusters} extra={extra} N={sc.n_vertices}", flush=True)
+    op = oracle.params(k=8, D=6, g=0.5, final_gather=fg, neighbours="clusters" if clusters else "knn")
+    if clusters:
+        fl = pg.PG_FLAG_CHECK | pg.PG_FLAG_CLUSTERS
+        img, gr = pg.pg_render(pg.DevicePaths(sc), pg.params(k=8, D=6, g=0.5, final_gather=fg, flags=fl), graph=True)
+        torch.cuda.synchronize()
+        ref_img, ref = oracle.render(sc, op, trace=True)
+        assert_within(gr["b"].cpu().numpy(), ref["b"], W_REL, W_ABS, "b")
+        assert_within(gr["d_pt"].cpu().numpy(), ref["d_pt"], W_REL, W_ABS, "d_pt")
+        assert_within(img.cpu().numpy(), ref_img, PIX_REL, PIX_ABS, "image")
+    else:
+        img, gr = gpu_render(sc, 8, 6, 0.5, fg=fg)
+        ref_img, ref = oracle.render(sc, op, trace=True)
+        compare_all(sc, 8, img, gr, ref_img, ref, f"point light {fg}/{extra}")
+    dark = oracle.render(replace(sc, dir_pl=None, l_pl=None), op)
+    assert not np.allclose(ref_img, dark)
+
+
+def test_entry_points_compose_with_point_light():
+    sc = scenegen.generate(replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 24, 24, 2),
+                                   pl_I=(0.4, 0.3, 0.2)))
+    paths = pg.DevicePaths(sc)
+    q = pg.params(k=8, D=4, g=0.5, flags=pg.PG_FLAG_CHECK)
+    rp, col = pg.pg_knn(paths, 8)
+    e = pg.pg_edges(paths, q, rp, col)
+    torch.cuda.synchronize()
+    _, ref = oracle.render(sc, oracle.params(k=8, D=4, g=0.5), trace=True)
+    assert_within(e["b"].cpu().numpy(), ref["b"], W_REL, W_ABS, "b")
+    assert_within(e["d_pt"].cpu().numpy(), ref["d_pt"], W_REL, W_ABS, "d_pt")
+    assert_within(e["lplus0"].cpu().numpy(), ref["lplus0"], W_REL, W_ABS, "lplus0")
+
+
 @pytest.mark.parametrize("k", [1, 2, 5, 12, 16, 33, 64])
 def test_neighbour_counts(k):
     sc = crop("tiny", 24, 24, 2)

@@ -99,6 +99,17 @@ def test_trace_extra_first_vertex_samples():
     assert torch.equal(plain.pos, rec.pos)
 
 
+def test_trace_point_light():
+    cfg = replace(scenegen.crop_of(scenegen.WORKLOADS["mid"].scene, 48, 48, 2), pl_I=(0.5, 0.4, 0.3),
+                  pl_pos=(0.2, 1.3, 0.4))
+    ref, rec = compare(cfg)
+    if np.array_equal(rec.path_offsets.cpu().numpy(), ref.path_offsets):
+        for name in ("dir_pl", "l_pl"):
+            a, b = getattr(rec, name).cpu().numpy(), getattr(ref, name)
+            ulps = np.abs(a.view(np.int32).astype(np.int64) - b.view(np.int32).astype(np.int64))
+            assert ((ulps > 2) & (a != b)).any(axis=1).sum() <= max(2, int(1e-4 * len(a))), name
+
+
 def test_traced_records_render_like_host_records():
     cfg = scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 48, 48, 2)
     ref = scenegen.generate(cfg)
@@ -129,7 +140,7 @@ def test_trace_records_rejects_foreign_offsets():
     N = rec.n_vertices
     bufs = {f: torch.full((N * (1 if f == "albedo" else 3),), -3.0, device="cuda") for f in FIELDS}
     e_cam = torch.empty(64 * 3, device="cuda")
-    r = pg.Records(*(bufs[f].data_ptr() for f in FIELDS), e_cam.data_ptr(), None, None, None)
+    r = pg.Records(*(bufs[f].data_ptr() for f in FIELDS), e_cam.data_ptr(), None, None, None, None, None)
     nb = ctypes.c_size_t()
     L = pg.lib()
     pg._check(L.pg_trace_workspace_size(ctypes.byref(t), ctypes.byref(nb)))
