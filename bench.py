@@ -50,10 +50,14 @@ def algorithmic_bytes(step, N, K, starts):
     return None
 
 
-def kernel_source_hash():
-    """sha256 over the propagation kernels' source and the header they include."""
+SOURCES = {"spmv": ("pg_prop.hip", "pg_internal.h"), "shift": ("pg_prop.hip", "pg_internal.h"),
+           "cagg": ("pg_clusters.hip", "pg_internal.h")}
+
+
+def kernel_source_hash(kernel="spmv"):
+    """sha256 over the kernel's source file and the header it includes."""
     hsh = hashlib.sha256()
-    for f in ("pg_prop.hip", "pg_internal.h"):
+    for f in SOURCES[kernel]:
         hsh.update(open(os.path.join(ROOT, "paper_2404_11894_amd", "csrc", f), "rb").read())
     return hsh.hexdigest()
 
@@ -69,7 +73,7 @@ def read_traffic(kernel, workload):
     h = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
     if not m or not h:
         return None
-    if kernel_source_hash() != h.group(1):
+    if kernel_source_hash(kernel if kernel in SOURCES else "spmv") != h.group(1):
         return None
     return float(m.group(1))
 
@@ -194,11 +198,12 @@ def time_clusters(pg, torch, sc, w, steps, warmup, knn_ms):
     del render, paths
     torch.cuda.empty_cache()
     return {"value": round(E * w.D / (ms / 1e3) / 1e9, 2), "unit": "Gedge-updates/s", "ms_per_step": round(ms, 3),
-            "vs_knn_render": round(knn_ms / ms, 3), "E": E, "clusters": int(nz.numel()),
+            "vs_knn_render": round(knn_ms / ms, 3) if knn_ms == knn_ms else None, "E": E, "clusters": int(nz.numel()),
             "mean_size": round(N / max(1, int(nz.numel())), 2), "max_size": int(nz.max().item()),
             "phases_ms": phases,
             "aggregation": {"kernel": "k_cagg", "avg_launch_ms": round(avg_s * 1e3, 4),
                             "algorithmic_bytes_per_launch": int(ab),
+                            "traffic": read_traffic("cagg", "mid") if w.name == "mid" else None,
                             "algorithmic_GBs": round(ab / avg_s / 1e9, 1), "hbm_frac": round(ab / avg_s / 1e9 / HBM_PEAK_GBS, 4),
                             "TFLOPs": round(flops / avg_s / 1e12, 2), "fp32_frac": round(flops / avg_s / 1e12 / 157.3, 4),
                             "gedge_per_s_per_launch": round(E / avg_s / 1e9, 1)},
@@ -371,6 +376,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-clusters", action="store_true")
     ap.add_argument("--no-tracer", action="store_true")
+    ap.add_argument("--only", choices=["clusters", "tracer", "adjoint", "batched"],
+                    help="run only this leg (for profiling) and print its JSON")
     ap.add_argument("--study", action="store_true",
                     help="convergence and 1-spp error study instead of the timing (one JSON line)")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -401,19 +408,32 @@ def main():
     paths = pg.DevicePaths(sc, device=dev)
     torch.cuda.synchronize()
     host_copy_s = time.perf_counter() - t0
+    if args.pmc_probe:
+        a = torch.ones(256 * 1024 * 1024, device=dev)          # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("pmc probe: copied 1 GiB (1 GiB read + 1 GiB written)")
+    if args.only:
+        if args.only == "clusters":
+            leg = time_clusters(pg, torch, sc, w, args.steps, max(1, args.warmup), float("nan"))
+        elif args.only == "tracer":
+            leg = time_tracer(pg, torch, w, host_gen_s, host_copy_s)
+        elif args.only == "adjoint":
+            leg = time_fwd_adjoint(pg, torch, sc, w, args.steps, max(1, args.warmup))
+        else:
+            del paths
+            torch.cuda.empty_cache()
+            leg = time_batched(pg, torch, args.steps)
+        print(json.dumps({"leg": args.only, **leg}), flush=True)
+        return
     q = pg.params(k=w.k, D=w.D, g=w.g, schedule=args.schedule, cell_shift=args.cell_shift)
     N = sc.n_vertices
     K = min(w.k, N)
     E = N * K
     render = pg.Renderer(paths, q)
     image = torch.empty(sc.height, sc.width, 3, device=dev)
-
-    if args.pmc_probe:
-        a = torch.ones(256 * 1024 * 1024, device=dev)          # 1 GiB
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log("pmc probe: copied 1 GiB (1 GiB read + 1 GiB written)")
 
     for _ in range(args.warmup):
         render(image)
