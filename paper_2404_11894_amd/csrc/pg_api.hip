@@ -81,7 +81,6 @@ pg_status validate_params(const pg_params* q) {
 
 pg_status validate_clusters(const pg_paths* p, const pg_params* q) {
     if (!(q->flags & PG_FLAG_CLUSTERS)) return PG_OK;
-    if (q->flags & PG_FLAG_TAPE) return fail(PG_ERR_UNSUPPORTED, "the reverse mode does not support PG_FLAG_CLUSTERS");
     if (q->schedule != 0 && q->schedule != PG_SCHED_TWO_PASS)
         return fail(PG_ERR_UNSUPPORTED, "PG_FLAG_CLUSTERS runs the two-pass schedule only");
     if (p->n_vertices > 0 && !p->cluster_key) return fail(PG_ERR_ARG, "PG_FLAG_CLUSTERS needs paths->cluster_key");

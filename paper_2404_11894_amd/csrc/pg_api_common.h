@@ -9,6 +9,22 @@
 
 namespace pg {
 
+// Sum of one double per thread over the block; the result is valid in thread 0.
+__device__ inline double block_sum_d(double v) {
+    __shared__ double sh[kBlock / kWave];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kBlock / kWave; ++w) t += sh[w];
+    return t;
+}
+
+__device__ inline float dot3(f3 a, f3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+
 extern thread_local std::string g_error;
 pg_status fail(pg_status code, const char* fmt, ...);
 pg_status hip_fail(hipError_t e, const char* where);
@@ -165,6 +181,7 @@ struct BackBufs {
     double* gpart = nullptr;   // [n_slots]
     double* gchunk = nullptr;   // per-chunk totals of gpart
     float* image = nullptr;    // forward image when the tape is recomputed
+    int32_t* cpid = nullptr;   // cluster relation: position -> path id
 };
 void carve_back(Carver& cv, BackBufs& bb, const RenderBufs& r, const pg_paths* p);
 hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, BackBufs& bb, const float* gimg,
@@ -193,6 +210,17 @@ hipError_t cluster_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, c
 hipError_t cluster_iterate(RenderBufs& r, const pg_params* q, float* x0, hipStream_t s, float** final_x);
 hipError_t cluster_output(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out,
                           float* image, const float* cur, hipStream_t s);
+// Reverse mode of the cluster relation (kernels in pg_clusters.hip).
+hipError_t launch_cluster_cpid(int64_t N, const RenderBufs& r, int32_t* cpid, hipStream_t s);
+hipError_t launch_cluster_out_adjoint(const pg_paths& P, const Consts& c, const RenderBufs& r, const float* gimg,
+                                      float* abar, float* dptbar, float* rbar, float* lam, double* gpart,
+                                      int64_t nblocks, hipStream_t s);
+hipError_t launch_cluster_reverse_step(const RenderBufs& r, const pg_params* q, int t, const float* lam,
+                                       float* lam_prev, float* abar, float* bbar, float* zbar, double* gpart,
+                                       hipStream_t s);
+hipError_t launch_cluster_edges_adjoint(const pg_paths& P, const Consts& c, const RenderBufs& r, const int32_t* cpid,
+                                        const float* bbar, const float* dptbar, const float* rbar, float* abar,
+                                        double* gpart, hipStream_t s);
 // Runs grid, kNN, edges, paths, D iterations and pixels; fills `out` if given.
 // *final_x receives the buffer holding L_D (sorted order).
 hipError_t run_render(const pg_paths* p, const pg_params* q, RenderBufs& r, const pg_graph_out* out, float* image,

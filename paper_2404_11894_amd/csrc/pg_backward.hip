@@ -11,25 +11,12 @@
 // go to fixed slots and are reduced in a fixed order, so dL/dg does not depend
 // on scheduling; the grid scatter and the output's neighbour scatter use
 // float atomics (order-dependent in the last bits).
+#include <utility>
+
 #include "pg_api_common.h"
 
 namespace pg {
 
-// Sum of one double per thread over the block; the result is valid in thread 0.
-__device__ inline double block_sum_d(double v) {
-    __shared__ double sh[kBlock / kWave];
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kBlock / kWave; ++w) t += sh[w];
-    return t;
-}
-
-__device__ inline float dot3(f3 a, f3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
 
 // ------------------------------------------------- transposed operator ---
 // W^T in a sliced ELL: T-row j (the rows i that have j as a neighbour) lives in
@@ -579,6 +566,24 @@ __global__ __launch_bounds__(kBlock) void k_reduce_g(int64_t n, const double* __
 
 void carve_back(Carver& cv, BackBufs& bb, const RenderBufs& r, const pg_paths* p) {
     const int64_t N = r.N, E = N * (int64_t)r.K;
+    if (r.clusters) {   // no transpose: the cluster's member range serves both products
+        bb.n_rows = div_up(N > 0 ? N : 1, kBlock);
+        bb.n_edge = div_up(N > 0 ? N : 1, kBlock);
+        bb.n_out = div_up(r.P > 0 ? r.P : 1, kBlock);
+        bb.n_slots = bb.n_rows + bb.n_edge + bb.n_out;
+        bb.lam_a = cv.take<float>(3 * N);
+        bb.lam_b = cv.take<float>(3 * N);
+        bb.zbar = cv.take<float>(3 * N);
+        bb.abar = cv.take<float>(N);
+        bb.bbar = cv.take<float>(3 * N);
+        bb.dptbar = cv.take<float>(3 * N);
+        bb.rbar = cv.take<float>(N);
+        bb.cpid = cv.take<int32_t>(N);
+        bb.gpart = cv.take<double>(bb.n_slots);
+        bb.gchunk = cv.take<double>(div_up(bb.n_slots, kReduceChunk));
+        bb.image = cv.take<float>((int64_t)p->width * p->height * 3);
+        return;
+    }
     int kp = 1;
     while (kp < (r.K > 0 ? r.K : 1)) kp *= 2;
     bb.n_rows = div_up(N > 0 ? N : 1, kBlock);          // reverse sweep: one thread per row
@@ -615,8 +620,69 @@ void carve_back(Carver& cv, BackBufs& bb, const RenderBufs& r, const pg_paths* p
         if (e_ != hipSuccess) return e_; \
     } while (0)
 
+// The reverse mode of the cluster relation: the same steps in cluster order,
+// with the transposed product taken over each sample's cluster.
+static hipError_t run_backward_clusters(const pg_paths* p, const pg_params* q, RenderBufs& r, BackBufs& bb,
+                                        const float* gimg, float* grad_grid, float* grad_alpha, float* grad_g,
+                                        hipStream_t s) {
+    const int64_t N = r.N;
+    const int D = r.D;
+    const Consts c = make_consts(q, r.K);
+    PG_TRY(launch_fill(bb.lam_a, (size_t)N * 12, s));
+    PG_TRY(launch_fill(bb.abar, (size_t)N * 4, s));
+    PG_TRY(launch_fill(bb.bbar, (size_t)N * 12, s));
+    PG_TRY(launch_fill(bb.dptbar, (size_t)N * 12, s));
+    PG_TRY(launch_fill(bb.rbar, (size_t)N * 4, s));
+    PG_TRY(launch_fill(bb.gpart, (size_t)bb.n_slots * 8, s));
+    if (grad_grid && p->albedo_grid) {
+        const int64_t R = p->albedo_grid_res;
+        PG_TRY(launch_fill(grad_grid, (size_t)(R * R * R) * 4, s));
+    }
+    PG_TRY(launch_cluster_cpid(N, r, bb.cpid, s));
+    double* g_rows = bb.gpart;
+    double* g_edges = bb.gpart + bb.n_rows;
+    double* g_out = bb.gpart + bb.n_rows + bb.n_edge;
+    {
+        ProfScope ps(s, "out_adjoint");
+        PG_TRY(launch_cluster_out_adjoint(*p, c, r, gimg, bb.abar, bb.dptbar, bb.rbar, bb.lam_a, g_out, bb.n_out, s));
+    }
+    float* lam = bb.lam_a;
+    float* lam_prev = bb.lam_b;
+    for (int t = D; t >= 1 && N > 0; --t) {
+        PG_TRY(launch_cluster_reverse_step(r, q, t, lam, lam_prev, bb.abar, bb.bbar, bb.zbar, g_rows, s));
+        std::swap(lam, lam_prev);
+    }
+    if (q->init == PG_INIT_PT && N > 0) {
+        ProfScope ps(s, "pt_adjoint");
+        hipLaunchKernelGGL(k_pt_adjoint, dim3((unsigned)div_up(r.P > 0 ? r.P : 1, kBlock)), dim3(kBlock), 0, s,
+                           r.P, N, p->path_offsets, r.cl.cinv, r.alpha, r.dpt, r.r, r.traj, lam, bb.abar, bb.dptbar,
+                           bb.rbar);
+        PG_TRY(hipGetLastError());
+    }
+    {
+        ProfScope ps(s, "edges_adjoint");
+        PG_TRY(launch_cluster_edges_adjoint(*p, c, r, bb.cpid, bb.bbar, bb.dptbar, bb.rbar, bb.abar, g_edges, s));
+    }
+    if (N > 0) {
+        ProfScope ps(s, "grid_adjoint");
+        hipLaunchKernelGGL(k_grid_adjoint, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, *p, bb.cpid,
+                           bb.abar, grad_grid, grad_alpha);
+        PG_TRY(hipGetLastError());
+    }
+    if (grad_g) {
+        const int64_t nchunk = div_up(bb.n_slots, kReduceChunk);
+        hipLaunchKernelGGL(k_reduce_g, dim3((unsigned)nchunk), dim3(kBlock), 0, s, bb.n_slots, bb.gpart, bb.gchunk,
+                           (float*)nullptr);
+        hipLaunchKernelGGL(k_reduce_g, dim3(1), dim3(kBlock), 0, s, nchunk, (const double*)bb.gchunk,
+                           (double*)nullptr, grad_g);
+        PG_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
 hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, BackBufs& bb, const float* gimg,
                         float* grad_grid, float* grad_alpha, float* grad_g, hipStream_t s) {
+    if (r.clusters) return run_backward_clusters(p, q, r, bb, gimg, grad_grid, grad_alpha, grad_g, s);
     const int64_t N = r.N, E = N * (int64_t)r.K;
     const int K = r.K, D = r.D;
     const Consts c = make_consts(q, K);
@@ -747,8 +813,7 @@ pg_status pg_backward_workspace_size(const pg_paths* paths, const pg_params* par
     pg_status st;
     if ((st = validate_paths(paths, true)) || (st = validate_params(params))) return st;
     if (!bytes) return fail(PG_ERR_ARG, "bytes is NULL");
-    if (params->flags & PG_FLAG_CLUSTERS)
-        return fail(PG_ERR_UNSUPPORTED, "the reverse mode does not support PG_FLAG_CLUSTERS");
+    if ((st = validate_clusters(paths, params))) return st;
     Carver cv(nullptr);
     RenderBufs r;
     BackBufs bb;
@@ -763,11 +828,10 @@ pg_status pg_backward(const pg_paths* paths, const pg_params* params, const floa
     pg_status st;
     if ((st = validate_paths(paths, true)) || (st = validate_params(params))) return st;
     if (!grad_image) return fail(PG_ERR_ARG, "grad_image is NULL");
-    if (params->flags & PG_FLAG_CLUSTERS)
-        return fail(PG_ERR_UNSUPPORTED, "the reverse mode does not support PG_FLAG_CLUSTERS");
+    if ((st = validate_clusters(paths, params))) return st;
     if (grad_grid && !paths->albedo_grid) return fail(PG_ERR_ARG, "grad_grid needs paths->albedo_grid");
     if (!grad_grid && !grad_albedo && !grad_g) return fail(PG_ERR_ARG, "no gradient requested");
-    {
+    if (!(params->flags & PG_FLAG_CLUSTERS)) {
         const int64_t N = paths->n_vertices, K = N < params->k ? N : params->k;
         if (N * K >= ((int64_t)1 << 32) || div_up(N, kSlice) * kSlice * 2 * K >= ((int64_t)1 << 32))
             return fail(PG_ERR_UNSUPPORTED, "pg_backward needs N*K < 2^31 edges");

@@ -664,6 +664,259 @@ __global__ __launch_bounds__(kBlock) void k_cexport(int64_t N, Consts c, const u
     }
 }
 
+// ------------------------------------------------------- reverse mode ---
+// The adjoint of the cluster render, in cluster order.  The tape holds
+// x_0 (traj[0]) and y_1..y_D (traj[t]): L_{t-1}(j) = x_0(j) for t = 1, else
+// y_{t-1}(succ j).  W_ij = rho_i(w_j) c_g / M+_j inside a cluster; since a
+// sample's cluster is also its receivers' cluster, the transpose product
+// lam_{t-1}(j) = sum_i W_ij zbar_i runs over the same member range as the
+// forward product, with the roles of (t, w) swapped: no transpose is built.
+
+// L_{t-1}(j) of the tape
+template <bool SHIFTED>
+__device__ __forceinline__ f3 tape_x(const float* __restrict__ x, const int32_t* __restrict__ succ, int64_t j) {
+    if (!SHIFTED) return ld3(x, j);
+    const int32_t sj = succ[j];
+    return sj >= 0 ? ld3(x, sj) : f3{0.f, 0.f, 0.f};
+}
+
+// Output: o_p = e + alpha (d + in) at the first vertex i of path p.
+__global__ __launch_bounds__(kBlock) void k_cout_adjoint(pg_paths P, Consts c, const int32_t* __restrict__ cinv,
+                                                         const uint2* __restrict__ crange,
+                                                         const float4* __restrict__ tq, const float4* __restrict__ wq,
+                                                         const float* __restrict__ xD, const float* __restrict__ dpt,
+                                                         const float* __restrict__ r, const float* __restrict__ gimg,
+                                                         float* __restrict__ abar, float* __restrict__ dptbar,
+                                                         float* __restrict__ rbar, float* __restrict__ lam,
+                                                         double* __restrict__ gpart) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double gl = 0.0;
+    if (p < P.n_paths) {
+        const int64_t a = P.path_offsets[p], e = P.path_offsets[p + 1];
+        if (e > a && a >= 0 && e <= P.n_vertices) {
+            const int64_t px = p / P.spp, i = cinv[a];
+            const float is = 1.0f / (float)P.spp;
+            const f3 ob{gimg[3 * px] * is, gimg[3 * px + 1] * is, gimg[3 * px + 2] * is};
+            const float4 t4 = tq[i];
+            const f3 ti{t4.x, t4.y, t4.z};
+            const bool extra = P.n_extra > 0;
+            f3 ddg{0.f, 0.f, 0.f};
+            const f3 d = extra ? extra_direct(P, p, a, ti, c.rho, c.g, c.sun, c.env_pdf, &ddg) : ld3(dpt, i);
+            const f3 zb{t4.w * ob.x, t4.w * ob.y, t4.w * ob.z};
+            if (extra) gl += (double)dot3(zb, ddg);
+            if (c.final_gather == 0) {
+                const uint2 rg = bounded(crange[i]);
+                f3 in{0.f, 0.f, 0.f}, ing{0.f, 0.f, 0.f};
+                for (uint32_t j = rg.x; j < rg.y; ++j) {
+                    const float4 w4 = wq[j];
+                    const f3 wj{w4.x, w4.y, w4.z};
+                    const float f = hg_shape(c.rho, ti, w4.x, w4.y, w4.z) * w4.w;
+                    const float fh = f * hg_dlog(c.g, one_minus_cos(ti, wj));
+                    const f3 xv = ld3(xD, j);
+                    in = f3{fmaf(f, xv.x, in.x), fmaf(f, xv.y, in.y), fmaf(f, xv.z, in.z)};
+                    ing = f3{fmaf(fh, xv.x, ing.x), fmaf(fh, xv.y, ing.y), fmaf(fh, xv.z, ing.z)};
+                    atomicAdd(&lam[3 * j], f * zb.x);
+                    atomicAdd(&lam[3 * j + 1], f * zb.y);
+                    atomicAdd(&lam[3 * j + 2], f * zb.z);
+                }
+                abar[i] += dot3(ob, f3{d.x + in.x, d.y + in.y, d.z + in.z});
+                gl += (double)dot3(zb, ing);
+            } else {
+                const f3 xv = ld3(xD, i);
+                const float rr = r[i];
+                abar[i] += dot3(ob, f3{fmaf(rr, xv.x, d.x), fmaf(rr, xv.y, d.y), fmaf(rr, xv.z, d.z)});
+                rbar[i] += dot3(zb, xv);
+                atomicAdd(&lam[3 * i], rr * zb.x);
+                atomicAdd(&lam[3 * i + 1], rr * zb.y);
+                atomicAdd(&lam[3 * i + 2], rr * zb.z);
+            }
+            if (!extra) {
+                dptbar[3 * i] += zb.x;
+                dptbar[3 * i + 1] += zb.y;
+                dptbar[3 * i + 2] += zb.z;
+            }
+        }
+    }
+    const double t = block_sum_d(gl);
+    if (threadIdx.x == 0) gpart[blockIdx.x] = t;
+}
+
+// Row i of iteration t: y_i = b_i + alpha_i z_i, z_i = sum_j W_ij L_{t-1}(j).
+// The adjoint of y_i is lam_t(pred i); adds <ybar, z_i> to abar_i and ybar to
+// bbar_i, stores zbar_i = alpha_i ybar and adds <zbar_i, sum_j dW_ij/dg
+// L_{t-1}(j)> (dW/dg = W h) to the block's dL/dg slot.  The block's member
+// span is staged in LDS as in the forward product.
+template <bool SHIFTED>
+__global__ __launch_bounds__(kBlock) void k_crev_rows(int64_t N, HG rho, float g, const uint2* __restrict__ crange,
+                                                      const float4* __restrict__ tq, const float4* __restrict__ wq,
+                                                      const float* __restrict__ x, const int32_t* __restrict__ succ,
+                                                      const float* __restrict__ lam, const int32_t* __restrict__ pred,
+                                                      float* __restrict__ abar, float* __restrict__ bbar,
+                                                      float* __restrict__ zbar, double* __restrict__ gpart) {
+    __shared__ float4 sw[kSpan];
+    __shared__ float sx[3 * kSpan];
+    const int64_t i0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t i = i0 + threadIdx.x;
+    const int64_t ilast = i0 + kBlock - 1 < N ? i0 + kBlock - 1 : N - 1;
+    const uint32_t lo = crange[i0].x, hi = crange[ilast].y;
+    const bool staged = hi - lo <= (uint32_t)kSpan;
+    if (staged) {
+        for (uint32_t t = threadIdx.x; t < hi - lo; t += kBlock) {
+            sw[t] = wq[lo + t];
+            const f3 v = tape_x<SHIFTED>(x, succ, lo + t);
+            sx[3 * t] = v.x;
+            sx[3 * t + 1] = v.y;
+            sx[3 * t + 2] = v.z;
+        }
+        __syncthreads();
+    }
+    double gl = 0.0;
+    if (i < N) {
+        const float4 t4 = tq[i];
+        const f3 ti{t4.x, t4.y, t4.z};
+        const uint2 rg = bounded(crange[i]);
+        f3 z{0.f, 0.f, 0.f}, zg{0.f, 0.f, 0.f};
+        for (uint32_t j = rg.x; j < rg.y; ++j) {
+            const float4 w4 = staged ? sw[j - lo] : wq[j];
+            const f3 xv = staged ? f3{sx[3 * (j - lo)], sx[3 * (j - lo) + 1], sx[3 * (j - lo) + 2]}
+                                 : tape_x<SHIFTED>(x, succ, j);
+            const float f = hg_shape(rho, ti, w4.x, w4.y, w4.z) * w4.w;
+            const float fh = f * hg_dlog(g, one_minus_cos(ti, f3{w4.x, w4.y, w4.z}));
+            z = f3{fmaf(f, xv.x, z.x), fmaf(f, xv.y, z.y), fmaf(f, xv.z, z.z)};
+            zg = f3{fmaf(fh, xv.x, zg.x), fmaf(fh, xv.y, zg.y), fmaf(fh, xv.z, zg.z)};
+        }
+        const int32_t pv = pred[i];
+        const f3 yb = pv >= 0 ? ld3(lam, pv) : f3{0.f, 0.f, 0.f};
+        abar[i] += dot3(yb, z);
+        bbar[3 * i] += yb.x;
+        bbar[3 * i + 1] += yb.y;
+        bbar[3 * i + 2] += yb.z;
+        const f3 zb{t4.w * yb.x, t4.w * yb.y, t4.w * yb.z};
+        st3(zbar, i, zb);
+        gl = (double)dot3(zb, zg);
+    }
+    const double t = block_sum_d(gl);
+    if (threadIdx.x == 0) gpart[blockIdx.x] += t;
+}
+
+// lam_{t-1}(j) = sum_{i in cluster(j)} W_ij zbar_i = (c_g / M+_j) sum_i
+// rho_i(w_j) zbar_i: the receivers' (t_i, zbar_i) of the span in LDS.
+__global__ __launch_bounds__(kBlock) void k_crev_cols(int64_t N, HG rho, const uint2* __restrict__ crange,
+                                                      const float4* __restrict__ tq, const float4* __restrict__ wq,
+                                                      const float* __restrict__ zbar, float* __restrict__ lam) {
+    __shared__ float4 st[kSpan];
+    __shared__ float sz[3 * kSpan];
+    const int64_t j0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t j = j0 + threadIdx.x;
+    const int64_t jlast = j0 + kBlock - 1 < N ? j0 + kBlock - 1 : N - 1;
+    const uint32_t lo = crange[j0].x, hi = crange[jlast].y;
+    const bool staged = hi - lo <= (uint32_t)kSpan;
+    if (staged) {
+        for (uint32_t t = threadIdx.x; t < hi - lo; t += kBlock) st[t] = tq[lo + t];
+        for (uint32_t t = threadIdx.x; t < 3 * (hi - lo); t += kBlock) sz[t] = zbar[3 * (int64_t)lo + t];
+        __syncthreads();
+    }
+    if (j >= N) return;
+    const float4 w4 = wq[j];
+    const uint2 rg = bounded(crange[j]);
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    for (uint32_t i = rg.x; i < rg.y; ++i) {
+        const float4 t4 = staged ? st[i - lo] : tq[i];
+        const f3 zb = staged ? f3{sz[3 * (i - lo)], sz[3 * (i - lo) + 1], sz[3 * (i - lo) + 2]} : ld3(zbar, i);
+        const float f = hg_shape(rho, f3{t4.x, t4.y, t4.z}, w4.x, w4.y, w4.z);
+        ax = fmaf(f, zb.x, ax);
+        ay = fmaf(f, zb.y, ay);
+        az = fmaf(f, zb.z, az);
+    }
+    st3(lam, j, f3{ax * w4.w, ay * w4.w, az * w4.w});
+}
+
+// Direct terms, per receiver over its cluster (mirrors k_cedges):
+//   d/d alpha_i += <bbar_i, d_agg_i>,
+//   dL/dg += <alpha_i bbar_i, d d_agg_i/dg> + <dptbar_i, d d_pt_i/dg> + rbar_i r_i h(u_w,i).
+__global__ __launch_bounds__(kBlock) void k_cedges_adjoint(int64_t N, Consts c, const uint2* __restrict__ crange,
+                                                           const VRec* __restrict__ crec,
+                                                           const float4* __restrict__ tq,
+                                                           const float* __restrict__ mp, const float* __restrict__ me,
+                                                           const int32_t* __restrict__ cpid,
+                                                           const float* __restrict__ dir_pl,
+                                                           const float* __restrict__ l_pl,
+                                                           const float* __restrict__ bbar,
+                                                           const float* __restrict__ dptbar,
+                                                           const float* __restrict__ rbar, float* __restrict__ abar,
+                                                           double* __restrict__ gpart) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double gl = 0.0;
+    if (i < N) {
+        const uint2 rg = bounded(crange[i]);
+        const float4 t4 = tq[i];
+        const f3 ti{t4.x, t4.y, t4.z};
+        f3 cv{0.f, 0.f, 0.f}, ch{0.f, 0.f, 0.f}, sv{0.f, 0.f, 0.f}, qv{0.f, 0.f, 0.f}, qh{0.f, 0.f, 0.f};
+        for (uint32_t j = rg.x; j < rg.y; ++j) {
+            const VRec& rj = crec[j];
+            const f3 wj{rj.w[0], rj.w[1], rj.w[2]}, wej{rj.we[0], rj.we[1], rj.we[2]};
+            const float uw = one_minus_cos(ti, wj), ue = one_minus_cos(ti, wej);
+            const float fp = c.rho(uw) / mp[j], fe = c.rho(ue) / me[j];
+            const float hp = hg_dlog(c.g, uw), he = hg_dlog(c.g, ue);
+            for (int a = 0; a < 3; ++a) {
+                const float v = fe * rj.le[a] + fp * rj.lp[a], h = fe * he * rj.le[a] + fp * hp * rj.lp[a];
+                if (a == 0) { cv.x += v; ch.x += h; sv.x += rj.ls[0]; }
+                if (a == 1) { cv.y += v; ch.y += h; sv.y += rj.ls[1]; }
+                if (a == 2) { cv.z += v; ch.z += h; sv.z += rj.ls[2]; }
+            }
+            if (dir_pl) {
+                const int64_t pj = cpid[j];
+                const float u = one_minus_cos(ti, ld3(dir_pl, pj));
+                const float rpl = c.rho(u), hpl = rpl * hg_dlog(c.g, u);
+                const f3 lq = ld3(l_pl, pj);
+                qv = f3{fmaf(rpl, lq.x, qv.x), fmaf(rpl, lq.y, qv.y), fmaf(rpl, lq.z, qv.z)};
+                qh = f3{fmaf(hpl, lq.x, qh.x), fmaf(hpl, lq.y, qh.y), fmaf(hpl, lq.z, qh.z)};
+            }
+        }
+        const float us = one_minus_cos(ti, c.sun);
+        const float rho_sun = c.rho(us), hs = hg_dlog(c.g, us);
+        const float invC = 1.0f / (float)(rg.y - rg.x);
+        const f3 dagg{fmaf(rho_sun * invC, sv.x, fmaf(invC, qv.x, cv.x)),
+                      fmaf(rho_sun * invC, sv.y, fmaf(invC, qv.y, cv.y)),
+                      fmaf(rho_sun * invC, sv.z, fmaf(invC, qv.z, cv.z))};
+        const f3 bb = ld3(bbar, i);
+        abar[i] += dot3(bb, dagg);
+        const f3 db{t4.w * bb.x, t4.w * bb.y, t4.w * bb.z};
+        const float ks = rho_sun * hs * invC;
+        gl += (double)dot3(db, f3{fmaf(ks, sv.x, fmaf(invC, qh.x, ch.x)), fmaf(ks, sv.y, fmaf(invC, qh.y, ch.y)),
+                                  fmaf(ks, sv.z, fmaf(invC, qh.z, ch.z))});
+        // own direct term and continuation ratio
+        const VRec& ri = crec[i];
+        const f3 w{ri.w[0], ri.w[1], ri.w[2]}, we{ri.we[0], ri.we[1], ri.we[2]};
+        const float u_w = one_minus_cos(ti, w), u_e = one_minus_cos(ti, we);
+        const float rho = c.rho(u_w), rho_e = c.rho(u_e);
+        const float hw = hg_dlog(c.g, u_w), he = hg_dlog(c.g, u_e);
+        const float p_w = c.pdf(u_w), p_e = c.pdf(u_e);
+        const float f_env = rho_e / (p_e + c.env_pdf), f_out = rho / (p_w + c.env_pdf);
+        const f3 pb = ld3(dptbar, i);
+        f3 dd{rho_sun * hs * ri.ls[0] + f_env * he * ri.le[0] + f_out * hw * ri.lp[0],
+              rho_sun * hs * ri.ls[1] + f_env * he * ri.le[1] + f_out * hw * ri.lp[1],
+              rho_sun * hs * ri.ls[2] + f_env * he * ri.le[2] + f_out * hw * ri.lp[2]};
+        if (dir_pl) {
+            const int64_t pi = cpid[i];
+            const float u = one_minus_cos(ti, ld3(dir_pl, pi));
+            const float hpl = c.rho(u) * hg_dlog(c.g, u);
+            const f3 lq = ld3(l_pl, pi);
+            dd = f3{fmaf(hpl, lq.x, dd.x), fmaf(hpl, lq.y, dd.y), fmaf(hpl, lq.z, dd.z)};
+        }
+        gl += (double)dot3(pb, dd);
+        gl += (double)(rbar[i] * (rho / p_w) * hw);
+    }
+    const double t = block_sum_d(gl);
+    if (threadIdx.x == 0) gpart[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cpid(int64_t N, const int32_t* __restrict__ cperm,
+                                                 const int32_t* __restrict__ perm, int32_t* __restrict__ cpid) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) cpid[i] = perm[cperm[i]];
+}
+
 }  // namespace
 
 int cluster_grid_bits(int64_t N, int K) {
@@ -838,13 +1091,14 @@ hipError_t cluster_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, c
     }
     if (out && out->b) PG_TRY(launch_permute3(N, cb.cinv, r.b, out->b, 1, s));
     if (out && out->d_pt) PG_TRY(launch_permute3(N, cb.cinv, r.dpt, out->d_pt, 1, s));
-    float* x0 = r.x;
+    float* x0 = r.tape ? r.traj : r.x;   // with the tape, traj[0] = x_0 and traj[t] = y_t
     PG_TRY(launch_fill_value(r.succ, (size_t)N * 4, 0xffffffffu, s));
+    if (r.pred) PG_TRY(launch_fill_value(r.pred, (size_t)N * 4, 0xffffffffu, s));
     PG_TRY(launch_fill(x0, (size_t)N * 12, s));
     {
         ProfScope ps(s, "paths");
         PG_TRY(launch_paths(r.P, N, p->path_offsets, cb.cinv, r.alpha, r.dpt, r.r, p->l_emit, q->init, r.succ,
-                            nullptr, x0, g.flag, s));
+                            r.pred, x0, g.flag, s));
     }
     *x0_out = x0;
     return hipSuccess;
@@ -860,22 +1114,24 @@ hipError_t cluster_iterate(RenderBufs& r, const pg_params* q, float* x0, hipStre
         *final_x = x0;
         return hipSuccess;
     }
-    float* yp = r.y;      // y_1
+    float* yp = r.tape ? r.traj + (size_t)N * 3 : r.y;   // y_1
     float* yq = r.cr.y2;
     for (int t = 1; t <= r.D; ++t) {
         ProfScope ps(s, "spmv");
-        if (t == 1)
+        if (t == 1) {
             hipLaunchKernelGGL(k_cagg<false>, grid_of(N), dim3(kBlock), 0, s, N, rho, r.cl.crange, r.cr.tq, r.cr.wq,
                                r.b, x0, r.succ, yp);
-        else
+        } else {
+            if (r.tape) yq = r.traj + (size_t)t * N * 3;
             hipLaunchKernelGGL(k_cagg<true>, grid_of(N), dim3(kBlock), 0, s, N, rho, r.cl.crange, r.cr.tq, r.cr.wq,
                                r.b, yp, r.succ, yq);
+        }
         PG_TRY(hipGetLastError());
         if (t > 1) std::swap(yp, yq);
     }
     ProfScope ps(s, "shift");
-    PG_TRY(launch_shift(N, r.succ, yp, x0, s));
-    *final_x = x0;
+    PG_TRY(launch_shift(N, r.succ, yp, r.x, s));   // L_D (with the tape x_0 stays in traj[0])
+    *final_x = r.x;
     return hipSuccess;
 }
 
@@ -891,6 +1147,57 @@ hipError_t cluster_output(const pg_paths* p, const pg_params* q, RenderBufs& r, 
     }
     if (out && out->lplus) PG_TRY(launch_permute3(r.N, r.cl.cinv, cur, out->lplus, 1, s));
     return hipSuccess;
+}
+
+// ------------------------------------------------ reverse-mode launchers ---
+
+hipError_t launch_cluster_cpid(int64_t N, const RenderBufs& r, int32_t* cpid, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cpid, grid_of(N), dim3(kBlock), 0, s, N, r.cl.cperm, r.g.perm, cpid);
+    return hipGetLastError();
+}
+
+hipError_t launch_cluster_out_adjoint(const pg_paths& P, const Consts& c, const RenderBufs& r, const float* gimg,
+                                      float* abar, float* dptbar, float* rbar, float* lam, double* gpart,
+                                      int64_t nblocks, hipStream_t s) {
+    const float* xD = r.D == 0 ? r.traj : r.x;   // L_D (x_0 itself when there is no iteration)
+    hipLaunchKernelGGL(k_cout_adjoint, dim3((unsigned)nblocks), dim3(kBlock), 0, s, P, c, r.cl.cinv, r.cl.crange,
+                       r.cr.tq, r.cr.wq, xD, r.dpt, r.r, gimg, abar, dptbar, rbar, lam, gpart);
+    return hipGetLastError();
+}
+
+// Reverse of iteration t: rows (adjoint of y_t, zbar), then columns (lam_{t-1}).
+hipError_t launch_cluster_reverse_step(const RenderBufs& r, const pg_params* q, int t, const float* lam,
+                                       float* lam_prev, float* abar, float* bbar, float* zbar, double* gpart,
+                                       hipStream_t s) {
+    const int64_t N = r.N;
+    if (N == 0) return hipSuccess;
+    const HG rho = HG::make(q->g);
+    const float* x = r.traj + (size_t)(t - 1) * N * 3;   // x_0, or y_{t-1} to be gathered through succ
+    {
+        ProfScope ps(s, "rev_rows");
+        if (t == 1)
+            hipLaunchKernelGGL(k_crev_rows<false>, grid_of(N), dim3(kBlock), 0, s, N, rho, q->g, r.cl.crange,
+                               r.cr.tq, r.cr.wq, x, r.succ, lam, r.pred, abar, bbar, zbar, gpart);
+        else
+            hipLaunchKernelGGL(k_crev_rows<true>, grid_of(N), dim3(kBlock), 0, s, N, rho, q->g, r.cl.crange,
+                               r.cr.tq, r.cr.wq, x, r.succ, lam, r.pred, abar, bbar, zbar, gpart);
+        PG_TRY(hipGetLastError());
+    }
+    ProfScope ps(s, "rev_cols");
+    hipLaunchKernelGGL(k_crev_cols, grid_of(N), dim3(kBlock), 0, s, N, rho, r.cl.crange, r.cr.tq, r.cr.wq, zbar,
+                       lam_prev);
+    return hipGetLastError();
+}
+
+hipError_t launch_cluster_edges_adjoint(const pg_paths& P, const Consts& c, const RenderBufs& r, const int32_t* cpid,
+                                        const float* bbar, const float* dptbar, const float* rbar, float* abar,
+                                        double* gpart, hipStream_t s) {
+    const int64_t N = r.N;
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cedges_adjoint, grid_of(N), dim3(kBlock), 0, s, N, c, r.cl.crange, r.cr.crec, r.cr.tq,
+                       r.cr.mp, r.cr.me, cpid, P.dir_pl, P.l_pl, bbar, dptbar, rbar, abar, gpart);
+    return hipGetLastError();
 }
 
 }  // namespace pg

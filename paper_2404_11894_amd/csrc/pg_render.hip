@@ -28,6 +28,10 @@ void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params*
         r.y = cv.take<float>(3 * N);
         carve_clusters(cv, r.cl, N, q->k);
         carve_cluster_render(cv, r.cr, N);
+        if (r.tape) {   // x_0 and y_1..y_D, and the predecessors
+            r.pred = cv.take<int32_t>(N);
+            r.traj = cv.take<float>((int64_t)(r.D + 1) * 3 * N);
+        }
         return;
     }
     const int64_t E = ell_size(N, r.K);   // sliced-ELL storage, padded to whole slices

@@ -142,12 +142,12 @@ def test_cluster_flag_validation():
     assert rc == pg.PG_ERR_ARG and "cluster_key" in msg
     s.cluster_key = 0x1000
     assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == 0
-    for flags, sched in ((pg.PG_FLAG_CLUSTERS | pg.PG_FLAG_TAPE, 0), (pg.PG_FLAG_CLUSTERS, pg.PG_SCHED_SHIFTED)):
-        qq = pg.params(k=8, D=4, flags=flags, schedule=sched)
-        rc, _ = status(L.pg_render_workspace_size, ctypes.byref(s), ctypes.byref(qq), ctypes.byref(nb))
-        assert rc == pg.PG_ERR_UNSUPPORTED
-    rc, _ = status(L.pg_backward_workspace_size, ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb))
+    qq = pg.params(k=8, D=4, flags=pg.PG_FLAG_CLUSTERS, schedule=pg.PG_SCHED_SHIFTED)
+    rc, _ = status(L.pg_render_workspace_size, ctypes.byref(s), ctypes.byref(qq), ctypes.byref(nb))
     assert rc == pg.PG_ERR_UNSUPPORTED
+    qt = pg.params(k=8, D=4, flags=pg.PG_FLAG_CLUSTERS | pg.PG_FLAG_TAPE)
+    assert L.pg_render_workspace_size(ctypes.byref(s), ctypes.byref(qt), ctypes.byref(nb)) == 0
+    assert L.pg_backward_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == 0
     assert L.pg_clusters_workspace_size(ctypes.byref(s), 8, 0, ctypes.byref(nb)) == 0 and nb.value > 0
     s.cluster_key = None
     rc, _ = status(L.pg_clusters, ctypes.byref(s), 8, 0, ctypes.c_void_p(0x4000), ctypes.c_void_p(0x10000),

@@ -170,3 +170,53 @@ def test_cluster_empty_and_errors():
         pg.Renderer(paths, q)(graph=g)
     torch.cuda.synchronize()
     assert (g["col"] == -7).all()
+
+
+def grad_close(got, ref, what):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    tol = 1e-4 * np.abs(ref) + 1e-4 * np.abs(ref).max()
+    err = np.abs(got - ref)
+    assert np.all(err <= tol), f"{what}: max err {err.max():.3e} (max |ref| {np.abs(ref).max():.3e})"
+
+
+@pytest.mark.parametrize("init,fg,D,extra", [("pt", 0, 6, 0), ("zero", 0, 5, 0), ("pt", 1, 4, 0), ("pt", 0, 0, 0),
+                                             ("pt", 0, 5, 2)])
+def test_cluster_backward_matches_oracle(init, fg, D, extra):
+    cfg = replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 32, 32, 2), extra_samples=extra)
+    sc = keyed(scenegen.generate(cfg), seed=3)
+    print(f"cluster adjoint init={init} fg={fg} D={D} extra={extra} N={sc.n_vertices}", flush=True)
+    rng = np.random.default_rng(5)
+    grid = rng.uniform(0.6, 0.95, size=(8, 8, 8)).astype(np.float32)
+    op = oracle.params(k=8, D=D, g=0.5, init=init, final_gather=fg, neighbours="clusters")
+    img = oracle.render(sc, op, alpha=oracle.albedo_from_grid(sc.pos, grid))
+    target = scenegen.target_image(img.shape, float(img.mean()), seed=4).astype(np.float64)
+    gimg = 2.0 * (img - target)
+    ref = oracle.backward(sc, op, gimg, grid=grid)
+    paths = pg.DevicePaths(sc, albedo_grid=grid)
+    q = pg.params(k=8, D=D, g=0.5, init=init, final_gather=fg, flags=pg.PG_FLAG_CHECK | pg.PG_FLAG_CLUSTERS)
+    out = pg.pg_backward(paths, q, torch.from_numpy(gimg.astype(np.float32)), grad_albedo=True)
+    torch.cuda.synchronize()
+    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid")
+    grad_close(out["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo")
+    grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
+
+
+def test_cluster_autograd_with_tape():
+    sc = keyed(crop("tiny", 24, 24, 2), seed=5)
+    rng = np.random.default_rng(6)
+    grid = rng.uniform(0.6, 0.95, size=(8, 8, 8)).astype(np.float32)
+    paths = pg.DevicePaths(sc, albedo_grid=grid)
+    q = pg.params(k=8, D=5, g=0.5, flags=pg.PG_FLAG_CLUSTERS)
+    gt = torch.tensor(grid, device="cuda", requires_grad=True)
+    g = torch.tensor(0.5, device="cuda", requires_grad=True)
+    img = pg.render_differentiable(paths, q, gt, g)
+    loss = (img ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    op = oracle.params(k=8, D=5, g=0.5, neighbours="clusters")
+    ref_img = oracle.render(sc, op, alpha=oracle.albedo_from_grid(sc.pos, grid))
+    ref = oracle.backward(sc, op, 2.0 * ref_img, grid=grid)
+    assert_within(img.detach().cpu().numpy(), ref_img, PIX_REL, PIX_ABS, "image")
+    grad_close(gt.grad.cpu().numpy(), ref["grad_grid"], "grad grid")
+    grad_close([g.grad.item()], [ref["grad_g"]], "grad g")
