@@ -164,7 +164,8 @@ def time_clusters(pg, torch, sc, w, steps, warmup, knn_ms):
     """The paper's own neighbour relation on the same paths: clusters of
     expected size k around centres drawn by seeded uniform keys (seed 7).
     One step = pg_render with PG_FLAG_CLUSTERS.  Counts E_c D, E_c = the sum
-    over clusters of size^2 (every member aggregates every member)."""
+    over clusters of size^2 (every member aggregates every member); also one
+    forward + reverse step with the albedo from the 64^3 grid (2 E_c D)."""
     import scenegen
     dev = torch.device("cuda:0")
     sck = dataclasses.replace(sc, cluster_key=scenegen.cluster_keys(sc.n_vertices, 7))
@@ -191,13 +192,37 @@ def time_clusters(pg, torch, sc, w, steps, warmup, knn_ms):
     cnt, tot, _ = prof["spmv"]
     avg_s = tot / cnt / 1e3
     N = sc.n_vertices
+    # forward + reverse mode with the cluster relation (albedo from the 64^3 grid, as fwd_adjoint)
+    del render
+    torch.cuda.empty_cache()
+    paths.set_albedo_grid(scenegen.albedo_grid(64, 0.95, 0.999, seed=2))
+    qt = pg.params(k=w.k, D=w.D, g=w.g, flags=pg.PG_FLAG_CLUSTERS | pg.PG_FLAG_TAPE)
+    rt = pg.Renderer(paths, qt)
+    target = torch.from_numpy(scenegen.target_image((sc.height, sc.width, 3), 0.3, seed=4)).to(dev)
+
+    def adj_step():
+        rt(image)
+        return pg.pg_backward(paths, qt, 2.0 * (image - target), workspace=(rt.ws, rt.ws_bytes))
+
+    adj_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_adj = max(2, steps // 2)
+    for _ in range(n_adj):
+        g_out = adj_step()
+    torch.cuda.synchronize()
+    adj_ms = (time.perf_counter() - t0) * 1e3 / n_adj
+    adj_ok = bool(torch.isfinite(g_out["grad_grid"]).all().item())
+    del rt
     # per row: (t, albedo) 16, range 8, b 12, y 12; each member's (w, 1/M+) 16 once, and its x: 12 read
     # (first iteration) or successor id 4 + gathered y 12 (the others, propagation folded in)
     ab = N * (76 + 80 * (w.D - 1)) / w.D
     flops = 22 * E  # per edge: 1 - cos 9, HG 7 (one rsqrt), 1/M+ 1, accumulate 6 (FMA = 2)
-    del render, paths
+    del paths
     torch.cuda.empty_cache()
     return {"value": round(E * w.D / (ms / 1e3) / 1e9, 2), "unit": "Gedge-updates/s", "ms_per_step": round(ms, 3),
+            "fwd_adjoint": {"value": round(2 * E * w.D / (adj_ms / 1e3) / 1e9, 2), "ms_per_step": round(adj_ms, 3),
+                            "finite": adj_ok},
             "vs_knn_render": round(knn_ms / ms, 3) if knn_ms == knn_ms else None, "E": E, "clusters": int(nz.numel()),
             "mean_size": round(N / max(1, int(nz.numel())), 2), "max_size": int(nz.max().item()),
             "phases_ms": phases,

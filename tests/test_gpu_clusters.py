@@ -180,10 +180,12 @@ def grad_close(got, ref, what):
     assert np.all(err <= tol), f"{what}: max err {err.max():.3e} (max |ref| {np.abs(ref).max():.3e})"
 
 
-@pytest.mark.parametrize("init,fg,D,extra", [("pt", 0, 6, 0), ("zero", 0, 5, 0), ("pt", 1, 4, 0), ("pt", 0, 0, 0),
-                                             ("pt", 0, 5, 2)])
-def test_cluster_backward_matches_oracle(init, fg, D, extra):
-    cfg = replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 32, 32, 2), extra_samples=extra)
+@pytest.mark.parametrize("init,fg,D,extra,point", [("pt", 0, 6, 0, False), ("zero", 0, 5, 0, False),
+                                                   ("pt", 1, 4, 0, False), ("pt", 0, 0, 0, False),
+                                                   ("pt", 0, 5, 2, False), ("zero", 0, 4, 0, True)])
+def test_cluster_backward_matches_oracle(init, fg, D, extra, point):
+    cfg = replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 32, 32, 2), extra_samples=extra,
+                  pl_I=(0.4, 0.3, 0.2) if point else (0.0, 0.0, 0.0))
     sc = keyed(scenegen.generate(cfg), seed=3)
     print(f"cluster adjoint init={init} fg={fg} D={D} extra={extra} N={sc.n_vertices}", flush=True)
     rng = np.random.default_rng(5)
