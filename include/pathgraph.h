@@ -61,10 +61,10 @@ typedef int32_t pg_status;
 #define PG_FLAG_EXACT_KNN 4u  /* every neighbour query takes the exact (d^2, id) search instead
                                  of the packed-key fast path: the same neighbours, slower; for
                                  validating the fallback the fast path hands rare queries to */
-#define PG_FLAG_CLUSTERS 8u  /* pg_render: neighbours are the disjoint clusters of pg_clusters
-                                (k = expected cluster size) instead of the k nearest.  Two-pass
-                                schedule only; not with PG_FLAG_TAPE, pg_backward or batching.
-                                The call synchronises the stream once to report device checks. */
+#define PG_FLAG_CLUSTERS 8u  /* pg_render / pg_backward: neighbours are the disjoint clusters of
+                                pg_clusters (k = expected cluster size) instead of the k nearest.
+                                Two-pass schedule only; not with batching.  The call synchronises
+                                the stream once to report device checks. */
 
 #define PG_SCHED_TWO_PASS 1  /* aggregate over spatially sorted rows, then shift along paths */
 #define PG_SCHED_SHIFTED  2  /* rows pre-arranged in predecessor order: one pass per iteration */
@@ -338,7 +338,8 @@ pg_status pg_render(const pg_paths* paths, const pg_params* params, float* image
  * call with the same paths and params (PG_FLAG_TAPE set) and must not have
  * been used since; otherwise the forward pass is recomputed first.
  * grad_grid is [R][R][R]; grad_albedo ([N], per vertex) may be NULL;
- * grad_g is one float. */
+ * grad_g is one float.  With PG_FLAG_CLUSTERS the tape holds x_0 and y_1..y_D
+ * and the transposed product runs over each sample's own cluster. */
 pg_status pg_backward_workspace_size(const pg_paths* paths, const pg_params* params, size_t* bytes);
 pg_status pg_backward(const pg_paths* paths, const pg_params* params, const float* grad_image,
                       float* grad_grid, float* grad_albedo, float* grad_g, void* ws, size_t ws_bytes,
