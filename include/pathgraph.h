@@ -63,8 +63,9 @@ typedef int32_t pg_status;
                                  validating the fallback the fast path hands rare queries to */
 #define PG_FLAG_CLUSTERS 8u  /* pg_render / pg_backward: neighbours are the disjoint clusters of
                                 pg_clusters (k = expected cluster size) instead of the k nearest.
-                                Two-pass schedule only; not with batching.  The call synchronises
-                                the stream once to report device checks. */
+                                Two-pass schedule only.  pg_render, pg_backward and
+                                pg_render_batched synchronise once to report device checks (a
+                                pg_batch plan does not report them). */
 
 #define PG_SCHED_TWO_PASS 1  /* aggregate over spatially sorted rows, then shift along paths */
 #define PG_SCHED_SHIFTED  2  /* rows pre-arranged in predecessor order: one pass per iteration */

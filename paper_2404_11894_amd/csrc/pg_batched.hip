@@ -1,7 +1,8 @@
 // pg_batched.hip -- many independent scenes per launch.
 //
 // Each scene gets its own slice of the workspace (the same buffers as a
-// single render).  The one-time steps (grid, kNN, weights, path pass, pixels)
+// single render).  A scene with the cluster relation runs its setup and its
+// own iterations on its setup stream, beside the batched loop of the others.  The one-time steps (grid, kNN, weights, path pass, pixels)
 // run per scene, spread over a few streams; the D iterations -- the hot loop
 // -- run as ONE spmv launch and ONE shift launch for all scenes per
 // iteration: a block finds its scene in a small descriptor table and leaves
@@ -104,8 +105,8 @@ static void carve_batch(Carver& cv, BatchLayout& L, int n, const pg_paths* paths
     int64_t blk = 0;
     for (int s = 0; s < n; ++s) {
         const RenderBufs& r = L.r[s];
+        if (r.N == 0 || r.clusters) continue;   // cluster scenes iterate on their own stream
         if (r.D > L.Dmax) L.Dmax = r.D;
-        if (r.N == 0) continue;
         SceneDesc d{r.col, r.w, r.b, r.alpha, r.succ, r.x, r.y, r.N, blk, r.K, r.D};
         L.host_tables.push_back(d);
         blk += div_up(r.N, kBlock);
@@ -121,8 +122,10 @@ static pg_status validate_batch(int n, const pg_paths* paths, const pg_params* p
         pg_status st;
         if ((st = validate_paths(&paths[s], true)) || (st = validate_params(&params[s])))
             return fail(st, "scene %d: %s", s, g_error.c_str());
-        if (params[s].flags & PG_FLAG_CLUSTERS)
-            return fail(PG_ERR_UNSUPPORTED, "scene %d: batching does not support PG_FLAG_CLUSTERS", s);
+        pg_params qs = params[s];
+        qs.schedule = PG_SCHED_TWO_PASS;
+        qs.flags &= ~PG_FLAG_TAPE;
+        if ((st = validate_clusters(&paths[s], &qs))) return fail(st, "scene %d: %s", s, g_error.c_str());
     }
     return PG_OK;
 }
@@ -176,6 +179,13 @@ static hipError_t run_batch(const pg_paths* paths, BatchLayout& L, float* const*
     }
     for (int s = 0; s < L.n; ++s) {
         float* x0 = nullptr;
+        if (L.r[s].clusters) {   // the cluster relation: setup and its own iterations on the scene's stream
+            float* xD = nullptr;
+            if ((e = cluster_setup(&paths[s], &L.q[s], L.r[s], nullptr, streams[which[s]], &x0)) != hipSuccess)
+                return e;
+            if ((e = cluster_iterate(L.r[s], &L.q[s], x0, streams[which[s]], &xD)) != hipSuccess) return e;
+            continue;
+        }
         if ((e = render_setup(&paths[s], &L.q[s], L.r[s], nullptr, streams[which[s]], &x0)) != hipSuccess)
             return e;
     }
@@ -191,10 +201,11 @@ static hipError_t run_batch(const pg_paths* paths, BatchLayout& L, float* const*
         for (int k = 1; k < ns; ++k)
             if ((e = hipStreamWaitEvent(streams[k], ev[0], 0)) != hipSuccess) return e;
     }
-    for (int s = 0; s < L.n; ++s)
-        if ((e = render_output(&paths[s], &L.q[s], L.r[s], nullptr, images[s], L.r[s].x, streams[which[s]])) !=
-            hipSuccess)
-            return e;
+    for (int s = 0; s < L.n; ++s) {
+        e = L.r[s].clusters ? cluster_output(&paths[s], &L.q[s], L.r[s], nullptr, images[s], L.r[s].x, streams[which[s]])
+                            : render_output(&paths[s], &L.q[s], L.r[s], nullptr, images[s], L.r[s].x, streams[which[s]]);
+        if (e != hipSuccess) return e;
+    }
     if (ns > 1) {
         for (int k = 1; k < ns; ++k) {
             if ((e = hipEventRecord(ev[k], streams[k])) != hipSuccess) return e;
@@ -350,7 +361,7 @@ pg_status pg_render_batched(int32_t n_scenes, const pg_paths* paths, const pg_pa
     if (e != hipSuccess) return hip_fail(e, "pg_render_batched");
     uint32_t fl = 0;
     for (int s = 0; s < n_scenes; ++s) fl |= params[s].flags;
-    if (fl & PG_FLAG_CHECK) {
+    if (fl & (PG_FLAG_CHECK | PG_FLAG_CLUSTERS)) {   // the cluster relation always reports its checks
         for (int s = 0; s < n_scenes; ++s) {
             pg_status fs = finish(s0, &params[s], L.r[s].g.flag, PG_FLAG_CHECK);
             if (fs) return fail(fs, "scene %d: %s", s, g_error.c_str());

@@ -51,6 +51,32 @@ def test_batched_equals_per_scene_and_oracle():
 
 
 @pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_mixes_cluster_and_knn_scenes(use_graph):
+    scenes, params, oparams = small_batch()
+    for s in (0, 2, 6):   # these use the cluster relation, the others the k nearest
+        scenes[s] = replace(scenes[s], cluster_key=scenegen.cluster_keys(scenes[s].n_vertices, 30 + s))
+        params[s] = pg.params(k=params[s].k, D=params[s].D, g=params[s].g,
+                              flags=pg.PG_FLAG_CHECK | pg.PG_FLAG_CLUSTERS)
+        oparams[s] = dict(oparams[s], neighbours="clusters")
+    paths = [pg.DevicePaths(sc) for sc in scenes]
+    imgs = [im.clone() for im in pg.pg_render_batched(paths, params)]
+    torch.cuda.synchronize()
+    for s, (sc, p, op) in enumerate(zip(scenes, params, oparams)):
+        single = pg.pg_render(paths[s], p)
+        torch.cuda.synchronize()
+        got = imgs[s].cpu().numpy()
+        assert np.array_equal(got, single.cpu().numpy()), f"scene {s}"
+        assert_within(got, oracle.render(sc, op), PIX_REL, PIX_ABS, f"scene {s} vs oracle")
+    plan = pg.Batch(paths, [pg.params(k=p.k, D=p.D, g=p.g, flags=p.flags & pg.PG_FLAG_CLUSTERS) for p in params],
+                    use_graph=use_graph)
+    for rep in range(3):
+        out = plan()
+        torch.cuda.synchronize()
+        for s in range(len(scenes)):
+            assert torch.equal(out[s], imgs[s]), (rep, s)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
 def test_batch_plan_replays(use_graph):
     scenes, params, _ = small_batch()
     paths = [pg.DevicePaths(s) for s in scenes]
