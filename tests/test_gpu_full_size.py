@@ -6,8 +6,15 @@ The oracle cannot run the whole graph at this size, so the checks are sampled
 rows it computes one by one (neighbour lists bit for bit, weights, direct
 terms), single-step propagation on sampled vertices, and properties that hold
 at any size (albedo 0 leaves the camera term; one neighbour reproduces path
-tracing, which the oracle computes in full).
+tracing, which the oracle computes in full).  The cluster relation is checked
+the same way: its centres by properties of the construction (a seeded vertex
+stays a centre unless it coincides with a seeded vertex of lower id, every
+centre is its own centre, a split never moves a vertex out of its nearest
+seeded centre's cluster), its CSR in full, sampled rows against the oracle's
+weights, and column sums of 1 when g equals g_s.
 """
+from dataclasses import replace
+
 import numpy as np
 import pytest
 import torch
@@ -98,3 +105,111 @@ def test_mid_single_neighbour_is_path_tracing(mid):
     torch.cuda.empty_cache()
     ref = oracle.render(mid, oracle.params(k=1, D=W.D, g=W.g))
     assert_within(img, ref, PIX_REL, PIX_ABS, "k=1")
+
+
+@pytest.fixture(scope="module")
+def mid_clusters(mid):
+    sc = replace(mid, cluster_key=scenegen.cluster_keys(mid.n_vertices, 7))
+    paths = pg.DevicePaths(sc)
+    centre = pg.pg_clusters(paths, W.k)
+    q = pg.params(k=W.k, D=W.D, g=W.g, flags=pg.PG_FLAG_CHECK | pg.PG_FLAG_CLUSTERS)
+    img, gr = pg.pg_render(paths, q, graph=True)
+    torch.cuda.synchronize()
+    out = {n: t.cpu().numpy() for n, t in gr.items()}
+    centre = centre.cpu().numpy()
+    img = img.cpu().numpy()
+    del paths, gr
+    torch.cuda.empty_cache()
+    print(f"mid clusters: {np.unique(centre).size} clusters, E={out['col'].size}", flush=True)
+    return sc, centre, img, out
+
+
+def nearest_seeded(qs, seeds, q, v):
+    """Lexicographically smallest (d^2, id) among the seeded centres, for each vertex in v."""
+    out = np.empty(len(v), np.int64)
+    for a, i in enumerate(v):
+        d2 = ((qs - q[i]) ** 2).sum(1)
+        out[a] = seeds[d2 == d2.min()].min()
+    return out
+
+
+def test_mid_cluster_centres_properties(mid_clusters):
+    sc, centre, _, _ = mid_clusters
+    N, K = sc.n_vertices, W.k
+    key = sc.cluster_key.astype(np.uint64)
+    seeds = np.union1d(np.flatnonzero(key < (1 << 32) // K), [int(np.argmin(key))])
+    assert centre.min() >= 0 and centre.max() < N
+    assert np.array_equal(centre[centre], centre)                  # a centre is its own centre
+    q, _ = oracle.quantize(sc.pos)
+    q = q.astype(np.int64)
+    # a seeded vertex is its own centre unless a seeded vertex of lower id sits
+    # at the same quantised position (distance 0, smaller id): then it joins that one
+    qp = (q[:, 0] << 40) | (q[:, 1] << 20) | q[:, 2]
+    o = np.lexsort((seeds, qp[seeds]))
+    grp = qp[seeds][o]
+    lead = np.r_[True, grp[1:] != grp[:-1]]
+    head = np.maximum.accumulate(np.where(lead, np.arange(len(o)), 0))
+    assert np.array_equal(centre[seeds[o]], seeds[o][head])
+    qs = q[seeds]
+    rng = np.random.default_rng(8)
+    v = rng.choice(N, 96, replace=False)
+    # splits only divide a cluster: a vertex and its final centre share the nearest seeded centre
+    assert np.array_equal(nearest_seeded(qs, seeds, q, v), nearest_seeded(qs, seeds, q, centre[v]))
+
+
+def test_mid_cluster_rows_match_oracle(mid_clusters):
+    sc, centre, img, gr = mid_clusters
+    N = sc.n_vertices
+    assert np.isfinite(img).all() and np.isfinite(gr["lplus"]).all()
+    size = np.bincount(centre, minlength=N).astype(np.int64)
+    rp = np.zeros(N + 1, np.int64)
+    rp[1:] = np.cumsum(size[centre])
+    assert np.array_equal(gr["row_ptr"], rp)
+    order = np.argsort(centre, kind="stable")                    # members of each cluster in ascending id
+    start = np.zeros(N + 1, np.int64)
+    start[1:] = np.cumsum(size)
+    rng = np.random.default_rng(9)
+    rows = np.sort(rng.choice(N, 4096, replace=False))
+    members = {int(i): order[start[centre[i]]:start[centre[i] + 1]] for i in rows}
+    for i in rows:
+        assert np.array_equal(gr["col"][rp[i]:rp[i + 1]], members[int(i)]), i
+    # weights and direct terms of sampled receivers: the oracle's per-receiver
+    # aggregation over the receiver's own cluster, grouped by cluster size
+    sub = rows[:: len(rows) // 64]
+    ln = rp[sub + 1] - rp[sub]
+    p = oracle.params(k=W.k, D=W.D, g=W.g)
+    for L in np.unique(ln):
+        r = sub[ln == L]
+        e = oracle.edges(sc, p, np.stack([members[int(i)] for i in r]), rows=r)
+        for name in ("w_ind", "w_ph", "w_env"):
+            got = np.stack([gr[name][rp[i]:rp[i + 1]] for i in r])
+            assert_within(got, e[name], W_REL, W_ABS, f"{name} size {L}")
+        assert_within(gr["b"][r], sc.albedo[r, None].astype(np.float64) * e["d_agg"], W_REL, W_ABS, "b")
+        assert_within(gr["d_pt"][r], e["d_pt"], W_REL, W_ABS, "d_pt")
+    # g = g_s: every sample's weights over its cluster's receivers sum to one
+    colsum = np.bincount(gr["col"], weights=gr["w_ind"].astype(np.float64), minlength=N)
+    assert np.abs(colsum - 1.0).max() < 2e-5
+
+
+def test_mid_cluster_one_iteration_from_zero(mid_clusters):
+    # D = 1 from zero: L_1(v) = b(succ v), the propagation step the cluster
+    # relation folds into its aggregation, on sampled vertices
+    sc, centre, _, _ = mid_clusters
+    paths = pg.DevicePaths(sc)
+    q = pg.params(k=W.k, D=1, g=W.g, init="zero", flags=pg.PG_FLAG_CHECK | pg.PG_FLAG_CLUSTERS)
+    _, gr = pg.pg_render(paths, q, graph=True)
+    lplus = gr["lplus"].cpu().numpy()
+    del paths, gr
+    torch.cuda.empty_cache()
+    off = sc.path_offsets
+    last = np.zeros(sc.n_vertices, bool)
+    last[off[1:][np.diff(off) > 0] - 1] = True
+    rng = np.random.default_rng(10)
+    v = np.sort(rng.choice(np.flatnonzero(~last), 24, replace=False))
+    p = oracle.params(k=W.k, D=1, g=W.g)
+    for a in v:
+        s = a + 1
+        mem = np.flatnonzero(centre == centre[s])
+        e = oracle.edges(sc, p, mem[None, :], rows=np.array([s]))
+        assert_within(lplus[a:a + 1], sc.albedo[s] * e["d_agg"], W_REL, W_ABS, f"L_1 at {a}")
+    assert not lplus[np.flatnonzero(last)[:1000]].any()
