@@ -432,16 +432,27 @@ __device__ __forceinline__ uint64_t make_key(uint64_t d2, uint32_t oid, const Ke
     return ((d2 < f.sat ? d2 : f.sat) << f.idb) | (uint64_t)oid;
 }
 
+// Insert c into the ascending list if it beats the last key, as a merge: slot
+// p keeps its key if c is not below it, takes c if c falls between slots p-1
+// and p, and the key of slot p-1 otherwise.  The comparisons against c are
+// independent of each other (a bubble pass would chain them), and each slot
+// costs one 64-bit compare and two selects.
 template <int KM>
 __device__ __forceinline__ void key_insert(uint64_t (&k)[KM], uint64_t c) {
     if (c < k[KM - 1]) {
-        k[KM - 1] = c;
+        bool lt[KM];
+        uint64_t v[KM];
 #pragma unroll
-        for (int p = KM - 1; p > 0; --p) {
-            const uint64_t a = k[p - 1], b = k[p];
-            k[p - 1] = b < a ? b : a;
-            k[p] = b < a ? a : b;
+        for (int p = 0; p < KM; ++p) {
+            lt[p] = c < k[p];
+            // an empty asm hides that v[p] equals k[p]: the selects below then
+            // reuse lt[] instead of being rebuilt as min/max with compares of their own
+            v[p] = k[p];
+            asm("" : "+v"(v[p]));
         }
+#pragma unroll
+        for (int p = KM - 1; p > 0; --p) k[p] = lt[p] ? (lt[p - 1] ? v[p - 1] : c) : v[p];
+        k[0] = lt[0] ? c : v[0];
     }
 }
 
