@@ -507,9 +507,10 @@ __device__ __forceinline__ void key_shell_search(int64_t s, int shift, int32_t q
 }
 
 // WPE: the minimum waves per SIMD the compiler must fit the search in.  For
-// the short key lists (k = 8, 16) a bound of 6 or 8 fits it in 64-70
-// registers without spilling, 7-8 resident waves instead of 4, which hides
-// more of the candidate loads' latency; longer lists take no bound (1).
+// the short key lists (k = 8, 16) a bound of 6 fits it in 64-68 registers
+// without spilling, 7-8 resident waves instead of 4, which hides more of the
+// candidate loads' latency (at k = 16 a bound of 8 squeezed it into 64
+// registers and ran 3% slower); longer lists take no bound (1).
 template <int KM, int WPE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_knn(int64_t N, int K, int shift, const uint64_t* __restrict__ qs,
                                                 const int32_t* __restrict__ perm, const int32_t* __restrict__ inv,
@@ -598,7 +599,7 @@ hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, cons
     const KeyFmt f = key_fmt(N);
     auto go = [&](auto km) {
         constexpr int KM = decltype(km)::value;
-        constexpr int WPE = KM == 15 ? 8 : (KM <= 16 ? 6 : 1);
+        constexpr int WPE = KM <= 16 ? 6 : 1;
         if (exact_only)
             hipLaunchKernelGGL(k_redo_all, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, redo, nredo);
         else
