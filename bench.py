@@ -88,7 +88,7 @@ def profile_entries(pg):
 
 def cpu_baseline(workload, k, D, g):
     """The FP64 oracle, single-threaded, on a centred 64x64-pixel crop of the
-    same workload (all 4 samples per pixel): the whole pipeline."""
+    same workload (all its samples per pixel): the whole pipeline."""
     import oracle
     import scenegen
     sc = scenegen.generate(scenegen.crop_of(workload.scene, 64, 64))
@@ -99,7 +99,7 @@ def cpu_baseline(workload, k, D, g):
     dt = time.perf_counter() - t0
     E = sc.n_vertices * K
     return {"value": E * D / dt / 1e9, "unit": "Gedge-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"centred 64x64-pixel crop of the same image, 4 spp: N={sc.n_vertices}, E={E}, D={D}; "
+            "sample": f"centred 64x64-pixel crop of the same image, {sc.spp} spp: N={sc.n_vertices}, E={E}, D={D}; "
                       f"whole pipeline (kNN, weights, {D} iterations, pixels) in {dt:.2f} s",
             "host": host_cpu()}
 

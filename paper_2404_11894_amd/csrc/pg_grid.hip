@@ -507,10 +507,11 @@ __device__ __forceinline__ void key_shell_search(int64_t s, int shift, int32_t q
 }
 
 // WPE: the minimum waves per SIMD the compiler must fit the search in.  For
-// the short key lists (k = 8, 16) a bound of 6 fits it in 64-68 registers
-// without spilling, 7-8 resident waves instead of 4, which hides more of the
-// candidate loads' latency (at k = 16 a bound of 8 squeezed it into 64
-// registers and ran 3% slower); longer lists take no bound (1).
+// lists of up to 16 keys a bound of 6 or 8 (whichever compiles without
+// spills: 8 for 7 and 9-14 keys, 6 for 8, 15 and 16) fits it in 55-68
+// registers, 7-8 resident waves instead of 4, which hides more of the
+// candidate loads' latency (at 15 keys the bound of 6 ran 3% faster than 8);
+// longer lists take no bound (1).
 template <int KM, int WPE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_knn(int64_t N, int K, int shift, const uint64_t* __restrict__ qs,
                                                 const int32_t* __restrict__ perm, const int32_t* __restrict__ inv,
@@ -599,7 +600,7 @@ hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, cons
     const KeyFmt f = key_fmt(N);
     auto go = [&](auto km) {
         constexpr int KM = decltype(km)::value;
-        constexpr int WPE = KM <= 16 ? 6 : 1;
+        constexpr int WPE = KM == 8 ? 6 : (KM <= 14 ? 8 : (KM <= 16 ? 6 : 1));
         if (exact_only)
             hipLaunchKernelGGL(k_redo_all, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, redo, nredo);
         else
@@ -610,12 +611,24 @@ hipError_t launch_knn(int64_t N, int K, int shift, const uint64_t* qsorted, cons
                            cell_range, col_sorted, col_canon, row_ptr, (const uint32_t*)redo,
                            (const uint32_t*)nredo);
     };
-    if (m == 7) go(std::integral_constant<int, 7>{});          // k = 8 and 16: no sentinel slot
-    else if (m <= 8) go(std::integral_constant<int, 8>{});
-    else if (m == 15) go(std::integral_constant<int, 15>{});
-    else if (m <= 16) go(std::integral_constant<int, 16>{});
-    else if (m <= 32) go(std::integral_constant<int, 32>{});
-    else go(std::integral_constant<int, 64>{});
+    // k = 8..17 get a list of exactly K-1 keys: a sentinel slot costs its
+    // compare and selects in every insertion
+    switch (m) {
+        case 7: go(std::integral_constant<int, 7>{}); break;
+        case 8: go(std::integral_constant<int, 8>{}); break;
+        case 9: go(std::integral_constant<int, 9>{}); break;
+        case 10: go(std::integral_constant<int, 10>{}); break;
+        case 11: go(std::integral_constant<int, 11>{}); break;
+        case 12: go(std::integral_constant<int, 12>{}); break;
+        case 13: go(std::integral_constant<int, 13>{}); break;
+        case 14: go(std::integral_constant<int, 14>{}); break;
+        case 15: go(std::integral_constant<int, 15>{}); break;
+        case 16: go(std::integral_constant<int, 16>{}); break;
+        default:
+            if (m < 7) go(std::integral_constant<int, 8>{});
+            else if (m <= 32) go(std::integral_constant<int, 32>{});
+            else go(std::integral_constant<int, 64>{});
+    }
     return hipGetLastError();
 }
 

@@ -11,7 +11,8 @@ the same way: its centres by properties of the construction (a seeded vertex
 stays a centre unless it coincides with a seeded vertex of lower id, every
 centre is its own centre, a split never moves a vertex out of its nearest
 seeded centre's cluster), its CSR in full, sampled rows against the oracle's
-weights, and column sums of 1 when g equals g_s.
+weights, and column sums of 1 when g equals g_s.  The large workload (512^3,
+1024 x 1024 px, depth 128, D 128) gets sampled rows and one propagation step.
 """
 from dataclasses import replace
 
@@ -212,4 +213,51 @@ def test_mid_cluster_one_iteration_from_zero(mid_clusters):
         mem = np.flatnonzero(centre == centre[s])
         e = oracle.edges(sc, p, mem[None, :], rows=np.array([s]))
         assert_within(lplus[a:a + 1], sc.albedo[s] * e["d_agg"], W_REL, W_ABS, f"L_1 at {a}")
+    assert not lplus[np.flatnonzero(last)[:1000]].any()
+
+
+# ---- the large workload (512^3 fBm, 1024 x 1024 px, 1 spp, depth 128, k 16, D 128)
+
+WL = scenegen.WORKLOADS["large"]
+
+
+@pytest.fixture(scope="module")
+def large():
+    sc = scenegen.generate(WL.scene)
+    print(f"large scene: N={sc.n_vertices} P={sc.n_paths}", flush=True)
+    return sc
+
+
+def test_large_sampled_rows_and_one_step_match_oracle(large):
+    N, K = large.n_vertices, WL.k
+    paths = pg.DevicePaths(large)
+    _, gr = pg.pg_render(paths, pg.params(k=K, D=WL.D, g=WL.g, flags=pg.PG_FLAG_CHECK), graph=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    rows = np.sort(rng.choice(N, 32, replace=False))
+    col = gr["col"].view(N, K)[torch.from_numpy(rows).to(gr["col"].device)].cpu().numpy()
+    w = {n: gr[n].view(N, K)[torch.from_numpy(rows).to(gr[n].device)].cpu().numpy()
+         for n in ("w_ind", "w_ph", "w_env")}
+    b, d_pt = gr["b"].cpu().numpy()[rows], gr["d_pt"].cpu().numpy()[rows]
+    del gr
+    torch.cuda.empty_cache()
+    col_ref = oracle.knn(large.pos, K, rows=rows)
+    assert np.array_equal(col, col_ref)
+    e = oracle.edges(large, oracle.params(k=K, D=WL.D, g=WL.g), col_ref, rows=rows)
+    for name in ("w_ind", "w_ph", "w_env"):
+        assert_within(w[name], e[name], W_REL, W_ABS, name)
+    assert_within(b, large.albedo[rows, None].astype(np.float64) * e["d_agg"], W_REL, W_ABS, "b")
+    assert_within(d_pt, e["d_pt"], W_REL, W_ABS, "d_pt")
+    # D = 1 from zero: L_1(v) = b(succ v) on sampled vertices
+    _, g1 = pg.pg_render(paths, pg.params(k=K, D=1, g=WL.g, init="zero", flags=pg.PG_FLAG_CHECK), graph=True)
+    lplus = g1["lplus"].cpu().numpy()
+    del paths, g1
+    torch.cuda.empty_cache()
+    off = large.path_offsets
+    last = np.zeros(N, bool)
+    last[off[1:][np.diff(off) > 0] - 1] = True
+    v = np.sort(rng.choice(np.flatnonzero(~last), 16, replace=False))
+    col1 = oracle.knn(large.pos, K, rows=v + 1)
+    e1 = oracle.edges(large, oracle.params(k=K, D=1, g=WL.g), col1, rows=v + 1)
+    assert_within(lplus[v], large.albedo[v + 1, None].astype(np.float64) * e1["d_agg"], W_REL, W_ABS, "L_1")
     assert not lplus[np.flatnonzero(last)[:1000]].any()
