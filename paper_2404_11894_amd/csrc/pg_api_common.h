@@ -107,6 +107,11 @@ struct ClusterBufs {
     unsigned long long* mkey = nullptr;   // by slot: key << 32 | path id
     uint64_t* mq = nullptr;          // by slot: packed quantised position
     uint8_t* newc = nullptr;         // by slot: new centre in the current split round
+    uint32_t* nsplit = nullptr;      // [r]: clusters split in round r
+    int32_t* splitlist = nullptr;    // their centres (sorted ids), one round at a time
+    int32_t* stage_m = nullptr;      // by slot: staging of members, mkey and mq while a
+    unsigned long long* stage_k = nullptr;   //   split cluster is regrouped in place
+    uint64_t* stage_q = nullptr;
     int32_t* cperm = nullptr;        // position -> sorted id
     int32_t* cinv = nullptr;         // path id -> position
     uint2* crange = nullptr;         // position -> [first, end) position of its cluster

@@ -24,6 +24,7 @@
 // reads 16 + 12 + 12 bytes of its own and its cluster's members' 16 + 12
 // bytes from L1/L2 (the members are contiguous and shared by the wave's
 // rows), against 8 bytes per edge plus a gather for the stored sliced ELL.
+#include <algorithm>
 #include <utility>
 
 #include "pg_api_common.h"
@@ -205,8 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_nearest_centre(int64_t N, const uint
 // ------------------------------------------------------------ grouping ---
 
 __global__ __launch_bounds__(kBlock) void k_ccount(int64_t N, const int32_t* __restrict__ cid,
-                                                   uint32_t* __restrict__ ccount, const int32_t* __restrict__ live) {
-    if (live && *live == 0) return;
+                                                   uint32_t* __restrict__ ccount) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s < N) (void)wave_count(ccount, cid[s]);
 }
@@ -219,8 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_cgroup(int64_t N, const int32_t* __r
                                                    const int32_t* __restrict__ perm, const uint32_t* __restrict__ key,
                                                    const uint64_t* __restrict__ qs, int32_t* __restrict__ members,
                                                    uint32_t* __restrict__ mslot, unsigned long long* __restrict__ mkey,
-                                                   uint64_t* __restrict__ mq, const int32_t* __restrict__ live) {
-    if (live && *live == 0) return;
+                                                   uint64_t* __restrict__ mq) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
     const int32_t c = cid[s];
@@ -242,14 +241,16 @@ __device__ inline uint2 bounded(uint2 rg) {
 // ----------------------------------------------------------- splitting ---
 
 // Members of a large cluster: the ceil(s/K) of smallest (key, path id)
-// become centres (newc, by group slot).  O(s) per member.
+// become centres (newc, by group slot).  O(s) per member.  The cluster's
+// centre is appended to the round's list of split clusters.
 __global__ __launch_bounds__(kBlock) void k_split_mark(int64_t N, int K, const int32_t* __restrict__ cid,
                                                        const uint32_t* __restrict__ ccount,
                                                        const uint32_t* __restrict__ cstart,
                                                        const uint32_t* __restrict__ mslot,
                                                        const unsigned long long* __restrict__ mkey,
                                                        uint8_t* __restrict__ newc, const int32_t* __restrict__ live,
-                                                       int32_t* __restrict__ split, int32_t* flag) {
+                                                       int32_t* __restrict__ split, uint32_t* __restrict__ nsplit,
+                                                       int32_t* __restrict__ splitlist, int32_t* flag) {
     if (live && *live == 0) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
@@ -267,6 +268,9 @@ __global__ __launch_bounds__(kBlock) void k_split_mark(int64_t N, int K, const i
     for (uint32_t e = a; e < a + sz; ++e) rank += mkey[e] < mine;
     newc[me] = rank < (sz + (uint32_t)K - 1u) / (uint32_t)K;
     if (__lane_id() == (uint32_t)(__ffsll((unsigned long long)__ballot(1)) - 1)) *split = 1;
+    const bool first = me == a;   // one member per split cluster lists it
+    const uint32_t at = wave_append(nsplit, first);
+    if (first) splitlist[at] = c;
 }
 
 // Members of a large cluster join the nearest of its new centres.
@@ -300,6 +304,111 @@ __global__ __launch_bounds__(kBlock) void k_split_assign(int64_t N, int K, const
         }
     }
     cid[s] = members[be];
+}
+
+// Exclusive prefix sum over the block's threads; total = the block's sum.
+__device__ inline uint32_t block_scan_excl(uint32_t v, uint32_t& total, uint32_t* wsum) {
+    const int lane = (int)__lane_id(), w = (int)(threadIdx.x / kWave);
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) wsum[w] = x;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) {
+        const uint32_t t = wsum[i];
+        off += i < w ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return off + x - v;
+}
+
+// After a split round, each split cluster is regrouped inside its own slot
+// range [a, a + size): its members joined new centres drawn from the same
+// cluster, so the new clusters partition that range and every other
+// cluster's grouping stays valid.  One block per split cluster (grid-stride
+// over the round's list).  The range is staged (same slots) and written back
+// grouped by new centre, in the slot order of the new centres; within a new
+// cluster the order is that of the block's atomics, as in the global
+// grouping (every later step ranks the members by key or path id).
+__global__ __launch_bounds__(kBlock) void k_regroup(const int32_t* __restrict__ list,
+                                                    const uint32_t* __restrict__ nlist,
+                                                    const int32_t* __restrict__ cid, uint32_t* __restrict__ ccount,
+                                                    uint32_t* __restrict__ cstart, int32_t* __restrict__ members,
+                                                    uint32_t* __restrict__ mslot,
+                                                    unsigned long long* __restrict__ mkey, uint64_t* __restrict__ mq,
+                                                    const uint8_t* __restrict__ newc, int32_t* __restrict__ stage_m,
+                                                    unsigned long long* __restrict__ stage_k,
+                                                    uint64_t* __restrict__ stage_q) {
+    __shared__ uint32_t s_cnt[kClusterMax];     // members per new centre, then fill counters
+    __shared__ uint32_t s_start[kClusterMax];   // first local slot of each new centre
+    __shared__ int32_t s_cent[kClusterMax];     // sorted id of each new centre
+    __shared__ uint16_t s_pre[kClusterMax];     // new centres in the local slots before t
+    __shared__ uint16_t s_idx[kClusterMax];     // each member's new-centre index
+    __shared__ uint32_t s_wsum[kBlock / kWave];
+    const uint32_t n = *nlist;
+    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const int32_t c = list[it];
+        const uint32_t a = cstart[c], sz = ccount[c];   // 2K < sz <= kClusterMax (split clusters only)
+        // the new centres in slot order, and the range staged
+        uint32_t nc = 0;
+        for (uint32_t base = 0; base < sz; base += kBlock) {
+            const uint32_t t = base + threadIdx.x;
+            const bool in = t < sz;
+            const uint32_t f = (in && newc[a + t]) ? 1u : 0u;
+            uint32_t tot;
+            const uint32_t pre = nc + block_scan_excl(f, tot, s_wsum);
+            if (in) {
+                const int32_t m = members[a + t];
+                s_pre[t] = (uint16_t)pre;
+                if (f) s_cent[pre] = m;
+                stage_m[a + t] = m;
+                stage_k[a + t] = mkey[a + t];
+                stage_q[a + t] = mq[a + t];
+            }
+            nc += tot;
+        }
+        for (uint32_t j = threadIdx.x; j < nc; j += kBlock) s_cnt[j] = 0;
+        __syncthreads();
+        // members per new centre (a new centre's slot is still its old one)
+        for (uint32_t t = threadIdx.x; t < sz; t += kBlock) {
+            const uint32_t j = s_pre[mslot[cid[stage_m[a + t]]] - a];
+            s_idx[t] = (uint16_t)j;
+            atomicAdd(&s_cnt[j], 1u);
+        }
+        __syncthreads();
+        uint32_t run = 0;
+        for (uint32_t base = 0; base < nc; base += kBlock) {
+            const uint32_t j = base + threadIdx.x;
+            uint32_t tot;
+            const uint32_t pre = run + block_scan_excl(j < nc ? s_cnt[j] : 0u, tot, s_wsum);
+            if (j < nc) s_start[j] = pre;
+            run += tot;
+        }
+        for (uint32_t j = threadIdx.x; j < nc; j += kBlock) {
+            ccount[s_cent[j]] = s_cnt[j];
+            cstart[s_cent[j]] = a + s_start[j];
+            s_cnt[j] = 0;
+        }
+        __syncthreads();
+        // write back grouped by new centre
+        for (uint32_t t = threadIdx.x; t < sz; t += kBlock) {
+            const uint32_t j = s_idx[t];
+            const uint32_t e = a + s_start[j] + atomicAdd(&s_cnt[j], 1u);
+            const int32_t m = stage_m[a + t];
+            members[e] = m;
+            mkey[e] = stage_k[a + t];
+            mq[e] = stage_q[a + t];
+            mslot[m] = e;
+        }
+        __syncthreads();
+    }
 }
 
 // ----------------------------------------------------------- the order ---
@@ -950,6 +1059,11 @@ void carve_clusters(Carver& cv, ClusterBufs& cb, int64_t N, int K) {
     cb.mkey = cv.take<unsigned long long>(N);
     cb.mq = cv.take<uint64_t>(N);
     cb.newc = cv.take<uint8_t>(N);
+    cb.nsplit = cv.take<uint32_t>(kClusterRounds);
+    cb.splitlist = cv.take<int32_t>(N / (2 * (int64_t)K + 1) + 1);
+    cb.stage_m = cv.take<int32_t>(N);
+    cb.stage_k = cv.take<unsigned long long>(N);
+    cb.stage_q = cv.take<uint64_t>(N);
     cb.cperm = cv.take<int32_t>(N);
     cb.cinv = cv.take<int32_t>(N);
     cb.crange = cv.take<uint2>(N);
@@ -963,16 +1077,16 @@ void carve_clusters(Carver& cv, ClusterBufs& cb, int64_t N, int K) {
 
 static dim3 grid_of(int64_t n) { return dim3((unsigned)div_up(n > 0 ? n : 1, kBlock)); }
 
-// (Re)builds the grouping of the vertices by cluster: counts, starts, members.
-static hipError_t group(const pg_paths* p, const GridBufs& g, int64_t N, ClusterBufs& cb, const int32_t* live,
-                        hipStream_t s) {
+// Groups the vertices by cluster (counts, starts, members): once, after the
+// nearest-centre assignment; the split rounds then regroup in place.
+static hipError_t group(const pg_paths* p, const GridBufs& g, int64_t N, ClusterBufs& cb, hipStream_t s) {
     PG_TRY(launch_fill(cb.ccount, (size_t)(N + 1) * 4, s));
     PG_TRY(launch_fill(cb.cfill, (size_t)N * 4, s));
-    hipLaunchKernelGGL(k_ccount, grid_of(N), dim3(kBlock), 0, s, N, cb.cid, cb.ccount, live);
+    hipLaunchKernelGGL(k_ccount, grid_of(N), dim3(kBlock), 0, s, N, cb.cid, cb.ccount);
     PG_TRY(hipGetLastError());
     PG_TRY(launch_scan_exclusive(cb.ccount, cb.cstart, N + 1, cb.cpart, s));
     hipLaunchKernelGGL(k_cgroup, grid_of(N), dim3(kBlock), 0, s, N, cb.cid, cb.cstart, cb.cfill, g.perm,
-                       p->cluster_key, g.qs, cb.members, cb.mslot, cb.mkey, cb.mq, live);
+                       p->cluster_key, g.qs, cb.members, cb.mslot, cb.mkey, cb.mq);
     return hipGetLastError();
 }
 
@@ -983,6 +1097,7 @@ hipError_t run_clusters(const pg_paths* p, GridBufs& g, ClusterBufs& cb, hipStre
     if (N == 0) return hipSuccess;
     PG_TRY(launch_fill(cb.live, 64 * 4, s));
     PG_TRY(launch_fill_value(cb.live, 4, 1u, s));
+    PG_TRY(launch_fill(cb.nsplit, kClusterRounds * 4, s));
     const int64_t nb = div_up(N, kBlock);
     hipLaunchKernelGGL(k_key_min, dim3((unsigned)nb), dim3(kBlock), 0, s, N, p->cluster_key, cb.part);
     PG_TRY(hipGetLastError());
@@ -1004,22 +1119,29 @@ hipError_t run_clusters(const pg_paths* p, GridBufs& g, ClusterBufs& cb, hipStre
                            cb.gs, cb.gpid, cb.cid, g.flag);
         PG_TRY(hipGetLastError());
     }
-    // split rounds; round r runs only if round r-1 split something
+    // split rounds; round r runs only if round r-1 split something.  The
+    // vertices are grouped by centre once; a round regroups only the
+    // clusters it split, each inside its own range.
     {
         ProfScope ps(s, "split");
+        PG_TRY(group(p, g, N, cb, s));
+        const unsigned rg_blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, N / (2 * (int64_t)K + 1)));
         for (int r = 0; r < kClusterRounds; ++r) {
             const int32_t* live = cb.live + r;
-            PG_TRY(group(p, g, N, cb, live, s));
             hipLaunchKernelGGL(k_split_mark, grid_of(N), dim3(kBlock), 0, s, N, K, cb.cid, cb.ccount, cb.cstart,
-                               cb.mslot, cb.mkey, cb.newc, live, cb.live + r + 1, g.flag);
+                               cb.mslot, cb.mkey, cb.newc, live, cb.live + r + 1, cb.nsplit + r, cb.splitlist,
+                               g.flag);
             PG_TRY(hipGetLastError());
             hipLaunchKernelGGL(k_split_assign, grid_of(N), dim3(kBlock), 0, s, N, K, g.qs, cb.cid, cb.ccount,
                                cb.cstart, cb.members, cb.mkey, cb.mq, cb.newc, live);
             PG_TRY(hipGetLastError());
+            hipLaunchKernelGGL(k_regroup, dim3(rg_blocks), dim3(kBlock), 0, s, cb.splitlist, cb.nsplit + r, cb.cid,
+                               cb.ccount, cb.cstart, cb.members, cb.mslot, cb.mkey, cb.mq, cb.newc, cb.stage_m,
+                               cb.stage_k, cb.stage_q);
+            PG_TRY(hipGetLastError());
         }
     }
     ProfScope ps(s, "cluster_order");
-    PG_TRY(group(p, g, N, cb, nullptr, s));
     hipLaunchKernelGGL(k_corder, grid_of(N), dim3(kBlock), 0, s, N, cb.cid, cb.ccount, cb.cstart, cb.mslot,
                        cb.mkey, g.perm, cb.cperm, cb.cinv, cb.crange, g.flag);
     return hipGetLastError();
