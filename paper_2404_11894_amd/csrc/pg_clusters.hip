@@ -565,6 +565,19 @@ __device__ __forceinline__ float hg_shape(const HG& rho, f3 t, float wx, float w
     return r * r * r;
 }
 
+// The shape r^3 of hg_shape (r = 1/sqrt(den), den = (1-g)^2 + 2 g u) and,
+// from the same denominator, d ln HG / d g = c0 - 3 (g - 1 + u) / den with
+// c0 = -2g / (1 - g^2) and 1/den = r^2 (rho built from g; gm1 = g - 1).
+__device__ __forceinline__ float hg_shape_dlog(const HG& rho, float c0, float gm1, f3 t, float wx, float wy,
+                                               float wz, float& dl) {
+    const float dx = t.x - wx, dy = t.y - wy, dz = t.z - wz;
+    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float r = __frsqrt_rn(fmaf(0.5f * rho.two_g, d2, rho.a));
+    const float r2 = r * r;
+    dl = fmaf(-3.0f * fmaf(0.5f, d2, gm1), r2, c0);
+    return r2 * r;
+}
+
 // sum_j rho_i(w_j) (1/M+_j) x_j over the cluster [a, e)
 __device__ __forceinline__ f3 cluster_gather(const HG& rho, f3 ti, uint2 rg, const float4* __restrict__ wq,
                                              const float* __restrict__ x) {
@@ -884,13 +897,15 @@ __global__ __launch_bounds__(kBlock) void k_crev_rows(int64_t N, HG rho, float g
         const float4 t4 = tq[i];
         const f3 ti{t4.x, t4.y, t4.z};
         const uint2 rg = bounded(crange[i]);
+        const float c0 = -2.0f * g / (1.0f - g * g), gm1 = g - 1.0f;
         f3 z{0.f, 0.f, 0.f}, zg{0.f, 0.f, 0.f};
         for (uint32_t j = rg.x; j < rg.y; ++j) {
             const float4 w4 = staged ? sw[j - lo] : wq[j];
             const f3 xv = staged ? f3{sx[3 * (j - lo)], sx[3 * (j - lo) + 1], sx[3 * (j - lo) + 2]}
                                  : tape_x<SHIFTED>(x, succ, j);
-            const float f = hg_shape(rho, ti, w4.x, w4.y, w4.z) * w4.w;
-            const float fh = f * hg_dlog(g, one_minus_cos(ti, f3{w4.x, w4.y, w4.z}));
+            float dl;
+            const float f = hg_shape_dlog(rho, c0, gm1, ti, w4.x, w4.y, w4.z, dl) * w4.w;
+            const float fh = f * dl;
             z = f3{fmaf(f, xv.x, z.x), fmaf(f, xv.y, z.y), fmaf(f, xv.z, z.z)};
             zg = f3{fmaf(fh, xv.x, zg.x), fmaf(fh, xv.y, zg.y), fmaf(fh, xv.z, zg.z)};
         }
