@@ -60,6 +60,44 @@ def test_centres_with_splits_and_cell_sizes():
         assert np.array_equal(gpu_centres(sc, 8, shift), ref), shift
 
 
+@pytest.mark.parametrize("n,k,seeds", [(9000, 3, [17, 1000, 2000, 4000, 5999, 7000]),
+                                        (6000, 2, [17, 1500, 4000, 5999])])
+def test_centres_few_seeds_split_in_large_rounds(n, k, seeds):
+    # a handful of seeded centres: the first assignment makes clusters of
+    # 500-2500 members (below the 4096 limit), whose splits create hundreds of
+    # new centres at once (the regrouping runs over many chunks of members
+    # and of centres)
+    rng = np.random.default_rng(21)
+    pos = rng.random((n, 3)).astype(np.float32)
+    key = np.maximum(rng.integers(1 << 31, 1 << 32, size=n, dtype=np.uint64),
+                     (1 << 32) // k).astype(np.uint32)
+    key[seeds] = np.arange(1, len(seeds) + 1)
+    sc = replace(synthetic(pos, rng), cluster_key=key)
+    ref = oracle.clusters(sc.pos, sc.cluster_key, k)
+    assert np.bincount(ref).max() <= 2 * k
+    print(f"few seeds n={n} k={k}: {np.unique(ref).size} clusters", flush=True)
+    assert np.array_equal(gpu_centres(sc, k), ref)
+
+
+def test_cluster_above_the_member_limit_is_reported():
+    # three seeded centres among 9000 vertices: a first cluster exceeds the
+    # 4096-member limit, which the kernels flag (its rows are left empty) and
+    # the calls report as invalid device data
+    rng = np.random.default_rng(21)
+    n, k = 9000, 3
+    pos = rng.random((n, 3)).astype(np.float32)
+    key = np.maximum(rng.integers(1 << 31, 1 << 32, size=n, dtype=np.uint64),
+                     (1 << 32) // k).astype(np.uint32)
+    key[[17, 4000, 5999]] = [5, 9, 1]
+    sc = replace(synthetic(pos, rng), cluster_key=key)
+    with pytest.raises(pg.PathGraphError, match="more than 4096 members"):
+        gpu_centres(sc, k)
+    q = pg.params(k=k, D=2, g=0.5, flags=pg.PG_FLAG_CHECK | pg.PG_FLAG_CLUSTERS)
+    with pytest.raises(pg.PathGraphError, match="more than 4096 members"):
+        pg.pg_render(pg.DevicePaths(sc), q)
+        torch.cuda.synchronize()
+
+
 def test_centres_duplicates_and_small_inputs():
     rng = np.random.default_rng(2)
     base = rng.random((50, 3)).astype(np.float32)
