@@ -151,9 +151,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_scatter(int64_t N, const int32_t*
 }
 
 // Nearest centre of every vertex: rings of cells at Chebyshev distance r
-// around the vertex's cell, r = 0, 1, ...; a cell at ring r+1 is farther
-// than r cell widths in every coordinate, so the search ends after ring r
-// once the best squared distance is at most (r * width)^2.
+// around the vertex's cell, r = 0, 1, ....  A cell whose box is farther than
+// the best distance so far is skipped (one at exactly that distance is read:
+// a tie may win on its path id).  After ring r every unvisited centre is at
+// least `gap` quantisation steps away on some axis, so the search ends once
+// the best squared distance is below gap^2.
 __global__ __launch_bounds__(kBlock) void k_nearest_centre(int64_t N, const uint64_t* __restrict__ qs, int b,
                                                            const uint32_t* __restrict__ gstart,
                                                            const uint64_t* __restrict__ gq,
@@ -170,18 +172,23 @@ __global__ __launch_bounds__(kBlock) void k_nearest_centre(int64_t N, const uint
     const int cx = qx >> sh, cy = qy >> sh, cz = qz >> sh;
     int64_t bd = INT64_MAX;
     int32_t bp = INT32_MAX, bs = -1;
+    const int64_t cw = (int64_t)1 << sh;   // cell width in quantisation steps
     for (int r = 0; r < side; ++r) {
         for (int dz = -r; dz <= r; ++dz) {
             const int z = cz + dz;
             if (z < 0 || z >= side) continue;
+            const int64_t gz = dz < 0 ? (int64_t)qz - ((int64_t)(z + 1) * cw - 1) : (dz > 0 ? (int64_t)z * cw - qz : 0);
             for (int dy = -r; dy <= r; ++dy) {
                 const int y = cy + dy;
                 if (y < 0 || y >= side) continue;
+                const int64_t gy = dy < 0 ? (int64_t)qy - ((int64_t)(y + 1) * cw - 1) : (dy > 0 ? (int64_t)y * cw - qy : 0);
                 const bool face = dz == -r || dz == r || dy == -r || dy == r;
                 const int step = face ? 1 : 2 * r;
                 for (int dx = -r; dx <= r; dx += step) {
                     const int x = cx + dx;
                     if (x < 0 || x >= side) continue;
+                    const int64_t gx = dx < 0 ? (int64_t)qx - ((int64_t)(x + 1) * cw - 1) : (dx > 0 ? (int64_t)x * cw - qx : 0);
+                    if (gx * gx + gy * gy + gz * gz > bd) continue;   // the whole cell is farther
                     const uint32_t cell = ((uint32_t)z << (2 * b)) | ((uint32_t)y << b) | (uint32_t)x;
                     const uint32_t e1 = gstart[cell + 1];
                     for (uint32_t e = gstart[cell]; e < e1; ++e) {
@@ -196,8 +203,17 @@ __global__ __launch_bounds__(kBlock) void k_nearest_centre(int64_t N, const uint
                 }
             }
         }
-        const int64_t lim = (int64_t)r << sh;
-        if (bs >= 0 && bd <= lim * lim) break;
+        // smallest per-axis distance from q to a cell outside the searched cube
+        int64_t gap = INT64_MAX;
+        const int c3[3] = {cx, cy, cz};
+        const int64_t q3[3] = {qx, qy, qz};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (c3[a] - r > 0) gap = min(gap, q3[a] - (int64_t)(c3[a] - r) * cw + 1);
+            if (c3[a] + r < side - 1) gap = min(gap, (int64_t)(c3[a] + r + 1) * cw - q3[a]);
+        }
+        if (gap == INT64_MAX) break;                // the whole grid was searched
+        if (bs >= 0 && bd < gap * gap) break;       // provably final
     }
     if (bs < 0) set_flag(flag, kFlagCluster);
     cid[s] = bs < 0 ? (int32_t)s : bs;
