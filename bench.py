@@ -236,8 +236,9 @@ def time_clusters(pg, torch, sc, w, steps, warmup, knn_ms):
 
 
 def time_tracer(pg, torch, w, host_gen_s, host_copy_s):
-    """Generating the workload's records on the GPU (pg_trace: count pass,
-    scan, record pass) against the host generator plus the copy to HBM."""
+    """Generating the workload's records on the GPU (pg_trace: the count pass
+    traces into the workspace, a scan, the record pass compacts) against the
+    host generator plus the copy to HBM."""
     import scenegen
     dev = torch.device("cuda:0")
     sigma, alb, maj = scenegen.medium(w.scene)
@@ -261,7 +262,7 @@ def time_tracer(pg, torch, w, host_gen_s, host_copy_s):
     return {"ms_device": round(ms, 2), "n_vertices": n, "paths": w.scene.width * w.scene.height * w.scene.spp,
             "ms_host_generate": round(host_gen_s * 1e3, 1), "ms_host_to_device_copy": round(host_copy_s * 1e3, 1),
             "speedup_vs_host_plus_copy": round((host_gen_s + host_copy_s) * 1e3 / ms, 2),
-            "note": "records traced twice on the device (count, then write); host: all cores of the box"}
+            "note": "records traced once into the workspace (pg_trace_count), then compacted (pg_trace_records); host: all cores of the box"}
 
 
 def study(pg, torch, w):

@@ -246,14 +246,18 @@ typedef struct pg_records {
 } pg_records;
 
 /* Pass 1: traces every path and writes path_offsets[P+1] (device); N to
- * *n_vertices (host; the call synchronises the stream once). */
+ * *n_vertices (host; the call synchronises the stream once).  The records
+ * stay in the workspace, which holds max_depth record slots per path
+ * (about 88 bytes each, 24 more with a point light) plus the paths' extra
+ * samples: pg_trace_workspace_size grows with P * max_depth. */
 pg_status pg_trace_workspace_size(const pg_tracer* t, size_t* bytes);
 pg_status pg_trace_count(const pg_tracer* t, int64_t* path_offsets, int64_t* n_vertices, void* ws,
                          size_t ws_bytes, void* stream);
-/* Pass 2: traces the same paths again and writes their records at the
- * offsets of pass 1 (same tracer settings and medium).  Offsets that do not
- * match the paths return PG_ERR_INPUT; no record is written outside a path's
- * slots.  Synchronises the stream once. */
+/* Pass 2: copies the records pass 1 left in the workspace to the offsets
+ * of pass 1 (same tracer settings; the workspace passed to pass 1, unchanged
+ * since).  A path whose offsets do not span exactly its traced vertex count
+ * is not written and the call returns PG_ERR_INPUT; no record is written
+ * outside a path's slots.  Synchronises the stream once. */
 pg_status pg_trace_records(const pg_tracer* t, const int64_t* path_offsets, const pg_records* out, void* ws,
                            size_t ws_bytes, void* stream);
 

@@ -303,26 +303,52 @@ __device__ int trace_path(const Tracer& tr, int64_t p, int64_t v0, int64_t vcap,
     return nv;
 }
 
-__global__ __launch_bounds__(kBlock) void k_trace_count(Tracer tr, int64_t P, uint32_t* __restrict__ count,
-                                                        float* __restrict__ e_cam) {
+// Pass 1: traces path p into its max_depth slots of the workspace slab
+// (slot p * max_depth + k), with its extra samples and camera term, and
+// counts its vertices.
+__global__ __launch_bounds__(kBlock) void k_trace_count(Tracer tr, int64_t P, uint32_t* __restrict__ count, Out slab,
+                                                        float* __restrict__ slab_ecam) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     float ec[3];
-    count[p] = (uint32_t)trace_path<false>(tr, p, 0, 0, Out{}, ec);   // the count pass draws no extra samples
-    if (e_cam)
-        for (int a = 0; a < 3; ++a) e_cam[3 * p + a] = ec[a];
+    const int64_t maxd = tr.t.max_depth;
+    count[p] = (uint32_t)trace_path<true>(tr, p, p * maxd, maxd, slab, ec);
+    for (int a = 0; a < 3; ++a) slab_ecam[3 * p + a] = ec[a];
 }
 
-__global__ __launch_bounds__(kBlock) void k_trace_write(Tracer tr, int64_t P, const int64_t* __restrict__ off,
-                                                        Out o, float* __restrict__ e_cam, int32_t* flag) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    float ec[3];
-    const int64_t a = off[p], cap = off[p + 1] - a;
-    const int nv = trace_path<true>(tr, p, a, cap, o, ec);
-    if (nv != cap) set_flag(flag, kFlagOffsets);   // offsets not from this tracer
-    if (e_cam)
-        for (int c = 0; c < 3; ++c) e_cam[3 * p + c] = ec[c];
+// Pass 2: one thread per slab slot (p, k) copies the k-th record of path p
+// to path_offsets[p] + k.  A path whose offsets do not span exactly its
+// traced vertex count (offsets not from this trace) is not written and is
+// reported.
+__global__ __launch_bounds__(kBlock) void k_trace_compact(int64_t P, int64_t maxd, const int64_t* __restrict__ off,
+                                                          const uint32_t* __restrict__ start, Out slab, Out o,
+                                                          bool point_light, int32_t* flag) {
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= P * maxd) return;
+    const int64_t p = slot / maxd, k = slot - p * maxd;
+    const int64_t c = (int64_t)start[p + 1] - (int64_t)start[p];
+    const int64_t a = off[p], n = off[p + 1] - a;
+    if (n != c || a < 0) {
+        if (k == 0) set_flag(flag, kFlagOffsets);   // offsets not from this tracer
+        return;
+    }
+    if (k >= c) return;
+    const int64_t v = a + k;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        o.pos[3 * v + q] = slab.pos[3 * slot + q];
+        o.dir_in[3 * v + q] = slab.dir_in[3 * slot + q];
+        o.dir_out[3 * v + q] = slab.dir_out[3 * slot + q];
+        o.l_sun[3 * v + q] = slab.l_sun[3 * slot + q];
+        o.dir_env[3 * v + q] = slab.dir_env[3 * slot + q];
+        o.l_env[3 * v + q] = slab.l_env[3 * slot + q];
+        o.l_phase[3 * v + q] = slab.l_phase[3 * slot + q];
+        if (point_light) {
+            o.dir_pl[3 * v + q] = slab.dir_pl[3 * slot + q];
+            o.l_pl[3 * v + q] = slab.l_pl[3 * slot + q];
+        }
+    }
+    o.albedo[v] = slab.albedo[slot];
 }
 
 // offsets (int64) from the scanned counts (uint32, P+1 entries)
@@ -368,31 +394,66 @@ int64_t tracer_paths(const pg_tracer* t) {
     return cw * ch * t->spp;
 }
 
-size_t trace_ws_size(const pg_tracer* t) {
+// Workspace: flags, the vertex counts (scanned in place to offsets), and the
+// slab the count pass traces into: max_depth record slots per path, the
+// paths' extra samples and camera terms.  Pass 2 copies from the slab, so
+// both passes must use the same workspace, unchanged in between.
+struct TraceWs {
+    int32_t* flag;
+    uint32_t* count;
+    uint32_t* part;
+    Out slab;
+    float* ecam;
+};
+
+static TraceWs carve_trace(Carver& cv, const pg_tracer* t) {
     const int64_t P = tracer_paths(t);
+    const int64_t S = P * (int64_t)t->max_depth;
+    const bool pl = t->pl_I[0] != 0.0 || t->pl_I[1] != 0.0 || t->pl_I[2] != 0.0;
+    const int64_t F = t->extra_samples > 0 ? P * (int64_t)t->extra_samples * 3 : 0;
+    TraceWs w;
+    w.flag = cv.take<int32_t>(64);
+    w.count = cv.take<uint32_t>(P + 1);
+    w.part = cv.take<uint32_t>(scan_partials_bytes(P + 1) / 4);
+    w.slab.pos = cv.take<float>(3 * S);
+    w.slab.dir_in = cv.take<float>(3 * S);
+    w.slab.dir_out = cv.take<float>(3 * S);
+    w.slab.albedo = cv.take<float>(S);
+    w.slab.l_sun = cv.take<float>(3 * S);
+    w.slab.dir_env = cv.take<float>(3 * S);
+    w.slab.l_env = cv.take<float>(3 * S);
+    w.slab.l_phase = cv.take<float>(3 * S);
+    w.slab.fb_l_sun = F ? cv.take<float>(F) : nullptr;
+    w.slab.fb_dir_env = F ? cv.take<float>(F) : nullptr;
+    w.slab.fb_l_env = F ? cv.take<float>(F) : nullptr;
+    w.slab.dir_pl = pl ? cv.take<float>(3 * S) : nullptr;
+    w.slab.l_pl = pl ? cv.take<float>(3 * S) : nullptr;
+    w.ecam = cv.take<float>(3 * P + 3);
+    return w;
+}
+
+size_t trace_ws_size(const pg_tracer* t) {
     Carver cv(nullptr);
-    cv.take<int32_t>(64);
-    cv.take<uint32_t>(P + 1);
-    cv.take<uint32_t>(scan_partials_bytes(P + 1) / 4);
+    (void)carve_trace(cv, t);
     return cv.size();
 }
 
 hipError_t run_trace_count(const pg_tracer* t, int64_t* path_offsets, float* e_cam, void* ws, hipStream_t s) {
+    (void)e_cam;   // kept in the slab; pass 2 writes it
     const int64_t P = tracer_paths(t);
     Carver cv(ws);
-    cv.take<int32_t>(64);
-    uint32_t* count = cv.take<uint32_t>(P + 1);
-    uint32_t* part = cv.take<uint32_t>(scan_partials_bytes(P + 1) / 4);
+    const TraceWs w = carve_trace(cv, t);
     hipError_t e;
-    if ((e = launch_fill(count, (size_t)(P + 1) * 4, s)) != hipSuccess) return e;
+    if ((e = launch_fill(w.count, (size_t)(P + 1) * 4, s)) != hipSuccess) return e;
     const Tracer tr = make_tracer(t);
     if (P > 0) {
         ProfScope ps(s, "trace_count");
-        hipLaunchKernelGGL(k_trace_count, dim3((unsigned)div_up(P, kBlock)), dim3(kBlock), 0, s, tr, P, count, e_cam);
+        hipLaunchKernelGGL(k_trace_count, dim3((unsigned)div_up(P, kBlock)), dim3(kBlock), 0, s, tr, P, w.count,
+                           w.slab, w.ecam);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = launch_scan_exclusive(count, count, P + 1, part, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_widen, dim3((unsigned)div_up(P + 1, kBlock)), dim3(kBlock), 0, s, P + 1, count,
+    if ((e = launch_scan_exclusive(w.count, w.count, P + 1, w.part, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)div_up(P + 1, kBlock)), dim3(kBlock), 0, s, P + 1, w.count,
                        path_offsets);
     return hipGetLastError();
 }
@@ -401,18 +462,28 @@ hipError_t run_trace_write(const pg_tracer* t, const int64_t* path_offsets, cons
                            hipStream_t s, int32_t** flag_out) {
     const int64_t P = tracer_paths(t);
     Carver cv(ws);
-    int32_t* flag = cv.take<int32_t>(64);
-    *flag_out = flag;
+    const TraceWs w = carve_trace(cv, t);
+    *flag_out = w.flag;
     hipError_t e;
-    if ((e = launch_fill(flag, 64 * 4, s)) != hipSuccess) return e;
+    if ((e = launch_fill(w.flag, 64 * 4, s)) != hipSuccess) return e;
     if (P == 0) return hipSuccess;
     const Tracer tr = make_tracer(t);
     Out out{o.pos, o.dir_in, o.dir_out, o.albedo, o.l_sun, o.dir_env, o.l_env, o.l_phase,
             o.fb_l_sun, o.fb_dir_env, o.fb_l_env, o.dir_pl, o.l_pl};
     ProfScope ps(s, "trace_write");
-    hipLaunchKernelGGL(k_trace_write, dim3((unsigned)div_up(P, kBlock)), dim3(kBlock), 0, s, tr, P, path_offsets, out,
-                       o.e_cam, flag);
-    return hipGetLastError();
+    const int64_t maxd = t->max_depth;
+    hipLaunchKernelGGL(k_trace_compact, dim3((unsigned)div_up(P * maxd, kBlock)), dim3(kBlock), 0, s, P, maxd,
+                       path_offsets, (const uint32_t*)w.count, w.slab, out, tr.point_light, w.flag);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(o.e_cam, w.ecam, (size_t)P * 12, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+    if (t->extra_samples > 0) {
+        const size_t F = (size_t)P * (size_t)t->extra_samples * 12;
+        if ((e = hipMemcpyAsync(o.fb_l_sun, w.slab.fb_l_sun, F, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(o.fb_dir_env, w.slab.fb_dir_env, F, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+            return e;
+        if ((e = hipMemcpyAsync(o.fb_l_env, w.slab.fb_l_env, F, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace pg

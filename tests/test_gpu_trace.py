@@ -145,6 +145,12 @@ def test_trace_records_rejects_foreign_offsets():
     L = pg.lib()
     pg._check(L.pg_trace_workspace_size(ctypes.byref(t), ctypes.byref(nb)))
     _, ws, n = pg._workspace(nb.value, torch.device("cuda"))
+    # pass 1 of the other seed fills the workspace; pass 2 is offered the first seed's offsets
+    off2 = torch.empty(rec.path_offsets.numel(), dtype=torch.int64, device="cuda")
+    n2 = ctypes.c_int64()
+    pg._check(L.pg_trace_count(ctypes.byref(t), pg._ptr(off2), ctypes.byref(n2), pg._ptr(ws), n,
+                               pg._stream(torch.device("cuda"))))
+    assert not torch.equal(off2, rec.path_offsets)
     rc = L.pg_trace_records(ctypes.byref(t), pg._ptr(rec.path_offsets),
                             ctypes.byref(r), pg._ptr(ws), n, pg._stream(torch.device("cuda")))
     torch.cuda.synchronize()
