@@ -16,9 +16,10 @@
 // the full image, seeded from (seed, sample index) through splitmix64, so a
 // crop traces the paths the full image traces there.
 //
-// One thread per path, in double precision without contraction; the records
-// are written in a second pass that re-traces every path with the same
-// stream at the offsets the first (counting) pass and a scan produced.
+// One thread per path, in double precision without contraction.  The
+// counting pass traces each path into max_depth record slots of its own in
+// the workspace; a scan gives the offsets, and the record pass copies each
+// path's records to its offsets.
 #include <cmath>
 
 #include "pg_api_common.h"
