@@ -174,6 +174,30 @@ def test_tracer_validation():
     assert rc == pg.PG_ERR_ARG
 
 
+def test_tracer_workspace_holds_max_depth_records_per_path():
+    # the counting pass keeps every path's records in the workspace: 88 bytes
+    # per slot (seven 3-vectors and the albedo), max_depth slots per path, and
+    # 24 more per slot with a point light
+    L = pg.lib()
+    t = pg.Tracer()
+    t.R, t.width, t.height, t.spp = 8, 64, 32, 2
+    t.sigma, t.majorant, t.g = 0x1000, 1.0, 0.5
+    P = 64 * 32 * 2
+
+    def ws(depth, pl=0.0):
+        tt = pg.Tracer.from_buffer_copy(t)
+        tt.max_depth = depth
+        tt.pl_I[0] = pl
+        nb = ctypes.c_size_t()
+        assert L.pg_trace_workspace_size(ctypes.byref(tt), ctypes.byref(nb)) == 0
+        return nb.value
+
+    grow = ws(96) - ws(32)
+    assert 88 * P * 64 <= grow <= 88 * P * 64 + 4096   # alignment padding of the carved arrays
+    grow_pl = ws(96, 1.0) - ws(32, 1.0)
+    assert 112 * P * 64 <= grow_pl <= 112 * P * 64 + 4096
+
+
 def test_calls_reject_bad_workspace_before_launching():
     L = pg.lib()
     s, q = fake_paths(), pg.params(k=8, D=4)
