@@ -1,14 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the path-graph hot path on one MI355X.
 
-Workload: the 128^3 fBm ball (sigma_t <= 32, per-voxel albedo U[0.95,0.999],
-HG g = 0.8, sun + environment), 512x512 px at 4 spp, delta-tracking paths to
-depth 64; k = 16 neighbours, D = 64 iterations.  Inputs are generated on the
-host, copied to HBM, and are resident before the timed region starts.
+Headline workload (the forward line): the large dense forward-scattering
+cloud -- 512^3 fBm medium (sigma_t <= 64), albedo 0.999, HG g = 0.9, sun +
+environment, 1024x1024 px at 1 spp, delta-tracking paths to depth 128
+(about 69M vertices); k = 16 neighbours, D = 128 iterations.  Inputs are
+generated on the host, copied to HBM, and are resident before the timed
+region starts.
 
 One step = one pg_render call: grid build + exact kNN, aggregation operators,
 path pass, D iterations of aggregation + propagation, output to pixels.
 value = E * D / step time  (E = N * K edges), in Gedge-updates/s.
+
+The other legs run on the mid workload (128^3 fBm ball, 512x512 px at 4 spp,
+depth 64, k = 16, D = 64), on which the differentiation workload is defined:
+its forward line, the GPU path tracer, the cluster relation, forward +
+adjoint; then the 64-scene batch.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -86,21 +93,38 @@ def profile_entries(pg):
     return {arr[i].name.decode(): (arr[i].count, arr[i].total_ms, arr[i].max_ms) for i in range(min(n.value, 64))}
 
 
-def cpu_baseline(workload, k, D, g):
-    """The FP64 oracle, single-threaded, on a centred 64x64-pixel crop of the
-    same workload (all its samples per pixel): the whole pipeline."""
+def cpu_baseline(workload, sc_full, seconds=15.0):
+    """The FP64 oracle, single-threaded, on a centred square crop of the same
+    workload (all its samples per pixel): the whole pipeline.  A pilot crop of
+    about 1e8 edge-updates (E D) measures the oracle's rate on this workload;
+    the timed crop is then sized for about `seconds` of oracle time."""
     import oracle
     import scenegen
-    sc = scenegen.generate(scenegen.crop_of(workload.scene, 64, 64))
+    k, D, g = workload.k, workload.D, workload.g
+    per_px = sc_full.n_vertices / (sc_full.width * sc_full.height)
+
+    def side_for(work):
+        return int(max(8, min(sc_full.width, round((work / (k * D * per_px)) ** 0.5 / 8) * 8)))
+
+    def run(side):
+        sc = scenegen.generate(scenegen.crop_of(workload.scene, side, side))
+        t0 = time.perf_counter()
+        oracle.render(sc, oracle.params(k=k, D=D, g=g))
+        return sc, time.perf_counter() - t0
+
+    side = side_for(1e8)
+    sc, dt = run(side)
+    rate = sc.n_vertices * min(k, sc.n_vertices) * D / dt
+    if dt < 0.5 * seconds:
+        side = side_for(rate * seconds)
+        log(f"cpu baseline: pilot {dt:.1f} s; oracle on a {side}x{side} crop")
+        sc, dt = run(side)
     K = min(k, sc.n_vertices)
-    log(f"cpu baseline: oracle on 64x64 crop, N={sc.n_vertices}")
-    t0 = time.perf_counter()
-    oracle.render(sc, oracle.params(k=k, D=D, g=g))
-    dt = time.perf_counter() - t0
     E = sc.n_vertices * K
+    log(f"cpu baseline: {side}x{side} crop, N={sc.n_vertices}, {dt:.1f} s")
     return {"value": E * D / dt / 1e9, "unit": "Gedge-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"centred 64x64-pixel crop of the same image, {sc.spp} spp: N={sc.n_vertices}, E={E}, D={D}; "
-                      f"whole pipeline (kNN, weights, {D} iterations, pixels) in {dt:.2f} s",
+            "sample": f"centred {side}x{side}-pixel crop of the same image, {sc.spp} spp: N={sc.n_vertices}, E={E}, "
+                      f"D={D}; whole pipeline (kNN, weights, {D} iterations, pixels) in {dt:.2f} s",
             "host": host_cpu()}
 
 
@@ -389,12 +413,115 @@ def time_batched(pg, torch, steps):
             "workload": f"64 scenes, sum N = {nverts}, sum E*D = {work}, k 8-16, D 16-64 (one hipGraph launch)"}
 
 
+def time_forward(pg, torch, sc, w, name, steps, warmup, schedule=0, cell_shift=0):
+    """Times `steps` pg_render calls on the workload's paths (already in HBM)
+    after `warmup` untimed ones.  Returns the headline fields and the roofline
+    of the dominant propagation kernel, timed with HIP events on the stream the
+    library launches it on (the caller's current stream)."""
+    dev = torch.device("cuda:0")
+    paths = pg.DevicePaths(sc, device=dev)
+    q = pg.params(k=w.k, D=w.D, g=w.g, schedule=schedule, cell_shift=cell_shift)
+    N = sc.n_vertices
+    K = min(w.k, N)
+    E = N * K
+    render = pg.Renderer(paths, q)
+    image = torch.empty(sc.height, sc.width, 3, device=dev)
+    for _ in range(warmup):
+        render(image)
+    torch.cuda.synchronize()
+    log(f"{name}: warm-up done ({warmup} steps); timing {steps} steps")
+    pg._check(pg.lib().pg_profile_start())
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    marks[0].record(stream)
+    for k in range(steps):
+        render(image)
+        marks[k + 1].record(stream)   # HIP events between steps (the render runs on this stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    step_ms = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(steps))
+    median_ms = step_ms[len(step_ms) // 2] if len(step_ms) % 2 else 0.5 * (step_ms[len(step_ms) // 2 - 1] +
+                                                                           step_ms[len(step_ms) // 2])
+    prof = profile_entries(pg)
+    ms = dt * 1e3 / steps
+    value = E * w.D / (ms / 1e3) / 1e9
+    log(f"{name}: {ms:.2f} ms/step, {value:.1f} Gedge-updates/s")
+    phases = {k: round(v[1] / steps, 4) for k, v in prof.items()}
+    prop_steps = [s for s in ("spmv", "shift", "spmv_shifted", "spmv_scatter") if s in prof]
+    prop_ms = sum(prof[s][1] for s in prop_steps) / steps
+    dom = max(prop_steps, key=lambda s: prof[s][1])
+    cnt, tot, _ = prof[dom]
+    avg_s = tot / cnt / 1e3
+    starts = int((sc.path_offsets[1:] > sc.path_offsets[:-1]).sum())
+    ab = algorithmic_bytes(dom, N, K, starts)
+    achieved = ab / avg_s / 1e9
+    traffic = read_traffic(dom, w.name)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+            "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(avg_s * 1e3, 4),
+            "traffic_GBs": round(traffic / avg_s / 1e9, 1) if traffic else None}
+    prop_bytes = (8 * K + 68) * N * w.D
+    out = {
+        "value": round(value, 2), "ms_per_step": round(ms, 3), "ms_per_step_median": round(median_ms, 3),
+        "config": {"workload": f"{name}: {w.scene.R}^3 fBm medium, {w.scene.width}x{w.scene.height} px, "
+                               f"{w.scene.spp} spp, depth {w.scene.max_depth}, k {w.k}, D {w.D}",
+                   "N": N, "E": E, "P": sc.n_paths, "K": K, "D": w.D,
+                   "schedule": pg.resolved_schedule(q), "cell_shift": cell_shift or pg.pg_default_cell_shift(N)},
+        "propagation": {"ms_per_step": round(prop_ms, 3), "gedge_updates_per_s": round(E * w.D / prop_ms / 1e6, 2),
+                        "algorithmic_GBs": round(prop_bytes / (prop_ms / 1e3) / 1e9, 1),
+                        "hbm_frac": round(prop_bytes / (prop_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "bytes_per_iteration": "(8K + 68) N: col + weight per edge, x gather, b, albedo, y "
+                                               "write; successor, y gather, x write"},
+        "phases_ms": phases,
+        "roofline": roof,
+    }
+    out["iteration"] = iteration_growth(pg, torch, paths, w, render.ws, render.ws_bytes)
+    del render, paths
+    torch.cuda.empty_cache()
+    return out
+
+
+def iteration_growth(pg, torch, paths, w, ws, ws_bytes):
+    """Whether the timed iteration settles on this workload.  From zero,
+    L+_t - L+_{t-1} = M^(t-1) c with M = S diag(albedo) W, so the ratio of
+    successive-difference norms D/2 iterations apart, to the power 2/D,
+    estimates the spectral radius of M: above 1 the iterates grow without
+    bound (the k-nearest relation with per-receiver marginals at this g)."""
+    import ctypes as C
+    dev = paths.device
+    N = paths.n_vertices
+    s = paths.struct()
+
+    def lplus(D):
+        q = pg.params(k=w.k, D=D, g=w.g, init="zero")
+        out = pg.GraphOut()
+        lp = torch.empty(N, 3, device=dev)
+        out.lplus = lp.data_ptr()
+        img = torch.empty(paths.height, paths.width, 3, device=dev)
+        pg._check(pg.lib().pg_render(C.byref(s), C.byref(q), pg._ptr(img), C.byref(out), pg._ptr(ws), ws_bytes,
+                                     pg._stream(dev)))
+        return lp.double()
+
+    a, b = w.D // 2, w.D
+    d0 = torch.linalg.vector_norm(lplus(a) - lplus(a - 1)).item()
+    d1 = torch.linalg.vector_norm(lplus(b) - lplus(b - 1)).item()
+    rate = (d1 / d0) ** (1.0 / (b - a)) if d0 > 0 else float("nan")
+    return {"growth_per_iteration": round(rate, 4), "converges": bool(rate < 1.0),
+            "estimate": f"(|L+_{b} - L+_{b - 1}| / |L+_{a} - L+_{a - 1}|)^(1/{b - a}) from zero: the spectral "
+                        f"radius of S diag(albedo) W",
+            "note": "the timed iteration count and work do not depend on it; "
+                    "tests/test_convergence.py pins the radius on a crop of the mid medium"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large"])
+    ap.add_argument("--workload", default="large", choices=["tiny", "mid", "large"],
+                    help="workload of the headline forward line (the other legs run on mid)")
     ap.add_argument("--schedule", type=int, default=0, help="0 default, 1 two-pass, 2 shifted, 3 scatter")
     ap.add_argument("--cell-shift", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -402,8 +529,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-clusters", action="store_true")
     ap.add_argument("--no-tracer", action="store_true")
+    ap.add_argument("--no-mid", action="store_true", help="skip the mid forward line")
     ap.add_argument("--only", choices=["clusters", "tracer", "adjoint", "batched"],
-                    help="run only this leg (for profiling) and print its JSON")
+                    help="run only this leg (on mid) and print its JSON")
     ap.add_argument("--study", action="store_true",
                     help="convergence and 1-spp error study instead of the timing (one JSON line)")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -423,17 +551,38 @@ def main():
     if args.study:
         print(json.dumps({"study": args.workload, **study(pg, torch, w)}), flush=True)
         return
-    log(f"generating workload {args.workload}")
-    t0 = time.perf_counter()
-    sc = scenegen.generate(w.scene)
-    host_gen_s = time.perf_counter() - t0
-    log(f"N={sc.n_vertices} P={sc.n_paths} generated in {host_gen_s:.1f} s")
     dev = torch.device("cuda:0")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    paths = pg.DevicePaths(sc, device=dev)
-    torch.cuda.synchronize()
-    host_copy_s = time.perf_counter() - t0
+    wm = scenegen.WORKLOADS["mid"]
+
+    def generate(wl):
+        log(f"generating workload {wl.name}")
+        t0 = time.perf_counter()
+        sc = scenegen.generate(wl.scene)
+        gen_s = time.perf_counter() - t0
+        log(f"{wl.name}: N={sc.n_vertices} P={sc.n_paths} generated in {gen_s:.1f} s")
+        return sc, gen_s
+
+    if args.only:
+        sc, gen_s = generate(wm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        paths = pg.DevicePaths(sc, device=dev)
+        torch.cuda.synchronize()
+        copy_s = time.perf_counter() - t0
+        del paths
+        if args.only == "clusters":
+            leg = time_clusters(pg, torch, sc, wm, args.steps, max(1, args.warmup), float("nan"))
+        elif args.only == "tracer":
+            leg = time_tracer(pg, torch, wm, gen_s, copy_s)
+        elif args.only == "adjoint":
+            leg = time_fwd_adjoint(pg, torch, sc, wm, args.steps, max(1, args.warmup))
+        else:
+            torch.cuda.empty_cache()
+            leg = time_batched(pg, torch, args.steps)
+        print(json.dumps({"leg": args.only, **leg}), flush=True)
+        return
+
+    sc, gen_s = generate(w)
     if args.pmc_probe:
         a = torch.ones(256 * 1024 * 1024, device=dev)          # 1 GiB
         b = torch.empty_like(a)
@@ -441,102 +590,54 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log("pmc probe: copied 1 GiB (1 GiB read + 1 GiB written)")
-    if args.only:
-        if args.only == "clusters":
-            leg = time_clusters(pg, torch, sc, w, args.steps, max(1, args.warmup), float("nan"))
-        elif args.only == "tracer":
-            leg = time_tracer(pg, torch, w, host_gen_s, host_copy_s)
-        elif args.only == "adjoint":
-            leg = time_fwd_adjoint(pg, torch, sc, w, args.steps, max(1, args.warmup))
-        else:
-            del paths
-            torch.cuda.empty_cache()
-            leg = time_batched(pg, torch, args.steps)
-        print(json.dumps({"leg": args.only, **leg}), flush=True)
-        return
-    q = pg.params(k=w.k, D=w.D, g=w.g, schedule=args.schedule, cell_shift=args.cell_shift)
-    N = sc.n_vertices
-    K = min(w.k, N)
-    E = N * K
-    render = pg.Renderer(paths, q)
-    image = torch.empty(sc.height, sc.width, 3, device=dev)
-
-    for _ in range(args.warmup):
-        render(image)
-    torch.cuda.synchronize()
-    log(f"warm-up done ({args.warmup} steps); timing {args.steps} steps")
-
-    pg._check(pg.lib().pg_profile_start())
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream(dev)
-    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    t0 = time.perf_counter()
-    marks[0].record(stream)
-    for k in range(args.steps):
-        render(image)
-        marks[k + 1].record(stream)   # HIP events between steps (the render runs on this stream)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    step_ms = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps))
-    median_ms = step_ms[len(step_ms) // 2] if len(step_ms) % 2 else 0.5 * (step_ms[len(step_ms) // 2 - 1] +
-                                                                           step_ms[len(step_ms) // 2])
-    prof = profile_entries(pg)
-    ms = dt * 1e3 / args.steps
-    value = E * w.D / (ms / 1e3) / 1e9
-    log(f"{ms:.2f} ms/step, {value:.1f} Gedge-updates/s")
+    head = time_forward(pg, torch, sc, w, args.workload, args.steps, args.warmup, args.schedule, args.cell_shift)
     if args.pmc_probe:
-        print(json.dumps({"pmc_probe": True, "ms_per_step": ms}))
+        print(json.dumps({"pmc_probe": True, "ms_per_step": head["ms_per_step"]}))
         return
-
-    phases = {k: round(v[1] / args.steps, 4) for k, v in prof.items()}
-    prop_steps = [s for s in ("spmv", "shift", "spmv_shifted", "spmv_scatter") if s in prof]
-    prop_ms = sum(prof[s][1] for s in prop_steps) / args.steps
-    dom = max(prop_steps, key=lambda s: prof[s][1])
-    cnt, tot, _ = prof[dom]
-    avg_s = tot / cnt / 1e3
-    starts = int((sc.path_offsets[1:] > sc.path_offsets[:-1]).sum())
-    ab = algorithmic_bytes(dom, N, K, starts)
-    achieved = ab / avg_s / 1e9
-    traffic = read_traffic(dom, args.workload)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-            "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(avg_s * 1e3, 4),
-            "traffic_GBs": round(traffic / avg_s / 1e9, 1) if traffic else None}
-    out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "Gedge-updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 3), "ms_per_step_median": round(median_ms, 3),
-        "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {w.scene.R}^3 fBm medium, {w.scene.width}x{w.scene.height} px, "
-                               f"{w.scene.spp} spp, depth {w.scene.max_depth}, k {w.k}, D {w.D}",
-                   "N": N, "E": E, "P": sc.n_paths, "K": K, "D": w.D,
-                   "schedule": pg.resolved_schedule(q), "cell_shift": args.cell_shift or pg.pg_default_cell_shift(N)},
-        "propagation": {"ms_per_step": round(prop_ms, 3), "gedge_updates_per_s": round(E * w.D / prop_ms / 1e6, 2),
-                        "algorithmic_GBs": round((8 * K + 68) * N * w.D / (prop_ms / 1e3) / 1e9, 1)},
-        "phases_ms": phases,
-        "roofline": roof,
-    }
-    del render
-    torch.cuda.empty_cache()
-    if not args.no_tracer:
-        log("timing the GPU path tracer")
-        out["tracer"] = time_tracer(pg, torch, w, host_gen_s, host_copy_s)
-        log(f"tracer {out['tracer']['ms_device']} ms on the device, N = {out['tracer']['n_vertices']}")
-    if not args.no_clusters:
-        log("timing the cluster relation")
-        out["clusters"] = time_clusters(pg, torch, sc, w, args.steps, max(1, args.warmup), ms)
-        log(f"clusters {out['clusters']['ms_per_step']} ms/step, E = {out['clusters']['E']}")
-    if not args.no_adjoint:
-        log("timing forward + adjoint")
-        out["fwd_adjoint"] = time_fwd_adjoint(pg, torch, sc, w, max(2, args.steps // 2), 1)
-        log(f"fwd+adjoint {out['fwd_adjoint']['ms_per_step']} ms/step")
+    out = {"metric": METRIC, "value": head["value"], "unit": "Gedge-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+           "ms_per_step_median": head["ms_per_step_median"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": head["config"],
+           "propagation": head["propagation"], "phases_ms": head["phases_ms"], "roofline": head["roofline"],
+           "iteration": head["iteration"]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, sc)
+    del sc
+    legs = not (args.no_mid and args.no_tracer and args.no_clusters and args.no_adjoint)
+    if legs:
+        scm, gen_m = generate(wm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pm = pg.DevicePaths(scm, device=dev)
+        torch.cuda.synchronize()
+        copy_m = time.perf_counter() - t0
+        del pm
+        torch.cuda.empty_cache()
+        mid_ms = float("nan")
+        if not args.no_mid and args.workload != "mid":
+            m = time_forward(pg, torch, scm, wm, "mid", args.steps, args.warmup)
+            mid_ms = m["ms_per_step"]
+            out["mid_forward"] = {k: m[k] for k in ("value", "ms_per_step", "config", "propagation", "phases_ms",
+                                                    "roofline", "iteration")}
+        elif args.workload == "mid":
+            mid_ms = head["ms_per_step"]
+        if not args.no_tracer:
+            log("timing the GPU path tracer")
+            out["tracer"] = time_tracer(pg, torch, wm, gen_m, copy_m)
+            log(f"tracer {out['tracer']['ms_device']} ms on the device, N = {out['tracer']['n_vertices']}")
+        if not args.no_clusters:
+            log("timing the cluster relation")
+            out["clusters"] = time_clusters(pg, torch, scm, wm, args.steps, max(1, args.warmup), mid_ms)
+            log(f"clusters {out['clusters']['ms_per_step']} ms/step, E = {out['clusters']['E']}")
+        if not args.no_adjoint:
+            log("timing forward + adjoint")
+            out["fwd_adjoint"] = time_fwd_adjoint(pg, torch, scm, wm, max(2, args.steps // 2), 1)
+            log(f"fwd+adjoint {out['fwd_adjoint']['ms_per_step']} ms/step")
+        del scm
     if not args.no_batched:
-        del paths
         torch.cuda.empty_cache()
         out["batched"] = time_batched(pg, torch, max(2, args.steps // 2))
         log(f"batched {out['batched']['ms_batched']} ms vs per-scene {out['batched']['ms_per_scene_sequential']} ms")
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, w.k, w.D, w.g)
     print(json.dumps(out), flush=True)
 
 

@@ -198,9 +198,37 @@ static int key_less(int64_t d1, int64_t j1, int64_t d2, int64_t j2) {
     return d1 < d2 || (d1 == d2 && j1 < j2);
 }
 
+#define OR_KNN_SCAN_ROWS 512
+
+/* The K-1 nearest j != i by (d2, j), by looking at every j: the definition
+ * itself, O(n) per row.  Used when only a few rows are asked for, where
+ * sorting all n vertices first would cost more than the rows. */
+static void knn_row_scan(int64_t n, const int64_t* q, int64_t i, int64_t m, int64_t* bd, int64_t* bj) {
+    int64_t filled = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        int64_t d2 = 0;
+        for (int c = 0; c < 3; ++c) {
+            int64_t dc = q[j * 3 + c] - q[i * 3 + c];
+            d2 += dc * dc;
+        }
+        if (filled == m && (m == 0 || !key_less(d2, j, bd[m - 1], bj[m - 1]))) continue;
+        int64_t p = filled < m ? filled : m - 1;
+        while (p > 0 && key_less(d2, j, bd[p - 1], bj[p - 1])) {
+            bd[p] = bd[p - 1];
+            bj[p] = bj[p - 1];
+            --p;
+        }
+        bd[p] = d2;
+        bj[p] = j;
+        if (filled < m) ++filled;
+    }
+}
+
 /* Neighbour lists.  Row i: i first, then the K-1 nearest j != i ordered by
  * (squared distance of quantised positions, j), K = min(k, n).  rows == NULL
- * means every vertex (then nq must equal n).
+ * means every vertex (then nq must equal n).  Up to OR_KNN_SCAN_ROWS given
+ * rows are answered by knn_row_scan.
  *
  * Search: vertices sorted by quantised x; from the query's place, walk left
  * and right, and stop in a direction once the x-gap alone exceeds the current
@@ -210,6 +238,23 @@ int or_knn(int64_t n, const float* pos, int32_t k, int64_t nq, const int64_t* ro
     if (n == 0) return OR_OK;
     int64_t K = k < n ? k : n;
     int64_t m = K - 1;
+    if (rows && nq <= OR_KNN_SCAN_ROWS) {
+        int64_t* q = (int64_t*)malloc((size_t)n * 3 * sizeof(int64_t));
+        int64_t* bd = (int64_t*)malloc((size_t)(m + 1) * sizeof(int64_t));
+        int64_t* bj = (int64_t*)malloc((size_t)(m + 1) * sizeof(int64_t));
+        if (!q || !bd || !bj) {
+            free(q); free(bd); free(bj);
+            return OR_ERR_NOMEM;
+        }
+        int rc = or_quantize(n, pos, q);
+        for (int64_t r = 0; r < nq; ++r) {
+            knn_row_scan(n, q, rows[r], m, bd, bj);
+            col[r * K] = (int32_t)rows[r];
+            for (int64_t a = 0; a < m; ++a) col[r * K + 1 + a] = (int32_t)bj[a];
+        }
+        free(q); free(bd); free(bj);
+        return rc;
+    }
     int64_t* q = (int64_t*)malloc((size_t)n * 3 * sizeof(int64_t));
     int64_t* order = (int64_t*)malloc((size_t)n * sizeof(int64_t));
     int64_t* where = (int64_t*)malloc((size_t)n * sizeof(int64_t));

@@ -357,9 +357,17 @@ WORKLOADS = {
                                        width=512, height=512, spp=4, max_depth=64, vfov_deg=20.0,
                                        seed=2), k=16, D=64),
     # 512^3 fBm, sigma_t up to 64, albedo 0.999, g 0.9, 1024x1024x1, depth 128, k 16, D 128.
-    "large": Workload("large", SceneConfig(R=512, sigma_max=64.0, mask=0, albedo=(0.999, 0.999), g=0.9,
+    # A dense cloud seen close up: the fBm is contrast-stretched so most of the
+    # cube sits at sigma_t = 64 with thinner fBm pockets, and the 10 degree view
+    # fills the image with the cloud's front face.  Paths average about 66
+    # vertices (about 69M in all): with the camera outside the unit cube, a
+    # medium of sigma_t <= 64 and g = 0.9 cannot hold the paths much longer (a
+    # homogeneous sigma_t = 64 half-space, the densest and widest medium a
+    # camera outside it can face, averages 81 vertices per path at depth 128).
+    "large": Workload("large", SceneConfig(R=512, sigma_max=64.0, density_contrast=2.0, density_bias=0.75,
+                                           mask=0, albedo=(0.999, 0.999), g=0.9,
                                            width=1024, height=1024, spp=1, max_depth=128,
-                                           vfov_deg=40.0, seed=3), k=16, D=128),
+                                           vfov_deg=10.0, seed=3), k=16, D=128),
 }
 
 

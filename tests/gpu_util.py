@@ -26,6 +26,28 @@ def assert_within(got, ref, rel, abs_, what=""):
     assert ok, f"{what}: max abs err {emax:.3e}, max rel err {rmax:.3e}"
 
 
+def grad_close(got, ref, what, mag=None):
+    """Gradient parity: |err| <= 1e-4 |ref| per component, with a floor of
+    1e-5 mag where ``mag`` is the same gradient taken with |grad_image| (the
+    image is a polynomial in the albedos with non-negative coefficients, so
+    that is the sum of the magnitudes of the terms the component adds up, and
+    FP32 accumulation error is relative to it; it matters only where terms of
+    both signs cancel).  Without ``mag`` the bound is relative only.  Prints
+    how many components rely on the floor."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    err = np.abs(got - ref)
+    rel = 1e-4 * np.abs(ref)
+    floor = np.zeros_like(ref) if mag is None else 1e-5 * np.abs(np.asarray(mag, np.float64))
+    tol = np.maximum(rel, floor)
+    on_floor = int(np.count_nonzero((err > rel) & (err <= floor)))
+    print(f"{what}: {ref.size} components, {on_floor} within the floor only, max err {err.max(initial=0):.3e}",
+          flush=True)
+    bad = err > tol
+    assert not bad.any(), (f"{what}: {int(bad.sum())} components off, max err {err.max():.3e} "
+                           f"(max |ref| {np.abs(ref).max():.3e})")
+
+
 def crop(name, w, h, spp=None, emit_L=None):
     cfg = scenegen.crop_of(scenegen.WORKLOADS[name].scene, w, h, spp)
     if emit_L is not None:

@@ -1,7 +1,10 @@
 """GPU reverse mode against the FP64 oracle's gradient (itself pinned to FP64
 central differences), the autograd wrapper, and GPU central differences.
 
-Gradient tolerance: |err| <= 1e-4 |ref| + 1e-4 max|ref| per component.
+Gradient tolerance (tests.gpu_util.grad_close): |err| <= 1e-4 |ref| per
+component; the albedo gradients take a floor of 1e-5 times the same gradient
+of |grad_image| (the summed magnitude of the terms, which bounds the FP32
+accumulation error where terms of both signs cancel); dL/dg has no floor.
 """
 import numpy as np
 import pytest
@@ -10,17 +13,9 @@ import torch
 import oracle
 import scenegen
 import paper_2404_11894_amd as pg
-from tests.gpu_util import crop, synthetic
+from tests.gpu_util import crop, grad_close, synthetic
 
 pytestmark = pytest.mark.gpu
-
-
-def grad_close(got, ref, what):
-    got = np.asarray(got, np.float64)
-    ref = np.asarray(ref, np.float64)
-    tol = 1e-4 * np.abs(ref) + 1e-4 * np.abs(ref).max()
-    err = np.abs(got - ref)
-    assert np.all(err <= tol), f"{what}: max err {err.max():.3e} (max |ref| {np.abs(ref).max():.3e})"
 
 
 def case(sc, R, k, D, g, init="pt", fg=0, seed=5, lo=0.6, hi=0.95):
@@ -32,6 +27,7 @@ def case(sc, R, k, D, g, init="pt", fg=0, seed=5, lo=0.6, hi=0.95):
     target = scenegen.target_image(img.shape, float(img.mean()), seed=4).astype(np.float64)
     gimg = 2.0 * (img - target)                  # d/dI of sum (I - T)^2 at the oracle image
     ref = oracle.backward(sc, op, gimg, grid=grid)
+    ref["mag"] = oracle.backward(sc, op, np.abs(gimg), grid=grid)
     return grid, gimg, ref
 
 
@@ -45,8 +41,8 @@ def test_backward_matches_oracle(init, fg, emit):
     q = pg.params(k=8, D=6, g=0.5, init=init, final_gather=fg, flags=pg.PG_FLAG_CHECK)
     out = pg.pg_backward(paths, q, torch.from_numpy(gimg.astype(np.float32)), grad_albedo=True)
     torch.cuda.synchronize()
-    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid")
-    grad_close(out["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo")
+    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid", ref["mag"]["grad_grid"])
+    grad_close(out["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo", ref["mag"]["grad_alpha"])
     grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
 
 
@@ -63,8 +59,8 @@ def test_backward_with_extra_samples_and_point_light(extra, point):
     q = pg.params(k=8, D=6, g=0.5, flags=pg.PG_FLAG_CHECK)
     out = pg.pg_backward(paths, q, torch.from_numpy(gimg.astype(np.float32)), grad_albedo=True)
     torch.cuda.synchronize()
-    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid")
-    grad_close(out["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo")
+    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid", ref["mag"]["grad_grid"])
+    grad_close(out["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo", ref["mag"]["grad_alpha"])
     grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
 
 
@@ -82,8 +78,8 @@ def test_backward_with_transpose_overflow():
     q = pg.params(k=4, D=5, g=0.6, flags=pg.PG_FLAG_CHECK)
     out = pg.pg_backward(paths, q, torch.from_numpy(gimg.astype(np.float32)), grad_albedo=True)
     torch.cuda.synchronize()
-    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid")
-    grad_close(out["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo")
+    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid", ref["mag"]["grad_grid"])
+    grad_close(out["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo", ref["mag"]["grad_alpha"])
     grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
 
 
@@ -100,11 +96,12 @@ def test_backward_workload_crop_matches_oracle():
     target = scenegen.target_image(img.shape, float(img.mean()), seed=4).astype(np.float64)
     gimg = 2.0 * (img - target)
     ref = oracle.backward(sc, op, gimg, grid=grid)
+    mag = oracle.backward(sc, op, np.abs(gimg), grid=grid)
     paths = pg.DevicePaths(sc, albedo_grid=grid)
     q = pg.params(k=w.k, D=w.D, g=w.g, flags=pg.PG_FLAG_CHECK)
     out = pg.pg_backward(paths, q, torch.from_numpy(gimg.astype(np.float32)))
     torch.cuda.synchronize()
-    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid")
+    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid", mag["grad_grid"])
     grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
 
 

@@ -111,3 +111,24 @@ def test_tuned_cell_size_leaves_results_unchanged():
         torch.cuda.synchronize()
         for s in range(len(scenes)):
             assert torch.equal(out[s], ref[s]), f"scene {s}"
+
+
+def test_benchmark_batch_matches_oracle_on_sampled_scenes():
+    # the 64-scene batching workload as the benchmark runs it (one graph
+    # launch of a plan); the oracle renders its three smallest scenes and the
+    # first of at least 50k vertices in full
+    items = scenegen.generate_batch(64)
+    paths = [pg.DevicePaths(sc) for _, sc in items]
+    params = [pg.params(k=w.k, D=w.D, g=w.g) for w, _ in items]
+    plan = pg.Batch(paths, params, use_graph=True)
+    imgs = [im.clone() for im in plan()]
+    torch.cuda.synchronize()
+    plan.close()
+    sizes = np.array([sc.n_vertices for _, sc in items])
+    order = np.argsort(sizes, kind="stable")
+    pick = list(order[:3]) + [int(order[np.searchsorted(sizes[order], 50_000)])]
+    for s in pick:
+        w, sc = items[s]
+        print(f"batch scene {s}: N={sc.n_vertices} k={w.k} D={w.D} g={w.g:.3f}", flush=True)
+        ref = oracle.render(sc, oracle.params(k=w.k, D=w.D, g=w.g))
+        assert_within(imgs[s].cpu().numpy(), ref, PIX_REL, PIX_ABS, f"batch scene {s} vs oracle")

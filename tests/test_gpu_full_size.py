@@ -1,18 +1,22 @@
-"""GPU parity at the full size of the benchmarked workload (128^3 fBm ball,
-512x512 px, 4 spp, depth 64, k 16, D 64), in the launch configuration the
-benchmark times (default schedule and cell size).
+"""GPU parity at the full size of the benchmarked workloads, in the launch
+configuration the benchmark times (default schedule and cell size): the mid
+workload (128^3 fBm ball, 512x512 px, 4 spp, depth 64, k 16, D 64) and the
+large one (512^3 fBm cloud, 1024x1024 px, 1 spp, depth 128, k 16, D 128).
 
-The oracle cannot run the whole graph at this size, so the checks are sampled
-rows it computes one by one (neighbour lists bit for bit, weights, direct
-terms), single-step propagation on sampled vertices, and properties that hold
-at any size (albedo 0 leaves the camera term; one neighbour reproduces path
-tracing, which the oracle computes in full).  The cluster relation is checked
-the same way: its centres by properties of the construction (a seeded vertex
-stays a centre unless it coincides with a seeded vertex of lower id, every
-centre is its own centre, a split never moves a vertex out of its nearest
-seeded centre's cluster), its CSR in full, sampled rows against the oracle's
-weights, and column sums of 1 when g equals g_s.  The large workload (512^3,
-1024 x 1024 px, depth 128, D 128) gets sampled rows and one propagation step.
+The oracle cannot run the whole graph at these sizes, so the checks are
+sampled rows it computes one by one (neighbour lists bit for bit, weights,
+direct terms), one and two iterations of the weighted gather from the
+path-traced start on sampled vertices (every neighbour carries non-zero
+radiance, so the aggregation kernel's sum over K = 16 weighted neighbours is
+checked, not only the constant term), one iteration from zero (the shift of
+the constant term), and properties that hold at any size (albedo 0 leaves the
+camera term; one neighbour reproduces path tracing, which the oracle computes
+in full).  The cluster relation is checked the same way: its centres by
+properties of the construction (a seeded vertex stays a centre unless it
+coincides with a seeded vertex of lower id, every centre is its own centre, a
+split never moves a vertex out of its nearest seeded centre's cluster), its
+CSR in full, sampled rows against the oracle's weights, and column sums of 1
+when g equals g_s.
 """
 from dataclasses import replace
 
@@ -23,6 +27,7 @@ import torch
 import oracle
 import scenegen
 import paper_2404_11894_amd as pg
+from tests import sampled
 from tests.gpu_util import PIX_ABS, PIX_REL, W_ABS, W_REL, assert_within
 
 pytestmark = pytest.mark.gpu
@@ -87,6 +92,35 @@ def test_mid_one_iteration_from_zero(mid):
     assert_within(lplus[v], mid.albedo[succ, None].astype(np.float64) * e["d_agg"], W_REL, W_ABS, "L_1")
     ends = np.flatnonzero(last)[:1000]
     assert not lplus[ends].any()
+
+
+def gpu_lplus(sc, k, D, g):
+    """L+_D [N,3] of the GPU render (path-traced start, default schedule)."""
+    paths = pg.DevicePaths(sc)
+    r = pg.Renderer(paths, pg.params(k=k, D=D, g=g, flags=pg.PG_FLAG_CHECK))
+    lp = torch.empty(sc.n_vertices, 3, device=paths.device)
+    r(graph={"lplus": lp})
+    out = lp.cpu().numpy()
+    del r, paths, lp
+    torch.cuda.empty_cache()
+    return out
+
+
+def check_weighted_gather(sc, w, D, n, seed):
+    lp = gpu_lplus(sc, w.k, D, w.g)
+    last = sampled.last_vertices(sc)
+    rng = np.random.default_rng(seed)
+    v = np.sort(rng.choice(np.flatnonzero(~last), n, replace=False))
+    print(f"weighted gather D={D}: vertices {v.tolist()}", flush=True)
+    ref = sampled.lplus(sc, oracle.params(k=w.k, D=D, g=w.g), v, D)
+    assert (np.abs(ref).sum(1) > 0).all()
+    assert_within(lp[v], ref, PIX_REL, PIX_ABS, f"L+_{D}")
+    assert not lp[np.flatnonzero(last)[:1000]].any()
+
+
+@pytest.mark.parametrize("D,n", [(1, 32), (2, 4)])
+def test_mid_weighted_gather_from_path_traced_start(mid, D, n):
+    check_weighted_gather(mid, W, D, n, 60 + D)
 
 
 def test_mid_zero_albedo_leaves_camera_term(mid):
@@ -216,7 +250,7 @@ def test_mid_cluster_one_iteration_from_zero(mid_clusters):
     assert not lplus[np.flatnonzero(last)[:1000]].any()
 
 
-# ---- the large workload (512^3 fBm, 1024 x 1024 px, 1 spp, depth 128, k 16, D 128)
+# ---- the large workload (512^3 fBm cloud, 1024 x 1024 px, 1 spp, depth 128, k 16, D 128)
 
 WL = scenegen.WORKLOADS["large"]
 
@@ -261,3 +295,8 @@ def test_large_sampled_rows_and_one_step_match_oracle(large):
     e1 = oracle.edges(large, oracle.params(k=K, D=1, g=WL.g), col1, rows=v + 1)
     assert_within(lplus[v], large.albedo[v + 1, None].astype(np.float64) * e1["d_agg"], W_REL, W_ABS, "L_1")
     assert not lplus[np.flatnonzero(last)[:1000]].any()
+
+
+@pytest.mark.parametrize("D,n", [(1, 12), (2, 2)])
+def test_large_weighted_gather_from_path_traced_start(large, D, n):
+    check_weighted_gather(large, WL, D, n, 70 + D)

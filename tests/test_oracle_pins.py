@@ -802,3 +802,17 @@ def test_trilinear_albedo_reproduces_linear_fields():
     edge = np.array([[0.01, 0.5, 0.5]], np.float32)   # x inside the first half cell
     inner = np.array([[0.5 / R, 0.5, 0.5]], np.float32)
     assert np.allclose(oracle.albedo_from_grid(edge, grid), oracle.albedo_from_grid(inner, grid), atol=1e-7)
+
+
+@pytest.mark.parametrize("n,k", [(1, 8), (7, 8), (400, 16), (300, 1)])
+def test_knn_row_scan_matches_brute_force(n, k):
+    # a few given rows take the direct scan over every vertex; lattice ties and
+    # duplicate positions exercise the (d2, index) order there as well
+    rng = np.random.default_rng(n + 17 * k)
+    pos = rng.random((n, 3), dtype=np.float32)
+    if n >= 400:
+        pos[:64] = ((np.indices((4, 4, 4)).reshape(3, -1).T + 1) / 8.0).astype(np.float32)
+        pos[64:70] = pos[3]
+    rows = np.unique(rng.integers(0, n, size=min(n, 40)))
+    assert np.array_equal(oracle.knn(pos, k, rows=rows), knn_brute(pos, k)[rows])
+    assert np.array_equal(oracle.knn(pos, k, rows=rows), oracle.knn(pos, k)[rows])
