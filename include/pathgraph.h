@@ -316,6 +316,24 @@ pg_status pg_propagate(const pg_paths* paths, const pg_params* params, const int
                        const int32_t* col, const float* w_ind, const float* b, float* lplus, float* traj,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* ---- step 3 without allocation -------------------------------------------
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, serving loops, harnesses that forbid hipMalloc): pg_propagate with
+ * the same arguments, results and errors, but no workspace argument.  Its
+ * workspace is a static device array of PG_STATIC_SCRATCH_BYTES (64 MiB) that
+ * the library holds on every GPU it runs on until the process ends; the call
+ * allocates nothing.  It serves graphs whose pg_propagate_workspace_size is at
+ * most that (20 bytes per vertex plus alignment: N up to about 3.3 million)
+ * and returns PG_ERR_WORKSPACE for larger ones.  The array's address on the
+ * current device (which must be the stream's) is looked up on the first call
+ * there.  Every call on one GPU uses the same array, so calls that overlap in
+ * time on one GPU (other streams, other threads) race and must be serialised
+ * by the caller; each call initialises the parts it reads. */
+#define PG_STATIC_SCRATCH_BYTES (64u << 20)
+pg_status pg_propagate_static(const pg_paths* paths, const pg_params* params, const int64_t* row_ptr,
+                              const int32_t* col, const float* w_ind, const float* b, float* lplus, float* traj,
+                              void* stream);
+
 /* ---- step 4: output to pixels --------------------------------------------
  * Paper Sec. "Rendering System", "Handling direct Light" and "Final output":
  * path p with first vertex v0 outputs

@@ -26,7 +26,7 @@ EXPORTS = ("pg_version", "pg_last_error", "pg_default_cell_shift", "pg_profile_s
            "pg_trace_workspace_size", "pg_trace_count", "pg_trace_records",
            "pg_knn_workspace_size", "pg_knn", "pg_clusters_workspace_size", "pg_clusters",
            "pg_edges_workspace_size", "pg_edges",
-           "pg_propagate_workspace_size", "pg_propagate", "pg_gather",
+           "pg_propagate_workspace_size", "pg_propagate", "pg_propagate_static", "pg_gather",
            "pg_render_workspace_size", "pg_render", "pg_backward_workspace_size", "pg_backward",
            "pg_render_batched_workspace_size", "pg_render_batched", "pg_batch_create", "pg_batch_launch",
            "pg_batch_destroy")
@@ -114,6 +114,7 @@ def lib():
             "pg_edges": (i32, [P, Q, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
             "pg_propagate_workspace_size": (i32, [P, Q, sz]),
             "pg_propagate": (i32, [P, Q, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+            "pg_propagate_static": (i32, [P, Q, vp, vp, vp, vp, vp, vp, vp]),
             "pg_gather": (i32, [P, Q, vp, vp, vp, vp, vp, vp, vp]),
             "pg_render_workspace_size": (i32, [P, Q, sz]),
             "pg_render": (i32, [P, Q, vp, ctypes.POINTER(GraphOut), vp, ctypes.c_size_t, vp]),
@@ -411,6 +412,15 @@ def pg_propagate(paths: DevicePaths, q: Params, row_ptr, col, w_ind, b, lplus, t
     _check(L.pg_propagate(ctypes.byref(s), ctypes.byref(q), _ptr(row_ptr), _ptr(col), _ptr(w_ind), _ptr(b),
                           _ptr(lplus), _ptr(tr), _ptr(ws), n, _stream(paths.device)))
     return (lplus, tr) if traj else lplus
+
+
+def pg_propagate_static(paths: DevicePaths, q: Params, row_ptr, col, w_ind, b, lplus, traj=None):
+    """pg_propagate without a workspace (the library's static device scratch):
+    lplus (L_0, [N,3]) is updated in place to L_D; ``traj``, if given, is a
+    caller tensor [D,N,3] that receives L_1..L_D.  Allocates nothing."""
+    _check(lib().pg_propagate_static(ctypes.byref(paths.struct()), ctypes.byref(q), _ptr(row_ptr), _ptr(col),
+                                     _ptr(w_ind), _ptr(b), _ptr(lplus), _ptr(traj), _stream(paths.device)))
+    return lplus
 
 
 def pg_gather(paths: DevicePaths, q: Params, row_ptr, col, w_ind, d_pt, lplus):

@@ -163,6 +163,50 @@ hipError_t run_grid(const pg_paths* p, GridBufs& g, VRec* rec, hipStream_t s) {
 
 int shift_of(const pg_params* q, int64_t N) { return q && q->cell_shift ? q->cell_shift : default_shift(N); }
 
+size_t propagate_size(const pg_paths* p, const pg_params* q) {
+    const int64_t N = p->n_vertices;
+    (void)q;
+    Carver cv(nullptr);
+    cv.take<int32_t>(64);
+    cv.take<int32_t>(N);      // succ
+    cv.take<float>(N);        // alpha
+    cv.take<float>(3 * N);    // y
+    return cv.size();
+}
+
+pg_status propagate_run(const pg_paths* paths, const pg_params* params, const int64_t* row_ptr, const int32_t* col,
+                        const float* w_ind, const float* b, float* lplus, float* traj, void* ws, size_t ws_bytes,
+                        hipStream_t s) {
+    pg_status st;
+    if ((st = validate_paths(paths, false)) || (st = validate_params(params))) return st;
+    const int64_t N = paths->n_vertices;
+    if (N > 0 && (!row_ptr || !col || !w_ind || !b || !lplus))
+        return fail(PG_ERR_ARG, "row_ptr, col, w_ind, b and lplus are required");
+    if ((st = check_ws(ws, ws_bytes, propagate_size(paths, params)))) return st;
+    const int K = (int)(N < params->k ? N : params->k);
+    Carver cv(ws);
+    int32_t* flag = cv.take<int32_t>(64);
+    int32_t* succ = cv.take<int32_t>(N);
+    float* alpha = cv.take<float>(N);
+    float* y = cv.take<float>(3 * N);
+    hipError_t e;
+    if ((e = launch_fill(flag, 64 * 4, s)) != hipSuccess) return hip_fail(e, "fill");
+    if (N == 0) return finish(s, params, flag, params->flags);
+    if ((e = launch_fill_value(succ, (size_t)N * 4, 0xffffffffu, s)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_paths(paths->n_paths, N, paths->path_offsets, nullptr, nullptr, nullptr, nullptr, nullptr, PG_INIT_ZERO,
+                          succ, nullptr, nullptr, flag, s)) != hipSuccess)
+        return hip_fail(e, "paths");
+    if ((e = launch_alpha(N, *paths, alpha, s)) != hipSuccess) return hip_fail(e, "alpha");
+    for (int t = 1; t <= params->D; ++t) {
+        if ((e = launch_spmv(N, K, col, w_ind, lplus, b, alpha, y, s)) != hipSuccess) return hip_fail(e, "spmv");
+        if ((e = launch_shift(N, succ, y, lplus, s)) != hipSuccess) return hip_fail(e, "shift");
+        if (traj && (e = hipMemcpyAsync(traj + (size_t)(t - 1) * N * 3, lplus, (size_t)N * 12,
+                                        hipMemcpyDeviceToDevice, s)) != hipSuccess)
+            return hip_fail(e, "hipMemcpyAsync");
+    }
+    return finish(s, params, flag, params->flags);
+}
+
 }  // namespace pg
 
 using namespace pg;
@@ -414,17 +458,6 @@ pg_status pg_edges(const pg_paths* paths, const pg_params* params, const int64_t
 
 // ------------------------------------------------------------ propagate ---
 
-static size_t propagate_size(const pg_paths* p, const pg_params* q) {
-    const int64_t N = p->n_vertices;
-    (void)q;
-    Carver cv(nullptr);
-    cv.take<int32_t>(64);
-    cv.take<int32_t>(N);      // succ
-    cv.take<float>(N);        // alpha
-    cv.take<float>(3 * N);    // y
-    return cv.size();
-}
-
 pg_status pg_propagate_workspace_size(const pg_paths* paths, const pg_params* params, size_t* bytes) {
     g_error.clear();
     pg_status st;
@@ -438,35 +471,7 @@ pg_status pg_propagate(const pg_paths* paths, const pg_params* params, const int
                        const float* w_ind, const float* b, float* lplus, float* traj, void* ws, size_t ws_bytes,
                        void* stream) {
     g_error.clear();
-    pg_status st;
-    if ((st = validate_paths(paths, false)) || (st = validate_params(params))) return st;
-    const int64_t N = paths->n_vertices;
-    if (N > 0 && (!row_ptr || !col || !w_ind || !b || !lplus))
-        return fail(PG_ERR_ARG, "row_ptr, col, w_ind, b and lplus are required");
-    if ((st = check_ws(ws, ws_bytes, propagate_size(paths, params)))) return st;
-    const int K = (int)(N < params->k ? N : params->k);
-    hipStream_t s = (hipStream_t)stream;
-    Carver cv(ws);
-    int32_t* flag = cv.take<int32_t>(64);
-    int32_t* succ = cv.take<int32_t>(N);
-    float* alpha = cv.take<float>(N);
-    float* y = cv.take<float>(3 * N);
-    hipError_t e;
-    if ((e = launch_fill(flag, 64 * 4, s)) != hipSuccess) return hip_fail(e, "fill");
-    if (N == 0) return finish(s, params, flag, params->flags);
-    if ((e = launch_fill_value(succ, (size_t)N * 4, 0xffffffffu, s)) != hipSuccess) return hip_fail(e, "fill");
-    if ((e = launch_paths(paths->n_paths, N, paths->path_offsets, nullptr, nullptr, nullptr, nullptr, nullptr, PG_INIT_ZERO,
-                          succ, nullptr, nullptr, flag, s)) != hipSuccess)
-        return hip_fail(e, "paths");
-    if ((e = launch_alpha(N, *paths, alpha, s)) != hipSuccess) return hip_fail(e, "alpha");
-    for (int t = 1; t <= params->D; ++t) {
-        if ((e = launch_spmv(N, K, col, w_ind, lplus, b, alpha, y, s)) != hipSuccess) return hip_fail(e, "spmv");
-        if ((e = launch_shift(N, succ, y, lplus, s)) != hipSuccess) return hip_fail(e, "shift");
-        if (traj && (e = hipMemcpyAsync(traj + (size_t)(t - 1) * N * 3, lplus, (size_t)N * 12,
-                                        hipMemcpyDeviceToDevice, s)) != hipSuccess)
-            return hip_fail(e, "hipMemcpyAsync");
-    }
-    return finish(s, params, flag, params->flags);
+    return propagate_run(paths, params, row_ptr, col, w_ind, b, lplus, traj, ws, ws_bytes, (hipStream_t)stream);
 }
 
 // --------------------------------------------------------------- gather ---

@@ -36,6 +36,12 @@ pg_status finish(hipStream_t s, const pg_params* q, const int32_t* dflag, uint32
 Consts make_consts(const pg_params* q, int K);
 int32_t default_shift(int64_t N);
 int shift_of(const pg_params* q, int64_t N);
+// pg_propagate after g_error is cleared: validation, the workspace check
+// against propagate_size, and the launches (shared with pg_propagate_static).
+size_t propagate_size(const pg_paths* p, const pg_params* q);
+pg_status propagate_run(const pg_paths* paths, const pg_params* params, const int64_t* row_ptr, const int32_t* col,
+                        const float* w_ind, const float* b, float* lplus, float* traj, void* ws, size_t ws_bytes,
+                        hipStream_t s);
 
 // Brackets one kernel step with HIP events on its stream while profiling is on.
 struct ProfScope {

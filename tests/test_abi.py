@@ -238,3 +238,18 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_static_propagate_rejects_graphs_beyond_its_scratch_on_the_host():
+    # 4M vertices need 80 MB of propagation workspace, more than the 64 MiB
+    # static scratch: refused before any device call
+    L = pg.lib()
+    s, q = fake_paths(N=4_000_000, P=16), pg.params(k=8, D=4)
+    nb = ctypes.c_size_t()
+    assert L.pg_propagate_workspace_size(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == 0
+    assert nb.value > 64 << 20
+    p = ctypes.c_void_p(0x1000)
+    rc, msg = status(L.pg_propagate_static, ctypes.byref(s), ctypes.byref(q), p, p, p, p, p, None, None)
+    assert rc == pg.PG_ERR_WORKSPACE and "static scratch" in msg
+    rc, msg = status(L.pg_propagate_static, ctypes.byref(s), None, p, p, p, p, p, None, None)
+    assert rc == pg.PG_ERR_ARG
