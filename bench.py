@@ -413,7 +413,7 @@ def time_batched(pg, torch, steps):
             "workload": f"64 scenes, sum N = {nverts}, sum E*D = {work}, k 8-16, D 16-64 (one hipGraph launch)"}
 
 
-def time_forward(pg, torch, sc, w, name, steps, warmup, schedule=0, cell_shift=0):
+def time_forward(pg, torch, sc, w, name, steps, warmup, schedule=0, cell_shift=0, growth=True):
     """Times `steps` pg_render calls on the workload's paths (already in HBM)
     after `warmup` untimed ones.  Returns the headline fields and the roofline
     of the dominant propagation kernel, timed with HIP events on the stream the
@@ -477,7 +477,8 @@ def time_forward(pg, torch, sc, w, name, steps, warmup, schedule=0, cell_shift=0
         "phases_ms": phases,
         "roofline": roof,
     }
-    out["iteration"] = iteration_growth(pg, torch, paths, w, render.ws, render.ws_bytes)
+    if growth:
+        out["iteration"] = iteration_growth(pg, torch, paths, w, render.ws, render.ws_bytes)
     del render, paths
     torch.cuda.empty_cache()
     return out
@@ -530,6 +531,7 @@ def main():
     ap.add_argument("--no-clusters", action="store_true")
     ap.add_argument("--no-tracer", action="store_true")
     ap.add_argument("--no-mid", action="store_true", help="skip the mid forward line")
+    ap.add_argument("--no-growth", action="store_true", help="skip the iteration-growth estimate (for profiling)")
     ap.add_argument("--only", choices=["clusters", "tracer", "adjoint", "batched"],
                     help="run only this leg (on mid) and print its JSON")
     ap.add_argument("--study", action="store_true",
@@ -590,7 +592,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log("pmc probe: copied 1 GiB (1 GiB read + 1 GiB written)")
-    head = time_forward(pg, torch, sc, w, args.workload, args.steps, args.warmup, args.schedule, args.cell_shift)
+    head = time_forward(pg, torch, sc, w, args.workload, args.steps, args.warmup, args.schedule, args.cell_shift,
+                        growth=not (args.pmc_probe or args.no_growth))
     if args.pmc_probe:
         print(json.dumps({"pmc_probe": True, "ms_per_step": head["ms_per_step"]}))
         return
@@ -599,7 +602,7 @@ def main():
            "ms_per_step_median": head["ms_per_step_median"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": head["config"],
            "propagation": head["propagation"], "phases_ms": head["phases_ms"], "roofline": head["roofline"],
-           "iteration": head["iteration"]}
+           "iteration": head.get("iteration")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, sc)
     del sc
