@@ -27,21 +27,35 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_DIR = os.path.join(_HERE, "_lib")
-_LIB_PATH = os.path.join(_LIB_DIR, "liboracle.so")
+_SANITIZE = os.environ.get("PG_SANITIZE") == "1"
+_LIB_PATH = os.path.join(_LIB_DIR, "liboracle_san.so" if _SANITIZE else "liboracle.so")
 _SRC = os.path.join(_HERE, "pg_oracle.c")
+# AddressSanitizer + UndefinedBehaviorSanitizer build (PG_SANITIZE=1): clang,
+# so that one sanitizer runtime serves the oracle, the generator and the host
+# side of the HIP library in one process.
+CLANG = "/opt/rocm/llvm/bin/clang"
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+             "-g", "-O1", "-shared-libsan"]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile pg_oracle.c into oracle/_lib/liboracle.so (gcc, no fast-math)."""
+def build(verbose: bool = False, sanitize: bool | None = None) -> str:
+    """Compile pg_oracle.c into oracle/_lib/liboracle.so (gcc, no fast-math);
+    with ``sanitize`` (default: PG_SANITIZE=1 in the environment) an
+    ASan + UBSan build with clang, liboracle_san.so."""
+    sanitize = _SANITIZE if sanitize is None else sanitize
     os.makedirs(_LIB_DIR, exist_ok=True)
-    tmp = _LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-shared", "-fPIC", "-ffp-contract=off", "-Wall", "-Wextra",
-           _SRC, "-lm", "-o", tmp]
+    out = os.path.join(_LIB_DIR, "liboracle_san.so" if sanitize else "liboracle.so")
+    tmp = out + ".tmp"
+    if sanitize:
+        cmd = [CLANG, *SAN_FLAGS, "-shared", "-fPIC", "-ffp-contract=off", "-Wall", "-Wextra", _SRC, "-lm",
+               "-o", tmp]
+    else:
+        cmd = ["gcc", "-O2", "-shared", "-fPIC", "-ffp-contract=off", "-Wall", "-Wextra", _SRC, "-lm", "-o", tmp]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 class _Scene(ctypes.Structure):

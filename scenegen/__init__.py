@@ -34,21 +34,33 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_DIR = os.path.join(_HERE, "_lib")
-_LIB_PATH = os.path.join(_LIB_DIR, "libscenegen.so")
+_SANITIZE = os.environ.get("PG_SANITIZE") == "1"
+_LIB_PATH = os.path.join(_LIB_DIR, "libscenegen_san.so" if _SANITIZE else "libscenegen.so")
 _SRC = os.path.join(_HERE, "scenegen.c")
+_CLANG = "/opt/rocm/llvm/bin/clang"
+_SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+              "-g", "-O1", "-shared-libsan"]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the generator into scenegen/_lib/libscenegen.so (gcc, OpenMP)."""
+def build(verbose: bool = False, sanitize: bool | None = None) -> str:
+    """Compile the generator into scenegen/_lib/libscenegen.so (gcc, OpenMP);
+    with ``sanitize`` (default: PG_SANITIZE=1 in the environment) an
+    ASan + UBSan build with clang and its OpenMP runtime, libscenegen_san.so."""
+    sanitize = _SANITIZE if sanitize is None else sanitize
     os.makedirs(_LIB_DIR, exist_ok=True)
-    tmp = _LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-ffp-contract=off",
-           "-Wall", "-Wextra", _SRC, "-lm", "-o", tmp]
+    out = os.path.join(_LIB_DIR, "libscenegen_san.so" if sanitize else "libscenegen.so")
+    tmp = out + ".tmp"
+    if sanitize:
+        cmd = [_CLANG, *_SAN_FLAGS, "-fopenmp", "-shared", "-fPIC", "-ffp-contract=off", "-Wall", "-Wextra", _SRC,
+               "-lm", "-Wl,-rpath,/opt/rocm/llvm/lib", "-o", tmp]
+    else:
+        cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-ffp-contract=off",
+               "-Wall", "-Wextra", _SRC, "-lm", "-o", tmp]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 class _Config(ctypes.Structure):
