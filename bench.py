@@ -40,14 +40,21 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(step, N, K, starts):
+def algorithmic_bytes(step, N, K, starts, n_far=None):
     """Compulsory HBM bytes of one launch of a propagation step (every input
     read once, every output written once):
-      spmv / spmv_shifted: col + weight per edge (8 B), one x gather, b (or c)
-      and albedo or row mask per row, one y write: N (8K + 12 + 12 + 4 + 12)
+      spmv with the compact ids (n_far given): per row the 16-bit ids and the
+      weights (2K + 4K), one x gather, b, albedo, one y write (12 + 12 + 4 +
+      12), plus 4 bytes per far id read from the side list and one 4-byte
+      list start per 64-row slice: N (6K + 40) + 4 n_far + 4 (N/64 + 1)
+      spmv / spmv_shifted with 32-bit ids: col + weight per edge (8 B), one x
+      gather, b (or c) and albedo or row mask per row, one y write:
+      N (8K + 12 + 12 + 4 + 12)
       spmv_scatter: the same plus the predecessor id, for the N - starts rows
       that have a predecessor; a path's first vertex reads only that id
       shift: successor id, one y gather, one x write: N (4 + 12 + 12)."""
+    if step == "spmv" and n_far is not None:
+        return N * (6 * K + 40) + 4 * n_far + 4 * (-(-N // 64) + 1)
     if step in ("spmv", "spmv_shifted"):
         return N * (8 * K + 40)
     if step == "spmv_scatter":
@@ -93,11 +100,13 @@ def profile_entries(pg):
     return {arr[i].name.decode(): (arr[i].count, arr[i].total_ms, arr[i].max_ms) for i in range(min(n.value, 64))}
 
 
-def cpu_baseline(workload, sc_full, seconds=15.0):
+def cpu_baseline(workload, sc_full, seconds=10.0):
     """The FP64 oracle, single-threaded, on a centred square crop of the same
-    workload (all its samples per pixel): the whole pipeline.  A pilot crop of
-    about 1e8 edge-updates (E D) measures the oracle's rate on this workload;
-    the timed crop is then sized for about `seconds` of oracle time."""
+    workload (all its samples per pixel): the whole pipeline.  The crop starts
+    at about 1e8 edge-updates (E D) and its work doubles until one run takes
+    at least `seconds` (the oracle slows per edge as its arrays outgrow the
+    host caches, so the size is found by measuring, not extrapolated); the
+    last run is reported."""
     import oracle
     import scenegen
     k, D, g = workload.k, workload.D, workload.g
@@ -106,22 +115,19 @@ def cpu_baseline(workload, sc_full, seconds=15.0):
     def side_for(work):
         return int(max(8, min(sc_full.width, round((work / (k * D * per_px)) ** 0.5 / 8) * 8)))
 
-    def run(side):
+    work = 1e8
+    while True:
+        side = side_for(work)
         sc = scenegen.generate(scenegen.crop_of(workload.scene, side, side))
         t0 = time.perf_counter()
         oracle.render(sc, oracle.params(k=k, D=D, g=g))
-        return sc, time.perf_counter() - t0
-
-    side = side_for(1e8)
-    sc, dt = run(side)
-    rate = sc.n_vertices * min(k, sc.n_vertices) * D / dt
-    if dt < 0.5 * seconds:
-        side = side_for(rate * seconds)
-        log(f"cpu baseline: pilot {dt:.1f} s; oracle on a {side}x{side} crop")
-        sc, dt = run(side)
+        dt = time.perf_counter() - t0
+        log(f"cpu baseline: {side}x{side} crop, N={sc.n_vertices}, {dt:.1f} s")
+        if dt >= seconds or side >= sc_full.width:
+            break
+        work *= 2
     K = min(k, sc.n_vertices)
     E = sc.n_vertices * K
-    log(f"cpu baseline: {side}x{side} crop, N={sc.n_vertices}, {dt:.1f} s")
     return {"value": E * D / dt / 1e9, "unit": "Gedge-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"centred {side}x{side}-pixel crop of the same image, {sc.spp} spp: N={sc.n_vertices}, E={E}, "
                       f"D={D}; whole pipeline (kNN, weights, {D} iterations, pixels) in {dt:.2f} s",
@@ -370,9 +376,10 @@ def study(pg, torch, w):
     return res
 
 
-def time_batched(pg, torch, steps):
-    """64 independent scenes: one hipGraph launch of a batch plan vs 64
-    sequential pg_render calls.  Counts sum_s E_s D_s."""
+def time_batched(pg, torch, steps, tune=True):
+    """64 independent scenes: one hipGraph launch of a batch plan (each
+    scene's cell size and the batch's edge tile from the autotuner) vs 64
+    sequential pg_render calls (library defaults).  Counts sum_s E_s D_s."""
     import scenegen
     dev = torch.device("cuda:0")
     log("generating the 64-scene batch")
@@ -391,7 +398,9 @@ def time_batched(pg, torch, steps):
         for r, im in zip(rends, imgs):
             r(im)
 
-    plan = pg.Batch(paths, params, use_graph=True)
+    t0 = time.perf_counter()
+    plan = pg.Batch(paths, params, use_graph=True, tune=tune)
+    tune_s = time.perf_counter() - t0
     for f in (per_scene, plan):
         f()
     torch.cuda.synchronize()
@@ -403,6 +412,7 @@ def time_batched(pg, torch, steps):
         torch.cuda.synchronize()
         res[name] = (time.perf_counter() - t0) * 1e3 / steps
     same = all(torch.equal(a, b) for a, b in zip(imgs, plan.images))
+    tuned = plan.tuned
     plan.close()
     del rends, plan
     torch.cuda.empty_cache()
@@ -410,17 +420,35 @@ def time_batched(pg, torch, steps):
             "ms_batched": round(res["batched"], 3), "ms_per_scene_sequential": round(res["per_scene"], 3),
             "speedup": round(res["per_scene"] / res["batched"], 3),
             "per_scene_value": round(work / (res["per_scene"] / 1e3) / 1e9, 2), "images_equal": same,
+            "autotuned": None if tuned is None else {"tile": tuned["tile"], "tile_group": tuned["tile_group"],
+                                                     "cell_shift_vs_default": sum(
+                                                         1 for sh, p in zip(tuned["cell_shift"], paths)
+                                                         if p.n_vertices and sh != pg.pg_default_cell_shift(
+                                                             p.n_vertices)),
+                                                     "plan_build_s_with_tuning": round(tune_s, 2)},
             "workload": f"64 scenes, sum N = {nverts}, sum E*D = {work}, k 8-16, D 16-64 (one hipGraph launch)"}
 
 
-def time_forward(pg, torch, sc, w, name, steps, warmup, schedule=0, cell_shift=0, growth=True):
+def time_forward(pg, torch, sc, w, name, steps, warmup, schedule=0, cell_shift=0, growth=True, tile=0, tile_group=0,
+                 tune=False):
     """Times `steps` pg_render calls on the workload's paths (already in HBM)
     after `warmup` untimed ones.  Returns the headline fields and the roofline
     of the dominant propagation kernel, timed with HIP events on the stream the
     library launches it on (the caller's current stream)."""
     dev = torch.device("cuda:0")
     paths = pg.DevicePaths(sc, device=dev)
-    q = pg.params(k=w.k, D=w.D, g=w.g, schedule=schedule, cell_shift=cell_shift)
+    tuned = None
+    if tune:   # the autotuner's cell size and edge tile (results unchanged); explicit flags win
+        from paper_2404_11894_amd import autotune
+        t0 = time.perf_counter()
+        tuned = autotune.tune(paths, w.k, w.g)
+        torch.cuda.synchronize()
+        tuned["tune_s"] = round(time.perf_counter() - t0, 2)
+        log(f"{name}: autotuned {tuned}")
+        cell_shift = cell_shift or tuned["cell_shift"]
+        tile = tile or tuned["tile"]
+        tile_group = tile_group or tuned["tile_group"]
+    q = pg.params(k=w.k, D=w.D, g=w.g, schedule=schedule, cell_shift=cell_shift, tile=tile, tile_group=tile_group)
     N = sc.n_vertices
     K = min(w.k, N)
     E = N * K
@@ -455,25 +483,37 @@ def time_forward(pg, torch, sc, w, name, steps, warmup, schedule=0, cell_shift=0
     cnt, tot, _ = prof[dom]
     avg_s = tot / cnt / 1e3
     starts = int((sc.path_offsets[1:] > sc.path_offsets[:-1]).sum())
-    ab = algorithmic_bytes(dom, N, K, starts)
+    nf = torch.zeros(1, dtype=torch.int64, device=dev)
+    render(image, graph={"n_far": nf})
+    n_far = int(nf.item()) if dom == "spmv" and pg.resolved_schedule(q) == "two-pass" else None
+    ab = algorithmic_bytes(dom, N, K, starts, n_far)
     achieved = ab / avg_s / 1e9
     traffic = read_traffic(dom, w.name)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
             "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(avg_s * 1e3, 4),
             "traffic_GBs": round(traffic / avg_s / 1e9, 1) if traffic else None}
+    if n_far is not None:
+        roof["ids"] = {"format": "16-bit offsets from the row, far ids from a side list", "n_far": n_far,
+                       "far_fraction": round(n_far / max(1, N * (K - 1)), 4),
+                       "canonical_GBs": round(N * (8 * K + 40) / avg_s / 1e9, 1),
+                       "note": "canonical_GBs: the same launch time against the 32-bit-id bytes N (8K + 40)"}
     prop_bytes = (8 * K + 68) * N * w.D
+    fmt_bytes = None if n_far is None else (algorithmic_bytes("spmv", N, K, starts, n_far) + 28 * N) * w.D
     out = {
         "value": round(value, 2), "ms_per_step": round(ms, 3), "ms_per_step_median": round(median_ms, 3),
         "config": {"workload": f"{name}: {w.scene.R}^3 fBm medium, {w.scene.width}x{w.scene.height} px, "
                                f"{w.scene.spp} spp, depth {w.scene.max_depth}, k {w.k}, D {w.D}",
                    "N": N, "E": E, "P": sc.n_paths, "K": K, "D": w.D,
-                   "schedule": pg.resolved_schedule(q), "cell_shift": cell_shift or pg.pg_default_cell_shift(N)},
+                   "schedule": pg.resolved_schedule(q), "cell_shift": cell_shift or pg.pg_default_cell_shift(N),
+                   "tile": tile or 256, "tile_group": tile_group or 1, "autotuned": tuned},
         "propagation": {"ms_per_step": round(prop_ms, 3), "gedge_updates_per_s": round(E * w.D / prop_ms / 1e6, 2),
                         "algorithmic_GBs": round(prop_bytes / (prop_ms / 1e3) / 1e9, 1),
                         "hbm_frac": round(prop_bytes / (prop_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                         "bytes_per_iteration": "(8K + 68) N: col + weight per edge, x gather, b, albedo, y "
-                                               "write; successor, y gather, x write"},
+                                               "write; successor, y gather, x write",
+                        "hbm_frac_own_format": None if fmt_bytes is None else
+                        round(fmt_bytes / (prop_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "phases_ms": phases,
         "roofline": roof,
     }
@@ -525,6 +565,10 @@ def main():
                     help="workload of the headline forward line (the other legs run on mid)")
     ap.add_argument("--schedule", type=int, default=0, help="0 default, 1 two-pass, 2 shifted, 3 scatter")
     ap.add_argument("--cell-shift", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0, help="workgroup size of the propagation kernels (0 = 256)")
+    ap.add_argument("--tile-group", type=int, default=0, help="consecutive row tiles per XCD in the aggregation")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="library defaults instead of the autotuner's cell size and edge tile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -580,7 +624,7 @@ def main():
             leg = time_fwd_adjoint(pg, torch, sc, wm, args.steps, max(1, args.warmup))
         else:
             torch.cuda.empty_cache()
-            leg = time_batched(pg, torch, args.steps)
+            leg = time_batched(pg, torch, args.steps, tune=not args.no_autotune)
         print(json.dumps({"leg": args.only, **leg}), flush=True)
         return
 
@@ -593,7 +637,8 @@ def main():
         del a, b
         log("pmc probe: copied 1 GiB (1 GiB read + 1 GiB written)")
     head = time_forward(pg, torch, sc, w, args.workload, args.steps, args.warmup, args.schedule, args.cell_shift,
-                        growth=not (args.pmc_probe or args.no_growth))
+                        growth=not (args.pmc_probe or args.no_growth), tile=args.tile, tile_group=args.tile_group,
+                        tune=not args.no_autotune)
     if args.pmc_probe:
         print(json.dumps({"pmc_probe": True, "ms_per_step": head["ms_per_step"]}))
         return
@@ -618,7 +663,7 @@ def main():
         torch.cuda.empty_cache()
         mid_ms = float("nan")
         if not args.no_mid and args.workload != "mid":
-            m = time_forward(pg, torch, scm, wm, "mid", args.steps, args.warmup)
+            m = time_forward(pg, torch, scm, wm, "mid", args.steps, args.warmup, tune=not args.no_autotune)
             mid_ms = m["ms_per_step"]
             out["mid_forward"] = {k: m[k] for k in ("value", "ms_per_step", "config", "propagation", "phases_ms",
                                                     "roofline", "iteration")}
@@ -639,7 +684,7 @@ def main():
         del scm
     if not args.no_batched:
         torch.cuda.empty_cache()
-        out["batched"] = time_batched(pg, torch, max(2, args.steps // 2))
+        out["batched"] = time_batched(pg, torch, max(2, args.steps // 2), tune=not args.no_autotune)
         log(f"batched {out['batched']['ms_batched']} ms vs per-scene {out['batched']['ms_per_scene_sequential']} ms")
     print(json.dumps(out), flush=True)
 

@@ -140,6 +140,15 @@ typedef struct pg_params {
     int32_t schedule;       /* propagation schedule, same result: 0 = default,
                                PG_SCHED_TWO_PASS, PG_SCHED_SHIFTED or PG_SCHED_SCATTER */
     uint32_t flags;         /* PG_FLAG_* */
+    /* Launch shape of the propagation kernels (pg_render's iterations and the
+     * batched ones); any value gives bit-identical results.  0 = default. */
+    int32_t tile;           /* workgroup size of the aggregation (one row per thread) and the
+                               shift (two vertices per thread): 64, 128, 256 (default), 512 or
+                               1024 */
+    int32_t tile_group;     /* consecutive row tiles each XCD takes in turn in the aggregation
+                               (the hardware hands workgroup b to XCD b mod 8): 1 (default) =
+                               plain launch order, G > 1 = tiles [8Gc + Gx, 8Gc + G(x + 1)) go
+                               to XCD x; at most 65536 */
 } pg_params;
 
 /* Optional outputs of pg_render; any pointer may be NULL. */
@@ -155,6 +164,10 @@ typedef struct pg_graph_out {
     float* lplus;           /* [N][3] incoming indirect radiance after D iterations */
     int64_t edge_capacity;  /* PG_FLAG_CLUSTERS: entries col / w_* hold; a larger E writes no
                                edges and returns PG_ERR_INPUT (E from pg_clusters' centres) */
+    int64_t* n_far;         /* [1]    edges whose neighbour lies more than 32767 rows from its
+                               row in the spatially sorted order the iterations run in (their
+                               ids are read from a side list, 4 more bytes each); 0 when the
+                               iterations do not use the compact 16-bit ids */
 } pg_graph_out;
 
 /* ---- utilities ---------------------------------------------------------- */
@@ -296,8 +309,13 @@ pg_status pg_clusters(const pg_paths* paths, int32_t k, int32_t cell_shift, int3
  * "Rendering System": the path tracer's own estimate, or zero): for v with
  * successor u, lplus0(v) = e_u + albedo_u (d_pt_u + rho_u(w_u)/p_u(w_u) lplus0(u))
  * with PG_INIT_PT, e_u with PG_INIT_ZERO; 0 at a path's end.
- * Inputs row_ptr/col as produced by pg_knn (row i starting with i).
- * Any of the outputs may be NULL. */
+ * Inputs row_ptr/col as produced by pg_knn (row i = [i K, (i+1) K), starting
+ * with i); this call, pg_propagate and pg_gather read col and the weights at
+ * i K + l.  PG_FLAG_CLUSTERS is refused with PG_ERR_UNSUPPORTED (cluster rows
+ * have other lengths: pg_render handles that relation).  With PG_FLAG_CHECK,
+ * row_ptr is verified on the device before col is read, and a row_ptr of any
+ * other layout returns PG_ERR_INPUT; without it, such a row_ptr is the
+ * caller's error.  Any of the outputs may be NULL. */
 pg_status pg_edges_workspace_size(const pg_paths* paths, const pg_params* params, size_t* bytes);
 pg_status pg_edges(const pg_paths* paths, const pg_params* params, const int64_t* row_ptr, const int32_t* col,
                    float* w_ind, float* w_ph, float* w_env, float* b, float* d_pt, float* lplus0,
@@ -310,7 +328,8 @@ pg_status pg_edges(const pg_paths* paths, const pg_params* params, const int64_t
  * is 1/sigma_t at the collision, which turns sigma_s * phase into albedo *
  * phase, so propagation is the shift to the predecessor.)
  * lplus holds L_0 on entry and L_D on return.  traj, if not NULL, receives
- * L_1..L_D as [D][N][3]. */
+ * L_1..L_D as [D][N][3].  row_ptr / col: the k-nearest layout, checked as in
+ * pg_edges. */
 pg_status pg_propagate_workspace_size(const pg_paths* paths, const pg_params* params, size_t* bytes);
 pg_status pg_propagate(const pg_paths* paths, const pg_params* params, const int64_t* row_ptr,
                        const int32_t* col, const float* w_ind, const float* b, float* lplus, float* traj,
@@ -341,7 +360,9 @@ pg_status pg_propagate_static(const pg_paths* paths, const pg_params* params, co
  *   o_p = e_v0 + albedo_v0 (d_pt_v0 + rho_v0(w_v0)/p_v0(w_v0) L(v0)) (final_gather = 1)
  * (0 for an empty path; d_pt_v0 replaced by the extra first-vertex samples'
  * estimate when paths->n_extra > 0) and image[pixel] = mean over its spp
- * paths of (e_cam_p + o_p).  image is [height][width][3].  No workspace. */
+ * paths of (e_cam_p + o_p).  image is [height][width][3].  No workspace, so
+ * PG_FLAG_CHECK is refused; row_ptr / col: the k-nearest layout, as in
+ * pg_edges (PG_FLAG_CLUSTERS refused). */
 pg_status pg_gather(const pg_paths* paths, const pg_params* params, const int64_t* row_ptr, const int32_t* col,
                     const float* w_ind, const float* d_pt, const float* lplus, float* image, void* stream);
 

@@ -69,7 +69,7 @@ class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("D", ctypes.c_int32), ("g", ctypes.c_float), ("g_s", ctypes.c_float),
                 ("sun_dir", ctypes.c_float * 3), ("env_pdf", ctypes.c_float), ("init", ctypes.c_int32),
                 ("final_gather", ctypes.c_int32), ("cell_shift", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("tile", ctypes.c_int32), ("tile_group", ctypes.c_int32)]
 
 
 class ProfileEntry(ctypes.Structure):
@@ -79,7 +79,7 @@ class ProfileEntry(ctypes.Structure):
 
 class GraphOut(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("row_ptr", "col", "w_ind", "w_ph", "w_env", "b", "d_pt", "lplus")] + [
-        ("edge_capacity", ctypes.c_int64)]
+        ("edge_capacity", ctypes.c_int64), ("n_far", ctypes.c_void_p)]
 
 
 _lib = None
@@ -238,7 +238,7 @@ class DevicePaths:
 
 
 def params(k=8, D=8, g=0.5, g_s=None, sun_dir=None, env_pdf=None, init="pt", final_gather=0, cell_shift=0,
-           schedule=0, flags=0) -> Params:
+           schedule=0, flags=0, tile=0, tile_group=0) -> Params:
     """Method parameters (defaults of the small workload)."""
     q = Params()
     q.k, q.D = int(k), int(D)
@@ -254,6 +254,8 @@ def params(k=8, D=8, g=0.5, g_s=None, sun_dir=None, env_pdf=None, init="pt", fin
     q.cell_shift = int(cell_shift)
     q.schedule = int(schedule)
     q.flags = int(flags)
+    q.tile = int(tile)
+    q.tile_group = int(tile_group)
     return q
 
 
@@ -585,10 +587,28 @@ class Batch:
     Work runs on a stream of its own, ordered after the current stream's work
     and before anything enqueued on the current stream afterwards."""
 
-    def __init__(self, paths_list, params_list, use_graph=True):
+    def __init__(self, paths_list, params_list, use_graph=True, tune=False):
+        """tune: pick every scene's cell shift and the batch's edge tile with
+        the autotuner (results unchanged; recorded in ``self.tuned``)."""
         torch = _torch()
         L = lib()
         self.paths_list = list(paths_list)
+        self.tuned = None
+        if tune:
+            from . import autotune
+            params_list = [Params.from_buffer_copy(q) for q in params_list]
+            shifts = []
+            for p, q in zip(self.paths_list, params_list):
+                if p.n_vertices and not (q.flags & PG_FLAG_CLUSTERS):
+                    q.cell_shift = autotune.tune_cell_shift(p, q.k)
+                shifts.append(q.cell_shift)
+            # the batched iterations are one launch shape for all scenes: tuned on the largest
+            big = max(range(len(params_list)), key=lambda s: self.paths_list[s].n_vertices)
+            qb = params_list[big]
+            tile, group = autotune.tune_tile(self.paths_list[big], qb.k, qb.g, cell_shift=qb.cell_shift)
+            for q in params_list:
+                q.tile, q.tile_group = tile, group
+            self.tuned = {"cell_shift": shifts, "tile": tile, "tile_group": group}
         n, self._P, self._Q = _batch_structs(paths_list, params_list)
         nb = ctypes.c_size_t()
         _check(L.pg_render_batched_workspace_size(n, self._P, self._Q, ctypes.byref(nb)))

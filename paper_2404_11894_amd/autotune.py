@@ -1,25 +1,37 @@
-"""Autotuner for the uniform-grid cell size of the neighbour search.
+"""Autotuner of the launch parameters that leave results unchanged.
 
-The kNN result does not depend on the cell size (every candidate is compared
-by exact integer distance and id), only its speed does.  The tuner times the
-neighbour search for the default cell shift and its two neighbours on the
-actual scene and keeps the fastest; results are cached per (vertex-count
-bucket, k) in memory and, optionally, in a JSON file.
+* Grid cell size of the neighbour search (``cell_shift``): the kNN result
+  does not depend on it (every candidate is compared by exact integer distance
+  and id), only its speed does.  Timed with ``pg_knn`` on the actual scene for
+  the default shift and its two neighbours.
+* Edge tile of the propagation (``tile``: workgroup size of the aggregation
+  and the shift; ``tile_group``: consecutive row tiles each XCD takes in turn
+  in the aggregation): the same rows, slots and arithmetic in every launch
+  shape, so images are bit-identical.  Timed as the summed ``spmv`` + ``shift``
+  phase time of a short render (``probe_D`` iterations) with the library's
+  phase profiler.
+
+Results are cached per (vertex-count bucket, k) in memory and, optionally, in
+a JSON file (``load`` / ``save``).
 """
 from __future__ import annotations
 
+import ctypes
 import json
 import math
 import os
 
-from . import DevicePaths, pg_default_cell_shift, pg_knn
+from . import DevicePaths, Renderer, lib, params, pg_default_cell_shift, pg_knn, _check
 
 _cache: dict = {}
 
+TILES = (128, 256, 512)
+GROUPS = (1, 4, 16)
 
-def _key(n: int, k: int) -> str:
+
+def _key(n: int, k: int, what: str = "cell") -> str:
     b = int(round(math.log2(max(n, 1)) * 2))   # half-octave buckets of N
-    return f"{b}:{k}"
+    return f"{what}:{b}:{k}"
 
 
 def load(path: str) -> None:
@@ -63,3 +75,52 @@ def tune_cell_shift(paths: DevicePaths, k: int, reps: int = 2) -> int:
             best, best_t = s, t
     _cache[key] = best
     return best
+
+
+def _propagation_ms(render, image) -> float:
+    """spmv + shift phase time of one render, from the phase profiler."""
+    from . import ProfileEntry
+    L = lib()
+    _check(L.pg_profile_start())
+    render(image)
+    arr = (ProfileEntry * 64)()
+    n = ctypes.c_int32()
+    _check(L.pg_profile_stop(64, arr, ctypes.byref(n)))
+    return sum(arr[i].total_ms for i in range(min(n.value, 64)) if arr[i].name in (b"spmv", b"shift"))
+
+
+def tune_tile(paths: DevicePaths, k: int, g: float = 0.5, probe_D: int = 16, cell_shift: int = 0,
+              margin: float = 0.02) -> tuple[int, int]:
+    """The fastest (tile, tile_group) for this scene's propagation (cached);
+    the default (256, 1) unless a candidate beats it by more than `margin`
+    (the probe's noise is about a percent)."""
+    import torch
+
+    n = paths.n_vertices
+    key = _key(n, k, "tile")
+    if key in _cache:
+        return tuple(_cache[key])
+    if n < 65536:                      # a few waves per XCD: the launch shape hardly matters
+        _cache[key] = (256, 1)
+        return 256, 1
+    image = torch.empty(paths.height, paths.width, 3, device=paths.device)
+    times = {}
+    for t in TILES:
+        for grp in GROUPS:
+            r = Renderer(paths, params(k=k, D=probe_D, g=g, cell_shift=cell_shift, tile=t, tile_group=grp))
+            r(image)                   # warm-up
+            times[(t, grp)] = min(_propagation_ms(r, image) for _ in range(3))
+            del r
+    torch.cuda.empty_cache()
+    best = min(times, key=times.get)
+    if times[best] > (1.0 - margin) * times[(256, 1)]:
+        best = (256, 1)
+    _cache[key] = best
+    return best
+
+
+def tune(paths: DevicePaths, k: int, g: float = 0.5, probe_D: int = 16) -> dict:
+    """cell_shift, tile and tile_group for this scene (each cached)."""
+    s = tune_cell_shift(paths, k)
+    t, grp = tune_tile(paths, k, g, probe_D, s)
+    return {"cell_shift": s, "tile": t, "tile_group": grp}

@@ -74,6 +74,9 @@ pg_status validate_params(const pg_params* q) {
     if (q->cell_shift != 0 && (q->cell_shift < kMinShift || q->cell_shift > kQBits))
         return fail(PG_ERR_ARG, "cell_shift must be 0 or in [%d, %d]", kMinShift, kQBits);
     if (q->schedule < 0 || q->schedule > PG_SCHED_SCATTER) return fail(PG_ERR_ARG, "unknown schedule");
+    if (q->tile != 0 && q->tile != 64 && q->tile != 128 && q->tile != 256 && q->tile != 512 && q->tile != 1024)
+        return fail(PG_ERR_ARG, "tile = %d: 0, 64, 128, 256, 512 or 1024", q->tile);
+    if (q->tile_group < 0 || q->tile_group > 65536) return fail(PG_ERR_ARG, "tile_group must be in [0, 65536]");
     if (q->flags & ~(PG_FLAG_CHECK | PG_FLAG_TAPE | PG_FLAG_EXACT_KNN | PG_FLAG_CLUSTERS))
         return fail(PG_ERR_ARG, "unknown flag bits");
     return PG_OK;
@@ -108,6 +111,25 @@ pg_status check_ws(void* ws, size_t ws_bytes, size_t need) {
     return PG_OK;
 }
 
+// pg_edges / pg_propagate / pg_gather take the k-nearest CSR of pg_knn.  The
+// cluster relation's rows have other lengths, so its flag is refused on the
+// host (no_clusters); with PG_FLAG_CHECK the caller's row_ptr is verified on
+// the device (and the call returns) before any kernel reads col.
+pg_status no_clusters(const pg_params* q) {
+    if (q->flags & PG_FLAG_CLUSTERS)
+        return fail(PG_ERR_UNSUPPORTED, "PG_FLAG_CLUSTERS: this call takes the k-nearest CSR of pg_knn (use "
+                                        "pg_render for the cluster relation)");
+    return PG_OK;
+}
+
+pg_status check_knn_layout(const pg_params* q, int64_t N, int K, const int64_t* row_ptr, int32_t* flag,
+                           hipStream_t s) {
+    if (!(q->flags & PG_FLAG_CHECK) || N == 0) return PG_OK;
+    hipError_t e = launch_check_rows(N, K, row_ptr, flag, s);
+    if (e != hipSuccess) return hip_fail(e, "check_rows");
+    return finish(s, q, flag, q->flags);
+}
+
 pg_status finish(hipStream_t s, const pg_params* q, const int32_t* dflag, uint32_t flags) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -125,6 +147,7 @@ pg_status finish(hipStream_t s, const pg_params* q, const int32_t* dflag, uint32
         if (h & kFlagIndex) m += " neighbour id out of range or row not starting with itself;";
         if (h & kFlagCluster) m += " a cluster has more than 4096 members (cluster_key not uniform?);";
         if (h & kFlagCapacity) m += " the cluster edges exceed out->edge_capacity (or 2^32);";
+        if (h & kFlagRows) m += " row_ptr is not the k-nearest layout row_ptr[i] = i*K;";
         return fail(PG_ERR_INPUT, "%s", m.c_str());
     }
     return PG_OK;
@@ -178,7 +201,8 @@ pg_status propagate_run(const pg_paths* paths, const pg_params* params, const in
                         const float* w_ind, const float* b, float* lplus, float* traj, void* ws, size_t ws_bytes,
                         hipStream_t s) {
     pg_status st;
-    if ((st = validate_paths(paths, false)) || (st = validate_params(params))) return st;
+    if ((st = validate_paths(paths, false)) || (st = validate_params(params)) || (st = no_clusters(params)))
+        return st;
     const int64_t N = paths->n_vertices;
     if (N > 0 && (!row_ptr || !col || !w_ind || !b || !lplus))
         return fail(PG_ERR_ARG, "row_ptr, col, w_ind, b and lplus are required");
@@ -191,6 +215,7 @@ pg_status propagate_run(const pg_paths* paths, const pg_params* params, const in
     float* y = cv.take<float>(3 * N);
     hipError_t e;
     if ((e = launch_fill(flag, 64 * 4, s)) != hipSuccess) return hip_fail(e, "fill");
+    if ((st = check_knn_layout(params, N, K, row_ptr, flag, s))) return st;
     if (N == 0) return finish(s, params, flag, params->flags);
     if ((e = launch_fill_value(succ, (size_t)N * 4, 0xffffffffu, s)) != hipSuccess) return hip_fail(e, "fill");
     if ((e = launch_paths(paths->n_paths, N, paths->path_offsets, nullptr, nullptr, nullptr, nullptr, nullptr, PG_INIT_ZERO,
@@ -413,7 +438,8 @@ pg_status pg_edges(const pg_paths* paths, const pg_params* params, const int64_t
                    size_t ws_bytes, void* stream) {
     g_error.clear();
     pg_status st;
-    if ((st = validate_paths(paths, true)) || (st = validate_params(params))) return st;
+    if ((st = validate_paths(paths, true)) || (st = validate_params(params)) || (st = no_clusters(params)))
+        return st;
     const int64_t N = paths->n_vertices;
     if (N > 0 && (!row_ptr || !col)) return fail(PG_ERR_ARG, "row_ptr and col are required");
     bool ok;
@@ -430,6 +456,7 @@ pg_status pg_edges(const pg_paths* paths, const pg_params* params, const int64_t
     float* al = cv.take<float>(N);
     hipError_t e;
     if ((e = launch_fill(flag, 64 * 4, s)) != hipSuccess) return hip_fail(e, "fill");
+    if ((st = check_knn_layout(params, N, K, row_ptr, flag, s))) return st;
     if (N == 0) return finish(s, params, flag, params->flags);
     if ((e = launch_pack_records(N, *paths, rec, flag, s)) != hipSuccess) return hip_fail(e, "pack");
     EdgeOut o{};
@@ -486,6 +513,7 @@ pg_status pg_gather(const pg_paths* paths, const pg_params* params, const int64_
     if (N > 0 && (!row_ptr || !col || !w_ind || !d_pt || !lplus))
         return fail(PG_ERR_ARG, "row_ptr, col, w_ind, d_pt and lplus are required");
     if (params->flags & PG_FLAG_CHECK) return fail(PG_ERR_UNSUPPORTED, "pg_gather has no workspace for PG_FLAG_CHECK");
+    if ((st = no_clusters(params))) return st;
     const int K = (int)(N < params->k ? N : params->k);
     hipStream_t s = (hipStream_t)stream;
     Consts c = make_consts(params, K);

@@ -33,6 +33,9 @@ pg_status validate_params(const pg_params* q);
 pg_status validate_clusters(const pg_paths* p, const pg_params* q);
 pg_status check_ws(void* ws, size_t ws_bytes, size_t need);
 pg_status finish(hipStream_t s, const pg_params* q, const int32_t* dflag, uint32_t flags);
+pg_status no_clusters(const pg_params* q);
+pg_status check_knn_layout(const pg_params* q, int64_t N, int K, const int64_t* row_ptr, int32_t* flag,
+                           hipStream_t s);
 Consts make_consts(const pg_params* q, int K);
 int32_t default_shift(int64_t N);
 int shift_of(const pg_params* q, int64_t N);
@@ -144,6 +147,7 @@ struct RenderBufs {
     GridBufs g;
     int64_t N = 0, P = 0;
     int K = 0, D = 0, schedule = 0;
+    int tile = 0, tile_group = 0;   // launch shape of the propagation kernels
     bool tape = false;
     VRec* rec = nullptr;
     int32_t* col = nullptr;   // [ell_size(N, K)] sorted ids, sliced ELL
@@ -157,6 +161,11 @@ struct RenderBufs {
     int32_t* pred = nullptr;  // [N] (tape)
     float* x = nullptr;       // [N*3]
     float* y = nullptr;       // [N*3]
+    int16_t* c16 = nullptr;   // compact ids of the two-pass aggregation (c16_row_sum)
+    uint32_t* c16_base = nullptr;   // [n_slices + 1]
+    uint32_t* c16_cnt = nullptr;    // [n_slices] scratch of the build
+    uint32_t* c16_part = nullptr;   // scan partials
+    int32_t* c16_ovf = nullptr;     // [ell_size] escaped ids
     int32_t* mcol = nullptr;  // shifted schedule
     float* mw = nullptr;
     float* c = nullptr;

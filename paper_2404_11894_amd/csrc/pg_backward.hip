@@ -8,9 +8,11 @@
 //   direct terms and the g-dependence of every phase evaluation  ->
 //   trilinear scatter of d/d albedo into the grid.
 // d rho / d g = rho * h(u),  h = d ln HG / d g.  Block partial sums of dL/dg
-// go to fixed slots and are reduced in a fixed order, so dL/dg does not depend
-// on scheduling; the grid scatter and the output's neighbour scatter use
-// float atomics (order-dependent in the last bits).
+// go to fixed slots and are reduced in a fixed order, so for one sorted layout
+// dL/dg does not depend on scheduling; the grid scatter and the output's
+// neighbour scatter use float atomics (order-dependent in the last bits).
+// The sorted layout itself follows the grid's atomic in-cell order, so the
+// reverse sums' order, and the gradients' last bits, can change between runs.
 #include <utility>
 
 #include "pg_api_common.h"
@@ -29,7 +31,8 @@ namespace pg {
 // Built in four passes: in-degrees with atomics, which also give every edge
 // its arrival rank at its T-row (one byte); slice lengths and their scan;
 // every edge stored at its rank (no atomics); each T-row sorted by source row
-// in registers, so the reverse sums run in a fixed order.
+// in registers, so the reverse sums run in a fixed order for a given sorted
+// layout.
 
 // Row i and slot l of ELL position e (inverse of eidx); l >= K is padding.
 __device__ inline void ell_slot(int64_t e, int K, int64_t& i, int& l) {
@@ -232,8 +235,11 @@ __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, co
 // <zbar_i, sum_l dw_il/dg L_{t-1}(j_l)> to the block's dL/dg slot.  One thread
 // per row over the sliced-ELL edges (all K loads issued before the gathers),
 // as in the forward product.  KT = ell_k4(K) at compile time, 0: runtime.
-template <int KT>
+template <int KT, bool C16>
 __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const int32_t* __restrict__ col,
+                                                     const int16_t* __restrict__ c16,
+                                                     const uint32_t* __restrict__ c16_base,
+                                                     const int32_t* __restrict__ c16_ovf,
                                                      const float* __restrict__ w, const float* __restrict__ gw,
                                                      const float* __restrict__ xprev, const float* __restrict__ lam,
                                                      const int32_t* __restrict__ pred,
@@ -256,7 +262,19 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const in
             gy = fmaf(gl_, xv.y, gy);
             gz = fmaf(gl_, xv.z, gz);
         };
-        if (KT) {
+        if constexpr (C16 && KT > 0) {   // ids from the compact layout (the same ids, the same order)
+            constexpr int NQ = KT / 4;
+            f32x4 ww[NQ], gg[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                ww[q] = ld_quad_nt(w + base + q * kQuadStride);
+                gg[q] = ld_quad_nt(gw + base + q * kQuadStride);
+            }
+            int32_t j[KT];
+            c16_row_ids<KT>(i, K, c16, c16_base, c16_ovf, j);
+#pragma unroll
+            for (int l = 0; l < KT; ++l) acc(j[l], ww[l >> 2][l & 3], gg[l >> 2][l & 3]);
+        } else if (KT) {
             constexpr int NQ = KT > 0 ? KT / 4 : 1;
             i32x4 j[NQ];
             f32x4 ww[NQ], gg[NQ];
@@ -739,8 +757,14 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
             ProfScope ps(s, "rev_rows");
             auto go = [&](auto kt) {
                 constexpr int KT = decltype(kt)::value;
-                hipLaunchKernelGGL(k_rev_rows<KT>, dim3((unsigned)bb.n_rows), dim3(kBlock), 0, s, N, K, r.col,
-                                   r.w, r.gw, xprev, lam, r.pred, r.alpha, bb.abar, bb.bbar, bb.zbar, g_rows);
+                if (KT > 0 && r.c16)
+                    hipLaunchKernelGGL((k_rev_rows<KT, true>), dim3((unsigned)bb.n_rows), dim3(kBlock), 0, s, N, K,
+                                       r.col, r.c16, r.c16_base, r.c16_ovf, r.w, r.gw, xprev, lam, r.pred, r.alpha,
+                                       bb.abar, bb.bbar, bb.zbar, g_rows);
+                else
+                    hipLaunchKernelGGL((k_rev_rows<KT, false>), dim3((unsigned)bb.n_rows), dim3(kBlock), 0, s, N, K,
+                                       r.col, r.c16, r.c16_base, r.c16_ovf, r.w, r.gw, xprev, lam, r.pred, r.alpha,
+                                       bb.abar, bb.bbar, bb.zbar, g_rows);
             };
             switch (ell_k4(K)) {
             case 8: go(std::integral_constant<int, 8>{}); break;

@@ -18,6 +18,9 @@ namespace pg {
 
 struct SceneDesc {
     const int32_t* col;
+    const int16_t* c16;          // compact ids (NULL: the 32-bit ids)
+    const uint32_t* c16_base;
+    const int32_t* c16_ovf;
     const float* w;
     const float* b;
     const float* alpha;
@@ -45,16 +48,25 @@ __device__ inline int find_scene(const SceneDesc* sd, int n, int64_t blk) {
 // uniform: K4 = 8, 12, 16 take the unrolled row sum, other counts the loop.
 template <int KT>
 __device__ __forceinline__ void spmv_batched_row(const SceneDesc& d, int64_t i) {
-    const f3 z = ell_row_sum<KT>(i, d.K, d.col, d.w, d.x);
+    f3 z;
+    if constexpr (KT > 0) {
+        if (d.c16) z = c16_row_sum<KT>(i, d.K, d.c16, d.c16_base, d.c16_ovf, d.w, d.x);
+        else z = ell_row_sum<KT>(i, d.K, d.col, d.w, d.x);
+    } else {
+        z = ell_row_sum<KT>(i, d.K, d.col, d.w, d.x);
+    }
     const float a = d.alpha[i];
     const f3 bb = ld3(d.b, i);
     st3_nt(d.y, i, f3{fmaf(a, z.x, bb.x), fmaf(a, z.y, bb.y), fmaf(a, z.z, bb.z)});
 }
 
-__global__ __launch_bounds__(kBlock) void k_spmv_batched(const SceneDesc* __restrict__ sd, int nsc, int t) {
-    const SceneDesc& d = sd[find_scene(sd, nsc, blockIdx.x)];
+// Workgroups of BS rows; tile_group as in the single-scene aggregation.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_spmv_batched(const SceneDesc* __restrict__ sd, int nsc, int t, int group) {
+    const int64_t blk = grouped_tile(blockIdx.x, gridDim.x, group);
+    const SceneDesc& d = sd[find_scene(sd, nsc, blk)];
     if (t > d.D) return;
-    const int64_t i = (blockIdx.x - d.blk0) * (int64_t)kBlock + threadIdx.x;
+    const int64_t i = (blk - d.blk0) * (int64_t)BS + threadIdx.x;
     if (i >= d.nrows) return;
     switch (ell_k4(d.K)) {
     case 8: spmv_batched_row<8>(d, i); break;
@@ -65,7 +77,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_batched(const SceneDesc* __rest
 }
 
 // x(v) = y(succ v), 0 at a path's end, for scenes still iterating.
-__global__ __launch_bounds__(kBlock) void k_shift_batched(const SceneDesc* __restrict__ sd, int nsc, int t) {
+template <int BS>
+__global__ __launch_bounds__(BS) void k_shift_batched(const SceneDesc* __restrict__ sd, int nsc, int t) {
     const SceneDesc& d = sd[find_scene(sd, nsc, blockIdx.x)];
     if (t > d.D) return;
     const int64_t v = (blockIdx.x - d.blk0) * (int64_t)blockDim.x + threadIdx.x;
@@ -82,7 +95,9 @@ struct BatchLayout {
     int n = 0;
     std::vector<RenderBufs> r;
     std::vector<pg_params> q;
-    // one descriptor per scene with vertices; 256 rows per block
+    // one descriptor per scene with vertices; `tile` rows per block (the first
+    // scene's params->tile, 0 = 256), tile_group likewise
+    int tile = kBlock, tile_group = 1;
     int64_t blocks = 0;
     std::vector<SceneDesc> host_tables;
     SceneDesc* dev_tables = nullptr;
@@ -102,14 +117,16 @@ static void carve_batch(Carver& cv, BatchLayout& L, int n, const pg_paths* paths
     }
     L.host_tables.clear();
     L.Dmax = 0;
+    L.tile = params[0].tile ? params[0].tile : kBlock;
+    L.tile_group = params[0].tile_group ? params[0].tile_group : 1;
     int64_t blk = 0;
     for (int s = 0; s < n; ++s) {
         const RenderBufs& r = L.r[s];
         if (r.N == 0 || r.clusters) continue;   // cluster scenes iterate on their own stream
         if (r.D > L.Dmax) L.Dmax = r.D;
-        SceneDesc d{r.col, r.w, r.b, r.alpha, r.succ, r.x, r.y, r.N, blk, r.K, r.D};
+        SceneDesc d{r.col, r.c16, r.c16_base, r.c16_ovf, r.w, r.b, r.alpha, r.succ, r.x, r.y, r.N, blk, r.K, r.D};
         L.host_tables.push_back(d);
-        blk += div_up(r.N, kBlock);
+        blk += div_up(r.N, L.tile);
     }
     L.blocks = blk;
     L.dev_tables = cv.take<SceneDesc>((int64_t)(L.host_tables.size() > 0 ? L.host_tables.size() : 1));
@@ -134,14 +151,16 @@ static pg_status validate_batch(int n, const pg_paths* paths, const pg_params* p
 static hipError_t batched_iterations(const BatchLayout& L, hipStream_t s) {
     const int nsc = (int)L.host_tables.size();
     for (int t = 1; t <= L.Dmax && L.blocks > 0; ++t) {
-        {
-            ProfScope ps(s, "spmv_batched");
-            hipLaunchKernelGGL(k_spmv_batched, dim3((unsigned)L.blocks), dim3(kBlock), 0, s, L.dev_tables, nsc, t);
-        }
-        {
+        dispatch_tile(L.tile, [&](auto bs) {
+            constexpr int BS = decltype(bs)::value;
+            {
+                ProfScope ps(s, "spmv_batched");
+                hipLaunchKernelGGL(k_spmv_batched<BS>, dim3((unsigned)L.blocks), dim3(BS), 0, s, L.dev_tables, nsc,
+                                   t, L.tile_group);
+            }
             ProfScope ps(s, "shift_batched");
-            hipLaunchKernelGGL(k_shift_batched, dim3((unsigned)L.blocks), dim3(kBlock), 0, s, L.dev_tables, nsc, t);
-        }
+            hipLaunchKernelGGL(k_shift_batched<BS>, dim3((unsigned)L.blocks), dim3(BS), 0, s, L.dev_tables, nsc, t);
+        });
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -1299,6 +1299,7 @@ hipError_t cluster_output(const pg_paths* p, const pg_params* q, RenderBufs& r, 
         PG_TRY(hipGetLastError());
     }
     if (out && out->lplus) PG_TRY(launch_permute3(r.N, r.cl.cinv, cur, out->lplus, 1, s));
+    if (out && out->n_far) PG_TRY(launch_fill(out->n_far, sizeof(int64_t), s));   // no compact ids here
     return hipSuccess;
 }
 

@@ -25,6 +25,7 @@ enum : int32_t {
     kFlagIndex = 4,     // neighbour id out of range in caller-provided CSR
     kFlagCluster = 8,   // a cluster above kClusterMax members (keys not uniform)
     kFlagCapacity = 16, // exported cluster edges exceed the caller's capacity
+    kFlagRows = 32,     // caller-provided row_ptr is not the k-nearest layout i K
 };
 
 // Cluster neighbour relation: rounds of splitting large clusters, and the
@@ -63,6 +64,31 @@ __device__ inline i32x4 ld_quad_nt(const int32_t* p) {
 }
 __device__ inline f32x4 ld_quad_nt(const float* p) {
     return __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+}
+
+// Workgroup b's row tile when each XCD takes G consecutive tiles in turn: the
+// hardware hands workgroup b to XCD b % 8, so tiles [8Gc + Gx, 8Gc + G(x+1))
+// of chunk c go to XCD x.  G = 1 is the plain launch order; the tail past the
+// last whole chunk keeps plain order.  A bijection on [0, nb).
+__device__ inline int64_t grouped_tile(int64_t b, int64_t nb, int G) {
+    if (G <= 1) return b;
+    const int64_t span = 8 * (int64_t)G;
+    if (b >= (nb / span) * span) return b;
+    const int64_t c = b / span, r = b - c * span;
+    return c * span + (r & 7) * G + (r >> 3);
+}
+
+// Runs go(std::integral_constant<int, BS>) with the workgroup size BS of a
+// propagation launch (tile 0 = 256).
+template <class F>
+inline void dispatch_tile(int tile, F&& go) {
+    switch (tile) {
+    case 64: go(std::integral_constant<int, 64>{}); break;
+    case 128: go(std::integral_constant<int, 128>{}); break;
+    case 512: go(std::integral_constant<int, 512>{}); break;
+    case 1024: go(std::integral_constant<int, 1024>{}); break;
+    default: go(std::integral_constant<int, 256>{}); break;
+    }
 }
 
 // XCD-aware block order.  The hardware hands block b to XCD b % 8; remap so
@@ -190,6 +216,77 @@ __device__ __forceinline__ f3 ell_row_sum(int64_t i, int K, const int32_t* __res
                 az = fmaf(wq[c], xv.z, az);
             }
         }
+    }
+    return f3{ax, ay, az};
+}
+
+// ------------------------------------------- compact edge ids (two-pass SpMV)
+// The aggregation streams every edge's id and weight once per iteration.  Its
+// ids are kept a second time as 16-bit offsets j - i from the row: the k
+// nearest lie a few grid cells away, so in the spatially sorted order most
+// offsets are small.  Layout: the sliced ELL with octets, row i's slots 8o..8o+7
+// in one 16-byte group (int16 element c16_row(i, K) + o * kOctStride + l % 8).
+// Slot 0 (always the row itself) holds instead the row's start, within its
+// slice, in the list of escaped ids; an offset outside [-32767, 32767] is
+// stored as kC16Escape and its id read from that list, which holds a slice's
+// escaped ids in row and slot order from c16_base[slice] on.
+constexpr int64_t kOctStride = 8 * kSlice;
+constexpr int32_t kC16Escape = -32768;
+__host__ __device__ inline int c16_k8(int K) { return (K + 7) & ~7; }
+__host__ __device__ inline int64_t c16_row(int64_t i, int K) {
+    return (i >> 6) * (int64_t)c16_k8(K) * kSlice + (i & (kSlice - 1)) * 8;
+}
+__host__ __device__ inline int64_t c16_size(int64_t N, int K) { return div_up(N, kSlice) * kSlice * c16_k8(K); }
+
+// Row i's K4 = KT neighbour ids from the compact layout.  Every id, an
+// escaped one included, is known before any gather: an escape's position in
+// the list follows from the escapes before it in the row.
+template <int KT>
+__device__ __forceinline__ void c16_row_ids(int64_t i, int K, const int16_t* __restrict__ c16,
+                                            const uint32_t* __restrict__ c16_base, const int32_t* __restrict__ ovf,
+                                            int32_t (&j)[KT]) {
+    static_assert(KT % 4 == 0 && KT > 0, "compile-time K4 only");
+    constexpr int NO = (KT + 7) / 8;
+    const int64_t b16 = c16_row(i, K);
+    i32x4 d[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) d[o] = ld_quad_nt(reinterpret_cast<const int32_t*>(c16 + b16 + o * kOctStride));
+    int64_t p = (int64_t)c16_base[i >> 6] + (uint32_t)(d[0][0] & 0xffff);
+    j[0] = (int32_t)i;
+#pragma unroll
+    for (int l = 1; l < KT; ++l) {
+        const int32_t word = d[l >> 3][(l & 7) >> 1];
+        const int32_t off = (l & 1) ? (word >> 16) : (int32_t)(int16_t)(word & 0xffff);
+        if (off == kC16Escape) {
+            j[l] = ovf[p];
+            ++p;
+        } else {
+            j[l] = (int32_t)(i + off);
+        }
+    }
+}
+
+// The same sum as ell_row_sum<KT> (same slots, same order, same FMAs: bit-
+// identical), with the ids decoded from the compact layout.
+template <int KT>
+__device__ __forceinline__ f3 c16_row_sum(int64_t i, int K, const int16_t* __restrict__ c16,
+                                          const uint32_t* __restrict__ c16_base, const int32_t* __restrict__ ovf,
+                                          const float* __restrict__ w, const float* __restrict__ x) {
+    constexpr int NQ = KT / 4;
+    const int64_t base = ell_row(i, K);
+    f32x4 ww[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) ww[q] = ld_quad_nt(w + base + q * kQuadStride);
+    int32_t j[KT];
+    c16_row_ids<KT>(i, K, c16, c16_base, ovf, j);
+    float ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll
+    for (int l = 0; l < KT; ++l) {
+        const f3 xv = ld3(x, j[l]);
+        const float wl = ww[l >> 2][l & 3];
+        ax = fmaf(wl, xv.x, ax);
+        ay = fmaf(wl, xv.y, ay);
+        az = fmaf(wl, xv.z, az);
     }
     return f3{ax, ay, az};
 }
@@ -434,13 +531,23 @@ hipError_t launch_paths(int64_t P, int64_t N, const int64_t* off, const int32_t*
 hipError_t launch_spmv(int64_t N, int K, const int32_t* col, const float* w, const float* x, const float* b,
                        const float* alpha, float* y, hipStream_t s);
 // the same product over the sliced-ELL layout, one thread per row
+// (tile: workgroup size, tile_group: consecutive tiles per XCD; 0 = defaults)
 hipError_t launch_spmv_ell(int64_t N, int K, const int32_t* col, const float* w, const float* x, const float* b,
-                           const float* alpha, const int32_t* rowmask, float* y, hipStream_t s);
+                           const float* alpha, const int32_t* rowmask, float* y, hipStream_t s, int tile = 0,
+                           int tile_group = 0);
 // aggregation fused with propagation: row i's result goes to x_new[pred i];
 // rows without a predecessor are skipped
 hipError_t launch_spmv_scatter(int64_t N, int K, const int32_t* col, const float* w, const float* x,
                                const float* b, const float* alpha, const int32_t* pred, float* xn, hipStream_t s);
-hipError_t launch_shift(int64_t N, const int32_t* succ, const float* y, float* x, hipStream_t s);
+hipError_t launch_shift(int64_t N, const int32_t* succ, const float* y, float* x, hipStream_t s, int tile = 0);
+hipError_t launch_check_rows(int64_t N, int K, const int64_t* row_ptr, int32_t* flag, hipStream_t s);
+// compact ids of the sliced ELL (see c16_row_sum): c16 [c16_size], c16_base
+// [n_slices + 1], ovf [ell_size] (room for every id), cnt / partials scratch
+hipError_t launch_c16_build(int64_t N, int K, const int32_t* col, int16_t* c16, uint32_t* cnt, uint32_t* c16_base,
+                            uint32_t* partials, int32_t* ovf, hipStream_t s);
+hipError_t launch_spmv_c16(int64_t N, int K, const int16_t* c16, const uint32_t* c16_base, const int32_t* ovf,
+                           const int32_t* col, const float* w, const float* x, const float* b, const float* alpha,
+                           float* y, hipStream_t s, int tile = 0, int tile_group = 0);
 hipError_t launch_shifted_build(int64_t N, int K, const int32_t* succ, const int32_t* col, const float* w,
                                 const float* b, const float* alpha, int32_t* mcol, float* mw, float* c,
                                 hipStream_t s);

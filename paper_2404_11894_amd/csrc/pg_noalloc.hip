@@ -43,7 +43,9 @@ extern "C" pg_status pg_propagate_static(const pg_paths* paths, const pg_params*
                                          float* traj, void* stream) {
     pg::g_error.clear();
     pg_status st;
-    if ((st = pg::validate_paths(paths, false)) || (st = pg::validate_params(params))) return st;
+    if ((st = pg::validate_paths(paths, false)) || (st = pg::validate_params(params)) ||
+        (st = pg::no_clusters(params)))
+        return st;
     const size_t need = pg::propagate_size(paths, params);
     if (need > (size_t)PG_STATIC_SCRATCH_BYTES)
         return pg::fail(PG_ERR_WORKSPACE,

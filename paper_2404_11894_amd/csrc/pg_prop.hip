@@ -83,13 +83,14 @@ hipError_t launch_spmv(int64_t N, int K, const int32_t* col, const float* w, con
 // sorted rows together, which measured faster here than giving each XCD its
 // own contiguous range), and the edge ids and weights, read exactly once, are
 // loaded non-temporally so they do not displace the gathered vector in L2.
-template <int KT, bool SCATTER>
-__global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int K, const int32_t* __restrict__ col,
-                                                     const float* __restrict__ w, const float* __restrict__ x,
-                                                     const float* __restrict__ b, const float* __restrict__ alpha,
-                                                     const int32_t* __restrict__ rowmask, float* __restrict__ y) {
-    const int64_t tile = blockIdx.x;
-    const int64_t i = tile * kBlock + threadIdx.x;
+template <int KT, bool SCATTER, int BS>
+__global__ __launch_bounds__(BS) void k_spmv_ell(int64_t N, int K, const int32_t* __restrict__ col,
+                                                 const float* __restrict__ w, const float* __restrict__ x,
+                                                 const float* __restrict__ b, const float* __restrict__ alpha,
+                                                 const int32_t* __restrict__ rowmask, float* __restrict__ y,
+                                                 int group) {
+    const int64_t tile = grouped_tile(blockIdx.x, gridDim.x, group);
+    const int64_t i = tile * BS + threadIdx.x;
     if (i >= N) return;
     int64_t dst = i;
     if (rowmask) {
@@ -108,56 +109,201 @@ __global__ __launch_bounds__(kBlock) void k_spmv_ell(int64_t N, int K, const int
 
 template <bool SCATTER>
 static void go_spmv_ell(int64_t N, int K, const int32_t* col, const float* w, const float* x, const float* b,
-                        const float* alpha, const int32_t* rowmask, float* y, hipStream_t s) {
-    dim3 grid((unsigned)div_up(N, kBlock)), block(kBlock);
-    dispatch_k4(K, [&](auto kt) {
-        constexpr int KT = decltype(kt)::value;
-        hipLaunchKernelGGL((k_spmv_ell<KT, SCATTER>), grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask, y);
+                        const float* alpha, const int32_t* rowmask, float* y, hipStream_t s, int tile, int group) {
+    dispatch_tile(tile, [&](auto bs) {
+        constexpr int BS = decltype(bs)::value;
+        dim3 grid((unsigned)div_up(N, BS)), block(BS);
+        dispatch_k4(K, [&](auto kt) {
+            constexpr int KT = decltype(kt)::value;
+            hipLaunchKernelGGL((k_spmv_ell<KT, SCATTER, BS>), grid, block, 0, s, N, K, col, w, x, b, alpha, rowmask,
+                               y, group);
+        });
     });
 }
 
 hipError_t launch_spmv_ell(int64_t N, int K, const int32_t* col, const float* w, const float* x, const float* b,
-                           const float* alpha, const int32_t* rowmask, float* y, hipStream_t s) {
+                           const float* alpha, const int32_t* rowmask, float* y, hipStream_t s, int tile,
+                           int tile_group) {
     if (N == 0) return hipSuccess;
-    go_spmv_ell<false>(N, K, col, w, x, b, alpha, rowmask, y, s);
+    go_spmv_ell<false>(N, K, col, w, x, b, alpha, rowmask, y, s, tile, tile_group);
     return hipGetLastError();
 }
 
 hipError_t launch_spmv_scatter(int64_t N, int K, const int32_t* col, const float* w, const float* x,
                                const float* b, const float* alpha, const int32_t* pred, float* xn, hipStream_t s) {
     if (N == 0) return hipSuccess;
-    go_spmv_ell<true>(N, K, col, w, x, b, alpha, pred, xn, s);
+    go_spmv_ell<true>(N, K, col, w, x, b, alpha, pred, xn, s, 0, 0);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- compact edge ids ---
+// One wave per 64-row slice: each lane counts its row's escaped offsets, a
+// wave prefix sum gives the row's start in the slice's escape list (slot 0),
+// and the row's octets are written as 16-byte stores.  Rows past N keep
+// offset 0 in every slot.
+__global__ __launch_bounds__(kBlock) void k_c16_build(int64_t N, int K, const int32_t* __restrict__ col,
+                                                      int16_t* __restrict__ c16, uint32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nsl = div_up(N, kSlice);
+    if ((i >> 6) >= nsl) return;   // whole waves leave together (a slice is one wave)
+    const int K4 = ell_k4(K), K8 = c16_k8(K);
+    uint32_t n = 0;
+    if (i < N)
+        for (int l = 1; l < K4; ++l) {
+            const int64_t off = (int64_t)col[eidx(i, l, K)] - i;
+            n += (off < -32767 || off > 32767) ? 1u : 0u;
+        }
+    uint32_t inc = n;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += t;
+    }
+    const uint32_t start = inc - n;
+    const int64_t b16 = c16_row(i, K);
+    for (int o = 0; 8 * o < K8; ++o) {
+        int32_t words[4];
+        for (int h = 0; h < 4; ++h) {
+            int32_t v[2];
+            for (int e = 0; e < 2; ++e) {
+                const int l = 8 * o + 2 * h + e;
+                int32_t val = 0;
+                if (l == 0) {
+                    val = (int32_t)(start & 0xffffu);
+                } else if (i < N && l < K4) {
+                    const int64_t off = (int64_t)col[eidx(i, l, K)] - i;
+                    val = (off < -32767 || off > 32767) ? kC16Escape : (int32_t)off;
+                }
+                v[e] = val & 0xffff;
+            }
+            words[h] = v[0] | (v[1] << 16);
+        }
+        *reinterpret_cast<i32x4*>(c16 + b16 + o * kOctStride) = i32x4{words[0], words[1], words[2], words[3]};
+    }
+    if (lane == kWave - 1) cnt[i >> 6] = inc;
+}
+
+// Escaped ids of each row at its slice's list start + its slot-0 start.
+__global__ __launch_bounds__(kBlock) void k_c16_escapes(int64_t N, int K, const int32_t* __restrict__ col,
+                                                        const int16_t* __restrict__ c16,
+                                                        const uint32_t* __restrict__ c16_base,
+                                                        int32_t* __restrict__ ovf) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N) return;
+    int64_t p = (int64_t)c16_base[i >> 6] + (uint16_t)c16[c16_row(i, K)];
+    const int K4 = ell_k4(K);
+    for (int l = 1; l < K4; ++l) {
+        const int32_t j = col[eidx(i, l, K)];
+        const int64_t off = (int64_t)j - i;
+        if (off < -32767 || off > 32767) ovf[p++] = j;
+    }
+}
+
+hipError_t launch_c16_build(int64_t N, int K, const int32_t* col, int16_t* c16, uint32_t* cnt, uint32_t* c16_base,
+                            uint32_t* partials, int32_t* ovf, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    const int64_t nsl = div_up(N, kSlice);
+    hipLaunchKernelGGL(k_c16_build, dim3((unsigned)div_up(nsl * kSlice, kBlock)), dim3(kBlock), 0, s, N, K, col,
+                       c16, cnt);
+    hipError_t e = launch_scan_exclusive(cnt, c16_base, nsl, partials, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_c16_escapes, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, K, col, c16,
+                       c16_base, ovf);
+    return hipGetLastError();
+}
+
+// The two-pass aggregation over the compact ids: the same rows, slots and
+// arithmetic as k_spmv_ell, so the same results bit for bit, with 2 bytes per
+// id streamed instead of 4 (plus the few escaped ids).
+template <int KT, int BS>
+__global__ __launch_bounds__(BS) void k_spmv_c16(int64_t N, int K, const int16_t* __restrict__ c16,
+                                                 const uint32_t* __restrict__ c16_base,
+                                                 const int32_t* __restrict__ ovf, const float* __restrict__ w,
+                                                 const float* __restrict__ x, const float* __restrict__ b,
+                                                 const float* __restrict__ alpha, float* __restrict__ y, int group) {
+    const int64_t tile = grouped_tile(blockIdx.x, gridDim.x, group);
+    const int64_t i = tile * BS + threadIdx.x;
+    if (i >= N) return;
+    const f3 z = c16_row_sum<KT>(i, K, c16, c16_base, ovf, w, x);
+    const f3 bb = ld3(b, i);
+    const float a = alpha ? alpha[i] : 1.0f;
+    st3_nt(y, i, f3{fmaf(a, z.x, bb.x), fmaf(a, z.y, bb.y), fmaf(a, z.z, bb.z)});
+}
+
+hipError_t launch_spmv_c16(int64_t N, int K, const int16_t* c16, const uint32_t* c16_base, const int32_t* ovf,
+                           const int32_t* col, const float* w, const float* x, const float* b, const float* alpha,
+                           float* y, hipStream_t s, int tile, int tile_group) {
+    if (N == 0) return hipSuccess;
+    if (ell_k4(K) > 32) return launch_spmv_ell(N, K, col, w, x, b, alpha, nullptr, y, s, tile, tile_group);
+    dispatch_tile(tile, [&](auto bs) {
+        constexpr int BS = decltype(bs)::value;
+        dim3 grid((unsigned)div_up(N, BS)), block(BS);
+        dispatch_k4(K, [&](auto kt) {
+            constexpr int KT = decltype(kt)::value;
+            if constexpr (KT > 0)
+                hipLaunchKernelGGL((k_spmv_c16<KT, BS>), grid, block, 0, s, N, K, c16, c16_base, ovf, w, x, b, alpha,
+                                   y, tile_group);
+        });
+    });
+    return hipGetLastError();
+}
+
+// A caller's CSR must have the k-nearest layout, row i = [i K, (i+1) K):
+// the kernels of pg_edges / pg_propagate index col and w as i K + l.
+__global__ __launch_bounds__(kBlock) void k_check_rows(int64_t N, int K, const int64_t* __restrict__ row_ptr,
+                                                       int32_t* flag) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i <= N && row_ptr[i] != i * (int64_t)K) set_flag(flag, kFlagRows);
+}
+
+hipError_t launch_check_rows(int64_t N, int K, const int64_t* row_ptr, int32_t* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_rows, dim3((unsigned)div_up(N + 1, kBlock)), dim3(kBlock), 0, s, N, K, row_ptr,
+                       flag);
     return hipGetLastError();
 }
 
 // L(v) = y(succ v), 0 at a path's end.  Two vertices per thread, strided by
 // the grid so every access stays coalesced, for two independent gathers; the
 // successor ids (read once) are streamed and L is stored non-temporally.
+// Every load is unconditional (indices clamped to a valid element, the value
+// masked afterwards), so both successor ids and then both gathers are in
+// flight together instead of each waiting at a branch.
 constexpr int kShiftPer = 2;
-__global__ __launch_bounds__(kBlock) void k_shift(int64_t N, const int32_t* __restrict__ succ,
-                                                  const float* __restrict__ y, float* __restrict__ x) {
+template <int BS>
+__global__ __launch_bounds__(BS) void k_shift(int64_t N, const int32_t* __restrict__ succ,
+                                              const float* __restrict__ y, float* __restrict__ x) {
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t v0 = tile * (int64_t)kBlock * kShiftPer + threadIdx.x;
-    int64_t u[kShiftPer];
+    const int64_t v0 = tile * (int64_t)BS * kShiftPer + threadIdx.x;
+    int32_t u[kShiftPer];
 #pragma unroll
     for (int k = 0; k < kShiftPer; ++k) {
-        const int64_t v = v0 + (int64_t)k * kBlock;
-        u[k] = v < N ? (int64_t)__builtin_nontemporal_load(succ + v) : -1;
+        const int64_t v = v0 + (int64_t)k * BS;
+        u[k] = __builtin_nontemporal_load(succ + (v < N ? v : N - 1));
     }
     f3 val[kShiftPer];
 #pragma unroll
-    for (int k = 0; k < kShiftPer; ++k) val[k] = u[k] >= 0 ? ld3(y, u[k]) : f3{0.f, 0.f, 0.f};
+    for (int k = 0; k < kShiftPer; ++k) val[k] = ld3(y, u[k] > 0 ? u[k] : 0);
+    // an empty asm that takes every gathered value keeps the compiler from
+    // sinking one vertex's loads into its guarded store (which serialises
+    // the two load chains)
+    asm volatile("" ::"v"(val[0].x), "v"(val[0].y), "v"(val[0].z), "v"(val[1].x), "v"(val[1].y), "v"(val[1].z));
+    static_assert(kShiftPer == 2, "the asm above names two vertices");
 #pragma unroll
     for (int k = 0; k < kShiftPer; ++k) {
-        const int64_t v = v0 + (int64_t)k * kBlock;
+        const int64_t v = v0 + (int64_t)k * BS;
+        if (u[k] < 0) val[k] = f3{0.f, 0.f, 0.f};
         if (v < N) st3_nt(x, v, val[k]);
     }
 }
 
-hipError_t launch_shift(int64_t N, const int32_t* succ, const float* y, float* x, hipStream_t s) {
+hipError_t launch_shift(int64_t N, const int32_t* succ, const float* y, float* x, hipStream_t s, int tile) {
     if (N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_shift, dim3((unsigned)div_up(N, (int64_t)kBlock * kShiftPer)), dim3(kBlock), 0, s, N,
-                       succ, y, x);
+    dispatch_tile(tile, [&](auto bs) {
+        constexpr int BS = decltype(bs)::value;
+        hipLaunchKernelGGL(k_shift<BS>, dim3((unsigned)div_up(N, (int64_t)BS * kShiftPer)), dim3(BS), 0, s, N,
+                           succ, y, x);
+    });
     return hipGetLastError();
 }
 

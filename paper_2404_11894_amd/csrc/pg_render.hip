@@ -14,6 +14,8 @@ void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params*
     r.K = (int)(N < q->k ? N : q->k);
     r.D = q->D;
     r.schedule = resolve_schedule(q);
+    r.tile = q->tile;
+    r.tile_group = q->tile_group;
     r.tape = (q->flags & PG_FLAG_TAPE) != 0;
     r.clusters = (q->flags & PG_FLAG_CLUSTERS) != 0;
     if (r.clusters) {   // no stored edges: the weights are recomputed from the cluster order
@@ -48,6 +50,14 @@ void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params*
     r.pred = (r.tape || r.schedule == PG_SCHED_SCATTER) ? cv.take<int32_t>(N) : nullptr;
     r.x = cv.take<float>(3 * N);
     r.y = cv.take<float>(3 * N);
+    if (r.schedule == PG_SCHED_TWO_PASS && ell_k4(r.K) <= 32 && E < ((int64_t)1 << 32)) {
+        const int64_t nsl = div_up(N, kSlice);
+        r.c16 = cv.take<int16_t>(c16_size(N, r.K));
+        r.c16_base = cv.take<uint32_t>(nsl + 1);
+        r.c16_cnt = cv.take<uint32_t>(nsl);
+        r.c16_part = cv.take<uint32_t>((int64_t)(scan_partials_bytes(nsl) / sizeof(uint32_t)));
+        r.c16_ovf = cv.take<int32_t>(E);
+    }
     if (r.schedule == PG_SCHED_SHIFTED) {
         r.mcol = cv.take<int32_t>(E);
         r.mw = cv.take<float>(E);
@@ -102,6 +112,10 @@ hipError_t render_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, co
         ProfScope ps(s, "edges");
         PG_TRY(launch_edges(N, c, r.col, r.rec, o, g.flag, s));
     }
+    if (r.c16) {
+        ProfScope ps(s, "compact_ids");
+        PG_TRY(launch_c16_build(N, K, r.col, r.c16, r.c16_cnt, r.c16_base, r.c16_part, r.c16_ovf, s));
+    }
     float* x0 = r.tape ? r.traj : r.x;
     PG_TRY(launch_fill_value(r.succ, (size_t)N * 4, 0xffffffffu, s));
     if (r.pred) PG_TRY(launch_fill_value(r.pred, (size_t)N * 4, 0xffffffffu, s));
@@ -142,10 +156,15 @@ hipError_t render_iterate(RenderBufs& r, float* x0, hipStream_t s, float** final
         } else {
             {
                 ProfScope ps(s, "spmv");
-                PG_TRY(launch_spmv_ell(N, K, r.col, r.w, cur, r.b, r.alpha, nullptr, r.y, s));
+                if (r.c16)
+                    PG_TRY(launch_spmv_c16(N, K, r.c16, r.c16_base, r.c16_ovf, r.col, r.w, cur, r.b, r.alpha, r.y, s,
+                                           r.tile, r.tile_group));
+                else
+                    PG_TRY(launch_spmv_ell(N, K, r.col, r.w, cur, r.b, r.alpha, nullptr, r.y, s, r.tile,
+                                           r.tile_group));
             }
             ProfScope ps(s, "shift");
-            PG_TRY(launch_shift(N, r.succ, r.y, nxt, s));
+            PG_TRY(launch_shift(N, r.succ, r.y, nxt, s, r.tile));
         }
         cur = nxt;
     }
@@ -161,6 +180,12 @@ hipError_t render_output(const pg_paths* p, const pg_params* q, RenderBufs& r, c
         PG_TRY(launch_pixels(*p, c, r.g.inv, r.col, r.w, cur, r.dpt, r.r, r.alpha, image, r.g.flag, s));
     }
     if (out && out->lplus) PG_TRY(launch_permute3(r.N, r.g.perm, cur, out->lplus, 0, s));
+    if (out && out->n_far) {   // the escape list's length, widened to int64
+        PG_TRY(launch_fill(out->n_far, sizeof(int64_t), s));
+        if (r.c16)
+            PG_TRY(hipMemcpyAsync(out->n_far, r.c16_base + div_up(r.N, kSlice), sizeof(uint32_t),
+                                  hipMemcpyDeviceToDevice, s));
+    }
     return hipSuccess;
 }
 

@@ -253,3 +253,18 @@ def test_static_propagate_rejects_graphs_beyond_its_scratch_on_the_host():
     assert rc == pg.PG_ERR_WORKSPACE and "static scratch" in msg
     rc, msg = status(L.pg_propagate_static, ctypes.byref(s), None, p, p, p, p, p, None, None)
     assert rc == pg.PG_ERR_ARG
+
+
+def test_csr_entry_points_refuse_the_cluster_flag_on_the_host():
+    # pg_edges / pg_propagate / pg_gather read the k-nearest layout i*K + l;
+    # the cluster relation's rows have other lengths
+    L = pg.lib()
+    s, q = fake_paths(), pg.params(k=8, D=4, flags=pg.PG_FLAG_CLUSTERS)
+    p = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x10000)
+    for fn, args in ((L.pg_edges, (p, p, p, p, p, p, p, p, ws, 1 << 30, None)),
+                     (L.pg_propagate, (p, p, p, p, p, None, ws, 1 << 30, None)),
+                     (L.pg_gather, (p, p, p, p, p, p, None)),
+                     (L.pg_propagate_static, (p, p, p, p, p, None, None))):
+        rc, msg = status(fn, ctypes.byref(s), ctypes.byref(q), *args)
+        assert rc == pg.PG_ERR_UNSUPPORTED and "k-nearest" in msg, fn

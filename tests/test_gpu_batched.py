@@ -106,11 +106,37 @@ def test_tuned_cell_size_leaves_results_unchanged():
         q = pg.params(k=p.k, D=p.D, g=p.g, cell_shift=autotune.tune_cell_shift(pth, p.k) if pth.n_vertices else 0)
         tuned.append(q)
     alt = [pg.params(k=p.k, D=p.D, g=p.g, cell_shift=14) for p in params]
-    for qs in (tuned, alt):
+    # the batch's edge tile: workgroup size and tiles per XCD of the batched iterations
+    tiles = [pg.params(k=p.k, D=p.D, g=p.g, tile=t, tile_group=grp)
+             for p, (t, grp) in zip(params, [(128, 3)] * len(params))]
+    tiles2 = [pg.params(k=p.k, D=p.D, g=p.g, tile=1024, tile_group=2) for p in params]
+    for qs in (tuned, alt, tiles, tiles2):
         out = pg.pg_render_batched(paths, qs)
         torch.cuda.synchronize()
         for s in range(len(scenes)):
             assert torch.equal(out[s], ref[s]), f"scene {s}"
+
+
+def test_autotuned_batch_plan_leaves_results_unchanged():
+    scenes, params, _ = small_batch()
+    paths = [pg.DevicePaths(s) for s in scenes]
+    ref = [im.clone() for im in pg.pg_render_batched(paths, params)]
+    plan = pg.Batch(paths, [pg.params(k=p.k, D=p.D, g=p.g) for p in params], use_graph=True, tune=True)
+    assert plan.tuned is not None and plan.tuned["tile"] in autotune.TILES + (256,)
+    out = plan()
+    torch.cuda.synchronize()
+    for s in range(len(scenes)):
+        assert torch.equal(out[s], ref[s]), f"scene {s}"
+    plan.close()
+    # the tuner itself on a scene large enough to time its propagation
+    sc = scenegen.generate(scenegen.crop_of(scenegen.WORKLOADS["mid"].scene, 64, 64, 4))
+    p = pg.DevicePaths(sc)
+    t = autotune.tune(p, 16, 0.8, probe_D=2)
+    assert t["tile"] in autotune.TILES and t["tile_group"] in autotune.GROUPS and 11 <= t["cell_shift"] <= 20
+    a = pg.pg_render(p, pg.params(k=16, D=3, g=0.8))
+    b = pg.pg_render(p, pg.params(k=16, D=3, g=0.8, **t))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
 
 
 def test_benchmark_batch_matches_oracle_on_sampled_scenes():

@@ -253,3 +253,24 @@ def test_cluster_autograd_with_tape():
     assert_within(img.detach().cpu().numpy(), ref_img, PIX_REL, PIX_ABS, "image")
     grad_close(gt.grad.cpu().numpy(), ref["grad_grid"], "grad grid", ref["grad_grid"])
     grad_close([g.grad.item()], [ref["grad_g"]], "grad g")
+
+
+def test_knn_entry_points_refuse_a_cluster_csr_under_check():
+    # pg_edges and pg_propagate read col at i*K + l: with PG_FLAG_CHECK a CSR
+    # of the cluster relation (other row lengths) is refused before col is read
+    sc = keyed(crop("tiny", 16, 16, 1))
+    paths = pg.DevicePaths(sc)
+    _, gr = pg.pg_render(paths, pg.params(k=8, D=2, g=0.5, flags=pg.PG_FLAG_CLUSTERS), graph=True)
+    torch.cuda.synchronize()
+    assert gr["row_ptr"][-1].item() != 8 * sc.n_vertices
+    q = pg.params(k=8, D=2, g=0.5, flags=pg.PG_FLAG_CHECK)
+    lp = torch.zeros(sc.n_vertices, 3, device="cuda")
+    with pytest.raises(pg.PathGraphError, match="k-nearest layout"):
+        pg.pg_propagate(paths, q, gr["row_ptr"], gr["col"], gr["w_ind"], gr["b"], lp)
+    with pytest.raises(pg.PathGraphError, match="k-nearest layout"):
+        pg.pg_edges(paths, q, gr["row_ptr"], gr["col"])
+    # the k-nearest CSR of the same scene passes the same check
+    rp, col = pg.pg_knn(paths, 8)
+    e = pg.pg_edges(paths, q, rp, col)
+    pg.pg_propagate(paths, q, rp, col, e["w_ind"], e["b"], e["lplus0"])
+    torch.cuda.synchronize()

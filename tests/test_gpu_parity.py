@@ -333,3 +333,39 @@ def test_device_input_errors_are_reported():
         pg.pg_render(paths, pg.params(k=4, D=2, flags=pg.PG_FLAG_CHECK))
     assert e.value.code == pg.PG_ERR_INPUT
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("tile,group", [(64, 1), (128, 3), (512, 2), (1024, 1), (256, 16), (256, 5000)])
+def test_launch_shape_leaves_results_unchanged(tile, group):
+    # workgroup size and the tiles-per-XCD grouping only move work between
+    # workgroups: images and L+ equal the default launch bit for bit, also
+    # where the row count leaves a partial chunk of tiles
+    sc = crop("tiny", 40, 40, 4)
+    paths = pg.DevicePaths(sc)
+    out = []
+    for t, g in ((0, 0), (tile, group)):
+        r = pg.Renderer(paths, pg.params(k=12, D=7, g=0.5, tile=t, tile_group=g, flags=pg.PG_FLAG_CHECK))
+        lp = torch.empty(sc.n_vertices, 3, device="cuda")
+        img = r(graph={"lplus": lp})
+        torch.cuda.synchronize()
+        out.append((img.cpu(), lp.cpu()))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
+def test_compact_ids_equal_full_ids_on_a_graph_with_far_neighbours():
+    # 0.5M vertices of the benchmark's ball: in the spatially sorted order some
+    # neighbours lie more than 32767 rows away, so the two-pass aggregation's
+    # 16-bit ids take the escape list there.  The scatter schedule reads the
+    # full 32-bit ids with the same row sums: images and L+ bit for bit.
+    sc = crop("mid", 160, 160, 4)
+    assert sc.n_vertices > 200_000
+    paths = pg.DevicePaths(sc)
+    out = []
+    for sched in (pg.PG_SCHED_TWO_PASS, pg.PG_SCHED_SCATTER):
+        r = pg.Renderer(paths, pg.params(k=16, D=6, g=0.8, schedule=sched, flags=pg.PG_FLAG_CHECK))
+        lp = torch.empty(sc.n_vertices, 3, device="cuda")
+        img = r(graph={"lplus": lp})
+        torch.cuda.synchronize()
+        out.append((img.cpu(), lp.cpu()))
+        del r
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import scenegen
 import paper_2404_11894_amd as pg
 from tests.gpu_util import PIX_ABS, PIX_REL, assert_within
@@ -119,6 +120,32 @@ def test_traced_records_render_like_host_records():
     b = pg.pg_render(pg.DevicePaths(ref), q)
     torch.cuda.synchronize()
     assert_within(a.cpu().numpy(), b.cpu().numpy(), PIX_REL, PIX_ABS, "device vs host records")
+
+
+def host_scene(rec, cfg):
+    """The device-traced records as a host Scene (numpy copies)."""
+    h = lambda name: None if getattr(rec, name, None) is None else getattr(rec, name).cpu().numpy()  # noqa: E731
+    return scenegen.Scene(width=rec.width, height=rec.height, spp=rec.spp, path_offsets=h("path_offsets"),
+                          pos=h("pos"), dir_in=h("dir_in"), dir_out=h("dir_out"), albedo=h("albedo"),
+                          l_sun=h("l_sun"), dir_env=h("dir_env"), l_env=h("l_env"), l_phase=h("l_phase"),
+                          e_cam=h("e_cam"), config=cfg, sun_dir=tuple(cfg.sun_dir), fb_l_sun=h("fb_l_sun"),
+                          fb_dir_env=h("fb_dir_env"), fb_l_env=h("fb_l_env"), dir_pl=h("dir_pl"), l_pl=h("l_pl"))
+
+
+@pytest.mark.parametrize("extra,pl", [(0, False), (2, True)])
+def test_traced_records_render_like_the_oracle(extra, pl):
+    # the records the GPU tracer wrote, rendered by the oracle (FP64) and by
+    # the GPU from the same device arrays
+    cfg = replace(scenegen.crop_of(scenegen.WORKLOADS["tiny"].scene, 40, 40, 2), extra_samples=extra,
+                  pl_I=(0.4, 0.3, 0.2) if pl else (0.0, 0.0, 0.0))
+    rec = traced(cfg)
+    sc = host_scene(rec, cfg)
+    print(f"traced N={sc.n_vertices} extra={extra} point light={pl}", flush=True)
+    q = pg.params(k=8, D=6, g=0.5, flags=pg.PG_FLAG_CHECK)
+    got = pg.pg_render(pg.DevicePaths(rec), q)
+    torch.cuda.synchronize()
+    ref = oracle.render(sc, oracle.params(k=8, D=6, g=0.5))
+    assert_within(got.cpu().numpy(), ref, PIX_REL, PIX_ABS, "device-traced records vs oracle")
 
 
 def test_trace_records_rejects_foreign_offsets():
