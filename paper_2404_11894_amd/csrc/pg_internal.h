@@ -240,7 +240,10 @@ __host__ __device__ inline int64_t c16_size(int64_t N, int K) { return div_up(N,
 
 // Row i's K4 = KT neighbour ids from the compact layout.  Every id, an
 // escaped one included, is known before any gather: an escape's position in
-// the list follows from the escapes before it in the row.
+// the list follows from the escapes before it in the row.  The row's first
+// four escaped ids are read from the four list slots at its start, with no
+// branch of their own (the list is as long as the ELL, so p0 + 3 stays
+// inside it; slots past the row's own escapes are never selected).
 template <int KT>
 __device__ __forceinline__ void c16_row_ids(int64_t i, int K, const int16_t* __restrict__ c16,
                                             const uint32_t* __restrict__ c16_base, const int32_t* __restrict__ ovf,
@@ -251,18 +254,22 @@ __device__ __forceinline__ void c16_row_ids(int64_t i, int K, const int16_t* __r
     i32x4 d[NO];
 #pragma unroll
     for (int o = 0; o < NO; ++o) d[o] = ld_quad_nt(reinterpret_cast<const int32_t*>(c16 + b16 + o * kOctStride));
-    int64_t p = (int64_t)c16_base[i >> 6] + (uint32_t)(d[0][0] & 0xffff);
+    const int64_t p0 = (int64_t)c16_base[i >> 6] + (uint32_t)(d[0][0] & 0xffff);
+    // more than four escaped ids take a load of their own
+    const int32_t e0 = ovf[p0], e1 = ovf[p0 + 1], e2 = ovf[p0 + 2], e3 = ovf[p0 + 3];
+    int r = 0;
     j[0] = (int32_t)i;
 #pragma unroll
     for (int l = 1; l < KT; ++l) {
         const int32_t word = d[l >> 3][(l & 7) >> 1];
         const int32_t off = (l & 1) ? (word >> 16) : (int32_t)(int16_t)(word & 0xffff);
+        int32_t v = (int32_t)(i + off);
         if (off == kC16Escape) {
-            j[l] = ovf[p];
-            ++p;
-        } else {
-            j[l] = (int32_t)(i + off);
+            v = r == 0 ? e0 : (r == 1 ? e1 : (r == 2 ? e2 : e3));
+            if (r >= 4) v = ovf[p0 + r];
+            ++r;
         }
+        j[l] = v;
     }
 }
 
