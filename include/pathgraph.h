@@ -67,6 +67,16 @@ typedef int32_t pg_status;
                                 pg_render_batched synchronise once to report device checks (a
                                 pg_batch plan does not report them). */
 
+#define PG_FLAG_PERSISTENT 16u  /* pg_render_batched / pg_batch_create (read from the first scene's
+                                   params; ignored by the other calls): all D iterations of all
+                                   scenes run as ONE cooperative kernel with grid barriers between
+                                   the aggregation and the shift, instead of one aggregation and one
+                                   shift launch per iteration.  Same results bit for bit; slower on
+                                   MI355X (every barrier is a device-scope release and acquire by
+                                   every workgroup across the XCDs' separate L2 caches).  Needs
+                                   tile 0 or 256.  pg_render_batched reports a timed-out barrier
+                                   as PG_ERR_HIP; a pg_batch plan does not check. */
+
 #define PG_SCHED_TWO_PASS 1  /* aggregate over spatially sorted rows, then shift along paths */
 #define PG_SCHED_SHIFTED  2  /* rows pre-arranged in predecessor order: one pass per iteration */
 #define PG_SCHED_SCATTER  3  /* sorted rows; each writes its result straight to its predecessor */

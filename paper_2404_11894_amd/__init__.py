@@ -18,7 +18,7 @@ from ._build import LIB_PATH, build  # noqa: F401
 
 PG_OK, PG_ERR_ARG, PG_ERR_WORKSPACE, PG_ERR_HIP, PG_ERR_INPUT, PG_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 PG_INIT_PT, PG_INIT_ZERO = 0, 1
-PG_FLAG_CHECK, PG_FLAG_TAPE, PG_FLAG_EXACT_KNN, PG_FLAG_CLUSTERS = 1, 2, 4, 8
+PG_FLAG_CHECK, PG_FLAG_TAPE, PG_FLAG_EXACT_KNN, PG_FLAG_CLUSTERS, PG_FLAG_PERSISTENT = 1, 2, 4, 8, 16
 PG_SCHED_TWO_PASS, PG_SCHED_SHIFTED, PG_SCHED_SCATTER = 1, 2, 3
 PG_MAX_K = 64
 

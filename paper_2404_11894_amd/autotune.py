@@ -90,10 +90,10 @@ def _propagation_ms(render, image) -> float:
 
 
 def tune_tile(paths: DevicePaths, k: int, g: float = 0.5, probe_D: int = 16, cell_shift: int = 0,
-              margin: float = 0.02) -> tuple[int, int]:
+              margin: float = 0.03) -> tuple[int, int]:
     """The fastest (tile, tile_group) for this scene's propagation (cached);
     the default (256, 1) unless a candidate beats it by more than `margin`
-    (the probe's noise is about a percent)."""
+    (the probe's noise is one to two percent)."""
     import torch
 
     n = paths.n_vertices

@@ -89,6 +89,70 @@ __global__ __launch_bounds__(BS) void k_shift_batched(const SceneDesc* __restric
     st3_nt(d.x, v, val);
 }
 
+// ----------------------------------------- persistent schedule (opt-in) ---
+// PG_FLAG_PERSISTENT: one cooperative launch runs every iteration of every
+// scene, a grid-stride loop over the same virtual blocks as the per-iteration
+// launches, with a grid barrier between the aggregation and the shift and
+// between iterations.  The cooperative launch makes every workgroup resident
+// at once, so every barrier is reached; the wait is still bounded (spin_limit
+// sleeps, about a second): a workgroup that runs out sets the abort word and
+// every workgroup leaves at its next barrier, and the host reports it.  Each
+// barrier is a device-scope release and acquire by every workgroup (the XCDs'
+// L2 caches are not coherent with each other), which costs more than the
+// kernel boundaries of the default schedule.
+__device__ bool grid_barrier(uint32_t* count, uint32_t* abortf, uint32_t target, uint32_t spin_limit) {
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ok = 1;
+        __threadfence();
+        atomicAdd(count, 1u);
+        uint32_t n = 0;
+        while (__hip_atomic_load(count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++n > spin_limit) {
+                atomicOr(abortf, 1u);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+        __threadfence();
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_persistent(const SceneDesc* __restrict__ sd, int nsc, int Dmax,
+                                                             int64_t nblk, uint32_t* bar, uint32_t spin_limit) {
+    uint32_t phase = 0;
+    for (int t = 1; t <= Dmax; ++t) {
+        for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+            const SceneDesc& d = sd[find_scene(sd, nsc, b)];
+            if (t > d.D) continue;
+            const int64_t i = (b - d.blk0) * (int64_t)kBlock + threadIdx.x;
+            if (i >= d.nrows) continue;
+            switch (ell_k4(d.K)) {
+            case 8: spmv_batched_row<8>(d, i); break;
+            case 12: spmv_batched_row<12>(d, i); break;
+            case 16: spmv_batched_row<16>(d, i); break;
+            default: spmv_batched_row<0>(d, i); break;
+            }
+        }
+        if (!grid_barrier(bar, bar + 1, ++phase * gridDim.x, spin_limit)) return;
+        for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+            const SceneDesc& d = sd[find_scene(sd, nsc, b)];
+            if (t > d.D) continue;
+            const int64_t v = (b - d.blk0) * (int64_t)kBlock + threadIdx.x;
+            if (v >= d.nrows) continue;
+            const int64_t u = __builtin_nontemporal_load(d.succ + v);
+            f3 val{0.f, 0.f, 0.f};
+            if (u >= 0) val = ld3(d.y, u);
+            st3_nt(d.x, v, val);
+        }
+        if (!grid_barrier(bar, bar + 1, ++phase * gridDim.x, spin_limit)) return;
+    }
+}
+
 // ------------------------------------------------------------------ host ---
 
 struct BatchLayout {
@@ -101,6 +165,8 @@ struct BatchLayout {
     int64_t blocks = 0;
     std::vector<SceneDesc> host_tables;
     SceneDesc* dev_tables = nullptr;
+    uint32_t* bar = nullptr;   // persistent schedule: barrier counter, abort word
+    bool persistent = false;
     int Dmax = 0;
 };
 
@@ -118,6 +184,7 @@ static void carve_batch(Carver& cv, BatchLayout& L, int n, const pg_paths* paths
     L.host_tables.clear();
     L.Dmax = 0;
     L.tile = params[0].tile ? params[0].tile : kBlock;
+    L.persistent = (params[0].flags & PG_FLAG_PERSISTENT) != 0;
     L.tile_group = params[0].tile_group ? params[0].tile_group : 1;
     int64_t blk = 0;
     for (int s = 0; s < n; ++s) {
@@ -130,6 +197,7 @@ static void carve_batch(Carver& cv, BatchLayout& L, int n, const pg_paths* paths
     }
     L.blocks = blk;
     L.dev_tables = cv.take<SceneDesc>((int64_t)(L.host_tables.size() > 0 ? L.host_tables.size() : 1));
+    L.bar = cv.take<uint32_t>(64);
 }
 
 static pg_status validate_batch(int n, const pg_paths* paths, const pg_params* params) {
@@ -144,12 +212,36 @@ static pg_status validate_batch(int n, const pg_paths* paths, const pg_params* p
         qs.flags &= ~PG_FLAG_TAPE;
         if ((st = validate_clusters(&paths[s], &qs))) return fail(st, "scene %d: %s", s, g_error.c_str());
     }
+    if ((params[0].flags & PG_FLAG_PERSISTENT) && params[0].tile != 0 && params[0].tile != kBlock)
+        return fail(PG_ERR_UNSUPPORTED, "PG_FLAG_PERSISTENT runs workgroups of 256 rows (tile 0 or 256)");
     return PG_OK;
 }
 
 // Phase B: the D iterations of every scene, batched.
 static hipError_t batched_iterations(const BatchLayout& L, hipStream_t s) {
     const int nsc = (int)L.host_tables.size();
+    if (L.persistent && L.blocks > 0 && L.Dmax > 0) {
+        int dev = 0, ncu = 0, per_cu = 0;
+        hipError_t e;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+        if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent, kBlock, 0)) != hipSuccess)
+            return e;
+        int64_t grid = (int64_t)ncu * per_cu;
+        if (grid > L.blocks) grid = L.blocks;
+        if (grid < 1) grid = 1;
+        if ((e = launch_fill(L.bar, 64 * 4, s)) != hipSuccess) return e;
+        const SceneDesc* sdp = L.dev_tables;
+        int nscv = nsc, dmax = L.Dmax;
+        int64_t nblk = L.blocks;
+        uint32_t* bar = L.bar;
+        uint32_t spin = 1u << 22;
+        void* args[] = {(void*)&sdp, (void*)&nscv, (void*)&dmax, (void*)&nblk, (void*)&bar, (void*)&spin};
+        ProfScope ps(s, "batched_persistent");
+        return hipLaunchCooperativeKernel((const void*)k_batch_persistent, dim3((unsigned)grid), dim3(kBlock), args,
+                                          0, s);
+    }
+    if (L.persistent) return hipSuccess;   // nothing to iterate
     for (int t = 1; t <= L.Dmax && L.blocks > 0; ++t) {
         dispatch_tile(L.tile, [&](auto bs) {
             constexpr int BS = decltype(bs)::value;
@@ -378,6 +470,13 @@ pg_status pg_render_batched(int32_t n_scenes, const pg_paths* paths, const pg_pa
     hipStream_t one[1] = {s0};
     if (e == hipSuccess) e = run_batch(paths, L, images, one, 1, nullptr);
     if (e != hipSuccess) return hip_fail(e, "pg_render_batched");
+    if (L.persistent && L.blocks > 0 && L.Dmax > 0) {   // the persistent schedule's abort word
+        uint32_t ab = 0;
+        if ((e = hipMemcpyAsync(&ab, L.bar + 1, sizeof ab, hipMemcpyDeviceToHost, s0)) != hipSuccess ||
+            (e = hipStreamSynchronize(s0)) != hipSuccess)
+            return hip_fail(e, "pg_render_batched");
+        if (ab) return fail(PG_ERR_HIP, "PG_FLAG_PERSISTENT: a grid barrier timed out; the images are not valid");
+    }
     uint32_t fl = 0;
     for (int s = 0; s < n_scenes; ++s) fl |= params[s].flags;
     if (fl & (PG_FLAG_CHECK | PG_FLAG_CLUSTERS)) {   // the cluster relation always reports its checks

@@ -268,3 +268,14 @@ def test_csr_entry_points_refuse_the_cluster_flag_on_the_host():
                      (L.pg_propagate_static, (p, p, p, p, p, None, None))):
         rc, msg = status(fn, ctypes.byref(s), ctypes.byref(q), *args)
         assert rc == pg.PG_ERR_UNSUPPORTED and "k-nearest" in msg, fn
+
+
+def test_persistent_batch_flag_needs_the_default_tile():
+    L = pg.lib()
+    s = (pg.Paths * 1)(fake_paths())
+    q = (pg.Params * 1)(pg.params(k=8, D=4, flags=pg.PG_FLAG_PERSISTENT, tile=512))
+    nb = ctypes.c_size_t()
+    rc, msg = status(L.pg_render_batched_workspace_size, 1, s, q, ctypes.byref(nb))
+    assert rc == pg.PG_ERR_UNSUPPORTED and "PERSISTENT" in msg
+    q[0].tile = 256
+    assert L.pg_render_batched_workspace_size(1, s, q, ctypes.byref(nb)) == 0

@@ -158,3 +158,29 @@ def test_benchmark_batch_matches_oracle_on_sampled_scenes():
         print(f"batch scene {s}: N={sc.n_vertices} k={w.k} D={w.D} g={w.g:.3f}", flush=True)
         ref = oracle.render(sc, oracle.params(k=w.k, D=w.D, g=w.g))
         assert_within(imgs[s].cpu().numpy(), ref, PIX_REL, PIX_ABS, f"batch scene {s} vs oracle")
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_persistent_schedule_equals_default(use_graph):
+    # PG_FLAG_PERSISTENT: every iteration of every scene in one cooperative
+    # launch with grid barriers; the same images bit for bit, eagerly and over
+    # graph replays with other GPU work in between
+    scenes, params, _ = small_batch()
+    paths = [pg.DevicePaths(s) for s in scenes]
+    ref = [im.clone() for im in pg.pg_render_batched(paths, params)]
+    pers = [pg.params(k=p.k, D=p.D, g=p.g, flags=pg.PG_FLAG_PERSISTENT) for p in params]
+    out = pg.pg_render_batched(paths, pers)
+    torch.cuda.synchronize()
+    for s in range(len(scenes)):
+        assert torch.equal(out[s], ref[s]), f"eager scene {s}"
+    plan = pg.Batch(paths, pers, use_graph=use_graph)
+    for rep in range(3):
+        got = plan()
+        torch.cuda.synchronize()
+        for s in range(len(scenes)):
+            assert torch.equal(got[s], ref[s]), f"replay {rep} scene {s}"
+        pg.pg_render(paths[0], params[0])
+        for im in got:
+            im.zero_()
+        torch.cuda.synchronize()
+    plan.close()
