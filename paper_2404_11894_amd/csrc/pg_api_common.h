@@ -176,6 +176,10 @@ struct RenderBufs {
 };
 
 // Reverse-mode buffers, carved right after a render's tape.
+// Window of the transposed operator's in-degree ordering (vertices).
+constexpr int kTWinBits = 7;
+constexpr int kTWin = 1 << kTWinBits;
+
 struct BackBufs {
     int64_t n_rows = 0, n_edge = 0, n_out = 0, n_slots = 0;   // dL/dg partial-sum slots
     float* lam_a = nullptr;    // adjoint of L_t, ping
@@ -185,13 +189,17 @@ struct BackBufs {
     float* bbar = nullptr;     // [N*3]
     float* dptbar = nullptr;   // [N*3]
     float* rbar = nullptr;     // [N]
-    // W^T as sliced ELL (slices of 64 T-rows, at most cap entries per T-row)
+    // W^T as sliced ELL (slices of 64 T-rows, at most cap entries per T-row),
+    // T-rows ordered by in-degree within windows of kTWin vertices
     uint32_t cap = 0;
     int64_t nslices = 0;
     uint32_t* tdeg = nullptr;  // in-degree [N+1]
     uint32_t* tlen = nullptr;  // slice lengths [nslices+1]
     uint8_t* trank = nullptr;  // arrival rank of each edge at its T-row [ell_size(N, K)]
     uint32_t* soff = nullptr;  // slice offsets [nslices+1]
+    int32_t* trow = nullptr;   // position -> vertex [N rounded up to kTWin]
+    int32_t* tpos = nullptr;   // vertex -> position [N]
+    int32_t* ppred = nullptr;  // position of each row's predecessor, -1: none [N]
     uint32_t* tpart = nullptr; // scan partials
     int32_t* tsrc = nullptr;   // [nslices*64*cap] source rows
     float* tw = nullptr;       // [nslices*64*cap]

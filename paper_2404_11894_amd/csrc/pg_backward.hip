@@ -21,18 +21,32 @@ namespace pg {
 
 
 // ------------------------------------------------- transposed operator ---
-// W^T in a sliced ELL: T-row j (the rows i that have j as a neighbour) lives in
-// slice j/64; entry q of the 64 T-rows of a slice is contiguous, and a slice
-// is as long as its longest T-row, capped at `cap` entries.  Entries past the
+// W^T in a sliced ELL over permuted T-rows (the SELL-C-sigma layout of
+// Kreutzer et al., 2014, with C = 64 and sigma = kTWin): within each window
+// of kTWin consecutive vertices, the T-rows (T-row j: the rows i that have j
+// as a neighbour) are ordered by decreasing in-degree, ties by vertex, and
+// T-row j takes position tpos[j] (trow is the inverse).  Position r lives in
+// slice r/64; entry q of a slice's 64 T-rows is contiguous, and a slice is as
+// long as its longest T-row, capped at `cap` entries.  On k-nearest-neighbour
+// graphs the padding is about 45% of the entries with slices of consecutive
+// vertices and about 26% with windows of 128.  Wider windows pad less (4% at
+// 1024) but spread a wave's lanes over more vertices, whose z-bar gathers
+// then share fewer cache lines: the transposed product was 5% faster at 128,
+// 2% at 256, and 18% and 42% slower at 512 and 1024.  Entries past the
 // cap go to an overflow list of (j, i, w) applied with atomics (none for
 // ordinary neighbour graphs; degenerate inputs such as many coincident points
 // can have a few).
 //
-// Built in four passes: in-degrees with atomics, which also give every edge
-// its arrival rank at its T-row (one byte); slice lengths and their scan;
-// every edge stored at its rank (no atomics); each T-row sorted by source row
-// in registers, so the reverse sums run in a fixed order for a given sorted
-// layout.
+// The reverse sweep keeps the adjoint lam of L_t in position order, so the
+// transposed product writes it contiguously: the row kernel reads it through
+// ppred (the predecessor's position), the output and path-traced adjoints
+// through tpos.
+//
+// Built in six passes: in-degrees with atomics, which also give every edge
+// its arrival rank at its T-row (one byte); the windows' order; slice lengths
+// and their scan; every edge stored at its rank (no atomics); each T-row
+// sorted by source row in registers, so the reverse sums run in a fixed order
+// for a given sorted layout; the predecessors' positions.
 
 // Row i and slot l of ELL position e (inverse of eidx); l >= K is padding.
 __device__ inline void ell_slot(int64_t e, int K, int64_t& i, int& l) {
@@ -57,20 +71,56 @@ __global__ __launch_bounds__(kBlock) void k_tcount(int64_t N, int K, int64_t EL,
     rank[e] = (uint8_t)(q < 255u ? q : 255u);
 }
 
+// The order of one window's T-rows: keys (cap - capped in-degree, vertex)
+// sorted ascending by a bitonic network in LDS; vertices past N sort last, so
+// positions below N hold exactly the vertices below N.  One block per window.
+__global__ __launch_bounds__(kBlock) void k_twin_order(int64_t N, uint32_t cap, const uint32_t* __restrict__ deg,
+                                                       int32_t* __restrict__ trow, int32_t* __restrict__ tpos) {
+    __shared__ uint32_t key[kTWin];
+    const int64_t w0 = (int64_t)blockIdx.x * kTWin;
+    for (int t = threadIdx.x; t < kTWin; t += kBlock) {
+        const int64_t j = w0 + t;
+        const uint32_t rk = j < N ? cap - min(deg[j], cap) : cap + 1u;
+        key[t] = (rk << kTWinBits) | (uint32_t)t;
+    }
+    __syncthreads();
+    for (int size = 2; size <= kTWin; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < kTWin / 2; t += kBlock) {
+                const int a = 2 * t - (t & (stride - 1)), b = a + stride;   // a has the stride bit clear
+                const uint32_t ka = key[a], kb = key[b];
+                if ((ka > kb) == ((a & size) == 0)) {
+                    key[a] = kb;
+                    key[b] = ka;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < kTWin; t += kBlock) {
+        const int64_t j = w0 + (key[t] & (kTWin - 1));
+        if (j < N) {
+            trow[w0 + t] = (int32_t)j;
+            tpos[j] = (int32_t)(w0 + t);
+        }
+    }
+}
+
 // slice length = 64 * min(max in-degree of its 64 T-rows, cap); one wave per slice
 __global__ __launch_bounds__(kBlock) void k_tslice_len(int64_t N, int64_t nslices, uint32_t cap,
                                                        const uint32_t* __restrict__ deg,
+                                                       const int32_t* __restrict__ trow,
                                                        uint32_t* __restrict__ len) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t d = j < N ? min(deg[j], cap) : 0u;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t d = r < N ? min(deg[trow[r]], cap) : 0u;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) d = max(d, (uint32_t)__shfl_xor((int)d, o, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0 && (j >> 6) < nslices) len[j >> 6] = d * (uint32_t)kSlice;
+    if ((threadIdx.x & (kWave - 1)) == 0 && (r >> 6) < nslices) len[r >> 6] = d * (uint32_t)kSlice;
 }
 
 __global__ __launch_bounds__(kBlock) void k_tscatter(int64_t N, int K, int64_t EL, uint32_t cap,
                                                      const int32_t* __restrict__ col, const float* __restrict__ w,
-                                                     const uint8_t* __restrict__ rank,
+                                                     const uint8_t* __restrict__ rank, const int32_t* __restrict__ tpos,
                                                      const uint32_t* __restrict__ soff, int32_t* __restrict__ tsrc,
                                                      float* __restrict__ tw, int32_t* __restrict__ ovf,
                                                      float* __restrict__ ovw, uint32_t* __restrict__ novf) {
@@ -84,7 +134,8 @@ __global__ __launch_bounds__(kBlock) void k_tscatter(int64_t N, int K, int64_t E
     const uint32_t q = rank[e];
     const uint32_t o = wave_append(novf, q >= cap);
     if (q < cap) {
-        const int64_t p = (int64_t)soff[j >> 6] + (int64_t)q * kSlice + (j & (kSlice - 1));
+        const int64_t pj = tpos[j];
+        const int64_t p = (int64_t)soff[pj >> 6] + (int64_t)q * kSlice + (pj & (kSlice - 1));
         tsrc[p] = (int32_t)i;
         tw[p] = w[e];
     } else {
@@ -97,15 +148,16 @@ __global__ __launch_bounds__(kBlock) void k_tscatter(int64_t N, int K, int64_t E
 // Each T-row sorted by source row (a fixed summation order), then padded with
 // zero-weight self entries up to its slice's length.  C >= cap: a bitonic
 // network over C register slots (unused slots hold INT_MAX); C = 0: insertion
-// sort in place, for long rows.
+// sort in place, for long rows.  One thread per position.
 template <int C>
 __global__ __launch_bounds__(kBlock) void k_tsort(int64_t N, uint32_t cap, const uint32_t* __restrict__ soff,
-                                                  const uint32_t* __restrict__ deg, int32_t* __restrict__ tsrc,
-                                                  float* __restrict__ tw) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    const int64_t base = (int64_t)soff[j >> 6] + (j & (kSlice - 1));
-    const uint32_t len = (soff[(j >> 6) + 1] - soff[j >> 6]) / kSlice;
+                                                  const uint32_t* __restrict__ deg, const int32_t* __restrict__ trow,
+                                                  int32_t* __restrict__ tsrc, float* __restrict__ tw) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    const int64_t j = trow[r];
+    const int64_t base = (int64_t)soff[r >> 6] + (r & (kSlice - 1));
+    const uint32_t len = (soff[(r >> 6) + 1] - soff[r >> 6]) / kSlice;
     const uint32_t n = min(deg[j], cap);
     if (C > 0) {
         constexpr int CC = C > 0 ? C : 1;
@@ -163,6 +215,15 @@ __global__ __launch_bounds__(kBlock) void k_tsort(int64_t N, uint32_t cap, const
     }
 }
 
+// ppred[i] = position of i's predecessor (-1: none).
+__global__ __launch_bounds__(kBlock) void k_tppred(int64_t N, const int32_t* __restrict__ pred,
+                                                   const int32_t* __restrict__ tpos, int32_t* __restrict__ ppred) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t v = pred[i];
+    ppred[i] = v >= 0 ? tpos[v] : -1;
+}
+
 // ------------------------------------------------- reverse of the output ---
 // One thread per path.  o_p = e + alpha (d + in), in = sum_l w_l L_D(j_l)
 // (own sample: r L_D(v0)), e the constant emission, d = d_pt or the extra
@@ -175,7 +236,8 @@ __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, co
                                                         const float* __restrict__ alpha,
                                                         const float* __restrict__ gimg, float* __restrict__ abar,
                                                         float* __restrict__ dptbar, float* __restrict__ rbar,
-                                                        float* __restrict__ lam, double* __restrict__ gpart) {
+                                                        const int32_t* __restrict__ tpos, float* __restrict__ lam,
+                                                        double* __restrict__ gpart) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double gl = 0.0;
     const int64_t N = P.n_vertices;
@@ -202,9 +264,10 @@ __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, co
                     const f3 xv = ld3(xD, j);
                     in = f3{fmaf(ww, xv.x, in.x), fmaf(ww, xv.y, in.y), fmaf(ww, xv.z, in.z)};
                     ing = f3{fmaf(gg, xv.x, ing.x), fmaf(gg, xv.y, ing.y), fmaf(gg, xv.z, ing.z)};
-                    atomicAdd(&lam[3 * j], ww * zb.x);
-                    atomicAdd(&lam[3 * j + 1], ww * zb.y);
-                    atomicAdd(&lam[3 * j + 2], ww * zb.z);
+                    const int64_t pj = tpos[j];
+                    atomicAdd(&lam[3 * pj], ww * zb.x);
+                    atomicAdd(&lam[3 * pj + 1], ww * zb.y);
+                    atomicAdd(&lam[3 * pj + 2], ww * zb.z);
                 }
                 abar[s0] += dot3(ob, f3{d.x + in.x, d.y + in.y, d.z + in.z});
                 gl += (double)dot3(zb, ing);
@@ -213,9 +276,10 @@ __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, co
                 const float rr = r[s0];
                 abar[s0] += dot3(ob, f3{fmaf(rr, xv.x, d.x), fmaf(rr, xv.y, d.y), fmaf(rr, xv.z, d.z)});
                 rbar[s0] += dot3(zb, xv);
-                atomicAdd(&lam[3 * s0], rr * zb.x);
-                atomicAdd(&lam[3 * s0 + 1], rr * zb.y);
-                atomicAdd(&lam[3 * s0 + 2], rr * zb.z);
+                const int64_t ps = tpos[s0];
+                atomicAdd(&lam[3 * ps], rr * zb.x);
+                atomicAdd(&lam[3 * ps + 1], rr * zb.y);
+                atomicAdd(&lam[3 * ps + 2], rr * zb.z);
             }
             if (!extra) {   // the extra samples replace d_pt in the output
                 dptbar[3 * s0] += zb.x;
@@ -230,7 +294,8 @@ __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, co
 
 // --------------------------------------------- reverse of one iteration ---
 // Row i: y_i = b_i + alpha_i z_i, z_i = sum_l w_il L_{t-1}(j_l), L_t(v) = y(succ v).
-// The adjoint of y_i is lam_t(pred i).  Accumulates d/d alpha_i += <ybar, z_i>
+// The adjoint of y_i is lam_t(pred i), read at the predecessor's position
+// (ppred).  Accumulates d/d alpha_i += <ybar, z_i>
 // and d/d b_i += ybar, stores zbar_i = alpha_i ybar and adds
 // <zbar_i, sum_l dw_il/dg L_{t-1}(j_l)> to the block's dL/dg slot.  One thread
 // per row over the sliced-ELL edges (all K loads issued before the gathers),
@@ -242,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const in
                                                      const int32_t* __restrict__ c16_ovf,
                                                      const float* __restrict__ w, const float* __restrict__ gw,
                                                      const float* __restrict__ xprev, const float* __restrict__ lam,
-                                                     const int32_t* __restrict__ pred,
+                                                     const int32_t* __restrict__ ppred,
                                                      const float* __restrict__ alpha, float* __restrict__ abar,
                                                      float* __restrict__ bbar, float* __restrict__ zbar,
                                                      double* __restrict__ gpart) {
@@ -298,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const in
                 for (int c = 0; c < 4; ++c) acc(jq[c], wq[c], gq[c]);
             }
         }
-        const int64_t pv = __builtin_nontemporal_load(pred + i);
+        const int64_t pv = __builtin_nontemporal_load(ppred + i);
         const f3 yb = pv >= 0 ? ld3(lam, pv) : f3{0.f, 0.f, 0.f};
         abar[i] += dot3(yb, f3{zx, zy, zz});
         bbar[3 * i] += yb.x;
@@ -313,35 +378,39 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const in
     if (threadIdx.x == 0) gpart[tile] += t;
 }
 
-// lam_{t-1}(j) = sum over rows i with j in N(i) of w_ij zbar_i: one thread per
-// T-row over the sliced-ELL transpose (every lane of a wave runs its slice's
-// length, the zero-weight padding included: a per-lane bound measured slower),
-// four entries loaded ahead.
+// lam_{t-1}(j) = sum over rows i with j in N(i) of w_ij zbar_i, stored at j's
+// position r: one thread per position over the sliced-ELL transpose (every
+// lane of a wave runs its slice's length, the zero-weight padding included: a
+// per-lane bound measured slower), eight entries loaded ahead (four: 7% slower).
 __global__ __launch_bounds__(kBlock) void k_rev_cols(int64_t N, const uint32_t* __restrict__ soff,
                                                      const int32_t* __restrict__ tsrc, const float* __restrict__ tw,
                                                      const float* __restrict__ zbar, float* __restrict__ lam) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    const int64_t base = (int64_t)soff[j >> 6] + (j & (kSlice - 1));
-    const uint32_t len = (soff[(j >> 6) + 1] - soff[j >> 6]) / kSlice;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    const int64_t base = (int64_t)soff[r >> 6] + (r & (kSlice - 1));
+    const uint32_t len = (soff[(r >> 6) + 1] - soff[r >> 6]) / kSlice;
     float ax = 0.f, ay = 0.f, az = 0.f;
     uint32_t q = 0;
-    for (; q + 4 <= len; q += 4) {
-        int32_t src[4];
-        float ww[4];
+    auto block = [&](auto n) {   // n entries: all ids and weights loaded, then the gathers in order
+        constexpr int U = decltype(n)::value;
+        int32_t src[U];
+        float ww[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             src[u] = __builtin_nontemporal_load(tsrc + base + (int64_t)(q + u) * kSlice);
             ww[u] = __builtin_nontemporal_load(tw + base + (int64_t)(q + u) * kSlice);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             const f3 zb = ld3(zbar, src[u]);
             ax = fmaf(ww[u], zb.x, ax);
             ay = fmaf(ww[u], zb.y, ay);
             az = fmaf(ww[u], zb.z, az);
         }
-    }
+        q += U;
+    };
+    while (q + 8 <= len) block(std::integral_constant<int, 8>{});
+    if (q + 4 <= len) block(std::integral_constant<int, 4>{});
     for (; q < len; ++q) {
         const f3 zb = ld3(zbar, tsrc[base + (int64_t)q * kSlice]);
         const float ww = tw[base + (int64_t)q * kSlice];
@@ -349,15 +418,16 @@ __global__ __launch_bounds__(kBlock) void k_rev_cols(int64_t N, const uint32_t* 
         ay = fmaf(ww, zb.y, ay);
         az = fmaf(ww, zb.z, az);
     }
-    st3_nt(lam, j, f3{ax, ay, az});
+    st3_nt(lam, r, f3{ax, ay, az});
 }
 
 __global__ __launch_bounds__(kBlock) void k_rev_overflow(const int32_t* __restrict__ ovf, const float* __restrict__ ovw,
                                                          const uint32_t* __restrict__ novf,
+                                                         const int32_t* __restrict__ tpos,
                                                          const float* __restrict__ zbar, float* __restrict__ lam) {
     const uint32_t n = *novf;
     for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < n; o += gridDim.x * blockDim.x) {
-        const int64_t j = ovf[2 * (int64_t)o], i = ovf[2 * (int64_t)o + 1];
+        const int64_t j = tpos[ovf[2 * (int64_t)o]], i = ovf[2 * (int64_t)o + 1];
         const float ww = ovw[o];
         const f3 zb = ld3(zbar, i);
         atomicAdd(&lam[3 * j], ww * zb.x);
@@ -368,11 +438,13 @@ __global__ __launch_bounds__(kBlock) void k_rev_overflow(const int32_t* __restri
 
 // ------------------------------- reverse of the path-traced initial value ---
 // L_0(v) = alpha_u (d_pt_u + r_u L_0(u)), u = succ v.  Walks each path from
-// its first vertex, so lam_0(u) is complete before u passes it on.
+// its first vertex, so lam_0(u) is complete before u passes it on (lam held at
+// the T-row positions tpos; null: at the vertices).
 __global__ __launch_bounds__(kBlock) void k_pt_adjoint(int64_t P, int64_t N, const int64_t* __restrict__ off,
                                                        const int32_t* __restrict__ inv,
                                                        const float* __restrict__ alpha, const float* __restrict__ dpt,
                                                        const float* __restrict__ r, const float* __restrict__ x0,
+                                                       const int32_t* __restrict__ tpos,
                                                        float* __restrict__ lam, float* __restrict__ abar,
                                                        float* __restrict__ dptbar, float* __restrict__ rbar) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -381,7 +453,8 @@ __global__ __launch_bounds__(kBlock) void k_pt_adjoint(int64_t P, int64_t N, con
     if (a < 0 || e < a || e > N) return;
     for (int64_t v = a; v + 1 < e; ++v) {
         const int64_t s = inv[v], u = inv[v + 1];
-        const f3 l = ld3(lam, s);
+        const int64_t pu = tpos ? tpos[u] : u;
+        const f3 l = ld3(lam, tpos ? tpos[s] : s);
         const float al = alpha[u], rr = r[u];
         const f3 d = ld3(dpt, u), xu = ld3(x0, u);
         abar[u] += dot3(l, f3{fmaf(rr, xu.x, d.x), fmaf(rr, xu.y, d.y), fmaf(rr, xu.z, d.z)});
@@ -389,9 +462,9 @@ __global__ __launch_bounds__(kBlock) void k_pt_adjoint(int64_t P, int64_t N, con
         dptbar[3 * u + 1] += al * l.y;
         dptbar[3 * u + 2] += al * l.z;
         rbar[u] += al * dot3(l, xu);
-        lam[3 * u] = fmaf(al * rr, l.x, lam[3 * u]);
-        lam[3 * u + 1] = fmaf(al * rr, l.y, lam[3 * u + 1]);
-        lam[3 * u + 2] = fmaf(al * rr, l.z, lam[3 * u + 2]);
+        lam[3 * pu] = fmaf(al * rr, l.x, lam[3 * pu]);
+        lam[3 * pu + 1] = fmaf(al * rr, l.y, lam[3 * pu + 1]);
+        lam[3 * pu + 2] = fmaf(al * rr, l.z, lam[3 * pu + 2]);
     }
 }
 
@@ -621,6 +694,9 @@ void carve_back(Carver& cv, BackBufs& bb, const RenderBufs& r, const pg_paths* p
     bb.tlen = cv.take<uint32_t>(bb.nslices + 1);
     bb.trank = cv.take<uint8_t>(ell_size(N, r.K));
     bb.soff = cv.take<uint32_t>(bb.nslices + 1);
+    bb.trow = cv.take<int32_t>(div_up(N > 0 ? N : 1, kTWin) * kTWin);
+    bb.tpos = cv.take<int32_t>(N > 0 ? N : 1);
+    bb.ppred = cv.take<int32_t>(N > 0 ? N : 1);
     bb.tpart = cv.take<uint32_t>(scan_partials_bytes(bb.nslices + 1) / 4);
     bb.tsrc = cv.take<int32_t>(bb.nslices * kSlice * (int64_t)bb.cap);
     bb.tw = cv.take<float>(bb.nslices * kSlice * (int64_t)bb.cap);
@@ -673,8 +749,8 @@ static hipError_t run_backward_clusters(const pg_paths* p, const pg_params* q, R
     if (q->init == PG_INIT_PT && N > 0) {
         ProfScope ps(s, "pt_adjoint");
         hipLaunchKernelGGL(k_pt_adjoint, dim3((unsigned)div_up(r.P > 0 ? r.P : 1, kBlock)), dim3(kBlock), 0, s,
-                           r.P, N, p->path_offsets, r.cl.cinv, r.alpha, r.dpt, r.r, r.traj, lam, bb.abar, bb.dptbar,
-                           bb.rbar);
+                           r.P, N, p->path_offsets, r.cl.cinv, r.alpha, r.dpt, r.r, r.traj, (const int32_t*)nullptr,
+                           lam, bb.abar, bb.dptbar, bb.rbar);
         PG_TRY(hipGetLastError());
     }
     {
@@ -723,20 +799,25 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
         const int64_t EL = ell_size(N, K);
         hipLaunchKernelGGL(k_tcount, dim3((unsigned)div_up(EL, kBlock)), dim3(kBlock), 0, s, N, K, EL, r.col,
                            bb.tdeg, bb.trank);
+        hipLaunchKernelGGL(k_twin_order, dim3((unsigned)div_up(N, kTWin)), dim3(kBlock), 0, s, N, bb.cap, bb.tdeg,
+                           bb.trow, bb.tpos);
         hipLaunchKernelGGL(k_tslice_len, dim3((unsigned)div_up(bb.nslices * kSlice, kBlock)), dim3(kBlock), 0, s,
-                           N, bb.nslices, bb.cap, bb.tdeg, bb.tlen);
+                           N, bb.nslices, bb.cap, bb.tdeg, bb.trow, bb.tlen);
         PG_TRY(launch_scan_exclusive(bb.tlen, bb.soff, bb.nslices, bb.tpart, s));
         hipLaunchKernelGGL(k_tscatter, dim3((unsigned)div_up(EL, kBlock)), dim3(kBlock), 0, s, N, K, EL, bb.cap,
-                           r.col, r.w, bb.trank, bb.soff, bb.tsrc, bb.tw, bb.ovf, bb.ovw, bb.novf);
+                           r.col, r.w, bb.trank, bb.tpos, bb.soff, bb.tsrc, bb.tw, bb.ovf, bb.ovw, bb.novf);
         auto sort = [&](auto c) {
             constexpr int C = decltype(c)::value;
             hipLaunchKernelGGL(k_tsort<C>, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.cap,
-                               (const uint32_t*)bb.soff, (const uint32_t*)bb.tdeg, bb.tsrc, bb.tw);
+                               (const uint32_t*)bb.soff, (const uint32_t*)bb.tdeg, (const int32_t*)bb.trow,
+                               bb.tsrc, bb.tw);
         };
         if (bb.cap <= 8) sort(std::integral_constant<int, 8>{});
         else if (bb.cap <= 16) sort(std::integral_constant<int, 16>{});
         else if (bb.cap <= 32) sort(std::integral_constant<int, 32>{});
         else sort(std::integral_constant<int, 0>{});
+        hipLaunchKernelGGL(k_tppred, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, r.pred,
+                           (const int32_t*)bb.tpos, bb.ppred);
         PG_TRY(hipGetLastError());
     }
     const float* xD = r.traj + (size_t)D * N * 3;
@@ -746,7 +827,7 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
     {
         ProfScope ps(s, "out_adjoint");
         hipLaunchKernelGGL(k_out_adjoint, dim3((unsigned)bb.n_out), dim3(kBlock), 0, s, *p, c, r.g.inv, r.col, r.w,
-                           r.gw, xD, r.dpt, r.r, r.alpha, gimg, bb.abar, bb.dptbar, bb.rbar, bb.lam_a, g_out);
+                           r.gw, xD, r.dpt, r.r, r.alpha, gimg, bb.abar, bb.dptbar, bb.rbar, bb.tpos, bb.lam_a, g_out);
         PG_TRY(hipGetLastError());
     }
     float* lam = bb.lam_a;
@@ -759,11 +840,11 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
                 constexpr int KT = decltype(kt)::value;
                 if (KT > 0 && r.c16)
                     hipLaunchKernelGGL((k_rev_rows<KT, true>), dim3((unsigned)bb.n_rows), dim3(kBlock), 0, s, N, K,
-                                       r.col, r.c16, r.c16_base, r.c16_ovf, r.w, r.gw, xprev, lam, r.pred, r.alpha,
+                                       r.col, r.c16, r.c16_base, r.c16_ovf, r.w, r.gw, xprev, lam, bb.ppred, r.alpha,
                                        bb.abar, bb.bbar, bb.zbar, g_rows);
                 else
                     hipLaunchKernelGGL((k_rev_rows<KT, false>), dim3((unsigned)bb.n_rows), dim3(kBlock), 0, s, N, K,
-                                       r.col, r.c16, r.c16_base, r.c16_ovf, r.w, r.gw, xprev, lam, r.pred, r.alpha,
+                                       r.col, r.c16, r.c16_base, r.c16_ovf, r.w, r.gw, xprev, lam, bb.ppred, r.alpha,
                                        bb.abar, bb.bbar, bb.zbar, g_rows);
             };
             switch (ell_k4(K)) {
@@ -777,8 +858,8 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
             ProfScope ps(s, "rev_cols");
             hipLaunchKernelGGL(k_rev_cols, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.soff,
                                bb.tsrc, bb.tw, bb.zbar, lam_next);
-            hipLaunchKernelGGL(k_rev_overflow, dim3(64), dim3(kBlock), 0, s, bb.ovf, bb.ovw, bb.novf, bb.zbar,
-                               lam_next);
+            hipLaunchKernelGGL(k_rev_overflow, dim3(64), dim3(kBlock), 0, s, bb.ovf, bb.ovw, bb.novf, bb.tpos,
+                               bb.zbar, lam_next);
         }
         PG_TRY(hipGetLastError());
         float* tmp = lam;
@@ -788,8 +869,8 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
     if (q->init == PG_INIT_PT && N > 0) {
         ProfScope ps(s, "pt_adjoint");
         hipLaunchKernelGGL(k_pt_adjoint, dim3((unsigned)div_up(r.P > 0 ? r.P : 1, kBlock)), dim3(kBlock), 0, s,
-                           r.P, N, p->path_offsets, r.g.inv, r.alpha, r.dpt, r.r, r.traj, lam, bb.abar, bb.dptbar,
-                           bb.rbar);
+                           r.P, N, p->path_offsets, r.g.inv, r.alpha, r.dpt, r.r, r.traj, (const int32_t*)bb.tpos,
+                           lam, bb.abar, bb.dptbar, bb.rbar);
         PG_TRY(hipGetLastError());
     }
     if (N > 0) {
