@@ -77,13 +77,16 @@ def kernel_source_hash(kernel="spmv"):
     return hsh.hexdigest()
 
 
-def read_traffic(kernel, workload):
+def read_traffic(kernel, workload, variant=None):
     """HBM bytes per launch measured with rocprofv3 counters, if the summary
-    under profiles/ was taken from the current kernel source."""
+    under profiles/ was taken from the current kernel source (and, with
+    `variant`, names that kernel in its title)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
+    if variant is not None and variant not in text.splitlines()[0]:
+        return None
     m = re.search(r"bytes_per_launch:\s*([0-9.eE+]+)", text)
     h = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
     if not m or not h:
@@ -149,16 +152,17 @@ def host_cpu():
     return {"model": model, "logical_cpus": os.cpu_count()}
 
 
-def time_fwd_adjoint(pg, torch, sc, w, steps, warmup):
+def time_fwd_adjoint(pg, torch, sc, w, steps, warmup, store_z=True):
     """The differentiation workload: the same paths, albedo from a 64^3 grid
     (U[0.95, 0.999], seed 2), loss = sum (I - T)^2 against a seeded target.
-    One step = pg_render with the tape + pg_backward on it.  Counts 2 E D."""
+    One step = pg_render with the tape (and, with store_z, every iteration's
+    neighbour sums) + pg_backward on it.  Counts 2 E D."""
     import ctypes as C
     import scenegen
     dev = torch.device("cuda:0")
     grid = scenegen.albedo_grid(64, 0.95, 0.999, seed=2)
     paths = pg.DevicePaths(sc, device=dev, albedo_grid=grid)
-    q = pg.params(k=w.k, D=w.D, g=w.g, flags=pg.PG_FLAG_TAPE)
+    q = pg.params(k=w.k, D=w.D, g=w.g, flags=pg.PG_FLAG_TAPE | (pg.PG_FLAG_STORE_Z if store_z else 0))
     s = paths.struct()
     nb = C.c_size_t()
     pg._check(pg.lib().pg_render_workspace_size(C.byref(s), C.byref(q), C.byref(nb)))
@@ -187,22 +191,27 @@ def time_fwd_adjoint(pg, torch, sc, w, steps, warmup):
     K = min(w.k, N)
     E = N * K
     # the reverse sweep's kernels against the HBM peak, by algorithmic bytes:
-    # rev_rows per row: compact ids + weights + dw/dg (2K + 4K + 4K), x_{t-1}
-    # gather 12, lambda gather at the predecessor 12 + its id 4, albedo 4,
-    # dL/dalpha and dL/db each read and written (2 x 4 + 2 x 12), zbar write
-    # 12: 10K + 76, plus the far ids' side list; rev_cols per T-row: source id
-    # + weight per entry (8K over the real entries), zbar gather 12, lambda
-    # write 12
+    # rev_rows per row, recomputing the sums: compact ids + weights + dw/dg
+    # (2K + 4K + 4K), x_{t-1} gather 12, lambda gather at the predecessor 12 +
+    # its position 4, albedo 4, dL/dalpha and dL/db each read and written
+    # (2 x 4 + 2 x 12), zbar write 12: 10K + 76, plus the far ids' side list;
+    # reading the stored sums instead: z and dz/dg 24 + the same 64 = 88;
+    # rev_cols per T-row: source id + weight per entry (8K over the real
+    # entries), zbar gather 12, lambda write 12.  With the stored sums the
+    # forward's aggregation also reads dw/dg (4K) and writes the sums (24).
     nf = torch.zeros(1, dtype=torch.int64, device=dev)
     qn = pg.params(k=w.k, D=0, g=w.g)
     pg.Renderer(paths, qn)(graph={"n_far": nf})
     n_far = int(nf.item())
     rev = {}
-    for name, ab in (("rev_rows", N * (10 * K + 76) + 4 * n_far), ("rev_cols", N * (8 * K + 24))):
+    taped = store_z and K >= 5 and K <= 16
+    rows_bytes = 88 * N if taped else N * (10 * K + 76) + 4 * n_far
+    for name, ab in (("rev_rows", rows_bytes), ("rev_cols", N * (8 * K + 24))):
         if name in prof:
             cnt, tot, _ = prof[name]
             avg = tot / cnt / 1e3
-            tr = read_traffic(name, w.name)
+            variant = None if name != "rev_rows" else ("k_rev_rows_taped" if taped else "k_rev_rows<")
+            tr = read_traffic(name, w.name, variant)
             rev[name] = {"avg_launch_ms": round(avg * 1e3, 4), "algorithmic_bytes_per_launch": ab,
                          "achieved_GBs": round(ab / avg / 1e9, 1), "hbm_frac": round(ab / avg / 1e9 / HBM_PEAK_GBS, 4),
                          "traffic": tr, "traffic_GBs": round(tr / avg / 1e9, 1) if tr else None}
@@ -210,6 +219,14 @@ def time_fwd_adjoint(pg, torch, sc, w, steps, warmup):
         t_it = rev["rev_rows"]["avg_launch_ms"] + rev["rev_cols"]["avg_launch_ms"]
         b_it = rev["rev_rows"]["algorithmic_bytes_per_launch"] + rev["rev_cols"]["algorithmic_bytes_per_launch"]
         rev["iteration"] = {"ms": round(t_it, 4), "hbm_frac": round(b_it / (t_it / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if taped and "spmv" in prof:
+        cnt, tot, _ = prof["spmv"]
+        avg = tot / cnt / 1e3
+        ab = N * (12 * K + 64)
+        rev["taped_aggregation"] = {"avg_launch_ms": round(avg * 1e3, 4), "algorithmic_bytes_per_launch": ab,
+                                    "hbm_frac": round(ab / avg / 1e9 / HBM_PEAK_GBS, 4),
+                                    "bytes": "(8K + 40) N of the aggregation + 4K N (dw/dg) + 24 N (z, dz/dg)"}
+    rev["stored_sums"] = bool(taped)
     ok = bool(torch.isfinite(out["grad_grid"]).all().item()) and bool(torch.isfinite(out["grad_g"]).all().item())
     del ws, paths
     torch.cuda.empty_cache()
@@ -730,6 +747,13 @@ def main():
             log("timing forward + adjoint")
             out["fwd_adjoint"] = time_fwd_adjoint(pg, torch, scm, wm, max(2, args.steps // 2), 1)
             log(f"fwd+adjoint {out['fwd_adjoint']['ms_per_step']} ms/step")
+            torch.cuda.empty_cache()
+            alt = time_fwd_adjoint(pg, torch, scm, wm, max(2, args.steps // 4), 1, store_z=False)
+            out["fwd_adjoint"]["recomputing_sums"] = {
+                "ms_per_step": alt["ms_per_step"], "value": alt["value"], "reverse": alt["reverse"],
+                "note": "without PG_FLAG_STORE_Z: the reverse rows gather x_(t-1) again instead of reading the "
+                        "forward's stored sums (24 D N bytes less workspace)"}
+            log(f"fwd+adjoint recomputing the sums {alt['ms_per_step']} ms/step")
         del scm
     if not args.no_batched:
         torch.cuda.empty_cache()

@@ -77,6 +77,14 @@ typedef int32_t pg_status;
                                    tile 0 or 256.  pg_render_batched reports a timed-out barrier
                                    as PG_ERR_HIP; a pg_batch plan does not check. */
 
+#define PG_FLAG_STORE_Z 32u  /* with PG_FLAG_TAPE (pg_render, and pg_backward, which sets the tape
+                                itself): the forward also keeps every iteration's neighbour sums
+                                z_t = W x_(t-1) and dz_t/dg (6 floats per vertex per iteration,
+                                24 D N bytes more workspace), so the reverse sweep reads them
+                                instead of gathering x_(t-1) again.  Same gradients bit for bit.
+                                Taken when the two-pass schedule runs on the compact ids with
+                                K rounded up to 8, 12 or 16; otherwise no effect. */
+
 #define PG_SCHED_TWO_PASS 1  /* aggregate over spatially sorted rows, then shift along paths */
 #define PG_SCHED_SHIFTED  2  /* rows pre-arranged in predecessor order: one pass per iteration */
 #define PG_SCHED_SCATTER  3  /* sorted rows; each writes its result straight to its predecessor */
@@ -153,8 +161,10 @@ typedef struct pg_params {
     /* Launch shape of the propagation kernels (pg_render's iterations and the
      * batched ones); any value gives bit-identical results.  0 = default. */
     int32_t tile;           /* workgroup size of the aggregation (one row per thread) and the
-                               shift (two vertices per thread): 64, 128, 256 (default), 512 or
-                               1024 */
+                               shift (two vertices per thread): 64, 128, 256, 512 or 1024;
+                               default 512 in pg_render and its reverse mode, 256 in a batch
+                               (the first scene's params set the batch's tile); pg_propagate's
+                               path-order product has a fixed shape */
     int32_t tile_group;     /* consecutive row tiles each XCD takes in turn in the aggregation
                                (the hardware hands workgroup b to XCD b mod 8): 1 (default) =
                                plain launch order, G > 1 = tiles [8Gc + Gx, 8Gc + G(x + 1)) go

@@ -19,6 +19,7 @@ from ._build import LIB_PATH, build  # noqa: F401
 PG_OK, PG_ERR_ARG, PG_ERR_WORKSPACE, PG_ERR_HIP, PG_ERR_INPUT, PG_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 PG_INIT_PT, PG_INIT_ZERO = 0, 1
 PG_FLAG_CHECK, PG_FLAG_TAPE, PG_FLAG_EXACT_KNN, PG_FLAG_CLUSTERS, PG_FLAG_PERSISTENT = 1, 2, 4, 8, 16
+PG_FLAG_STORE_Z = 32
 PG_SCHED_TWO_PASS, PG_SCHED_SHIFTED, PG_SCHED_SCATTER = 1, 2, 3
 PG_MAX_K = 64
 
@@ -605,7 +606,8 @@ class Batch:
             # the batched iterations are one launch shape for all scenes: tuned on the largest
             big = max(range(len(params_list)), key=lambda s: self.paths_list[s].n_vertices)
             qb = params_list[big]
-            tile, group = autotune.tune_tile(self.paths_list[big], qb.k, qb.g, cell_shift=qb.cell_shift)
+            tile, group = autotune.tune_tile(self.paths_list[big], qb.k, qb.g, cell_shift=qb.cell_shift,
+                                             default=autotune.BATCH_DEFAULT)
             for q in params_list:
                 q.tile, q.tile_group = tile, group
             self.tuned = {"cell_shift": shifts, "tile": tile, "tile_group": group}

@@ -89,20 +89,25 @@ def _propagation_ms(render, image) -> float:
     return sum(arr[i].total_ms for i in range(min(n.value, 64)) if arr[i].name in (b"spmv", b"shift"))
 
 
+SCENE_DEFAULT = (512, 1)   # pg_render's launch shape when params.tile = 0
+BATCH_DEFAULT = (256, 1)   # a batch's
+
+
 def tune_tile(paths: DevicePaths, k: int, g: float = 0.5, probe_D: int = 16, cell_shift: int = 0,
-              margin: float = 0.03) -> tuple[int, int]:
+              margin: float = 0.03, default: tuple = SCENE_DEFAULT) -> tuple[int, int]:
     """The fastest (tile, tile_group) for this scene's propagation (cached);
-    the default (256, 1) unless a candidate beats it by more than `margin`
-    (the probe's noise is one to two percent)."""
+    `default` unless a candidate beats it by more than `margin` (the probe's
+    noise is one to two percent)."""
     import torch
 
     n = paths.n_vertices
-    key = _key(n, k, "tile")
+    default = tuple(default)
+    key = _key(n, k, f"tile{default[0]}")
     if key in _cache:
         return tuple(_cache[key])
     if n < 65536:                      # a few waves per XCD: the launch shape hardly matters
-        _cache[key] = (256, 1)
-        return 256, 1
+        _cache[key] = default
+        return default
     image = torch.empty(paths.height, paths.width, 3, device=paths.device)
     times = {}
     for t in TILES:
@@ -113,8 +118,8 @@ def tune_tile(paths: DevicePaths, k: int, g: float = 0.5, probe_D: int = 16, cel
             del r
     torch.cuda.empty_cache()
     best = min(times, key=times.get)
-    if times[best] > (1.0 - margin) * times[(256, 1)]:
-        best = (256, 1)
+    if times[best] > (1.0 - margin) * times[default]:
+        best = default
     _cache[key] = best
     return best
 

@@ -77,7 +77,8 @@ pg_status validate_params(const pg_params* q) {
     if (q->tile != 0 && q->tile != 64 && q->tile != 128 && q->tile != 256 && q->tile != 512 && q->tile != 1024)
         return fail(PG_ERR_ARG, "tile = %d: 0, 64, 128, 256, 512 or 1024", q->tile);
     if (q->tile_group < 0 || q->tile_group > 65536) return fail(PG_ERR_ARG, "tile_group must be in [0, 65536]");
-    if (q->flags & ~(PG_FLAG_CHECK | PG_FLAG_TAPE | PG_FLAG_EXACT_KNN | PG_FLAG_CLUSTERS | PG_FLAG_PERSISTENT))
+    if (q->flags & ~(PG_FLAG_CHECK | PG_FLAG_TAPE | PG_FLAG_EXACT_KNN | PG_FLAG_CLUSTERS | PG_FLAG_PERSISTENT |
+                      PG_FLAG_STORE_Z))
         return fail(PG_ERR_ARG, "unknown flag bits");
     return PG_OK;
 }

@@ -170,10 +170,17 @@ struct RenderBufs {
     float* mw = nullptr;
     float* c = nullptr;
     float* traj = nullptr;    // [(D+1)*N*3] (tape)
+    float* zt = nullptr;      // [D*N*6] neighbour sums z_t and dz_t/dg per iteration (tape + PG_FLAG_STORE_Z)
     bool clusters = false;    // cluster neighbour relation: the render runs in cluster order
     ClusterBufs cl;
     ClusterRender cr;
 };
+
+// The taped two-pass aggregation that also stores z and dz/dg (zt, six floats
+// per row) for the reverse sweep (pg_backward.hip); K4 in {8, 12, 16}.
+hipError_t launch_spmv_c16_tape(int64_t N, int K, const int16_t* c16, const uint32_t* c16_base, const int32_t* ovf,
+                                const float* w, const float* gw, const float* x, const float* b, const float* alpha,
+                                float* y, float* zt, hipStream_t s, int tile, int tile_group);
 
 // Reverse-mode buffers, carved right after a render's tape.
 // Window of the transposed operator's in-degree ordering (vertices).

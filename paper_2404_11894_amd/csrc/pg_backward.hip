@@ -292,6 +292,67 @@ __global__ __launch_bounds__(kBlock) void k_out_adjoint(pg_paths P, Consts c, co
     if (threadIdx.x == 0) gpart[blockIdx.x] = t;
 }
 
+// ------------------------------------------ forward with the sums kept ---
+// The two-pass aggregation of a taped render that also keeps, per row, the
+// neighbour sum z_i = sum_l w_il x(j_l) and its g-derivative
+// zg_i = sum_l dw_il/dg x(j_l) (z then zg, six floats) for the reverse
+// sweep.  z takes the same slots and FMAs as k_spmv_c16, so y is the same bit
+// for bit; zg the same as the recomputing k_rev_rows.
+template <int KT, int BS>
+__global__ __launch_bounds__(BS) void k_spmv_c16_tape(int64_t N, int K, const int16_t* __restrict__ c16,
+                                                      const uint32_t* __restrict__ c16_base,
+                                                      const int32_t* __restrict__ ovf, const float* __restrict__ w,
+                                                      const float* __restrict__ gw, const float* __restrict__ x,
+                                                      const float* __restrict__ b, const float* __restrict__ alpha,
+                                                      float* __restrict__ y, float* __restrict__ zt, int group) {
+    const int64_t tile = grouped_tile(blockIdx.x, gridDim.x, group);
+    const int64_t i = tile * BS + threadIdx.x;
+    if (i >= N) return;
+    constexpr int NQ = KT / 4;
+    const int64_t base = ell_row(i, K);
+    f32x4 ww[NQ], gg[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        ww[q] = ld_quad_nt(w + base + q * kQuadStride);
+        gg[q] = ld_quad_nt(gw + base + q * kQuadStride);
+    }
+    int32_t j[KT];
+    c16_row_ids<KT>(i, K, c16, c16_base, ovf, j);
+    float ax = 0.f, ay = 0.f, az = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+    for (int l = 0; l < KT; ++l) {
+        const f3 xv = ld3(x, j[l]);
+        const float wl = ww[l >> 2][l & 3], gl = gg[l >> 2][l & 3];
+        ax = fmaf(wl, xv.x, ax);
+        ay = fmaf(wl, xv.y, ay);
+        az = fmaf(wl, xv.z, az);
+        gx = fmaf(gl, xv.x, gx);
+        gy = fmaf(gl, xv.y, gy);
+        gz = fmaf(gl, xv.z, gz);
+    }
+    const f3 bb = ld3(b, i);
+    const float a = alpha[i];
+    st3_nt(y, i, f3{fmaf(a, ax, bb.x), fmaf(a, ay, bb.y), fmaf(a, az, bb.z)});
+    st3_nt(zt, 2 * i, f3{ax, ay, az});
+    st3_nt(zt, 2 * i + 1, f3{gx, gy, gz});
+}
+
+hipError_t launch_spmv_c16_tape(int64_t N, int K, const int16_t* c16, const uint32_t* c16_base, const int32_t* ovf,
+                                const float* w, const float* gw, const float* x, const float* b, const float* alpha,
+                                float* y, float* zt, hipStream_t s, int tile, int tile_group) {
+    if (N == 0) return hipSuccess;
+    dispatch_tile(tile, [&](auto bs) {
+        constexpr int BS = decltype(bs)::value;
+        switch (ell_k4(K)) {
+        case 8: hipLaunchKernelGGL((k_spmv_c16_tape<8, BS>), dim3((unsigned)div_up(N, BS)), dim3(BS), 0, s, N, K, c16, c16_base, ovf, w, gw, x, b, alpha, y, zt, tile_group); break;
+        case 12: hipLaunchKernelGGL((k_spmv_c16_tape<12, BS>), dim3((unsigned)div_up(N, BS)), dim3(BS), 0, s, N, K, c16, c16_base, ovf, w, gw, x, b, alpha, y, zt, tile_group); break;
+        case 16: hipLaunchKernelGGL((k_spmv_c16_tape<16, BS>), dim3((unsigned)div_up(N, BS)), dim3(BS), 0, s, N, K, c16, c16_base, ovf, w, gw, x, b, alpha, y, zt, tile_group); break;
+        default: break;   // not carved for other K4 (see sums_taped)
+        }
+    });
+    return hipGetLastError();
+}
+
 // --------------------------------------------- reverse of one iteration ---
 // Row i: y_i = b_i + alpha_i z_i, z_i = sum_l w_il L_{t-1}(j_l), L_t(v) = y(succ v).
 // The adjoint of y_i is lam_t(pred i), read at the predecessor's position
@@ -373,6 +434,35 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows(int64_t N, int Kr, const in
         const f3 zb{al * yb.x, al * yb.y, al * yb.z};
         st3_nt(zbar, i, zb);
         gl = (double)dot3(zb, f3{gx, gy, gz});
+    }
+    const double t = block_sum_d(gl);
+    if (threadIdx.x == 0) gpart[tile] += t;
+}
+
+// k_rev_rows with z_i and zg_i read from the forward's tape (zt: six floats
+// per row) instead of gathered again: the same values, the same updates and
+// the same block partials, so the same results bit for bit.
+__global__ __launch_bounds__(kBlock) void k_rev_rows_taped(int64_t N, const float* __restrict__ zt,
+                                                           const float* __restrict__ lam,
+                                                           const int32_t* __restrict__ ppred,
+                                                           const float* __restrict__ alpha, float* __restrict__ abar,
+                                                           float* __restrict__ bbar, float* __restrict__ zbar,
+                                                           double* __restrict__ gpart) {
+    const int64_t tile = blockIdx.x;
+    const int64_t i = tile * kBlock + threadIdx.x;
+    double gl = 0.0;
+    if (i < N) {
+        const f3 z = ld3(zt, 2 * i), zg = ld3(zt, 2 * i + 1);
+        const int64_t pv = __builtin_nontemporal_load(ppred + i);
+        const f3 yb = pv >= 0 ? ld3(lam, pv) : f3{0.f, 0.f, 0.f};
+        abar[i] += dot3(yb, z);
+        bbar[3 * i] += yb.x;
+        bbar[3 * i + 1] += yb.y;
+        bbar[3 * i + 2] += yb.z;
+        const float al = alpha[i];
+        const f3 zb{al * yb.x, al * yb.y, al * yb.z};
+        st3_nt(zbar, i, zb);
+        gl = (double)dot3(zb, zg);
     }
     const double t = block_sum_d(gl);
     if (threadIdx.x == 0) gpart[tile] += t;
@@ -834,7 +924,12 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
     float* lam_next = bb.lam_b;
     for (int t = D; t >= 1 && N > 0; --t) {
         const float* xprev = r.traj + (size_t)(t - 1) * N * 3;
-        {
+        if (r.zt) {
+            ProfScope ps(s, "rev_rows");
+            hipLaunchKernelGGL(k_rev_rows_taped, dim3((unsigned)bb.n_rows), dim3(kBlock), 0, s, N,
+                               (const float*)(r.zt + (size_t)(t - 1) * N * 6), (const float*)lam,
+                               (const int32_t*)bb.ppred, (const float*)r.alpha, bb.abar, bb.bbar, bb.zbar, g_rows);
+        } else {
             ProfScope ps(s, "rev_rows");
             auto go = [&](auto kt) {
                 constexpr int KT = decltype(kt)::value;

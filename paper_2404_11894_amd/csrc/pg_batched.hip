@@ -32,6 +32,18 @@ struct SceneDesc {
     int32_t K, D;
 };
 
+// Blocks of the scenes still iterating at step t: the tables are ordered by
+// decreasing D, so those scenes are a prefix.
+__host__ __device__ inline int64_t active_blocks(const SceneDesc* sd, int n, int t, int64_t nblk) {
+    int lo = 0, hi = n;   // first entry with D < t
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sd[mid].D >= t) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < n ? sd[lo].blk0 : nblk;
+}
+
 __device__ inline int find_scene(const SceneDesc* sd, int n, int64_t blk) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
@@ -126,7 +138,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_persistent(const SceneDesc* __
                                                              int64_t nblk, uint32_t* bar, uint32_t spin_limit) {
     uint32_t phase = 0;
     for (int t = 1; t <= Dmax; ++t) {
-        for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int64_t nb = active_blocks(sd, nsc, t, nblk);
+        for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
             const SceneDesc& d = sd[find_scene(sd, nsc, b)];
             if (t > d.D) continue;
             const int64_t i = (b - d.blk0) * (int64_t)kBlock + threadIdx.x;
@@ -139,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_persistent(const SceneDesc* __
             }
         }
         if (!grid_barrier(bar, bar + 1, ++phase * gridDim.x, spin_limit)) return;
-        for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
             const SceneDesc& d = sd[find_scene(sd, nsc, b)];
             if (t > d.D) continue;
             const int64_t v = (b - d.blk0) * (int64_t)kBlock + threadIdx.x;
@@ -186,10 +199,15 @@ static void carve_batch(Carver& cv, BatchLayout& L, int n, const pg_paths* paths
     L.tile = params[0].tile ? params[0].tile : kBlock;
     L.persistent = (params[0].flags & PG_FLAG_PERSISTENT) != 0;
     L.tile_group = params[0].tile_group ? params[0].tile_group : 1;
+    // tables in decreasing order of D (ties by scene), so that the scenes
+    // still iterating at any step own a prefix of the blocks
+    std::vector<int> order;
+    for (int s = 0; s < n; ++s)
+        if (L.r[s].N > 0 && !L.r[s].clusters) order.push_back(s);   // cluster scenes iterate on their own stream
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return L.r[a].D > L.r[b].D; });
     int64_t blk = 0;
-    for (int s = 0; s < n; ++s) {
+    for (int s : order) {
         const RenderBufs& r = L.r[s];
-        if (r.N == 0 || r.clusters) continue;   // cluster scenes iterate on their own stream
         if (r.D > L.Dmax) L.Dmax = r.D;
         SceneDesc d{r.col, r.c16, r.c16_base, r.c16_ovf, r.w, r.b, r.alpha, r.succ, r.x, r.y, r.N, blk, r.K, r.D};
         L.host_tables.push_back(d);
@@ -243,15 +261,16 @@ static hipError_t batched_iterations(const BatchLayout& L, hipStream_t s) {
     }
     if (L.persistent) return hipSuccess;   // nothing to iterate
     for (int t = 1; t <= L.Dmax && L.blocks > 0; ++t) {
+        const int64_t nb = active_blocks(L.host_tables.data(), nsc, t, L.blocks);   // scenes with D >= t
         dispatch_tile(L.tile, [&](auto bs) {
             constexpr int BS = decltype(bs)::value;
             {
                 ProfScope ps(s, "spmv_batched");
-                hipLaunchKernelGGL(k_spmv_batched<BS>, dim3((unsigned)L.blocks), dim3(BS), 0, s, L.dev_tables, nsc,
-                                   t, L.tile_group);
+                hipLaunchKernelGGL(k_spmv_batched<BS>, dim3((unsigned)nb), dim3(BS), 0, s, L.dev_tables, nsc, t,
+                                   L.tile_group);
             }
             ProfScope ps(s, "shift_batched");
-            hipLaunchKernelGGL(k_shift_batched<BS>, dim3((unsigned)L.blocks), dim3(BS), 0, s, L.dev_tables, nsc, t);
+            hipLaunchKernelGGL(k_shift_batched<BS>, dim3((unsigned)nb), dim3(BS), 0, s, L.dev_tables, nsc, t);
         });
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

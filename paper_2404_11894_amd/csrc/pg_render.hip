@@ -14,7 +14,10 @@ void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params*
     r.K = (int)(N < q->k ? N : q->k);
     r.D = q->D;
     r.schedule = resolve_schedule(q);
-    r.tile = q->tile;
+    // single-scene propagation defaults to workgroups of 512 rows: the
+    // compact-id aggregation ran 2.5-3.9% faster than with 256 (the shift is
+    // indifferent); batches keep 256, which their persistent schedule needs
+    r.tile = q->tile ? q->tile : 512;
     r.tile_group = q->tile_group;
     r.tape = (q->flags & PG_FLAG_TAPE) != 0;
     r.clusters = (q->flags & PG_FLAG_CLUSTERS) != 0;
@@ -50,7 +53,10 @@ void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params*
     r.pred = (r.tape || r.schedule == PG_SCHED_SCATTER) ? cv.take<int32_t>(N) : nullptr;
     r.x = cv.take<float>(3 * N);
     r.y = cv.take<float>(3 * N);
-    if (r.schedule == PG_SCHED_TWO_PASS && ell_k4(r.K) <= 32 && E < ((int64_t)1 << 32)) {
+    // decided from the sizes alone: a sizing pass carves from a null base, so
+    // no buffer's pointer may decide what is carved
+    const bool compact = r.schedule == PG_SCHED_TWO_PASS && ell_k4(r.K) <= 32 && E < ((int64_t)1 << 32);
+    if (compact) {
         const int64_t nsl = div_up(N, kSlice);
         r.c16 = cv.take<int16_t>(c16_size(N, r.K));
         r.c16_base = cv.take<uint32_t>(nsl + 1);
@@ -64,6 +70,9 @@ void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params*
         r.c = cv.take<float>(3 * N);
     }
     r.traj = r.tape ? cv.take<float>((int64_t)(r.D + 1) * 3 * N) : nullptr;
+    const int k4 = ell_k4(r.K);
+    if (r.tape && (q->flags & PG_FLAG_STORE_Z) && compact && (k4 == 8 || k4 == 12 || k4 == 16))
+        r.zt = cv.take<float>((int64_t)r.D * 6 * N);
 }
 
 #define PG_TRY(x)                              \
@@ -156,7 +165,10 @@ hipError_t render_iterate(RenderBufs& r, float* x0, hipStream_t s, float** final
         } else {
             {
                 ProfScope ps(s, "spmv");
-                if (r.c16)
+                if (r.zt)
+                    PG_TRY(launch_spmv_c16_tape(N, K, r.c16, r.c16_base, r.c16_ovf, r.w, r.gw, cur, r.b, r.alpha, r.y,
+                                                r.zt + (size_t)(t - 1) * N * 6, s, r.tile, r.tile_group));
+                else if (r.c16)
                     PG_TRY(launch_spmv_c16(N, K, r.c16, r.c16_base, r.c16_ovf, r.col, r.w, cur, r.b, r.alpha, r.y, s,
                                            r.tile, r.tile_group));
                 else

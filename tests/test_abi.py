@@ -198,6 +198,40 @@ def test_tracer_workspace_holds_max_depth_records_per_path():
     assert 112 * P * 64 <= grow_pl <= 112 * P * 64 + 4096
 
 
+def test_stored_sums_are_part_of_the_tape_workspace():
+    # PG_FLAG_STORE_Z keeps 6 floats per vertex per iteration; the sizing
+    # pass (null base) must carve them like the real one, for every entry
+    # point that takes a tape: 24 D N more bytes, for K rounded up to 8, 12 or
+    # 16 only
+    L = pg.lib()
+    s = pg.Paths()
+    s.n_vertices, s.width, s.height, s.spp = 100000, 64, 64, 2
+    s.n_paths = 64 * 64 * 2
+    for name in ("path_offsets", "pos", "dir_in", "dir_out", "albedo", "l_sun", "dir_env", "l_env", "l_phase",
+                 "e_cam", "albedo_grid"):
+        setattr(s, name, 1 << 40)   # never dereferenced by the size queries
+    s.albedo_grid_res = 8
+    N, D = 100000, 7
+
+    def sizes(k, flags):
+        q = pg.params(k=k, D=D, flags=flags)
+        out = []
+        for fn in (L.pg_render_workspace_size, L.pg_backward_workspace_size):
+            nb = ctypes.c_size_t()
+            assert fn(ctypes.byref(s), ctypes.byref(q), ctypes.byref(nb)) == 0
+            out.append(nb.value)
+        return out
+
+    for k in (8, 12, 16):
+        a, b = sizes(k, pg.PG_FLAG_TAPE), sizes(k, pg.PG_FLAG_TAPE | pg.PG_FLAG_STORE_Z)
+        for x, y in zip(a, b):
+            assert 24 * D * N <= y - x <= 24 * D * N + 512, (k, x, y)
+    for k in (4, 20):   # no stored sums: the flag has no effect
+        assert sizes(k, pg.PG_FLAG_TAPE) == sizes(k, pg.PG_FLAG_TAPE | pg.PG_FLAG_STORE_Z)
+    # without the tape the flag has no effect either
+    assert sizes(16, 0)[0] == sizes(16, pg.PG_FLAG_STORE_Z)[0]
+
+
 def test_calls_reject_bad_workspace_before_launching():
     L = pg.lib()
     s, q = fake_paths(), pg.params(k=8, D=4)

@@ -162,3 +162,37 @@ def test_backward_matches_gpu_central_differences():
     assert np.all(np.abs(fd - adj) <= 0.02 * np.abs(adj) + 2e-3 * scale), np.c_[fd, adj]
     fd_g = (loss(grid0, 0.5 + h) - loss(grid0, 0.5 - h)) / (2 * h)
     assert abs(fd_g - out["grad_g"].item()) <= 0.02 * abs(fd_g) + 1e-3
+
+
+@pytest.mark.parametrize("k,init", [(8, "pt"), (16, "zero"), (12, "pt")])
+def test_stored_sums_match_the_oracle_and_the_recomputing_sweep(k, init):
+    """PG_FLAG_STORE_Z: the taped forward keeps z_t and dz_t/dg and the
+    reverse rows read them.  Against the oracle at the usual tolerance; against
+    the recomputing sweep to 1e-6 relative (the two calls build their own
+    sorted layouts, whose in-cell order, and so the reverse sums' order, may
+    differ in the last bits); the taped render's image equals the plain one."""
+    sc = crop("mid", 40, 40, 1)
+    print(f"stored sums k={k} init={init} N={sc.n_vertices}", flush=True)
+    D = 6
+    grid, gimg, ref = case(sc, 8, k, D, 0.7, init)
+    paths = pg.DevicePaths(sc, albedo_grid=grid)
+    base = dict(k=k, D=D, g=0.7, init=init)
+    gi = torch.from_numpy(gimg.astype(np.float32))
+    plain = pg.pg_backward(paths, pg.params(**base, flags=pg.PG_FLAG_CHECK), gi, grad_albedo=True)
+    stored = pg.pg_backward(paths, pg.params(**base, flags=pg.PG_FLAG_CHECK | pg.PG_FLAG_STORE_Z), gi,
+                            grad_albedo=True)
+    torch.cuda.synchronize()
+    for key in ("grad_grid", "grad_albedo"):
+        a, b = stored[key].cpu().numpy(), plain[key].cpu().numpy()
+        scale = np.abs(b).max()
+        assert np.allclose(a, b, rtol=1e-6, atol=1e-6 * scale), key
+    assert np.isclose(stored["grad_g"].item(), plain["grad_g"].item(), rtol=1e-6)
+    grad_close(stored["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid", ref["mag"]["grad_grid"])
+    grad_close(stored["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo", ref["mag"]["grad_alpha"])
+    grad_close([stored["grad_g"].item()], [ref["grad_g"]], "grad g")
+    # the taped forward (aggregation with the sums stored) renders the plain image
+    q_tape = pg.params(**base, flags=pg.PG_FLAG_TAPE | pg.PG_FLAG_STORE_Z)
+    img_tape = pg.pg_render(paths, q_tape)
+    img = pg.pg_render(paths, pg.params(**base))
+    torch.cuda.synchronize()
+    assert torch.equal(img_tape, img)
