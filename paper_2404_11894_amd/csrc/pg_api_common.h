@@ -208,8 +208,7 @@ struct BackBufs {
     int32_t* tpos = nullptr;   // vertex -> position [N]
     int32_t* ppred = nullptr;  // position of each row's predecessor, -1: none [N]
     uint32_t* tpart = nullptr; // scan partials
-    int32_t* tsrc = nullptr;   // [nslices*64*cap] source rows
-    float* tw = nullptr;       // [nslices*64*cap]
+    uint2* tent = nullptr;     // [nslices*64*cap] (source row, weight bits)
     int32_t* ovf = nullptr;    // overflow (j, i) pairs [2E]
     float* ovw = nullptr;      // overflow weights [E]
     uint32_t* novf = nullptr;

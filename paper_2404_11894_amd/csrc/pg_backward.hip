@@ -26,7 +26,10 @@ namespace pg {
 // of kTWin consecutive vertices, the T-rows (T-row j: the rows i that have j
 // as a neighbour) are ordered by decreasing in-degree, ties by vertex, and
 // T-row j takes position tpos[j] (trow is the inverse).  Position r lives in
-// slice r/64; entry q of a slice's 64 T-rows is contiguous, and a slice is as
+// slice r/64; an entry is (source row, weight) in 8 bytes (one load each in
+// the transposed product; the build's passes move one word instead of two:
+// build 14.1 -> 12.0 ms at 22M vertices, the product within 1%); entry q of
+// a slice's 64 T-rows is contiguous, and a slice is as
 // long as its longest T-row, capped at `cap` entries.  On k-nearest-neighbour
 // graphs the padding is about 45% of the entries with slices of consecutive
 // vertices and about 26% with windows of 128.  Wider windows pad less (4% at
@@ -121,8 +124,8 @@ __global__ __launch_bounds__(kBlock) void k_tslice_len(int64_t N, int64_t nslice
 __global__ __launch_bounds__(kBlock) void k_tscatter(int64_t N, int K, int64_t EL, uint32_t cap,
                                                      const int32_t* __restrict__ col, const float* __restrict__ w,
                                                      const uint8_t* __restrict__ rank, const int32_t* __restrict__ tpos,
-                                                     const uint32_t* __restrict__ soff, int32_t* __restrict__ tsrc,
-                                                     float* __restrict__ tw, int32_t* __restrict__ ovf,
+                                                     const uint32_t* __restrict__ soff, uint2* __restrict__ tent,
+                                                     int32_t* __restrict__ ovf,
                                                      float* __restrict__ ovw, uint32_t* __restrict__ novf) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= EL) return;
@@ -136,8 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_tscatter(int64_t N, int K, int64_t E
     if (q < cap) {
         const int64_t pj = tpos[j];
         const int64_t p = (int64_t)soff[pj >> 6] + (int64_t)q * kSlice + (pj & (kSlice - 1));
-        tsrc[p] = (int32_t)i;
-        tw[p] = w[e];
+        tent[p] = make_uint2((uint32_t)i, __float_as_uint(w[e]));
     } else {
         ovf[2 * (int64_t)o] = (int32_t)j;
         ovf[2 * (int64_t)o + 1] = (int32_t)i;
@@ -152,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_tscatter(int64_t N, int K, int64_t E
 template <int C>
 __global__ __launch_bounds__(kBlock) void k_tsort(int64_t N, uint32_t cap, const uint32_t* __restrict__ soff,
                                                   const uint32_t* __restrict__ deg, const int32_t* __restrict__ trow,
-                                                  int32_t* __restrict__ tsrc, float* __restrict__ tw) {
+                                                  uint2* __restrict__ tent) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= N) return;
     const int64_t j = trow[r];
@@ -165,8 +167,9 @@ __global__ __launch_bounds__(kBlock) void k_tsort(int64_t N, uint32_t cap, const
         float v[CC];
 #pragma unroll
         for (int q = 0; q < CC; ++q) {
-            k[q] = (uint32_t)q < n ? tsrc[base + (int64_t)q * kSlice] : INT32_MAX;
-            v[q] = (uint32_t)q < n ? tw[base + (int64_t)q * kSlice] : 0.0f;
+            const uint2 ev = (uint32_t)q < n ? tent[base + (int64_t)q * kSlice] : make_uint2(0u, 0u);
+            k[q] = (uint32_t)q < n ? (int32_t)ev.x : INT32_MAX;
+            v[q] = (uint32_t)q < n ? __uint_as_float(ev.y) : 0.0f;
         }
 #pragma unroll
         for (int size = 2; size <= CC; size <<= 1) {
@@ -191,27 +194,24 @@ __global__ __launch_bounds__(kBlock) void k_tsort(int64_t N, uint32_t cap, const
 #pragma unroll
         for (int q = 0; q < CC; ++q) {
             if ((uint32_t)q < len) {
-                tsrc[base + (int64_t)q * kSlice] = (uint32_t)q < n ? k[q] : (int32_t)j;
-                tw[base + (int64_t)q * kSlice] = (uint32_t)q < n ? v[q] : 0.0f;
+                tent[base + (int64_t)q * kSlice] = (uint32_t)q < n ? make_uint2((uint32_t)k[q], __float_as_uint(v[q]))
+                                                                   : make_uint2((uint32_t)j, 0u);
             }
         }
         return;
     }
     for (uint32_t q = 1; q < n; ++q) {
-        const int32_t sv = tsrc[base + (int64_t)q * kSlice];
-        const float wv = tw[base + (int64_t)q * kSlice];
+        const uint2 ev = tent[base + (int64_t)q * kSlice];
+        const int32_t sv = (int32_t)ev.x;
         uint32_t r = q;
-        while (r > 0 && tsrc[base + (int64_t)(r - 1) * kSlice] > sv) {
-            tsrc[base + (int64_t)r * kSlice] = tsrc[base + (int64_t)(r - 1) * kSlice];
-            tw[base + (int64_t)r * kSlice] = tw[base + (int64_t)(r - 1) * kSlice];
+        while (r > 0 && (int32_t)tent[base + (int64_t)(r - 1) * kSlice].x > sv) {
+            tent[base + (int64_t)r * kSlice] = tent[base + (int64_t)(r - 1) * kSlice];
             --r;
         }
-        tsrc[base + (int64_t)r * kSlice] = sv;
-        tw[base + (int64_t)r * kSlice] = wv;
+        tent[base + (int64_t)r * kSlice] = ev;
     }
     for (uint32_t q = n; q < len; ++q) {
-        tsrc[base + (int64_t)q * kSlice] = (int32_t)j;
-        tw[base + (int64_t)q * kSlice] = 0.0f;
+        tent[base + (int64_t)q * kSlice] = make_uint2((uint32_t)j, 0u);
     }
 }
 
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows_taped(int64_t N, const floa
 // lane of a wave runs its slice's length, the zero-weight padding included: a
 // per-lane bound measured slower), eight entries loaded ahead (four: 7% slower).
 __global__ __launch_bounds__(kBlock) void k_rev_cols(int64_t N, const uint32_t* __restrict__ soff,
-                                                     const int32_t* __restrict__ tsrc, const float* __restrict__ tw,
+                                                     const uint2* __restrict__ tent,
                                                      const float* __restrict__ zbar, float* __restrict__ lam) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= N) return;
@@ -487,8 +487,10 @@ __global__ __launch_bounds__(kBlock) void k_rev_cols(int64_t N, const uint32_t* 
         float ww[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            src[u] = __builtin_nontemporal_load(tsrc + base + (int64_t)(q + u) * kSlice);
-            ww[u] = __builtin_nontemporal_load(tw + base + (int64_t)(q + u) * kSlice);
+            const uint64_t ev = __builtin_nontemporal_load(
+                reinterpret_cast<const uint64_t*>(tent) + base + (int64_t)(q + u) * kSlice);
+            src[u] = (int32_t)(uint32_t)ev;
+            ww[u] = __uint_as_float((uint32_t)(ev >> 32));
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -502,8 +504,9 @@ __global__ __launch_bounds__(kBlock) void k_rev_cols(int64_t N, const uint32_t* 
     while (q + 8 <= len) block(std::integral_constant<int, 8>{});
     if (q + 4 <= len) block(std::integral_constant<int, 4>{});
     for (; q < len; ++q) {
-        const f3 zb = ld3(zbar, tsrc[base + (int64_t)q * kSlice]);
-        const float ww = tw[base + (int64_t)q * kSlice];
+        const uint2 ev = tent[base + (int64_t)q * kSlice];
+        const f3 zb = ld3(zbar, (int32_t)ev.x);
+        const float ww = __uint_as_float(ev.y);
         ax = fmaf(ww, zb.x, ax);
         ay = fmaf(ww, zb.y, ay);
         az = fmaf(ww, zb.z, az);
@@ -788,8 +791,7 @@ void carve_back(Carver& cv, BackBufs& bb, const RenderBufs& r, const pg_paths* p
     bb.tpos = cv.take<int32_t>(N > 0 ? N : 1);
     bb.ppred = cv.take<int32_t>(N > 0 ? N : 1);
     bb.tpart = cv.take<uint32_t>(scan_partials_bytes(bb.nslices + 1) / 4);
-    bb.tsrc = cv.take<int32_t>(bb.nslices * kSlice * (int64_t)bb.cap);
-    bb.tw = cv.take<float>(bb.nslices * kSlice * (int64_t)bb.cap);
+    bb.tent = cv.take<uint2>(bb.nslices * kSlice * (int64_t)bb.cap);
     bb.ovf = cv.take<int32_t>(2 * E);
     bb.ovw = cv.take<float>(E);
     bb.novf = cv.take<uint32_t>(64);
@@ -895,12 +897,12 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
                            N, bb.nslices, bb.cap, bb.tdeg, bb.trow, bb.tlen);
         PG_TRY(launch_scan_exclusive(bb.tlen, bb.soff, bb.nslices, bb.tpart, s));
         hipLaunchKernelGGL(k_tscatter, dim3((unsigned)div_up(EL, kBlock)), dim3(kBlock), 0, s, N, K, EL, bb.cap,
-                           r.col, r.w, bb.trank, bb.tpos, bb.soff, bb.tsrc, bb.tw, bb.ovf, bb.ovw, bb.novf);
+                           r.col, r.w, bb.trank, bb.tpos, bb.soff, bb.tent, bb.ovf, bb.ovw, bb.novf);
         auto sort = [&](auto c) {
             constexpr int C = decltype(c)::value;
             hipLaunchKernelGGL(k_tsort<C>, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.cap,
                                (const uint32_t*)bb.soff, (const uint32_t*)bb.tdeg, (const int32_t*)bb.trow,
-                               bb.tsrc, bb.tw);
+                               bb.tent);
         };
         if (bb.cap <= 8) sort(std::integral_constant<int, 8>{});
         else if (bb.cap <= 16) sort(std::integral_constant<int, 16>{});
@@ -952,7 +954,7 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
         {
             ProfScope ps(s, "rev_cols");
             hipLaunchKernelGGL(k_rev_cols, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, bb.soff,
-                               bb.tsrc, bb.tw, bb.zbar, lam_next);
+                               (const uint2*)bb.tent, bb.zbar, lam_next);
             hipLaunchKernelGGL(k_rev_overflow, dim3(64), dim3(kBlock), 0, s, bb.ovf, bb.ovw, bb.novf, bb.tpos,
                                bb.zbar, lam_next);
         }
