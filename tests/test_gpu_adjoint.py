@@ -164,10 +164,11 @@ def test_backward_matches_gpu_central_differences():
     assert abs(fd_g - out["grad_g"].item()) <= 0.02 * abs(fd_g) + 1e-3
 
 
-@pytest.mark.parametrize("k,init", [(8, "pt"), (16, "zero"), (12, "pt")])
+@pytest.mark.parametrize("k,init", [(8, "pt"), (16, "zero"), (12, "pt"), (20, "pt")])
 def test_stored_sums_match_the_oracle_and_the_recomputing_sweep(k, init):
     """PG_FLAG_STORE_Z: the taped forward keeps z_t and dz_t/dg and the
-    reverse rows read them.  Against the oracle at the usual tolerance; against
+    reverse rows read them (k = 20 has no stored sums: the flag leaves the
+    recomputing sweep).  Against the oracle at the usual tolerance; against
     the recomputing sweep to 1e-6 relative (the two calls build their own
     sorted layouts, whose in-cell order, and so the reverse sums' order, may
     differ in the last bits); the taped render's image equals the plain one."""
