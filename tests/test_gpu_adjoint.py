@@ -191,9 +191,23 @@ def test_stored_sums_match_the_oracle_and_the_recomputing_sweep(k, init):
     grad_close(stored["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid", ref["mag"]["grad_grid"])
     grad_close(stored["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo", ref["mag"]["grad_alpha"])
     grad_close([stored["grad_g"].item()], [ref["grad_g"]], "grad g")
-    # the taped forward (aggregation with the sums stored) renders the plain image
+    # the taped forward (aggregation with the sums stored) renders the plain
+    # image, and pg_backward on its workspace (sized by the query, so the
+    # stored sums must fit in it) gives the stateless call's gradients
+    import ctypes
     q_tape = pg.params(**base, flags=pg.PG_FLAG_TAPE | pg.PG_FLAG_STORE_Z)
-    img_tape = pg.pg_render(paths, q_tape)
+    s = paths.struct()
+    nb = ctypes.c_size_t()
+    pg._check(pg.lib().pg_render_workspace_size(ctypes.byref(s), ctypes.byref(q_tape), ctypes.byref(nb)))
+    _, ws, n = pg._workspace(nb.value, paths.device)
+    img_tape = torch.empty(sc.height, sc.width, 3, device=paths.device)
+    pg._check(pg.lib().pg_render(ctypes.byref(s), ctypes.byref(q_tape), pg._ptr(img_tape), None, pg._ptr(ws), n,
+                                 pg._stream(paths.device)))
+    reused = pg.pg_backward(paths, q_tape, gi, grad_albedo=True, workspace=(ws, n))
     img = pg.pg_render(paths, pg.params(**base))
     torch.cuda.synchronize()
     assert torch.equal(img_tape, img)
+    for key in ("grad_grid", "grad_albedo"):
+        a, b = reused[key].cpu().numpy(), plain[key].cpu().numpy()
+        assert np.allclose(a, b, rtol=1e-6, atol=1e-6 * np.abs(b).max()), key
+    assert np.isclose(reused["grad_g"].item(), plain["grad_g"].item(), rtol=1e-6)
