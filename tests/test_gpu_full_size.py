@@ -142,6 +142,37 @@ def test_mid_single_neighbour_is_path_tracing(mid):
     assert_within(img, ref, PIX_REL, PIX_ABS, "k=1")
 
 
+def test_mid_stored_sums_gradient_equals_recomputed(mid):
+    """The differentiation workload at full size (the mid paths, albedo from
+    the 64^3 grid, seed 2, L2 loss against the seeded target): pg_backward with
+    the stored neighbour sums (PG_FLAG_STORE_Z, a 74 GB workspace) gives the
+    recomputing sweep's gradients.  Both are GPU results, from two calls that
+    build their own sorted layouts (in-cell order and float atomics differ in
+    the last bits, over 64 reverse iterations), so the bound is 1e-5 relative
+    with a floor of 1e-5 of the largest voxel gradient; the oracle's gradient
+    is checked on crops of this workload."""
+    grid = scenegen.albedo_grid(64, 0.95, 0.999, seed=2)
+    paths = pg.DevicePaths(mid, albedo_grid=grid)
+    base = dict(k=W.k, D=W.D, g=W.g)
+    img = pg.pg_render(paths, pg.params(**base))
+    target = torch.from_numpy(scenegen.target_image((mid.height, mid.width, 3), 0.3, seed=4)).to(img.device)
+    gi = 2.0 * (img - target)
+    out = {}
+    for name, flags in (("recomputed", 0), ("stored", pg.PG_FLAG_STORE_Z)):
+        print(f"mid backward, {name} sums", flush=True)
+        r = pg.pg_backward(paths, pg.params(**base, flags=flags), gi)
+        torch.cuda.synchronize()
+        out[name] = {k: v.cpu().numpy() for k, v in r.items()}
+        del r
+        torch.cuda.empty_cache()
+    a, b = out["stored"]["grad_grid"], out["recomputed"]["grad_grid"]
+    assert np.isfinite(a).all() and np.abs(b).max() > 0
+    assert np.allclose(a, b, rtol=1e-5, atol=1e-5 * np.abs(b).max())
+    assert np.isclose(out["stored"]["grad_g"][0], out["recomputed"]["grad_g"][0], rtol=1e-5)
+    del paths
+    torch.cuda.empty_cache()
+
+
 @pytest.fixture(scope="module")
 def mid_clusters(mid):
     sc = replace(mid, cluster_key=scenegen.cluster_keys(mid.n_vertices, 7))
