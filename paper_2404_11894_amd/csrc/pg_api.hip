@@ -173,8 +173,9 @@ void carve_grid(Carver& cv, GridBufs& g, int64_t N, int shift) {
     g.nredo = cv.take<uint32_t>(64);
 }
 
-// quantise, count, scan, scatter.  rec may be NULL.
-hipError_t run_grid(const pg_paths* p, GridBufs& g, VRec* rec, hipStream_t s) {
+// quantise, count, scan, scatter.  rec may be NULL; with recp the records are
+// packed in path order first and gathered into the sorted order.
+hipError_t run_grid(const pg_paths* p, GridBufs& g, VRec* rec, hipStream_t s, VRec* recp) {
     const int64_t N = p->n_vertices;
     hipError_t e;
     if ((e = launch_fill(g.flag, 64 * sizeof(int32_t), s)) != hipSuccess) return e;
@@ -182,6 +183,13 @@ hipError_t run_grid(const pg_paths* p, GridBufs& g, VRec* rec, hipStream_t s) {
     if ((e = launch_quantize_count(N, p->pos, g.shift, g.cells, g.cellid, g.rank, g.flag, s)) != hipSuccess) return e;
     if ((e = launch_scan_exclusive(g.cells, g.cells, g.ncells, g.partials, s)) != hipSuccess) return e;
     if ((e = launch_cell_range(g.ncells, g.shift, g.cells, g.range, s)) != hipSuccess) return e;
+    if (rec && recp) {
+        if ((e = launch_pack_records(N, *p, recp, g.flag, s)) != hipSuccess) return e;
+        if ((e = launch_scatter(N, *p, g.shift, g.cellid, g.rank, g.cells, g.perm, g.inv, g.qs, nullptr, s)) !=
+            hipSuccess)
+            return e;
+        return launch_gather_records(N, g.perm, recp, rec, s);
+    }
     return launch_scatter(N, *p, g.shift, g.cellid, g.rank, g.cells, g.perm, g.inv, g.qs, rec, s);
 }
 

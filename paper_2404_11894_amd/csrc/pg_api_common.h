@@ -87,7 +87,8 @@ struct GridBufs {
 };
 
 void carve_grid(Carver& cv, GridBufs& g, int64_t N, int shift);
-hipError_t run_grid(const pg_paths* p, GridBufs& g, VRec* rec, hipStream_t s);
+hipError_t run_grid(const pg_paths* p, GridBufs& g, VRec* rec, hipStream_t s, VRec* recp = nullptr);
+hipError_t launch_gather_records(int64_t N, const int32_t* perm, const VRec* recp, VRec* rec, hipStream_t s);
 
 // The cluster neighbour relation (pg_clusters.hip).  Arrays indexed by a
 // sorted id unless noted; "position" is the place in cluster order.
@@ -150,6 +151,7 @@ struct RenderBufs {
     int tile = 0, tile_group = 0;   // launch shape of the propagation kernels
     bool tape = false;
     VRec* rec = nullptr;
+    VRec* recp = nullptr;     // [N] the records in path order (grid build scratch)
     int32_t* col = nullptr;   // [ell_size(N, K)] sorted ids, sliced ELL
     float* w = nullptr;       // [ell_size(N, K)]
     float* gw = nullptr;      // [ell_size(N, K)] dw/dg (tape)

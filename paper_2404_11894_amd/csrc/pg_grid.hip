@@ -262,6 +262,28 @@ hipError_t launch_alpha(int64_t N, const pg_paths& paths, float* alpha, hipStrea
     return hipGetLastError();
 }
 
+// rec[s] = recp[perm[s]]: the records packed in path order, gathered into the
+// sorted order (one 80-byte read and one coalesced 80-byte write per vertex
+// instead of scattering them from path order).
+__global__ __launch_bounds__(kBlock) void k_gather_records(int64_t N, const int32_t* __restrict__ perm,
+                                                           const VRec* __restrict__ recp, VRec* __restrict__ rec) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const float4* src = reinterpret_cast<const float4*>(recp + perm[s]);
+    float4* dst = reinterpret_cast<float4*>(rec + s);
+    float4 v[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] = src[k];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) dst[k] = v[k];
+}
+
+hipError_t launch_gather_records(int64_t N, const int32_t* perm, const VRec* recp, VRec* rec, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_records, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, perm, recp, rec);
+    return hipGetLastError();
+}
+
 hipError_t launch_pack_records(int64_t N, const pg_paths& paths, VRec* rec, int32_t* flag, hipStream_t s) {
     if (N == 0) return hipSuccess;
     hipLaunchKernelGGL(k_pack_records, dim3((unsigned)div_up(N, kBlock)), dim3(kBlock), 0, s, N, paths, rec,

@@ -42,6 +42,7 @@ void carve_render(Carver& cv, RenderBufs& r, const pg_paths* p, const pg_params*
     const int64_t E = ell_size(N, r.K);   // sliced-ELL storage, padded to whole slices
     carve_grid(cv, r.g, N, shift_of(q, N));
     r.rec = cv.take<VRec>(N);
+    r.recp = cv.take<VRec>(N);
     r.col = cv.take<int32_t>(E);
     r.w = cv.take<float>(E);
     r.gw = r.tape ? cv.take<float>(E) : nullptr;
@@ -88,7 +89,7 @@ hipError_t render_setup(const pg_paths* p, const pg_params* q, RenderBufs& r, co
     GridBufs& g = r.g;
     {
         ProfScope ps(s, "grid");
-        PG_TRY(run_grid(p, g, r.rec, s));
+        PG_TRY(run_grid(p, g, r.rec, s, r.recp));
     }
     if (N == 0) {
         if (out && out->row_ptr) PG_TRY(launch_fill(out->row_ptr, sizeof(int64_t), s));
