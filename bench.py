@@ -631,7 +631,7 @@ def main():
                     help="workload of the headline forward line (the other legs run on mid)")
     ap.add_argument("--schedule", type=int, default=0, help="0 default, 1 two-pass, 2 shifted, 3 scatter")
     ap.add_argument("--cell-shift", type=int, default=0)
-    ap.add_argument("--tile", type=int, default=0, help="workgroup size of the propagation kernels (0 = 256)")
+    ap.add_argument("--tile", type=int, default=0, help="workgroup size of the propagation kernels (0 = 512)")
     ap.add_argument("--tile-group", type=int, default=0, help="consecutive row tiles per XCD in the aggregation")
     ap.add_argument("--no-autotune", action="store_true",
                     help="library defaults instead of the autotuner's cell size and edge tile")
