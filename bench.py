@@ -572,7 +572,7 @@ def time_forward(pg, torch, sc, w, name, steps, warmup, schedule=0, cell_shift=0
                                f"{w.scene.spp} spp, depth {w.scene.max_depth}, k {w.k}, D {w.D}",
                    "N": N, "E": E, "P": sc.n_paths, "K": K, "D": w.D,
                    "schedule": pg.resolved_schedule(q), "cell_shift": cell_shift or pg.pg_default_cell_shift(N),
-                   "tile": tile or 256, "tile_group": tile_group or 1, "autotuned": tuned},
+                   "tile": tile or 512, "tile_group": tile_group or 1, "autotuned": tuned},
         "propagation": {"ms_per_step": round(prop_ms, 3), "gedge_updates_per_s": round(E * w.D / prop_ms / 1e6, 2),
                         "algorithmic_GBs": round(prop_bytes / (prop_ms / 1e3) / 1e9, 1),
                         "hbm_frac": round(prop_bytes / (prop_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
