@@ -150,79 +150,85 @@ hipError_t launch_edges(int64_t N, const Consts& c, const int32_t* col, const VR
     return hipGetLastError();
 }
 
-// One thread per path, walking it backwards.  Writes, in local ids,
-// succ(v) / pred(v) (-1 at the ends) and the initial radiance arriving from
-// the successor u along the continuation: 0 at the last vertex, else
-// e_u + albedo_u (d_pt_u + r_u L(u)) -- the path tracer's own estimate (init
-// PT) -- or e_u alone (init zero: the indirect part starts at 0), e_u being
-// the volume emission collected at u (emit, path order, nullable: 0).
-// The path is taken in chunks of kPathChunk vertices whose scattered loads
-// are all issued before the recurrence consumes them (16: 4% faster than 8
-// on paths of about 66 vertices, 4 slower).
+// One wave per path.  Writes, in local ids, succ(v) / pred(v) (-1 at the
+// ends) and the initial radiance arriving from the successor u along the
+// continuation: 0 at the last vertex, else e_u + albedo_u (d_pt_u + r_u L(u))
+// -- the path tracer's own estimate (init PT) -- or e_u alone (init zero: the
+// indirect part starts at 0), e_u being the volume emission collected at u
+// (emit, path order, nullable: 0).  The recurrence L(v) = F_u(L(u)), F_u an
+// affine map, is taken 64 vertices at a time from the path's end: lane c
+// holds vertex hi - c, a wave-level inclusive scan composes the lanes' maps
+// (F(L) = A + B L; F2 o F1 = (A2 + B2 A1, B2 B1)), and each lane applies
+// the composition of the lanes above it to the value arriving at the chunk.
 // succ, pred and x0 must be pre-filled with -1, -1, 0.
-constexpr int kPathChunk = 16;
 __global__ __launch_bounds__(kBlock) void k_paths(int64_t P, int64_t N, const int64_t* __restrict__ off,
                                                   const int32_t* __restrict__ inv, const float* __restrict__ alpha,
                                                   const float* __restrict__ dpt, const float* __restrict__ r,
                                                   const float* __restrict__ emit, int init,
                                                   int32_t* __restrict__ succ, int32_t* __restrict__ pred,
                                                   float* __restrict__ x0, int32_t* flag) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0 && (off[0] != 0 || off[P] != N)) set_flag(flag, kFlagOffsets);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;   // uniform over the wave
+    if (p == 0 && lane == 0 && (off[0] != 0 || off[P] != N)) set_flag(flag, kFlagOffsets);
     if (p >= P) return;
     const int64_t a = off[p], e = off[p + 1];
     if (a < 0 || e < a || e > N) {
-        set_flag(flag, kFlagOffsets);
+        if (lane == 0) set_flag(flag, kFlagOffsets);
         return;
     }
     const bool pt = init == PG_INIT_PT && x0;
     const bool ez = !pt && emit && x0;   // init zero with emission
-    f3 L{0.f, 0.f, 0.f};
-    int32_t next = -1;   // local id of the successor
-    for (int64_t v = e - 1; v >= a; v -= kPathChunk) {
-        // chunk: vertices v, v-1, ..., v-n+1 (n <= kPathChunk)
-        const int n = v - a + 1 < kPathChunk ? (int)(v - a + 1) : kPathChunk;
-        int32_t sv[kPathChunk + 1];
-        float al[kPathChunk], rr[kPathChunk];
-        f3 d[kPathChunk], em[kPathChunk];
-#pragma unroll
-        for (int c = 0; c <= kPathChunk; ++c) {
-            const int64_t u = v - c;   // c == n: the predecessor of the chunk's first vertex
-            sv[c] = (c <= n && u >= a) ? (inv ? inv[u] : (int32_t)u) : -1;
+    auto sid = [&](int64_t u) { return inv ? inv[u] : (int32_t)u; };
+    f3 carry{0.f, 0.f, 0.f};   // the value arriving at the chunk's highest vertex
+    for (int64_t hi = e - 1; hi >= a; hi -= kWave) {
+        const int64_t v = hi - lane;
+        const bool valid = v >= a;
+        const int32_t s = valid ? sid(v) : -1;
+        if (valid) {
+            if (succ) succ[s] = v + 1 < e ? sid(v + 1) : -1;
+            if (pred) pred[s] = v > a ? sid(v - 1) : -1;
         }
-        if (pt) {
-#pragma unroll
-            for (int c = 0; c < kPathChunk; ++c) {
-                if (c < n) {
-                    al[c] = alpha[sv[c]];
-                    rr[c] = r[sv[c]];
-                    d[c] = ld3(dpt, sv[c]);
-                    em[c] = emit ? ld3(emit, v - c) : f3{0.f, 0.f, 0.f};
-                }
-            }
-        } else if (ez) {
-#pragma unroll
-            for (int c = 0; c < kPathChunk; ++c)
-                if (c < n) em[c] = ld3(emit, v - c);
-        }
-#pragma unroll
-        for (int c = 0; c < kPathChunk; ++c) {
-            if (c < n) {
-                const int64_t s = sv[c];
-                if (succ) succ[s] = next;
-                if (pred) pred[s] = sv[c + 1];
-                if (pt) {
-                    st3(x0, s, L);
-                    L = f3{fmaf(al[c], fmaf(rr[c], L.x, d[c].x), em[c].x),
-                           fmaf(al[c], fmaf(rr[c], L.y, d[c].y), em[c].y),
-                           fmaf(al[c], fmaf(rr[c], L.z, d[c].z), em[c].z)};
-                } else if (ez) {
-                    st3(x0, s, L);
-                    L = em[c];
-                }
-                next = (int32_t)s;
+        if (!pt && !ez) continue;
+        // this vertex's map: the value arriving at its predecessor from the
+        // value arriving at it (identity on the lanes past the path's start)
+        float B = 1.0f;
+        f3 A{0.f, 0.f, 0.f};
+        if (valid) {
+            const f3 em = emit ? ld3(emit, v) : f3{0.f, 0.f, 0.f};
+            if (pt) {
+                const float al = alpha[s];
+                const f3 d = ld3(dpt, s);
+                B = al * r[s];
+                A = f3{fmaf(al, d.x, em.x), fmaf(al, d.y, em.y), fmaf(al, d.z, em.z)};
+            } else {
+                B = 0.0f;
+                A = em;
             }
         }
+        // inclusive scan: lane c composes the maps of lanes 0..c (lane c's
+        // applied last)
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const float Bo = __shfl_up(B, o, kWave);
+            const float Ax = __shfl_up(A.x, o, kWave), Ay = __shfl_up(A.y, o, kWave), Az = __shfl_up(A.z, o, kWave);
+            if (lane >= o) {
+                A = f3{fmaf(B, Ax, A.x), fmaf(B, Ay, A.y), fmaf(B, Az, A.z)};
+                B *= Bo;
+            }
+        }
+        // exclusive: the lanes above this one, applied to the carry
+        // every lane takes part in the shuffles (a lane inactive in one
+        // gives no data to its neighbour), then lane 0 takes the identity
+        const float Bsh = __shfl_up(B, 1, kWave);
+        const float Be = lane > 0 ? Bsh : 1.0f;
+        const float Aex = __shfl_up(A.x, 1, kWave), Aey = __shfl_up(A.y, 1, kWave), Aez = __shfl_up(A.z, 1, kWave);
+        const f3 Ae = lane > 0 ? f3{Aex, Aey, Aez} : f3{0.f, 0.f, 0.f};
+        if (valid) st3(x0, s, f3{fmaf(Be, carry.x, Ae.x), fmaf(Be, carry.y, Ae.y), fmaf(Be, carry.z, Ae.z)});
+        // the value arriving at the next chunk's highest vertex (the whole
+        // chunk's composition, held by lane 63)
+        const float Bl = __shfl(B, kWave - 1, kWave);
+        const f3 Al{__shfl(A.x, kWave - 1, kWave), __shfl(A.y, kWave - 1, kWave), __shfl(A.z, kWave - 1, kWave)};
+        carry = f3{fmaf(Bl, carry.x, Al.x), fmaf(Bl, carry.y, Al.y), fmaf(Bl, carry.z, Al.z)};
     }
 }
 
@@ -230,8 +236,8 @@ hipError_t launch_paths(int64_t P, int64_t N, const int64_t* off, const int32_t*
                         const float* dpt, const float* r, const float* emit, int init, int32_t* succ, int32_t* pred,
                         float* x0, int32_t* flag, hipStream_t s) {
     const int64_t n = P > 0 ? P : 1;
-    hipLaunchKernelGGL(k_paths, dim3((unsigned)div_up(n, kBlock)), dim3(kBlock), 0, s, P, N, off, inv, alpha, dpt,
-                       r, emit, init, succ, pred, x0, flag);
+    hipLaunchKernelGGL(k_paths, dim3((unsigned)div_up(n * kWave, kBlock)), dim3(kBlock), 0, s, P, N, off, inv, alpha,
+                       dpt, r, emit, init, succ, pred, x0, flag);
     return hipGetLastError();
 }
 

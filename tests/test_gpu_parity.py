@@ -261,6 +261,20 @@ def test_duplicate_positions():
     compare_all(sc, 8, img, gr, ref_img, ref, "duplicates")
 
 
+@pytest.mark.parametrize("init", ["pt", "zero"])
+def test_paths_longer_than_a_wave(init):
+    """The path pass takes a path 64 vertices at a time: paths of 1, 41, 64,
+    65, 129 and 200 vertices and an empty one; D = 0 compares the initial
+    value itself, D = 3 its propagation."""
+    rng = np.random.default_rng(9)
+    lengths = np.array([200, 1, 64, 65, 129, 0, 41])
+    sc = synthetic(rng.random((int(lengths.sum()), 3)), rng, lengths=lengths)
+    for D in (0, 3):
+        img, gr = gpu_render(sc, 8, D, 0.5, init=init)
+        ref_img, ref = oracle.render(sc, oracle.params(k=8, D=D, g=0.5, init=init), trace=True)
+        compare_all(sc, 8, img, gr, ref_img, ref, f"long paths init={init} D={D}")
+
+
 def test_lattice_ties():
     rng = np.random.default_rng(3)
     g = np.array([(x, y, z) for z in range(8) for y in range(8) for x in range(8)], np.float64)
