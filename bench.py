@@ -66,7 +66,7 @@ def algorithmic_bytes(step, N, K, starts, n_far=None):
 
 SOURCES = {"spmv": ("pg_prop.hip", "pg_internal.h"), "shift": ("pg_prop.hip", "pg_internal.h"),
            "cagg": ("pg_clusters.hip", "pg_internal.h"), "rev_rows": ("pg_backward.hip", "pg_internal.h"),
-           "rev_cols": ("pg_backward.hip", "pg_internal.h")}
+           "rev_cols": ("pg_backward.hip", "pg_internal.h"), "spmv_tape": ("pg_backward.hip", "pg_internal.h")}
 
 
 def kernel_source_hash(kernel="spmv"):
@@ -223,9 +223,11 @@ def time_fwd_adjoint(pg, torch, sc, w, steps, warmup, store_z=True):
         cnt, tot, _ = prof["spmv"]
         avg = tot / cnt / 1e3
         ab = N * (12 * K + 64)
+        tr = read_traffic("spmv_tape", w.name)
         rev["taped_aggregation"] = {"avg_launch_ms": round(avg * 1e3, 4), "algorithmic_bytes_per_launch": ab,
                                     "hbm_frac": round(ab / avg / 1e9 / HBM_PEAK_GBS, 4),
-                                    "bytes": "(8K + 40) N of the aggregation + 4K N (dw/dg) + 24 N (z, dz/dg)"}
+                                    "bytes": "(8K + 40) N of the aggregation + 4K N (dw/dg) + 24 N (z, dz/dg)",
+                                    "traffic": tr, "traffic_GBs": round(tr / avg / 1e9, 1) if tr else None}
     rev["stored_sums"] = bool(taped)
     ok = bool(torch.isfinite(out["grad_grid"]).all().item()) and bool(torch.isfinite(out["grad_g"]).all().item())
     del ws, paths
