@@ -74,6 +74,72 @@ __global__ __launch_bounds__(kBlock) void k_tcount(int64_t N, int K, int64_t EL,
     rank[e] = (uint8_t)(q < 255u ? q : 255u);
 }
 
+// The same counts and ranks with most atomics in LDS.  A block takes the
+// kTcRows rows of four slices; a source's neighbours lie mostly near it in
+// sorted order, so arrivals at the kTcWin ids around those rows are counted
+// in LDS (a local rank per edge), and each touched id then takes one global
+// atomic for the block's whole count, whose return is the base added to the
+// local ranks.  Arrivals outside the window take a global atomic each.  The
+// ranks of one T-row are distinct and dense (0 .. in-degree - 1) as before;
+// which edge gets which rank is as unordered as with one atomic per edge.
+// A local rank is below kTcRows * K (below kTcRows when no row repeats an
+// id), which the 19 bits it is packed in hold.  M4 = ell_k4(K) ELL positions
+// per thread, at most kTcMaxM4.
+constexpr int kTcRows = 4 * kSlice;
+constexpr int kTcWin = 4096;
+constexpr int kTcHalo = (kTcWin - kTcRows) / 2;
+constexpr int kTcMaxM4 = 32;
+static_assert(kTcRows == kBlock, "one row of the block's four slices per thread");
+static_assert(kTcWin <= (1 << 12) && kTcRows * kTcMaxM4 < (1 << 19), "packed window slot and local rank");
+
+__global__ __launch_bounds__(kBlock) void k_tcount_win(int64_t N, int K, int64_t EL,
+                                                       const int32_t* __restrict__ col, uint32_t* __restrict__ cnt,
+                                                       uint8_t* __restrict__ rank) {
+    __shared__ uint32_t c[kTcWin];
+    const int M4 = ell_k4(K);
+    const int64_t w0 = (int64_t)blockIdx.x * kTcRows - kTcHalo;
+    const int64_t p0 = (int64_t)blockIdx.x * kTcRows * M4;   // slices 4b .. 4b + 3
+    for (int t = threadIdx.x; t < kTcWin; t += kBlock) c[t] = 0u;
+    __syncthreads();
+    // per position: kInvalid, kFinal | global rank, or (window slot << 19) | local rank
+    constexpr uint32_t kInvalid = 0xffffffffu, kFinal = 0x80000000u;
+    uint32_t st[kTcMaxM4];
+#pragma unroll
+    for (int m = 0; m < kTcMaxM4; ++m) {
+        st[m] = kInvalid;
+        if (m < M4) {
+            const int64_t e = p0 + threadIdx.x + (int64_t)m * kBlock;
+            int64_t i = N;
+            int l = K;
+            if (e < EL) ell_slot(e, K, i, l);
+            if (i < N && l < K) {
+                const int32_t j = col[e];
+                const int64_t d = (int64_t)j - w0;
+                if (d >= 0 && d < kTcWin) {
+                    st[m] = ((uint32_t)d << 19) | atomicAdd(&c[d], 1u);
+                } else {
+                    const uint32_t q = atomicAdd(&cnt[j], 1u);
+                    st[m] = kFinal | (q < 255u ? q : 255u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kTcWin; t += kBlock) {
+        const uint32_t n = c[t];
+        if (n > 0u) c[t] = atomicAdd(&cnt[w0 + t], n);   // n > 0 only for ids in [0, N)
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kTcMaxM4; ++m) {
+        if (m < M4 && st[m] != kInvalid) {
+            const int64_t e = p0 + threadIdx.x + (int64_t)m * kBlock;
+            const uint32_t q = (st[m] & kFinal) ? (st[m] & 0xffu) : c[st[m] >> 19] + (st[m] & 0x7ffffu);
+            rank[e] = (uint8_t)(q < 255u ? q : 255u);
+        }
+    }
+}
+
 // The order of one window's T-rows: keys (cap - capped in-degree, vertex)
 // sorted ascending by a bitonic network in LDS; vertices past N sort last, so
 // positions below N hold exactly the vertices below N.  One block per window.
@@ -889,8 +955,12 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
         PG_TRY(launch_fill(bb.tlen, (size_t)(bb.nslices + 1) * 4, s));
         PG_TRY(launch_fill(bb.novf, 4, s));
         const int64_t EL = ell_size(N, K);
-        hipLaunchKernelGGL(k_tcount, dim3((unsigned)div_up(EL, kBlock)), dim3(kBlock), 0, s, N, K, EL, r.col,
-                           bb.tdeg, bb.trank);
+        if (ell_k4(K) <= kTcMaxM4)
+            hipLaunchKernelGGL(k_tcount_win, dim3((unsigned)div_up(N, kTcRows)), dim3(kBlock), 0, s, N, K, EL, r.col,
+                               bb.tdeg, bb.trank);
+        else
+            hipLaunchKernelGGL(k_tcount, dim3((unsigned)div_up(EL, kBlock)), dim3(kBlock), 0, s, N, K, EL, r.col,
+                               bb.tdeg, bb.trank);
         hipLaunchKernelGGL(k_twin_order, dim3((unsigned)div_up(N, kTWin)), dim3(kBlock), 0, s, N, bb.cap, bb.tdeg,
                            bb.trow, bb.tpos);
         hipLaunchKernelGGL(k_tslice_len, dim3((unsigned)div_up(bb.nslices * kSlice, kBlock)), dim3(kBlock), 0, s,
