@@ -596,9 +596,15 @@ __global__ __launch_bounds__(kBlock) void k_rev_overflow(const int32_t* __restri
 }
 
 // ------------------------------- reverse of the path-traced initial value ---
-// L_0(v) = alpha_u (d_pt_u + r_u L_0(u)), u = succ v.  Walks each path from
-// its first vertex, so lam_0(u) is complete before u passes it on (lam held at
-// the T-row positions tpos; null: at the vertices).
+// L_0(v) = alpha_u (d_pt_u + r_u L_0(u)), u = succ v.  Its adjoint runs from
+// each path's first vertex: lam_0(u) += alpha_u r_u lam_0(v), v = pred u, an
+// affine recurrence l(u) = A_u + B_u l(v) with A_u the adjoint the sweep left
+// at u and B_u = alpha_u r_u (B = 0 at the first vertex).  One wave per path
+// takes 64 vertices at a time: a wave-level inclusive scan composes the
+// lanes' maps (G2 o G1 = (A2 + B2 A1, B2 B1)), applied to the value carried
+// from the previous chunk; each lane then adds its vertex's albedo, d_pt and r
+// adjoints from its predecessor's l and stores its own l (lam held at the
+// T-row positions tpos; null: at the vertices).
 __global__ __launch_bounds__(kBlock) void k_pt_adjoint(int64_t P, int64_t N, const int64_t* __restrict__ off,
                                                        const int32_t* __restrict__ inv,
                                                        const float* __restrict__ alpha, const float* __restrict__ dpt,
@@ -606,24 +612,58 @@ __global__ __launch_bounds__(kBlock) void k_pt_adjoint(int64_t P, int64_t N, con
                                                        const int32_t* __restrict__ tpos,
                                                        float* __restrict__ lam, float* __restrict__ abar,
                                                        float* __restrict__ dptbar, float* __restrict__ rbar) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;   // uniform over the wave
     if (p >= P) return;
     const int64_t a = off[p], e = off[p + 1];
     if (a < 0 || e < a || e > N) return;
-    for (int64_t v = a; v + 1 < e; ++v) {
-        const int64_t s = inv[v], u = inv[v + 1];
-        const int64_t pu = tpos ? tpos[u] : u;
-        const f3 l = ld3(lam, tpos ? tpos[s] : s);
-        const float al = alpha[u], rr = r[u];
-        const f3 d = ld3(dpt, u), xu = ld3(x0, u);
-        abar[u] += dot3(l, f3{fmaf(rr, xu.x, d.x), fmaf(rr, xu.y, d.y), fmaf(rr, xu.z, d.z)});
-        dptbar[3 * u] += al * l.x;
-        dptbar[3 * u + 1] += al * l.y;
-        dptbar[3 * u + 2] += al * l.z;
-        rbar[u] += al * dot3(l, xu);
-        lam[3 * pu] = fmaf(al * rr, l.x, lam[3 * pu]);
-        lam[3 * pu + 1] = fmaf(al * rr, l.y, lam[3 * pu + 1]);
-        lam[3 * pu + 2] = fmaf(al * rr, l.z, lam[3 * pu + 2]);
+    f3 carry{0.f, 0.f, 0.f};   // l at the vertex before the chunk
+    for (int64_t lo = a; lo < e; lo += kWave) {
+        const int64_t v = lo + lane;
+        const bool valid = v < e, step = valid && v > a;
+        int64_t u = 0, pu = 0;
+        float al = 0.0f, rr = 0.0f, B = 1.0f;   // identity past the path's end
+        f3 A{0.f, 0.f, 0.f}, d{0.f, 0.f, 0.f}, xu{0.f, 0.f, 0.f};
+        if (valid) {
+            u = inv[v];
+            pu = tpos ? tpos[u] : u;
+            A = ld3(lam, pu);
+            B = 0.0f;
+            if (step) {
+                al = alpha[u];
+                rr = r[u];
+                d = ld3(dpt, u);
+                xu = ld3(x0, u);
+                B = al * rr;
+            }
+        }
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const float Bo = __shfl_up(B, o, kWave);
+            const float Ax = __shfl_up(A.x, o, kWave), Ay = __shfl_up(A.y, o, kWave), Az = __shfl_up(A.z, o, kWave);
+            if (lane >= o) {
+                A = f3{fmaf(B, Ax, A.x), fmaf(B, Ay, A.y), fmaf(B, Az, A.z)};
+                B *= Bo;
+            }
+        }
+        // l at the predecessor: the lanes below this one applied to the
+        // carry (every lane shuffles; lane 0 then takes the identity)
+        const float Bsh = __shfl_up(B, 1, kWave);
+        const float Aex = __shfl_up(A.x, 1, kWave), Aey = __shfl_up(A.y, 1, kWave), Aez = __shfl_up(A.z, 1, kWave);
+        const float Be = lane > 0 ? Bsh : 1.0f;
+        const f3 Ae = lane > 0 ? f3{Aex, Aey, Aez} : f3{0.f, 0.f, 0.f};
+        const f3 l{fmaf(Be, carry.x, Ae.x), fmaf(Be, carry.y, Ae.y), fmaf(Be, carry.z, Ae.z)};
+        if (step) {
+            abar[u] += dot3(l, f3{fmaf(rr, xu.x, d.x), fmaf(rr, xu.y, d.y), fmaf(rr, xu.z, d.z)});
+            dptbar[3 * u] += al * l.x;
+            dptbar[3 * u + 1] += al * l.y;
+            dptbar[3 * u + 2] += al * l.z;
+            rbar[u] += al * dot3(l, xu);
+            st3(lam, pu, f3{fmaf(B, carry.x, A.x), fmaf(B, carry.y, A.y), fmaf(B, carry.z, A.z)});
+        }
+        const float Bl = __shfl(B, kWave - 1, kWave);
+        const f3 Al{__shfl(A.x, kWave - 1, kWave), __shfl(A.y, kWave - 1, kWave), __shfl(A.z, kWave - 1, kWave)};
+        carry = f3{fmaf(Bl, carry.x, Al.x), fmaf(Bl, carry.y, Al.y), fmaf(Bl, carry.z, Al.z)};
     }
 }
 
@@ -906,7 +946,7 @@ static hipError_t run_backward_clusters(const pg_paths* p, const pg_params* q, R
     }
     if (q->init == PG_INIT_PT && N > 0) {
         ProfScope ps(s, "pt_adjoint");
-        hipLaunchKernelGGL(k_pt_adjoint, dim3((unsigned)div_up(r.P > 0 ? r.P : 1, kBlock)), dim3(kBlock), 0, s,
+        hipLaunchKernelGGL(k_pt_adjoint, dim3((unsigned)div_up((r.P > 0 ? r.P : 1) * kWave, kBlock)), dim3(kBlock), 0, s,
                            r.P, N, p->path_offsets, r.cl.cinv, r.alpha, r.dpt, r.r, r.traj, (const int32_t*)nullptr,
                            lam, bb.abar, bb.dptbar, bb.rbar);
         PG_TRY(hipGetLastError());
@@ -1035,7 +1075,7 @@ hipError_t run_backward(const pg_paths* p, const pg_params* q, RenderBufs& r, Ba
     }
     if (q->init == PG_INIT_PT && N > 0) {
         ProfScope ps(s, "pt_adjoint");
-        hipLaunchKernelGGL(k_pt_adjoint, dim3((unsigned)div_up(r.P > 0 ? r.P : 1, kBlock)), dim3(kBlock), 0, s,
+        hipLaunchKernelGGL(k_pt_adjoint, dim3((unsigned)div_up((r.P > 0 ? r.P : 1) * kWave, kBlock)), dim3(kBlock), 0, s,
                            r.P, N, p->path_offsets, r.g.inv, r.alpha, r.dpt, r.r, r.traj, (const int32_t*)bb.tpos,
                            lam, bb.abar, bb.dptbar, bb.rbar);
         PG_TRY(hipGetLastError());

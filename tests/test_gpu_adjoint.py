@@ -46,6 +46,24 @@ def test_backward_matches_oracle(init, fg, emit):
     grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
 
 
+@pytest.mark.parametrize("D", [0, 3])
+def test_backward_paths_longer_than_a_wave(D):
+    """The adjoint of the path-traced initial value takes a path 64 vertices
+    at a time: paths of 1, 41, 64, 65, 129 and 200 vertices and an empty one."""
+    rng = np.random.default_rng(9)
+    lengths = np.array([200, 1, 64, 65, 129, 0, 41])
+    sc = synthetic(rng.random((int(lengths.sum()), 3)), rng, lengths=lengths)
+    print(f"adjoint long paths D={D} N={sc.n_vertices}", flush=True)
+    grid, gimg, ref = case(sc, 8, 8, D, 0.5, "pt", 0)
+    paths = pg.DevicePaths(sc, albedo_grid=grid)
+    q = pg.params(k=8, D=D, g=0.5, flags=pg.PG_FLAG_CHECK)
+    out = pg.pg_backward(paths, q, torch.from_numpy(gimg.astype(np.float32)), grad_albedo=True)
+    torch.cuda.synchronize()
+    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid", ref["mag"]["grad_grid"])
+    grad_close(out["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo", ref["mag"]["grad_alpha"])
+    grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
+
+
 @pytest.mark.parametrize("extra,point", [(3, False), (0, True), (2, True)])
 def test_backward_with_extra_samples_and_point_light(extra, point):
     from dataclasses import replace
