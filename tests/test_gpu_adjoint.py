@@ -101,6 +101,24 @@ def test_backward_with_transpose_overflow():
     grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
 
 
+@pytest.mark.parametrize("k", [33, 40, 64])
+def test_backward_rows_longer_than_32(k):
+    """Rows of more than 32 neighbours: the transposed operator's counting
+    pass takes one global atomic per edge there, and the reverse rows their
+    generic width."""
+    rng = np.random.default_rng(11)
+    sc = synthetic(rng.random((600, 3)), rng, lengths=np.full(30, 20))
+    print(f"adjoint k={k} N={sc.n_vertices}", flush=True)
+    grid, gimg, ref = case(sc, 4, k, 4, 0.6)
+    paths = pg.DevicePaths(sc, albedo_grid=grid)
+    q = pg.params(k=k, D=4, g=0.6, flags=pg.PG_FLAG_CHECK)
+    out = pg.pg_backward(paths, q, torch.from_numpy(gimg.astype(np.float32)), grad_albedo=True)
+    torch.cuda.synchronize()
+    grad_close(out["grad_grid"].cpu().numpy(), ref["grad_grid"], "grad grid", ref["mag"]["grad_grid"])
+    grad_close(out["grad_albedo"].cpu().numpy(), ref["grad_alpha"], "grad albedo", ref["mag"]["grad_alpha"])
+    grad_close([out["grad_g"].item()], [ref["grad_g"]], "grad g")
+
+
 def test_backward_workload_crop_matches_oracle():
     """The differentiation workload: the 128^3 ball's paths held fixed, albedo
     from a 64^3 grid (U[0.95,0.999], seed 2), k 16, D 64, g 0.8, on the
