@@ -97,8 +97,9 @@ __global__ __launch_bounds__(kBlock) void k_tcount_win(int64_t N, int K, int64_t
                                                        uint8_t* __restrict__ rank) {
     __shared__ uint32_t c[kTcWin];
     const int M4 = ell_k4(K);
-    const int64_t w0 = (int64_t)blockIdx.x * kTcRows - kTcHalo;
-    const int64_t p0 = (int64_t)blockIdx.x * kTcRows * M4;   // slices 4b .. 4b + 3
+    const int64_t b = xcd_tile(blockIdx.x, gridDim.x);   // neighbouring windows on one L2
+    const int64_t w0 = b * kTcRows - kTcHalo;
+    const int64_t p0 = b * kTcRows * M4;   // slices 4b .. 4b + 3
     for (int t = threadIdx.x; t < kTcWin; t += kBlock) c[t] = 0u;
     __syncthreads();
     // per position: kInvalid, kFinal | global rank, or (window slot << 19) | local rank
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_tscatter(int64_t N, int K, int64_t E
                                                      const uint32_t* __restrict__ soff, uint2* __restrict__ tent,
                                                      int32_t* __restrict__ ovf,
                                                      float* __restrict__ ovw, uint32_t* __restrict__ novf) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;   // nearby T-rows on one L2
     if (e >= EL) return;
     int64_t i;
     int l;
