@@ -515,7 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_rev_rows_taped(int64_t N, const floa
                                                            const float* __restrict__ alpha, float* __restrict__ abar,
                                                            float* __restrict__ bbar, float* __restrict__ zbar,
                                                            double* __restrict__ gpart) {
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);   // the predecessors' lambda lines on one L2
     const int64_t i = tile * kBlock + threadIdx.x;
     double gl = 0.0;
     if (i < N) {
