@@ -91,9 +91,10 @@ __global__ __launch_bounds__(BS) void k_spmv_batched(const SceneDesc* __restrict
 // x(v) = y(succ v), 0 at a path's end, for scenes still iterating.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_shift_batched(const SceneDesc* __restrict__ sd, int nsc, int t) {
-    const SceneDesc& d = sd[find_scene(sd, nsc, blockIdx.x)];
+    const int64_t blk = xcd_tile(blockIdx.x, gridDim.x);   // as the single-scene shift
+    const SceneDesc& d = sd[find_scene(sd, nsc, blk)];
     if (t > d.D) return;
-    const int64_t v = (blockIdx.x - d.blk0) * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t v = (blk - d.blk0) * (int64_t)blockDim.x + threadIdx.x;
     if (v >= d.nrows) return;
     const int64_t u = __builtin_nontemporal_load(d.succ + v);
     f3 val{0.f, 0.f, 0.f};
