@@ -626,7 +626,8 @@ __global__ __launch_bounds__(kBlock) void k_cagg(int64_t N, HG rho, const uint2*
                                                  const int32_t* __restrict__ succ, float* __restrict__ y) {
     __shared__ float4 sw[kSpan];
     __shared__ float sx[3 * kSpan];
-    const int64_t i0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);   // the path neighbours' lines on one L2
+    const int64_t i0 = tile * kBlock;
     const int64_t i = i0 + threadIdx.x;
     const int64_t ilast = i0 + kBlock - 1 < N ? i0 + kBlock - 1 : N - 1;
     const uint32_t lo = crange[i0].x, hi = crange[ilast].y;
@@ -893,7 +894,8 @@ __global__ __launch_bounds__(kBlock) void k_crev_rows(int64_t N, HG rho, float g
                                                       float* __restrict__ zbar, double* __restrict__ gpart) {
     __shared__ float4 sw[kSpan];
     __shared__ float sx[3 * kSpan];
-    const int64_t i0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);   // the path neighbours' lines on one L2
+    const int64_t i0 = tile * kBlock;
     const int64_t i = i0 + threadIdx.x;
     const int64_t ilast = i0 + kBlock - 1 < N ? i0 + kBlock - 1 : N - 1;
     const uint32_t lo = crange[i0].x, hi = crange[ilast].y;
@@ -936,7 +938,7 @@ __global__ __launch_bounds__(kBlock) void k_crev_rows(int64_t N, HG rho, float g
         gl = (double)dot3(zb, zg);
     }
     const double t = block_sum_d(gl);
-    if (threadIdx.x == 0) gpart[blockIdx.x] += t;
+    if (threadIdx.x == 0) gpart[tile] += t;
 }
 
 // lam_{t-1}(j) = sum_{i in cluster(j)} W_ij zbar_i = (c_g / M+_j) sum_i
